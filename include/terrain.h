@@ -1,0 +1,237 @@
+/*
+ * terrain.h -- C-ABI of libterrain.so: one time step of the agitated-soil
+ * particle system of Servin, Berglund & Nystedt, "A multiscale model of terrain
+ * dynamics for real-time earthmoving simulation" (arXiv 2011.00459), on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The soil in an active zone is a set of frictional-cohesive spheres (section
+ * "Microscopic model": pseudo-particles with parameters [rho, mu_t, mu_r, c_p,
+ * E]).  Their equation of motion is Eq. eqmotb (section "Mesoscale model"):
+ * gravity plus contact impulses from the other spheres, from the moving
+ * equipment B and from the resting terrain C, both treated as geometric
+ * boundaries.  One step (Algorithm 1: collision detection, the mesoscale
+ * contact constraints, the PGS solve and the position update, plus the
+ * aggregation of each active zone into a body with Eqs. aggregate_mass ..
+ * aggregate_rot_vel) runs entirely on the GPU.
+ *
+ * Conventions
+ *  - Every function returns TR_OK (0) or a negative TR_E_* code; the message
+ *    is available from get_last_error() until the next call on that scene.
+ *  - Host arrays passed in are borrowed for the duration of the call and
+ *    copied; the library never keeps a host pointer.
+ *  - A scene owns its device buffers (allocated through desc.alloc_fn when
+ *    given, else hipMalloc) and runs all work on desc.stream (the null stream
+ *    when NULL).  Handles are not thread-safe; one scene uses one stream.
+ *  - Positions are stored in FP32 in the frame they are given in; callers
+ *    should place each environment near the origin (FP32 resolution).
+ *  - Particle ids are consecutive per environment: env e owns the id range
+ *    [e * cap_particles, (e + 1) * cap_particles).
+ *  - A failed step leaves the particle state unchanged.
+ */
+#ifndef TERRAIN_H
+#define TERRAIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TR_OK 0
+#define TR_E_INVAL (-1)     /* invalid argument (NULL, out of range, unsupported option) */
+#define TR_E_NOMEM (-2)     /* device or host allocation failed */
+#define TR_E_DEVICE (-3)    /* HIP runtime error; message carries the HIP error string */
+#define TR_E_STATE (-4)     /* call not valid in the scene's current state */
+#define TR_E_CAPACITY (-5)  /* a capacity (particles, contacts, colours, cells) was exceeded */
+#define TR_E_NONFINITE (-6) /* NaN or Inf in an input */
+
+enum tr_warm_start {
+    TR_WARM_COLD = 0,    /* lambda^0 = 0 */
+    TR_WARM_PREV = 1,    /* previous step's impulses, matched by contact key */
+    TR_WARM_LEARNED = 2  /* MLP prediction, falling back to PREV/COLD */
+};
+
+enum tr_shape_type { TR_PLANE = 0, TR_BOX = 1, TR_HEIGHTFIELD = 2 };
+
+/* Particle and contact-law parameters, p_p = [rho, mu_t, mu_r, c_p, E]
+ * (section "Microscopic model") and the contact law of Eqs. signCoul1-2 with
+ * the Hertz mapping and SPOOK parameters (section "Contacting rigid
+ * multibodies").  Defaults from section "Soil library": E = 1e9 Pa,
+ * nu = 0.15, restitution 0. */
+typedef struct tr_material {
+    double rho;         /* particle density [kg/m^3], used when add_particles gets no density */
+    double mu_t;        /* Coulomb friction coefficient */
+    double mu_r;        /* rolling resistance; must be 0 (rows not modelled) */
+    double c_p;         /* particle cohesion [Pa]; 0 disables cohesion and its range */
+    double E;           /* Young's modulus [Pa] */
+    double nu;          /* Poisson's ratio */
+    double restitution; /* must be 0 (no impact stage) */
+    double tau_n;       /* normal damping time [s]; <= 0 means 2 dt */
+    double gamma_t;     /* tangential regularisation [s]; 0 = ideal Coulomb */
+    double kappa_c;     /* cohesive range: delta > -kappa_c (r1 + r2) keeps a contact */
+    double kappa_min;   /* compliance uses max(delta, kappa_min (r1 + r2)) */
+} tr_material;
+
+/* Device memory callbacks: alloc returns device memory usable on `stream`
+ * (e.g. from a framework's caching allocator); free releases it. */
+typedef void* (*tr_alloc_fn)(void* ctx, size_t bytes, void* stream);
+typedef void (*tr_free_fn)(void* ctx, void* ptr, void* stream);
+
+typedef struct tr_scene_desc {
+    int32_t n_envs;          /* independent environments stepped together (>= 1) */
+    double dt;               /* time step [s] */
+    double gravity[3];       /* [m/s^2] */
+    int32_t max_sweeps;      /* PGS sweeps per step (cap when tol > 0) */
+    double tol;              /* stop when the sweep residual R_k <= tol; 0 = fixed sweeps */
+    int32_t warm_start;      /* enum tr_warm_start */
+    tr_material material;
+    int64_t cap_particles;   /* particle capacity per environment */
+    int64_t cap_contacts;    /* contact capacity per environment */
+    const double* env_bounds;/* n_envs x 6: lo xyz, hi xyz of each env's cell grid
+                                (particles outside are clamped to the border cells) */
+    double r_ref;            /* nominal radius (learned-start feature scale); 0 = mean radius */
+    void* stream;            /* hipStream_t, or NULL */
+    tr_alloc_fn alloc_fn;    /* NULL: hipMalloc */
+    tr_free_fn free_fn;      /* NULL: hipFree */
+    void* alloc_ctx;
+} tr_scene_desc;
+
+/* Boundary shape of a kinematic body (equipment B or resting terrain C).
+ *   TR_PLANE       : surface normal . y = offset in the body frame; particles
+ *                    live on the +normal side.
+ *   TR_BOX         : oriented box with half extents `half`, centred at
+ *                    `center` in the body frame, axes of the body frame.
+ *   TR_HEIGHTFIELD : the terrain surface of Eq. surface, heights[j*nx+i] at
+ *                    (origin[0] + i l0, origin[1] + j l0), linear between grid
+ *                    points, in the world frame; its body must be static. */
+typedef struct tr_shape_desc {
+    int32_t type;
+    double normal[3];
+    double offset;
+    double half[3];
+    double center[3];
+    int32_t nx, ny;
+    double origin[2];
+    double l0;
+    const float* heights;    /* nx*ny values, copied */
+} tr_shape_desc;
+
+/* A kinematic body: its pose advances every step with its constant linear and
+ * angular velocity (x += dt v; q <- normalize(q + dt/2 (0, w) q)).  An optional
+ * active zone is given by up to 8 half-spaces in the body frame, a particle
+ * being inside when planes[k][0..2] . y <= planes[k][3] for every k (the wedge
+ * of Eq. failure_plane; see zones.py for a builder). */
+typedef struct tr_body_desc {
+    int32_t id;
+    double pos[3];
+    double quat[4];          /* (w, x, y, z) */
+    double linvel[3];
+    double angvel[3];
+    int32_t n_shapes;
+    const tr_shape_desc* shapes;
+    int32_t n_halfspaces;    /* 0 = no active zone */
+    double planes[8][4];
+} tr_body_desc;
+
+typedef struct tr_step_stats {
+    int64_t contacts;        /* all contacts of the env (pairs + boundary) */
+    int64_t pair_contacts;
+    int32_t colours;         /* colours of the scene's schedule */
+    int32_t sweeps;          /* PGS sweeps done */
+    double residual;         /* R_k after the last sweep */
+    double residual_first;   /* R_1 */
+    int32_t fallback_used;   /* learned start rejected, PREV/COLD used */
+    int32_t overflow;        /* nonzero when a capacity was exceeded (step aborted) */
+} tr_step_stats;
+
+/* Aggregate body of one active zone (Eqs. aggregate_mass .. aggregate_rot_vel,
+ * particle sums only), FP64, after the step's position update. */
+typedef struct tr_aggregate {
+    int32_t zone;            /* id of the body that owns the zone */
+    int32_t pad;
+    int64_t n_particles;
+    double M;
+    double x[3];             /* centre of mass */
+    double v[3];
+    double I[6];             /* inertia about x: xx, yy, zz, xy, xz, yz */
+    double w[3];             /* I^-1 L */
+} tr_aggregate;
+
+typedef struct tr_scene tr_scene;
+
+/* Creates a scene from *d (copied, env_bounds included).  Allocates all
+ * device buffers at their capacities.  TR_E_INVAL for bad sizes or options
+ * (mu_r or restitution nonzero), TR_E_NOMEM, TR_E_DEVICE. */
+int create_scene(const tr_scene_desc* d, tr_scene** out);
+
+/* Releases every buffer of the scene.  NULL is accepted. */
+int destroy_scene(tr_scene* s);
+
+/* Appends n spheres to env (Eq. eqmotb bodies with m = rho 4/3 pi r^3,
+ * I = 2/5 m r^2).  pos: 3n, vel: 3n or NULL (zero), radius: n, density: n or
+ * NULL (material.rho).  Ids are consecutive; the first is written to
+ * *first_id.  TR_E_CAPACITY when the env would exceed cap_particles,
+ * TR_E_NONFINITE for NaN/Inf, TR_E_INVAL for radius <= 0. Clears the
+ * warm-start cache. */
+int add_particles(tr_scene* s, int32_t env, int64_t n, const double* pos, const double* vel,
+                  const double* radius, const double* density, int64_t* first_id);
+
+/* Replaces the env's kinematic bodies (equipment B and resting terrain C,
+ * Eq. eqmotb's boundary terms) with b[0..n-1].  Shapes and heights are
+ * copied. */
+int set_kinematic_bodies(tr_scene* s, int32_t env, int32_t n, const tr_body_desc* b);
+
+/* Advances every env by n_steps steps.  Asynchronous on the scene's stream
+ * when stats is NULL; otherwise waits and writes one tr_step_stats per env
+ * (of the last step).  TR_E_CAPACITY when contacts, colours or cells
+ * overflow: the step is abandoned before any particle state changes. */
+int step(tr_scene* s, int32_t n_steps, tr_step_stats* stats);
+
+/* Mean contact force and torque (about the body's position at the start of
+ * the step) exerted by the particles on body body_id of env during the last
+ * step: impulse / dt, summed in FP64 (the force from which the digging
+ * resistance follows, section "Microscopic model").  Synchronises. */
+int get_contact_forces(tr_scene* s, int32_t env, int32_t body_id, double force[3], double torque[3]);
+
+/* Aggregate bodies of env's active zones after the last step, one per body
+ * with a zone, in body order.  Writes min(cap, count) records and the count
+ * to *n_out.  Synchronises. */
+int get_aggregates(tr_scene* s, int32_t env, int32_t cap, tr_aggregate* out, int32_t* n_out);
+
+/* Message of the last error on this scene ("" when none); valid until the
+ * next call on the scene. */
+const char* get_last_error(tr_scene* s);
+
+/* Canonical contact list of env from the last step, sorted by key (a pair of
+ * ids a < b has key a<<32 | b; a boundary contact of particle a with the
+ * env's shape s has key a<<32 | 0x80000000 | s), with the impulses
+ * (lambda_n, lambda_t xyz) of the step.  Writes min(cap, count) entries and
+ * the count to *n.  impulse4 may be NULL.  Synchronises. */
+int get_contacts(tr_scene* s, int32_t env, int64_t cap, uint64_t* keys, float* impulse4, int64_t* n);
+
+/* Particle state of env in id order (any output may be NULL): pos, vel,
+ * angvel 3n each, radius n.  *n receives the env's particle count.
+ * Synchronises. */
+int get_particles(tr_scene* s, int32_t env, double* pos, double* vel, double* angvel, double* radius,
+                  int64_t* n);
+
+/* Overwrites the state of env's particles in id order (NULL leaves a field
+ * unchanged) and clears the warm-start cache. */
+int set_particles(tr_scene* s, int32_t env, const double* pos, const double* vel, const double* angvel);
+
+/* Loads the learned warm-start network (12 -> 64 -> 64 -> 3, SiLU): n floats
+ * laid out W1[64][12], b1[64], W2[64][64], b2[64], W3[3][64], b3[3],
+ * in_scale[12].  TR_E_INVAL when n differs from that size. */
+int set_mlp_weights(tr_scene* s, const float* weights, int64_t n);
+
+/* Device time (ms, from HIP events on the scene's stream) of the last step's
+ * phases: [0] detection+ordering, [1] rows+colouring+warm start, [2] PGS,
+ * [3] integration+forces+aggregates, [4] whole step.  Writes min(cap, 5)
+ * values.  Synchronises. */
+int get_phase_times(tr_scene* s, float* ms, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

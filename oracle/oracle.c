@@ -1,0 +1,1147 @@
+/*
+ * oracle.c -- plain FP64 CPU reference of one agitated-soil particle step.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Built with -O2 -ffp-contract=off.
+ * Written for readability against the paper, not for speed: every step below
+ * names the passage of Servin, Berglund & Nystedt (arXiv 2011.00459) it
+ * follows, and the readings taken where the paper is silent or garbled.
+ *
+ * Conventions (readings, each listed with its reason in the design notes):
+ *  - Contact normal n points from body 1 to body 2.  A pair is ordered by id
+ *    (body 1 = lower id); for a boundary contact body 1 is the kinematic shape
+ *    and body 2 the particle.
+ *  - Overlap delta > 0 when penetrating.  The constraint function of Eq.
+ *    signCoul1 is read as g_n = -delta^(5/4) (negative when penetrating), so a
+ *    positive lambda_n pushes body 2 along +n.
+ *  - The Hertz mapping (epsilon_n read as 5/(4 k_n)) is applied to the row
+ *    divided by ||G_n|| = (5/4) delta^(1/4): g' = -(4/5) delta,
+ *    eps' = 4 / (5 k_n sqrt(delta)), lambda' = impulse along n.  Scaling a row
+ *    does not change the MCP solution; the cohesion bound becomes c_p A_p.
+ *  - SPOOK (section "Contacting rigid multibodies") as printed:
+ *    Upsilon = 1/(1+4 tau/dt), Sigma = (4/dt^2) eps Upsilon,
+ *    q = -(4/dt) Upsilon g + Upsilon G v_n.  lambda is an impulse.
+ *  - Cohesion: a contact exists while delta > -delta_c with delta_c = kappa_c
+ *    (r1 + r2) (pairs) or 2 kappa_c r (walls) when c_p > 0, else delta > 0;
+ *    lambda_n >= -c_p pi min(r1,r2)^2 dt.
+ *  - Friction disk ||lambda_t|| <= mu |lambda_n| (Eq. signCoul2 literally).
+ *  - Contact point at the middle of the overlap: lever arms l_i = r_i - delta/2.
+ *  - tau_n = 2 dt for every contact; no impact stage (restitution 0).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------ */
+/* small vector helpers                                                 */
+/* ------------------------------------------------------------------ */
+static double dot3(const double* a, const double* b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+static void cross3(const double* a, const double* b, double* c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Rotation matrix of a unit quaternion (w, x, y, z); R[i][j] row-major. */
+static void quat_matrix(const double* q, double R[3][3])
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0][0] = 1.0 - 2.0 * (y * y + z * z);
+    R[0][1] = 2.0 * (x * y - w * z);
+    R[0][2] = 2.0 * (x * z + w * y);
+    R[1][0] = 2.0 * (x * y + w * z);
+    R[1][1] = 1.0 - 2.0 * (x * x + z * z);
+    R[1][2] = 2.0 * (y * z - w * x);
+    R[2][0] = 2.0 * (x * z - w * y);
+    R[2][1] = 2.0 * (y * z + w * x);
+    R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+/* splitmix64 (Steele, Lea & Flood 2014; Vigna's published constants). */
+static uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double particle_mass(const orc_params* P, const double* rho, int64_t i, const double* r)
+{
+    double dens = rho ? rho[i] : P->m.rho;
+    return dens * (4.0 / 3.0) * PI * r[i] * r[i] * r[i];
+}
+
+/* ------------------------------------------------------------------ */
+/* Contact detection ("do collision detection", Algorithm 1)            */
+/* ------------------------------------------------------------------ */
+
+/* Cohesive range added to the contact distance (reading of "cohesion is
+ * active when the overlap is smaller than delta_c = 0.025 d"). */
+static double pair_range(const orc_params* P, double ri, double rj)
+{
+    return P->m.c_p > 0.0 ? P->m.kappa_c * (ri + rj) : 0.0;
+}
+static double wall_range(const orc_params* P, double r)
+{
+    return P->m.c_p > 0.0 ? P->m.kappa_c * (2.0 * r) : 0.0;
+}
+
+/* Pinned pair predicate: evaluated exactly in this order, no contraction. */
+static int pair_touch(const orc_params* P, const double* xi, double ri, const double* xj, double rj, double* d2out)
+{
+    double dx = xj[0] - xi[0];
+    double dy = xj[1] - xi[1];
+    double dz = xj[2] - xi[2];
+    double d2 = (dx * dx + dy * dy) + dz * dz;
+    double R = (ri + rj) + pair_range(P, ri, rj);
+    *d2out = d2;
+    return d2 < R * R;
+}
+
+/* World-frame plane of a PLANE shape: normal nw and offset dw. */
+static void plane_world(const orc_shape* s, const orc_body* b, double nw[3], double* dw)
+{
+    double R[3][3];
+    quat_matrix(b->quat, R);
+    for (int k = 0; k < 3; ++k) nw[k] = (R[k][0] * s->n[0] + R[k][1] * s->n[1]) + R[k][2] * s->n[2];
+    *dw = s->d + ((nw[0] * b->pos[0] + nw[1] * b->pos[1]) + nw[2] * b->pos[2]);
+}
+
+/* Boundary geometry of one sphere against one shape.  Returns 1 if in contact
+ * and fills delta, normal (shape -> particle). */
+static int shape_touch(const orc_params* P, const orc_shape* s, const orc_body* bodies,
+                       const double* x, double r, double* delta, double nrm[3])
+{
+    double Rr = r + wall_range(P, r);
+    if (s->type == ORC_PLANE) {
+        double nw[3], dw;
+        plane_world(s, &bodies[s->body], nw, &dw);
+        double sd = ((nw[0] * x[0] + nw[1] * x[1]) + nw[2] * x[2]) - dw;
+        if (!(sd < 0.0 || sd * sd < Rr * Rr)) return 0;
+        *delta = r - sd;
+        nrm[0] = nw[0]; nrm[1] = nw[1]; nrm[2] = nw[2];
+        return 1;
+    }
+    if (s->type == ORC_BOX) {
+        const orc_body* b = &bodies[s->body];
+        double R[3][3];
+        quat_matrix(b->quat, R);
+        double c[3];
+        for (int k = 0; k < 3; ++k) c[k] = b->pos[k] + ((R[k][0] * s->off[0] + R[k][1] * s->off[1]) + R[k][2] * s->off[2]);
+        double dx = x[0] - c[0], dy = x[1] - c[1], dz = x[2] - c[2];
+        double l[3];
+        for (int k = 0; k < 3; ++k) l[k] = (R[0][k] * dx + R[1][k] * dy) + R[2][k] * dz;
+        int inside = 1;
+        double q[3];
+        for (int k = 0; k < 3; ++k) {
+            q[k] = l[k];
+            if (q[k] > s->half[k]) { q[k] = s->half[k]; inside = 0; }
+            if (q[k] < -s->half[k]) { q[k] = -s->half[k]; inside = 0; }
+        }
+        if (inside) {
+            /* centre inside the box: least-penetration face, ties to the lower
+             * axis, + side when the coordinate is >= 0 */
+            int kbest = 0;
+            double pbest = s->half[0] - fabs(l[0]);
+            for (int k = 1; k < 3; ++k) {
+                double p = s->half[k] - fabs(l[k]);
+                if (p < pbest) { pbest = p; kbest = k; }
+            }
+            double sg = l[kbest] >= 0.0 ? 1.0 : -1.0;
+            for (int k = 0; k < 3; ++k) nrm[k] = sg * R[k][kbest];
+            *delta = r + pbest;
+            return 1;
+        }
+        double e0 = l[0] - q[0], e1 = l[1] - q[1], e2 = l[2] - q[2];
+        double d2 = (e0 * e0 + e1 * e1) + e2 * e2;
+        if (!(d2 < Rr * Rr)) return 0;
+        double dist = sqrt(d2);
+        double nl[3] = {e0 / dist, e1 / dist, e2 / dist};
+        for (int k = 0; k < 3; ++k) nrm[k] = (R[k][0] * nl[0] + R[k][1] * nl[1]) + R[k][2] * nl[2];
+        *delta = r - dist;
+        return 1;
+    }
+    if (s->type == ORC_HFIELD) {
+        /* Eq. surface: heights interpolated linearly between grid points,
+         * read as bilinear; local tangent-plane distance. */
+        double inv = 1.0 / s->l0;
+        double fx = (x[0] - s->ox) * inv;
+        double fy = (x[1] - s->oy) * inv;
+        double fi = floor(fx), fj = floor(fy);
+        if (fi < 0.0) fi = 0.0;
+        if (fi > (double)(s->nx - 2)) fi = (double)(s->nx - 2);
+        if (fj < 0.0) fj = 0.0;
+        if (fj > (double)(s->ny - 2)) fj = (double)(s->ny - 2);
+        int i = (int)fi, j = (int)fj;
+        double t = fx - fi, u = fy - fj;
+        double h00 = s->h[j * s->nx + i], h10 = s->h[j * s->nx + i + 1];
+        double h01 = s->h[(j + 1) * s->nx + i], h11 = s->h[(j + 1) * s->nx + i + 1];
+        double h = (h00 * (1.0 - t) + h10 * t) * (1.0 - u) + (h01 * (1.0 - t) + h11 * t) * u;
+        double hx = ((h10 - h00) * (1.0 - u) + (h11 - h01) * u) * inv;
+        double hy = ((h01 - h00) * (1.0 - t) + (h11 - h10) * t) * inv;
+        double dz = x[2] - h;
+        double m2 = (1.0 + hx * hx) + hy * hy;
+        if (!(dz < 0.0 || dz * dz < (Rr * Rr) * m2)) return 0;
+        double nz = 1.0 / sqrt(m2);
+        nrm[0] = -hx * nz; nrm[1] = -hy * nz; nrm[2] = nz;
+        *delta = r - dz * nz;
+        return 1;
+    }
+    return 0;
+}
+
+typedef struct {
+    uint64_t key;
+    int64_t a, b;   /* particle indices; a = -1 for a boundary contact */
+    int32_t shape;  /* shape index for a boundary contact */
+} raw_contact;
+
+static int cmp_raw(const void* p, const void* q)
+{
+    uint64_t a = ((const raw_contact*)p)->key, b = ((const raw_contact*)q)->key;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+typedef struct { int64_t cell; int64_t idx; } cell_entry;
+static int cmp_cell(const void* p, const void* q)
+{
+    const cell_entry* a = (const cell_entry*)p;
+    const cell_entry* b = (const cell_entry*)q;
+    if (a->cell != b->cell) return a->cell < b->cell ? -1 : 1;
+    return a->idx < b->idx ? -1 : (a->idx > b->idx ? 1 : 0);
+}
+
+/* Append a pair (i, j) if it touches; keys ordered by id. */
+static int add_pair(const orc_params* P, const int64_t* id, const double* x, const double* r,
+                    int64_t i, int64_t j, raw_contact** buf, int64_t* nc, int64_t* capb)
+{
+    int64_t lo = id[i] < id[j] ? i : j, hi = id[i] < id[j] ? j : i;
+    double d2;
+    if (!pair_touch(P, &x[3 * lo], r[lo], &x[3 * hi], r[hi], &d2)) return 0;
+    if (*nc == *capb) {
+        *capb = *capb ? 2 * *capb : 1024;
+        *buf = (raw_contact*)realloc(*buf, (size_t)*capb * sizeof(raw_contact));
+    }
+    raw_contact* c = &(*buf)[(*nc)++];
+    c->key = ((uint64_t)id[lo] << 32) | (uint64_t)(uint32_t)id[hi];
+    c->a = lo; c->b = hi; c->shape = -1;
+    return 1;
+}
+
+/* Detect all contacts, return them sorted by key (caller frees *out). */
+static int64_t detect_all(const orc_params* P, int64_t n, const int64_t* id, const double* x, const double* r,
+                          int32_t nb, const orc_body* bodies, int32_t ns, const orc_shape* shapes,
+                          raw_contact** out)
+{
+    raw_contact* buf = NULL;
+    int64_t nc = 0, capb = 0;
+    (void)nb;
+    if (P->detect == ORC_BRUTE || n < 2) {
+        /* the plain definition: every unordered pair */
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j) add_pair(P, id, x, r, i, j, &buf, &nc, &capb);
+    } else {
+        /* uniform cell list with cell size = the largest contact distance */
+        double rmax = 0.0, lo[3] = {1e300, 1e300, 1e300};
+        for (int64_t i = 0; i < n; ++i) {
+            if (r[i] > rmax) rmax = r[i];
+            for (int k = 0; k < 3; ++k) if (x[3 * i + k] < lo[k]) lo[k] = x[3 * i + k];
+        }
+        double h = 2.0 * rmax + pair_range(P, rmax, rmax);
+        h *= 1.0000001; /* margin: any touching pair lies in adjacent cells */
+        int64_t dim[3] = {1, 1, 1};
+        int64_t* cx = (int64_t*)malloc((size_t)n * 3 * sizeof(int64_t));
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < 3; ++k) {
+                cx[3 * i + k] = (int64_t)floor((x[3 * i + k] - lo[k]) / h);
+                if (cx[3 * i + k] + 1 > dim[k]) dim[k] = cx[3 * i + k] + 1;
+            }
+        cell_entry* ce = (cell_entry*)malloc((size_t)n * sizeof(cell_entry));
+        for (int64_t i = 0; i < n; ++i) {
+            ce[i].cell = (cx[3 * i + 2] * dim[1] + cx[3 * i + 1]) * dim[0] + cx[3 * i];
+            ce[i].idx = i;
+        }
+        qsort(ce, (size_t)n, sizeof(cell_entry), cmp_cell);
+        for (int64_t s = 0; s < n; ++s) {
+            int64_t i = ce[s].idx;
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int64_t c0 = cx[3 * i] + dx, c1 = cx[3 * i + 1] + dy, c2 = cx[3 * i + 2] + dz;
+                        if (c0 < 0 || c1 < 0 || c2 < 0 || c0 >= dim[0] || c1 >= dim[1] || c2 >= dim[2]) continue;
+                        int64_t cell = (c2 * dim[1] + c1) * dim[0] + c0;
+                        /* binary search for the first entry of that cell */
+                        int64_t a = 0, b = n;
+                        while (a < b) {
+                            int64_t m = (a + b) / 2;
+                            if (ce[m].cell < cell) a = m + 1; else b = m;
+                        }
+                        for (int64_t t = a; t < n && ce[t].cell == cell; ++t) {
+                            int64_t j = ce[t].idx;
+                            if (id[j] > id[i]) add_pair(P, id, x, r, i, j, &buf, &nc, &capb);
+                        }
+                    }
+        }
+        free(ce);
+        free(cx);
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t s = 0; s < ns; ++s) {
+            double dl, nr[3];
+            if (!shape_touch(P, &shapes[s], bodies, &x[3 * i], r[i], &dl, nr)) continue;
+            if (nc == capb) {
+                capb = capb ? 2 * capb : 1024;
+                buf = (raw_contact*)realloc(buf, (size_t)capb * sizeof(raw_contact));
+            }
+            raw_contact* c = &buf[nc++];
+            c->key = ((uint64_t)id[i] << 32) | 0x80000000ull | (uint64_t)(uint32_t)s;
+            c->a = -1; c->b = i; c->shape = s;
+        }
+    if (nc > 1) qsort(buf, (size_t)nc, sizeof(raw_contact), cmp_raw);
+    *out = buf;
+    return nc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Contact rows                                                          */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    uint64_t key;
+    int64_t a, b;        /* body 1 (particle index or -1), body 2 (particle index) */
+    int32_t shape, body; /* kinematic side (boundary contacts) */
+    double n[3];         /* body 1 -> body 2 */
+    double delta;
+    double l1, l2;       /* lever arms from the centres to the contact point */
+    double p[3];         /* contact point */
+    double vk[3];        /* kinematic velocity at p (boundary contacts) */
+    double Wn, Wt, Dn, Dt, Sig, q, lo, mu;
+    double ln, lt[3];    /* impulses */
+    int persistent;
+    int colour;
+} row;
+
+typedef struct {
+    double* im;   /* 1/m per particle */
+    double* iI;   /* 1/I per particle */
+} inv_mass;
+
+/* Relative velocity at the contact point, body 2 minus body 1. */
+static void rel_vel(const row* c, const double* v, const double* w, double u[3])
+{
+    double n[3] = {c->n[0], c->n[1], c->n[2]};
+    double u2[3], u1[3], t[3], arm[3];
+    /* body 2: v2 + w2 x (p - x2), p - x2 = -l2 n */
+    for (int k = 0; k < 3; ++k) arm[k] = -c->l2 * n[k];
+    cross3(&w[3 * c->b], arm, t);
+    for (int k = 0; k < 3; ++k) u2[k] = v[3 * c->b + k] + t[k];
+    if (c->a >= 0) {
+        for (int k = 0; k < 3; ++k) arm[k] = c->l1 * n[k];
+        cross3(&w[3 * c->a], arm, t);
+        for (int k = 0; k < 3; ++k) u1[k] = v[3 * c->a + k] + t[k];
+    } else {
+        for (int k = 0; k < 3; ++k) u1[k] = c->vk[k];
+    }
+    for (int k = 0; k < 3; ++k) u[k] = u2[k] - u1[k];
+}
+
+/* Apply impulse J (vector, on body 2; -J on body 1) at the contact point. */
+static void apply_impulse(const row* c, const inv_mass* M, double* v, double* w, const double J[3])
+{
+    double arm[3], t[3];
+    int64_t b = c->b;
+    for (int k = 0; k < 3; ++k) v[3 * b + k] += M->im[b] * J[k];
+    for (int k = 0; k < 3; ++k) arm[k] = -c->l2 * c->n[k];
+    cross3(arm, J, t);
+    for (int k = 0; k < 3; ++k) w[3 * b + k] += M->iI[b] * t[k];
+    if (c->a >= 0) {
+        int64_t a = c->a;
+        for (int k = 0; k < 3; ++k) v[3 * a + k] -= M->im[a] * J[k];
+        for (int k = 0; k < 3; ++k) arm[k] = c->l1 * c->n[k];
+        cross3(arm, J, t);
+        for (int k = 0; k < 3; ++k) w[3 * a + k] -= M->iI[a] * t[k];
+    }
+}
+
+/* Geometry and SPOOK/Hertz scalars of every contact (v = start-of-step). */
+static void build_rows(const orc_params* P, const int64_t* id, const double* r, const inv_mass* M,
+                       const double* x, const double* v, const double* w,
+                       const orc_body* bodies, const orc_shape* shapes,
+                       const raw_contact* rc, int64_t nc, row* rows)
+{
+    const orc_material* m = &P->m;
+    double dt = P->dt;
+    double tau = m->tau_n > 0.0 ? m->tau_n : 2.0 * dt;
+    double Ups = 1.0 / (1.0 + 4.0 * tau / dt);
+    double a_coef = (4.0 / dt) * Ups;
+    double b_coef = Ups;
+    double Estar = m->E / (2.0 * (1.0 - m->nu * m->nu)); /* same material both sides */
+    (void)id;
+    for (int64_t c = 0; c < nc; ++c) {
+        row* R = &rows[c];
+        memset(R, 0, sizeof(row));
+        R->key = rc[c].key;
+        R->a = rc[c].a;
+        R->b = rc[c].b;
+        R->shape = rc[c].shape;
+        R->body = -1;
+        double dstar, dref, rmin;
+        int64_t b = R->b;
+        if (R->a >= 0) {
+            int64_t a = R->a;
+            double e[3] = {x[3 * b] - x[3 * a], x[3 * b + 1] - x[3 * a + 1], x[3 * b + 2] - x[3 * a + 2]};
+            double d = sqrt(dot3(e, e));
+            if (d > 0.0) { for (int k = 0; k < 3; ++k) R->n[k] = e[k] / d; }
+            else { R->n[0] = 0.0; R->n[1] = 0.0; R->n[2] = 1.0; }
+            R->delta = (r[a] + r[b]) - d;
+            R->l1 = r[a] - 0.5 * R->delta;
+            R->l2 = r[b] - 0.5 * R->delta;
+            double da = 2.0 * r[a], db = 2.0 * r[b];
+            dstar = 1.0 / (1.0 / da + 1.0 / db);
+            dref = r[a] + r[b];
+            rmin = r[a] < r[b] ? r[a] : r[b];
+        } else {
+            const orc_shape* s = &shapes[R->shape];
+            shape_touch(P, s, bodies, &x[3 * b], r[b], &R->delta, R->n);
+            R->body = s->body;
+            R->l1 = 0.0;
+            R->l2 = r[b] - 0.5 * R->delta;
+            dstar = 2.0 * r[b];
+            dref = 2.0 * r[b];
+            rmin = r[b];
+        }
+        for (int k = 0; k < 3; ++k) R->p[k] = x[3 * b + k] - R->l2 * R->n[k];
+        if (R->a < 0) {
+            const orc_body* B = &bodies[R->body];
+            double arm[3] = {R->p[0] - B->pos[0], R->p[1] - B->pos[1], R->p[2] - B->pos[2]};
+            double t[3];
+            cross3(B->angvel, arm, t);
+            for (int k = 0; k < 3; ++k) R->vk[k] = B->linvel[k] + t[k];
+        }
+        /* Hertz stiffness k_n = E* sqrt(d*) / 3 and the scaled row */
+        double kn = Estar * sqrt(dstar) / 3.0;
+        double de = R->delta > m->kappa_min * dref ? R->delta : m->kappa_min * dref;
+        double eps = 4.0 / (5.0 * kn * sqrt(de));
+        double gq = -0.8 * R->delta;
+        R->Sig = (4.0 / (dt * dt)) * eps * Ups;
+        double u[3];
+        rel_vel(R, v, w, u);
+        double un = dot3(R->n, u);
+        R->q = -a_coef * gq + b_coef * un;
+        double ima = R->a >= 0 ? M->im[R->a] : 0.0, imb = M->im[b];
+        double iIa = R->a >= 0 ? M->iI[R->a] : 0.0, iIb = M->iI[b];
+        R->Wn = ima + imb;
+        R->Wt = ima + imb + R->l1 * R->l1 * iIa + R->l2 * R->l2 * iIb;
+        R->Dn = R->Wn + R->Sig;
+        R->Dt = R->Wt + m->gamma_t / dt;
+        R->lo = -m->c_p * PI * rmin * rmin * dt;
+        R->mu = m->mu_t;
+    }
+}
+
+/* Project (ln, lt) onto {ln >= lo, |lt| <= mu |ln|}. */
+static void project(const row* R, double* ln, double lt[3])
+{
+    if (*ln < R->lo) *ln = R->lo;
+    double tn = dot3(R->n, lt);
+    for (int k = 0; k < 3; ++k) lt[k] -= tn * R->n[k];
+    double lim = R->mu * fabs(*ln);
+    double m = sqrt(dot3(lt, lt));
+    if (m > lim) {
+        double s = m > 0.0 ? lim / m : 0.0;
+        for (int k = 0; k < 3; ++k) lt[k] *= s;
+    }
+}
+
+/* One projected Gauss-Seidel update of one contact (normal row, then the
+ * tangential disk row).  Adds the D-weighted change and value to acc. */
+static void pgs_contact(row* R, const inv_mass* M, double* v, double* w, double gamma_dt, double acc[2])
+{
+    double u[3];
+    /* normal row */
+    rel_vel(R, v, w, u);
+    double un = dot3(R->n, u);
+    double ln_new = R->ln - (un + R->Sig * R->ln - R->q) / R->Dn;
+    if (ln_new < R->lo) ln_new = R->lo;
+    double dn = ln_new - R->ln;
+    R->ln = ln_new;
+    double J[3] = {dn * R->n[0], dn * R->n[1], dn * R->n[2]};
+    apply_impulse(R, M, v, w, J);
+    /* tangential row */
+    rel_vel(R, v, w, u);
+    un = dot3(R->n, u);
+    double ut[3] = {u[0] - un * R->n[0], u[1] - un * R->n[1], u[2] - un * R->n[2]};
+    double lt[3];
+    for (int k = 0; k < 3; ++k) lt[k] = R->lt[k] - (ut[k] + gamma_dt * R->lt[k]) / R->Dt;
+    double lim = R->mu * fabs(R->ln);
+    double mag = sqrt(dot3(lt, lt));
+    if (mag > lim) {
+        double s = mag > 0.0 ? lim / mag : 0.0;
+        for (int k = 0; k < 3; ++k) lt[k] *= s;
+    }
+    double dtv[3] = {lt[0] - R->lt[0], lt[1] - R->lt[1], lt[2] - R->lt[2]};
+    for (int k = 0; k < 3; ++k) R->lt[k] = lt[k];
+    apply_impulse(R, M, v, w, dtv);
+    acc[0] += R->Dn * dn * dn + R->Dt * dot3(dtv, dtv);
+    acc[1] += R->Dn * R->ln * R->ln + R->Dt * dot3(R->lt, R->lt);
+}
+
+/* ------------------------------------------------------------------ */
+/* Colouring: greedy in decreasing (splitmix64(key), key) order.  This is the */
+/* unique result of Jones-Plassmann with that priority.                  */
+/* ------------------------------------------------------------------ */
+typedef struct { uint64_t h, key; int64_t idx; } prio;
+static int cmp_prio_desc(const void* p, const void* q)
+{
+    const prio* a = (const prio*)p;
+    const prio* b = (const prio*)q;
+    if (a->h != b->h) return a->h > b->h ? -1 : 1;
+    if (a->key != b->key) return a->key > b->key ? -1 : 1;
+    return 0;
+}
+
+static int colour_contacts(row* rows, int64_t nc, int64_t n)
+{
+    /* incidence lists of dynamic particles */
+    int64_t* cnt = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t c = 0; c < nc; ++c) {
+        cnt[rows[c].b + 1]++;
+        if (rows[c].a >= 0) cnt[rows[c].a + 1]++;
+    }
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    int64_t* fill = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
+    memcpy(fill, cnt, (size_t)(n + 1) * sizeof(int64_t));
+    int64_t* inc = (int64_t*)malloc((size_t)(cnt[n] > 0 ? cnt[n] : 1) * sizeof(int64_t));
+    for (int64_t c = 0; c < nc; ++c) {
+        inc[fill[rows[c].b]++] = c;
+        if (rows[c].a >= 0) inc[fill[rows[c].a]++] = c;
+    }
+    prio* order = (prio*)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(prio));
+    for (int64_t c = 0; c < nc; ++c) {
+        order[c].h = splitmix64(rows[c].key);
+        order[c].key = rows[c].key;
+        order[c].idx = c;
+        rows[c].colour = -1;
+    }
+    qsort(order, (size_t)nc, sizeof(prio), cmp_prio_desc);
+    int maxc = 0;
+    for (int64_t t = 0; t < nc; ++t) {
+        row* R = &rows[order[t].idx];
+        unsigned char used[256];
+        memset(used, 0, sizeof(used));
+        int64_t parts[2] = {R->b, R->a};
+        for (int s = 0; s < 2; ++s) {
+            if (parts[s] < 0) continue;
+            for (int64_t e = cnt[parts[s]]; e < cnt[parts[s] + 1]; ++e) {
+                int col = rows[inc[e]].colour;
+                if (col >= 0 && col < 256) used[col] = 1;
+            }
+        }
+        int col = 0;
+        while (col < 256 && used[col]) ++col;
+        R->colour = col;
+        if (col + 1 > maxc) maxc = col + 1;
+    }
+    free(order);
+    free(inc);
+    free(fill);
+    free(cnt);
+    return maxc;
+}
+
+/* ------------------------------------------------------------------ */
+/* MLP (learned warm start)                                             */
+/* ------------------------------------------------------------------ */
+static double silu(double z) { return z / (1.0 + exp(-z)); }
+static double dsilu(double z)
+{
+    double s = 1.0 / (1.0 + exp(-z));
+    return s * (1.0 + z * (1.0 - s));
+}
+
+void orc_mlp_forward(const orc_mlp* net, int64_t B, const double* feat, double* out)
+{
+    for (int64_t b = 0; b < B; ++b) {
+        double x0[12], h1[64], h2[64];
+        for (int i = 0; i < 12; ++i) x0[i] = feat[12 * b + i] * net->in_scale[i];
+        for (int o = 0; o < 64; ++o) {
+            double z = net->b1[o];
+            for (int i = 0; i < 12; ++i) z += net->W1[o * 12 + i] * x0[i];
+            h1[o] = silu(z);
+        }
+        for (int o = 0; o < 64; ++o) {
+            double z = net->b2[o];
+            for (int i = 0; i < 64; ++i) z += net->W2[o * 64 + i] * h1[i];
+            h2[o] = silu(z);
+        }
+        for (int o = 0; o < 3; ++o) {
+            double z = net->b3[o];
+            for (int i = 0; i < 64; ++i) z += net->W3[o * 64 + i] * h2[i];
+            out[3 * b + o] = z;
+        }
+    }
+}
+
+double orc_mlp_loss_grad(const orc_mlp* net, int64_t B, const double* feat, const double* label, double* grads)
+{
+    double* gW1 = grads;
+    double* gb1 = gW1 + 64 * 12;
+    double* gW2 = gb1 + 64;
+    double* gb2 = gW2 + 64 * 64;
+    double* gW3 = gb2 + 64;
+    double* gb3 = gW3 + 3 * 64;
+    memset(grads, 0, sizeof(double) * (64 * 12 + 64 + 64 * 64 + 64 + 3 * 64 + 3));
+    double loss = 0.0;
+    for (int64_t b = 0; b < B; ++b) {
+        double x0[12], z1[64], h1[64], z2[64], h2[64], y[3];
+        for (int i = 0; i < 12; ++i) x0[i] = feat[12 * b + i] * net->in_scale[i];
+        for (int o = 0; o < 64; ++o) {
+            double z = net->b1[o];
+            for (int i = 0; i < 12; ++i) z += net->W1[o * 12 + i] * x0[i];
+            z1[o] = z; h1[o] = silu(z);
+        }
+        for (int o = 0; o < 64; ++o) {
+            double z = net->b2[o];
+            for (int i = 0; i < 64; ++i) z += net->W2[o * 64 + i] * h1[i];
+            z2[o] = z; h2[o] = silu(z);
+        }
+        double gy[3];
+        for (int o = 0; o < 3; ++o) {
+            double z = net->b3[o];
+            for (int i = 0; i < 64; ++i) z += net->W3[o * 64 + i] * h2[i];
+            y[o] = z;
+            double e = y[o] - label[3 * b + o];
+            loss += 0.5 * e * e;
+            gy[o] = e / (double)B;
+        }
+        double gh2[64], gz2[64], gh1[64], gz1[64];
+        for (int i = 0; i < 64; ++i) gh2[i] = 0.0;
+        for (int o = 0; o < 3; ++o) {
+            gb3[o] += gy[o];
+            for (int i = 0; i < 64; ++i) {
+                gW3[o * 64 + i] += gy[o] * h2[i];
+                gh2[i] += net->W3[o * 64 + i] * gy[o];
+            }
+        }
+        for (int i = 0; i < 64; ++i) { gz2[i] = gh2[i] * dsilu(z2[i]); gh1[i] = 0.0; }
+        for (int o = 0; o < 64; ++o) {
+            gb2[o] += gz2[o];
+            for (int i = 0; i < 64; ++i) {
+                gW2[o * 64 + i] += gz2[o] * h1[i];
+                gh1[i] += net->W2[o * 64 + i] * gz2[o];
+            }
+        }
+        for (int i = 0; i < 64; ++i) gz1[i] = gh1[i] * dsilu(z1[i]);
+        for (int o = 0; o < 64; ++o) {
+            gb1[o] += gz1[o];
+            for (int i = 0; i < 12; ++i) gW1[o * 12 + i] += gz1[o] * x0[i];
+        }
+    }
+    return loss / (double)B;
+}
+
+/* ------------------------------------------------------------------ */
+/* Learned-start features (12 per contact) and the contact frame.       */
+/* ------------------------------------------------------------------ */
+static void contact_frame(const row* R, const double u[3], const double ltp[3], double t1[3], double t2[3])
+{
+    double un = dot3(R->n, u);
+    double ut[3] = {u[0] - un * R->n[0], u[1] - un * R->n[1], u[2] - un * R->n[2]};
+    double m = sqrt(dot3(ut, ut));
+    double src[3];
+    if (m > 1e-12) { for (int k = 0; k < 3; ++k) src[k] = ut[k] / m; }
+    else {
+        double lm = sqrt(dot3(ltp, ltp));
+        if (lm > 0.0) { for (int k = 0; k < 3; ++k) src[k] = ltp[k] / lm; }
+        else {
+            /* any unit vector orthogonal to n: the axis least aligned with n */
+            double ax[3] = {0.0, 0.0, 0.0};
+            int k0 = 0;
+            for (int k = 1; k < 3; ++k) if (fabs(R->n[k]) < fabs(R->n[k0])) k0 = k;
+            ax[k0] = 1.0;
+            double dn = dot3(ax, R->n);
+            for (int k = 0; k < 3; ++k) src[k] = ax[k] - dn * R->n[k];
+            double sm = sqrt(dot3(src, src));
+            for (int k = 0; k < 3; ++k) src[k] /= sm;
+        }
+    }
+    for (int k = 0; k < 3; ++k) t1[k] = src[k];
+    cross3(R->n, t1, t2);
+}
+
+/* Column heights: max(z + r) over the grid column of side h. */
+static void learned_features(const orc_params* P, int64_t n, const double* x, const double* r,
+                             const double* v, const double* w, const inv_mass* M,
+                             const row* rows, int64_t nc, const double* ltprev, double* F,
+                             double (*frames)[6])
+{
+    double rmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) if (r[i] > rmax) rmax = r[i];
+    double h = 2.0 * rmax * (1.0 + (P->m.c_p > 0.0 ? P->m.kappa_c : 0.0));
+    /* column of every particle, then the highest top z + r per column */
+    cell_entry* ce = (cell_entry*)malloc((size_t)(n > 0 ? n : 1) * sizeof(cell_entry));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t cx = (int64_t)floor((x[3 * i] - P->grid_lo[0]) / h);
+        int64_t cy = (int64_t)floor((x[3 * i + 1] - P->grid_lo[1]) / h);
+        ce[i].cell = cy * 1048576 + cx;
+        ce[i].idx = i;
+    }
+    qsort(ce, (size_t)n, sizeof(cell_entry), cmp_cell);
+    double* depth = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int64_t s0 = 0; s0 < n;) {
+        int64_t s1 = s0;
+        double top = -1e300;
+        while (s1 < n && ce[s1].cell == ce[s0].cell) {
+            int64_t j = ce[s1].idx;
+            if (x[3 * j + 2] + r[j] > top) top = x[3 * j + 2] + r[j];
+            ++s1;
+        }
+        for (int64_t t = s0; t < s1; ++t) depth[ce[t].idx] = top - x[3 * ce[t].idx + 2];
+        s0 = s1;
+    }
+    free(ce);
+    double gmag = sqrt(dot3(P->g, P->g));
+    double gdt = gmag * P->dt;
+    for (int64_t c = 0; c < nc; ++c) {
+        const row* R = &rows[c];
+        double u[3];
+        rel_vel(R, v, w, u);
+        double un = dot3(R->n, u);
+        double ut[3] = {u[0] - un * R->n[0], u[1] - un * R->n[1], u[2] - un * R->n[2]};
+        double t1[3], t2[3];
+        contact_frame(R, u, &ltprev[3 * c], t1, t2);
+        double meff = 1.0 / R->Wn;
+        double ls = meff * gdt;
+        double rbar = R->a >= 0 ? 0.5 * (r[R->a] + r[R->b]) : r[R->b];
+        double* f = &F[12 * c];
+        f[0] = R->delta / rbar;
+        f[1] = un / gdt;
+        f[2] = sqrt(dot3(ut, ut)) / gdt;
+        f[3] = R->ln / ls;
+        f[4] = dot3(&ltprev[3 * c], t1) / ls;
+        f[5] = dot3(&ltprev[3 * c], t2) / ls;
+        f[6] = R->a >= 0 ? depth[R->a] / rbar : 0.0;
+        f[7] = depth[R->b] / rbar;
+        f[8] = R->a >= 0 ? r[R->a] / P->r_ref : 0.0;
+        f[9] = r[R->b] / P->r_ref;
+        f[10] = R->a >= 0 ? 0.0 : 1.0;
+        f[11] = R->persistent ? 1.0 : 0.0;
+        for (int k = 0; k < 3; ++k) { frames[c][k] = t1[k]; frames[c][3 + k] = t2[k]; }
+    }
+    (void)M;
+    free(depth);
+}
+
+/* ------------------------------------------------------------------ */
+/* Public entry points                                                  */
+/* ------------------------------------------------------------------ */
+int64_t orc_detect(const orc_params* P, int64_t n, const int64_t* id, const double* x, const double* r,
+                   int32_t nb, const orc_body* bodies, int32_t ns, const orc_shape* shapes,
+                   int64_t cap, uint64_t* keys, double* delta)
+{
+    raw_contact* rc = NULL;
+    int64_t nc = detect_all(P, n, id, x, r, nb, bodies, ns, shapes, &rc);
+    if (nc > cap) { free(rc); return -5; }
+    for (int64_t c = 0; c < nc; ++c) {
+        keys[c] = rc[c].key;
+        if (delta) {
+            if (rc[c].a >= 0) {
+                int64_t a = rc[c].a, b = rc[c].b;
+                double e[3] = {x[3 * b] - x[3 * a], x[3 * b + 1] - x[3 * a + 1], x[3 * b + 2] - x[3 * a + 2]};
+                delta[c] = (r[a] + r[b]) - sqrt(dot3(e, e));
+            } else {
+                double nr[3];
+                shape_touch(P, &shapes[rc[c].shape], bodies, &x[3 * rc[c].b], r[rc[c].b], &delta[c], nr);
+            }
+        }
+    }
+    free(rc);
+    return nc;
+}
+
+static void make_inv_mass(const orc_params* P, int64_t n, const double* r, const double* rho, inv_mass* M)
+{
+    M->im = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    M->iI = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        double m = particle_mass(P, rho, i, r);
+        M->im[i] = 1.0 / m;
+        M->iI[i] = 1.0 / (0.4 * m * r[i] * r[i]);
+    }
+}
+
+/* Look up key in the previous cache (sorted); returns index or -1. */
+static int64_t find_prev(int64_t nprev, const uint64_t* keys, uint64_t k)
+{
+    int64_t a = 0, b = nprev;
+    while (a < b) {
+        int64_t m = (a + b) / 2;
+        if (keys[m] < k) a = m + 1; else b = m;
+    }
+    return (a < nprev && keys[a] == k) ? a : -1;
+}
+
+/* Aggregate body of every zone (Eqs. aggregate_mass .. aggregate_rot_vel):
+ * particles are labelled with the first body (in order) whose zone contains
+ * them; sums over particles only, with the spheres' own inertia 2/5 m r^2
+ * and spin (the inertia formula as printed is read as the standard
+ * parallel-axis sum about x_A). */
+int32_t orc_aggregates(int64_t n, const double* r, const double* inv_m, const double* x, const double* v,
+                       const double* w, int32_t nb, const orc_body* bodies, orc_aggregate* agg)
+{
+    int32_t na = 0;
+    int32_t* zone_of = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    double (*wp)[8][4] = malloc((size_t)(nb > 0 ? nb : 1) * sizeof(double[8][4]));
+    for (int32_t b = 0; b < nb; ++b) {
+        double Rm[3][3];
+        quat_matrix(bodies[b].quat, Rm);
+        for (int p = 0; p < bodies[b].nplanes; ++p) {
+            const double* pl = bodies[b].planes[p];
+            double nw[3];
+            for (int k = 0; k < 3; ++k) nw[k] = (Rm[k][0] * pl[0] + Rm[k][1] * pl[1]) + Rm[k][2] * pl[2];
+            for (int k = 0; k < 3; ++k) wp[b][p][k] = nw[k];
+            wp[b][p][3] = pl[3] + dot3(nw, bodies[b].pos);
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        zone_of[i] = -1;
+        for (int32_t b = 0; b < nb && zone_of[i] < 0; ++b) {
+            if (bodies[b].nplanes <= 0) continue;
+            int in = 1;
+            for (int p = 0; p < bodies[b].nplanes; ++p)
+                if (dot3(wp[b][p], &x[3 * i]) - wp[b][p][3] > 0.0) { in = 0; break; }
+            if (in) zone_of[i] = b;
+        }
+    }
+    for (int32_t b = 0; b < nb; ++b) {
+        if (bodies[b].nplanes <= 0) continue;
+        orc_aggregate* A = &agg[na++];
+        memset(A, 0, sizeof(*A));
+        A->zone = b;
+        double Mt = 0.0, mx[3] = {0, 0, 0}, mv[3] = {0, 0, 0};
+        for (int64_t i = 0; i < n; ++i) {
+            if (zone_of[i] != b) continue;
+            double m = 1.0 / inv_m[i];
+            A->n_particles++;
+            Mt += m;
+            for (int k = 0; k < 3; ++k) { mx[k] += m * x[3 * i + k]; mv[k] += m * v[3 * i + k]; }
+        }
+        A->M = Mt;
+        if (Mt <= 0.0) continue;
+        for (int k = 0; k < 3; ++k) { A->x[k] = mx[k] / Mt; A->v[k] = mv[k] / Mt; }
+        double I[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, L[3] = {0, 0, 0};
+        for (int64_t i = 0; i < n; ++i) {
+            if (zone_of[i] != b) continue;
+            double m = 1.0 / inv_m[i];
+            double rho_[3] = {x[3 * i] - A->x[0], x[3 * i + 1] - A->x[1], x[3 * i + 2] - A->x[2]};
+            double rr = dot3(rho_, rho_);
+            double Is = 0.4 * m * r[i] * r[i];
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q)
+                    I[p][q] += (p == q ? Is + m * rr : 0.0) - m * rho_[p] * rho_[q];
+            double cxv[3];
+            cross3(rho_, &v[3 * i], cxv);
+            for (int k = 0; k < 3; ++k) L[k] += m * cxv[k] + Is * w[3 * i + k];
+        }
+        A->I[0] = I[0][0]; A->I[1] = I[1][1]; A->I[2] = I[2][2];
+        A->I[3] = I[0][1]; A->I[4] = I[0][2]; A->I[5] = I[1][2];
+        for (int k = 0; k < 3; ++k) A->L[k] = L[k];
+        /* omega_A = I^-1 L by Cramer's rule */
+        double det = I[0][0] * (I[1][1] * I[2][2] - I[1][2] * I[2][1])
+                   - I[0][1] * (I[1][0] * I[2][2] - I[1][2] * I[2][0])
+                   + I[0][2] * (I[1][0] * I[2][1] - I[1][1] * I[2][0]);
+        for (int k = 0; k < 3; ++k) {
+            double Mk[3][3];
+            memcpy(Mk, I, sizeof(Mk));
+            for (int p = 0; p < 3; ++p) Mk[p][k] = L[p];
+            double dk = Mk[0][0] * (Mk[1][1] * Mk[2][2] - Mk[1][2] * Mk[2][1])
+                      - Mk[0][1] * (Mk[1][0] * Mk[2][2] - Mk[1][2] * Mk[2][0])
+                      + Mk[0][2] * (Mk[1][0] * Mk[2][1] - Mk[1][1] * Mk[2][0]);
+            A->w[k] = det != 0.0 ? dk / det : 0.0;
+        }
+    }
+    free(wp);
+    free(zone_of);
+    return na;
+}
+
+/* Run one sweep over all colours; returns the residual of that sweep. */
+static double sweep(row* rows, int64_t nc, int ncol, const int64_t* cstart, const int64_t* corder,
+                    const inv_mass* M, double* v, double* w, double gamma_dt)
+{
+    double acc[2] = {0.0, 0.0};
+    for (int col = 0; col < ncol; ++col)
+        for (int64_t t = cstart[col]; t < cstart[col + 1]; ++t)
+            pgs_contact(&rows[corder[t]], M, v, w, gamma_dt, acc);
+    (void)nc;
+    if (acc[1] > 0.0) return sqrt(acc[0]) / sqrt(acc[1]);
+    return acc[0] > 0.0 ? 1.0 : 0.0;
+}
+
+/* Warm-start values lambda^0 for every contact into (ln0, lt0). */
+static void apply_start(row* rows, int64_t nc, const inv_mass* M, double* v, double* w)
+{
+    for (int64_t c = 0; c < nc; ++c) {
+        row* R = &rows[c];
+        project(R, &R->ln, R->lt);
+        double J[3];
+        for (int k = 0; k < 3; ++k) J[k] = R->ln * R->n[k] + R->lt[k];
+        apply_impulse(R, M, v, w, J);
+    }
+}
+
+int64_t orc_step(const orc_params* P,
+                 int64_t n, const int64_t* id, const double* r, const double* rho,
+                 double* x, double* v, double* w,
+                 int32_t nb, orc_body* bodies,
+                 int32_t ns, const orc_shape* shapes,
+                 int64_t nprev, const uint64_t* prev_keys, const double* prev_lam,
+                 const orc_mlp* mlp,
+                 int64_t cap, uint64_t* keys_out, double* lam_out, int32_t* colour_out,
+                 orc_stats* st, double* body_ft,
+                 orc_aggregate* agg, int32_t* n_agg, double* resid)
+{
+    if (P->m.mu_r != 0.0 || P->m.restitution != 0.0) return -1;
+    double dt = P->dt;
+    inv_mass M;
+    make_inv_mass(P, n, r, rho, &M);
+
+    /* 1-2. detection and canonical order */
+    raw_contact* rc = NULL;
+    int64_t nc = detect_all(P, n, id, x, r, nb, bodies, ns, shapes, &rc);
+    if (nc > cap) {
+        free(rc); free(M.im); free(M.iI);
+        return -5;
+    }
+    row* rows = (row*)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(row));
+
+    /* 3-5. rows from the start-of-step state */
+    build_rows(P, id, r, &M, x, v, w, bodies, shapes, rc, nc, rows);
+    free(rc);
+
+    /* previous-step impulses, matched by key */
+    double* ltprev = (double*)calloc((size_t)(nc > 0 ? nc : 1) * 3, sizeof(double));
+    double* lnprev = (double*)calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t k = nprev > 0 ? find_prev(nprev, prev_keys, rows[c].key) : -1;
+        rows[c].persistent = k >= 0;
+        if (k >= 0) {
+            lnprev[c] = prev_lam[4 * k];
+            for (int j = 0; j < 3; ++j) ltprev[3 * c + j] = prev_lam[4 * k + 1 + j];
+            /* re-project onto the new tangent plane */
+            double tn = dot3(rows[c].n, &ltprev[3 * c]);
+            for (int j = 0; j < 3; ++j) ltprev[3 * c + j] -= tn * rows[c].n[j];
+        }
+    }
+
+    /* 6. prediction v* = v + dt g */
+    double* v0 = (double*)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
+    memcpy(v0, v, (size_t)n * 3 * sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) v[3 * i + k] += dt * P->g[k];
+
+    /* colouring and colour-ordered contact list */
+    int ncol = colour_contacts(rows, nc, n);
+    int64_t* cstart = (int64_t*)calloc((size_t)ncol + 2, sizeof(int64_t));
+    int64_t* corder = (int64_t*)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int64_t));
+    for (int64_t c = 0; c < nc; ++c) cstart[rows[c].colour + 1]++;
+    for (int k = 0; k < ncol; ++k) cstart[k + 1] += cstart[k];
+    {
+        int64_t* f = (int64_t*)malloc((size_t)(ncol + 1) * sizeof(int64_t));
+        memcpy(f, cstart, (size_t)(ncol + 1) * sizeof(int64_t));
+        for (int64_t c = 0; c < nc; ++c) corder[f[rows[c].colour]++] = c;
+        free(f);
+    }
+
+    double gamma_dt = P->m.gamma_t / dt;
+    int sweeps_done = 0;
+    double R = 1.0;
+    int fallback = 0, learned_used = 0;
+    double r1 = 0.0;
+
+    /* warm start (A8): cold, previous-step, or learned with fallback */
+    for (int64_t c = 0; c < nc; ++c) { rows[c].ln = 0.0; rows[c].lt[0] = rows[c].lt[1] = rows[c].lt[2] = 0.0; }
+    int have_prev = 0;
+    for (int64_t c = 0; c < nc; ++c) have_prev |= rows[c].persistent;
+    if (P->warm == ORC_PREV || P->warm == ORC_LEARNED) {
+        for (int64_t c = 0; c < nc; ++c) {
+            rows[c].ln = lnprev[c];
+            for (int j = 0; j < 3; ++j) rows[c].lt[j] = ltprev[3 * c + j];
+        }
+    }
+    if (P->warm == ORC_LEARNED && mlp && nc > 0 && P->max_sweeps > 0) {
+        /* trial: learned start and its first sweep */
+        double* F = (double*)malloc((size_t)nc * 12 * sizeof(double));
+        double (*fr)[6] = malloc((size_t)nc * sizeof(double[6]));
+        double* y = (double*)malloc((size_t)nc * 3 * sizeof(double));
+        learned_features(P, n, x, r, v0, w, &M, rows, nc, ltprev, F, fr);
+        orc_mlp_forward(mlp, nc, F, y);
+        double gmag = sqrt(dot3(P->g, P->g));
+        int finite = 1;
+        row* rl = (row*)malloc((size_t)nc * sizeof(row));
+        memcpy(rl, rows, (size_t)nc * sizeof(row));
+        for (int64_t c = 0; c < nc; ++c) {
+            double ls = (1.0 / rl[c].Wn) * gmag * dt;
+            rl[c].ln = y[3 * c] * ls;
+            for (int k = 0; k < 3; ++k) rl[c].lt[k] = (y[3 * c + 1] * fr[c][k] + y[3 * c + 2] * fr[c][3 + k]) * ls;
+            if (!isfinite(rl[c].ln) || !isfinite(rl[c].lt[0]) || !isfinite(rl[c].lt[1]) || !isfinite(rl[c].lt[2])) finite = 0;
+        }
+        double* vl = (double*)malloc((size_t)n * 3 * sizeof(double));
+        double* wl = (double*)malloc((size_t)n * 3 * sizeof(double));
+        memcpy(vl, v, (size_t)n * 3 * sizeof(double));
+        memcpy(wl, w, (size_t)n * 3 * sizeof(double));
+        double r1l = 1e300;
+        if (finite) {
+            apply_start(rl, nc, &M, vl, wl);
+            r1l = sweep(rl, nc, ncol, cstart, corder, &M, vl, wl, gamma_dt);
+            if (!isfinite(r1l)) finite = 0;
+        }
+        /* reference: previous-step start (cold when there is no cache) */
+        apply_start(rows, nc, &M, v, w);
+        double r1p = sweep(rows, nc, ncol, cstart, corder, &M, v, w, gamma_dt);
+        if (finite && !(r1l > r1p)) {
+            memcpy(rows, rl, (size_t)nc * sizeof(row));
+            memcpy(v, vl, (size_t)n * 3 * sizeof(double));
+            memcpy(w, wl, (size_t)n * 3 * sizeof(double));
+            R = r1l;
+            learned_used = 1;
+        } else {
+            R = r1p;
+            fallback = 1;
+        }
+        (void)have_prev;
+        r1 = R;
+        if (resid) resid[0] = R;
+        sweeps_done = 1;
+        free(vl); free(wl); free(rl); free(y); free(fr); free(F);
+    } else {
+        apply_start(rows, nc, &M, v, w);
+    }
+
+    /* 7. PGS sweeps in colour order */
+    while (sweeps_done < P->max_sweeps) {
+        if (sweeps_done > 0 && P->tol > 0.0 && R <= P->tol) break;
+        R = sweep(rows, nc, ncol, cstart, corder, &M, v, w, gamma_dt);
+        if (resid) resid[sweeps_done] = R;
+        if (sweeps_done == 0) r1 = R;
+        ++sweeps_done;
+    }
+
+    /* 8. symplectic position update and kinematic poses */
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) x[3 * i + k] += dt * v[3 * i + k];
+
+    /* 9. contact force and torque on each kinematic body (start-of-step pose) */
+    if (body_ft) {
+        for (int32_t b = 0; b < nb; ++b) for (int k = 0; k < 6; ++k) body_ft[6 * b + k] = 0.0;
+        for (int64_t c = 0; c < nc; ++c) {
+            const row* Rw = &rows[c];
+            if (Rw->a >= 0) continue;
+            const orc_body* B = &bodies[Rw->body];
+            double f[3], arm[3], t[3];
+            for (int k = 0; k < 3; ++k) f[k] = -(Rw->ln * Rw->n[k] + Rw->lt[k]) / dt;
+            for (int k = 0; k < 3; ++k) arm[k] = Rw->p[k] - B->pos[k];
+            cross3(arm, f, t);
+            for (int k = 0; k < 3; ++k) { body_ft[6 * Rw->body + k] += f[k]; body_ft[6 * Rw->body + 3 + k] += t[k]; }
+        }
+    }
+    for (int32_t b = 0; b < nb; ++b) {
+        orc_body* B = &bodies[b];
+        for (int k = 0; k < 3; ++k) B->pos[k] += dt * B->linvel[k];
+        /* q <- normalize(q + dt/2 (0, w) (x) q) */
+        double q0 = B->quat[0], q1 = B->quat[1], q2 = B->quat[2], q3 = B->quat[3];
+        double wx = B->angvel[0], wy = B->angvel[1], wz = B->angvel[2];
+        double h = 0.5 * dt;
+        double n0 = q0 + h * (-wx * q1 - wy * q2 - wz * q3);
+        double n1 = q1 + h * (wx * q0 + wy * q3 - wz * q2);
+        double n2 = q2 + h * (-wx * q3 + wy * q0 + wz * q1);
+        double n3 = q3 + h * (wx * q2 - wy * q1 + wz * q0);
+        double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2 + n3 * n3);
+        B->quat[0] = n0 / nn; B->quat[1] = n1 / nn; B->quat[2] = n2 / nn; B->quat[3] = n3 / nn;
+    }
+
+    /* 10. aggregate bodies of the active zones (Eqs. aggregate_mass..rot_vel) */
+    if (agg && n_agg) *n_agg = orc_aggregates(n, r, M.im, x, v, w, nb, bodies, agg);
+
+    /* 11. outputs and the cache of this step */
+    for (int64_t c = 0; c < nc; ++c) {
+        keys_out[c] = rows[c].key;
+        if (lam_out) {
+            lam_out[4 * c] = rows[c].ln;
+            for (int k = 0; k < 3; ++k) lam_out[4 * c + 1 + k] = rows[c].lt[k];
+        }
+        if (colour_out) colour_out[c] = rows[c].colour;
+    }
+    if (st) {
+        int64_t np = 0;
+        for (int64_t c = 0; c < nc; ++c) np += rows[c].a >= 0;
+        st->contacts = nc;
+        st->pair_contacts = np;
+        st->colours = ncol;
+        st->sweeps = sweeps_done;
+        st->residual = R;
+        st->fallback_used = fallback;
+        st->learned_used = learned_used;
+        st->r1_first = r1;
+    }
+    free(ltprev); free(lnprev); free(v0);
+    free(cstart); free(corder); free(rows);
+    free(M.im); free(M.iI);
+    return nc;
+}
+
+double orc_natural_residual(const orc_params* P,
+                            int64_t n, const int64_t* id, const double* r, const double* rho,
+                            const double* x, const double* v, const double* w,
+                            int32_t nb, const orc_body* bodies,
+                            int32_t ns, const orc_shape* shapes,
+                            int64_t nc_in, const double* lam)
+{
+    inv_mass M;
+    make_inv_mass(P, n, r, rho, &M);
+    raw_contact* rc = NULL;
+    int64_t nc = detect_all(P, n, id, x, r, nb, bodies, ns, shapes, &rc);
+    if (nc != nc_in) { free(rc); free(M.im); free(M.iI); return -1.0; }
+    row* rows = (row*)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(row));
+    build_rows(P, id, r, &M, x, v, w, bodies, shapes, rc, nc, rows);
+    free(rc);
+    double* vv = (double*)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
+    double* ww = (double*)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) { vv[3 * i + k] = v[3 * i + k] + P->dt * P->g[k]; ww[3 * i + k] = w[3 * i + k]; }
+    for (int64_t c = 0; c < nc; ++c) {
+        rows[c].ln = lam[4 * c];
+        for (int k = 0; k < 3; ++k) rows[c].lt[k] = lam[4 * c + 1 + k];
+        double J[3];
+        for (int k = 0; k < 3; ++k) J[k] = rows[c].ln * rows[c].n[k] + rows[c].lt[k];
+        apply_impulse(&rows[c], &M, vv, ww, J);
+    }
+    double num = 0.0, den = 0.0, gdt = P->m.gamma_t / P->dt;
+    for (int64_t c = 0; c < nc; ++c) {
+        row* R = &rows[c];
+        double u[3];
+        rel_vel(R, vv, ww, u);
+        double un = dot3(R->n, u);
+        double ln2 = R->ln - (un + R->Sig * R->ln - R->q) / R->Dn;
+        if (ln2 < R->lo) ln2 = R->lo;
+        double ut[3] = {u[0] - un * R->n[0], u[1] - un * R->n[1], u[2] - un * R->n[2]};
+        double lt2[3];
+        for (int k = 0; k < 3; ++k) lt2[k] = R->lt[k] - (ut[k] + gdt * R->lt[k]) / R->Dt;
+        double lim = R->mu * fabs(R->ln);
+        double mag = sqrt(dot3(lt2, lt2));
+        if (mag > lim) { double s = mag > 0.0 ? lim / mag : 0.0; for (int k = 0; k < 3; ++k) lt2[k] *= s; }
+        double en = R->ln - ln2, et[3] = {R->lt[0] - lt2[0], R->lt[1] - lt2[1], R->lt[2] - lt2[2]};
+        num += R->Dn * en * en + R->Dt * dot3(et, et);
+        den += R->Dn * R->ln * R->ln + R->Dt * dot3(R->lt, R->lt);
+    }
+    free(vv); free(ww); free(rows); free(M.im); free(M.iI);
+    if (den > 0.0) return sqrt(num) / sqrt(den);
+    return num > 0.0 ? 1.0 : 0.0;
+}
+
+/* Eq. failure_plane: theta(phi, beta) = pi/2 - (phi + beta)/2. */
+double orc_failure_angle(double phi, double beta) { return 0.5 * PI - 0.5 * (phi + beta); }

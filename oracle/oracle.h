@@ -1,0 +1,178 @@
+/*
+ * oracle.h -- plain FP64 CPU reference of one time step of the agitated-soil
+ * (coarse-particle) system of Servin, Berglund & Nystedt, "A multiscale model
+ * of terrain dynamics for real-time earthmoving simulation" (arXiv 2011.00459).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no header, helper or constant with the
+ * GPU library: every formula here is written out independently from the paper.
+ *
+ * What it computes (section "Mesoscale model", Eq. eqmotb; Algorithm 1, the
+ * collision-detection, aggregate and mesoscale-PGS lines):
+ *   1. contact detection between spheres and against kinematic boundaries,
+ *   2. canonical contact order and warm-start matching,
+ *   3. Hertz-mapped SPOOK rows of the frictional-cohesive contact law
+ *      (Eqs. signCoul1-2, the Hertz mapping and the SPOOK MCP of section
+ *      "Contacting rigid multibodies"),
+ *   4. a greedy colouring in hashed-key priority order,
+ *   5. projected Gauss-Seidel sweeps in colour order,
+ *   6. symplectic position update x += dt v,
+ *   7. contact force/torque on each kinematic body,
+ *   8. aggregate-body mass/inertia/momentum of each active zone
+ *      (Eqs. aggregate_mass .. aggregate_rot_vel), in FP64.
+ */
+#ifndef TERRAIN_ORACLE_H
+#define TERRAIN_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_PLANE = 0, ORC_BOX = 1, ORC_HFIELD = 2 };
+enum { ORC_COLD = 0, ORC_PREV = 1, ORC_LEARNED = 2 };
+enum { ORC_BRUTE = 0, ORC_CELLS = 1 };
+
+typedef struct orc_material {
+    double rho;         /* particle density [kg/m^3] (used when rho array is NULL) */
+    double mu_t;        /* Coulomb friction coefficient */
+    double mu_r;        /* rolling resistance (must be 0: rows not modelled) */
+    double c_p;         /* particle cohesion [Pa] */
+    double E;           /* Young's modulus [Pa] */
+    double nu;          /* Poisson's ratio */
+    double restitution; /* must be 0 (no impact stage) */
+    double tau_n;       /* normal damping time [s]; <= 0 means 2 dt */
+    double gamma_t;     /* tangential regularisation (0 = ideal Coulomb) */
+    double kappa_c;     /* cohesive range as a fraction of the summed radii */
+    double kappa_min;   /* floor of the overlap used in the compliance */
+} orc_material;
+
+typedef struct orc_params {
+    double dt;
+    double g[3];
+    double grid_lo[3];   /* origin of the column grid used by the learned start */
+    double r_ref;        /* nominal particle radius (learned-start features) */
+    int32_t max_sweeps;
+    double tol;          /* 0: fixed number of sweeps */
+    int32_t warm;        /* ORC_COLD / ORC_PREV / ORC_LEARNED */
+    int32_t detect;      /* ORC_BRUTE or ORC_CELLS */
+    orc_material m;
+} orc_params;
+
+/* Kinematic body: pose, velocities and an optional active zone given as up to
+ * eight half-spaces in the body frame (inside iff n.y <= d for all planes). */
+typedef struct orc_body {
+    double pos[3];
+    double quat[4];      /* (w, x, y, z), unit */
+    double linvel[3];
+    double angvel[3];
+    int32_t nplanes;
+    double planes[8][4];
+} orc_body;
+
+/* Boundary shape attached to a body.
+ *   PLANE : surface n.y = d in the body frame, particles on the n side.
+ *   BOX   : oriented box, half extents half[], centre off[] in the body frame.
+ *   HFIELD: heights h[j*nx+i] at (ox + i l0, oy + j l0), world frame, static.
+ */
+typedef struct orc_shape {
+    int32_t type;
+    int32_t body;
+    double n[3];
+    double d;
+    double half[3];
+    double off[3];
+    int32_t nx, ny;
+    double ox, oy, l0;
+    const float* h;
+} orc_shape;
+
+/* MLP 12 -> 64 -> 64 -> 3 with SiLU, weights row-major W[out][in]. */
+typedef struct orc_mlp {
+    const double* W1; const double* b1;  /* 64x12, 64 */
+    const double* W2; const double* b2;  /* 64x64, 64 */
+    const double* W3; const double* b3;  /* 3x64,  3  */
+    double in_scale[12];                  /* feature normalisation (multiplied) */
+} orc_mlp;
+
+typedef struct orc_stats {
+    int64_t contacts;
+    int64_t pair_contacts;
+    int32_t colours;
+    int32_t sweeps;
+    double residual;
+    int32_t fallback_used;
+    int32_t learned_used;
+    double r1_first;     /* residual after the first sweep */
+} orc_stats;
+
+typedef struct orc_aggregate {
+    int32_t zone;        /* index of the body owning the zone */
+    int64_t n_particles;
+    double M;
+    double x[3];
+    double v[3];
+    double I[6];         /* xx, yy, zz, xy, xz, yz about x */
+    double w[3];
+    double L[3];
+} orc_aggregate;
+
+/* Contact detection only.  Writes the canonical (sorted) keys and the overlap
+ * of each contact.  Key of a pair (lower id a, higher id b) is a<<32 | b; key of
+ * a boundary contact with shape s is id<<32 | 0x80000000 | s.
+ * Returns the contact count, or -5 when it exceeds cap. */
+int64_t orc_detect(const orc_params* P, int64_t n, const int64_t* id,
+                   const double* x, const double* r,
+                   int32_t nb, const orc_body* bodies,
+                   int32_t ns, const orc_shape* shapes,
+                   int64_t cap, uint64_t* keys, double* delta);
+
+/* One full step.  x, v, w (3n each) and the body poses are updated in place.
+ * prev_keys/prev_lam (4 per contact: lambda_n, lambda_t xyz) is the previous
+ * step's cache (may be empty).  Outputs: keys_out, lam_out (4 per contact),
+ * colour_out (per contact), body_ft (6 per body: force, torque about the body
+ * origin, as impulse/dt), agg (one per body that owns a zone, in body order,
+ * count returned in *n_agg), resid (one per sweep done).
+ * Returns the contact count or a negative error. */
+int64_t orc_step(const orc_params* P,
+                 int64_t n, const int64_t* id, const double* r, const double* rho,
+                 double* x, double* v, double* w,
+                 int32_t nb, orc_body* bodies,
+                 int32_t ns, const orc_shape* shapes,
+                 int64_t nprev, const uint64_t* prev_keys, const double* prev_lam,
+                 const orc_mlp* mlp,
+                 int64_t cap, uint64_t* keys_out, double* lam_out, int32_t* colour_out,
+                 orc_stats* st, double* body_ft,
+                 orc_aggregate* agg, int32_t* n_agg, double* resid);
+
+/* Aggregate bodies (Eqs. aggregate_mass .. aggregate_rot_vel) of the zones
+ * of the bodies that have one, for the state (x, v, w); inv_m is 1/m per
+ * particle.  Returns the number written to agg (one per body with a zone). */
+int32_t orc_aggregates(int64_t n, const double* r, const double* inv_m, const double* x, const double* v,
+                       const double* w, int32_t nb, const orc_body* bodies, orc_aggregate* agg);
+
+/* Natural-map complementarity residual of the MCP built for the state
+ * (x, v, w) with impulses lam (4 per canonical contact), evaluated at the
+ * velocities those impulses give.  Used only by tests. */
+double orc_natural_residual(const orc_params* P,
+                            int64_t n, const int64_t* id, const double* r, const double* rho,
+                            const double* x, const double* v, const double* w,
+                            int32_t nb, const orc_body* bodies,
+                            int32_t ns, const orc_shape* shapes,
+                            int64_t nc, const double* lam);
+
+/* MLP in FP64: forward for a batch (feat: B x 12, out: B x 3), and the
+ * gradient of 0.5 * mean_b ||y_b - label_b||^2 w.r.t. every parameter
+ * (grads laid out W1,b1,W2,b2,W3,b3 contiguously).  Returns the loss. */
+void orc_mlp_forward(const orc_mlp* net, int64_t B, const double* feat, double* out);
+double orc_mlp_loss_grad(const orc_mlp* net, int64_t B, const double* feat,
+                         const double* label, double* grads);
+
+/* Failure-plane angle of the active zone, Eq. failure_plane. */
+double orc_failure_angle(double phi, double beta);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

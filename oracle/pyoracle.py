@@ -1,0 +1,347 @@
+"""ctypes wrapper of the FP64 CPU oracle (``oracle/liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product package.  It marshals
+a plain scene description (numpy arrays and dicts, see ``scenegen``) into the
+oracle's own C structs; it contains none of the method's arithmetic.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+PLANE, BOX, HFIELD = 0, 1, 2
+COLD, PREV, LEARNED = 0, 1, 2
+BRUTE, CELLS = 0, 1
+_SHAPE_CODES = {"plane": PLANE, "box": BOX, "hfield": HFIELD}
+_WARM_CODES = {"cold": COLD, "prev": PREV, "learned": LEARNED}
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with -O2 -ffp-contract=off (plain C, libm only)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-fPIC", "-shared",
+           os.path.join(HERE, "oracle.c"), "-o", LIB_PATH + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class Material(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("rho", "mu_t", "mu_r", "c_p", "E", "nu", "restitution", "tau_n",
+                 "gamma_t", "kappa_c", "kappa_min")]
+
+
+class Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("g", C.c_double * 3), ("grid_lo", C.c_double * 3),
+                ("r_ref", C.c_double), ("max_sweeps", C.c_int32), ("tol", C.c_double),
+                ("warm", C.c_int32), ("detect", C.c_int32), ("m", Material)]
+
+
+class Body(C.Structure):
+    _fields_ = [("pos", C.c_double * 3), ("quat", C.c_double * 4), ("linvel", C.c_double * 3),
+                ("angvel", C.c_double * 3), ("nplanes", C.c_int32), ("planes", (C.c_double * 4) * 8)]
+
+
+class Shape(C.Structure):
+    _fields_ = [("type", C.c_int32), ("body", C.c_int32), ("n", C.c_double * 3), ("d", C.c_double),
+                ("half", C.c_double * 3), ("off", C.c_double * 3), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("ox", C.c_double), ("oy", C.c_double), ("l0", C.c_double), ("h", C.POINTER(C.c_float))]
+
+
+class Mlp(C.Structure):
+    _fields_ = [("W1", C.POINTER(C.c_double)), ("b1", C.POINTER(C.c_double)),
+                ("W2", C.POINTER(C.c_double)), ("b2", C.POINTER(C.c_double)),
+                ("W3", C.POINTER(C.c_double)), ("b3", C.POINTER(C.c_double)),
+                ("in_scale", C.c_double * 12)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("contacts", C.c_int64), ("pair_contacts", C.c_int64), ("colours", C.c_int32),
+                ("sweeps", C.c_int32), ("residual", C.c_double), ("fallback_used", C.c_int32),
+                ("learned_used", C.c_int32), ("r1_first", C.c_double)]
+
+
+class Aggregate(C.Structure):
+    _fields_ = [("zone", C.c_int32), ("n_particles", C.c_int64), ("M", C.c_double),
+                ("x", C.c_double * 3), ("v", C.c_double * 3), ("I", C.c_double * 6),
+                ("w", C.c_double * 3), ("L", C.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        i64p = C.POINTER(C.c_int64)
+        u64p = C.POINTER(C.c_uint64)
+        L.orc_detect.restype = C.c_int64
+        L.orc_detect.argtypes = [C.POINTER(Params), C.c_int64, i64p, dp, dp, C.c_int32, C.POINTER(Body),
+                                 C.c_int32, C.POINTER(Shape), C.c_int64, u64p, dp]
+        L.orc_step.restype = C.c_int64
+        L.orc_step.argtypes = [C.POINTER(Params), C.c_int64, i64p, dp, dp, dp, dp, dp,
+                               C.c_int32, C.POINTER(Body), C.c_int32, C.POINTER(Shape),
+                               C.c_int64, u64p, dp, C.POINTER(Mlp),
+                               C.c_int64, u64p, dp, C.POINTER(C.c_int32), C.POINTER(Stats), dp,
+                               C.POINTER(Aggregate), C.POINTER(C.c_int32), dp]
+        L.orc_aggregates.restype = C.c_int32
+        L.orc_aggregates.argtypes = [C.c_int64, dp, dp, dp, dp, dp, C.c_int32, C.POINTER(Body),
+                                     C.POINTER(Aggregate)]
+        L.orc_natural_residual.restype = C.c_double
+        L.orc_natural_residual.argtypes = [C.POINTER(Params), C.c_int64, i64p, dp, dp, dp, dp, dp,
+                                           C.c_int32, C.POINTER(Body), C.c_int32, C.POINTER(Shape),
+                                           C.c_int64, dp]
+        L.orc_mlp_forward.restype = None
+        L.orc_mlp_forward.argtypes = [C.POINTER(Mlp), C.c_int64, dp, dp]
+        L.orc_mlp_loss_grad.restype = C.c_double
+        L.orc_mlp_loss_grad.argtypes = [C.POINTER(Mlp), C.c_int64, dp, dp, dp]
+        L.orc_failure_angle.restype = C.c_double
+        L.orc_failure_angle.argtypes = [C.c_double, C.c_double]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+DEFAULT_MATERIAL = dict(rho=2000.0, mu_t=0.6, mu_r=0.0, c_p=1000.0, E=1e9, nu=0.15, restitution=0.0,
+                        tau_n=0.0, gamma_t=0.0, kappa_c=0.025, kappa_min=1e-4)
+
+
+def make_params(spec: dict, detect: int = CELLS) -> Params:
+    P = Params()
+    P.dt = spec["dt"]
+    for k in range(3):
+        P.g[k] = spec["gravity"][k]
+        P.grid_lo[k] = spec.get("grid_lo", (0.0, 0.0, 0.0))[k]
+    P.r_ref = spec.get("r_ref", 0.05)
+    P.max_sweeps = spec["max_sweeps"]
+    P.tol = spec.get("tol", 0.0)
+    P.warm = _WARM_CODES[spec.get("warm_start", "cold")]
+    P.detect = detect
+    mat = dict(DEFAULT_MATERIAL)
+    mat.update(spec.get("material", {}))
+    for k, v in mat.items():
+        setattr(P.m, k, v)
+    return P
+
+
+class _Bodies:
+    """Holds the ctypes arrays for bodies and shapes (and the heightfields)."""
+
+    def __init__(self, bodies: list):
+        self.keep = []
+        nb = len(bodies)
+        self.nb = nb
+        self.bodies = (Body * max(nb, 1))()
+        shapes = []
+        for bi, b in enumerate(bodies):
+            B = self.bodies[bi]
+            for k in range(3):
+                B.pos[k] = b["pos"][k]
+                B.linvel[k] = b.get("linvel", (0, 0, 0))[k]
+                B.angvel[k] = b.get("angvel", (0, 0, 0))[k]
+            q = b.get("quat", (1.0, 0.0, 0.0, 0.0))
+            for k in range(4):
+                B.quat[k] = q[k]
+            planes = np.asarray(b.get("zone_planes", np.zeros((0, 4))), dtype=np.float64).reshape(-1, 4)
+            B.nplanes = len(planes)
+            for p in range(len(planes)):
+                for k in range(4):
+                    B.planes[p][k] = planes[p, k]
+            for s in b.get("shapes", []):
+                shapes.append((bi, s))
+        self.ns = len(shapes)
+        self.shapes = (Shape * max(self.ns, 1))()
+        for si, (bi, s) in enumerate(shapes):
+            S = self.shapes[si]
+            S.type = _SHAPE_CODES[s["type"]]
+            S.body = bi
+            for k in range(3):
+                S.n[k] = s.get("n", (0, 0, 1))[k]
+                S.half[k] = s.get("half", (0, 0, 0))[k]
+                S.off[k] = s.get("off", (0, 0, 0))[k]
+            S.d = s.get("d", 0.0)
+            if s["type"] == "hfield":
+                h = np.ascontiguousarray(s["h"], dtype=np.float32)
+                self.keep.append(h)
+                S.nx, S.ny = int(s["nx"]), int(s["ny"])
+                S.ox, S.oy, S.l0 = s["ox"], s["oy"], s["l0"]
+                S.h = h.ctypes.data_as(C.POINTER(C.c_float))
+
+    def poses(self):
+        out = []
+        for bi in range(self.nb):
+            B = self.bodies[bi]
+            out.append(dict(pos=np.array(B.pos[:]), quat=np.array(B.quat[:])))
+        return out
+
+
+def detect(spec: dict, method: int = CELLS, cap: int | None = None):
+    """Sorted contact keys and overlaps of the spec's particle state."""
+    L = lib()
+    P = make_params(spec, method)
+    x = _c64(spec["x"]).reshape(-1, 3)
+    n = len(x)
+    r = _c64(spec["r"])
+    ids = np.ascontiguousarray(spec.get("id", np.arange(n)), dtype=np.int64)
+    bb = _Bodies(spec.get("bodies", []))
+    cap = cap or max(64, 16 * n + 64)
+    keys = np.zeros(cap, dtype=np.uint64)
+    delta = np.zeros(cap, dtype=np.float64)
+    nc = L.orc_detect(C.byref(P), n, ids.ctypes.data_as(C.POINTER(C.c_int64)), _dp(x), _dp(r),
+                      bb.nb, bb.bodies, bb.ns, bb.shapes, cap,
+                      keys.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(delta))
+    if nc < 0:
+        raise RuntimeError(f"orc_detect failed ({nc})")
+    return keys[:nc].copy(), delta[:nc].copy()
+
+
+def mlp_struct(weights: dict):
+    """Build an Mlp struct from a dict of float64 arrays (kept alive by the caller)."""
+    m = Mlp()
+    keep = {}
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        a = np.ascontiguousarray(weights[k], dtype=np.float64)
+        keep[k] = a
+        setattr(m, k, _dp(a))
+    sc = np.asarray(weights.get("in_scale", np.ones(12)), dtype=np.float64)
+    for i in range(12):
+        m.in_scale[i] = sc[i]
+    return m, keep
+
+
+class OracleScene:
+    """A single-environment scene stepped by the oracle; holds its own state."""
+
+    def __init__(self, spec: dict, detect_method: int = CELLS, mlp: dict | None = None):
+        self.spec = spec
+        self.P = make_params(spec, detect_method)
+        self.x = _c64(spec["x"]).reshape(-1, 3).copy()
+        n = len(self.x)
+        self.n = n
+        self.v = _c64(spec.get("v", np.zeros((n, 3)))).reshape(-1, 3).copy()
+        self.w = _c64(spec.get("w", np.zeros((n, 3)))).reshape(-1, 3).copy()
+        self.r = _c64(spec["r"]).copy()
+        self.rho = None if spec.get("rho") is None else _c64(spec["rho"]).copy()
+        self.ids = np.ascontiguousarray(spec.get("id", np.arange(n)), dtype=np.int64)
+        self.bb = _Bodies(spec.get("bodies", []))
+        self.prev_keys = np.zeros(0, dtype=np.uint64)
+        self.prev_lam = np.zeros((0, 4), dtype=np.float64)
+        self.mlp = None
+        if mlp is not None:
+            self.mlp, self._mlp_keep = mlp_struct(mlp)
+        self.cap = max(1024, 16 * n + 1024)
+        self.last = None
+
+    def step(self):
+        L = lib()
+        cap = self.cap
+        keys = np.zeros(cap, dtype=np.uint64)
+        lam = np.zeros((cap, 4), dtype=np.float64)
+        col = np.zeros(cap, dtype=np.int32)
+        st = Stats()
+        nb = self.bb.nb
+        ft = np.zeros((max(nb, 1), 6), dtype=np.float64)
+        agg = (Aggregate * max(nb, 1))()
+        nagg = C.c_int32(0)
+        resid = np.zeros(max(self.P.max_sweeps, 1) + 1, dtype=np.float64)
+        rho_p = _dp(self.rho) if self.rho is not None else C.POINTER(C.c_double)()
+        mlp_p = C.byref(self.mlp) if self.mlp is not None else C.POINTER(Mlp)()
+        pk = np.ascontiguousarray(self.prev_keys)
+        pl = np.ascontiguousarray(self.prev_lam)
+        nc = L.orc_step(C.byref(self.P), self.n, self.ids.ctypes.data_as(C.POINTER(C.c_int64)),
+                        _dp(self.r), rho_p, _dp(self.x), _dp(self.v), _dp(self.w),
+                        nb, self.bb.bodies, self.bb.ns, self.bb.shapes,
+                        len(pk), pk.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(pl), mlp_p,
+                        cap, keys.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(lam),
+                        col.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(st), _dp(ft),
+                        agg, C.byref(nagg), _dp(resid))
+        if nc < 0:
+            raise RuntimeError(f"orc_step failed ({nc})")
+        self.prev_keys = keys[:nc].copy()
+        self.prev_lam = lam[:nc].copy()
+        aggs = []
+        for a in agg[: nagg.value]:
+            aggs.append(dict(zone=a.zone, n_particles=a.n_particles, M=a.M, x=np.array(a.x[:]),
+                             v=np.array(a.v[:]), I=np.array(a.I[:]), w=np.array(a.w[:]),
+                             L=np.array(a.L[:])))
+        self.last = dict(keys=keys[:nc].copy(), lam=lam[:nc].copy(), colour=col[:nc].copy(),
+                         contacts=st.contacts, pair_contacts=st.pair_contacts, colours=st.colours,
+                         sweeps=st.sweeps, residual=st.residual, fallback_used=st.fallback_used,
+                         learned_used=st.learned_used, r1=st.r1_first,
+                         resid=resid[: st.sweeps].copy(), body_ft=ft[:nb].copy(), aggregates=aggs)
+        return self.last
+
+    def natural_residual(self, x, v, w, lam):
+        L = lib()
+        x = _c64(x); v = _c64(v); w = _c64(w); lam = _c64(lam)
+        rho_p = _dp(self.rho) if self.rho is not None else C.POINTER(C.c_double)()
+        return L.orc_natural_residual(C.byref(self.P), self.n, self.ids.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      _dp(self.r), rho_p, _dp(x), _dp(v), _dp(w),
+                                      self.bb.nb, self.bb.bodies, self.bb.ns, self.bb.shapes,
+                                      len(lam), _dp(lam))
+
+
+def aggregates(x, v, w, r, mass, bodies: list):
+    """Aggregate bodies of the zones of `bodies` for the given particle state."""
+    x = _c64(x).reshape(-1, 3)
+    n = len(x)
+    v = _c64(v).reshape(-1, 3)
+    w = _c64(w).reshape(-1, 3)
+    r = _c64(r)
+    im = 1.0 / _c64(mass)
+    bb = _Bodies(bodies)
+    agg = (Aggregate * max(bb.nb, 1))()
+    na = lib().orc_aggregates(n, _dp(r), _dp(im), _dp(x), _dp(v), _dp(w), bb.nb, bb.bodies, agg)
+    return [dict(zone=a.zone, n_particles=a.n_particles, M=a.M, x=np.array(a.x[:]), v=np.array(a.v[:]),
+                 I=np.array(a.I[:]), w=np.array(a.w[:]), L=np.array(a.L[:])) for a in agg[:na]]
+
+
+def mlp_forward(weights: dict, feat: np.ndarray) -> np.ndarray:
+    m, keep = mlp_struct(weights)
+    f = _c64(feat).reshape(-1, 12)
+    out = np.zeros((len(f), 3))
+    lib().orc_mlp_forward(C.byref(m), len(f), _dp(f), _dp(out))
+    return out
+
+
+N_MLP_PARAMS = 64 * 12 + 64 + 64 * 64 + 64 + 3 * 64 + 3
+
+
+def mlp_loss_grad(weights: dict, feat: np.ndarray, label: np.ndarray):
+    m, keep = mlp_struct(weights)
+    f = _c64(feat).reshape(-1, 12)
+    lb = _c64(label).reshape(-1, 3)
+    g = np.zeros(N_MLP_PARAMS)
+    loss = lib().orc_mlp_loss_grad(C.byref(m), len(f), _dp(f), _dp(lb), _dp(g))
+    o = 0
+    out = {}
+    for k, shp in (("W1", (64, 12)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
+                   ("W3", (3, 64)), ("b3", (3,))):
+        sz = int(np.prod(shp))
+        out[k] = g[o:o + sz].reshape(shp)
+        o += sz
+    return loss, out
+
+
+def failure_angle(phi: float, beta: float) -> float:
+    return lib().orc_failure_angle(phi, beta)

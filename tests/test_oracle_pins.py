@@ -1,0 +1,547 @@
+"""Pins of the FP64 oracle against what the paper and mechanics fix.
+
+Each test checks the oracle against something other than its own formulas:
+exact rational arithmetic, closed-form mechanics of one sphere or a column,
+conservation laws, an independent round-based colouring, finite differences,
+and the worked relations printed in the paper.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import pyoracle as O
+from paper_2011_00459_amd import scenegen as SG
+
+G = 9.81
+DT = 1.0 / 60.0
+ESTAR = 1e9 / (2.0 * (1.0 - 0.15 ** 2))
+
+
+def sphere_mass(r, rho=2000.0):
+    return rho * 4.0 / 3.0 * math.pi * r ** 3
+
+
+def base_spec(x, r, bodies, mu=0.0, c=0.0, sweeps=50, g=(0.0, 0.0, -G), v=None, w=None, **mat):
+    n = len(x)
+    spec = dict(x=np.asarray(x, dtype=np.float64).reshape(-1, 3), r=np.asarray(r, dtype=np.float64),
+                v=np.zeros((n, 3)) if v is None else np.asarray(v, dtype=np.float64),
+                w=np.zeros((n, 3)) if w is None else np.asarray(w, dtype=np.float64),
+                id=np.arange(n), bodies=bodies, material=SG.material(mu, c, **mat), dt=DT, gravity=g,
+                max_sweeps=sweeps, tol=0.0, warm_start="cold", grid_lo=(-5.0, -5.0, -5.0), r_ref=0.05)
+    return spec
+
+
+def floor_body(z=0.0):
+    return dict(pos=(0.0, 0.0, 0.0), quat=(1.0, 0.0, 0.0, 0.0), shapes=[dict(type="plane", n=(0, 0, 1), d=z)])
+
+
+# --------------------------------------------------------------------------
+# Detection: cell list == brute force == exact rational predicate
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("cohesion", [0.0, 1000.0])
+def test_detection_cells_equal_bruteforce(cohesion):
+    rng = np.random.default_rng(7)
+    n = 900
+    r = SG.fp32(0.05 * rng.uniform(0.9, 1.1, n))
+    x = SG.fp32(rng.uniform(-0.45, 0.45, (n, 3)) * np.array([1.0, 1.0, 1.0]))
+    spec = base_spec(x, r, [SG.walls_body(1.0, 1.0, -0.45)], c=cohesion)
+    kb, db = O.detect(spec, O.BRUTE)
+    kc, dc = O.detect(spec, O.CELLS)
+    assert len(kb) > 2 * n
+    assert np.array_equal(kb, kc)
+    assert np.array_equal(db, dc)
+    assert np.all(np.diff(kb.astype(np.float64)) > 0)  # canonical, strictly sorted
+
+
+def test_detection_matches_exact_rational_predicate():
+    rng = np.random.default_rng(11)
+    n = 300
+    r = SG.fp32(0.05 * rng.uniform(0.9, 1.1, n))
+    x = SG.fp32(rng.uniform(-0.3, 0.3, (n, 3)))
+    kc = 0.025
+    spec = base_spec(x, r, [], c=1000.0)
+    keys, _ = O.detect(spec, O.BRUTE)
+    got = set(int(k) for k in keys)
+    kcf = Fraction(kc)
+    undecided = 0
+    for i in range(n):
+        xi = [Fraction(float(v)) for v in x[i]]
+        for j in range(i + 1, n):
+            d2 = sum((Fraction(float(x[j, k])) - xi[k]) ** 2 for k in range(3))
+            R = (Fraction(float(r[i])) + Fraction(float(r[j]))) * (1 + kcf)
+            gap = d2 - R * R
+            key = (i << 32) | j
+            if abs(gap) <= Fraction(1, 10 ** 12) * R * R:
+                undecided += 1
+                continue
+            assert (gap < 0) == (key in got), (i, j, float(gap))
+    assert undecided < 3
+
+
+def test_detection_boundary_cases_at_one_ulp():
+    # two spheres of radius 0.5 at distance exactly 1: touching is not a contact
+    spec = base_spec([[0, 0, 0], [1.0, 0, 0]], [0.5, 0.5], [])
+    assert len(O.detect(spec, O.BRUTE)[0]) == 0
+    spec = base_spec([[0, 0, 0], [np.nextafter(1.0, 0.0), 0, 0]], [0.5, 0.5], [])
+    assert len(O.detect(spec, O.BRUTE)[0]) == 1
+    # a sphere exactly resting on a plane is not in contact; one ulp lower is
+    spec = base_spec([[0, 0, 0.5]], [0.5], [floor_body()])
+    assert len(O.detect(spec, O.BRUTE)[0]) == 0
+    spec = base_spec([[0, 0, np.nextafter(0.5, 0.0)]], [0.5], [floor_body()])
+    k, d = O.detect(spec, O.BRUTE)
+    assert len(k) == 1 and int(k[0]) == (0x80000000 | 0) and d[0] > 0.0
+
+
+def test_box_face_equals_plane_and_inside_rule():
+    # a sphere under the top face of an axis-aligned box sees the same overlap
+    # as against the equivalent plane
+    r = 0.05
+    z = 0.5 + r - 1e-4
+    box = dict(pos=(0.0, 0.0, 0.0), quat=(1, 0, 0, 0), shapes=[dict(type="box", half=(1.0, 1.0, 0.5))])
+    plane = dict(pos=(0.0, 0.0, 0.0), quat=(1, 0, 0, 0), shapes=[dict(type="plane", n=(0, 0, 1), d=0.5)])
+    kb, db = O.detect(base_spec([[0.1, -0.2, z]], [r], [box]), O.BRUTE)
+    kp, dp = O.detect(base_spec([[0.1, -0.2, z]], [r], [plane]), O.BRUTE)
+    assert len(kb) == 1 and len(kp) == 1
+    assert db[0] == pytest.approx(dp[0], rel=1e-12, abs=1e-15)
+    # centre inside: least-penetration face (+z here), overlap r + depth
+    k, d = O.detect(base_spec([[0.3, 0.2, 0.45]], [r], [box]), O.BRUTE)
+    assert d[0] == pytest.approx(r + 0.05, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Hertz / SPOOK mapping: resting column (closed form)
+# --------------------------------------------------------------------------
+def test_resting_column_impulses_and_overlaps():
+    K, r = 5, 0.05
+    m = sphere_mass(r)
+    x = [[0.0, 0.0, r + 2 * r * k] for k in range(K)]
+    spec = base_spec(x, [r] * K, [floor_body()], mu=0.0, c=0.0, sweeps=300)
+    sc = O.OracleScene(spec)
+    for _ in range(400):
+        out = sc.step()
+    keys, lam = out["keys"], out["lam"]
+    kn_pair = ESTAR * math.sqrt(r) / 3.0          # d* = (1/2r + 1/2r)^-1 = r
+    kn_wall = ESTAR * math.sqrt(2 * r) / 3.0      # d* = 2r
+    assert kn_pair == pytest.approx(3.81e7, rel=2e-3)   # printed-scale check of k_n
+    assert kn_wall == pytest.approx(5.39e7, rel=2e-3)
+    found = 0
+    for key, l in zip(keys, lam):
+        a, b = int(key) >> 32, int(key) & 0xFFFFFFFF
+        if b & 0x80000000:
+            assert a == 0
+            assert l[0] == pytest.approx(K * m * G * DT, rel=1e-7)
+            delta = r - sc.x[0, 2]
+            assert delta == pytest.approx((K * m * G / kn_wall) ** (2.0 / 3.0), rel=1e-5)
+            found += 1
+        else:
+            k_above = K - b  # contacts from the top carry k m g dt
+            assert l[0] == pytest.approx(k_above * m * G * DT, rel=1e-7)
+            delta = 2 * r - (sc.x[b, 2] - sc.x[a, 2])
+            assert delta == pytest.approx((k_above * m * G / kn_pair) ** (2.0 / 3.0), rel=1e-5)
+            found += 1
+    assert found == K
+    assert np.max(np.abs(sc.v)) < 1e-9
+
+
+def test_spook_tau_to_zero_limit():
+    # Ideal stiff constraint: G v_{n+1} = -(4/dt) g (scaled row: g' = -4/5 delta)
+    r, delta = 0.05, 1e-4
+    spec = base_spec([[0.0, 0.0, r - delta]], [r], [floor_body()], g=(0.0, 0.0, 0.0), sweeps=1,
+                     E=1e18, tau_n=1e-14)
+    sc = O.OracleScene(spec)
+    sc.step()
+    assert sc.v[0, 2] == pytest.approx((4.0 / DT) * 0.8 * delta, rel=1e-6)
+
+
+def test_zero_restitution_drop_does_not_rebound():
+    # restitution 0 and tau_n = 2 dt: an impact is damped out, no rebound
+    # (the damping of the printed SPOOK form is strong at tau = 2 dt)
+    r, h0 = 0.05, 0.3
+    spec = base_spec([[0.0, 0.0, r + h0]], [r], [floor_body()], mu=0.5, sweeps=5)
+    sc = O.OracleScene(spec)
+    touched, peak_after = False, -1.0
+    for _ in range(150):
+        out = sc.step()
+        if out["contacts"] > 0:
+            touched = True
+        if touched:
+            peak_after = max(peak_after, sc.x[0, 2] - r)
+    assert touched
+    assert peak_after < 0.01 * h0
+    assert abs(sc.v[0, 2]) < 1e-6
+
+
+# --------------------------------------------------------------------------
+# Coulomb friction: sliding sphere (closed form, exact per step)
+# --------------------------------------------------------------------------
+def test_sliding_sphere_stick_slip():
+    r, mu, v0 = 0.05, 0.3, 2.0
+    m = sphere_mass(r)
+    kn = ESTAR * math.sqrt(2 * r) / 3.0
+    d0 = (m * G / kn) ** (2.0 / 3.0)
+    spec = base_spec([[0.0, 0.0, r - d0]], [r], [floor_body()], mu=mu, v=[[v0, 0.0, 0.0]], sweeps=1)
+    sc = O.OracleScene(spec)
+    l2 = r - d0 / 2
+    I = 0.4 * m * r * r
+    kappa = m * l2 * l2 / I
+    vprev, wprev = v0, 0.0
+    slipping_steps = 0
+    for _ in range(120):
+        sc.step()
+        vx, wy = sc.v[0, 0], sc.w[0, 1]
+        slip_prev = vprev - l2 * wprev
+        if slip_prev > mu * G * DT * (1 + kappa) * (1 + 1e-9):
+            assert vx - vprev == pytest.approx(-mu * G * DT, rel=1e-9)
+            assert wy - wprev == pytest.approx(mu * G * DT * m * l2 / I, rel=1e-9)
+            slipping_steps += 1
+        vprev, wprev = vx, wy
+    assert slipping_steps > 10
+    assert sc.v[0, 0] == pytest.approx(v0 * kappa / (1 + kappa), rel=1e-9)
+    assert sc.v[0, 0] == pytest.approx(5.0 / 7.0 * v0, rel=2e-3)
+    assert abs(sc.v[0, 0] - l2 * sc.w[0, 1]) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Heightfield: incline rolls or slips per the closed form; flat == plane
+# --------------------------------------------------------------------------
+def incline_hfield(tan_theta=0.5):
+    l0, n = 0.25, 17
+    ox = oy = -2.0
+    xs = ox + l0 * np.arange(n)
+    h = np.tile((-tan_theta * xs).astype(np.float32), (n, 1))  # h[j, i]
+    return dict(pos=(0.0, 0.0, 0.0), quat=(1, 0, 0, 0),
+                shapes=[dict(type="hfield", nx=n, ny=n, ox=ox, oy=oy, l0=l0, h=h.ravel())])
+
+
+@pytest.mark.parametrize("mu,rolls", [(0.3, True), (0.1, False)])
+def test_incline_roll_or_slip(mu, rolls):
+    tan_t = 0.5
+    th = math.atan(tan_t)
+    r = 0.05
+    m = sphere_mass(r)
+    kn = ESTAR * math.sqrt(2 * r) / 3.0
+    d0 = (m * G * math.cos(th) / kn) ** (2.0 / 3.0)
+    nrm = np.array([math.sin(th), 0.0, math.cos(th)])
+    x0 = (r - d0) * nrm  # surface passes through the origin
+    spec = base_spec([x0], [r], [incline_hfield(tan_t)], mu=mu, sweeps=1)
+    sc = O.OracleScene(spec)
+    sdir = np.array([math.cos(th), 0.0, -math.sin(th)])  # down-slope
+    l2 = r - d0 / 2
+    I = 0.4 * m * r * r
+    vs_prev = 0.0
+    for k in range(20):
+        sc.step()
+        vs = float(sc.v[0] @ sdir)
+        dv = vs - vs_prev
+        if rolls:
+            expect = G * math.sin(th) * DT / (1.0 + I / (m * l2 * l2))
+        else:
+            expect = G * (math.sin(th) - mu * math.cos(th)) * DT
+        assert dv == pytest.approx(expect, rel=2e-6), k
+        vs_prev = vs
+    if rolls:
+        assert (5.0 / 7.0) * G * math.sin(th) * DT == pytest.approx(expect, rel=3e-3)
+
+
+def test_tilted_hfield_matches_plane():
+    tan_t = 0.5
+    th = math.atan(tan_t)
+    r = 0.05
+    nrm = (math.sin(th), 0.0, math.cos(th))
+    plane = dict(pos=(0.0, 0.0, 0.0), quat=(1, 0, 0, 0), shapes=[dict(type="plane", n=nrm, d=0.0)])
+    x0 = (r - 3e-5) * np.array(nrm)
+    a = O.OracleScene(base_spec([x0], [r], [incline_hfield(tan_t)], mu=0.3, sweeps=1))
+    b = O.OracleScene(base_spec([x0], [r], [plane], mu=0.3, sweeps=1))
+    for _ in range(10):
+        a.step()
+        b.step()
+    assert np.allclose(a.v, b.v, rtol=1e-6, atol=1e-9)
+    assert np.allclose(a.x, b.x, rtol=1e-9, atol=1e-12)
+
+
+def test_flat_hfield_equals_plane_exactly():
+    spec = SG.column_scene(seed=4, n=120, footprint=0.6, sweeps=20)
+    flat = np.zeros(8 * 8, dtype=np.float32)
+    hf = dict(type="hfield", nx=8, ny=8, ox=-2.0, oy=-2.0, l0=0.5, h=flat)
+    spec_hf = dict(spec)
+    walls = dict(spec["bodies"][0])
+    walls_hf = dict(walls)
+    walls_hf["shapes"] = [hf] + walls["shapes"][1:]
+    spec_hf["bodies"] = [walls_hf]
+    a, b = O.OracleScene(spec), O.OracleScene(spec_hf)
+    for _ in range(30):
+        oa, ob = a.step(), b.step()
+        assert np.array_equal(oa["keys"], ob["keys"])
+    assert np.array_equal(a.x, b.x)
+    assert np.array_equal(a.v, b.v)
+    assert np.array_equal(oa["lam"], ob["lam"])
+
+
+# --------------------------------------------------------------------------
+# Cohesion: a hanging sphere holds iff m g < c_p pi r^2
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("c,holds", [(1000.0, False), (2000.0, True)])
+def test_hanging_cohesive_sphere(c, holds):
+    r = 0.05
+    m = sphere_mass(r)
+    assert (m * G < c * math.pi * r * r) == holds
+    ceiling = dict(pos=(0.0, 0.0, 0.0), quat=(1, 0, 0, 0), shapes=[dict(type="plane", n=(0, 0, -1), d=-1.0)])
+    # sphere just touching the ceiling z = 1 from below
+    spec = base_spec([[0.0, 0.0, 1.0 - r]], [r], [ceiling], mu=0.5, c=c, sweeps=5)
+    sc = O.OracleScene(spec)
+    for _ in range(60):
+        out = sc.step()
+    gap = (1.0 - r) - sc.x[0, 2]
+    if holds:
+        assert gap < 2 * 0.025 * r
+        assert len(out["keys"]) == 1
+        assert out["lam"][0, 0] == pytest.approx(-m * G * DT, rel=1e-6)
+    else:
+        assert gap > 0.5
+        assert len(out["keys"]) == 0
+
+
+# --------------------------------------------------------------------------
+# Conservation: no gravity, no boundaries
+# --------------------------------------------------------------------------
+def test_momentum_and_angular_momentum_conserved():
+    rng = np.random.default_rng(5)
+    n = 200
+    r = SG.fp32(0.05 * rng.uniform(0.9, 1.1, n))
+    x, _ = SG.lattice(rng, n, 0.6, 0.6, 0.098, r)
+    v = rng.normal(0, 0.5, (n, 3))
+    w = rng.normal(0, 3.0, (n, 3))
+    spec = base_spec(x, r, [], mu=0.5, c=1000.0, g=(0.0, 0.0, 0.0), v=v, w=w, sweeps=30)
+    sc = O.OracleScene(spec)
+    m = sphere_mass(r)
+    I = 0.4 * m * r * r
+
+    def moments():
+        p = (m[:, None] * sc.v).sum(0)
+        L = (m[:, None] * np.cross(sc.x, sc.v)).sum(0) + (I[:, None] * sc.w).sum(0)
+        return p, L
+
+    p0, L0 = moments()
+    total = 0
+    for _ in range(20):
+        total += sc.step()["contacts"]
+    p1, L1 = moments()
+    assert total > 100
+    scale_p = (m[:, None] * np.abs(sc.v)).sum()
+    assert np.allclose(p0, p1, rtol=0, atol=1e-12 * scale_p)
+    scale_L = (m[:, None] * np.abs(np.cross(sc.x, sc.v))).sum() + (I[:, None] * np.abs(sc.w)).sum()
+    assert np.allclose(L0, L1, rtol=0, atol=1e-12 * scale_L)
+
+
+# --------------------------------------------------------------------------
+# Colouring: valid, order independent, equal to parallel Jones-Plassmann
+# --------------------------------------------------------------------------
+def splitmix64(x):
+    M = (1 << 64) - 1
+    z = (x + 0x9E3779B97F4A7C15) & M
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+    return z ^ (z >> 31)
+
+
+def parts(key):
+    a, b = key >> 32, key & 0xFFFFFFFF
+    return (a,) if b & 0x80000000 else (a, b)
+
+
+def jones_plassmann_rounds(keys):
+    """Parallel JP: each round, every uncoloured vertex that beats all its
+    uncoloured neighbours takes the least colour free among its coloured ones."""
+    keys = [int(k) for k in keys]
+    pr = {k: (splitmix64(k), k) for k in keys}
+    inc = {}
+    for k in keys:
+        for p in parts(k):
+            inc.setdefault(p, []).append(k)
+    nbr = {k: set(e for p in parts(k) for e in inc[p] if e != k) for k in keys}
+    col = {}
+    rounds = 0
+    while len(col) < len(keys):
+        rounds += 1
+        winners = [k for k in keys if k not in col and all(e in col or pr[e] < pr[k] for e in nbr[k])]
+        new = {}
+        for k in winners:
+            used = {col[e] for e in nbr[k] if e in col}
+            c = 0
+            while c in used:
+                c += 1
+            new[k] = c
+        col.update(new)
+    return col, rounds, nbr
+
+
+def settled(seed, n, steps, sweeps=10, footprint=0.5):
+    spec = SG.column_scene(seed=seed, n=n, footprint=footprint, fill=0.45, sweeps=sweeps)
+    sc = O.OracleScene(spec)
+    for _ in range(steps):
+        sc.step()
+    out = dict(spec)
+    out.update(x=sc.x.copy(), v=sc.v.copy(), w=sc.w.copy())
+    return out
+
+
+def test_colouring_valid_and_equal_to_parallel_jp():
+    spec = settled(9, 400, 60)
+    out = O.OracleScene(spec).step()
+    keys, colour = out["keys"], out["colour"]
+    assert len(keys) > 300
+    jp, rounds, nbr = jones_plassmann_rounds(keys)
+    for k, c in zip(keys, colour):
+        assert jp[int(k)] == c
+        for e in nbr[int(k)]:
+            assert jp[e] != c
+    assert out["colours"] == max(colour) + 1
+    assert rounds >= 3
+
+
+def test_colouring_independent_of_input_order():
+    spec = settled(10, 300, 60)
+    a = O.OracleScene(spec)
+    oa = a.step()
+    perm = np.random.default_rng(0).permutation(len(spec["x"]))
+    spec_p = dict(spec)
+    for k in ("x", "v", "w"):
+        spec_p[k] = spec[k][perm]
+    spec_p["r"] = spec["r"][perm]
+    spec_p["id"] = spec["id"][perm]
+    b = O.OracleScene(spec_p)
+    ob = b.step()
+    assert np.array_equal(oa["keys"], ob["keys"])
+    assert np.array_equal(oa["colour"], ob["colour"])
+    assert np.array_equal(oa["lam"], ob["lam"])
+    inv = np.argsort(perm)
+    assert np.array_equal(a.v, b.v[inv])
+
+
+# --------------------------------------------------------------------------
+# PGS convergence: the natural-map residual goes to zero
+# --------------------------------------------------------------------------
+def test_natural_residual_vanishes_with_sweeps():
+    spec = SG.column_scene(seed=12, n=150, footprint=0.4, fill=0.5, sweeps=40)
+    sc = O.OracleScene(spec)
+    for _ in range(40):
+        sc.step()
+    res = []
+    for sweeps in (5, 500, 20000):
+        s2 = dict(spec)
+        s2.update(x=sc.x.copy(), v=sc.v.copy(), w=sc.w.copy(), max_sweeps=sweeps)
+        t = O.OracleScene(s2)
+        x0, v0, w0 = t.x.copy(), t.v.copy(), t.w.copy()
+        out = t.step()
+        res.append(t.natural_residual(x0, v0, w0, out["lam"]))
+    assert res[0] > res[1] > res[2]
+    assert res[2] < 1e-6
+
+
+def test_prev_warm_start_speeds_up_convergence():
+    spec = SG.column_scene(seed=13, n=200, footprint=0.4, fill=0.5, sweeps=60)
+    spec["warm_start"] = "prev"
+    sc = O.OracleScene(spec)
+    for _ in range(40):
+        out = sc.step()
+    s_cold = dict(spec)
+    s_cold.update(x=sc.x.copy(), v=sc.v.copy(), w=sc.w.copy(), warm_start="cold", max_sweeps=1)
+    cold = O.OracleScene(s_cold).step()
+    warm = O.OracleScene(dict(s_cold, warm_start="prev"))
+    warm.prev_keys, warm.prev_lam = sc.prev_keys.copy(), sc.prev_lam.copy()
+    ow = warm.step()
+    assert ow["r1"] < 0.5 * cold["r1"]
+
+
+# --------------------------------------------------------------------------
+# Aggregates (Eqs. aggregate_mass .. aggregate_rot_vel): closed forms
+# --------------------------------------------------------------------------
+BIG_ZONE = [[1, 0, 0, 10], [-1, 0, 0, 10], [0, 1, 0, 10], [0, -1, 0, 10], [0, 0, 1, 10], [0, 0, -1, 10]]
+
+
+def zone_body(planes=BIG_ZONE, pos=(0.0, 0.0, 0.0)):
+    return dict(pos=pos, quat=(1, 0, 0, 0), zone_planes=planes, shapes=[])
+
+
+def test_aggregate_single_sphere_and_dumbbell():
+    r, m = 0.05, 1.7
+    a = O.aggregates([[0.3, -0.1, 0.2]], np.zeros((1, 3)), np.zeros((1, 3)), [r], [m], [zone_body()])[0]
+    Is = 0.4 * m * r * r
+    assert a["M"] == m and a["n_particles"] == 1
+    assert np.allclose(a["I"], [Is, Is, Is, 0, 0, 0], rtol=1e-14, atol=1e-18)
+    d = 0.4
+    a = O.aggregates([[d, 0, 0], [-d, 0, 0]], np.zeros((2, 3)), np.zeros((2, 3)), [r, r], [m, m],
+                     [zone_body()])[0]
+    assert np.allclose(a["x"], 0.0)
+    assert np.allclose(a["I"], [2 * Is, 2 * Is + 2 * m * d * d, 2 * Is + 2 * m * d * d, 0, 0, 0], rtol=1e-13)
+
+
+def test_aggregate_rigid_motion():
+    rng = np.random.default_rng(3)
+    n = 50
+    x = rng.uniform(-1, 1, (n, 3))
+    r = rng.uniform(0.02, 0.06, n)
+    m = rng.uniform(0.5, 2.0, n)
+    vt = np.array([0.3, -1.2, 0.5])
+    a = O.aggregates(x, np.tile(vt, (n, 1)), np.zeros((n, 3)), r, m, [zone_body()])[0]
+    assert np.allclose(a["v"], vt, rtol=1e-14)
+    assert np.allclose(a["w"], 0.0, atol=1e-14)
+    om = np.array([0.7, -0.2, 1.9])
+    c = np.array([0.1, 0.2, -0.3])
+    v = vt + np.cross(om, x - c)
+    a = O.aggregates(x, v, np.tile(om, (n, 1)), r, m, [zone_body()])[0]
+    assert np.allclose(a["w"], om, rtol=1e-12)
+    assert np.allclose(a["v"], vt + np.cross(om, a["x"] - c), rtol=1e-12)
+
+
+def test_zone_membership_first_body_wins():
+    x = np.array([[0.0, 0, 0], [2.0, 0, 0], [5.0, 0, 0]])
+    b1 = zone_body([[1, 0, 0, 1.0]])          # x <= 1
+    b2 = zone_body([[1, 0, 0, 3.0]])          # x <= 3
+    aggs = O.aggregates(x, np.zeros((3, 3)), np.zeros((3, 3)), [0.05] * 3, [1.0] * 3, [b1, b2])
+    assert [a["n_particles"] for a in aggs] == [1, 1]
+    # zone planes move with the body pose
+    b3 = zone_body([[1, 0, 0, 0.0]], pos=(4.0, 0.0, 0.0))  # x <= 4 in the world
+    assert O.aggregates(x, np.zeros((3, 3)), np.zeros((3, 3)), [0.05] * 3, [1.0] * 3, [b3])[0]["n_particles"] == 2
+
+
+def test_failure_plane_reduces_to_rankine():
+    for phi_deg in (20, 30, 40, 44.5):
+        phi = math.radians(phi_deg)
+        assert O.failure_angle(phi, math.pi / 2) == pytest.approx(math.pi / 4 - phi / 2, rel=1e-15)
+    # a sloped separation plate steepens the wedge by half the slope
+    assert O.failure_angle(0.7, 0.5) - O.failure_angle(0.7, 0.6) == pytest.approx(0.05, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# MLP: FP64 gradients against central finite differences
+# --------------------------------------------------------------------------
+def random_mlp(seed=0):
+    rng = np.random.default_rng(seed)
+    return dict(W1=rng.normal(0, 0.4, (64, 12)), b1=rng.normal(0, 0.1, 64), W2=rng.normal(0, 0.15, (64, 64)),
+                b2=rng.normal(0, 0.1, 64), W3=rng.normal(0, 0.15, (3, 64)), b3=rng.normal(0, 0.1, 3),
+                in_scale=rng.uniform(0.5, 2.0, 12))
+
+
+def test_mlp_gradient_matches_finite_differences():
+    net = random_mlp(1)
+    rng = np.random.default_rng(2)
+    feat = rng.normal(0, 1, (7, 12))
+    label = rng.normal(0, 1, (7, 3))
+    loss, grads = O.mlp_loss_grad(net, feat, label)
+    y = O.mlp_forward(net, feat)
+    assert loss == pytest.approx(0.5 * np.mean(np.sum((y - label) ** 2, axis=1)), rel=1e-13)
+    eps = 1e-6
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        flat = net[name].reshape(-1)
+        for idx in rng.choice(len(flat), size=min(6, len(flat)), replace=False):
+            orig = flat[idx]
+            flat[idx] = orig + eps
+            lp, _ = O.mlp_loss_grad(net, feat, label)
+            flat[idx] = orig - eps
+            lm, _ = O.mlp_loss_grad(net, feat, label)
+            flat[idx] = orig
+            fd = (lp - lm) / (2 * eps)
+            assert grads[name].reshape(-1)[idx] == pytest.approx(fd, rel=1e-6, abs=1e-10), (name, idx)
