@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark: one full particle step (detection, canonical order, rows,
+colouring, warm start, PGS, integration, body forces, zone aggregates) of the
+50,000-sphere bulldozing bed on one MI355X.
+
+Workload: 50k spheres r = 0.03 m U(0.9, 1.1), rho 2000, mu 0.7, c_p 2 kPa,
+poured over a 4 x 2 m floor with walls and settled on the GPU before timing;
+a 1.5 x 0.05 x 0.6 m box blade cuts 0.2 m below the settled surface at 1 m/s;
+dt = 1/60 s, 150 PGS sweeps, previous-step warm start.  Inputs are resident
+in HBM when the timed region starts.
+
+Prints one JSON line.  value = contacts * PGS sweeps / s over the whole step.
+roofline: the persistent PGS kernel, algorithmic bytes (176 B per pair
+contact-sweep, 128 B per boundary contact-sweep) / its event-timed duration.
+cpu_baseline: the FP64 oracle (single thread) on a 50k-sphere jammed bed of the
+same radius, a bounded sample of about 10-30 s.
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2011_00459_amd import scenegen as SG  # noqa: E402
+from paper_2011_00459_amd import terrain as T  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+PAIR_BYTES, BOUND_BYTES = 176, 128
+
+
+def device_sync():
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    rc = hip.hipDeviceSynchronize()
+    if rc != 0:
+        raise RuntimeError(f"hipDeviceSynchronize failed ({rc})")
+
+
+def build_bed(args):
+    spec = SG.bed_scene(seed=2, n=args.n, r0=0.03, spread=0.1, lx=4.0, ly=2.0, mu=0.7, c=2000.0,
+                        sweeps=args.sweeps, tool="none")
+    solids = float(np.sum(4.0 / 3.0 * np.pi * spec["r"] ** 3))
+    est_top = solids / (4.0 * 2.0 * 0.6)
+    blade = SG.box_blade(-1.6, est_top - 0.2, width=1.5, thick=0.05, height=0.6, vx=0.0)
+    spec["bodies"] = spec["bodies"] + [blade]
+    spec["warm_start"] = "prev"
+    sc = T.scene_from_specs(spec, cap_contacts=16 * args.n)
+    return sc, spec, blade, est_top
+
+
+def settle(sc, spec, blade, steps):
+    # pour and settle with fewer sweeps, blade static in place
+    sc.step(steps, stats=False)
+    st = sc.step(1)[0]
+    p = sc.get_particles(0)
+    top = float(np.percentile(p["x"][:, 2] + p["r"], 99.0))
+    return st, top
+
+
+def timed_steps(sc, k):
+    """K steps, one at a time so that every step's contact count is known."""
+    device_sync()
+    t0 = time.perf_counter()
+    tot_cs = 0
+    tot_bytes_pgs = 0
+    pgs_ms = 0.0
+    stats = []
+    for _ in range(k):
+        st = sc.step(1)[0]
+        ph = sc.get_phase_times()
+        pairs, allc = st["pair_contacts"], st["contacts"]
+        tot_cs += allc * st["sweeps"]
+        tot_bytes_pgs += (pairs * PAIR_BYTES + (allc - pairs) * BOUND_BYTES) * st["sweeps"]
+        pgs_ms += ph["pgs"]
+        stats.append((st, ph))
+    device_sync()
+    t1 = time.perf_counter()
+    return t1 - t0, tot_cs, tot_bytes_pgs, pgs_ms, stats
+
+
+def cpu_baseline(args):
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import pyoracle as O
+    nx, ny = 60, 30
+    nz = max(1, int(round(args.n / (nx * ny))))
+    spec = SG.jammed_bed(seed=21, nx=nx, ny=ny, nz=nz, r0=0.03, sweeps=args.sweeps)
+    o = O.OracleScene(spec)
+    t0 = time.perf_counter()
+    cs = 0
+    steps = 0
+    while True:
+        out = o.step()
+        cs += out["contacts"] * out["sweeps"]
+        steps += 1
+        if time.perf_counter() - t0 > args.cpu_seconds or steps >= 8:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=cs / dt, unit="contacts*sweeps/s", cores=1, kind="oracle",
+                sample=f"{steps} FP64 oracle steps (single thread) of a {len(spec['x'])}-sphere jammed bed, "
+                       f"r 0.03 m, {args.sweeps} sweeps, {out['contacts']} contacts/step")
+
+
+def tol_rate(sc, mode, k, cap):
+    """steps/s of the same bed stepping to R_k <= 1e-4 (cap sweeps)."""
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=50000)
+    ap.add_argument("--sweeps", type=int, default=150)
+    ap.add_argument("--settle", type=int, default=150)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is design-only",
+              file=sys.stderr)
+        sys.exit(2)
+
+    sc, spec, blade, est_top = build_bed(args)
+    st0, top = settle(sc, spec, blade, args.settle)
+    print(f"# settled: {st0['contacts']} contacts, top {top:.3f} m (estimate {est_top:.3f})", file=sys.stderr,
+          flush=True)
+    moving = dict(blade)
+    moving["pos"] = (-1.6, 0.0, top - 0.2 + 0.3)
+    moving["linvel"] = (1.0, 0.0, 0.0)
+    bodies = [dict(spec["bodies"][0], id=0), dict(moving, id=1)]
+    sc.set_kinematic_bodies(0, bodies)
+    for _ in range(args.warmup):
+        sc.step(1)
+    wall, tot_cs, pgs_bytes, pgs_ms, stats = timed_steps(sc, args.steps)
+    value = tot_cs / wall
+    ms_per_step = 1e3 * wall / args.steps
+    pgs_launch_ms = pgs_ms / args.steps
+    achieved = pgs_bytes / args.steps / (pgs_launch_ms * 1e-3) / 1e9 if pgs_launch_ms > 0 else 0.0
+    last = stats[-1][0]
+    f, _ = sc.get_contact_forces(0, 1)
+    aggs = sc.get_aggregates(0)
+    line = {
+        "metric": "contacts*PGS-sweeps/s (whole step)",
+        "value": value,
+        "unit": "contacts*sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"bulldozing bed: {args.n} spheres r 0.03 m, 4x2 m, box blade 1.5x0.05x0.6 m "
+                               f"at 1 m/s, 0.2 m deep, dt 1/60 s, {args.sweeps} sweeps, prev warm start",
+                   "contacts_per_step": last["contacts"], "pair_contacts": last["pair_contacts"],
+                   "colours": last["colours"], "sweeps": last["sweeps"],
+                   "pgs_ms_per_step": pgs_launch_ms,
+                   "blade_force_x_N": float(f[0])},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_pgs (persistent colour-synchronous PGS)"},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,706 @@
+// terrain_capi.hip -- the C-ABI of libterrain.so (see include/terrain.h).
+//
+// Host side of the step: validates and copies inputs, keeps the per-env
+// tables (cell grids, bodies, shapes, zones), owns every device buffer and
+// enqueues the kernel families of terrain_kernels.hip on the scene's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "terrain.h"
+#include "terrain_internal.h"
+
+using namespace trk;
+
+namespace {
+
+struct EnvHost {
+    int64_t n = 0;
+    double rmax = 0.0;
+    std::vector<tr_body_desc> bodies;             // shapes pointer unused (see shapes)
+    std::vector<std::vector<tr_shape_desc>> shapes;
+    std::vector<std::vector<std::vector<float>>> heights;
+};
+
+}  // namespace
+
+struct tr_scene {
+    tr_scene_desc desc{};
+    std::vector<double> bounds;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<EnvHost> envs;
+    DevBuffers b{};
+    Sizes z{};
+    StepParams p{};
+    int64_t n_total = 0;
+    bool tables_dirty = true;
+    bool have_prev = false;
+    bool stepped = false;
+    std::vector<std::pair<void*, size_t>> allocs;
+    int64_t cells_alloc = 0;
+    int64_t zone_chunk_alloc = 0;
+    int64_t hf_alloc = 0;
+    int bodies_alloc = 0, shapes_alloc = 0, zones_alloc = 0;
+    std::vector<BodyDev> body_host;   // last uploaded body table (poses refreshed on download)
+    std::vector<EnvDev> env_host;
+    std::vector<std::vector<int>> zone_slots;  // per env: global zone index of each zone body
+    hipEvent_t ev[5] = {};
+    bool events = false;
+    float* staging = nullptr;         // 12 floats per particle (device), id-order exchange
+};
+
+namespace {
+
+int fail(tr_scene* s, int code, const std::string& msg)
+{
+    if (s) s->err = msg;
+    return code;
+}
+
+int hip_fail(tr_scene* s, hipError_t e, const char* what)
+{
+    return fail(s, TR_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_CHECK(s, call)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail((s), e_, #call); \
+    } while (0)
+
+void* dalloc(tr_scene* s, size_t bytes)
+{
+    bytes = std::max<size_t>(bytes, 256);
+    void* p = nullptr;
+    if (s->desc.alloc_fn) {
+        p = s->desc.alloc_fn(s->desc.alloc_ctx, bytes, s->desc.stream);
+    } else {
+        if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    }
+    if (p) s->allocs.push_back({p, bytes});
+    return p;
+}
+
+void dfree(tr_scene* s, void* p)
+{
+    if (!p) return;
+    for (size_t i = 0; i < s->allocs.size(); ++i) {
+        if (s->allocs[i].first == p) {
+            if (s->desc.free_fn) s->desc.free_fn(s->desc.alloc_ctx, p, s->desc.stream);
+            else (void)hipFree(p);
+            s->allocs.erase(s->allocs.begin() + (long)i);
+            return;
+        }
+    }
+}
+
+template <class T>
+bool alloc_n(tr_scene* s, T*& p, int64_t n)
+{
+    p = (T*)dalloc(s, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+    return p != nullptr;
+}
+
+bool finite3(const double* a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+int ceil_log2(int v)
+{
+    int b = 0;
+    while ((1 << b) < v) ++b;
+    return b;
+}
+
+// Rebuild the per-env tables (grids, bodies, shapes, zones, chunk list) and
+// upload them; device poses are kept by downloading them first.
+int rebuild_tables(tr_scene* s)
+{
+    const int E = s->desc.n_envs;
+    const bool cohesive = s->desc.material.c_p > 0.0;
+    std::vector<EnvDev> ed(E);
+    std::vector<BodyDev> bd;
+    std::vector<ShapeDev> sd;
+    std::vector<float> pool;
+    std::vector<int4> chunks;
+    int64_t NC = 0;
+    int n_zones = 0;
+    int64_t slot = 0;
+    s->zone_slots.assign(E, {});
+    for (int e = 0; e < E; ++e) {
+        EnvHost& H = s->envs[e];
+        EnvDev& D = ed[e];
+        const double* bo = &s->bounds[6 * e];
+        double rmax = H.rmax > 0.0 ? H.rmax : 0.05;
+        double h = 2.0 * rmax * (1.0 + (cohesive ? s->desc.material.kappa_c : 0.0)) * 1.001;
+        for (int k = 0; k < 3; ++k) {
+            double ext = bo[3 + k] - bo[k];
+            int dims = std::max(1, (int)std::ceil(ext / h));
+            if (dims > 1024) return fail(s, TR_E_CAPACITY, "env grid exceeds 1024 cells along an axis");
+            D.lo[k] = (float)bo[k];
+            D.dims[k] = dims;
+            D.bits[k] = ceil_log2(dims);
+        }
+        D.inv_h = (float)(1.0 / h);
+        D.cell_base = (uint32_t)NC;
+        NC += (int64_t)1 << (D.bits[0] + D.bits[1] + D.bits[2]);
+        if (NC >= ((int64_t)1 << 31)) return fail(s, TR_E_CAPACITY, "too many cells");
+        D.id_base = (int)(e * s->desc.cap_particles);
+        D.n = (int)H.n;
+        D.slot_begin = (int)slot;
+        D.body_begin = (int)bd.size();
+        D.shape_begin = (int)sd.size();
+        D.zone_count = 0;
+        for (size_t bi = 0; bi < H.bodies.size(); ++bi) {
+            const tr_body_desc& B = H.bodies[bi];
+            BodyDev X;
+            memset(&X, 0, sizeof(X));
+            int gi = (int)bd.size();
+            for (int k = 0; k < 3; ++k) { X.pos[k] = B.pos[k]; X.linvel[k] = B.linvel[k]; X.angvel[k] = B.angvel[k]; }
+            for (int k = 0; k < 4; ++k) X.quat[k] = B.quat[k];
+            X.env = e;
+            X.user_id = B.id;
+            X.nplanes = B.n_halfspaces;
+            for (int k = 0; k < B.n_halfspaces; ++k)
+                for (int j = 0; j < 4; ++j) X.planes[k][j] = B.planes[k][j];
+            if (B.n_halfspaces > 0) {
+                if (D.zone_count >= kMaxZonesPerEnv) return fail(s, TR_E_CAPACITY, "more than 4 zones in an env");
+                D.zone_body[D.zone_count] = gi;
+                D.zone_slot[D.zone_count] = n_zones;
+                s->zone_slots[e].push_back(n_zones);
+                ++D.zone_count;
+                ++n_zones;
+            }
+            bd.push_back(X);
+            for (size_t si = 0; si < H.shapes[bi].size(); ++si) {
+                const tr_shape_desc& S = H.shapes[bi][si];
+                ShapeDev Y;
+                memset(&Y, 0, sizeof(Y));
+                Y.type = S.type;
+                Y.body = gi;
+                Y.env = e;
+                for (int k = 0; k < 3; ++k) { Y.n[k] = S.normal[k]; Y.half[k] = S.half[k]; Y.off[k] = S.center[k]; }
+                Y.d = S.offset;
+                if (S.type == TR_HEIGHTFIELD) {
+                    Y.nx = S.nx; Y.ny = S.ny;
+                    Y.ox = S.origin[0]; Y.oy = S.origin[1];
+                    Y.l0 = S.l0;
+                    Y.inv_l0 = 1.0 / S.l0;
+                    Y.hf_off = (int)pool.size();
+                    const std::vector<float>& hh = H.heights[bi][si];
+                    pool.insert(pool.end(), hh.begin(), hh.end());
+                }
+                sd.push_back(Y);
+            }
+        }
+        D.body_end = (int)bd.size();
+        D.shape_end = (int)sd.size();
+        for (int64_t b0 = slot; b0 < slot + H.n; b0 += kZoneChunk) {
+            int64_t b1 = std::min<int64_t>(b0 + kZoneChunk, slot + H.n);
+            chunks.push_back(make_int4(e, (int)b0, (int)b1, (int)(chunks.size() * kMaxZonesPerEnv)));
+        }
+        slot += H.n;
+    }
+    hipStream_t st = s->stream;
+    // (re)allocate tables whose size depends on the scene content
+    if (NC + 1 > s->cells_alloc) {
+        dfree(s, s->b.cell_count); dfree(s, s->b.cell_start); dfree(s, s->b.cell_fill);
+        dfree(s, s->b.scan_tmp);
+        if (!alloc_n(s, s->b.cell_count, NC) || !alloc_n(s, s->b.cell_start, NC + 1) || !alloc_n(s, s->b.cell_fill, NC))
+            return fail(s, TR_E_NOMEM, "cell arrays");
+        int64_t words = std::max({scan_tmp_words(NC), scan_tmp_words(s->z.NID), scan_tmp_words(s->z.P),
+                                  scan_tmp_words((int64_t)kMaxColours * s->z.NB)});
+        if (!alloc_n(s, s->b.scan_tmp, words)) return fail(s, TR_E_NOMEM, "scan scratch");
+        s->cells_alloc = NC + 1;
+    }
+    if ((int)bd.size() > s->bodies_alloc || (int)sd.size() > s->shapes_alloc || n_zones > s->zones_alloc) {
+        dfree(s, s->b.bodies); dfree(s, s->b.shapes); dfree(s, s->b.force_part); dfree(s, s->b.body_ft);
+        dfree(s, s->b.zone_mom); dfree(s, s->b.aggs);
+        int nb = std::max<int>((int)bd.size(), 1), ns = std::max<int>((int)sd.size(), 1), nz = std::max(n_zones, 1);
+        if (!alloc_n(s, s->b.bodies, nb) || !alloc_n(s, s->b.shapes, ns) ||
+            !alloc_n(s, s->b.force_part, (int64_t)nb * kForceChunks * 6) || !alloc_n(s, s->b.body_ft, (int64_t)nb * 6) ||
+            !alloc_n(s, s->b.zone_mom, (int64_t)nz * kZoneMoments) || !alloc_n(s, s->b.aggs, nz))
+            return fail(s, TR_E_NOMEM, "body tables");
+        s->bodies_alloc = nb; s->shapes_alloc = ns; s->zones_alloc = nz;
+        HIP_CHECK(s, hipMemsetAsync(s->b.body_ft, 0, sizeof(double) * nb * 6, st));
+        HIP_CHECK(s, hipMemsetAsync(s->b.aggs, 0, sizeof(tr_aggregate) * nz, st));
+    }
+    if ((int64_t)chunks.size() > s->zone_chunk_alloc) {
+        dfree(s, s->b.zone_chunks); dfree(s, s->b.zone_part);
+        int64_t nch = std::max<int64_t>((int64_t)chunks.size(), 1);
+        if (!alloc_n(s, s->b.zone_chunks, nch) || !alloc_n(s, s->b.zone_part, nch * kMaxZonesPerEnv * kZoneMoments))
+            return fail(s, TR_E_NOMEM, "zone chunks");
+        s->zone_chunk_alloc = nch;
+    }
+    if ((int64_t)pool.size() > s->hf_alloc) {
+        dfree(s, s->b.hf_pool);
+        if (!alloc_n(s, s->b.hf_pool, (int64_t)pool.size())) return fail(s, TR_E_NOMEM, "heightfields");
+        s->hf_alloc = (int64_t)pool.size();
+    }
+    HIP_CHECK(s, hipMemcpyAsync(s->b.envs, ed.data(), sizeof(EnvDev) * E, hipMemcpyHostToDevice, st));
+    if (!bd.empty()) HIP_CHECK(s, hipMemcpyAsync(s->b.bodies, bd.data(), sizeof(BodyDev) * bd.size(), hipMemcpyHostToDevice, st));
+    if (!sd.empty()) HIP_CHECK(s, hipMemcpyAsync(s->b.shapes, sd.data(), sizeof(ShapeDev) * sd.size(), hipMemcpyHostToDevice, st));
+    if (!pool.empty()) HIP_CHECK(s, hipMemcpyAsync(s->b.hf_pool, pool.data(), sizeof(float) * pool.size(), hipMemcpyHostToDevice, st));
+    if (!chunks.empty()) HIP_CHECK(s, hipMemcpyAsync(s->b.zone_chunks, chunks.data(), sizeof(int4) * chunks.size(), hipMemcpyHostToDevice, st));
+    HIP_CHECK(s, hipStreamSynchronize(st));  // host vectors die here
+    s->body_host = bd;
+    s->env_host = ed;
+    s->z.NC = NC;
+    s->z.n_zone_chunks = (int)chunks.size();
+    s->p.n_bodies = (int)bd.size();
+    s->p.n_shapes = (int)sd.size();
+    s->p.n_zones = n_zones;
+    s->tables_dirty = false;
+    return TR_OK;
+}
+
+// Download the device poses into the host body descriptions (they advance on
+// the device), so that rebuilding the tables keeps them.
+int sync_poses(tr_scene* s)
+{
+    if (s->body_host.empty()) return TR_OK;
+    std::vector<BodyDev> bd(s->body_host.size());
+    HIP_CHECK(s, hipMemcpyAsync(bd.data(), s->b.bodies, sizeof(BodyDev) * bd.size(), hipMemcpyDeviceToHost, s->stream));
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    for (const BodyDev& X : bd) {
+        EnvHost& H = s->envs[X.env];
+        for (tr_body_desc& B : H.bodies)
+            if (B.id == X.user_id) {
+                for (int k = 0; k < 3; ++k) B.pos[k] = X.pos[k];
+                for (int k = 0; k < 4; ++k) B.quat[k] = X.quat[k];
+            }
+    }
+    s->body_host = bd;
+    return TR_OK;
+}
+
+void fill_params(tr_scene* s)
+{
+    const tr_scene_desc& d = s->desc;
+    const tr_material& m = d.material;
+    StepParams& p = s->p;
+    double dt = d.dt;
+    double tau = m.tau_n > 0.0 ? m.tau_n : 2.0 * dt;
+    double ups = 1.0 / (1.0 + 4.0 * tau / dt);
+    p.dt = (float)dt;
+    for (int k = 0; k < 3; ++k) p.g[k] = (float)d.gravity[k];
+    p.mu = (float)m.mu_t;
+    p.gamma_dt = (float)(m.gamma_t / dt);
+    p.kappa_c = m.c_p > 0.0 ? m.kappa_c : 0.0;
+    p.kappa_min = m.kappa_min;
+    p.Estar = m.E / (2.0 * (1.0 - m.nu * m.nu));
+    p.a_coef = (4.0 / dt) * ups;
+    p.b_coef = ups;
+    p.sig_coef = (4.0 / (dt * dt)) * ups;
+    p.lo_coef = m.c_p * 3.14159265358979323846 * dt;
+    p.id_cap = (uint32_t)d.cap_particles;
+    p.n_envs = d.n_envs;
+    p.max_sweeps = d.max_sweeps;
+    p.tol = (float)d.tol;
+    p.warm = d.warm_start;
+}
+
+}  // namespace
+
+extern "C" {
+
+int create_scene(const tr_scene_desc* d, tr_scene** out)
+{
+    if (!d || !out) return TR_E_INVAL;
+    *out = nullptr;
+    if (d->n_envs < 1 || d->dt <= 0.0 || d->max_sweeps < 0 || d->cap_particles < 1 || d->cap_contacts < 1 ||
+        !d->env_bounds)
+        return TR_E_INVAL;
+    if (d->material.mu_r != 0.0 || d->material.restitution != 0.0) return TR_E_INVAL;
+    if (d->warm_start < TR_WARM_COLD || d->warm_start > TR_WARM_LEARNED) return TR_E_INVAL;
+    if ((int64_t)d->n_envs * d->cap_particles >= ((int64_t)1 << 31) ||
+        (int64_t)d->n_envs * d->cap_contacts >= ((int64_t)1 << 31))
+        return TR_E_CAPACITY;
+    if (!finite3(d->env_bounds, 6 * (int64_t)d->n_envs)) return TR_E_NONFINITE;
+    tr_scene* s = new tr_scene();
+    s->desc = *d;
+    s->bounds.assign(d->env_bounds, d->env_bounds + 6 * d->n_envs);
+    s->desc.env_bounds = s->bounds.data();
+    s->stream = (hipStream_t)d->stream;
+    s->envs.resize(d->n_envs);
+    fill_params(s);
+    Sizes& z = s->z;
+    z.P = (int64_t)d->n_envs * d->cap_particles;
+    z.C = (int64_t)d->n_envs * d->cap_contacts;
+    z.NID = z.P;
+    z.NB = (z.C + 255) / 256;
+    z.pgs_block = 256;
+    z.pgs_grid = std::min(pgs_resident_blocks(256), 1024);
+    z.col_grid = std::min(colour_resident_blocks(), 2048);
+    DevBuffers& b = s->b;
+    bool ok = alloc_n(s, b.xr, z.P) && alloc_n(s, b.vm, z.P) && alloc_n(s, b.wi, z.P) && alloc_n(s, b.xr2, z.P) &&
+              alloc_n(s, b.vm2, z.P) && alloc_n(s, b.wi2, z.P) && alloc_n(s, b.pid, z.P) && alloc_n(s, b.pid2, z.P) &&
+              alloc_n(s, b.rho, z.P) && alloc_n(s, b.rho2, z.P) && alloc_n(s, b.pkey, z.P) &&
+              alloc_n(s, b.perm, z.P) && alloc_n(s, b.id2slot, z.NID) && alloc_n(s, b.rkey, z.C) &&
+              alloc_n(s, b.ckey, z.C) && alloc_n(s, b.pkeyc, z.C) && alloc_n(s, b.rpair, z.C) &&
+              alloc_n(s, b.cpair, z.C) && alloc_n(s, b.lamc, z.C) && alloc_n(s, b.plam, z.C) &&
+              alloc_n(s, b.id_count, z.NID) && alloc_n(s, b.id_start, z.NID + 1) && alloc_n(s, b.id_fill, z.NID) &&
+              alloc_n(s, b.pid_start, z.NID + 1) && alloc_n(s, b.inc_count, z.P) &&
+              alloc_n(s, b.inc_start, z.P + 1) && alloc_n(s, b.inc_fill, z.P) && alloc_n(s, b.inc, 2 * z.C) &&
+              alloc_n(s, b.colour, z.C) && alloc_n(s, b.col_hist, (int64_t)kMaxColours * z.NB) &&
+              alloc_n(s, b.col_start, (int64_t)kMaxColours * z.NB + 1) && alloc_n(s, b.cpos, z.C) &&
+              alloc_n(s, b.r0, z.C) && alloc_n(s, b.r1, z.C) && alloc_n(s, b.r2, z.C) && alloc_n(s, b.rk, z.C) &&
+              alloc_n(s, b.lam, z.C) && alloc_n(s, b.lam0, z.C) &&
+              alloc_n(s, b.block_part, (int64_t)4 * z.pgs_grid) && alloc_n(s, b.envs, d->n_envs) &&
+              alloc_n(s, b.cnt, 1) && alloc_n(s, b.env_stats, d->n_envs) && alloc_n(s, b.mlp, kMlpParams) &&
+              alloc_n(s, s->staging, 12 * z.P);
+    if (!ok) {
+        destroy_scene(s);
+        return TR_E_NOMEM;
+    }
+    hipError_t e = hipMemsetAsync(b.cnt, 0, sizeof(Counters), s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b.env_stats, 0, sizeof(EnvStats) * d->n_envs, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b.id_start, 0, sizeof(uint32_t) * (z.NID + 1), s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b.pid_start, 0, sizeof(uint32_t) * (z.NID + 1), s->stream);
+    for (int k = 0; k < 5 && e == hipSuccess; ++k) e = hipEventCreate(&s->ev[k]);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        destroy_scene(s);
+        return TR_E_DEVICE;
+    }
+    s->events = true;
+    *out = s;
+    return TR_OK;
+}
+
+int destroy_scene(tr_scene* s)
+{
+    if (!s) return TR_OK;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    else (void)hipDeviceSynchronize();
+    while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
+    if (s->events)
+        for (int k = 0; k < 5; ++k) (void)hipEventDestroy(s->ev[k]);
+    delete s;
+    return TR_OK;
+}
+
+int add_particles(tr_scene* s, int32_t env, int64_t n, const double* pos, const double* vel, const double* radius,
+                  const double* density, int64_t* first_id)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs || n < 0 || (n > 0 && (!pos || !radius)))
+        return fail(s, TR_E_INVAL, "add_particles: bad arguments");
+    EnvHost& H = s->envs[env];
+    if (H.n + n > s->desc.cap_particles) return fail(s, TR_E_CAPACITY, "add_particles: env particle capacity");
+    if (!finite3(pos, 3 * n) || (vel && !finite3(vel, 3 * n)) || !finite3(radius, n) || (density && !finite3(density, n)))
+        return fail(s, TR_E_NONFINITE, "add_particles: non-finite input");
+    for (int64_t i = 0; i < n; ++i) {
+        if (radius[i] <= 0.0) return fail(s, TR_E_INVAL, "add_particles: radius <= 0");
+        if (density && density[i] <= 0.0) return fail(s, TR_E_INVAL, "add_particles: density <= 0");
+    }
+    int64_t id0 = (int64_t)env * s->desc.cap_particles + H.n;
+    if (first_id) *first_id = id0;
+    if (n == 0) return TR_OK;
+    std::vector<float4> xr(n), vm(n), wi(n);
+    std::vector<int> pid(n), id2s(n);
+    std::vector<float> rho(n);
+    const double pi = 3.14159265358979323846;
+    for (int64_t i = 0; i < n; ++i) {
+        float r = (float)radius[i];
+        double dens = density ? density[i] : s->desc.material.rho;
+        float rhof = (float)dens;
+        double rr = r;
+        double m = (double)rhof * (4.0 / 3.0) * pi * rr * rr * rr;
+        xr[i] = make_float4((float)pos[3 * i], (float)pos[3 * i + 1], (float)pos[3 * i + 2], r);
+        vm[i] = make_float4(vel ? (float)vel[3 * i] : 0.f, vel ? (float)vel[3 * i + 1] : 0.f,
+                            vel ? (float)vel[3 * i + 2] : 0.f, (float)(1.0 / m));
+        wi[i] = make_float4(0.f, 0.f, 0.f, (float)(1.0 / (0.4 * m * rr * rr)));
+        pid[i] = (int)(id0 + i);
+        id2s[i] = (int)(s->n_total + i);
+        rho[i] = rhof;
+        H.rmax = std::max(H.rmax, rr);
+    }
+    hipStream_t st = s->stream;
+    int64_t at = s->n_total;
+    HIP_CHECK(s, hipMemcpyAsync(s->b.xr + at, xr.data(), sizeof(float4) * n, hipMemcpyHostToDevice, st));
+    HIP_CHECK(s, hipMemcpyAsync(s->b.vm + at, vm.data(), sizeof(float4) * n, hipMemcpyHostToDevice, st));
+    HIP_CHECK(s, hipMemcpyAsync(s->b.wi + at, wi.data(), sizeof(float4) * n, hipMemcpyHostToDevice, st));
+    HIP_CHECK(s, hipMemcpyAsync(s->b.pid + at, pid.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    HIP_CHECK(s, hipMemcpyAsync(s->b.rho + at, rho.data(), sizeof(float) * n, hipMemcpyHostToDevice, st));
+    HIP_CHECK(s, hipMemcpyAsync(s->b.id2slot + id0, id2s.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    HIP_CHECK(s, hipStreamSynchronize(st));
+    H.n += n;
+    s->n_total += n;
+    s->p.n_particles = (int)s->n_total;
+    s->have_prev = false;
+    // particles of later envs must follow this env in slot order: the next
+    // step's sort restores (env, cell, id) order
+    int rc = sync_poses(s);
+    if (rc) return rc;
+    s->tables_dirty = true;
+    return TR_OK;
+}
+
+int set_kinematic_bodies(tr_scene* s, int32_t env, int32_t n, const tr_body_desc* b)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs || n < 0 || (n > 0 && !b)) return fail(s, TR_E_INVAL, "set_kinematic_bodies: bad arguments");
+    int rc = sync_poses(s);
+    if (rc) return rc;
+    EnvHost& H = s->envs[env];
+    std::vector<tr_body_desc> bodies;
+    std::vector<std::vector<tr_shape_desc>> shapes;
+    std::vector<std::vector<std::vector<float>>> heights;
+    int zones = 0;
+    for (int i = 0; i < n; ++i) {
+        const tr_body_desc& B = b[i];
+        if (B.n_shapes < 0 || (B.n_shapes > 0 && !B.shapes) || B.n_halfspaces < 0 || B.n_halfspaces > 8)
+            return fail(s, TR_E_INVAL, "body: bad shapes or half-spaces");
+        if (!finite3(B.pos, 3) || !finite3(B.quat, 4) || !finite3(B.linvel, 3) || !finite3(B.angvel, 3) ||
+            !finite3(&B.planes[0][0], 4 * B.n_halfspaces))
+            return fail(s, TR_E_NONFINITE, "body: non-finite pose");
+        double qn = std::sqrt(B.quat[0] * B.quat[0] + B.quat[1] * B.quat[1] + B.quat[2] * B.quat[2] + B.quat[3] * B.quat[3]);
+        if (std::fabs(qn - 1.0) > 1e-6) return fail(s, TR_E_INVAL, "body: quaternion not unit");
+        if (B.n_halfspaces > 0) ++zones;
+        for (int j = 0; j < i; ++j)
+            if (b[j].id == B.id) return fail(s, TR_E_INVAL, "body: duplicate id");
+        bodies.push_back(B);
+        bodies.back().shapes = nullptr;
+        shapes.emplace_back();
+        heights.emplace_back();
+        for (int k = 0; k < B.n_shapes; ++k) {
+            tr_shape_desc S = B.shapes[k];
+            std::vector<float> hh;
+            if (S.type == TR_HEIGHTFIELD) {
+                if (S.nx < 2 || S.ny < 2 || S.l0 <= 0.0 || !S.heights) return fail(s, TR_E_INVAL, "heightfield: bad grid");
+                hh.assign(S.heights, S.heights + (int64_t)S.nx * S.ny);
+                for (float v : hh)
+                    if (!std::isfinite(v)) return fail(s, TR_E_NONFINITE, "heightfield: non-finite height");
+                S.heights = nullptr;
+            } else if (S.type == TR_BOX) {
+                if (S.half[0] <= 0 || S.half[1] <= 0 || S.half[2] <= 0) return fail(s, TR_E_INVAL, "box: half extents");
+            } else if (S.type == TR_PLANE) {
+                double nn = S.normal[0] * S.normal[0] + S.normal[1] * S.normal[1] + S.normal[2] * S.normal[2];
+                if (std::fabs(nn - 1.0) > 1e-9) return fail(s, TR_E_INVAL, "plane: normal not unit");
+            } else {
+                return fail(s, TR_E_INVAL, "shape: unknown type");
+            }
+            shapes.back().push_back(S);
+            heights.back().push_back(std::move(hh));
+        }
+    }
+    if (zones > kMaxZonesPerEnv) return fail(s, TR_E_CAPACITY, "more than 4 zones in an env");
+    H.bodies = std::move(bodies);
+    H.shapes = std::move(shapes);
+    H.heights = std::move(heights);
+    s->tables_dirty = true;
+    s->have_prev = false;
+    return TR_OK;
+}
+
+int step(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (n_steps < 0) return fail(s, TR_E_INVAL, "step: n_steps < 0");
+    if (s->tables_dirty) {
+        int rc = rebuild_tables(s);
+        if (rc) return rc;
+    }
+    hipStream_t st = s->stream;
+    for (int k = 0; k < n_steps; ++k) {
+        (void)hipEventRecord(s->ev[0], st);
+        launch_step_begin(s->b, s->p, st);
+        launch_sort_particles(s->b, s->p, s->z, st);
+        std::swap(s->b.xr, s->b.xr2);
+        std::swap(s->b.vm, s->b.vm2);
+        std::swap(s->b.wi, s->b.wi2);
+        std::swap(s->b.pid, s->b.pid2);
+        std::swap(s->b.rho, s->b.rho2);
+        launch_narrow(s->b, s->p, s->z, st);
+        launch_canonical(s->b, s->p, s->z, st);
+        (void)hipEventRecord(s->ev[1], st);
+        launch_colour(s->b, s->p, s->z, st);
+        launch_rows(s->b, s->p, s->z, s->have_prev, st);
+        if (s->p.warm == TR_WARM_LEARNED) launch_learned_start(s->b, s->p, s->z, st);
+        launch_warm_apply(s->b, s->p, s->z, st);
+        (void)hipEventRecord(s->ev[2], st);
+        launch_pgs(s->b, s->p, s->z, st);
+        (void)hipEventRecord(s->ev[3], st);
+        launch_finish(s->b, s->p, s->z, st);
+        (void)hipEventRecord(s->ev[4], st);
+        std::swap(s->b.ckey, s->b.pkeyc);
+        std::swap(s->b.lamc, s->b.plam);
+        std::swap(s->b.id_start, s->b.pid_start);
+        s->have_prev = true;
+        s->stepped = true;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(s, e, "step launch");
+    if (stats) {
+        HIP_CHECK(s, hipStreamSynchronize(st));
+        Counters c;
+        std::vector<EnvStats> es(s->desc.n_envs);
+        HIP_CHECK(s, hipMemcpy(&c, s->b.cnt, sizeof(c), hipMemcpyDeviceToHost));
+        HIP_CHECK(s, hipMemcpy(es.data(), s->b.env_stats, sizeof(EnvStats) * es.size(), hipMemcpyDeviceToHost));
+        for (int e2 = 0; e2 < s->desc.n_envs; ++e2) {
+            tr_step_stats& o = stats[e2];
+            o.contacts = es[e2].contacts;
+            o.pair_contacts = es[e2].pairs;
+            o.colours = (int32_t)c.n_colours;
+            o.sweeps = (int32_t)c.sweeps;
+            o.residual = c.resid;
+            o.residual_first = c.resid_first;
+            o.fallback_used = (int32_t)c.fallback;
+            o.overflow = (int32_t)c.overflow;
+        }
+        if (c.overflow) {
+            s->have_prev = false;
+            char msg[128];
+            snprintf(msg, sizeof msg, "step: capacity or schedule failure (flags 0x%x, %u contacts found)", c.overflow, c.n_raw);
+            return fail(s, TR_E_CAPACITY, msg);
+        }
+    }
+    return TR_OK;
+}
+
+int get_contact_forces(tr_scene* s, int32_t env, int32_t body_id, double force[3], double torque[3])
+{
+    if (!s || !force || !torque) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "get_contact_forces: env");
+    if (s->tables_dirty) return fail(s, TR_E_STATE, "get_contact_forces: no step since the bodies changed");
+    int gi = -1;
+    for (size_t i = 0; i < s->body_host.size(); ++i)
+        if (s->body_host[i].env == env && s->body_host[i].user_id == body_id) gi = (int)i;
+    if (gi < 0) return fail(s, TR_E_INVAL, "get_contact_forces: unknown body");
+    double ft[6];
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    HIP_CHECK(s, hipMemcpy(ft, s->b.body_ft + 6 * gi, sizeof(ft), hipMemcpyDeviceToHost));
+    for (int k = 0; k < 3; ++k) { force[k] = ft[k]; torque[k] = ft[3 + k]; }
+    return TR_OK;
+}
+
+int get_aggregates(tr_scene* s, int32_t env, int32_t cap, tr_aggregate* out, int32_t* n_out)
+{
+    if (!s || !n_out || cap < 0 || (cap > 0 && !out)) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "get_aggregates: env");
+    if (s->tables_dirty) {
+        *n_out = 0;
+        return fail(s, TR_E_STATE, "get_aggregates: no step since the bodies changed");
+    }
+    const std::vector<int>& zs = s->zone_slots[env];
+    *n_out = (int32_t)zs.size();
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    for (int k = 0; k < (int)zs.size() && k < cap; ++k)
+        HIP_CHECK(s, hipMemcpy(&out[k], s->b.aggs + zs[k], sizeof(tr_aggregate), hipMemcpyDeviceToHost));
+    return TR_OK;
+}
+
+const char* get_last_error(tr_scene* s) { return s ? s->err.c_str() : "null scene"; }
+
+int get_contacts(tr_scene* s, int32_t env, int64_t cap, uint64_t* keys, float* impulse4, int64_t* n)
+{
+    if (!s || !n || cap < 0 || (cap > 0 && !keys)) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "get_contacts: env");
+    *n = 0;
+    if (!s->stepped) return TR_OK;
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    // after a step the canonical lists of that step live in the "previous" buffers
+    int64_t base = (int64_t)env * s->desc.cap_particles;
+    uint32_t r[2];
+    HIP_CHECK(s, hipMemcpy(&r[0], s->b.pid_start + base, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    HIP_CHECK(s, hipMemcpy(&r[1], s->b.pid_start + base + s->desc.cap_particles, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    int64_t cnt = (int64_t)r[1] - (int64_t)r[0];
+    *n = cnt;
+    int64_t m = std::min(cnt, cap);
+    if (m > 0) {
+        HIP_CHECK(s, hipMemcpy(keys, s->b.pkeyc + r[0], sizeof(uint64_t) * m, hipMemcpyDeviceToHost));
+        if (impulse4) HIP_CHECK(s, hipMemcpy(impulse4, s->b.plam + r[0], sizeof(float4) * m, hipMemcpyDeviceToHost));
+    }
+    // keys of boundary contacts carry the env-local shape index already
+    return TR_OK;
+}
+
+int get_particles(tr_scene* s, int32_t env, double* pos, double* vel, double* angvel, double* radius, int64_t* n)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "get_particles: env");
+    int64_t ne = s->envs[env].n;
+    if (n) *n = ne;
+    if (ne == 0) return TR_OK;
+    float4* st4 = (float4*)s->staging;
+    launch_gather_by_id(s->b, (int)(env * s->desc.cap_particles), (int)ne, st4, st4 + ne, st4 + 2 * ne, s->stream);
+    std::vector<float4> h(3 * ne);
+    HIP_CHECK(s, hipMemcpyAsync(h.data(), st4, sizeof(float4) * 3 * ne, hipMemcpyDeviceToHost, s->stream));
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    for (int64_t i = 0; i < ne; ++i) {
+        const float4 &x = h[i], &v = h[ne + i], &w = h[2 * ne + i];
+        if (pos) { pos[3 * i] = x.x; pos[3 * i + 1] = x.y; pos[3 * i + 2] = x.z; }
+        if (radius) radius[i] = x.w;
+        if (vel) { vel[3 * i] = v.x; vel[3 * i + 1] = v.y; vel[3 * i + 2] = v.z; }
+        if (angvel) { angvel[3 * i] = w.x; angvel[3 * i + 1] = w.y; angvel[3 * i + 2] = w.z; }
+    }
+    return TR_OK;
+}
+
+int set_particles(tr_scene* s, int32_t env, const double* pos, const double* vel, const double* angvel)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "set_particles: env");
+    int64_t ne = s->envs[env].n;
+    if (ne == 0) return TR_OK;
+    if ((pos && !finite3(pos, 3 * ne)) || (vel && !finite3(vel, 3 * ne)) || (angvel && !finite3(angvel, 3 * ne)))
+        return fail(s, TR_E_NONFINITE, "set_particles: non-finite input");
+    std::vector<float4> h(3 * ne, make_float4(0.f, 0.f, 0.f, 0.f));
+    for (int64_t i = 0; i < ne; ++i) {
+        if (pos) h[i] = make_float4((float)pos[3 * i], (float)pos[3 * i + 1], (float)pos[3 * i + 2], 0.f);
+        if (vel) h[ne + i] = make_float4((float)vel[3 * i], (float)vel[3 * i + 1], (float)vel[3 * i + 2], 0.f);
+        if (angvel) h[2 * ne + i] = make_float4((float)angvel[3 * i], (float)angvel[3 * i + 1], (float)angvel[3 * i + 2], 0.f);
+    }
+    float4* st4 = (float4*)s->staging;
+    HIP_CHECK(s, hipMemcpyAsync(st4, h.data(), sizeof(float4) * 3 * ne, hipMemcpyHostToDevice, s->stream));
+    int mask = (pos ? 1 : 0) | (vel ? 2 : 0) | (angvel ? 4 : 0);
+    launch_scatter_by_id(s->b, (int)(env * s->desc.cap_particles), (int)ne, st4, st4 + ne, st4 + 2 * ne, mask, s->stream);
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    s->have_prev = false;
+    return TR_OK;
+}
+
+int set_mlp_weights(tr_scene* s, const float* weights, int64_t n)
+{
+    if (!s || !weights) return TR_E_INVAL;
+    s->err.clear();
+    if (n != kMlpParams) return fail(s, TR_E_INVAL, "set_mlp_weights: wrong parameter count");
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(weights[i])) return fail(s, TR_E_NONFINITE, "set_mlp_weights: non-finite weight");
+    HIP_CHECK(s, hipMemcpyAsync(s->b.mlp, weights, sizeof(float) * n, hipMemcpyHostToDevice, s->stream));
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    return TR_OK;
+}
+
+int get_phase_times(tr_scene* s, float* ms, int32_t cap)
+{
+    if (!s || !ms || cap < 0) return TR_E_INVAL;
+    s->err.clear();
+    if (!s->stepped) return fail(s, TR_E_STATE, "get_phase_times: no step yet");
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    float t[5];
+    for (int k = 0; k < 4; ++k) HIP_CHECK(s, hipEventElapsedTime(&t[k], s->ev[k], s->ev[k + 1]));
+    HIP_CHECK(s, hipEventElapsedTime(&t[4], s->ev[0], s->ev[4]));
+    for (int k = 0; k < cap && k < 5; ++k) ms[k] = t[k];
+    return TR_OK;
+}
+
+}  // extern "C"

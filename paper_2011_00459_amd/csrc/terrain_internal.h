@@ -1,0 +1,203 @@
+// terrain_internal.h -- device data layout and kernel launchers of libterrain.
+//
+// Layout in HBM (all arrays allocated once at their capacities):
+//   particles, sorted every step by (environment, Morton cell, id):
+//     xr[P]  float4 (x, y, z, r)         vm[P] float4 (v, 1/m)
+//     wi[P]  float4 (omega, 1/I)         pid[P] int32 global id   rho[P] float
+//   cells: per environment a dense grid, keys = cell_base + Morton code
+//   contacts (capacity C):
+//     raw detection output  rkey[C] u64, rpair[C] int2
+//     canonical (key order) ckey[C] u64, cpair[C] int2, lamc[C] float4
+//     colour order rows     r0 (n, l1), r1 (l2, 1/Dn, 1/Dt, Sigma),
+//                           r2 (q, lo, body1, body2), rk (kinematic velocity), lam (impulses)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "terrain.h"
+
+namespace trk {
+
+constexpr int kMaxColours = 64;     // colours of the contact schedule (64-bit masks)
+constexpr int kMaxHits = 32;        // contacts one particle may emit per step
+constexpr int kMaxZonesPerEnv = 4;  // bodies with an active zone per environment
+constexpr int kZoneMoments = 20;    // M, mx(3), mv(3), mxx(6), m x*v(3), sum Is(1), sum Is w(3)
+constexpr int kForceChunks = 32;    // deterministic chunks of the body-force reduction
+constexpr int kZoneChunk = 2048;    // particles per chunk of the zone reduction
+constexpr int kMlpParams = 64 * 12 + 64 + 64 * 64 + 64 + 3 * 64 + 3 + 12;
+
+// Overflow / failure bits of Counters::overflow
+enum : uint32_t {
+    kOvfContacts = 1u,
+    kOvfHits = 2u,
+    kOvfColours = 4u,
+    kFailColouring = 8u,
+    kFailBarrier = 16u,
+    kOvfZones = 32u,
+};
+
+struct EnvDev {
+    float lo[3];
+    float inv_h;
+    int dims[3];
+    int bits[3];
+    uint32_t cell_base;
+    int shape_begin, shape_end;   // env's shapes in the shape table
+    int body_begin, body_end;     // env's bodies
+    int id_base;                  // first particle id of the env
+    int n;                        // particles of the env
+    int slot_begin;               // first slot of the env in sorted order
+    int zone_count;
+    int zone_body[kMaxZonesPerEnv];  // global body index of each zone
+    int zone_slot[kMaxZonesPerEnv];  // global zone index of each zone
+};
+
+struct BodyDev {
+    double pos[3];
+    double quat[4];
+    double linvel[3];
+    double angvel[3];
+    double R[9];          // rotation of quat, row-major (start of step)
+    double planes[8][4];  // zone half-spaces, body frame
+    double wplanes[8][4]; // zone half-spaces, world frame (end of step)
+    int env;
+    int nplanes;
+    int user_id;
+    int pad;
+};
+
+struct ShapeDev {
+    int type;
+    int body;        // global body index
+    int env;
+    int hf_off;      // offset of the heights in the heightfield pool
+    double n[3];     // plane normal (body frame)
+    double d;        // plane offset
+    double half[3];  // box half extents
+    double off[3];   // box centre (body frame)
+    int nx, ny;
+    double ox, oy, l0, inv_l0;
+    // world-frame values of the current step
+    double wn[3];
+    double wd;
+    double wc[3];
+    double R[9];
+};
+
+struct StepParams {
+    float dt;
+    float g[3];
+    float mu;
+    float gamma_dt;     // gamma_t / dt
+    double kappa_c;     // cohesive range fraction (0 when c_p == 0)
+    double kappa_min;
+    double Estar;
+    double a_coef;      // (4/dt) Upsilon
+    double b_coef;      // Upsilon
+    double sig_coef;    // (4/dt^2) Upsilon
+    double lo_coef;     // c_p pi dt
+    uint32_t id_cap;    // ids per environment
+    int n_envs;
+    int max_sweeps;
+    float tol;
+    int warm;
+    int n_particles;    // all envs
+    int n_bodies;
+    int n_shapes;
+    int n_zones;
+};
+
+struct Counters {
+    uint32_t n_raw;        // contacts found by detection (may exceed capacity)
+    uint32_t n_pairs;
+    uint32_t overflow;     // kOvf* / kFail* bits, sticky within a step
+    uint32_t n_colours;
+    uint32_t sweeps;
+    uint32_t fallback;
+    uint32_t barrier_count;
+    uint32_t barrier_gen;
+    double resid;
+    double resid_first;
+};
+
+struct EnvStats {
+    int64_t contacts;
+    int64_t pairs;
+};
+
+// Everything the kernels touch, as raw device pointers.
+struct DevBuffers {
+    // particles (capacity P, double buffered for the sort)
+    float4 *xr, *vm, *wi, *xr2, *vm2, *wi2;
+    int *pid, *pid2;
+    float *rho, *rho2;
+    uint32_t *pkey, *perm;
+    int* id2slot;         // [NID]
+    // cells
+    uint32_t *cell_count, *cell_start, *cell_fill;  // [NC], [NC+1], [NC]
+    // contacts
+    unsigned long long *rkey, *ckey, *pkeyc;        // raw, canonical, previous canonical
+    int2 *rpair, *cpair;
+    float4 *lamc, *plam;                            // canonical impulses (current, previous)
+    uint32_t *id_count, *id_start, *id_fill, *pid_start;  // [NID], [NID+1], [NID], [NID+1]
+    uint32_t *inc_count, *inc_start, *inc_fill, *inc;     // [P], [P+1], [P], [2C]
+    int* colour;                                    // [C]
+    uint32_t *col_hist, *col_start;                 // [64*NB], [64*NB+1]
+    uint32_t* cpos;                                 // canonical -> colour position
+    float4 *r0, *r1, *r2, *rk, *lam, *lam0;         // colour order
+    // reductions
+    double* resid_acc;    // [max_sweeps * 2] per-sweep numerator / denominator... (block partials)
+    double* block_part;   // [grid * 2]
+    double* force_part;   // [bodies * kForceChunks * 6]
+    double* body_ft;      // [bodies * 6]
+    double* zone_part;    // [chunks * kMaxZonesPerEnv * kZoneMoments]
+    double* zone_mom;     // [zones * kZoneMoments]
+    tr_aggregate* aggs;   // [zones]
+    int4* zone_chunks;    // (env, begin, end, first zone) per chunk
+    // scene tables
+    EnvDev* envs;
+    BodyDev* bodies;
+    ShapeDev* shapes;
+    float* hf_pool;
+    Counters* cnt;
+    EnvStats* env_stats;
+    uint32_t* scan_tmp;   // scratch of the device-wide scan
+    float* mlp;           // learned-start weights
+};
+
+// Sizes that fix the launch shapes.
+struct Sizes {
+    int64_t P;      // particle capacity (all envs)
+    int64_t C;      // contact capacity (all envs)
+    int64_t NID;    // id space = n_envs * cap_particles
+    int64_t NC;     // cells (all envs)
+    int64_t NB;     // blocks of 256 over C (colour bucketing)
+    int n_zone_chunks;
+    int pgs_grid;   // resident blocks of the persistent PGS kernel
+    int pgs_block;
+    int col_grid;   // resident blocks of the colouring kernel
+};
+
+// ---- launchers (terrain_kernels.hip) ----
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s);
+int64_t scan_tmp_words(int64_t n);
+void launch_step_begin(const DevBuffers& b, const StepParams& p, hipStream_t s);
+// writes the sorted particle arrays into the *2 buffers: swap them after
+void launch_sort_particles(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+void launch_narrow(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+void launch_canonical(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, hipStream_t s);
+void launch_learned_start(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+void launch_finish(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+void launch_gather_by_id(const DevBuffers& b, int id_base, int n, float4* xo, float4* vo, float4* wo,
+                         hipStream_t s);
+void launch_scatter_by_id(const DevBuffers& b, int id_base, int n, const float4* xi, const float4* vi,
+                          const float4* wi, int mask, hipStream_t s);
+int pgs_resident_blocks(int block);
+int colour_resident_blocks();
+
+}  // namespace trk

@@ -1,0 +1,1353 @@
+// terrain_kernels.hip -- gfx950 kernels of one agitated-soil particle step.
+//
+// The step (Algorithm 1 of Servin, Berglund & Nystedt: collision detection,
+// the mesoscale contact constraints, the aggregate bodies, the PGS solve and
+// the position update) is split into these kernel families:
+//   bin/scan/scatter/gather   particles sorted by (env, Morton cell, id)
+//   narrow                    sphere-sphere and sphere-boundary contacts with
+//                             a pinned FP64 predicate, wave-compacted
+//   id count/scatter/sort     canonical contact order (key order)
+//   incidence + colour        per-particle incidence lists and a greedy
+//                             colouring in splitmix64 priority order
+//   rows                      Hertz-mapped SPOOK rows (Eqs. signCoul1-2)
+//   warm apply                v* = v + dt g + M^-1 G^T lambda^0
+//   pgs                       persistent colour-synchronous projected
+//                             Gauss-Seidel sweeps with the residual fused in
+//   finish                    body forces (FP64), x += dt v, kinematic poses,
+//                             zone aggregates (FP64, Eqs. aggregate_mass ..
+//                             aggregate_rot_vel)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "terrain_internal.h"
+
+namespace trk {
+
+constexpr int kBlk = 256;
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// generic fill and device-wide exclusive scan (out[n] = total)
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += st) p[i] = v;
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    int grid = (int)std::min<int64_t>(cdiv(n, kBlk), 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(kBlk), 0, s, p, v, n);
+}
+
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlk * kScanItems;
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// exclusive block scan of one value per thread; returns the block total via *tot
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* tot)
+{
+    __shared__ uint32_t wsum[kBlk / 64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, all = 0;
+    for (int k = 0; k < kBlk / 64; ++k) {
+        if (k < w) off += wsum[k];
+        all += wsum[k];
+    }
+    __syncthreads();
+    *tot = all;
+    return off + inc - v;
+}
+
+__global__ void k_scan_reduce(const uint32_t* in, int64_t n, uint32_t* tmp)
+{
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+        if (i < n) s += in[i];
+    }
+    uint32_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_top(uint32_t* tmp, int64_t nb)
+{
+    // single block: exclusive scan of the block totals, total at tmp[nb]
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += kBlk) {
+        int64_t i = base + threadIdx.x;
+        uint32_t v = i < nb ? tmp[i] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(v, &tot);
+        if (i < nb) tmp[i] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tmp[nb] = carry;
+}
+
+__global__ void k_scan_down(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* tmp, int64_t nb)
+{
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+        v[k] = i < n ? in[i] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(s, &tot) + tmp[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+        if (i < n) out[i] = ex;
+        ex += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tmp[nb];
+}
+
+int64_t scan_tmp_words(int64_t n) { return cdiv(std::max<int64_t>(n, 1), kScanTile) + 1; }
+
+void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s)
+{
+    int64_t nb = cdiv(std::max<int64_t>(n, 1), kScanTile);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlk), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlk), 0, s, tmp, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlk), 0, s, in, out, n, tmp, nb);
+}
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t env_of(int id, uint32_t id_cap) { return (uint32_t)id / id_cap; }
+
+__device__ inline uint32_t morton(int cx, int cy, int cz, const int bits[3])
+{
+    // non-uniform interleave: one bit of each axis that still has bits, x first
+    uint32_t key = 0;
+    int pos = 0;
+    int mb = max(bits[0], max(bits[1], bits[2]));
+    for (int b = 0; b < mb; ++b) {
+        if (b < bits[0]) key |= (uint32_t)((cx >> b) & 1) << pos++;
+        if (b < bits[1]) key |= (uint32_t)((cy >> b) & 1) << pos++;
+        if (b < bits[2]) key |= (uint32_t)((cz >> b) & 1) << pos++;
+    }
+    return key;
+}
+
+__device__ inline void cell_of(const EnvDev& E, float x, float y, float z, int c[3])
+{
+    float f[3] = {(x - E.lo[0]) * E.inv_h, (y - E.lo[1]) * E.inv_h, (z - E.lo[2]) * E.inv_h};
+    for (int k = 0; k < 3; ++k) {
+        float g = fminf(fmaxf(floorf(f[k]), 0.0f), (float)(E.dims[k] - 1));
+        c[k] = (int)g;
+    }
+}
+
+__device__ inline unsigned long long splitmix64(unsigned long long x)
+{
+    unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Rotation matrix of a unit quaternion (w, x, y, z), row-major.  The
+// operation order is fixed: box and plane predicates depend on it bitwise.
+__device__ inline void quat_to_R(const double* q, double* R)
+{
+#pragma clang fp contract(off)
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Pinned sphere-sphere predicate (FP64, fixed order, no contraction).
+__device__ inline bool pair_touch(double xi, double yi, double zi, double ri, double xj, double yj, double zj,
+                                  double rj, double kappa_c)
+{
+#pragma clang fp contract(off)
+    double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+    double d2 = (dx * dx + dy * dy) + dz * dz;
+    double rs = ri + rj;
+    double R = rs + (kappa_c > 0.0 ? kappa_c * rs : 0.0);
+    return d2 < R * R;
+}
+
+struct ShapeHit {
+    double delta;
+    double n[3];
+};
+
+// Sphere against a boundary shape (world data of the step).  Returns true on
+// contact; fills overlap and the normal (shape -> particle) when hit != NULL.
+__device__ inline bool shape_touch(const ShapeDev& S, const float* hf, double x, double y, double z, double r,
+                                   double kappa_c, ShapeHit* hit)
+{
+#pragma clang fp contract(off)
+    double Rr = r + (kappa_c > 0.0 ? kappa_c * (2.0 * r) : 0.0);
+    if (S.type == TR_PLANE) {
+        double sd = ((S.wn[0] * x + S.wn[1] * y) + S.wn[2] * z) - S.wd;
+        if (!(sd < 0.0 || sd * sd < Rr * Rr)) return false;
+        if (hit) {
+            hit->delta = r - sd;
+            hit->n[0] = S.wn[0]; hit->n[1] = S.wn[1]; hit->n[2] = S.wn[2];
+        }
+        return true;
+    }
+    if (S.type == TR_BOX) {
+        const double* R = S.R;
+        double dx = x - S.wc[0], dy = y - S.wc[1], dz = z - S.wc[2];
+        double l[3], q[3];
+        bool inside = true;
+        for (int k = 0; k < 3; ++k) {
+            l[k] = (R[0 * 3 + k] * dx + R[1 * 3 + k] * dy) + R[2 * 3 + k] * dz;
+            q[k] = l[k];
+            if (q[k] > S.half[k]) { q[k] = S.half[k]; inside = false; }
+            if (q[k] < -S.half[k]) { q[k] = -S.half[k]; inside = false; }
+        }
+        if (inside) {
+            if (hit) {
+                int kb = 0;
+                double pb = S.half[0] - fabs(l[0]);
+                for (int k = 1; k < 3; ++k) {
+                    double pk = S.half[k] - fabs(l[k]);
+                    if (pk < pb) { pb = pk; kb = k; }
+                }
+                double sg = l[kb] >= 0.0 ? 1.0 : -1.0;
+                for (int k = 0; k < 3; ++k) hit->n[k] = sg * R[k * 3 + kb];
+                hit->delta = r + pb;
+            }
+            return true;
+        }
+        double e0 = l[0] - q[0], e1 = l[1] - q[1], e2 = l[2] - q[2];
+        double d2 = (e0 * e0 + e1 * e1) + e2 * e2;
+        if (!(d2 < Rr * Rr)) return false;
+        if (hit) {
+            double dist = sqrt(d2);
+            double nl[3] = {e0 / dist, e1 / dist, e2 / dist};
+            for (int k = 0; k < 3; ++k) hit->n[k] = (R[k * 3 + 0] * nl[0] + R[k * 3 + 1] * nl[1]) + R[k * 3 + 2] * nl[2];
+            hit->delta = r - dist;
+        }
+        return true;
+    }
+    if (S.type == TR_HEIGHTFIELD) {
+        double fx = (x - S.ox) * S.inv_l0;
+        double fy = (y - S.oy) * S.inv_l0;
+        double fi = floor(fx), fj = floor(fy);
+        if (fi < 0.0) fi = 0.0;
+        if (fi > (double)(S.nx - 2)) fi = (double)(S.nx - 2);
+        if (fj < 0.0) fj = 0.0;
+        if (fj > (double)(S.ny - 2)) fj = (double)(S.ny - 2);
+        int i = (int)fi, j = (int)fj;
+        double t = fx - fi, u = fy - fj;
+        const float* h = hf + S.hf_off;
+        double h00 = h[j * S.nx + i], h10 = h[j * S.nx + i + 1];
+        double h01 = h[(j + 1) * S.nx + i], h11 = h[(j + 1) * S.nx + i + 1];
+        double hh = (h00 * (1.0 - t) + h10 * t) * (1.0 - u) + (h01 * (1.0 - t) + h11 * t) * u;
+        double hx = ((h10 - h00) * (1.0 - u) + (h11 - h01) * u) * S.inv_l0;
+        double hy = ((h01 - h00) * (1.0 - t) + (h11 - h10) * t) * S.inv_l0;
+        double dz = z - hh;
+        double m2 = (1.0 + hx * hx) + hy * hy;
+        if (!(dz < 0.0 || dz * dz < (Rr * Rr) * m2)) return false;
+        if (hit) {
+            double nz = 1.0 / sqrt(m2);
+            hit->n[0] = -hx * nz; hit->n[1] = -hy * nz; hit->n[2] = nz;
+            hit->delta = r - dz * nz;
+        }
+        return true;
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// step begin: world data of shapes, clears
+// ---------------------------------------------------------------------------
+__global__ void k_step_begin(DevBuffers b, StepParams p)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        Counters* c = b.cnt;
+        c->n_raw = 0; c->n_pairs = 0; c->overflow = 0; c->n_colours = 0;
+        c->sweeps = 0; c->fallback = 0; c->barrier_count = 0; c->barrier_gen = 0;
+        c->resid = 0.0; c->resid_first = 0.0;
+    }
+    if (t < p.n_envs) { b.env_stats[t].contacts = 0; b.env_stats[t].pairs = 0; }
+    if (t < p.n_shapes) {
+#pragma clang fp contract(off)
+        ShapeDev& S = b.shapes[t];
+        const BodyDev& B = b.bodies[S.body];
+        double R[9];
+        quat_to_R(B.quat, R);
+        for (int k = 0; k < 9; ++k) S.R[k] = R[k];
+        for (int k = 0; k < 3; ++k) S.wn[k] = (R[k * 3 + 0] * S.n[0] + R[k * 3 + 1] * S.n[1]) + R[k * 3 + 2] * S.n[2];
+        S.wd = S.d + ((S.wn[0] * B.pos[0] + S.wn[1] * B.pos[1]) + S.wn[2] * B.pos[2]);
+        for (int k = 0; k < 3; ++k)
+            S.wc[k] = B.pos[k] + ((R[k * 3 + 0] * S.off[0] + R[k * 3 + 1] * S.off[1]) + R[k * 3 + 2] * S.off[2]);
+    }
+}
+
+void launch_step_begin(const DevBuffers& b, const StepParams& p, hipStream_t s)
+{
+    int n = std::max(1, std::max(p.n_shapes, p.n_envs));
+    hipLaunchKernelGGL(k_step_begin, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, s, b, p);
+}
+
+// ---------------------------------------------------------------------------
+// A1-A2: binning, counting sort by cell key, per-cell id order, gather
+// ---------------------------------------------------------------------------
+__global__ void k_bin(DevBuffers b, StepParams p)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n_particles) return;
+    float4 x = b.xr[i];
+    const EnvDev& E = b.envs[env_of(b.pid[i], p.id_cap)];
+    int c[3];
+    cell_of(E, x.x, x.y, x.z, c);
+    uint32_t key = E.cell_base + morton(c[0], c[1], c[2], E.bits);
+    b.pkey[i] = key;
+    atomicAdd(&b.cell_count[key], 1u);
+}
+
+__global__ void k_scatter_cells(DevBuffers b, StepParams p)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n_particles) return;
+    uint32_t key = b.pkey[i];
+    uint32_t slot = b.cell_start[key] + atomicAdd(&b.cell_fill[key], 1u);
+    b.perm[slot] = (uint32_t)i;
+}
+
+// the first slot of every cell orders the cell's particles by id
+__global__ void k_cell_order(DevBuffers b, StepParams p)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n_particles) return;
+    uint32_t key = b.pkey[b.perm[s]];
+    uint32_t beg = b.cell_start[key], end = b.cell_start[key + 1];
+    if ((uint32_t)s != beg) return;
+    for (uint32_t a = beg + 1; a < end; ++a) {
+        uint32_t v = b.perm[a];
+        int idv = b.pid[v];
+        uint32_t t = a;
+        while (t > beg && b.pid[b.perm[t - 1]] > idv) {
+            b.perm[t] = b.perm[t - 1];
+            --t;
+        }
+        b.perm[t] = v;
+    }
+}
+
+__global__ void k_gather(DevBuffers b, StepParams p)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n_particles) return;
+    uint32_t i = b.perm[s];
+    b.xr2[s] = b.xr[i];
+    b.vm2[s] = b.vm[i];
+    b.wi2[s] = b.wi[i];
+    b.rho2[s] = b.rho[i];
+    int id = b.pid[i];
+    b.pid2[s] = id;
+    b.id2slot[id] = s;
+}
+
+void launch_sort_particles(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+{
+    int n = p.n_particles;
+    launch_fill_u32(b.cell_count, 0u, z.NC, s);
+    launch_fill_u32(b.cell_fill, 0u, z.NC, s);
+    if (n <= 0) return;
+    unsigned g = (unsigned)cdiv(n, kBlk);
+    hipLaunchKernelGGL(k_bin, dim3(g), dim3(kBlk), 0, s, b, p);
+    launch_scan_u32(b.cell_count, b.cell_start, z.NC, b.scan_tmp, s);
+    hipLaunchKernelGGL(k_scatter_cells, dim3(g), dim3(kBlk), 0, s, b, p);
+    hipLaunchKernelGGL(k_cell_order, dim3(g), dim3(kBlk), 0, s, b, p);
+    hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlk), 0, s, b, p);
+}
+
+// ---------------------------------------------------------------------------
+// A3-A4: narrow phase (pairs through the 27 neighbour cells, then the env's
+// boundary shapes), compacted per wave
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlk) void k_narrow(DevBuffers b, StepParams p, int64_t cap)
+{
+    __shared__ int hits[kBlk][kMaxHits + 1];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int nh = 0;
+    int idi = 0;
+    bool ovf = false;
+    uint32_t env = 0;
+    if (i < p.n_particles) {
+        float4 xi = b.xr[i];
+        idi = b.pid[i];
+        env = env_of(idi, p.id_cap);
+        const EnvDev& E = b.envs[env];
+        int c[3];
+        cell_of(E, xi.x, xi.y, xi.z, c);
+        double X = xi.x, Y = xi.y, Z = xi.z, Ri = xi.w;
+        for (int dz = -1; dz <= 1; ++dz) {
+            int cz = c[2] + dz;
+            if (cz < 0 || cz >= E.dims[2]) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                int cy = c[1] + dy;
+                if (cy < 0 || cy >= E.dims[1]) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int cx = c[0] + dx;
+                    if (cx < 0 || cx >= E.dims[0]) continue;
+                    uint32_t key = E.cell_base + morton(cx, cy, cz, E.bits);
+                    uint32_t beg = b.cell_start[key], end = b.cell_start[key + 1];
+                    for (uint32_t j = beg; j < end; ++j) {
+                        int idj = b.pid[j];
+                        if (idj <= idi) continue;
+                        float4 xj = b.xr[j];
+                        if (pair_touch(X, Y, Z, Ri, (double)xj.x, (double)xj.y, (double)xj.z, (double)xj.w, p.kappa_c)) {
+                            if (nh < kMaxHits) hits[threadIdx.x][nh++] = (int)j;
+                            else ovf = true;
+                        }
+                    }
+                }
+            }
+        }
+        for (int sg = E.shape_begin; sg < E.shape_end; ++sg) {
+            if (shape_touch(b.shapes[sg], b.hf_pool, X, Y, Z, Ri, p.kappa_c, nullptr)) {
+                if (nh < kMaxHits) hits[threadIdx.x][nh++] = -1 - sg;
+                else ovf = true;
+            }
+        }
+    }
+    // wave-level compaction: one atomic per wave
+    int lane = threadIdx.x & 63;
+    uint32_t inc = wave_incl_scan((uint32_t)nh);
+    uint32_t total = __shfl(inc, 63, 64);
+    uint32_t base = 0;
+    if (lane == 63 && total > 0) base = atomicAdd(&b.cnt->n_raw, total);
+    base = __shfl(base, 63, 64);
+    uint32_t off = base + inc - (uint32_t)nh;
+    int npairs = 0;
+    for (int k = 0; k < nh; ++k) {
+        int h = hits[threadIdx.x][k];
+        uint64_t idx = (uint64_t)off + (uint64_t)k;
+        if (idx >= (uint64_t)cap) { ovf = true; continue; }
+        if (h >= 0) {
+            int idj = b.pid[h];
+            b.rkey[idx] = ((unsigned long long)(uint32_t)idi << 32) | (uint32_t)idj;
+            b.rpair[idx] = make_int2(i, h);
+            ++npairs;
+        } else {
+            int sg = -1 - h;
+            int local = sg - b.envs[env].shape_begin;
+            b.rkey[idx] = ((unsigned long long)(uint32_t)idi << 32) | 0x80000000ull | (uint32_t)local;
+            b.rpair[idx] = make_int2(h, i);
+        }
+    }
+    if (npairs) atomicAdd((unsigned long long*)&b.env_stats[env].pairs, (unsigned long long)npairs);
+    if (ovf) atomicOr(&b.cnt->overflow, kOvfContacts);
+}
+
+void launch_narrow(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+{
+    if (p.n_particles <= 0) return;
+    hipLaunchKernelGGL(k_narrow, dim3((unsigned)cdiv(p.n_particles, kBlk)), dim3(kBlk), 0, s, b, p, z.C);
+}
+
+// ---------------------------------------------------------------------------
+// A5: canonical order (counting sort by the lower id, then by key inside
+// each id), per-particle incidence lists
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t n_contacts(const DevBuffers& b, int64_t cap)
+{
+    uint32_t n = b.cnt->n_raw;
+    return n < (uint64_t)cap ? n : (uint32_t)cap;
+}
+
+__global__ void k_id_count(DevBuffers b, int64_t cap)
+{
+    uint32_t nc = n_contacts(b, cap);
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
+        atomicAdd(&b.id_count[(uint32_t)(b.rkey[c] >> 32)], 1u);
+}
+
+__global__ void k_id_scatter(DevBuffers b, int64_t cap)
+{
+    uint32_t nc = n_contacts(b, cap);
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+        unsigned long long k = b.rkey[c];
+        uint32_t a = (uint32_t)(k >> 32);
+        uint32_t pos = b.id_start[a] + atomicAdd(&b.id_fill[a], 1u);
+        b.ckey[pos] = k;
+        b.cpair[pos] = b.rpair[c];
+    }
+}
+
+__global__ void k_id_sort(DevBuffers b, int64_t nid)
+{
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nid) return;
+    uint32_t beg = b.id_start[a], end = b.id_start[a + 1];
+    for (uint32_t u = beg + 1; u < end; ++u) {
+        unsigned long long k = b.ckey[u];
+        int2 pr = b.cpair[u];
+        uint32_t t = u;
+        while (t > beg && b.ckey[t - 1] > k) {
+            b.ckey[t] = b.ckey[t - 1];
+            b.cpair[t] = b.cpair[t - 1];
+            --t;
+        }
+        b.ckey[t] = k;
+        b.cpair[t] = pr;
+    }
+}
+
+__global__ void k_inc_count(DevBuffers b, int64_t cap)
+{
+    uint32_t nc = n_contacts(b, cap);
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+        int2 pr = b.cpair[c];
+        atomicAdd(&b.inc_count[pr.y], 1u);
+        if (pr.x >= 0) atomicAdd(&b.inc_count[pr.x], 1u);
+    }
+}
+
+__global__ void k_inc_fill(DevBuffers b, int64_t cap)
+{
+    uint32_t nc = n_contacts(b, cap);
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+        int2 pr = b.cpair[c];
+        b.inc[b.inc_start[pr.y] + atomicAdd(&b.inc_fill[pr.y], 1u)] = c;
+        if (pr.x >= 0) b.inc[b.inc_start[pr.x] + atomicAdd(&b.inc_fill[pr.x], 1u)] = c;
+    }
+}
+
+__global__ void k_inc_sort(DevBuffers b, int n)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    uint32_t beg = b.inc_start[s], end = b.inc_start[s + 1];
+    for (uint32_t u = beg + 1; u < end; ++u) {
+        uint32_t v = b.inc[u];
+        uint32_t t = u;
+        while (t > beg && b.inc[t - 1] > v) {
+            b.inc[t] = b.inc[t - 1];
+            --t;
+        }
+        b.inc[t] = v;
+    }
+}
+
+void launch_canonical(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+{
+    unsigned gc = (unsigned)std::min<int64_t>(cdiv(z.C, kBlk), 2048);
+    launch_fill_u32(b.id_count, 0u, z.NID, s);
+    launch_fill_u32(b.id_fill, 0u, z.NID, s);
+    hipLaunchKernelGGL(k_id_count, dim3(gc), dim3(kBlk), 0, s, b, z.C);
+    launch_scan_u32(b.id_count, b.id_start, z.NID, b.scan_tmp, s);
+    hipLaunchKernelGGL(k_id_scatter, dim3(gc), dim3(kBlk), 0, s, b, z.C);
+    hipLaunchKernelGGL(k_id_sort, dim3((unsigned)cdiv(z.NID, kBlk)), dim3(kBlk), 0, s, b, z.NID);
+    int n = std::max(p.n_particles, 1);
+    launch_fill_u32(b.inc_count, 0u, n, s);
+    launch_fill_u32(b.inc_fill, 0u, n, s);
+    hipLaunchKernelGGL(k_inc_count, dim3(gc), dim3(kBlk), 0, s, b, z.C);
+    launch_scan_u32(b.inc_count, b.inc_start, n, b.scan_tmp, s);
+    hipLaunchKernelGGL(k_inc_fill, dim3(gc), dim3(kBlk), 0, s, b, z.C);
+    hipLaunchKernelGGL(k_inc_sort, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, s, b, n);
+}
+
+// ---------------------------------------------------------------------------
+// A7: colouring.  Each contact takes the least colour unused by its
+// conflicting contacts of higher (splitmix64(key), key) priority, once all of
+// those are coloured: the unique Jones-Plassmann result.  Resident grid, each
+// thread re-visits its uncoloured contacts until none is left (bounded).
+// ---------------------------------------------------------------------------
+__device__ inline int ld_colour(const int* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kBlk) void k_colour(DevBuffers b, int64_t cap, int max_pass)
+{
+    uint32_t nc = n_contacts(b, cap);
+    uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
+    int local_max = 0;
+    bool ovf = false, left = true;
+    int pass = 0;
+    for (; pass < max_pass; ++pass) {
+        left = false;
+        for (uint32_t c = first; c < nc; c += stride) {
+            if (ld_colour(&b.colour[c]) >= 0) continue;
+            unsigned long long key = b.ckey[c];
+            unsigned long long h = splitmix64(key);
+            int2 pr = b.cpair[c];
+            unsigned long long used = 0;
+            bool ready = true;
+            int parts[2] = {pr.y, pr.x};
+            for (int q = 0; q < 2 && ready; ++q) {
+                int s = parts[q];
+                if (s < 0) continue;
+                uint32_t beg = b.inc_start[s], end = b.inc_start[s + 1];
+                for (uint32_t t = beg; t < end; ++t) {
+                    uint32_t e = b.inc[t];
+                    if (e == c) continue;
+                    int ce = ld_colour(&b.colour[e]);
+                    if (ce < 0) {
+                        unsigned long long ke = b.ckey[e];
+                        unsigned long long he = splitmix64(ke);
+                        if (he > h || (he == h && ke > key)) { ready = false; break; }
+                    } else {
+                        used |= 1ull << ce;
+                    }
+                }
+            }
+            if (!ready) { left = true; continue; }
+            int col = __builtin_ctzll(~used);
+            if (used == ~0ull) { col = kMaxColours - 1; ovf = true; }
+            __hip_atomic_store(&b.colour[c], col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            local_max = max(local_max, col + 1);
+        }
+        if (!__syncthreads_or(left)) break;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    if (local_max) atomicMax(&b.cnt->n_colours, (uint32_t)local_max);
+    if (ovf) atomicOr(&b.cnt->overflow, kOvfColours);
+    if (left) atomicOr(&b.cnt->overflow, kFailColouring);
+}
+
+// stable bucketing of the canonical list by colour
+__global__ void k_col_hist(DevBuffers b, int64_t cap, int64_t NB)
+{
+    __shared__ uint32_t h[kMaxColours];
+    uint32_t nc = n_contacts(b, cap);
+    if (threadIdx.x < kMaxColours) h[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nc) {
+        int col = b.colour[c];
+        if (col >= 0 && col < kMaxColours) atomicAdd(&h[col], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxColours) b.col_hist[(int64_t)threadIdx.x * NB + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_col_scatter(DevBuffers b, int64_t cap, int64_t NB)
+{
+    __shared__ int col[kBlk];
+    uint32_t nc = n_contacts(b, cap);
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    int my = c < nc ? b.colour[c] : -1;
+    col[threadIdx.x] = my;
+    __syncthreads();
+    if (c >= nc) return;
+    if (my < 0 || my >= kMaxColours) {  // failed colouring: the step is abandoned
+        b.cpos[c] = c;
+        return;
+    }
+    uint32_t rank = 0;
+    for (int t = 0; t < (int)threadIdx.x; ++t) rank += col[t] == my;
+    b.cpos[c] = b.col_start[(int64_t)my * NB + blockIdx.x] + rank;
+}
+
+void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+{
+    launch_fill_u32((uint32_t*)b.colour, 0xFFFFFFFFu, z.C, s);
+    hipLaunchKernelGGL(k_colour, dim3(z.col_grid), dim3(kBlk), 0, s, b, z.C, 100000);
+    hipLaunchKernelGGL(k_col_hist, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB);
+    launch_scan_u32(b.col_hist, b.col_start, (int64_t)kMaxColours * z.NB, b.scan_tmp, s);
+    hipLaunchKernelGGL(k_col_scatter, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB);
+    (void)p;
+}
+
+// ---------------------------------------------------------------------------
+// A6 + A8: contact rows in colour order, with lambda^0 (cold or previous-step
+// impulses matched by key, re-projected onto the tangent plane and onto the
+// feasible set).  Geometry in FP64, stored in FP32.
+// ---------------------------------------------------------------------------
+__global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
+{
+    uint32_t nc = n_contacts(b, cap);
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    if (b.cnt->overflow) return;
+    unsigned long long key = b.ckey[c];
+    int2 pr = b.cpair[c];
+    int ia = pr.x, ib = pr.y;
+    float4 x2 = b.xr[ib];
+    float4 v2 = b.vm[ib];
+    double X2[3] = {x2.x, x2.y, x2.z};
+    double r2 = x2.w;
+    double n[3], delta, l1, l2, dstar, dref, rmin, im1 = 0.0, iI1 = 0.0, un;
+    double vk[3] = {0.0, 0.0, 0.0};
+    if (ia >= 0) {
+        float4 x1 = b.xr[ia];
+        float4 v1 = b.vm[ia];
+        double r1 = x1.w;
+        double e[3] = {X2[0] - x1.x, X2[1] - x1.y, X2[2] - x1.z};
+        double d = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        if (d > 0.0) { n[0] = e[0] / d; n[1] = e[1] / d; n[2] = e[2] / d; }
+        else { n[0] = 0.0; n[1] = 0.0; n[2] = 1.0; }
+        delta = (r1 + r2) - d;
+        l1 = r1 - 0.5 * delta;
+        l2 = r2 - 0.5 * delta;
+        dstar = 1.0 / (1.0 / (2.0 * r1) + 1.0 / (2.0 * r2));
+        dref = r1 + r2;
+        rmin = fmin(r1, r2);
+        im1 = v1.w;
+        iI1 = b.wi[ia].w;
+        un = n[0] * ((double)v2.x - v1.x) + n[1] * ((double)v2.y - v1.y) + n[2] * ((double)v2.z - v1.z);
+    } else {
+        int sg = -1 - ia;
+        const ShapeDev& S = b.shapes[sg];
+        ShapeHit hit;
+        shape_touch(S, b.hf_pool, X2[0], X2[1], X2[2], r2, p.kappa_c, &hit);
+        delta = hit.delta;
+        n[0] = hit.n[0]; n[1] = hit.n[1]; n[2] = hit.n[2];
+        l1 = 0.0;
+        l2 = r2 - 0.5 * delta;
+        dstar = 2.0 * r2;
+        dref = 2.0 * r2;
+        rmin = r2;
+        const BodyDev& B = b.bodies[S.body];
+        double pc[3] = {X2[0] - l2 * n[0], X2[1] - l2 * n[1], X2[2] - l2 * n[2]};
+        double arm[3] = {pc[0] - B.pos[0], pc[1] - B.pos[1], pc[2] - B.pos[2]};
+        vk[0] = B.linvel[0] + (B.angvel[1] * arm[2] - B.angvel[2] * arm[1]);
+        vk[1] = B.linvel[1] + (B.angvel[2] * arm[0] - B.angvel[0] * arm[2]);
+        vk[2] = B.linvel[2] + (B.angvel[0] * arm[1] - B.angvel[1] * arm[0]);
+        un = n[0] * ((double)v2.x - vk[0]) + n[1] * ((double)v2.y - vk[1]) + n[2] * ((double)v2.z - vk[2]);
+    }
+    // Hertz stiffness and the row scaled to unit Jacobian
+    double kn = p.Estar * sqrt(dstar) / 3.0;
+    double de = fmax(delta, p.kappa_min * dref);
+    double eps = 4.0 / (5.0 * kn * sqrt(de));
+    double Sig = p.sig_coef * eps;
+    double q = p.a_coef * (0.8 * delta) + p.b_coef * un;
+    double im2 = v2.w, iI2 = b.wi[ib].w;
+    double Wn = im1 + im2;
+    double Wt = im1 + im2 + l1 * l1 * iI1 + l2 * l2 * iI2;
+    double Dn = Wn + Sig;
+    double Dt = Wt + (double)p.gamma_dt;
+    double lo = -p.lo_coef * rmin * rmin;
+
+    // warm start: previous-step impulses of the same key
+    float4 L = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (use_prev) {
+        uint32_t a = (uint32_t)(key >> 32);
+        uint32_t beg = b.pid_start[a], end = b.pid_start[a + 1];
+        for (uint32_t t = beg; t < end; ++t)
+            if (b.pkeyc[t] == key) { L = b.plam[t]; break; }
+    }
+    float nf[3] = {(float)n[0], (float)n[1], (float)n[2]};
+    {
+        float ln = fmaxf(L.x, (float)lo);
+        float tn = nf[0] * L.y + nf[1] * L.z + nf[2] * L.w;
+        float t0 = L.y - tn * nf[0], t1 = L.z - tn * nf[1], t2 = L.w - tn * nf[2];
+        float lim = p.mu * fabsf(ln);
+        float m2 = t0 * t0 + t1 * t1 + t2 * t2;
+        if (m2 > lim * lim) {
+            float sc = m2 > 0.f ? lim * rsqrtf(m2) : 0.f;
+            t0 *= sc; t1 *= sc; t2 *= sc;
+        }
+        L = make_float4(ln, t0, t1, t2);
+    }
+    uint32_t pos = b.cpos[c];
+    b.r0[pos] = make_float4(nf[0], nf[1], nf[2], (float)l1);
+    b.r1[pos] = make_float4((float)l2, (float)(1.0 / Dn), (float)(1.0 / Dt), (float)Sig);
+    b.r2[pos] = make_float4((float)q, (float)lo, __int_as_float(ia), __int_as_float(ib));
+    b.rk[pos] = make_float4((float)vk[0], (float)vk[1], (float)vk[2], (float)Dn);
+    b.lam[pos] = L;
+    b.lam0[pos] = L;
+}
+
+void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rows, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, p, z.C,
+                       have_prev && p.warm != TR_WARM_COLD ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// v* = v + dt g + M^-1 G^T lambda^0, gathered per particle over its sorted
+// incidence list (fixed order)
+// ---------------------------------------------------------------------------
+__global__ void k_warm_apply(DevBuffers b, StepParams p)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n_particles) return;
+    if (b.cnt->overflow) return;
+    float4 v = b.vm[s], w = b.wi[s];
+    v.x += p.dt * p.g[0];
+    v.y += p.dt * p.g[1];
+    v.z += p.dt * p.g[2];
+    uint32_t beg = b.inc_start[s], end = b.inc_start[s + 1];
+    for (uint32_t t = beg; t < end; ++t) {
+        uint32_t pos = b.cpos[b.inc[t]];
+        float4 L = b.lam[pos];
+        if (L.x == 0.f && L.y == 0.f && L.z == 0.f && L.w == 0.f) continue;
+        float4 a = b.r0[pos];
+        float4 q = b.r2[pos];
+        float J0 = L.x * a.x + L.y, J1 = L.x * a.y + L.z, J2 = L.x * a.z + L.w;
+        float sgn, lev;
+        if (__float_as_int(q.w) == s) { sgn = 1.f; lev = -b.r1[pos].x; }
+        else { sgn = -1.f; lev = a.w; }
+        // arm = lev n; dw = sgn * iI (arm x J)
+        float c0 = lev * (a.y * J2 - a.z * J1), c1 = lev * (a.z * J0 - a.x * J2), c2 = lev * (a.x * J1 - a.y * J0);
+        v.x += sgn * v.w * J0; v.y += sgn * v.w * J1; v.z += sgn * v.w * J2;
+        w.x += sgn * w.w * c0; w.y += sgn * w.w * c1; w.z += sgn * w.w * c2;
+    }
+    b.vm[s] = v;
+    b.wi[s] = w;
+}
+
+void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+{
+    if (p.n_particles <= 0) return;
+    hipLaunchKernelGGL(k_warm_apply, dim3((unsigned)cdiv(p.n_particles, kBlk)), dim3(kBlk), 0, s, b, p);
+    (void)z;
+}
+
+// ---------------------------------------------------------------------------
+// A9: persistent projected Gauss-Seidel.  Sweeps x colours; inside a colour
+// no two contacts share a dynamic particle, so every contact updates its two
+// bodies without atomics.  A grid barrier separates colours.  The residual
+// R_k = ||d lambda||_D / ||lambda||_D of each sweep is reduced per block in
+// fixed order and combined identically by every block, which then all take
+// the same stopping decision.
+// ---------------------------------------------------------------------------
+__device__ inline bool grid_barrier(Counters* cnt, unsigned nblocks, unsigned& gen, int& sh_ok)
+{
+    bool ok = true;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        unsigned g = gen;
+        unsigned arrived = __hip_atomic_fetch_add(&cnt->barrier_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&cnt->barrier_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&cnt->barrier_gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long spins = 0;
+            while (__hip_atomic_load(&cnt->barrier_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(1);
+                if ((++spins & 1023) == 0 &&
+                    (__hip_atomic_load(&cnt->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFailBarrier)) {
+                    ok = false;
+                    break;
+                }
+                if (spins > (1l << 22)) { ok = false; break; }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        gen = g + 1;
+        if (!ok) atomicOr(&cnt->overflow, kFailBarrier);
+        sh_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    return sh_ok != 0;
+}
+
+__device__ inline void pgs_contact(const DevBuffers& b, uint32_t c, float mu, float gdt, float& num, float& den)
+{
+    float4 a = b.r0[c];
+    float4 r1 = b.r1[c];
+    float4 q = b.r2[c];
+    float4 L = b.lam[c];
+    int ia = __float_as_int(q.z), ib = __float_as_int(q.w);
+    float4 vb = b.vm[ib], wb = b.wi[ib];
+    float4 va, wa;
+    float3 vk;
+    bool pair = ia >= 0;
+    if (pair) {
+        va = b.vm[ia];
+        wa = b.wi[ia];
+    } else {
+        float4 k4 = b.rk[c];
+        vk = make_float3(k4.x, k4.y, k4.z);
+        va = make_float4(vk.x, vk.y, vk.z, 0.f);
+        wa = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float nx = a.x, ny = a.y, nz = a.z, l1 = a.w;
+    float l2 = r1.x, iDn = r1.y, iDt = r1.z, Sig = r1.w;
+    // normal row
+    float un = nx * (vb.x - va.x) + ny * (vb.y - va.y) + nz * (vb.z - va.z);
+    float ln = fmaxf(q.y, L.x - (un + Sig * L.x - q.x) * iDn);
+    float dn = ln - L.x;
+    vb.x += dn * nx * vb.w; vb.y += dn * ny * vb.w; vb.z += dn * nz * vb.w;
+    va.x -= dn * nx * va.w; va.y -= dn * ny * va.w; va.z -= dn * nz * va.w;
+    // tangential disk row: u = (vb - va) - (l2 wb + l1 wa) x n
+    float sx = l2 * wb.x + l1 * wa.x, sy = l2 * wb.y + l1 * wa.y, sz = l2 * wb.z + l1 * wa.z;
+    float ux = (vb.x - va.x) - (sy * nz - sz * ny);
+    float uy = (vb.y - va.y) - (sz * nx - sx * nz);
+    float uz = (vb.z - va.z) - (sx * ny - sy * nx);
+    float udn = ux * nx + uy * ny + uz * nz;
+    ux -= udn * nx; uy -= udn * ny; uz -= udn * nz;
+    float tx = L.y - (ux + gdt * L.y) * iDt;
+    float ty = L.z - (uy + gdt * L.z) * iDt;
+    float tz = L.w - (uz + gdt * L.w) * iDt;
+    float lim = mu * fabsf(ln);
+    float m2 = tx * tx + ty * ty + tz * tz;
+    if (m2 > lim * lim) {
+        float sc = m2 > 0.f ? lim * rsqrtf(m2) : 0.f;
+        tx *= sc; ty *= sc; tz *= sc;
+    }
+    float dx = tx - L.y, dy = ty - L.z, dz = tz - L.w;
+    // impulse d at the contact point: +d on body 2 (arm -l2 n), -d on body 1 (arm +l1 n)
+    float cx = ny * dz - nz * dy, cy = nz * dx - nx * dz, cz = nx * dy - ny * dx;  // n x d
+    vb.x += dx * vb.w; vb.y += dy * vb.w; vb.z += dz * vb.w;
+    wb.x -= l2 * wb.w * cx; wb.y -= l2 * wb.w * cy; wb.z -= l2 * wb.w * cz;
+    b.vm[ib] = vb;
+    b.wi[ib] = wb;
+    if (pair) {
+        va.x -= dx * va.w; va.y -= dy * va.w; va.z -= dz * va.w;
+        wa.x -= l1 * wa.w * cx; wa.y -= l1 * wa.w * cy; wa.z -= l1 * wa.w * cz;
+        b.vm[ia] = va;
+        b.wi[ia] = wa;
+    }
+    b.lam[c] = make_float4(ln, tx, ty, tz);
+    float Dn = 1.0f / iDn, Dt = 1.0f / iDt;
+    num += Dn * dn * dn + Dt * (dx * dx + dy * dy + dz * dz);
+    den += Dn * ln * ln + Dt * (tx * tx + ty * ty + tz * tz);
+}
+
+__global__ __launch_bounds__(kBlk) void k_pgs(DevBuffers b, StepParams p, int64_t cap, int64_t NB)
+{
+    __shared__ double red[2][kBlk / 64];
+    __shared__ int stop_flag;
+    __shared__ int bar_ok;
+    if (b.cnt->overflow) return;  // uniform: written by earlier kernels only
+    uint32_t ncol = b.cnt->n_colours;
+    unsigned G = gridDim.x;
+    unsigned gen = 0;
+    int sweeps = 0;
+    double Rk = 0.0, R1 = 0.0;
+    for (int k = 0; k < p.max_sweeps; ++k) {
+        float num = 0.f, den = 0.f;
+        for (uint32_t col = 0; col < ncol; ++col) {
+            uint32_t beg = b.col_start[(int64_t)col * NB], end = b.col_start[(int64_t)(col + 1) * NB];
+            uint32_t len = end - beg;
+            uint32_t lo = beg + (uint32_t)(((uint64_t)len * blockIdx.x) / G);
+            uint32_t hi = beg + (uint32_t)(((uint64_t)len * (blockIdx.x + 1)) / G);
+            for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) pgs_contact(b, c, p.mu, p.gamma_dt, num, den);
+            if (col + 1 == ncol) {
+                // block partials of this sweep, before the last barrier
+                double dnum = num, dden = den;
+                for (int o = 32; o > 0; o >>= 1) {
+                    dnum += __shfl_down(dnum, o, 64);
+                    dden += __shfl_down(dden, o, 64);
+                }
+                if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = dnum; red[1][threadIdx.x >> 6] = dden; }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double sn = 0.0, sd = 0.0;
+                    for (int w = 0; w < kBlk / 64; ++w) { sn += red[0][w]; sd += red[1][w]; }
+                    double* part = b.block_part + (size_t)(k & 1) * 2 * G;
+                    part[2 * blockIdx.x] = sn;
+                    part[2 * blockIdx.x + 1] = sd;
+                }
+            }
+            if (!grid_barrier(b.cnt, G, gen, bar_ok)) return;  // every block leaves
+        }
+        if (ncol == 0) {
+            Rk = 0.0;
+        } else {
+            // every block reduces all block partials in the same fixed order
+            const double* part = b.block_part + (size_t)(k & 1) * 2 * G;
+            double sn = 0.0, sd = 0.0;
+            for (unsigned t = threadIdx.x; t < G; t += blockDim.x) { sn += part[2 * t]; sd += part[2 * t + 1]; }
+            for (int o = 32; o > 0; o >>= 1) {
+                sn += __shfl_down(sn, o, 64);
+                sd += __shfl_down(sd, o, 64);
+            }
+            __syncthreads();
+            if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = sn; red[1][threadIdx.x >> 6] = sd; }
+            __syncthreads();
+            sn = 0.0; sd = 0.0;
+            for (int w = 0; w < kBlk / 64; ++w) { sn += red[0][w]; sd += red[1][w]; }
+            Rk = sd > 0.0 ? sqrt(sn) / sqrt(sd) : (sn > 0.0 ? 1.0 : 0.0);
+        }
+        if (k == 0) R1 = Rk;
+        sweeps = k + 1;
+        if (threadIdx.x == 0) stop_flag = (p.tol > 0.f && Rk <= (double)p.tol) ? 1 : 0;
+        __syncthreads();
+        if (stop_flag) break;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        b.cnt->sweeps = (uint32_t)sweeps;
+        b.cnt->resid = Rk;
+        b.cnt->resid_first = R1;
+    }
+}
+
+int pgs_resident_blocks(int block)
+{
+    int dev = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t pr;
+    (void)hipGetDeviceProperties(&pr, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pgs, block, 0);
+    return std::max(1, per_cu) * pr.multiProcessorCount;
+}
+
+int colour_resident_blocks()
+{
+    int dev = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t pr;
+    (void)hipGetDeviceProperties(&pr, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_colour, kBlk, 0);
+    return std::max(1, per_cu) * pr.multiProcessorCount;
+}
+
+void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pgs, dim3(z.pgs_grid), dim3(kBlk), 0, s, b, p, z.C, z.NB);
+}
+
+// ---------------------------------------------------------------------------
+// finish: canonical impulses, body forces (A11), integration (A10), poses,
+// zone aggregates (A12), env stats
+// ---------------------------------------------------------------------------
+__global__ void k_lam_back(DevBuffers b, int64_t cap)
+{
+    uint32_t nc = n_contacts(b, cap);
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    b.lamc[c] = b.cnt->overflow ? make_float4(0.f, 0.f, 0.f, 0.f) : b.lam[b.cpos[c]];
+}
+
+__device__ inline double block_sum_d(double v, double* sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    return s;
+}
+
+constexpr int kRedBlk = 128;
+
+// partial force/torque of (body, chunk) over the env's canonical contacts
+__global__ __launch_bounds__(kRedBlk) void k_force_part(DevBuffers b, StepParams p, int64_t cap)
+{
+    __shared__ double sh[kRedBlk / 64];
+    int body = blockIdx.x / kForceChunks, ch = blockIdx.x % kForceChunks;
+    const BodyDev& B = b.bodies[body];
+    const EnvDev& E = b.envs[B.env];
+    uint32_t nc = n_contacts(b, cap);
+    uint32_t beg = b.id_start[E.id_base], end = b.id_start[E.id_base + p.id_cap];
+    if (end > nc) end = nc;
+    if (beg > end) beg = end;
+    uint32_t len = end - beg;
+    uint32_t lo = beg + (uint32_t)(((uint64_t)len * ch) / kForceChunks);
+    uint32_t hi = beg + (uint32_t)(((uint64_t)len * (ch + 1)) / kForceChunks);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (b.cnt->overflow) hi = lo;
+    for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
+        int2 pr = b.cpair[c];
+        if (pr.x >= 0) continue;
+        int sg = -1 - pr.x;
+        if (b.shapes[sg].body != body) continue;
+        uint32_t pos = b.cpos[c];
+        float4 L = b.lam[pos];
+        float4 a = b.r0[pos];
+        double l2 = b.r1[pos].x;
+        float4 x2 = b.xr[pr.y];
+        double f[3] = {-((double)L.x * a.x + L.y) / p.dt, -((double)L.x * a.y + L.z) / p.dt,
+                       -((double)L.x * a.z + L.w) / p.dt};
+        double arm[3] = {(double)x2.x - l2 * a.x - B.pos[0], (double)x2.y - l2 * a.y - B.pos[1],
+                         (double)x2.z - l2 * a.z - B.pos[2]};
+        acc[0] += f[0]; acc[1] += f[1]; acc[2] += f[2];
+        acc[3] += arm[1] * f[2] - arm[2] * f[1];
+        acc[4] += arm[2] * f[0] - arm[0] * f[2];
+        acc[5] += arm[0] * f[1] - arm[1] * f[0];
+    }
+    for (int k = 0; k < 6; ++k) {
+        double s = block_sum_d(acc[k], sh);
+        if (threadIdx.x == 0) b.force_part[((size_t)body * kForceChunks + ch) * 6 + k] = s;
+    }
+}
+
+__global__ void k_force_final(DevBuffers b, StepParams p)
+{
+    int body = blockIdx.x * blockDim.x + threadIdx.x;
+    if (body >= p.n_bodies) return;
+    for (int k = 0; k < 6; ++k) {
+        double s = 0.0;
+        for (int ch = 0; ch < kForceChunks; ++ch) s += b.force_part[((size_t)body * kForceChunks + ch) * 6 + k];
+        b.body_ft[body * 6 + k] = s;
+    }
+}
+
+__global__ void k_integrate(DevBuffers b, StepParams p)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n_particles) return;
+    if (b.cnt->overflow) return;
+    float4 x = b.xr[s];
+    float4 v = b.vm[s];
+    x.x += p.dt * v.x;
+    x.y += p.dt * v.y;
+    x.z += p.dt * v.z;
+    b.xr[s] = x;
+}
+
+// poses advance with their constant velocities; world zone planes of the new pose
+__global__ void k_bodies_end(DevBuffers b, StepParams p)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p.n_bodies) return;
+    if (b.cnt->overflow) return;
+    BodyDev& B = b.bodies[t];
+    double dt = p.dt;
+    for (int k = 0; k < 3; ++k) B.pos[k] += dt * B.linvel[k];
+    double q0 = B.quat[0], q1 = B.quat[1], q2 = B.quat[2], q3 = B.quat[3];
+    double wx = B.angvel[0], wy = B.angvel[1], wz = B.angvel[2];
+    double h = 0.5 * dt;
+    double n0 = q0 + h * (-wx * q1 - wy * q2 - wz * q3);
+    double n1 = q1 + h * (wx * q0 + wy * q3 - wz * q2);
+    double n2 = q2 + h * (-wx * q3 + wy * q0 + wz * q1);
+    double n3 = q3 + h * (wx * q2 - wy * q1 + wz * q0);
+    double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2 + n3 * n3);
+    B.quat[0] = n0 / nn; B.quat[1] = n1 / nn; B.quat[2] = n2 / nn; B.quat[3] = n3 / nn;
+    double R[9];
+    quat_to_R(B.quat, R);
+    for (int k = 0; k < B.nplanes; ++k) {
+        double nw[3];
+        for (int r = 0; r < 3; ++r)
+            nw[r] = (R[r * 3 + 0] * B.planes[k][0] + R[r * 3 + 1] * B.planes[k][1]) + R[r * 3 + 2] * B.planes[k][2];
+        for (int r = 0; r < 3; ++r) B.wplanes[k][r] = nw[r];
+        B.wplanes[k][3] = B.planes[k][3] + (nw[0] * B.pos[0] + nw[1] * B.pos[1] + nw[2] * B.pos[2]);
+    }
+}
+
+// zone moments of one chunk of an env's particles (sorted slots), per zone
+__global__ __launch_bounds__(kRedBlk) void k_zone_part(DevBuffers b, StepParams p)
+{
+    __shared__ double sh[kRedBlk / 64];
+    int4 ck = b.zone_chunks[blockIdx.x];   // env, begin, end, partial base
+    const EnvDev& E = b.envs[ck.x];
+    for (int z = 0; z < E.zone_count; ++z) {
+        const BodyDev& B = b.bodies[E.zone_body[z]];
+        double acc[kZoneMoments];
+        for (int k = 0; k < kZoneMoments; ++k) acc[k] = 0.0;
+        for (int s = ck.y + threadIdx.x; s < ck.z; s += blockDim.x) {
+            float4 xf = b.xr[s];
+            double x[3] = {xf.x, xf.y, xf.z};
+            // first zone (body order) containing x wins
+            int zone = -1;
+            for (int zz = 0; zz < E.zone_count && zone < 0; ++zz) {
+                const BodyDev& Bz = b.bodies[E.zone_body[zz]];
+                bool in = Bz.nplanes > 0;
+                for (int k = 0; k < Bz.nplanes && in; ++k)
+                    if (Bz.wplanes[k][0] * x[0] + Bz.wplanes[k][1] * x[1] + Bz.wplanes[k][2] * x[2] - Bz.wplanes[k][3] > 0.0)
+                        in = false;
+                if (in) zone = zz;
+            }
+            if (zone != z) continue;
+            double r = xf.w;
+            double m = (double)b.rho[s] * (4.0 / 3.0) * 3.14159265358979323846 * r * r * r;
+            float4 vf = b.vm[s], wf = b.wi[s];
+            double v[3] = {vf.x, vf.y, vf.z};
+            double Is = 0.4 * m * r * r;
+            acc[0] += m;
+            for (int k = 0; k < 3; ++k) { acc[1 + k] += m * x[k]; acc[4 + k] += m * v[k]; }
+            acc[7] += m * x[0] * x[0]; acc[8] += m * x[1] * x[1]; acc[9] += m * x[2] * x[2];
+            acc[10] += m * x[0] * x[1]; acc[11] += m * x[0] * x[2]; acc[12] += m * x[1] * x[2];
+            acc[13] += m * (x[1] * v[2] - x[2] * v[1]);
+            acc[14] += m * (x[2] * v[0] - x[0] * v[2]);
+            acc[15] += m * (x[0] * v[1] - x[1] * v[0]);
+            acc[16] += Is;
+            acc[17] += Is * wf.x; acc[18] += Is * wf.y; acc[19] += Is * wf.z;
+        }
+        (void)B;
+        for (int k = 0; k < kZoneMoments; ++k) {
+            double s = block_sum_d(acc[k], sh);
+            if (threadIdx.x == 0) b.zone_part[((size_t)ck.w + z) * kZoneMoments + k] = s;
+        }
+    }
+}
+
+// per zone: sum the chunk partials in order, then the aggregate body
+__global__ void k_zone_final(DevBuffers b, StepParams p, int n_chunks)
+{
+    int zs = blockIdx.x * blockDim.x + threadIdx.x;
+    if (zs >= p.n_zones) return;
+    // locate env and zone index of this global zone
+    int env = -1, zi = -1;
+    for (int e = 0; e < p.n_envs && env < 0; ++e)
+        for (int z = 0; z < b.envs[e].zone_count; ++z)
+            if (b.envs[e].zone_slot[z] == zs) { env = e; zi = z; }
+    if (env < 0) return;
+    double S[kZoneMoments];
+    for (int k = 0; k < kZoneMoments; ++k) S[k] = 0.0;
+    for (int c = 0; c < n_chunks; ++c) {
+        int4 ck = b.zone_chunks[c];
+        if (ck.x != env) continue;
+        for (int k = 0; k < kZoneMoments; ++k) S[k] += b.zone_part[((size_t)ck.w + zi) * kZoneMoments + k];
+    }
+    for (int k = 0; k < kZoneMoments; ++k) b.zone_mom[(size_t)zs * kZoneMoments + k] = S[k];
+    tr_aggregate A;
+    A.zone = b.bodies[b.envs[env].zone_body[zi]].user_id;
+    A.pad = 0;
+    double M = S[0];
+    A.M = M;
+    A.n_particles = 0;
+    for (int k = 0; k < 3; ++k) { A.x[k] = 0.0; A.v[k] = 0.0; A.w[k] = 0.0; }
+    for (int k = 0; k < 6; ++k) A.I[k] = 0.0;
+    if (M > 0.0) {
+        double x[3] = {S[1] / M, S[2] / M, S[3] / M};
+        double v[3] = {S[4] / M, S[5] / M, S[6] / M};
+        // second moments about x_A
+        double Cxx = S[7] - M * x[0] * x[0], Cyy = S[8] - M * x[1] * x[1], Czz = S[9] - M * x[2] * x[2];
+        double Cxy = S[10] - M * x[0] * x[1], Cxz = S[11] - M * x[0] * x[2], Cyz = S[12] - M * x[1] * x[2];
+        double tr = Cxx + Cyy + Czz;
+        double I[3][3] = {{S[16] + tr - Cxx, -Cxy, -Cxz}, {-Cxy, S[16] + tr - Cyy, -Cyz}, {-Cxz, -Cyz, S[16] + tr - Czz}};
+        // angular momentum about x_A: sum m x*v - x_A * sum m v + spins
+        double L[3] = {S[13] - (x[1] * S[6] - x[2] * S[5]) + S[17], S[14] - (x[2] * S[4] - x[0] * S[6]) + S[18],
+                       S[15] - (x[0] * S[5] - x[1] * S[4]) + S[19]};
+        double det = I[0][0] * (I[1][1] * I[2][2] - I[1][2] * I[2][1]) - I[0][1] * (I[1][0] * I[2][2] - I[1][2] * I[2][0]) +
+                     I[0][2] * (I[1][0] * I[2][1] - I[1][1] * I[2][0]);
+        // inverse by cofactors (I symmetric)
+        double inv[3][3];
+        inv[0][0] = (I[1][1] * I[2][2] - I[1][2] * I[2][1]);
+        inv[0][1] = -(I[0][1] * I[2][2] - I[0][2] * I[2][1]);
+        inv[0][2] = (I[0][1] * I[1][2] - I[0][2] * I[1][1]);
+        inv[1][0] = -(I[1][0] * I[2][2] - I[1][2] * I[2][0]);
+        inv[1][1] = (I[0][0] * I[2][2] - I[0][2] * I[2][0]);
+        inv[1][2] = -(I[0][0] * I[1][2] - I[0][2] * I[1][0]);
+        inv[2][0] = (I[1][0] * I[2][1] - I[1][1] * I[2][0]);
+        inv[2][1] = -(I[0][0] * I[2][1] - I[0][1] * I[2][0]);
+        inv[2][2] = (I[0][0] * I[1][1] - I[0][1] * I[1][0]);
+        for (int r = 0; r < 3; ++r) {
+            A.x[r] = x[r];
+            A.v[r] = v[r];
+            A.w[r] = det != 0.0 ? (inv[r][0] * L[0] + inv[r][1] * L[1] + inv[r][2] * L[2]) / det : 0.0;
+        }
+        A.I[0] = I[0][0]; A.I[1] = I[1][1]; A.I[2] = I[2][2];
+        A.I[3] = I[0][1]; A.I[4] = I[0][2]; A.I[5] = I[1][2];
+    }
+    b.aggs[zs] = A;
+}
+
+// zone particle counts (integers, order free)
+__global__ void k_zone_count(DevBuffers b, StepParams p)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n_particles) return;
+    const EnvDev& E = b.envs[env_of(b.pid[s], p.id_cap)];
+    float4 xf = b.xr[s];
+    double x[3] = {xf.x, xf.y, xf.z};
+    for (int zz = 0; zz < E.zone_count; ++zz) {
+        const BodyDev& Bz = b.bodies[E.zone_body[zz]];
+        bool in = Bz.nplanes > 0;
+        for (int k = 0; k < Bz.nplanes && in; ++k)
+            if (Bz.wplanes[k][0] * x[0] + Bz.wplanes[k][1] * x[1] + Bz.wplanes[k][2] * x[2] - Bz.wplanes[k][3] > 0.0)
+                in = false;
+        if (in) {
+            atomicAdd((unsigned long long*)&b.aggs[E.zone_slot[zz]].n_particles, 1ull);
+            break;
+        }
+    }
+}
+
+__global__ void k_env_stats(DevBuffers b, StepParams p)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= p.n_envs) return;
+    int64_t base = (int64_t)e * p.id_cap;
+    b.env_stats[e].contacts = (int64_t)b.id_start[base + p.id_cap] - (int64_t)b.id_start[base];
+}
+
+void launch_finish(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lam_back, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, z.C);
+    if (p.n_bodies > 0) {
+        hipLaunchKernelGGL(k_force_part, dim3(p.n_bodies * kForceChunks), dim3(kRedBlk), 0, s, b, p, z.C);
+        hipLaunchKernelGGL(k_force_final, dim3((unsigned)cdiv(p.n_bodies, kBlk)), dim3(kBlk), 0, s, b, p);
+    }
+    if (p.n_particles > 0)
+        hipLaunchKernelGGL(k_integrate, dim3((unsigned)cdiv(p.n_particles, kBlk)), dim3(kBlk), 0, s, b, p);
+    if (p.n_bodies > 0)
+        hipLaunchKernelGGL(k_bodies_end, dim3((unsigned)cdiv(p.n_bodies, kBlk)), dim3(kBlk), 0, s, b, p);
+    if (p.n_zones > 0 && z.n_zone_chunks > 0) {
+        hipLaunchKernelGGL(k_zone_part, dim3(z.n_zone_chunks), dim3(kRedBlk), 0, s, b, p);
+        hipLaunchKernelGGL(k_zone_final, dim3((unsigned)cdiv(p.n_zones, 64)), dim3(64), 0, s, b, p, z.n_zone_chunks);
+        hipLaunchKernelGGL(k_zone_count, dim3((unsigned)cdiv(std::max(p.n_particles, 1), kBlk)), dim3(kBlk), 0, s,
+                           b, p);
+    }
+    hipLaunchKernelGGL(k_env_stats, dim3((unsigned)cdiv(std::max(p.n_envs, 1), 64)), dim3(64), 0, s, b, p);
+}
+
+// ---------------------------------------------------------------------------
+// host <-> device particle exchange in id order
+// ---------------------------------------------------------------------------
+__global__ void k_gather_by_id(DevBuffers b, int id_base, int n, float4* xo, float4* vo, float4* wo)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int s = b.id2slot[id_base + k];
+    xo[k] = b.xr[s];
+    vo[k] = b.vm[s];
+    wo[k] = b.wi[s];
+}
+
+void launch_gather_by_id(const DevBuffers& b, int id_base, int n, float4* xo, float4* vo, float4* wo, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_by_id, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, s, b, id_base, n, xo, vo, wo);
+}
+
+__global__ void k_scatter_by_id(DevBuffers b, int id_base, int n, const float4* xi, const float4* vi,
+                                const float4* wi, int mask)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int s = b.id2slot[id_base + k];
+    if (mask & 1) { float4 o = b.xr[s]; float4 v = xi[k]; b.xr[s] = make_float4(v.x, v.y, v.z, o.w); }
+    if (mask & 2) { float4 o = b.vm[s]; float4 v = vi[k]; b.vm[s] = make_float4(v.x, v.y, v.z, o.w); }
+    if (mask & 4) { float4 o = b.wi[s]; float4 v = wi[k]; b.wi[s] = make_float4(v.x, v.y, v.z, o.w); }
+}
+
+void launch_scatter_by_id(const DevBuffers& b, int id_base, int n, const float4* xi, const float4* vi,
+                          const float4* wi, int mask, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_scatter_by_id, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, s, b, id_base, n, xi, vi, wi,
+                       mask);
+}
+
+void launch_learned_start(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+{
+    (void)b; (void)p; (void)z; (void)s;
+}
+
+}  // namespace trk

@@ -172,3 +172,25 @@ def excavation_scene(seed=5, n=500000, sweeps=200, dt=1.0 / 60.0):
     bucket = open_bucket(-3.5, top - 0.4, width=1.2, length=1.0, height=0.8, vx=0.8)
     rng_probe["bodies"].append(bucket)
     return rng_probe
+
+
+def jammed_bed(seed=21, nx=40, ny=20, nz=12, r0=0.03, spread=0.002, jitter=0.001, blade=True, sweeps=150,
+               mu=0.7, c=2000.0, dt=1.0 / 60.0):
+    """A dense cubic packing at spacing 2 r0 with radii r0 U(1-spread, 1+spread):
+    about half of the lattice neighbours overlap by up to 2 spread r0 (a jammed
+    bed resting on its floor), with a box blade cutting into its top."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = 2.0 * r0
+    i = np.arange(nx * ny * nz)
+    ix, iy, iz = i % nx, (i // nx) % ny, i // (nx * ny)
+    x = np.stack([(ix - (nx - 1) / 2) * s, (iy - (ny - 1) / 2) * s, r0 + iz * s], axis=1)
+    x += rng.uniform(-1, 1, x.shape) * jitter * r0
+    n = len(x)
+    r = r0 * rng.uniform(1 - spread, 1 + spread, n)
+    lx, ly = nx * s, ny * s
+    top = r0 + (nz - 1) * s + r0
+    bodies = [walls_body(lx + 1e-3, ly + 1e-3, 0.0, True)]
+    if blade:
+        bodies.append(box_blade(-lx / 2 + 0.2, top - 0.1, width=0.6 * ly, height=0.4, vx=1.0))
+    bounds = ((-lx / 2 - 2 * s, -ly / 2 - 2 * s, -2 * s), (lx / 2 + 2 * s, ly / 2 + 2 * s, top + 0.6))
+    return _spec(x, r, bodies, material(mu, c), dt, sweeps, bounds, r0)

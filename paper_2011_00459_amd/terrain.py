@@ -1,0 +1,325 @@
+"""ctypes binding of libterrain.so (include/terrain.h): argument marshalling only.
+
+Every step of the particle system runs in the library's HIP kernels; this
+module converts numpy arrays and plain dicts to the C structs, optionally
+hands the library PyTorch's caching allocator and current stream, and turns
+error codes into exceptions.  It raises at import when the built library is
+missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libterrain.so")
+
+TR_OK, TR_E_INVAL, TR_E_NOMEM, TR_E_DEVICE, TR_E_STATE, TR_E_CAPACITY, TR_E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
+WARM = {"cold": 0, "prev": 1, "learned": 2}
+SHAPE = {"plane": 0, "box": 1, "hfield": 2}
+MLP_PARAMS = 64 * 12 + 64 + 64 * 64 + 64 + 3 * 64 + 3 + 12
+EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodies", "step",
+           "get_contact_forces", "get_aggregates", "get_last_error", "get_contacts", "get_particles",
+           "set_particles", "set_mlp_weights", "get_phase_times")
+
+
+class TerrainError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"terrain error {code}: {msg}")
+        self.code = code
+
+
+class tr_material(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("rho", "mu_t", "mu_r", "c_p", "E", "nu", "restitution", "tau_n", "gamma_t", "kappa_c", "kappa_min")]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class tr_scene_desc(C.Structure):
+    _fields_ = [("n_envs", C.c_int32), ("dt", C.c_double), ("gravity", C.c_double * 3),
+                ("max_sweeps", C.c_int32), ("tol", C.c_double), ("warm_start", C.c_int32),
+                ("material", tr_material), ("cap_particles", C.c_int64), ("cap_contacts", C.c_int64),
+                ("env_bounds", C.POINTER(C.c_double)), ("r_ref", C.c_double), ("stream", C.c_void_p),
+                ("alloc_fn", ALLOC_FN), ("free_fn", FREE_FN), ("alloc_ctx", C.c_void_p)]
+
+
+class tr_shape_desc(C.Structure):
+    _fields_ = [("type", C.c_int32), ("normal", C.c_double * 3), ("offset", C.c_double),
+                ("half", C.c_double * 3), ("center", C.c_double * 3), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("origin", C.c_double * 2), ("l0", C.c_double), ("heights", C.POINTER(C.c_float))]
+
+
+class tr_body_desc(C.Structure):
+    _fields_ = [("id", C.c_int32), ("pos", C.c_double * 3), ("quat", C.c_double * 4),
+                ("linvel", C.c_double * 3), ("angvel", C.c_double * 3), ("n_shapes", C.c_int32),
+                ("shapes", C.POINTER(tr_shape_desc)), ("n_halfspaces", C.c_int32),
+                ("planes", (C.c_double * 4) * 8)]
+
+
+class tr_step_stats(C.Structure):
+    _fields_ = [("contacts", C.c_int64), ("pair_contacts", C.c_int64), ("colours", C.c_int32),
+                ("sweeps", C.c_int32), ("residual", C.c_double), ("residual_first", C.c_double),
+                ("fallback_used", C.c_int32), ("overflow", C.c_int32)]
+
+
+class tr_aggregate(C.Structure):
+    _fields_ = [("zone", C.c_int32), ("pad", C.c_int32), ("n_particles", C.c_int64), ("M", C.c_double),
+                ("x", C.c_double * 3), ("v", C.c_double * 3), ("I", C.c_double * 6), ("w", C.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libterrain.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2011_00459_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        dp = C.POINTER(C.c_double)
+        L.create_scene.argtypes = [C.POINTER(tr_scene_desc), C.POINTER(C.c_void_p)]
+        L.destroy_scene.argtypes = [P]
+        L.add_particles.argtypes = [P, C.c_int32, C.c_int64, dp, dp, dp, dp, C.POINTER(C.c_int64)]
+        L.set_kinematic_bodies.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(tr_body_desc)]
+        L.step.argtypes = [P, C.c_int32, C.POINTER(tr_step_stats)]
+        L.get_contact_forces.argtypes = [P, C.c_int32, C.c_int32, dp, dp]
+        L.get_aggregates.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(tr_aggregate), C.POINTER(C.c_int32)]
+        L.get_last_error.argtypes = [P]
+        L.get_last_error.restype = C.c_char_p
+        L.get_contacts.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_uint64), C.POINTER(C.c_float),
+                                   C.POINTER(C.c_int64)]
+        L.get_particles.argtypes = [P, C.c_int32, dp, dp, dp, dp, C.POINTER(C.c_int64)]
+        L.set_particles.argtypes = [P, C.c_int32, dp, dp, dp]
+        L.set_mlp_weights.argtypes = [P, C.POINTER(C.c_float), C.c_int64]
+        L.get_phase_times.argtypes = [P, C.POINTER(C.c_float), C.c_int32]
+        for name in EXPORTS:
+            if name != "get_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _c64(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a.reshape(shape) if shape is not None else a
+
+
+MATERIAL_DEFAULTS = dict(rho=2000.0, mu_t=0.6, mu_r=0.0, c_p=1000.0, E=1e9, nu=0.15, restitution=0.0,
+                         tau_n=0.0, gamma_t=0.0, kappa_c=0.025, kappa_min=1e-4)
+
+
+class _TorchMemory:
+    """Device memory and stream from PyTorch's caching allocator."""
+
+    def __init__(self):
+        import torch  # noqa: F401  (only when the caller asks for it)
+        self.torch = torch
+        self.alloc_cb = ALLOC_FN(self._alloc)
+        self.free_cb = FREE_FN(self._free)
+
+    def _alloc(self, ctx, nbytes, stream):
+        return self.torch.cuda.caching_allocator_alloc(int(nbytes), stream=stream or None)
+
+    def _free(self, ctx, ptr, stream):
+        self.torch.cuda.caching_allocator_delete(ptr)
+
+
+class Scene:
+    """One libterrain scene (n_envs independent environments)."""
+
+    def __init__(self, n_envs=1, dt=1.0 / 60.0, gravity=(0.0, 0.0, -9.81), max_sweeps=100, tol=0.0,
+                 warm_start="cold", material=None, cap_particles=1024, cap_contacts=16384, env_bounds=None,
+                 r_ref=0.0, torch_memory=False, stream=None):
+        L = lib()
+        d = tr_scene_desc()
+        d.n_envs = n_envs
+        d.dt = dt
+        for k in range(3):
+            d.gravity[k] = gravity[k]
+        d.max_sweeps = max_sweeps
+        d.tol = tol
+        d.warm_start = WARM[warm_start] if isinstance(warm_start, str) else int(warm_start)
+        mat = dict(MATERIAL_DEFAULTS)
+        mat.update(material or {})
+        for k, v in mat.items():
+            setattr(d.material, k, v)
+        d.cap_particles = cap_particles
+        d.cap_contacts = cap_contacts
+        self._bounds = np.ascontiguousarray(np.asarray(env_bounds, dtype=np.float64).reshape(n_envs, 6))
+        d.env_bounds = self._bounds.ctypes.data_as(C.POINTER(C.c_double))
+        d.r_ref = r_ref
+        self._mem = None
+        if torch_memory:
+            self._mem = _TorchMemory()
+            d.alloc_fn = self._mem.alloc_cb
+            d.free_fn = self._mem.free_cb
+            d.stream = self._mem.torch.cuda.current_stream().cuda_stream
+        elif stream is not None:
+            d.stream = stream
+        self.n_envs = n_envs
+        self.max_sweeps = max_sweeps
+        h = C.c_void_p()
+        rc = L.create_scene(C.byref(d), C.byref(h))
+        if rc != TR_OK:
+            raise TerrainError(rc, "create_scene failed")
+        self.h = h
+        self._desc = d
+
+    def _check(self, rc, what):
+        if rc != TR_OK:
+            msg = lib().get_last_error(self.h)
+            raise TerrainError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().destroy_scene(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_particles(self, env, pos, radius, vel=None, density=None):
+        pos = _c64(pos, (-1, 3))
+        n = len(pos)
+        radius = _c64(radius, (n,))
+        vel = _c64(vel, (n, 3))
+        density = _c64(density, (n,))
+        first = C.c_int64()
+        self._check(lib().add_particles(self.h, env, n, _dp(pos), _dp(vel), _dp(radius), _dp(density),
+                                        C.byref(first)), "add_particles")
+        return first.value
+
+    def set_kinematic_bodies(self, env, bodies):
+        keep = []
+        arr = (tr_body_desc * max(len(bodies), 1))()
+        for i, b in enumerate(bodies):
+            B = arr[i]
+            B.id = int(b.get("id", i))
+            for k in range(3):
+                B.pos[k] = b["pos"][k]
+                B.linvel[k] = b.get("linvel", (0, 0, 0))[k]
+                B.angvel[k] = b.get("angvel", (0, 0, 0))[k]
+            q = b.get("quat", (1.0, 0.0, 0.0, 0.0))
+            for k in range(4):
+                B.quat[k] = q[k]
+            planes = np.asarray(b.get("zone_planes", np.zeros((0, 4))), dtype=np.float64).reshape(-1, 4)
+            B.n_halfspaces = len(planes)
+            for p in range(len(planes)):
+                for k in range(4):
+                    B.planes[p][k] = planes[p, k]
+            shapes = b.get("shapes", [])
+            sa = (tr_shape_desc * max(len(shapes), 1))()
+            for j, s in enumerate(shapes):
+                S = sa[j]
+                S.type = SHAPE[s["type"]]
+                for k in range(3):
+                    S.normal[k] = s.get("n", (0, 0, 1))[k]
+                    S.half[k] = s.get("half", (0, 0, 0))[k]
+                    S.center[k] = s.get("off", (0, 0, 0))[k]
+                S.offset = s.get("d", 0.0)
+                if s["type"] == "hfield":
+                    h = np.ascontiguousarray(s["h"], dtype=np.float32)
+                    keep.append(h)
+                    S.nx, S.ny = int(s["nx"]), int(s["ny"])
+                    S.origin[0], S.origin[1] = s["ox"], s["oy"]
+                    S.l0 = s["l0"]
+                    S.heights = h.ctypes.data_as(C.POINTER(C.c_float))
+            keep.append(sa)
+            B.n_shapes = len(shapes)
+            B.shapes = C.cast(sa, C.POINTER(tr_shape_desc))
+        self._check(lib().set_kinematic_bodies(self.h, env, len(bodies), arr), "set_kinematic_bodies")
+
+    def step(self, n_steps=1, stats=True):
+        if not stats:
+            self._check(lib().step(self.h, n_steps, None), "step")
+            return None
+        st = (tr_step_stats * self.n_envs)()
+        self._check(lib().step(self.h, n_steps, st), "step")
+        return [dict(contacts=s.contacts, pair_contacts=s.pair_contacts, colours=s.colours, sweeps=s.sweeps,
+                     residual=s.residual, residual_first=s.residual_first, fallback_used=s.fallback_used,
+                     overflow=s.overflow) for s in st]
+
+    def get_contact_forces(self, env, body_id):
+        f = np.zeros(3)
+        t = np.zeros(3)
+        self._check(lib().get_contact_forces(self.h, env, body_id, _dp(f), _dp(t)), "get_contact_forces")
+        return f, t
+
+    def get_aggregates(self, env, cap=8):
+        out = (tr_aggregate * cap)()
+        n = C.c_int32()
+        self._check(lib().get_aggregates(self.h, env, cap, out, C.byref(n)), "get_aggregates")
+        return [dict(zone=a.zone, n_particles=a.n_particles, M=a.M, x=np.array(a.x[:]), v=np.array(a.v[:]),
+                     I=np.array(a.I[:]), w=np.array(a.w[:])) for a in out[: min(n.value, cap)]]
+
+    def get_contacts(self, env, cap=None):
+        n = C.c_int64()
+        self._check(lib().get_contacts(self.h, env, 0, None, None, C.byref(n)), "get_contacts")
+        cap = n.value if cap is None else cap
+        keys = np.zeros(max(cap, 1), dtype=np.uint64)
+        lam = np.zeros((max(cap, 1), 4), dtype=np.float32)
+        self._check(lib().get_contacts(self.h, env, cap, keys.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                       lam.ctypes.data_as(C.POINTER(C.c_float)), C.byref(n)), "get_contacts")
+        m = min(n.value, cap)
+        return keys[:m], lam[:m]
+
+    def get_particles(self, env):
+        n = C.c_int64()
+        self._check(lib().get_particles(self.h, env, None, None, None, None, C.byref(n)), "get_particles")
+        m = n.value
+        x = np.zeros((m, 3)); v = np.zeros((m, 3)); w = np.zeros((m, 3)); r = np.zeros(m)
+        self._check(lib().get_particles(self.h, env, _dp(x), _dp(v), _dp(w), _dp(r), C.byref(n)), "get_particles")
+        return dict(x=x, v=v, w=w, r=r)
+
+    def set_particles(self, env, x=None, v=None, w=None):
+        self._check(lib().set_particles(self.h, env, _dp(_c64(x, (-1, 3))), _dp(_c64(v, (-1, 3))),
+                                        _dp(_c64(w, (-1, 3)))), "set_particles")
+
+    def set_mlp_weights(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        self._check(lib().set_mlp_weights(self.h, flat.ctypes.data_as(C.POINTER(C.c_float)), len(flat)),
+                    "set_mlp_weights")
+
+    def get_phase_times(self):
+        t = (C.c_float * 5)()
+        self._check(lib().get_phase_times(self.h, t, 5), "get_phase_times")
+        return dict(detect=t[0], rows=t[1], pgs=t[2], finish=t[3], step=t[4])
+
+
+def scene_from_specs(specs, cap_particles=None, cap_contacts=None, **kw):
+    """Build a Scene holding one env per spec (see scenegen) and load it."""
+    if isinstance(specs, dict):
+        specs = [specs]
+    s0 = specs[0]
+    nmax = max(len(s["x"]) for s in specs)
+    cap_p = cap_particles or nmax
+    cap_c = cap_contacts or max(16 * nmax, 1024)
+    bounds = np.array([list(s["grid_lo"]) + list(s["grid_hi"]) for s in specs], dtype=np.float64)
+    args = dict(n_envs=len(specs), dt=s0["dt"], gravity=s0["gravity"], max_sweeps=s0["max_sweeps"],
+                tol=s0.get("tol", 0.0), warm_start=s0.get("warm_start", "cold"), material=s0["material"],
+                cap_particles=cap_p, cap_contacts=cap_c, env_bounds=bounds, r_ref=s0.get("r_ref", 0.0))
+    args.update(kw)
+    sc = Scene(**args)
+    for e, s in enumerate(specs):
+        sc.add_particles(e, s["x"], s["r"], vel=s.get("v"), density=s.get("rho"))
+        if s.get("w") is not None and np.any(s["w"]):
+            sc.set_particles(e, w=s["w"])
+        bodies = [dict(b, id=i) for i, b in enumerate(s.get("bodies", []))]  # id = body index
+        sc.set_kinematic_bodies(e, bodies)
+    return sc

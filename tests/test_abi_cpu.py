@@ -1,0 +1,76 @@
+"""The C-ABI library loads on a host without a GPU and exports every entry
+point its header declares; the binding's structs match the header sizes."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "terrain.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("create_scene", "add_particles", "set_kinematic_bodies", "step", "get_contact_forces",
+                     "get_aggregates"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2011_00459_amd import terrain as T
+    lib = T.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in T.EXPORTS
+
+
+def test_struct_layouts_match_header():
+    # sizes computed by the C compiler from the header itself
+    import subprocess
+    import tempfile
+    from paper_2011_00459_amd import terrain as T
+    code = r'''
+#include <stdio.h>
+#include "terrain.h"
+int main(void){printf("%zu %zu %zu %zu %zu %zu\n", sizeof(tr_material), sizeof(tr_scene_desc),
+ sizeof(tr_shape_desc), sizeof(tr_body_desc), sizeof(tr_step_stats), sizeof(tr_aggregate));return 0;}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        srcf = os.path.join(d, "s.c")
+        open(srcf, "w").write(code)
+        exe = os.path.join(d, "s")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), srcf, "-o", exe])
+        sizes = [int(v) for v in subprocess.check_output([exe]).split()]
+    mine = [C.sizeof(T.tr_material), C.sizeof(T.tr_scene_desc), C.sizeof(T.tr_shape_desc),
+            C.sizeof(T.tr_body_desc), C.sizeof(T.tr_step_stats), C.sizeof(T.tr_aggregate)]
+    assert sizes == mine
+
+
+def test_invalid_arguments_rejected_without_device_work():
+    from paper_2011_00459_amd import terrain as T
+    lib = T.lib()
+    h = C.c_void_p()
+    assert lib.create_scene(None, C.byref(h)) == T.TR_E_INVAL
+    d = T.tr_scene_desc()
+    d.n_envs = 0
+    assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_INVAL
+    d.n_envs, d.dt, d.max_sweeps, d.cap_particles, d.cap_contacts = 1, 0.01, 10, 10, 10
+    assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_INVAL  # no env bounds
+    import numpy as np
+    b = np.array([0, 0, 0, 1, 1, 1.0])
+    d.env_bounds = b.ctypes.data_as(C.POINTER(C.c_double))
+    d.material.mu_r = 0.1
+    assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_INVAL  # rolling resistance not modelled
+    d.material.mu_r = 0.0
+    bn = np.array([0, 0, 0, 1, np.nan, 1.0])
+    d.env_bounds = bn.ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_NONFINITE
+    assert lib.destroy_scene(None) == T.TR_OK
+    assert lib.step(None, 1, None) == T.TR_E_INVAL
