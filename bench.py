@@ -143,6 +143,7 @@ def main():
     pgs_launch_ms = pgs_ms / args.steps
     achieved = pgs_bytes / args.steps / (pgs_launch_ms * 1e-3) / 1e9 if pgs_launch_ms > 0 else 0.0
     last = stats[-1][0]
+    phases = {k: float(np.mean([ph[k] for _, ph in stats])) for k in ("detect", "rows", "pgs", "finish", "step")}
     f, _ = sc.get_contact_forces(0, 1)
     aggs = sc.get_aggregates(0)
     line = {
@@ -163,6 +164,7 @@ def main():
                    "contacts_per_step": last["contacts"], "pair_contacts": last["pair_contacts"],
                    "colours": last["colours"], "sweeps": last["sweeps"],
                    "pgs_ms_per_step": pgs_launch_ms,
+                   "phase_ms": phases,
                    "blade_force_x_N": float(f[0])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -90,7 +90,7 @@ typedef struct tr_scene_desc {
     int64_t cap_contacts;    /* contact capacity per environment */
     const double* env_bounds;/* n_envs x 6: lo xyz, hi xyz of each env's cell grid
                                 (particles outside are clamped to the border cells) */
-    double r_ref;            /* nominal radius (learned-start feature scale); 0 = mean radius */
+    double r_ref;            /* nominal radius (learned-start feature scale); <= 0 means 1 m */
     void* stream;            /* hipStream_t, or NULL */
     tr_alloc_fn alloc_fn;    /* NULL: hipMalloc */
     tr_free_fn free_fn;      /* NULL: hipFree */
@@ -220,10 +220,50 @@ int get_particles(tr_scene* s, int32_t env, double* pos, double* vel, double* an
  * unchanged) and clears the warm-start cache. */
 int set_particles(tr_scene* s, int32_t env, const double* pos, const double* vel, const double* angvel);
 
-/* Loads the learned warm-start network (12 -> 64 -> 64 -> 3, SiLU): n floats
- * laid out W1[64][12], b1[64], W2[64][64], b2[64], W3[3][64], b3[3],
- * in_scale[12].  TR_E_INVAL when n differs from that size. */
+/* Loads the learned warm-start network (12 -> 64 -> 64 -> 3, SiLU): n = 5199
+ * floats laid out W1[64][12], b1[64], W2[64][64], b2[64], W3[3][64], b3[3],
+ * in_scale[12] (inputs are multiplied by in_scale).  With warm_start
+ * TR_WARM_LEARNED, each step predicts lambda^0, projects it onto the bounds,
+ * and keeps it only when it is finite and its first-sweep residual does not
+ * exceed the previous-step start's (else PREV, or COLD without a cache;
+ * step_stats.fallback_used).  Without weights LEARNED behaves as PREV.
+ * TR_E_INVAL when n differs from 5199. */
 int set_mlp_weights(tr_scene* s, const float* weights, int64_t n);
+
+/* Precision of the learned start's network inside step: nonzero (default)
+ * runs it in BF16 on the matrix cores (FP32 accumulate), zero in FP32. */
+int set_learned_precision(tr_scene* s, int32_t use_bf16);
+
+/* Training samples of env's last step in canonical contact order: the 12
+ * learned-start inputs (feat, 12 per contact: overlap / mean radius, normal
+ * and tangential relative speed / (g dt), previous-step impulses in the
+ * contact frame / (m_eff g dt), the two depths below the column top / mean
+ * radius, the two radii / r_ref, is_boundary, is_persistent) and the step's
+ * final impulses in the same frame / (m_eff g dt) (label, 3 per contact).
+ * Writes min(cap, count) entries and the count to *n.  Synchronises. */
+int get_learn_samples(tr_scene* s, int32_t env, int64_t cap, float* feat, float* label, int64_t* n);
+
+/* ---- learned-start network on device buffers (training support) ----
+ * weights: the set_mlp_weights layout (W1, b1, W2, b2, W3, b3, in_scale), in
+ * device memory; feat: B x 12, label and out: B x 3, all FP32 device memory,
+ * enqueued on `stream` (hipStream_t or NULL).  Asynchronous. */
+
+/* out = network(feat): use_bf16 selects the MFMA BF16 kernel, else FP32. */
+int mlp_forward(const float* weights, const float* feat, int64_t B, float* out, int32_t use_bf16, void* stream);
+
+/* Floats of device scratch mlp_loss_grad needs for a batch of B. */
+int64_t mlp_grad_scratch_floats(int64_t B);
+
+/* loss = 0.5 mean_b ||network(feat_b) - label_b||^2 (written to *loss, device)
+ * and its gradient w.r.t. W1, b1, W2, b2, W3, b3 (grad: 5187 floats, device),
+ * in FP32.  TR_E_CAPACITY when scratch_floats < mlp_grad_scratch_floats(B). */
+int mlp_loss_grad(const float* weights, const float* feat, const float* label, int64_t B, float* grad, float* loss,
+                  float* scratch, int64_t scratch_floats, void* stream);
+
+/* One Adam step (bias-corrected, step count t >= 1) on the 5187 trainable
+ * weights in place; m and v are the moment buffers (device, 5187 each). */
+int mlp_adam_step(float* weights, const float* grad, float* m, float* v, float lr, float beta1, float beta2, float eps,
+                  int32_t t, void* stream);
 
 /* Device time (ms, from HIP events on the scene's stream) of the last step's
  * phases: [0] detection+ordering, [1] rows+colouring+warm start, [2] PGS,

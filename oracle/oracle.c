@@ -673,25 +673,44 @@ static void contact_frame(const row* R, const double u[3], const double ltp[3], 
     cross3(R->n, t1, t2);
 }
 
-/* Column heights: max(z + r) over the grid column of side h. */
-static void learned_features(const orc_params* P, int64_t n, const double* x, const double* r,
-                             const double* v, const double* w, const inv_mass* M,
-                             const row* rows, int64_t nc, const double* ltprev, double* F,
-                             double (*frames)[6])
+/* Column of a particle for the depth feature: the (x, y) cell of the env's
+ * detection grid, evaluated in FP32 on the FP32 state (cell size
+ * 2 r_max (1 + kappa_c) * 1.001 from the grid origin, clamped to the grid),
+ * so that the GPU, whose grid this is, assigns every particle the same column. */
+static void column_of(const orc_params* P, double rmax, const double* x, int64_t* cx, int64_t* cy)
+{
+    double h = 2.0 * rmax * (1.0 + (P->m.c_p > 0.0 ? P->m.kappa_c : 0.0)) * 1.001;
+    float inv = (float)(1.0 / h);
+    int64_t dims[2];
+    for (int k = 0; k < 2; ++k) {
+        double ext = P->grid_hi[k] - P->grid_lo[k];
+        double dd = ceil(ext / h);
+        dims[k] = dd < 1.0 ? 1 : (int64_t)dd;
+    }
+    float lo0 = (float)P->grid_lo[0], lo1 = (float)P->grid_lo[1];
+    float f0 = ((float)x[0] - lo0) * inv, f1 = ((float)x[1] - lo1) * inv;
+    float g0 = floorf(f0), g1 = floorf(f1);
+    if (!(g0 >= 0.0f)) g0 = 0.0f;
+    if (!(g1 >= 0.0f)) g1 = 0.0f;
+    if (g0 > (float)(dims[0] - 1)) g0 = (float)(dims[0] - 1);
+    if (g1 > (float)(dims[1] - 1)) g1 = (float)(dims[1] - 1);
+    *cx = (int64_t)g0;
+    *cy = (int64_t)g1;
+}
+
+/* depth_i = max over the particle's column of (z + r) minus z_i */
+static void column_depths(const orc_params* P, int64_t n, const double* x, const double* r, double* depth)
 {
     double rmax = 0.0;
     for (int64_t i = 0; i < n; ++i) if (r[i] > rmax) rmax = r[i];
-    double h = 2.0 * rmax * (1.0 + (P->m.c_p > 0.0 ? P->m.kappa_c : 0.0));
-    /* column of every particle, then the highest top z + r per column */
     cell_entry* ce = (cell_entry*)malloc((size_t)(n > 0 ? n : 1) * sizeof(cell_entry));
     for (int64_t i = 0; i < n; ++i) {
-        int64_t cx = (int64_t)floor((x[3 * i] - P->grid_lo[0]) / h);
-        int64_t cy = (int64_t)floor((x[3 * i + 1] - P->grid_lo[1]) / h);
+        int64_t cx, cy;
+        column_of(P, rmax, &x[3 * i], &cx, &cy);
         ce[i].cell = cy * 1048576 + cx;
         ce[i].idx = i;
     }
     qsort(ce, (size_t)n, sizeof(cell_entry), cmp_cell);
-    double* depth = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     for (int64_t s0 = 0; s0 < n;) {
         int64_t s1 = s0;
         double top = -1e300;
@@ -704,6 +723,18 @@ static void learned_features(const orc_params* P, int64_t n, const double* x, co
         s0 = s1;
     }
     free(ce);
+}
+
+/* The 12 inputs of the learned start (one reading of the configuration's
+ * "overlap, normal/tangential relative velocity, previous-step impulses,
+ * depth below free surface, radii"), the frame and the impulse scale. */
+static void learned_features(const orc_params* P, int64_t n, const double* x, const double* r,
+                             const double* v, const double* w, const row* rows, int64_t nc,
+                             const double* lnprev, const double* ltprev, double* F, double (*frames)[6],
+                             double* scale)
+{
+    double* depth = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    column_depths(P, n, x, r, depth);
     double gmag = sqrt(dot3(P->g, P->g));
     double gdt = gmag * P->dt;
     for (int64_t c = 0; c < nc; ++c) {
@@ -714,14 +745,13 @@ static void learned_features(const orc_params* P, int64_t n, const double* x, co
         double ut[3] = {u[0] - un * R->n[0], u[1] - un * R->n[1], u[2] - un * R->n[2]};
         double t1[3], t2[3];
         contact_frame(R, u, &ltprev[3 * c], t1, t2);
-        double meff = 1.0 / R->Wn;
-        double ls = meff * gdt;
+        double ls = (1.0 / R->Wn) * gdt;
         double rbar = R->a >= 0 ? 0.5 * (r[R->a] + r[R->b]) : r[R->b];
         double* f = &F[12 * c];
         f[0] = R->delta / rbar;
         f[1] = un / gdt;
         f[2] = sqrt(dot3(ut, ut)) / gdt;
-        f[3] = R->ln / ls;
+        f[3] = lnprev[c] / ls;
         f[4] = dot3(&ltprev[3 * c], t1) / ls;
         f[5] = dot3(&ltprev[3 * c], t2) / ls;
         f[6] = R->a >= 0 ? depth[R->a] / rbar : 0.0;
@@ -731,8 +761,8 @@ static void learned_features(const orc_params* P, int64_t n, const double* x, co
         f[10] = R->a >= 0 ? 0.0 : 1.0;
         f[11] = R->persistent ? 1.0 : 0.0;
         for (int k = 0; k < 3; ++k) { frames[c][k] = t1[k]; frames[c][3 + k] = t2[k]; }
+        scale[c] = ls;
     }
-    (void)M;
     free(depth);
 }
 
@@ -977,15 +1007,15 @@ int64_t orc_step(const orc_params* P,
         /* trial: learned start and its first sweep */
         double* F = (double*)malloc((size_t)nc * 12 * sizeof(double));
         double (*fr)[6] = malloc((size_t)nc * sizeof(double[6]));
+        double* lsc = (double*)malloc((size_t)nc * sizeof(double));
         double* y = (double*)malloc((size_t)nc * 3 * sizeof(double));
-        learned_features(P, n, x, r, v0, w, &M, rows, nc, ltprev, F, fr);
+        learned_features(P, n, x, r, v0, w, rows, nc, lnprev, ltprev, F, fr, lsc);
         orc_mlp_forward(mlp, nc, F, y);
-        double gmag = sqrt(dot3(P->g, P->g));
         int finite = 1;
         row* rl = (row*)malloc((size_t)nc * sizeof(row));
         memcpy(rl, rows, (size_t)nc * sizeof(row));
         for (int64_t c = 0; c < nc; ++c) {
-            double ls = (1.0 / rl[c].Wn) * gmag * dt;
+            double ls = lsc[c];
             rl[c].ln = y[3 * c] * ls;
             for (int k = 0; k < 3; ++k) rl[c].lt[k] = (y[3 * c + 1] * fr[c][k] + y[3 * c + 2] * fr[c][3 + k]) * ls;
             if (!isfinite(rl[c].ln) || !isfinite(rl[c].lt[0]) || !isfinite(rl[c].lt[1]) || !isfinite(rl[c].lt[2])) finite = 0;
@@ -1017,7 +1047,7 @@ int64_t orc_step(const orc_params* P,
         r1 = R;
         if (resid) resid[0] = R;
         sweeps_done = 1;
-        free(vl); free(wl); free(rl); free(y); free(fr); free(F);
+        free(vl); free(wl); free(rl); free(y); free(lsc); free(fr); free(F);
     } else {
         apply_start(rows, nc, &M, v, w);
     }
@@ -1091,6 +1121,39 @@ int64_t orc_step(const orc_params* P,
     free(ltprev); free(lnprev); free(v0);
     free(cstart); free(corder); free(rows);
     free(M.im); free(M.iI);
+    return nc;
+}
+
+int64_t orc_features(const orc_params* P, int64_t n, const int64_t* id, const double* r, const double* rho,
+                     const double* x, const double* v, const double* w,
+                     int32_t nb, const orc_body* bodies, int32_t ns, const orc_shape* shapes,
+                     int64_t nprev, const uint64_t* prev_keys, const double* prev_lam,
+                     int64_t cap, double* feat, double* frame, double* scale)
+{
+    inv_mass M;
+    make_inv_mass(P, n, r, rho, &M);
+    raw_contact* rc = NULL;
+    int64_t nc = detect_all(P, n, id, x, r, nb, bodies, ns, shapes, &rc);
+    if (nc > cap) { free(rc); free(M.im); free(M.iI); return -5; }
+    row* rows = (row*)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(row));
+    build_rows(P, id, r, &M, x, v, w, bodies, shapes, rc, nc, rows);
+    free(rc);
+    double* lt = (double*)calloc((size_t)(nc > 0 ? nc : 1) * 3, sizeof(double));
+    double* ln = (double*)calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t k = nprev > 0 ? find_prev(nprev, prev_keys, rows[c].key) : -1;
+        rows[c].persistent = k >= 0;
+        if (k >= 0) {
+            ln[c] = prev_lam[4 * k];
+            for (int j = 0; j < 3; ++j) lt[3 * c + j] = prev_lam[4 * k + 1 + j];
+            double tn = dot3(rows[c].n, &lt[3 * c]);
+            for (int j = 0; j < 3; ++j) lt[3 * c + j] -= tn * rows[c].n[j];
+        }
+    }
+    double (*fr)[6] = malloc((size_t)(nc > 0 ? nc : 1) * sizeof(double[6]));
+    learned_features(P, n, x, r, v, w, rows, nc, ln, lt, feat, fr, scale);
+    for (int64_t c = 0; c < nc; ++c) for (int k = 0; k < 6; ++k) frame[6 * c + k] = fr[c][k];
+    free(fr); free(lt); free(ln); free(rows); free(M.im); free(M.iI);
     return nc;
 }
 

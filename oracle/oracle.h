@@ -51,7 +51,8 @@ typedef struct orc_material {
 typedef struct orc_params {
     double dt;
     double g[3];
-    double grid_lo[3];   /* origin of the column grid used by the learned start */
+    double grid_lo[3];   /* grid bounds of the env: origin and far corner of the column grid */
+    double grid_hi[3];   /* used by the learned-start depth feature */
     double r_ref;        /* nominal particle radius (learned-start features) */
     int32_t max_sweeps;
     double tol;          /* 0: fixed number of sweeps */
@@ -151,6 +152,16 @@ int64_t orc_step(const orc_params* P,
  * particle.  Returns the number written to agg (one per body with a zone). */
 int32_t orc_aggregates(int64_t n, const double* r, const double* inv_m, const double* x, const double* v,
                        const double* w, int32_t nb, const orc_body* bodies, orc_aggregate* agg);
+
+/* Learned-start features (12 per canonical contact), the contact frame
+ * (t1, t2: 6 per contact) and the impulse scale m_eff g dt (1 per contact)
+ * for the state (x, v, w) and the previous-step cache.  Returns the contact
+ * count (the list is the one orc_detect gives). */
+int64_t orc_features(const orc_params* P, int64_t n, const int64_t* id, const double* r, const double* rho,
+                     const double* x, const double* v, const double* w,
+                     int32_t nb, const orc_body* bodies, int32_t ns, const orc_shape* shapes,
+                     int64_t nprev, const uint64_t* prev_keys, const double* prev_lam,
+                     int64_t cap, double* feat, double* frame, double* scale);
 
 /* Natural-map complementarity residual of the MCP built for the state
  * (x, v, w) with impulses lam (4 per canonical contact), evaluated at the

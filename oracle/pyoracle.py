@@ -42,7 +42,7 @@ class Material(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("g", C.c_double * 3), ("grid_lo", C.c_double * 3),
-                ("r_ref", C.c_double), ("max_sweeps", C.c_int32), ("tol", C.c_double),
+                ("grid_hi", C.c_double * 3), ("r_ref", C.c_double), ("max_sweeps", C.c_int32), ("tol", C.c_double),
                 ("warm", C.c_int32), ("detect", C.c_int32), ("m", Material)]
 
 
@@ -100,6 +100,10 @@ def lib():
         L.orc_aggregates.restype = C.c_int32
         L.orc_aggregates.argtypes = [C.c_int64, dp, dp, dp, dp, dp, C.c_int32, C.POINTER(Body),
                                      C.POINTER(Aggregate)]
+        L.orc_features.restype = C.c_int64
+        L.orc_features.argtypes = [C.POINTER(Params), C.c_int64, i64p, dp, dp, dp, dp, dp,
+                                   C.c_int32, C.POINTER(Body), C.c_int32, C.POINTER(Shape),
+                                   C.c_int64, u64p, dp, C.c_int64, dp, dp, dp]
         L.orc_natural_residual.restype = C.c_double
         L.orc_natural_residual.argtypes = [C.POINTER(Params), C.c_int64, i64p, dp, dp, dp, dp, dp,
                                            C.c_int32, C.POINTER(Body), C.c_int32, C.POINTER(Shape),
@@ -132,6 +136,7 @@ def make_params(spec: dict, detect: int = CELLS) -> Params:
     for k in range(3):
         P.g[k] = spec["gravity"][k]
         P.grid_lo[k] = spec.get("grid_lo", (0.0, 0.0, 0.0))[k]
+        P.grid_hi[k] = spec.get("grid_hi", (1.0, 1.0, 1.0))[k]
     P.r_ref = spec.get("r_ref", 0.05)
     P.max_sweeps = spec["max_sweeps"]
     P.tol = spec.get("tol", 0.0)
@@ -290,6 +295,24 @@ class OracleScene:
                          learned_used=st.learned_used, r1=st.r1_first,
                          resid=resid[: st.sweeps].copy(), body_ft=ft[:nb].copy(), aggregates=aggs)
         return self.last
+
+    def features(self):
+        """Learned-start features, frames and impulse scales of the current
+        state and cache (the inputs the next step's learned start sees)."""
+        L = lib()
+        cap = self.cap
+        feat = np.zeros((cap, 12)); frame = np.zeros((cap, 6)); scale = np.zeros(cap)
+        rho_p = _dp(self.rho) if self.rho is not None else C.POINTER(C.c_double)()
+        pk = np.ascontiguousarray(self.prev_keys)
+        pl = np.ascontiguousarray(self.prev_lam)
+        nc = L.orc_features(C.byref(self.P), self.n, self.ids.ctypes.data_as(C.POINTER(C.c_int64)),
+                            _dp(self.r), rho_p, _dp(self.x), _dp(self.v), _dp(self.w),
+                            self.bb.nb, self.bb.bodies, self.bb.ns, self.bb.shapes,
+                            len(pk), pk.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(pl),
+                            cap, _dp(feat), _dp(frame), _dp(scale))
+        if nc < 0:
+            raise RuntimeError(f"orc_features failed ({nc})")
+        return feat[:nc].copy(), frame[:nc].copy(), scale[:nc].copy()
 
     def natural_residual(self, x, v, w, lam):
         L = lib()

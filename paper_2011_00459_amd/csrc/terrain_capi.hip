@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -53,6 +54,9 @@ struct tr_scene {
     hipEvent_t ev[5] = {};
     bool events = false;
     float* staging = nullptr;         // 12 floats per particle (device), id-order exchange
+    int64_t cols_alloc = 0;
+    bool mlp_loaded = false;
+    bool mlp_bf16 = true;
 };
 
 namespace {
@@ -133,6 +137,7 @@ int rebuild_tables(tr_scene* s)
     std::vector<float> pool;
     std::vector<int4> chunks;
     int64_t NC = 0;
+    int64_t NCOL = 0;
     int n_zones = 0;
     int64_t slot = 0;
     s->zone_slots.assign(E, {});
@@ -152,6 +157,8 @@ int rebuild_tables(tr_scene* s)
         }
         D.inv_h = (float)(1.0 / h);
         D.cell_base = (uint32_t)NC;
+        D.col_base = (int)NCOL;
+        NCOL += (int64_t)D.dims[0] * D.dims[1];
         NC += (int64_t)1 << (D.bits[0] + D.bits[1] + D.bits[2]);
         if (NC >= ((int64_t)1 << 31)) return fail(s, TR_E_CAPACITY, "too many cells");
         D.id_base = (int)(e * s->desc.cap_particles);
@@ -234,6 +241,11 @@ int rebuild_tables(tr_scene* s)
         HIP_CHECK(s, hipMemsetAsync(s->b.body_ft, 0, sizeof(double) * nb * 6, st));
         HIP_CHECK(s, hipMemsetAsync(s->b.aggs, 0, sizeof(tr_aggregate) * nz, st));
     }
+    if (NCOL > s->cols_alloc) {
+        dfree(s, s->b.colmax);
+        if (!alloc_n(s, s->b.colmax, NCOL)) return fail(s, TR_E_NOMEM, "depth columns");
+        s->cols_alloc = NCOL;
+    }
     if ((int64_t)chunks.size() > s->zone_chunk_alloc) {
         dfree(s, s->b.zone_chunks); dfree(s, s->b.zone_part);
         int64_t nch = std::max<int64_t>((int64_t)chunks.size(), 1);
@@ -255,6 +267,7 @@ int rebuild_tables(tr_scene* s)
     s->body_host = bd;
     s->env_host = ed;
     s->z.NC = NC;
+    s->z.NCOL = NCOL;
     s->z.n_zone_chunks = (int)chunks.size();
     s->p.n_bodies = (int)bd.size();
     s->p.n_shapes = (int)sd.size();
@@ -307,6 +320,10 @@ void fill_params(tr_scene* s)
     p.max_sweeps = d.max_sweeps;
     p.tol = (float)d.tol;
     p.warm = d.warm_start;
+    p.dt_d = dt;
+    p.gdt = std::sqrt(d.gravity[0] * d.gravity[0] + d.gravity[1] * d.gravity[1] + d.gravity[2] * d.gravity[2]) * dt;
+    if (!(p.gdt > 0.0)) p.gdt = 1.0;
+    p.r_ref = d.r_ref > 0.0 ? d.r_ref : 1.0;
 }
 
 }  // namespace
@@ -339,7 +356,17 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
     z.NID = z.P;
     z.NB = (z.C + 255) / 256;
     z.pgs_block = 256;
-    z.pgs_grid = std::min(pgs_resident_blocks(256), 1024);
+    // PGS grid: few blocks keep the colour barrier cheap (about 1.5 us at 64
+    // blocks against 18 us at 1024 on MI355X); large scenes want more CUs
+    {
+        int64_t per_env = d->cap_contacts;
+        int64_t total = z.C;
+        int want = total >= 2000000 ? 256 : (total >= 400000 ? 128 : 64);
+        (void)per_env;
+        const char* ev = getenv("TR_PGS_GRID");
+        if (ev && atoi(ev) > 0) want = atoi(ev);
+        z.pgs_grid = std::max(1, std::min(pgs_resident_blocks(256), want));
+    }
     z.col_grid = std::min(colour_resident_blocks(), 2048);
     DevBuffers& b = s->b;
     bool ok = alloc_n(s, b.xr, z.P) && alloc_n(s, b.vm, z.P) && alloc_n(s, b.wi, z.P) && alloc_n(s, b.xr2, z.P) &&
@@ -357,7 +384,9 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
               alloc_n(s, b.lam, z.C) && alloc_n(s, b.lam0, z.C) &&
               alloc_n(s, b.block_part, (int64_t)4 * z.pgs_grid) && alloc_n(s, b.envs, d->n_envs) &&
               alloc_n(s, b.cnt, 1) && alloc_n(s, b.env_stats, d->n_envs) && alloc_n(s, b.mlp, kMlpParams) &&
-              alloc_n(s, s->staging, 12 * z.P);
+              alloc_n(s, s->staging, 12 * z.P) && alloc_n(s, b.feat, 12 * z.C) && alloc_n(s, b.frm1, z.C) &&
+              alloc_n(s, b.frm2, z.C) && alloc_n(s, b.lamL, z.C) && alloc_n(s, b.mlp_out, 3 * z.C) &&
+              alloc_n(s, b.pdepth, z.P);
     if (!ok) {
         destroy_scene(s);
         return TR_E_NOMEM;
@@ -527,9 +556,25 @@ int step(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
         launch_narrow(s->b, s->p, s->z, st);
         launch_canonical(s->b, s->p, s->z, st);
         (void)hipEventRecord(s->ev[1], st);
+        launch_depth(s->b, s->p, s->z, st);
         launch_colour(s->b, s->p, s->z, st);
         launch_rows(s->b, s->p, s->z, s->have_prev, st);
-        if (s->p.warm == TR_WARM_LEARNED) launch_learned_start(s->b, s->p, s->z, st);
+        if (s->p.warm == TR_WARM_LEARNED && s->mlp_loaded) {
+            // learned start, then the first-sweep trial against the previous-step start
+            launch_mlp_infer(s->b.mlp, s->b.feat, s->b.mlp_out, &s->b.cnt->n_raw, s->z.C, s->mlp_bf16, st);
+            launch_learned_lam(s->b, s->p, s->z, st);
+            launch_vel_copy(s->b, s->p, true, st);
+            launch_select_start(s->b, s->z, 1, st);
+            launch_warm_apply(s->b, s->p, s->z, st);
+            launch_pgs(s->b, s->p, s->z, st, 1, 1);
+            launch_vel_copy(s->b, s->p, false, st);
+            launch_select_start(s->b, s->z, 0, st);
+            launch_warm_apply(s->b, s->p, s->z, st);
+            launch_pgs(s->b, s->p, s->z, st, 1, 2);
+            launch_choose_start(s->b, st);
+            launch_vel_copy(s->b, s->p, false, st);
+            launch_select_start(s->b, s->z, 2, st);
+        }
         launch_warm_apply(s->b, s->p, s->z, st);
         (void)hipEventRecord(s->ev[2], st);
         launch_pgs(s->b, s->p, s->z, st);
@@ -678,6 +723,71 @@ int set_particles(tr_scene* s, int32_t env, const double* pos, const double* vel
     return TR_OK;
 }
 
+int set_learned_precision(tr_scene* s, int32_t use_bf16)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    s->mlp_bf16 = use_bf16 != 0;
+    return TR_OK;
+}
+
+int get_learn_samples(tr_scene* s, int32_t env, int64_t cap, float* feat, float* label, int64_t* n)
+{
+    if (!s || !n || cap < 0 || (cap > 0 && (!feat || !label))) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "get_learn_samples: env");
+    *n = 0;
+    if (!s->stepped) return TR_OK;
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    int64_t base = (int64_t)env * s->desc.cap_particles;
+    uint32_t r[2];
+    HIP_CHECK(s, hipMemcpy(&r[0], s->b.pid_start + base, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    HIP_CHECK(s, hipMemcpy(&r[1], s->b.pid_start + base + s->desc.cap_particles, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    int64_t cnt = (int64_t)r[1] - (int64_t)r[0];
+    *n = cnt;
+    int64_t m = std::min(cnt, cap);
+    int64_t done = 0;
+    // through the staging buffer (12 floats per particle) in chunks
+    int64_t chunk = std::max<int64_t>(1, (12 * s->z.P) / 15);
+    while (done < m) {
+        int64_t k = std::min(chunk, m - done);
+        float* df = s->staging;
+        float* dl = s->staging + 12 * k;
+        launch_learn_samples(s->b, (int64_t)r[0] + done, k, df, dl, s->stream);
+        HIP_CHECK(s, hipMemcpyAsync(feat + 12 * done, df, sizeof(float) * 12 * k, hipMemcpyDeviceToHost, s->stream));
+        HIP_CHECK(s, hipMemcpyAsync(label + 3 * done, dl, sizeof(float) * 3 * k, hipMemcpyDeviceToHost, s->stream));
+        HIP_CHECK(s, hipStreamSynchronize(s->stream));
+        done += k;
+    }
+    return TR_OK;
+}
+
+int mlp_forward(const float* weights, const float* feat, int64_t B, float* out, int32_t use_bf16, void* stream)
+{
+    if (!weights || (B > 0 && (!feat || !out)) || B < 0) return TR_E_INVAL;
+    launch_mlp_infer(weights, feat, out, nullptr, B, use_bf16 != 0, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? TR_OK : TR_E_DEVICE;
+}
+
+int64_t mlp_grad_scratch_floats(int64_t B) { return B > 0 ? mlp_grad_scratch(B) : 0; }
+
+int mlp_loss_grad(const float* weights, const float* feat, const float* label, int64_t B, float* grad, float* loss,
+                  float* scratch, int64_t scratch_floats, void* stream)
+{
+    if (!weights || !feat || !label || !grad || !scratch || B <= 0) return TR_E_INVAL;
+    if (scratch_floats < mlp_grad_scratch(B)) return TR_E_CAPACITY;
+    launch_mlp_grad(weights, feat, label, B, grad, loss, scratch, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? TR_OK : TR_E_DEVICE;
+}
+
+int mlp_adam_step(float* weights, const float* grad, float* m, float* v, float lr, float beta1, float beta2, float eps,
+                  int32_t t, void* stream)
+{
+    if (!weights || !grad || !m || !v || t < 1 || !(lr > 0.0f)) return TR_E_INVAL;
+    launch_adam(weights, grad, m, v, mlp_trainable(), lr, beta1, beta2, eps, t, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? TR_OK : TR_E_DEVICE;
+}
+
 int set_mlp_weights(tr_scene* s, const float* weights, int64_t n)
 {
     if (!s || !weights) return TR_E_INVAL;
@@ -687,6 +797,7 @@ int set_mlp_weights(tr_scene* s, const float* weights, int64_t n)
         if (!std::isfinite(weights[i])) return fail(s, TR_E_NONFINITE, "set_mlp_weights: non-finite weight");
     HIP_CHECK(s, hipMemcpyAsync(s->b.mlp, weights, sizeof(float) * n, hipMemcpyHostToDevice, s->stream));
     HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    s->mlp_loaded = true;
     return TR_OK;
 }
 

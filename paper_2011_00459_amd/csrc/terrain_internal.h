@@ -47,6 +47,7 @@ struct EnvDev {
     int id_base;                  // first particle id of the env
     int n;                        // particles of the env
     int slot_begin;               // first slot of the env in sorted order
+    int col_base;                 // first depth column of the env (dims[0] x dims[1] columns)
     int zone_count;
     int zone_body[kMaxZonesPerEnv];  // global body index of each zone
     int zone_slot[kMaxZonesPerEnv];  // global zone index of each zone
@@ -105,6 +106,9 @@ struct StepParams {
     int n_bodies;
     int n_shapes;
     int n_zones;
+    double dt_d;        // dt in FP64 (learned-start features)
+    double gdt;         // |g| dt
+    double r_ref;       // nominal radius of the features
 };
 
 struct Counters {
@@ -118,6 +122,9 @@ struct Counters {
     uint32_t barrier_gen;
     double resid;
     double resid_first;
+    uint32_t learn_flags;  // bit 0: non-finite network output
+    uint32_t use_learned;  // 1 when the learned start won the first-sweep trial
+    double r1_trial[2];    // first-sweep residual from the learned / previous start
 };
 
 struct EnvStats {
@@ -162,7 +169,14 @@ struct DevBuffers {
     Counters* cnt;
     EnvStats* env_stats;
     uint32_t* scan_tmp;   // scratch of the device-wide scan
-    float* mlp;           // learned-start weights
+    float* mlp;           // learned-start weights (kMlpParams)
+    // learned start (colour order) and the depth feature
+    float* feat;          // [C * 12]
+    float4 *frm1, *frm2;  // (t1, m_eff g dt), (t2, 0)
+    float4* lamL;         // learned lambda^0
+    float* mlp_out;       // [C * 3]
+    float* pdepth;        // [P] depth below the column top
+    uint32_t* colmax;     // [columns] ordered-int max of z + r
 };
 
 // Sizes that fix the launch shapes.
@@ -176,6 +190,7 @@ struct Sizes {
     int pgs_grid;   // resident blocks of the persistent PGS kernel
     int pgs_block;
     int col_grid;   // resident blocks of the colouring kernel
+    int64_t NCOL;   // depth columns (all envs)
 };
 
 // ---- launchers (terrain_kernels.hip) ----
@@ -189,9 +204,26 @@ void launch_narrow(const DevBuffers& b, const StepParams& p, const Sizes& z, hip
 void launch_canonical(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, hipStream_t s);
-void launch_learned_start(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
-void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+// sweeps_cap < 0: the scene's max_sweeps; slot 0 writes the step stats,
+// slot 1/2 the first-sweep residual of the learned / previous-step trial
+void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s, int sweeps_cap = -1,
+                int slot = 0);
+void launch_depth(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+void launch_vel_copy(const DevBuffers& b, const StepParams& p, bool backup, hipStream_t s);
+void launch_select_start(const DevBuffers& b, const Sizes& z, int mode, hipStream_t s);
+void launch_choose_start(const DevBuffers& b, hipStream_t s);
+void launch_learn_samples(const DevBuffers& b, int64_t beg, int64_t n, float* feat, float* label, hipStream_t s);
+// terrain_mlp.hip
+void launch_mlp_infer(const float* W, const float* feat, float* out, const uint32_t* d_n, int64_t cap, bool bf16,
+                      hipStream_t s);
+void launch_learned_lam(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+void launch_mlp_grad(const float* W, const float* feat, const float* label, int64_t B, float* grad, float* loss,
+                     float* scratch, hipStream_t s);
+void launch_adam(float* W, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps, int t,
+                 hipStream_t s);
+int64_t mlp_grad_scratch(int64_t B);
+int mlp_trainable();
 void launch_finish(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_gather_by_id(const DevBuffers& b, int id_base, int n, float4* xo, float4* vo, float4* wo,
                          hipStream_t s);

@@ -26,6 +26,10 @@
 namespace trk {
 
 constexpr int kBlk = 256;
+#ifndef TRK_BARRIER_SPINS
+#define TRK_BARRIER_SPINS (1l << 22)
+#endif
+constexpr long kBarrierSpins = TRK_BARRIER_SPINS;  // bounded wait of a grid barrier
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -301,6 +305,7 @@ __global__ void k_step_begin(DevBuffers b, StepParams p)
         c->n_raw = 0; c->n_pairs = 0; c->overflow = 0; c->n_colours = 0;
         c->sweeps = 0; c->fallback = 0; c->barrier_count = 0; c->barrier_gen = 0;
         c->resid = 0.0; c->resid_first = 0.0;
+        c->learn_flags = 0; c->use_learned = 0; c->r1_trial[0] = 0.0; c->r1_trial[1] = 0.0;
     }
     if (t < p.n_envs) { b.env_stats[t].contacts = 0; b.env_stats[t].pairs = 0; }
     if (t < p.n_shapes) {
@@ -707,9 +712,11 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     double r2 = x2.w;
     double n[3], delta, l1, l2, dstar, dref, rmin, im1 = 0.0, iI1 = 0.0, un;
     double vk[3] = {0.0, 0.0, 0.0};
+    double u1[3] = {0.0, 0.0, 0.0};  // velocity of body 1 at the contact point
     if (ia >= 0) {
         float4 x1 = b.xr[ia];
         float4 v1 = b.vm[ia];
+        float4 w1 = b.wi[ia];
         double r1 = x1.w;
         double e[3] = {X2[0] - x1.x, X2[1] - x1.y, X2[2] - x1.z};
         double d = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
@@ -722,8 +729,12 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
         dref = r1 + r2;
         rmin = fmin(r1, r2);
         im1 = v1.w;
-        iI1 = b.wi[ia].w;
+        iI1 = w1.w;
         un = n[0] * ((double)v2.x - v1.x) + n[1] * ((double)v2.y - v1.y) + n[2] * ((double)v2.z - v1.z);
+        // v1 + w1 x (l1 n)
+        u1[0] = (double)v1.x + l1 * ((double)w1.y * n[2] - (double)w1.z * n[1]);
+        u1[1] = (double)v1.y + l1 * ((double)w1.z * n[0] - (double)w1.x * n[2]);
+        u1[2] = (double)v1.z + l1 * ((double)w1.x * n[1] - (double)w1.y * n[0]);
     } else {
         int sg = -1 - ia;
         const ShapeDev& S = b.shapes[sg];
@@ -743,6 +754,7 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
         vk[1] = B.linvel[1] + (B.angvel[2] * arm[0] - B.angvel[0] * arm[2]);
         vk[2] = B.linvel[2] + (B.angvel[0] * arm[1] - B.angvel[1] * arm[0]);
         un = n[0] * ((double)v2.x - vk[0]) + n[1] * ((double)v2.y - vk[1]) + n[2] * ((double)v2.z - vk[2]);
+        u1[0] = vk[0]; u1[1] = vk[1]; u1[2] = vk[2];
     }
     // Hertz stiffness and the row scaled to unit Jacobian
     double kn = p.Estar * sqrt(dstar) / 3.0;
@@ -759,13 +771,66 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
 
     // warm start: previous-step impulses of the same key
     float4 L = make_float4(0.f, 0.f, 0.f, 0.f);
+    bool persistent = false;
     if (use_prev) {
         uint32_t a = (uint32_t)(key >> 32);
         uint32_t beg = b.pid_start[a], end = b.pid_start[a + 1];
         for (uint32_t t = beg; t < end; ++t)
-            if (b.pkeyc[t] == key) { L = b.plam[t]; break; }
+            if (b.pkeyc[t] == key) { L = b.plam[t]; persistent = true; break; }
+    }
+    uint32_t pos = b.cpos[c];
+    // learned-start features (12), contact frame and impulse scale, in FP64
+    {
+        float4 w2 = b.wi[ib];
+        double u[3];
+        u[0] = ((double)v2.x - l2 * ((double)w2.y * n[2] - (double)w2.z * n[1])) - u1[0];
+        u[1] = ((double)v2.y - l2 * ((double)w2.z * n[0] - (double)w2.x * n[2])) - u1[1];
+        u[2] = ((double)v2.z - l2 * ((double)w2.x * n[1] - (double)w2.y * n[0])) - u1[2];
+        double unf = (n[0] * u[0] + n[1] * u[1]) + n[2] * u[2];
+        double ut[3] = {u[0] - unf * n[0], u[1] - unf * n[1], u[2] - unf * n[2]};
+        double utm = sqrt((ut[0] * ut[0] + ut[1] * ut[1]) + ut[2] * ut[2]);
+        double lp[3] = {L.y, L.z, L.w};
+        double lpn = (n[0] * lp[0] + n[1] * lp[1]) + n[2] * lp[2];
+        for (int k = 0; k < 3; ++k) lp[k] -= lpn * n[k];
+        double t1[3];
+        if (utm > 1e-12) {
+            for (int k = 0; k < 3; ++k) t1[k] = ut[k] / utm;
+        } else {
+            double lm = sqrt((lp[0] * lp[0] + lp[1] * lp[1]) + lp[2] * lp[2]);
+            if (lm > 0.0) {
+                for (int k = 0; k < 3; ++k) t1[k] = lp[k] / lm;
+            } else {
+                int k0 = 0;
+                for (int k = 1; k < 3; ++k) if (fabs(n[k]) < fabs(n[k0])) k0 = k;
+                double ax[3] = {0.0, 0.0, 0.0};
+                ax[k0] = 1.0;
+                double dn = (ax[0] * n[0] + ax[1] * n[1]) + ax[2] * n[2];
+                for (int k = 0; k < 3; ++k) t1[k] = ax[k] - dn * n[k];
+                double sm = sqrt((t1[0] * t1[0] + t1[1] * t1[1]) + t1[2] * t1[2]);
+                for (int k = 0; k < 3; ++k) t1[k] /= sm;
+            }
+        }
+        double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+        double ls = (1.0 / Wn) * p.gdt;
+        double rbar = ia >= 0 ? 0.5 * ((double)b.xr[ia].w + r2) : r2;
+        float* f = b.feat + (size_t)pos * 12;
+        f[0] = (float)(delta / rbar);
+        f[1] = (float)(unf / p.gdt);
+        f[2] = (float)(utm / p.gdt);
+        f[3] = (float)((double)L.x / ls);
+        f[4] = (float)(((lp[0] * t1[0] + lp[1] * t1[1]) + lp[2] * t1[2]) / ls);
+        f[5] = (float)(((lp[0] * t2[0] + lp[1] * t2[1]) + lp[2] * t2[2]) / ls);
+        f[6] = ia >= 0 ? (float)((double)b.pdepth[ia] / rbar) : 0.0f;
+        f[7] = (float)((double)b.pdepth[ib] / rbar);
+        f[8] = ia >= 0 ? (float)((double)b.xr[ia].w / p.r_ref) : 0.0f;
+        f[9] = (float)(r2 / p.r_ref);
+        f[10] = ia >= 0 ? 0.0f : 1.0f;
+        f[11] = persistent ? 1.0f : 0.0f;
+        b.frm1[pos] = make_float4((float)t1[0], (float)t1[1], (float)t1[2], (float)ls);
+        b.frm2[pos] = make_float4((float)t2[0], (float)t2[1], (float)t2[2], 0.0f);
     }
     float nf[3] = {(float)n[0], (float)n[1], (float)n[2]};
+    if (p.warm == TR_WARM_COLD) L = make_float4(0.f, 0.f, 0.f, 0.f);
     {
         float ln = fmaxf(L.x, (float)lo);
         float tn = nf[0] * L.y + nf[1] * L.z + nf[2] * L.w;
@@ -778,7 +843,6 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
         }
         L = make_float4(ln, t0, t1, t2);
     }
-    uint32_t pos = b.cpos[c];
     b.r0[pos] = make_float4(nf[0], nf[1], nf[2], (float)l1);
     b.r1[pos] = make_float4((float)l2, (float)(1.0 / Dn), (float)(1.0 / Dt), (float)Sig);
     b.r2[pos] = make_float4((float)q, (float)lo, __int_as_float(ia), __int_as_float(ib));
@@ -789,8 +853,7 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
 
 void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rows, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, p, z.C,
-                       have_prev && p.warm != TR_WARM_COLD ? 1 : 0);
+    hipLaunchKernelGGL(k_rows, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, p, z.C, have_prev ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -836,61 +899,78 @@ void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z,
 // ---------------------------------------------------------------------------
 // A9: persistent projected Gauss-Seidel.  Sweeps x colours; inside a colour
 // no two contacts share a dynamic particle, so every contact updates its two
-// bodies without atomics.  A grid barrier separates colours.  The residual
-// R_k = ||d lambda||_D / ||lambda||_D of each sweep is reduced per block in
-// fixed order and combined identically by every block, which then all take
-// the same stopping decision.
+// bodies without atomics.  Contact c of a colour is always handled by the same
+// thread, so its rows (read-only) and its impulses (thread-owned) go through
+// the ordinary caches; the bodies, shared by blocks on all XCDs, are read and
+// written with device-coherent (sc1) 128-bit buffer accesses, which lets the
+// colour barrier be a plain counter without L2 write-back or invalidation.
+// The residual R_k = ||d lambda||_D / ||lambda||_D of each sweep is reduced per
+// block in fixed order and combined identically by every block, which then
+// all take the same stopping decision.
 // ---------------------------------------------------------------------------
-__device__ inline bool grid_barrier(Counters* cnt, unsigned nblocks, unsigned& gen, int& sh_ok)
+constexpr int kCoherent = 16;  // cache-policy bits of a device-scope (sc1) access
+
+__device__ inline __amdgpu_buffer_rsrc_t raw_rsrc(const void* p)
 {
-    bool ok = true;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ inline float4 ld_coherent(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 16, 0, kCoherent));
+}
+__device__ inline void st_coherent(__amdgpu_buffer_rsrc_t r, int idx, float4 v)
+{
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, idx * 16, 0, kCoherent);
+}
+
+// Counter barrier: the t-th barrier of a launch completes when the counter
+// (zeroed before the launch) reaches (t + 1) * nblocks.  Every thread has
+// waited for its own stores before the block arrives.  Bounded wait; a failed
+// barrier makes every block leave.
+__device__ inline bool grid_barrier(Counters* cnt, unsigned nblocks, unsigned& t, int& sh_ok)
+{
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        unsigned g = gen;
-        unsigned arrived = __hip_atomic_fetch_add(&cnt->barrier_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&cnt->barrier_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&cnt->barrier_gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            long spins = 0;
-            while (__hip_atomic_load(&cnt->barrier_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(1);
-                if ((++spins & 1023) == 0 &&
-                    (__hip_atomic_load(&cnt->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFailBarrier)) {
-                    ok = false;
-                    break;
-                }
-                if (spins > (1l << 22)) { ok = false; break; }
+        bool ok = true;
+        unsigned target = (t + 1) * nblocks;
+        __hip_atomic_fetch_add(&cnt->barrier_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        long spins = 0;
+        while (__hip_atomic_load(&cnt->barrier_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 1023) == 0 &&
+                (__hip_atomic_load(&cnt->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFailBarrier)) {
+                ok = false;
+                break;
             }
+            if (spins > kBarrierSpins) { ok = false; break; }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        gen = g + 1;
         if (!ok) atomicOr(&cnt->overflow, kFailBarrier);
         sh_ok = ok ? 1 : 0;
     }
+    ++t;
     __syncthreads();
     return sh_ok != 0;
 }
 
-__device__ inline void pgs_contact(const DevBuffers& b, uint32_t c, float mu, float gdt, float& num, float& den)
+__device__ inline void pgs_contact(const DevBuffers& b, __amdgpu_buffer_rsrc_t rv, __amdgpu_buffer_rsrc_t rw, uint32_t c,
+                                   float mu, float gdt, float& num, float& den)
 {
     float4 a = b.r0[c];
     float4 r1 = b.r1[c];
     float4 q = b.r2[c];
     float4 L = b.lam[c];
     int ia = __float_as_int(q.z), ib = __float_as_int(q.w);
-    float4 vb = b.vm[ib], wb = b.wi[ib];
-    float4 va, wa;
-    float3 vk;
     bool pair = ia >= 0;
+    float4 vb = ld_coherent(rv, ib), wb = ld_coherent(rw, ib);
+    float4 va, wa;
     if (pair) {
-        va = b.vm[ia];
-        wa = b.wi[ia];
+        va = ld_coherent(rv, ia);
+        wa = ld_coherent(rw, ia);
     } else {
         float4 k4 = b.rk[c];
-        vk = make_float3(k4.x, k4.y, k4.z);
-        va = make_float4(vk.x, vk.y, vk.z, 0.f);
+        va = make_float4(k4.x, k4.y, k4.z, 0.f);
         wa = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     float nx = a.x, ny = a.y, nz = a.z, l1 = a.w;
@@ -922,13 +1002,13 @@ __device__ inline void pgs_contact(const DevBuffers& b, uint32_t c, float mu, fl
     float cx = ny * dz - nz * dy, cy = nz * dx - nx * dz, cz = nx * dy - ny * dx;  // n x d
     vb.x += dx * vb.w; vb.y += dy * vb.w; vb.z += dz * vb.w;
     wb.x -= l2 * wb.w * cx; wb.y -= l2 * wb.w * cy; wb.z -= l2 * wb.w * cz;
-    b.vm[ib] = vb;
-    b.wi[ib] = wb;
+    st_coherent(rv, ib, vb);
+    st_coherent(rw, ib, wb);
     if (pair) {
         va.x -= dx * va.w; va.y -= dy * va.w; va.z -= dz * va.w;
         wa.x -= l1 * wa.w * cx; wa.y -= l1 * wa.w * cy; wa.z -= l1 * wa.w * cz;
-        b.vm[ia] = va;
-        b.wi[ia] = wa;
+        st_coherent(rv, ia, va);
+        st_coherent(rw, ia, wa);
     }
     b.lam[c] = make_float4(ln, tx, ty, tz);
     float Dn = 1.0f / iDn, Dt = 1.0f / iDt;
@@ -936,7 +1016,10 @@ __device__ inline void pgs_contact(const DevBuffers& b, uint32_t c, float mu, fl
     den += Dn * ln * ln + Dt * (tx * tx + ty * ty + tz * tz);
 }
 
-__global__ __launch_bounds__(kBlk) void k_pgs(DevBuffers b, StepParams p, int64_t cap, int64_t NB)
+__global__ void k_pgs_reset(Counters* cnt) { cnt->barrier_count = 0; }
+
+__global__ __launch_bounds__(kBlk) void k_pgs(DevBuffers b, StepParams p, int64_t cap, int64_t NB, int sweeps_cap,
+                                              int slot)
 {
     __shared__ double red[2][kBlk / 64];
     __shared__ int stop_flag;
@@ -944,19 +1027,21 @@ __global__ __launch_bounds__(kBlk) void k_pgs(DevBuffers b, StepParams p, int64_
     if (b.cnt->overflow) return;  // uniform: written by earlier kernels only
     uint32_t ncol = b.cnt->n_colours;
     unsigned G = gridDim.x;
-    unsigned gen = 0;
+    unsigned nbar = 0;
     int sweeps = 0;
     double Rk = 0.0, R1 = 0.0;
-    for (int k = 0; k < p.max_sweeps; ++k) {
+    __amdgpu_buffer_rsrc_t rv = raw_rsrc(b.vm), rw = raw_rsrc(b.wi);
+    for (int k = 0; k < sweeps_cap; ++k) {
         float num = 0.f, den = 0.f;
+        double* part = b.block_part + (size_t)(k & 1) * 2 * G;
         for (uint32_t col = 0; col < ncol; ++col) {
             uint32_t beg = b.col_start[(int64_t)col * NB], end = b.col_start[(int64_t)(col + 1) * NB];
             uint32_t len = end - beg;
             uint32_t lo = beg + (uint32_t)(((uint64_t)len * blockIdx.x) / G);
             uint32_t hi = beg + (uint32_t)(((uint64_t)len * (blockIdx.x + 1)) / G);
-            for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) pgs_contact(b, c, p.mu, p.gamma_dt, num, den);
+            for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) pgs_contact(b, rv, rw, c, p.mu, p.gamma_dt, num, den);
             if (col + 1 == ncol) {
-                // block partials of this sweep, before the last barrier
+                // block partials of this sweep, published before the last barrier
                 double dnum = num, dden = den;
                 for (int o = 32; o > 0; o >>= 1) {
                     dnum += __shfl_down(dnum, o, 64);
@@ -967,20 +1052,21 @@ __global__ __launch_bounds__(kBlk) void k_pgs(DevBuffers b, StepParams p, int64_
                 if (threadIdx.x == 0) {
                     double sn = 0.0, sd = 0.0;
                     for (int w = 0; w < kBlk / 64; ++w) { sn += red[0][w]; sd += red[1][w]; }
-                    double* part = b.block_part + (size_t)(k & 1) * 2 * G;
-                    part[2 * blockIdx.x] = sn;
-                    part[2 * blockIdx.x + 1] = sd;
+                    __hip_atomic_store(&part[2 * blockIdx.x], sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&part[2 * blockIdx.x + 1], sd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
-            if (!grid_barrier(b.cnt, G, gen, bar_ok)) return;  // every block leaves
+            if (!grid_barrier(b.cnt, G, nbar, bar_ok)) return;  // every block leaves
         }
         if (ncol == 0) {
             Rk = 0.0;
         } else {
             // every block reduces all block partials in the same fixed order
-            const double* part = b.block_part + (size_t)(k & 1) * 2 * G;
             double sn = 0.0, sd = 0.0;
-            for (unsigned t = threadIdx.x; t < G; t += blockDim.x) { sn += part[2 * t]; sd += part[2 * t + 1]; }
+            for (unsigned t = threadIdx.x; t < G; t += blockDim.x) {
+                sn += __hip_atomic_load(&part[2 * t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sd += __hip_atomic_load(&part[2 * t + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             for (int o = 32; o > 0; o >>= 1) {
                 sn += __shfl_down(sn, o, 64);
                 sd += __shfl_down(sd, o, 64);
@@ -999,9 +1085,13 @@ __global__ __launch_bounds__(kBlk) void k_pgs(DevBuffers b, StepParams p, int64_
         if (stop_flag) break;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        b.cnt->sweeps = (uint32_t)sweeps;
-        b.cnt->resid = Rk;
-        b.cnt->resid_first = R1;
+        if (slot == 0) {
+            b.cnt->sweeps = (uint32_t)sweeps;
+            b.cnt->resid = Rk;
+            b.cnt->resid_first = R1;
+        } else {
+            b.cnt->r1_trial[slot - 1] = R1;
+        }
     }
 }
 
@@ -1025,9 +1115,124 @@ int colour_resident_blocks()
     return std::max(1, per_cu) * pr.multiProcessorCount;
 }
 
-void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s, int sweeps_cap, int slot)
 {
-    hipLaunchKernelGGL(k_pgs, dim3(z.pgs_grid), dim3(kBlk), 0, s, b, p, z.C, z.NB);
+    int sw = sweeps_cap < 0 ? p.max_sweeps : sweeps_cap;
+    hipLaunchKernelGGL(k_pgs_reset, dim3(1), dim3(1), 0, s, b.cnt);
+    hipLaunchKernelGGL(k_pgs, dim3(z.pgs_grid), dim3(kBlk), 0, s, b, p, z.C, z.NB, sw, slot);
+}
+
+// ---------------------------------------------------------------------------
+// depth below the free surface: per env grid column the max of z + r
+// (ordered-integer atomic max, order free), then depth = top - z
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t f2ord(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float ord2f(uint32_t u) { return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u); }
+
+__device__ inline uint32_t column_of(const EnvDev& E, float4 x)
+{
+    int c[3];
+    cell_of(E, x.x, x.y, x.z, c);
+    return (uint32_t)E.col_base + (uint32_t)(c[1] * E.dims[0] + c[0]);
+}
+
+__global__ void k_colmax(DevBuffers b, StepParams p)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n_particles) return;
+    float4 x = b.xr[s];
+    const EnvDev& E = b.envs[env_of(b.pid[s], p.id_cap)];
+    atomicMax(&b.colmax[column_of(E, x)], f2ord(x.z + x.w));
+}
+
+__global__ void k_depth(DevBuffers b, StepParams p)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.n_particles) return;
+    float4 x = b.xr[s];
+    const EnvDev& E = b.envs[env_of(b.pid[s], p.id_cap)];
+    b.pdepth[s] = ord2f(b.colmax[column_of(E, x)]) - x.z;
+}
+
+void launch_depth(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+{
+    launch_fill_u32(b.colmax, 0u, z.NCOL, s);
+    if (p.n_particles <= 0) return;
+    unsigned g = (unsigned)cdiv(p.n_particles, kBlk);
+    hipLaunchKernelGGL(k_colmax, dim3(g), dim3(kBlk), 0, s, b, p);
+    hipLaunchKernelGGL(k_depth, dim3(g), dim3(kBlk), 0, s, b, p);
+}
+
+// ---------------------------------------------------------------------------
+// learned-start trial plumbing: velocity backup/restore, start selection,
+// the first-sweep comparison
+// ---------------------------------------------------------------------------
+__global__ void k_vel_copy(DevBuffers b, int n, int backup)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    if (backup) { b.vm2[s] = b.vm[s]; b.wi2[s] = b.wi[s]; }
+    else { b.vm[s] = b.vm2[s]; b.wi[s] = b.wi2[s]; }
+}
+
+void launch_vel_copy(const DevBuffers& b, const StepParams& p, bool backup, hipStream_t s)
+{
+    if (p.n_particles <= 0) return;
+    hipLaunchKernelGGL(k_vel_copy, dim3((unsigned)cdiv(p.n_particles, kBlk)), dim3(kBlk), 0, s, b, p.n_particles,
+                       backup ? 1 : 0);
+}
+
+__global__ void k_select_start(DevBuffers b, int64_t cap, int mode)
+{
+    uint32_t nc = n_contacts(b, cap);
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    bool learned = mode == 1 || (mode == 2 && b.cnt->use_learned);
+    b.lam[c] = learned ? b.lamL[c] : b.lam0[c];
+}
+
+void launch_select_start(const DevBuffers& b, const Sizes& z, int mode, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_select_start, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, z.C, mode);
+}
+
+__global__ void k_choose_start(DevBuffers b)
+{
+    Counters* c = b.cnt;
+    bool finite = (c->learn_flags & 1u) == 0 && isfinite(c->r1_trial[0]);
+    bool use = finite && !(c->r1_trial[0] > c->r1_trial[1]);
+    c->use_learned = use ? 1u : 0u;
+    c->fallback = use ? 0u : 1u;
+}
+
+void launch_choose_start(const DevBuffers& b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_choose_start, dim3(1), dim3(1), 0, s, b);
+}
+
+// training samples of the last step in canonical order: the 12 features and
+// the final impulses in the contact frame divided by m_eff g dt
+__global__ void k_learn_samples(DevBuffers b, int64_t beg, int64_t n, float* feat, float* label)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t pos = b.cpos[beg + k];
+    for (int q = 0; q < 12; ++q) feat[k * 12 + q] = b.feat[(size_t)pos * 12 + q];
+    float4 L = b.lam[pos], f1 = b.frm1[pos], f2 = b.frm2[pos];
+    float ls = f1.w;
+    label[k * 3 + 0] = L.x / ls;
+    label[k * 3 + 1] = (L.y * f1.x + L.z * f1.y + L.w * f1.z) / ls;
+    label[k * 3 + 2] = (L.y * f2.x + L.z * f2.y + L.w * f2.z) / ls;
+}
+
+void launch_learn_samples(const DevBuffers& b, int64_t beg, int64_t n, float* feat, float* label, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_learn_samples, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, s, b, beg, n, feat, label);
 }
 
 // ---------------------------------------------------------------------------
@@ -1343,11 +1548,6 @@ void launch_scatter_by_id(const DevBuffers& b, int id_base, int n, const float4*
     if (n <= 0) return;
     hipLaunchKernelGGL(k_scatter_by_id, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, s, b, id_base, n, xi, vi, wi,
                        mask);
-}
-
-void launch_learned_start(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
-{
-    (void)b; (void)p; (void)z; (void)s;
 }
 
 }  // namespace trk

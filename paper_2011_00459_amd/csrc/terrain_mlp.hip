@@ -1,0 +1,358 @@
+// terrain_mlp.hip -- the learned warm start: a 12 -> 64 -> 64 -> 3 SiLU MLP
+// that predicts each contact's initial impulses (lambda_n, lambda_t1,
+// lambda_t2) / (m_eff g dt) in the contact frame.
+//
+//   k_mlp_bf16    inference on MFMA (v_mfma_f32_32x32x8_bf16): one wave per 32
+//                 contacts, weights and activations in BF16, FP32 accumulate
+//   k_mlp_f32     the same network in FP32 on the vector ALU (reference)
+//   k_learned_lam lambda^0 = frame x output x scale, projected onto the bounds
+//   k_mlp_train   FP32 forward + backward of 0.5 mean ||y - label||^2, with
+//                 per-block gradient partials reduced in fixed order
+//   k_adam        Adam update
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "terrain_internal.h"
+
+namespace trk {
+
+namespace {
+
+constexpr int kIn = 12, kH = 64, kOut = 3;
+// offsets of the flat parameter vector
+constexpr int oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
+              ob3 = oW3 + kOut * kH, oScale = ob3 + kOut;
+constexpr int kNP = oScale;  // trainable parameters (in_scale is fixed)
+static_assert(oScale + kIn == kMlpParams, "parameter layout");
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float dsilu(float z)
+{
+    float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// round-to-nearest-even FP32 -> BF16 bits
+__device__ inline short to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// BF16 MFMA inference.  Block = 4 waves; each wave takes 32 contacts at a time.
+//   layer 1: X[32 x 16] (12 inputs padded) . W1^T[16 x 64]: 2 N-tiles x 2 K-steps
+//   layer 2: H1[32 x 64] . W2^T[64 x 64]: 2 N-tiles x 8 K-steps
+//   layer 3: 3 outputs per contact on the vector ALU from H2 (FP32 in LDS)
+// Operand layouts of v_mfma_f32_32x32x8_bf16 (A 32x8, B 8x32, D 32x32):
+//   A[i][k] -> lane i + 32 (k / 4), element k % 4
+//   B[k][j] -> lane j + 32 (k / 4), element k % 4
+//   D[i][j] -> lane j + 32 ((i / 4) % 2), element (i % 4) + 4 (i / 8)
+// ---------------------------------------------------------------------------
+constexpr int kMlpWaves = 4;
+
+__global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_bf16(const float* __restrict__ W, const float* __restrict__ feat,
+                                                              float* __restrict__ out, const uint32_t* d_n, int64_t cap)
+{
+    __shared__ short w1[kH][16];            // W1 rows, K padded to 16
+    __shared__ short w2[kH][kH];
+    __shared__ float w3[kOut][kH];
+    __shared__ float b1[kH], b2[kH], b3[kOut], sc[kIn];
+    __shared__ short xs[kMlpWaves][32][16];
+    __shared__ short hs[kMlpWaves][32][kH + 4];
+    __shared__ float h2s[kMlpWaves][32][kH + 1];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < kH * 16; t += blockDim.x) {
+        int j = t / 16, k = t % 16;
+        w1[j][k] = k < kIn ? to_bf16(W[oW1 + j * kIn + k]) : (short)0;
+    }
+    for (int t = tid; t < kH * kH; t += blockDim.x) w2[t / kH][t % kH] = to_bf16(W[oW2 + t]);
+    for (int t = tid; t < kOut * kH; t += blockDim.x) w3[t / kH][t % kH] = W[oW3 + t];
+    for (int t = tid; t < kH; t += blockDim.x) { b1[t] = W[ob1 + t]; b2[t] = W[ob2 + t]; }
+    if (tid < kOut) b3[tid] = W[ob3 + tid];
+    if (tid < kIn) sc[tid] = W[oScale + tid];
+    __syncthreads();
+
+    uint64_t n = d_n ? (uint64_t)min((uint64_t)*d_n, (uint64_t)cap) : (uint64_t)cap;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int half = lane >> 5, col = lane & 31;
+    uint64_t ntiles = (n + 31) / 32;
+    // every wave of the block runs the same number of iterations (barriers)
+    for (uint64_t base = (uint64_t)blockIdx.x * kMlpWaves; base < ntiles; base += (uint64_t)gridDim.x * kMlpWaves) {
+        uint64_t c0 = (base + wave) * 32;
+        // stage the 32 x 16 input tile (scaled features, BF16)
+        for (int t = lane; t < 32 * 16; t += 64) {
+            int i = t / 16, k = t % 16;
+            uint64_t c = c0 + i;
+            float v = (k < kIn && c < n) ? feat[c * kIn + k] * sc[k] : 0.0f;
+            xs[wave][i][k] = to_bf16(v);
+        }
+        __syncthreads();
+        // layer 1
+        for (int nt = 0; nt < 2; ++nt) {
+            floatx16 acc = {};
+            for (int ks = 0; ks < 2; ++ks) {
+                int k0 = ks * 8 + half * 4;
+                bf16x4 a, bb;
+                for (int e = 0; e < 4; ++e) { a[e] = xs[wave][col][k0 + e]; bb[e] = w1[nt * 32 + col][k0 + e]; }
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc, 0, 0, 0);
+            }
+            for (int e = 0; e < 16; ++e) {
+                int i = (e & 3) + 8 * (e >> 2) + 4 * half;
+                int j = nt * 32 + col;
+                hs[wave][i][j] = to_bf16(silu(acc[e] + b1[j]));
+            }
+        }
+        __syncthreads();
+        // layer 2
+        for (int nt = 0; nt < 2; ++nt) {
+            floatx16 acc = {};
+            for (int ks = 0; ks < 8; ++ks) {
+                int k0 = ks * 8 + half * 4;
+                bf16x4 a, bb;
+                for (int e = 0; e < 4; ++e) { a[e] = hs[wave][col][k0 + e]; bb[e] = w2[nt * 32 + col][k0 + e]; }
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc, 0, 0, 0);
+            }
+            for (int e = 0; e < 16; ++e) {
+                int i = (e & 3) + 8 * (e >> 2) + 4 * half;
+                int j = nt * 32 + col;
+                h2s[wave][i][j] = silu(acc[e] + b2[j]);
+            }
+        }
+        __syncthreads();
+        // layer 3: lanes 0..31 own one contact each, the two halves split K
+        {
+            int i = col;
+            float y[kOut];
+            for (int o = 0; o < kOut; ++o) {
+                float s = 0.0f;
+                for (int k = half * 32; k < half * 32 + 32; ++k) s += w3[o][k] * h2s[wave][i][k];
+                s += __shfl_xor(s, 32, 64);
+                y[o] = s + b3[o];
+            }
+            uint64_t c = c0 + i;
+            if (half == 0 && c < n)
+                for (int o = 0; o < kOut; ++o) out[c * kOut + o] = y[o];
+        }
+        __syncthreads();
+    }
+}
+
+// FP32 reference inference: one thread per contact
+__global__ __launch_bounds__(256) void k_mlp_f32(const float* __restrict__ W, const float* __restrict__ feat,
+                                                 float* __restrict__ out, const uint32_t* d_n, int64_t cap)
+{
+    __shared__ float w[kMlpParams];
+    for (int t = threadIdx.x; t < kMlpParams; t += blockDim.x) w[t] = W[t];
+    __syncthreads();
+    uint64_t n = d_n ? (uint64_t)min((uint64_t)*d_n, (uint64_t)cap) : (uint64_t)cap;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (uint64_t)gridDim.x * blockDim.x) {
+        float x0[kIn], h1[kH];
+        for (int k = 0; k < kIn; ++k) x0[k] = feat[c * kIn + k] * w[oScale + k];
+        for (int o = 0; o < kH; ++o) {
+            float z = w[ob1 + o];
+            for (int k = 0; k < kIn; ++k) z += w[oW1 + o * kIn + k] * x0[k];
+            h1[o] = silu(z);
+        }
+        float y[kOut] = {w[ob3], w[ob3 + 1], w[ob3 + 2]};
+        for (int o = 0; o < kH; ++o) {
+            float z = w[ob2 + o];
+            for (int k = 0; k < kH; ++k) z += w[oW2 + o * kH + k] * h1[k];
+            float h = silu(z);
+            for (int q = 0; q < kOut; ++q) y[q] += w[oW3 + q * kH + o] * h;
+        }
+        for (int q = 0; q < kOut; ++q) out[c * kOut + q] = y[q];
+    }
+}
+
+void launch_mlp_infer(const float* W, const float* feat, float* out, const uint32_t* d_n, int64_t cap, bool bf16,
+                      hipStream_t s)
+{
+    if (cap <= 0) return;
+    if (bf16) {
+        int64_t tiles = (cap + 31) / 32;
+        int grid = (int)std::min<int64_t>((tiles + kMlpWaves - 1) / kMlpWaves, 2048);
+        hipLaunchKernelGGL(k_mlp_bf16, dim3(grid), dim3(64 * kMlpWaves), 0, s, W, feat, out, d_n, cap);
+    } else {
+        int grid = (int)std::min<int64_t>((cap + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_mlp_f32, dim3(grid), dim3(256), 0, s, W, feat, out, d_n, cap);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// lambda^0 of the learned start (colour order): world impulse from the network
+// output in the contact frame, projected onto {ln >= lo, |lt| <= mu |ln|}
+// ---------------------------------------------------------------------------
+__global__ void k_learned_lam(DevBuffers b, StepParams p, int64_t cap)
+{
+    uint32_t nc = b.cnt->n_raw < (uint64_t)cap ? b.cnt->n_raw : (uint32_t)cap;
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc || b.cnt->overflow) return;
+    float4 f1 = b.frm1[c], f2 = b.frm2[c], a = b.r0[c], q = b.r2[c];
+    float y0 = b.mlp_out[3 * (size_t)c], y1 = b.mlp_out[3 * (size_t)c + 1], y2 = b.mlp_out[3 * (size_t)c + 2];
+    float ls = f1.w;
+    float ln = y0 * ls;
+    float t0 = (y1 * f1.x + y2 * f2.x) * ls, t1 = (y1 * f1.y + y2 * f2.y) * ls, t2 = (y1 * f1.z + y2 * f2.z) * ls;
+    if (!(isfinite(ln) && isfinite(t0) && isfinite(t1) && isfinite(t2))) {
+        atomicOr(&b.cnt->learn_flags, 1u);
+        ln = 0.f; t0 = t1 = t2 = 0.f;
+    }
+    ln = fmaxf(ln, q.y);
+    float tn = a.x * t0 + a.y * t1 + a.z * t2;
+    t0 -= tn * a.x; t1 -= tn * a.y; t2 -= tn * a.z;
+    float lim = p.mu * fabsf(ln);
+    float m2 = t0 * t0 + t1 * t1 + t2 * t2;
+    if (m2 > lim * lim) {
+        float sc = m2 > 0.f ? lim * rsqrtf(m2) : 0.f;
+        t0 *= sc; t1 *= sc; t2 *= sc;
+    }
+    b.lamL[c] = make_float4(ln, t0, t1, t2);
+}
+
+void launch_learned_lam(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_learned_lam, dim3((unsigned)((z.C + 255) / 256)), dim3(256), 0, s, b, p, z.C);
+}
+
+// ---------------------------------------------------------------------------
+// training: per block of 64 samples, forward + backward in FP32, gradient
+// partials of the block written to part[block][kNP], loss to part[.][kNP]
+// ---------------------------------------------------------------------------
+constexpr int kTrainB = 64;
+
+__global__ __launch_bounds__(kTrainB) void k_mlp_train(const float* __restrict__ W, const float* __restrict__ feat,
+                                                       const float* __restrict__ label, int64_t B, float* __restrict__ part)
+{
+    __shared__ float w[kMlpParams];
+    __shared__ float x0s[kTrainB][kIn];
+    __shared__ float h1s[kTrainB][kH + 1];
+    __shared__ float h2s[kTrainB][kH + 1];
+    __shared__ float g1s[kTrainB][kH + 1];
+    __shared__ float g2s[kTrainB][kH + 1];
+    __shared__ float gys[kTrainB][kOut];
+    __shared__ float lred[kTrainB];
+    const int t = threadIdx.x;
+    for (int k = t; k < kMlpParams; k += blockDim.x) w[k] = W[k];
+    __syncthreads();
+    int64_t s = (int64_t)blockIdx.x * kTrainB + t;
+    bool act = s < B;
+    float inv_b = 1.0f / (float)B;
+    float loss = 0.0f;
+    // forward
+    for (int k = 0; k < kIn; ++k) x0s[t][k] = act ? feat[s * kIn + k] * w[oScale + k] : 0.0f;
+    for (int o = 0; o < kH; ++o) {
+        float z = w[ob1 + o];
+        for (int k = 0; k < kIn; ++k) z += w[oW1 + o * kIn + k] * x0s[t][k];
+        g1s[t][o] = z;          // z1 kept for the backward pass
+        h1s[t][o] = silu(z);
+    }
+    float y[kOut] = {w[ob3], w[ob3 + 1], w[ob3 + 2]};
+    for (int o = 0; o < kH; ++o) {
+        float z = w[ob2 + o];
+        for (int k = 0; k < kH; ++k) z += w[oW2 + o * kH + k] * h1s[t][k];
+        g2s[t][o] = z;          // z2
+        float h = silu(z);
+        h2s[t][o] = h;
+        for (int q = 0; q < kOut; ++q) y[q] += w[oW3 + q * kH + o] * h;
+    }
+    for (int q = 0; q < kOut; ++q) {
+        float e = act ? y[q] - label[s * kOut + q] : 0.0f;
+        loss += 0.5f * e * e;
+        gys[t][q] = e * inv_b;
+    }
+    // backward to gz2 (in place of z2), then gz1 (in place of z1)
+    for (int o = 0; o < kH; ++o) {
+        float gh = 0.0f;
+        for (int q = 0; q < kOut; ++q) gh += w[oW3 + q * kH + o] * gys[t][q];
+        g2s[t][o] = gh * dsilu(g2s[t][o]);
+    }
+    for (int i = 0; i < kH; ++i) {
+        float gh = 0.0f;
+        for (int o = 0; o < kH; ++o) gh += w[oW2 + o * kH + i] * g2s[t][o];
+        g1s[t][i] = gh * dsilu(g1s[t][i]);
+    }
+    lred[t] = act ? loss * inv_b : 0.0f;
+    __syncthreads();
+    // gradient partials of this block: thread t handles parameters t, t + 64, ...
+    float* out = part + (size_t)blockIdx.x * (kNP + 1);
+    for (int pidx = t; pidx < kNP; pidx += blockDim.x) {
+        float g = 0.0f;
+        if (pidx < ob1) {
+            int o = pidx / kIn, k = pidx % kIn;
+            for (int q = 0; q < kTrainB; ++q) g += g1s[q][o] * x0s[q][k];
+        } else if (pidx < oW2) {
+            int o = pidx - ob1;
+            for (int q = 0; q < kTrainB; ++q) g += g1s[q][o];
+        } else if (pidx < ob2) {
+            int o = (pidx - oW2) / kH, k = (pidx - oW2) % kH;
+            for (int q = 0; q < kTrainB; ++q) g += g2s[q][o] * h1s[q][k];
+        } else if (pidx < oW3) {
+            int o = pidx - ob2;
+            for (int q = 0; q < kTrainB; ++q) g += g2s[q][o];
+        } else if (pidx < ob3) {
+            int o = (pidx - oW3) / kH, k = (pidx - oW3) % kH;
+            for (int q = 0; q < kTrainB; ++q) g += gys[q][o] * h2s[q][k];
+        } else {
+            int o = pidx - ob3;
+            for (int q = 0; q < kTrainB; ++q) g += gys[q][o];
+        }
+        out[pidx] = g;
+    }
+    if (t == 0) {
+        float l = 0.0f;
+        for (int q = 0; q < kTrainB; ++q) l += lred[q];
+        out[kNP] = l;
+    }
+}
+
+__global__ void k_grad_reduce(const float* __restrict__ part, int nblocks, float* __restrict__ grad, float* loss)
+{
+    int pidx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pidx > kNP) return;
+    float g = 0.0f;
+    for (int b = 0; b < nblocks; ++b) g += part[(size_t)b * (kNP + 1) + pidx];
+    if (pidx < kNP) grad[pidx] = g;
+    else if (loss) *loss = g;
+}
+
+__global__ void k_adam(float* W, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    float gk = g[k];
+    float mk = b1 * m[k] + (1.0f - b1) * gk;
+    float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    W[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+int64_t mlp_grad_scratch(int64_t B) { return ((B + kTrainB - 1) / kTrainB) * (int64_t)(kNP + 1); }
+int mlp_trainable() { return kNP; }
+
+void launch_mlp_grad(const float* W, const float* feat, const float* label, int64_t B, float* grad, float* loss,
+                     float* scratch, hipStream_t s)
+{
+    int nb = (int)((B + kTrainB - 1) / kTrainB);
+    hipLaunchKernelGGL(k_mlp_train, dim3(nb), dim3(kTrainB), 0, s, W, feat, label, B, scratch);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((kNP + 1 + 255) / 256), dim3(256), 0, s, scratch, nb, grad, loss);
+}
+
+void launch_adam(float* W, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps, int t,
+                 hipStream_t s)
+{
+    float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, W, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+}  // namespace trk

@@ -22,7 +22,9 @@ SHAPE = {"plane": 0, "box": 1, "hfield": 2}
 MLP_PARAMS = 64 * 12 + 64 + 64 * 64 + 64 + 3 * 64 + 3 + 12
 EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodies", "step",
            "get_contact_forces", "get_aggregates", "get_last_error", "get_contacts", "get_particles",
-           "set_particles", "set_mlp_weights", "get_phase_times")
+           "set_particles", "set_mlp_weights", "get_phase_times", "set_learned_precision", "get_learn_samples",
+           "mlp_forward", "mlp_grad_scratch_floats", "mlp_loss_grad", "mlp_adam_step")
+MLP_TRAINABLE = MLP_PARAMS - 12
 
 
 class TerrainError(RuntimeError):
@@ -99,9 +101,17 @@ def lib():
         L.set_particles.argtypes = [P, C.c_int32, dp, dp, dp]
         L.set_mlp_weights.argtypes = [P, C.POINTER(C.c_float), C.c_int64]
         L.get_phase_times.argtypes = [P, C.POINTER(C.c_float), C.c_int32]
+        L.set_learned_precision.argtypes = [P, C.c_int32]
+        fp = C.POINTER(C.c_float)
+        L.get_learn_samples.argtypes = [P, C.c_int32, C.c_int64, fp, fp, C.POINTER(C.c_int64)]
+        L.mlp_forward.argtypes = [P, P, C.c_int64, P, C.c_int32, P]
+        L.mlp_loss_grad.argtypes = [P, P, P, C.c_int64, P, P, P, C.c_int64, P]
+        L.mlp_adam_step.argtypes = [P, P, P, P, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32, P]
         for name in EXPORTS:
             if name != "get_last_error":
                 getattr(L, name).restype = C.c_int
+        L.mlp_grad_scratch_floats.argtypes = [C.c_int64]
+        L.mlp_grad_scratch_floats.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -296,10 +306,48 @@ class Scene:
         self._check(lib().set_mlp_weights(self.h, flat.ctypes.data_as(C.POINTER(C.c_float)), len(flat)),
                     "set_mlp_weights")
 
+    def set_learned_precision(self, bf16=True):
+        self._check(lib().set_learned_precision(self.h, 1 if bf16 else 0), "set_learned_precision")
+
+    def get_learn_samples(self, env):
+        n = C.c_int64()
+        self._check(lib().get_learn_samples(self.h, env, 0, None, None, C.byref(n)), "get_learn_samples")
+        m = n.value
+        feat = np.zeros((max(m, 1), 12), dtype=np.float32)
+        lab = np.zeros((max(m, 1), 3), dtype=np.float32)
+        fp = C.POINTER(C.c_float)
+        self._check(lib().get_learn_samples(self.h, env, m, feat.ctypes.data_as(fp), lab.ctypes.data_as(fp),
+                                            C.byref(n)), "get_learn_samples")
+        return feat[:m], lab[:m]
+
     def get_phase_times(self):
         t = (C.c_float * 5)()
         self._check(lib().get_phase_times(self.h, t, 5), "get_phase_times")
         return dict(detect=t[0], rows=t[1], pgs=t[2], finish=t[3], step=t[4])
+
+
+def _check_rc(rc, what):
+    if rc != TR_OK:
+        raise TerrainError(rc, what)
+
+
+def mlp_forward(weights_ptr, feat_ptr, B, out_ptr, bf16=True, stream=None):
+    """Device-pointer network forward (pointers as ints, e.g. tensor.data_ptr())."""
+    _check_rc(lib().mlp_forward(weights_ptr, feat_ptr, B, out_ptr, 1 if bf16 else 0, stream), "mlp_forward")
+
+
+def mlp_grad_scratch_floats(B):
+    return lib().mlp_grad_scratch_floats(B)
+
+
+def mlp_loss_grad(weights_ptr, feat_ptr, label_ptr, B, grad_ptr, loss_ptr, scratch_ptr, scratch_floats, stream=None):
+    _check_rc(lib().mlp_loss_grad(weights_ptr, feat_ptr, label_ptr, B, grad_ptr, loss_ptr, scratch_ptr,
+                                  scratch_floats, stream), "mlp_loss_grad")
+
+
+def mlp_adam_step(weights_ptr, grad_ptr, m_ptr, v_ptr, lr, t, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check_rc(lib().mlp_adam_step(weights_ptr, grad_ptr, m_ptr, v_ptr, lr, beta1, beta2, eps, t, stream),
+              "mlp_adam_step")
 
 
 def scene_from_specs(specs, cap_particles=None, cap_contacts=None, **kw):
