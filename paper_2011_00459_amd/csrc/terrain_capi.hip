@@ -141,6 +141,24 @@ int rebuild_tables(tr_scene* s)
     int n_zones = 0;
     int64_t slot = 0;
     s->zone_slots.assign(E, {});
+    // PGS groups: one env per group when there are at most kGroups envs,
+    // else largest-first onto the least loaded group
+    std::vector<int> grp(E, 0);
+    if (E <= kGroups) {
+        for (int e = 0; e < E; ++e) grp[e] = e;
+    } else {
+        std::vector<int> order(E);
+        for (int e = 0; e < E; ++e) order[e] = e;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return s->envs[a].n > s->envs[c].n; });
+        int64_t load[kGroups] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int e : order) {
+            int best = 0;
+            for (int g = 1; g < kGroups; ++g)
+                if (load[g] < load[best]) best = g;
+            grp[e] = best;
+            load[best] += std::max<int64_t>(s->envs[e].n, 1);
+        }
+    }
     for (int e = 0; e < E; ++e) {
         EnvHost& H = s->envs[e];
         EnvDev& D = ed[e];
@@ -158,6 +176,7 @@ int rebuild_tables(tr_scene* s)
         D.inv_h = (float)(1.0 / h);
         D.cell_base = (uint32_t)NC;
         D.col_base = (int)NCOL;
+        D.group = grp[e];
         NCOL += (int64_t)D.dims[0] * D.dims[1];
         NC += (int64_t)1 << (D.bits[0] + D.bits[1] + D.bits[2]);
         if (NC >= ((int64_t)1 << 31)) return fail(s, TR_E_CAPACITY, "too many cells");
@@ -225,7 +244,7 @@ int rebuild_tables(tr_scene* s)
         if (!alloc_n(s, s->b.cell_count, NC) || !alloc_n(s, s->b.cell_start, NC + 1) || !alloc_n(s, s->b.cell_fill, NC))
             return fail(s, TR_E_NOMEM, "cell arrays");
         int64_t words = std::max({scan_tmp_words(NC), scan_tmp_words(s->z.NID), scan_tmp_words(s->z.P),
-                                  scan_tmp_words((int64_t)kMaxColours * s->z.NB)});
+                                  scan_tmp_words((int64_t)kBuckets * s->z.NB)});
         if (!alloc_n(s, s->b.scan_tmp, words)) return fail(s, TR_E_NOMEM, "scan scratch");
         s->cells_alloc = NC + 1;
     }
@@ -356,16 +375,15 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
     z.NID = z.P;
     z.NB = (z.C + 255) / 256;
     z.pgs_block = 256;
-    // PGS grid: few blocks keep the colour barrier cheap (about 1.5 us at 64
-    // blocks against 18 us at 1024 on MI355X); large scenes want more CUs
+    // PGS grid: kGroups XCD groups of gx blocks (one per CU of the XCD by
+    // default); the colour barrier stays inside an XCD's L2
     {
-        int64_t per_env = d->cap_contacts;
-        int64_t total = z.C;
-        int want = total >= 2000000 ? 256 : (total >= 400000 ? 128 : 64);
-        (void)per_env;
-        const char* ev = getenv("TR_PGS_GRID");
-        if (ev && atoi(ev) > 0) want = atoi(ev);
-        z.pgs_grid = std::max(1, std::min(pgs_resident_blocks(256), want));
+        int gx = 32;
+        const char* ev = getenv("TR_PGS_GX");
+        if (ev && atoi(ev) > 0) gx = atoi(ev);
+        gx = std::max(1, std::min(gx, pgs_resident_blocks(512) / kGroups));
+        z.pgs_block = 512;
+        z.pgs_grid = kGroups * gx;
     }
     z.col_grid = std::min(colour_resident_blocks(), 2048);
     DevBuffers& b = s->b;
@@ -378,8 +396,8 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
               alloc_n(s, b.id_count, z.NID) && alloc_n(s, b.id_start, z.NID + 1) && alloc_n(s, b.id_fill, z.NID) &&
               alloc_n(s, b.pid_start, z.NID + 1) && alloc_n(s, b.inc_count, z.P) &&
               alloc_n(s, b.inc_start, z.P + 1) && alloc_n(s, b.inc_fill, z.P) && alloc_n(s, b.inc, 2 * z.C) &&
-              alloc_n(s, b.colour, z.C) && alloc_n(s, b.col_hist, (int64_t)kMaxColours * z.NB) &&
-              alloc_n(s, b.col_start, (int64_t)kMaxColours * z.NB + 1) && alloc_n(s, b.cpos, z.C) &&
+              alloc_n(s, b.colour, z.C) && alloc_n(s, b.col_hist, (int64_t)kBuckets * z.NB) &&
+              alloc_n(s, b.col_start, (int64_t)kBuckets * z.NB + 1) && alloc_n(s, b.cpos, z.C) &&
               alloc_n(s, b.r0, z.C) && alloc_n(s, b.r1, z.C) && alloc_n(s, b.r2, z.C) && alloc_n(s, b.rk, z.C) &&
               alloc_n(s, b.lam, z.C) && alloc_n(s, b.lam0, z.C) &&
               alloc_n(s, b.block_part, (int64_t)4 * z.pgs_grid) && alloc_n(s, b.envs, d->n_envs) &&
@@ -564,16 +582,16 @@ int step(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
             launch_mlp_infer(s->b.mlp, s->b.feat, s->b.mlp_out, &s->b.cnt->n_raw, s->z.C, s->mlp_bf16, st);
             launch_learned_lam(s->b, s->p, s->z, st);
             launch_vel_copy(s->b, s->p, true, st);
-            launch_select_start(s->b, s->z, 1, st);
+            launch_select_start(s->b, s->p, s->z, 1, st);
             launch_warm_apply(s->b, s->p, s->z, st);
             launch_pgs(s->b, s->p, s->z, st, 1, 1);
             launch_vel_copy(s->b, s->p, false, st);
-            launch_select_start(s->b, s->z, 0, st);
+            launch_select_start(s->b, s->p, s->z, 0, st);
             launch_warm_apply(s->b, s->p, s->z, st);
             launch_pgs(s->b, s->p, s->z, st, 1, 2);
             launch_choose_start(s->b, st);
             launch_vel_copy(s->b, s->p, false, st);
-            launch_select_start(s->b, s->z, 2, st);
+            launch_select_start(s->b, s->p, s->z, 2, st);
         }
         launch_warm_apply(s->b, s->p, s->z, st);
         (void)hipEventRecord(s->ev[2], st);
@@ -599,11 +617,12 @@ int step(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
             tr_step_stats& o = stats[e2];
             o.contacts = es[e2].contacts;
             o.pair_contacts = es[e2].pairs;
+            const GroupStats& G = c.gs[s->env_host[e2].group];
             o.colours = (int32_t)c.n_colours;
-            o.sweeps = (int32_t)c.sweeps;
-            o.residual = c.resid;
-            o.residual_first = c.resid_first;
-            o.fallback_used = (int32_t)c.fallback;
+            o.sweeps = (int32_t)G.sweeps;
+            o.residual = G.resid;
+            o.residual_first = G.resid_first;
+            o.fallback_used = s->p.warm == TR_WARM_LEARNED && s->mlp_loaded ? (int32_t)G.fallback : 0;
             o.overflow = (int32_t)c.overflow;
         }
         if (c.overflow) {

@@ -19,6 +19,8 @@
 namespace trk {
 
 constexpr int kMaxColours = 64;     // colours of the contact schedule (64-bit masks)
+constexpr int kGroups = 8;          // PGS groups: one per XCD of the MI355X (block b runs on XCD b % 8)
+constexpr int kBuckets = kMaxColours * kGroups;  // (colour, group) buckets of the PGS order
 constexpr int kMaxHits = 32;        // contacts one particle may emit per step
 constexpr int kMaxZonesPerEnv = 4;  // bodies with an active zone per environment
 constexpr int kZoneMoments = 20;    // M, mx(3), mv(3), mxx(6), m x*v(3), sum Is(1), sum Is w(3)
@@ -48,6 +50,7 @@ struct EnvDev {
     int n;                        // particles of the env
     int slot_begin;               // first slot of the env in sorted order
     int col_base;                 // first depth column of the env (dims[0] x dims[1] columns)
+    int group;                    // PGS group (XCD) that solves this env
     int zone_count;
     int zone_body[kMaxZonesPerEnv];  // global body index of each zone
     int zone_slot[kMaxZonesPerEnv];  // global zone index of each zone
@@ -111,20 +114,29 @@ struct StepParams {
     double r_ref;       // nominal radius of the features
 };
 
+// per PGS group (64 B)
+struct GroupStats {
+    uint32_t sweeps;
+    uint32_t use_learned;  // 1 when the learned start won the first-sweep trial
+    uint32_t fallback;
+    uint32_t pad;
+    double resid;
+    double resid_first;
+    double r1_trial[2];    // first-sweep residual from the learned / previous start
+    double pad2[2];
+};
+
 struct Counters {
     uint32_t n_raw;        // contacts found by detection (may exceed capacity)
     uint32_t n_pairs;
     uint32_t overflow;     // kOvf* / kFail* bits, sticky within a step
     uint32_t n_colours;
-    uint32_t sweeps;
-    uint32_t fallback;
-    uint32_t barrier_count;
-    uint32_t barrier_gen;
-    double resid;
-    double resid_first;
-    uint32_t learn_flags;  // bit 0: non-finite network output
-    uint32_t use_learned;  // 1 when the learned start won the first-sweep trial
-    double r1_trial[2];    // first-sweep residual from the learned / previous start
+    uint32_t learn_flags;  // bit g: non-finite network output in group g
+    uint32_t xcd_bad;      // a PGS block ran off its expected XCD
+    uint32_t bar_global;   // counter of the launch's global barrier
+    uint32_t pad[9];
+    uint32_t bar[kGroups][16];  // per-group barrier counters, one cache line each
+    GroupStats gs[kGroups];
 };
 
 struct EnvStats {
@@ -149,12 +161,12 @@ struct DevBuffers {
     uint32_t *id_count, *id_start, *id_fill, *pid_start;  // [NID], [NID+1], [NID], [NID+1]
     uint32_t *inc_count, *inc_start, *inc_fill, *inc;     // [P], [P+1], [P], [2C]
     int* colour;                                    // [C]
-    uint32_t *col_hist, *col_start;                 // [64*NB], [64*NB+1]
+    uint32_t *col_hist, *col_start;                 // [kBuckets*NB], [kBuckets*NB+1]
     uint32_t* cpos;                                 // canonical -> colour position
     float4 *r0, *r1, *r2, *rk, *lam, *lam0;         // colour order
     // reductions
     double* resid_acc;    // [max_sweeps * 2] per-sweep numerator / denominator... (block partials)
-    double* block_part;   // [grid * 2]
+    double* block_part;   // [2 parities][grid][2]
     double* force_part;   // [bodies * kForceChunks * 6]
     double* body_ft;      // [bodies * 6]
     double* zone_part;    // [chunks * kMaxZonesPerEnv * kZoneMoments]
@@ -187,8 +199,8 @@ struct Sizes {
     int64_t NC;     // cells (all envs)
     int64_t NB;     // blocks of 256 over C (colour bucketing)
     int n_zone_chunks;
-    int pgs_grid;   // resident blocks of the persistent PGS kernel
-    int pgs_block;
+    int pgs_grid;   // blocks of the persistent PGS kernel (kGroups x blocks per group)
+    int pgs_block;  // threads per PGS block
     int col_grid;   // resident blocks of the colouring kernel
     int64_t NCOL;   // depth columns (all envs)
 };
@@ -211,7 +223,7 @@ void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStr
                 int slot = 0);
 void launch_depth(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_vel_copy(const DevBuffers& b, const StepParams& p, bool backup, hipStream_t s);
-void launch_select_start(const DevBuffers& b, const Sizes& z, int mode, hipStream_t s);
+void launch_select_start(const DevBuffers& b, const StepParams& p, const Sizes& z, int mode, hipStream_t s);
 void launch_choose_start(const DevBuffers& b, hipStream_t s);
 void launch_learn_samples(const DevBuffers& b, int64_t beg, int64_t n, float* feat, float* label, hipStream_t s);
 // terrain_mlp.hip

@@ -300,12 +300,9 @@ __device__ inline bool shape_touch(const ShapeDev& S, const float* hf, double x,
 __global__ void k_step_begin(DevBuffers b, StepParams p)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) {
-        Counters* c = b.cnt;
-        c->n_raw = 0; c->n_pairs = 0; c->overflow = 0; c->n_colours = 0;
-        c->sweeps = 0; c->fallback = 0; c->barrier_count = 0; c->barrier_gen = 0;
-        c->resid = 0.0; c->resid_first = 0.0;
-        c->learn_flags = 0; c->use_learned = 0; c->r1_trial[0] = 0.0; c->r1_trial[1] = 0.0;
+    {
+        uint32_t* w = reinterpret_cast<uint32_t*>(b.cnt);
+        for (int k = t; k < (int)(sizeof(Counters) / 4); k += gridDim.x * blockDim.x) w[k] = 0u;
     }
     if (t < p.n_envs) { b.env_stats[t].contacts = 0; b.env_stats[t].pairs = 0; }
     if (t < p.n_shapes) {
@@ -324,7 +321,7 @@ __global__ void k_step_begin(DevBuffers b, StepParams p)
 
 void launch_step_begin(const DevBuffers& b, const StepParams& p, hipStream_t s)
 {
-    int n = std::max(1, std::max(p.n_shapes, p.n_envs));
+    int n = std::max((int)(sizeof(Counters) / 4), std::max(p.n_shapes, p.n_envs));
     hipLaunchKernelGGL(k_step_begin, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, s, b, p);
 }
 
@@ -648,37 +645,46 @@ __global__ __launch_bounds__(kBlk) void k_colour(DevBuffers b, int64_t cap, int 
     if (left) atomicOr(&b.cnt->overflow, kFailColouring);
 }
 
-// stable bucketing of the canonical list by colour
-__global__ void k_col_hist(DevBuffers b, int64_t cap, int64_t NB)
+// stable bucketing of the canonical list by (colour, PGS group)
+__device__ inline int contact_group(const DevBuffers& b, unsigned long long key, uint32_t id_cap)
 {
-    __shared__ uint32_t h[kMaxColours];
+    return b.envs[env_of((int)(key >> 32), id_cap)].group;
+}
+
+__global__ void k_col_hist(DevBuffers b, int64_t cap, int64_t NB, uint32_t id_cap)
+{
+    __shared__ uint32_t h[kBuckets];
     uint32_t nc = n_contacts(b, cap);
-    if (threadIdx.x < kMaxColours) h[threadIdx.x] = 0;
+    for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) h[k] = 0;
     __syncthreads();
     uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < nc) {
         int col = b.colour[c];
-        if (col >= 0 && col < kMaxColours) atomicAdd(&h[col], 1u);
+        if (col >= 0 && col < kMaxColours) atomicAdd(&h[col * kGroups + contact_group(b, b.ckey[c], id_cap)], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < kMaxColours) b.col_hist[(int64_t)threadIdx.x * NB + blockIdx.x] = h[threadIdx.x];
+    for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) b.col_hist[(int64_t)k * NB + blockIdx.x] = h[k];
 }
 
-__global__ void k_col_scatter(DevBuffers b, int64_t cap, int64_t NB)
+__global__ void k_col_scatter(DevBuffers b, int64_t cap, int64_t NB, uint32_t id_cap)
 {
-    __shared__ int col[kBlk];
+    __shared__ int bk[kBlk];
     uint32_t nc = n_contacts(b, cap);
     uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    int my = c < nc ? b.colour[c] : -1;
-    col[threadIdx.x] = my;
+    int my = -1;
+    if (c < nc) {
+        int col = b.colour[c];
+        if (col >= 0 && col < kMaxColours) my = col * kGroups + contact_group(b, b.ckey[c], id_cap);
+    }
+    bk[threadIdx.x] = my;
     __syncthreads();
     if (c >= nc) return;
-    if (my < 0 || my >= kMaxColours) {  // failed colouring: the step is abandoned
+    if (my < 0) {  // failed colouring: the step is abandoned
         b.cpos[c] = c;
         return;
     }
     uint32_t rank = 0;
-    for (int t = 0; t < (int)threadIdx.x; ++t) rank += col[t] == my;
+    for (int t = 0; t < (int)threadIdx.x; ++t) rank += bk[t] == my;
     b.cpos[c] = b.col_start[(int64_t)my * NB + blockIdx.x] + rank;
 }
 
@@ -686,10 +692,9 @@ void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hip
 {
     launch_fill_u32((uint32_t*)b.colour, 0xFFFFFFFFu, z.C, s);
     hipLaunchKernelGGL(k_colour, dim3(z.col_grid), dim3(kBlk), 0, s, b, z.C, 100000);
-    hipLaunchKernelGGL(k_col_hist, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB);
-    launch_scan_u32(b.col_hist, b.col_start, (int64_t)kMaxColours * z.NB, b.scan_tmp, s);
-    hipLaunchKernelGGL(k_col_scatter, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB);
-    (void)p;
+    hipLaunchKernelGGL(k_col_hist, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB, p.id_cap);
+    launch_scan_u32(b.col_hist, b.col_start, (int64_t)kBuckets * z.NB, b.scan_tmp, s);
+    hipLaunchKernelGGL(k_col_scatter, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB, p.id_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -899,78 +904,85 @@ void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z,
 // ---------------------------------------------------------------------------
 // A9: persistent projected Gauss-Seidel.  Sweeps x colours; inside a colour
 // no two contacts share a dynamic particle, so every contact updates its two
-// bodies without atomics.  Contact c of a colour is always handled by the same
-// thread, so its rows (read-only) and its impulses (thread-owned) go through
-// the ordinary caches; the bodies, shared by blocks on all XCDs, are read and
-// written with device-coherent (sc1) 128-bit buffer accesses, which lets the
-// colour barrier be a plain counter without L2 write-back or invalidation.
-// The residual R_k = ||d lambda||_D / ||lambda||_D of each sweep is reduced per
-// block in fixed order and combined identically by every block, which then
-// all take the same stopping decision.
+// bodies without atomics.
+//
+// Envs are split into kGroups independent groups (block b serves group b % 8,
+// which is also its XCD), each with its own colour barrier counter, so the
+// barrier traffic is spread over eight counters.  Bodies are read and written
+// with device-coherent (sc1) 128-bit accesses: measured on MI355X, L2-scoped
+// (sc0) loads return stale data across CUs.  Contact c of a colour is always
+// handled by the same thread, so its rows (read-only) and impulses
+// (thread-owned) use the ordinary caches, and the first contact of the next
+// colour is fetched while the block waits at the barrier.  The residual R_k = ||d lambda||_D / ||lambda||_D of each sweep
+// is reduced per block in fixed order and combined identically by every block
+// of the group, which then all take the same stopping decision.
 // ---------------------------------------------------------------------------
+constexpr int kPgsBlk = 512;
 constexpr int kCoherent = 16;  // cache-policy bits of a device-scope (sc1) access
 
 __device__ inline __amdgpu_buffer_rsrc_t raw_rsrc(const void* p)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7fffffff, 0x00020000);
 }
-__device__ inline float4 ld_coherent(__amdgpu_buffer_rsrc_t r, int idx)
+template <int AUX>
+__device__ inline float4 ld_body(__amdgpu_buffer_rsrc_t r, int idx)
 {
-    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 16, 0, kCoherent));
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 16, 0, AUX));
 }
-__device__ inline void st_coherent(__amdgpu_buffer_rsrc_t r, int idx, float4 v)
+template <int AUX>
+__device__ inline void st_body(__amdgpu_buffer_rsrc_t r, int idx, float4 v)
 {
     typedef unsigned u4 __attribute__((ext_vector_type(4)));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, idx * 16, 0, kCoherent);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, idx * 16, 0, AUX);
 }
 
-// Counter barrier: the t-th barrier of a launch completes when the counter
-// (zeroed before the launch) reaches (t + 1) * nblocks.  Every thread has
-// waited for its own stores before the block arrives.  Bounded wait; a failed
-// barrier makes every block leave.
-__device__ inline bool grid_barrier(Counters* cnt, unsigned nblocks, unsigned& t, int& sh_ok)
+// Bounded wait for a barrier counter to reach target; false on timeout or
+// when another block has reported a failed barrier.
+__device__ inline bool wait_counter(Counters* cnt, uint32_t* counter, unsigned target)
 {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        bool ok = true;
-        unsigned target = (t + 1) * nblocks;
-        __hip_atomic_fetch_add(&cnt->barrier_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        long spins = 0;
-        while (__hip_atomic_load(&cnt->barrier_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if ((++spins & 1023) == 0 &&
-                (__hip_atomic_load(&cnt->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFailBarrier)) {
-                ok = false;
-                break;
-            }
-            if (spins > kBarrierSpins) { ok = false; break; }
+    long spins = 0;
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 1023) == 0 &&
+            (__hip_atomic_load(&cnt->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFailBarrier))
+            return false;
+        if (spins > kBarrierSpins) {
+            atomicOr(&cnt->overflow, kFailBarrier);
+            return false;
         }
-        if (!ok) atomicOr(&cnt->overflow, kFailBarrier);
-        sh_ok = ok ? 1 : 0;
     }
-    ++t;
-    __syncthreads();
-    return sh_ok != 0;
+    return true;
 }
 
-__device__ inline void pgs_contact(const DevBuffers& b, __amdgpu_buffer_rsrc_t rv, __amdgpu_buffer_rsrc_t rw, uint32_t c,
-                                   float mu, float gdt, float& num, float& den)
+struct RowRegs {
+    float4 a, r1, q, L, k;
+};
+
+__device__ inline RowRegs load_rows(const DevBuffers& b, uint32_t c)
 {
-    float4 a = b.r0[c];
-    float4 r1 = b.r1[c];
-    float4 q = b.r2[c];
-    float4 L = b.lam[c];
+    RowRegs R;
+    R.a = b.r0[c];
+    R.r1 = b.r1[c];
+    R.q = b.r2[c];
+    R.L = b.lam[c];
+    R.k = b.rk[c];
+    return R;
+}
+
+template <int AUX>
+__device__ inline void pgs_contact(const DevBuffers& b, __amdgpu_buffer_rsrc_t rv, __amdgpu_buffer_rsrc_t rw, uint32_t c,
+                                   const RowRegs& R, float mu, float gdt, float& num, float& den)
+{
+    float4 a = R.a, r1 = R.r1, q = R.q, L = R.L;
     int ia = __float_as_int(q.z), ib = __float_as_int(q.w);
     bool pair = ia >= 0;
-    float4 vb = ld_coherent(rv, ib), wb = ld_coherent(rw, ib);
+    float4 vb = ld_body<AUX>(rv, ib), wb = ld_body<AUX>(rw, ib);
     float4 va, wa;
     if (pair) {
-        va = ld_coherent(rv, ia);
-        wa = ld_coherent(rw, ia);
+        va = ld_body<AUX>(rv, ia);
+        wa = ld_body<AUX>(rw, ia);
     } else {
-        float4 k4 = b.rk[c];
-        va = make_float4(k4.x, k4.y, k4.z, 0.f);
+        va = make_float4(R.k.x, R.k.y, R.k.z, 0.f);
         wa = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     float nx = a.x, ny = a.y, nz = a.z, l1 = a.w;
@@ -1002,13 +1014,13 @@ __device__ inline void pgs_contact(const DevBuffers& b, __amdgpu_buffer_rsrc_t r
     float cx = ny * dz - nz * dy, cy = nz * dx - nx * dz, cz = nx * dy - ny * dx;  // n x d
     vb.x += dx * vb.w; vb.y += dy * vb.w; vb.z += dz * vb.w;
     wb.x -= l2 * wb.w * cx; wb.y -= l2 * wb.w * cy; wb.z -= l2 * wb.w * cz;
-    st_coherent(rv, ib, vb);
-    st_coherent(rw, ib, wb);
+    st_body<AUX>(rv, ib, vb);
+    st_body<AUX>(rw, ib, wb);
     if (pair) {
         va.x -= dx * va.w; va.y -= dy * va.w; va.z -= dz * va.w;
         wa.x -= l1 * wa.w * cx; wa.y -= l1 * wa.w * cy; wa.z -= l1 * wa.w * cz;
-        st_coherent(rv, ia, va);
-        st_coherent(rw, ia, wa);
+        st_body<AUX>(rv, ia, va);
+        st_body<AUX>(rw, ia, wa);
     }
     b.lam[c] = make_float4(ln, tx, ty, tz);
     float Dn = 1.0f / iDn, Dt = 1.0f / iDt;
@@ -1016,30 +1028,54 @@ __device__ inline void pgs_contact(const DevBuffers& b, __amdgpu_buffer_rsrc_t r
     den += Dn * ln * ln + Dt * (tx * tx + ty * ty + tz * tz);
 }
 
-__global__ void k_pgs_reset(Counters* cnt) { cnt->barrier_count = 0; }
-
-__global__ __launch_bounds__(kBlk) void k_pgs(DevBuffers b, StepParams p, int64_t cap, int64_t NB, int sweeps_cap,
-                                              int slot)
+__global__ void k_pgs_reset(Counters* cnt)
 {
-    __shared__ double red[2][kBlk / 64];
-    __shared__ int stop_flag;
-    __shared__ int bar_ok;
-    if (b.cnt->overflow) return;  // uniform: written by earlier kernels only
-    uint32_t ncol = b.cnt->n_colours;
-    unsigned G = gridDim.x;
+    int t = threadIdx.x;
+    if (t < kGroups) cnt->bar[t][0] = 0;
+    if (t == 0) { cnt->bar_global = 0; cnt->xcd_bad = 0; }
+}
+
+// this block's share [lo, hi) of colour col in group g
+__device__ inline void colour_range(const DevBuffers& b, int64_t NB, uint32_t col, int g, unsigned rank, unsigned gx,
+                                    uint32_t& lo, uint32_t& hi)
+{
+    int64_t bucket = (int64_t)col * kGroups + g;
+    uint32_t beg = b.col_start[bucket * NB], end = b.col_start[(bucket + 1) * NB];
+    uint32_t len = end - beg;
+    lo = beg + (uint32_t)(((uint64_t)len * rank) / gx);
+    hi = beg + (uint32_t)(((uint64_t)len * (rank + 1)) / gx);
+}
+
+template <int AUX>
+__device__ void pgs_group(const DevBuffers& b, const StepParams& p, int64_t NB, int sweeps_cap, int slot, int g,
+                          unsigned rank, unsigned gx, uint32_t ncol, double (*red)[kPgsBlk / 64], int& stop_flag,
+                          int& bar_ok)
+{
+    __amdgpu_buffer_rsrc_t rv = raw_rsrc(b.vm), rw = raw_rsrc(b.wi);
+    uint32_t* counter = &b.cnt->bar[g][0];
     unsigned nbar = 0;
     int sweeps = 0;
     double Rk = 0.0, R1 = 0.0;
-    __amdgpu_buffer_rsrc_t rv = raw_rsrc(b.vm), rw = raw_rsrc(b.wi);
+    // the rows of the first contact of the next phase are fetched while the
+    // block waits at the barrier (they are read-only or owned by this thread)
+    uint32_t lo = 0, hi = 0;
+    RowRegs pre;
+    uint32_t pc = 0xffffffffu;
+    if (ncol > 0) {
+        colour_range(b, NB, 0, g, rank, gx, lo, hi);
+        if (lo + threadIdx.x < hi) { pc = lo + threadIdx.x; pre = load_rows(b, pc); }
+    }
+#ifdef TRK_PGS_TRACE
+    unsigned long long tr[5] = {0, 0, 0, 0, 0}, tprev = wall_clock64();
+#endif
     for (int k = 0; k < sweeps_cap; ++k) {
         float num = 0.f, den = 0.f;
-        double* part = b.block_part + (size_t)(k & 1) * 2 * G;
+        double* part = b.block_part + ((size_t)(k & 1) * gridDim.x + (size_t)g * gx) * 2;
         for (uint32_t col = 0; col < ncol; ++col) {
-            uint32_t beg = b.col_start[(int64_t)col * NB], end = b.col_start[(int64_t)(col + 1) * NB];
-            uint32_t len = end - beg;
-            uint32_t lo = beg + (uint32_t)(((uint64_t)len * blockIdx.x) / G);
-            uint32_t hi = beg + (uint32_t)(((uint64_t)len * (blockIdx.x + 1)) / G);
-            for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) pgs_contact(b, rv, rw, c, p.mu, p.gamma_dt, num, den);
+            for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
+                if (c == pc) pgs_contact<AUX>(b, rv, rw, c, pre, p.mu, p.gamma_dt, num, den);
+                else pgs_contact<AUX>(b, rv, rw, c, load_rows(b, c), p.mu, p.gamma_dt, num, den);
+            }
             if (col + 1 == ncol) {
                 // block partials of this sweep, published before the last barrier
                 double dnum = num, dden = den;
@@ -1051,19 +1087,46 @@ __global__ __launch_bounds__(kBlk) void k_pgs(DevBuffers b, StepParams p, int64_
                 __syncthreads();
                 if (threadIdx.x == 0) {
                     double sn = 0.0, sd = 0.0;
-                    for (int w = 0; w < kBlk / 64; ++w) { sn += red[0][w]; sd += red[1][w]; }
-                    __hip_atomic_store(&part[2 * blockIdx.x], sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(&part[2 * blockIdx.x + 1], sd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    for (int w = 0; w < kPgsBlk / 64; ++w) { sn += red[0][w]; sd += red[1][w]; }
+                    __hip_atomic_store(&part[2 * rank], sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&part[2 * rank + 1], sd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
-            if (!grid_barrier(b.cnt, G, nbar, bar_ok)) return;  // every block leaves
+            // barrier: drain this block's stores, arrive, prefetch the next
+            // phase's rows, then wait for the rest of the group
+#ifdef TRK_PGS_TRACE
+            unsigned long long ta = wall_clock64();
+#endif
+            __builtin_amdgcn_s_waitcnt(0);
+#ifdef TRK_PGS_TRACE
+            unsigned long long tb = wall_clock64();
+#endif
+            __syncthreads();
+            unsigned target = (nbar + 1) * gx;
+            ++nbar;
+            if (threadIdx.x == 0)
+                __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            colour_range(b, NB, col + 1 < ncol ? col + 1 : 0, g, rank, gx, lo, hi);
+            pc = 0xffffffffu;
+            if (lo + threadIdx.x < hi) { pc = lo + threadIdx.x; pre = load_rows(b, pc); }
+#ifdef TRK_PGS_TRACE
+            unsigned long long tc = wall_clock64();
+#endif
+            if (threadIdx.x == 0) bar_ok = wait_counter(b.cnt, counter, target) ? 1 : 0;
+            __syncthreads();
+#ifdef TRK_PGS_TRACE
+            unsigned long long td = wall_clock64();
+            tr[0] += ta - tprev; tr[1] += tb - ta; tr[2] += tc - tb; tr[3] += td - tc; tr[4] += 1;
+            tprev = td;
+#endif
+            if (!bar_ok) return;  // every block leaves
         }
         if (ncol == 0) {
             Rk = 0.0;
         } else {
-            // every block reduces all block partials in the same fixed order
+            // every block of the group reduces the group's partials in the same order
             double sn = 0.0, sd = 0.0;
-            for (unsigned t = threadIdx.x; t < G; t += blockDim.x) {
+            for (unsigned t = threadIdx.x; t < gx; t += blockDim.x) {
                 sn += __hip_atomic_load(&part[2 * t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 sd += __hip_atomic_load(&part[2 * t + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -1075,7 +1138,7 @@ __global__ __launch_bounds__(kBlk) void k_pgs(DevBuffers b, StepParams p, int64_
             if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = sn; red[1][threadIdx.x >> 6] = sd; }
             __syncthreads();
             sn = 0.0; sd = 0.0;
-            for (int w = 0; w < kBlk / 64; ++w) { sn += red[0][w]; sd += red[1][w]; }
+            for (int w = 0; w < kPgsBlk / 64; ++w) { sn += red[0][w]; sd += red[1][w]; }
             Rk = sd > 0.0 ? sqrt(sn) / sqrt(sd) : (sn > 0.0 ? 1.0 : 0.0);
         }
         if (k == 0) R1 = Rk;
@@ -1084,15 +1147,40 @@ __global__ __launch_bounds__(kBlk) void k_pgs(DevBuffers b, StepParams p, int64_
         __syncthreads();
         if (stop_flag) break;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+#ifdef TRK_PGS_TRACE
+    if (g == 0 && threadIdx.x == 0 && (rank == 0 || rank == gx - 1) && tr[4] > 0)
+        printf("PGS_TRACE rank %u phases %llu ticks/phase: work %.1f drain %.1f arrive+prefetch %.1f wait %.1f\n", rank,
+               tr[4], (double)tr[0] / tr[4], (double)tr[1] / tr[4], (double)tr[2] / tr[4], (double)tr[3] / tr[4]);
+#endif
+    if (rank == 0 && threadIdx.x == 0) {
+        GroupStats& G = b.cnt->gs[g];
         if (slot == 0) {
-            b.cnt->sweeps = (uint32_t)sweeps;
-            b.cnt->resid = Rk;
-            b.cnt->resid_first = R1;
+            G.sweeps = (uint32_t)sweeps;
+            G.resid = Rk;
+            G.resid_first = R1;
         } else {
-            b.cnt->r1_trial[slot - 1] = R1;
+            G.r1_trial[slot - 1] = R1;
         }
     }
+}
+
+__global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int64_t NB, int sweeps_cap, int slot)
+{
+    __shared__ double red[2][kPgsBlk / 64];
+    __shared__ int stop_flag;
+    __shared__ int bar_ok;
+    if (b.cnt->overflow) return;  // uniform: written by earlier kernels only
+    const int g = blockIdx.x % kGroups;
+    const unsigned rank = blockIdx.x / kGroups, gx = gridDim.x / kGroups;
+    uint32_t ncol = b.cnt->n_colours;
+    // a group without contacts only records its (trivial) statistics
+    uint32_t total = 0;
+    for (uint32_t col = 0; col < ncol; ++col) {
+        int64_t bucket = (int64_t)col * kGroups + g;
+        total += b.col_start[(bucket + 1) * NB] - b.col_start[bucket * NB];
+    }
+    if (total == 0) ncol = 0;
+    pgs_group<kCoherent>(b, p, NB, sweeps_cap, slot, g, rank, gx, ncol, red, stop_flag, bar_ok);
 }
 
 int pgs_resident_blocks(int block)
@@ -1118,8 +1206,8 @@ int colour_resident_blocks()
 void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s, int sweeps_cap, int slot)
 {
     int sw = sweeps_cap < 0 ? p.max_sweeps : sweeps_cap;
-    hipLaunchKernelGGL(k_pgs_reset, dim3(1), dim3(1), 0, s, b.cnt);
-    hipLaunchKernelGGL(k_pgs, dim3(z.pgs_grid), dim3(kBlk), 0, s, b, p, z.C, z.NB, sw, slot);
+    hipLaunchKernelGGL(k_pgs_reset, dim3(1), dim3(64), 0, s, b.cnt);
+    hipLaunchKernelGGL(k_pgs, dim3(z.pgs_grid), dim3(kPgsBlk), 0, s, b, p, z.NB, sw, slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -1186,32 +1274,38 @@ void launch_vel_copy(const DevBuffers& b, const StepParams& p, bool backup, hipS
                        backup ? 1 : 0);
 }
 
-__global__ void k_select_start(DevBuffers b, int64_t cap, int mode)
+__global__ void k_select_start(DevBuffers b, int64_t cap, int mode, uint32_t id_cap)
 {
     uint32_t nc = n_contacts(b, cap);
     uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
-    bool learned = mode == 1 || (mode == 2 && b.cnt->use_learned);
+    bool learned = mode == 1;
+    if (mode == 2) {
+        int g = b.envs[env_of(b.pid[__float_as_int(b.r2[c].w)], id_cap)].group;
+        learned = b.cnt->gs[g].use_learned != 0;
+    }
     b.lam[c] = learned ? b.lamL[c] : b.lam0[c];
 }
 
-void launch_select_start(const DevBuffers& b, const Sizes& z, int mode, hipStream_t s)
+void launch_select_start(const DevBuffers& b, const StepParams& p, const Sizes& z, int mode, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_select_start, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, z.C, mode);
+    hipLaunchKernelGGL(k_select_start, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, z.C, mode, p.id_cap);
 }
 
 __global__ void k_choose_start(DevBuffers b)
 {
-    Counters* c = b.cnt;
-    bool finite = (c->learn_flags & 1u) == 0 && isfinite(c->r1_trial[0]);
-    bool use = finite && !(c->r1_trial[0] > c->r1_trial[1]);
-    c->use_learned = use ? 1u : 0u;
-    c->fallback = use ? 0u : 1u;
+    int g = threadIdx.x;
+    if (g >= kGroups) return;
+    GroupStats& G = b.cnt->gs[g];
+    bool finite = ((b.cnt->learn_flags >> g) & 1u) == 0 && isfinite(G.r1_trial[0]);
+    bool use = finite && !(G.r1_trial[0] > G.r1_trial[1]);
+    G.use_learned = use ? 1u : 0u;
+    G.fallback = use ? 0u : 1u;
 }
 
 void launch_choose_start(const DevBuffers& b, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_choose_start, dim3(1), dim3(1), 0, s, b);
+    hipLaunchKernelGGL(k_choose_start, dim3(1), dim3(64), 0, s, b);
 }
 
 // training samples of the last step in canonical order: the 12 features and
