@@ -50,6 +50,8 @@ def build_bed(args):
     spec["bodies"] = spec["bodies"] + [blade]
     spec["warm_start"] = "prev"
     sc = T.scene_from_specs(spec, cap_contacts=16 * args.n)
+    # eager launches: the HIP events around the PGS kernel time it inside the timed region
+    sc.set_step_graphs(False)
     return sc, spec, blade, est_top
 
 
@@ -105,6 +107,65 @@ def cpu_baseline(args):
                        f"r 0.03 m, {args.sweeps} sweeps, {out['contacts']} contacts/step")
 
 
+def build_batched(args):
+    specs = SG.batch_specs(seed=3000, n_envs=args.envs, sweeps=args.sweeps)
+    mat = specs[0]["material"]
+    specs = [dict(s, material=mat, warm_start="prev") for s in specs]
+    nmax = max(len(s["x"]) for s in specs)
+    sc = T.scene_from_specs(specs, cap_particles=nmax, cap_contacts=8 * nmax)
+    # tools held still while the beds settle
+    still = []
+    for e, s in enumerate(specs):
+        b = [dict(x, id=i) for i, x in enumerate(s["bodies"])]
+        moving = [dict(x) for x in b]
+        for x in b:
+            x["linvel"] = (0.0, 0.0, 0.0)
+        sc.set_kinematic_bodies(e, b)
+        still.append(moving)
+    return sc, specs, still
+
+
+def bench_batched(args):
+    sc, specs, moving = build_batched(args)
+    if args.schedule:
+        sc.set_solver_config(**json.loads(args.schedule))
+    sc.step(args.settle, stats=False)
+    for e, b in enumerate(moving):
+        sc.set_kinematic_bodies(e, b)
+    for _ in range(args.warmup):
+        sc.step(1)
+    device_sync()
+    # stats of one step (synchronising), then the timed steps without host reads
+    st = sc.step(1)
+    cs_step = sum(x["contacts"] * x["sweeps"] for x in st)
+    device_sync()
+    t0 = time.perf_counter()
+    sc.step(args.steps, stats=False)
+    device_sync()
+    wall = time.perf_counter() - t0
+    # one eager step for the phase breakdown (graph replays are timed as a whole)
+    sc.set_step_graphs(False)
+    st2 = sc.step(1)
+    ph = sc.get_phase_times()
+    n = sum(len(s["x"]) for s in specs)
+    contacts = sum(x["contacts"] for x in st2)
+    line = {
+        "metric": "contacts*PGS-sweeps/s (whole step)",
+        "value": cs_step * args.steps / wall,
+        "unit": "contacts*sweeps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched: {len(specs)} independent beds, {n} spheres (log-uniform 500-20000 per "
+                               f"bed), blade or bucket at U(0.3, 1.5) m/s, dt 1/60 s, {args.sweeps} sweeps, "
+                               f"prev warm start, step graphs",
+                   "contacts_per_step": contacts, "steps_per_s": args.steps / wall,
+                   "schedule": sc.get_solver_config(),
+                   "eager_phase_ms": {k: float(v) for k, v in ph.items()}},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def tol_rate(sc, mode, k, cap):
     """steps/s of the same bed stepping to R_k <= 1e-4 (cap sweeps)."""
     return None
@@ -116,17 +177,27 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=50000)
-    ap.add_argument("--sweeps", type=int, default=150)
+    ap.add_argument("--sweeps", type=int, default=None, help="PGS sweeps (150 for the bed, 100 batched)")
     ap.add_argument("--settle", type=int, default=150)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", choices=("bed", "batched"), default="bed")
+    ap.add_argument("--envs", type=int, default=256)
+    ap.add_argument("--schedule", default="", help="PGS schedule as JSON (set_solver_config fields)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is design-only",
               file=sys.stderr)
         sys.exit(2)
+    if args.sweeps is None:
+        args.sweeps = 100 if args.workload == "batched" else 150
+    if args.workload == "batched":
+        bench_batched(args)
+        return
 
     sc, spec, blade, est_top = build_bed(args)
+    if args.schedule:
+        sc.set_solver_config(**json.loads(args.schedule))
     st0, top = settle(sc, spec, blade, args.settle)
     print(f"# settled: {st0['contacts']} contacts, top {top:.3f} m (estimate {est_top:.3f})", file=sys.stderr,
           flush=True)

@@ -137,7 +137,7 @@ typedef struct tr_body_desc {
 typedef struct tr_step_stats {
     int64_t contacts;        /* all contacts of the env (pairs + boundary) */
     int64_t pair_contacts;
-    int32_t colours;         /* colours of the scene's schedule */
+    int32_t colours;         /* colours used by this env's contacts */
     int32_t sweeps;          /* PGS sweeps done */
     double residual;         /* R_k after the last sweep */
     double residual_first;   /* R_1 */
@@ -264,6 +264,41 @@ int mlp_loss_grad(const float* weights, const float* feat, const float* label, i
  * weights in place; m and v are the moment buffers (device, 5187 each). */
 int mlp_adam_step(float* weights, const float* grad, float* m, float* v, float lr, float beta1, float beta2, float eps,
                   int32_t t, void* stream);
+
+/* Schedule of the PGS solve (Sec. numerical solver: the sweeps of the
+ * projected Gauss-Seidel method over the graph-coloured contacts).  It changes
+ * how the work is spread over the GPU, not the arithmetic: with tol == 0 every
+ * schedule gives the same impulses.  With tol > 0 the stopping test of
+ * TR_PGS_GROUPED is taken per group of envs (one group per env when the scene
+ * has at most 8 envs), that of TR_PGS_PER_ENV per env.
+ *   TR_PGS_GROUPED: envs in 8 groups, one per XCD; each group is solved by
+ *     blocks_per_xcd blocks that meet at a barrier after every colour.
+ *   TR_PGS_PER_ENV: each env is solved by its own block (bodies staged in
+ *     LDS when it has at most lds_particles particles) or, when it has more
+ *     than T particles, by a cluster of ceil(n / T) blocks; small envs share
+ *     blocks and run on them one after another.  T = cluster_particles, or
+ *     with 0 the mean particles per resident block (at least 4096). */
+#define TR_PGS_GROUPED 0
+#define TR_PGS_PER_ENV 1
+typedef struct tr_solver_config {
+    int32_t mode;              /* TR_PGS_GROUPED or TR_PGS_PER_ENV */
+    int32_t blocks_per_xcd;    /* grouped: >= 1, clamped to the resident limit */
+    int32_t lds_particles;     /* per-env: >= 0, clamped to what LDS holds */
+    int32_t cluster_particles; /* per-env: T, or 0 for the automatic choice */
+} tr_solver_config;
+
+/* Set / read the schedule.  Takes effect at the next step; TR_E_INVAL on a bad
+ * field.  The default is TR_PGS_GROUPED with 32 blocks per XCD for up to 8
+ * envs, else TR_PGS_PER_ENV with the LDS limit and automatic clusters. */
+int set_solver_config(tr_scene* s, const tr_solver_config* cfg);
+int get_solver_config(tr_scene* s, tr_solver_config* cfg);
+
+/* Step graphs (on by default): from the second step after the scene or its
+ * tables last changed, each step replays a captured HIP graph of its launches
+ * instead of launching them one by one.  Results are identical either way;
+ * enable = 0 launches every step eagerly.  With graphs, the phase times of
+ * get_phase_times are all recorded around the whole step. */
+int set_step_graphs(tr_scene* s, int32_t enable);
 
 /* Device time (ms, from HIP events on the scene's stream) of the last step's
  * phases: [0] detection+ordering, [1] rows+colouring+warm start, [2] PGS,

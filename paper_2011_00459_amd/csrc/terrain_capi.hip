@@ -57,6 +57,19 @@ struct tr_scene {
     int64_t cols_alloc = 0;
     bool mlp_loaded = false;
     bool mlp_bf16 = true;
+    tr_solver_config cfg{};           // PGS schedule
+    int64_t plan_alloc = 0;           // plan tasks allocated
+    int64_t plan_idx_alloc = 0;       // plan block offsets allocated
+    int64_t part_alloc = 0;           // block partials allocated (doubles)
+    int max_lds_particles = 0;        // bodies one per-env block can stage in LDS
+    // step graphs: a step swaps the sorted-particle and contact-cache buffers,
+    // so the launch sequence repeats every two steps; gexec[q] replays the
+    // step taken when (steps since capture) % 2 == q
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipStream_t cap_stream = nullptr;
+    bool graphs = false;
+    bool use_graphs = true;
+    int parity = 0;
 };
 
 namespace {
@@ -123,6 +136,110 @@ int ceil_log2(int v)
     int b = 0;
     while ((1 << b) < v) ++b;
     return b;
+}
+
+void invalidate_graphs(tr_scene* s)
+{
+    for (int q = 0; q < 2; ++q)
+        if (s->gexec[q]) {
+            (void)hipGraphExecDestroy(s->gexec[q]);
+            s->gexec[q] = nullptr;
+        }
+    s->graphs = false;
+}
+
+// PGS schedule: the solve unit of every env and, in per-env mode, the task
+// plan of the resident blocks.  Envs larger than T particles per block get a
+// cluster of ceil(n / T) blocks in one XCD lane (indices congruent mod 8, so
+// they share an XCD); the others, largest first, go to the least loaded block
+// and run there one after another.
+int rebuild_plan(tr_scene* s)
+{
+    invalidate_graphs(s);
+    const int E = s->desc.n_envs;
+    hipStream_t st = s->stream;
+    std::vector<int4> plan;
+    std::vector<uint32_t> plan_idx;
+    int lds_cap = 0;
+    int blocks = 0;
+    if (s->cfg.mode == TR_PGS_PER_ENV) {
+        lds_cap = std::max(0, std::min(s->cfg.lds_particles, s->max_lds_particles));
+        // every block is resident (clusters wait for each other); a whole number per XCD
+        int B = std::max(kGroups, pgs_env_resident_blocks(lds_cap * 32));
+        B -= B % kGroups;
+        const int per_lane = B / kGroups;
+        double total = 0.0;
+        for (int e = 0; e < E; ++e) total += (double)s->envs[e].n;
+        // particles per block: envs above it are split into clusters
+        double T = s->cfg.cluster_particles > 0 ? (double)s->cfg.cluster_particles : std::max(total / B, 4096.0);
+        std::vector<int> order;
+        for (int e = 0; e < E; ++e)
+            if (s->envs[e].n > 0) order.push_back(e);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return s->envs[a].n > s->envs[c].n; });
+        std::vector<std::vector<int4>> tasks(B);
+        std::vector<double> load(B, 0.0);
+        std::vector<int> lane_next(kGroups, 0);
+        for (int e : order) {
+            int64_t n = s->envs[e].n;
+            int K = (int)std::min<double>(std::ceil((double)n / T), (double)per_lane);
+            int lane = 0;
+            for (int x = 1; x < kGroups; ++x)
+                if (lane_next[x] < lane_next[lane]) lane = x;
+            K = std::min(K, per_lane - lane_next[lane]);
+            if (K >= 2) {
+                // a cluster: K blocks of one lane (block indices congruent mod 8)
+                int first = lane + kGroups * lane_next[lane];
+                for (int r = 0; r < K; ++r) {
+                    int blk = first + kGroups * r;
+                    tasks[blk].push_back(make_int4(e, r, K, first));
+                    load[blk] += (double)n / K;
+                }
+                lane_next[lane] += K;
+                continue;
+            }
+            // a single-block task onto the least loaded block
+            int best = 0;
+            for (int blk = 1; blk < B; ++blk)
+                if (load[blk] < load[best]) best = blk;
+            tasks[best].push_back(make_int4(e, 0, 1, best));
+            load[best] += (double)n;
+        }
+        plan_idx.assign(B + 1, 0);
+        for (int blk = 0; blk < B; ++blk) {
+            plan_idx[blk] = (uint32_t)plan.size();
+            plan.insert(plan.end(), tasks[blk].begin(), tasks[blk].end());
+        }
+        plan_idx[B] = (uint32_t)plan.size();
+        blocks = B;
+        for (int e = 0; e < E; ++e) s->env_host[e].unit = e;
+    } else {
+        for (int e = 0; e < E; ++e) s->env_host[e].unit = s->env_host[e].group;
+    }
+    if ((int64_t)plan.size() > s->plan_alloc) {
+        dfree(s, s->b.plan);
+        if (!alloc_n(s, s->b.plan, (int64_t)plan.size())) return fail(s, TR_E_NOMEM, "PGS plan");
+        s->plan_alloc = (int64_t)plan.size();
+    }
+    if ((int64_t)plan_idx.size() > s->plan_idx_alloc) {
+        dfree(s, s->b.plan_idx);
+        if (!alloc_n(s, s->b.plan_idx, (int64_t)plan_idx.size())) return fail(s, TR_E_NOMEM, "PGS plan");
+        s->plan_idx_alloc = (int64_t)plan_idx.size();
+    }
+    int64_t parts = 4 * std::max<int64_t>(s->z.pgs_grid, blocks);
+    if (parts > s->part_alloc) {
+        dfree(s, s->b.block_part);
+        if (!alloc_n(s, s->b.block_part, parts)) return fail(s, TR_E_NOMEM, "PGS partials");
+        s->part_alloc = parts;
+    }
+    if (!plan.empty()) HIP_CHECK(s, hipMemcpyAsync(s->b.plan, plan.data(), sizeof(int4) * plan.size(), hipMemcpyHostToDevice, st));
+    if (!plan_idx.empty())
+        HIP_CHECK(s, hipMemcpyAsync(s->b.plan_idx, plan_idx.data(), sizeof(uint32_t) * plan_idx.size(), hipMemcpyHostToDevice, st));
+    s->z.pgs_mode = s->cfg.mode;
+    s->z.plan_blocks = blocks;
+    s->z.lds_cap = lds_cap;
+    HIP_CHECK(s, hipMemcpyAsync(s->b.envs, s->env_host.data(), sizeof(EnvDev) * E, hipMemcpyHostToDevice, st));
+    HIP_CHECK(s, hipStreamSynchronize(st));  // the host plan dies here
+    return TR_OK;
 }
 
 // Rebuild the per-env tables (grids, bodies, shapes, zones, chunk list) and
@@ -292,7 +409,7 @@ int rebuild_tables(tr_scene* s)
     s->p.n_shapes = (int)sd.size();
     s->p.n_zones = n_zones;
     s->tables_dirty = false;
-    return TR_OK;
+    return rebuild_plan(s);
 }
 
 // Download the device poses into the host body descriptions (they advance on
@@ -374,17 +491,17 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
     z.C = (int64_t)d->n_envs * d->cap_contacts;
     z.NID = z.P;
     z.NB = (z.C + 255) / 256;
-    z.pgs_block = 256;
-    // PGS grid: kGroups XCD groups of gx blocks (one per CU of the XCD by
-    // default); the colour barrier stays inside an XCD's L2
-    {
-        int gx = 32;
-        const char* ev = getenv("TR_PGS_GX");
-        if (ev && atoi(ev) > 0) gx = atoi(ev);
-        gx = std::max(1, std::min(gx, pgs_resident_blocks(512) / kGroups));
-        z.pgs_block = 512;
-        z.pgs_grid = kGroups * gx;
-    }
+    z.n_envs = d->n_envs;
+    z.pgs_block = 512;
+    s->p.n_units = std::max(kGroups, d->n_envs);
+    // default schedule: grouped for a few envs (XCD groups of 32 blocks, one
+    // per CU), per-env blocks with LDS-resident bodies for many envs
+    s->max_lds_particles = std::max(0, (pgs_env_max_lds() - 1024) / 32);
+    s->cfg.mode = d->n_envs > kGroups ? TR_PGS_PER_ENV : TR_PGS_GROUPED;
+    s->cfg.blocks_per_xcd = 32;
+    s->cfg.lds_particles = s->max_lds_particles;
+    s->cfg.cluster_particles = 0;
+    z.pgs_grid = kGroups * std::max(1, std::min(s->cfg.blocks_per_xcd, pgs_resident_blocks(512) / kGroups));
     z.col_grid = std::min(colour_resident_blocks(), 2048);
     DevBuffers& b = s->b;
     bool ok = alloc_n(s, b.xr, z.P) && alloc_n(s, b.vm, z.P) && alloc_n(s, b.wi, z.P) && alloc_n(s, b.xr2, z.P) &&
@@ -400,7 +517,9 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
               alloc_n(s, b.col_start, (int64_t)kBuckets * z.NB + 1) && alloc_n(s, b.cpos, z.C) &&
               alloc_n(s, b.r0, z.C) && alloc_n(s, b.r1, z.C) && alloc_n(s, b.r2, z.C) && alloc_n(s, b.rk, z.C) &&
               alloc_n(s, b.lam, z.C) && alloc_n(s, b.lam0, z.C) &&
-              alloc_n(s, b.block_part, (int64_t)4 * z.pgs_grid) && alloc_n(s, b.envs, d->n_envs) &&
+              alloc_n(s, b.envs, d->n_envs) && alloc_n(s, b.ustats, s->p.n_units) &&
+              alloc_n(s, b.env_col, (int64_t)d->n_envs * (kMaxColours + 1)) && alloc_n(s, b.env_ncol, d->n_envs) &&
+              alloc_n(s, b.env_bar, (int64_t)d->n_envs * 16) &&
               alloc_n(s, b.cnt, 1) && alloc_n(s, b.env_stats, d->n_envs) && alloc_n(s, b.mlp, kMlpParams) &&
               alloc_n(s, s->staging, 12 * z.P) && alloc_n(s, b.feat, 12 * z.C) && alloc_n(s, b.frm1, z.C) &&
               alloc_n(s, b.frm2, z.C) && alloc_n(s, b.lamL, z.C) && alloc_n(s, b.mlp_out, 3 * z.C) &&
@@ -411,6 +530,8 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
     }
     hipError_t e = hipMemsetAsync(b.cnt, 0, sizeof(Counters), s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b.env_stats, 0, sizeof(EnvStats) * d->n_envs, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b.ustats, 0, sizeof(UnitStats) * s->p.n_units, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b.env_ncol, 0, sizeof(uint32_t) * d->n_envs, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b.id_start, 0, sizeof(uint32_t) * (z.NID + 1), s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b.pid_start, 0, sizeof(uint32_t) * (z.NID + 1), s->stream);
     for (int k = 0; k < 5 && e == hipSuccess; ++k) e = hipEventCreate(&s->ev[k]);
@@ -429,6 +550,8 @@ int destroy_scene(tr_scene* s)
     if (!s) return TR_OK;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     else (void)hipDeviceSynchronize();
+    invalidate_graphs(s);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
     if (s->events)
         for (int k = 0; k < 5; ++k) (void)hipEventDestroy(s->ev[k]);
@@ -552,6 +675,104 @@ int set_kinematic_bodies(tr_scene* s, int32_t env, int32_t n, const tr_body_desc
     return TR_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// host side of a step's buffer rotation: the sorted particle arrays (written
+// into the *2 buffers) and the previous-step contact cache
+void swap_particle_buffers(tr_scene* s)
+{
+    std::swap(s->b.xr, s->b.xr2);
+    std::swap(s->b.vm, s->b.vm2);
+    std::swap(s->b.wi, s->b.wi2);
+    std::swap(s->b.pid, s->b.pid2);
+    std::swap(s->b.rho, s->b.rho2);
+}
+
+void swap_step_buffers(tr_scene* s)
+{
+    std::swap(s->b.ckey, s->b.pkeyc);
+    std::swap(s->b.lamc, s->b.plam);
+    std::swap(s->b.id_start, s->b.pid_start);
+}
+
+// Every launch of one step, in stream order (A1-A12).  The sorted particle
+// arrays are written into the *2 buffers and swapped in; the canonical keys,
+// impulses and id ranges become the next step's previous-step cache.
+void enqueue_step(tr_scene* s, hipStream_t st, bool events)
+{
+    if (events) (void)hipEventRecord(s->ev[0], st);
+    launch_step_begin(s->b, s->p, st);
+    launch_sort_particles(s->b, s->p, s->z, st);
+    swap_particle_buffers(s);
+    launch_narrow(s->b, s->p, s->z, st);
+    launch_canonical(s->b, s->p, s->z, st);
+    if (events) (void)hipEventRecord(s->ev[1], st);
+    launch_depth(s->b, s->p, s->z, st);
+    launch_colour(s->b, s->p, s->z, st);
+    launch_rows(s->b, s->p, s->z, s->have_prev, st);
+    if (s->p.warm == TR_WARM_LEARNED && s->mlp_loaded) {
+        // learned start, then the first-sweep trial against the previous-step start
+        launch_mlp_infer(s->b.mlp, s->b.feat, s->b.mlp_out, &s->b.cnt->n_raw, s->z.C, s->mlp_bf16, st);
+        launch_learned_lam(s->b, s->p, s->z, st);
+        launch_vel_copy(s->b, s->p, true, st);
+        launch_select_start(s->b, s->p, s->z, 1, st);
+        launch_warm_apply(s->b, s->p, s->z, st);
+        launch_pgs(s->b, s->p, s->z, st, 1, 1);
+        launch_vel_copy(s->b, s->p, false, st);
+        launch_select_start(s->b, s->p, s->z, 0, st);
+        launch_warm_apply(s->b, s->p, s->z, st);
+        launch_pgs(s->b, s->p, s->z, st, 1, 2);
+        launch_choose_start(s->b, s->p, st);
+        launch_vel_copy(s->b, s->p, false, st);
+        launch_select_start(s->b, s->p, s->z, 2, st);
+    }
+    launch_warm_apply(s->b, s->p, s->z, st);
+    if (events) (void)hipEventRecord(s->ev[2], st);
+    launch_pgs(s->b, s->p, s->z, st);
+    if (events) (void)hipEventRecord(s->ev[3], st);
+    launch_finish(s->b, s->p, s->z, st);
+    if (events) (void)hipEventRecord(s->ev[4], st);
+    swap_step_buffers(s);
+}
+
+// Capture the two steps of the buffer rotation as graphs, on a private
+// stream (a scene on the null stream can replay them too).  Capturing
+// records launches without running them; the two captured rotations bring
+// the host buffer state back to where it was.
+int capture_graphs(tr_scene* s)
+{
+    invalidate_graphs(s);
+    if (!s->cap_stream) HIP_CHECK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    for (int q = 0; q < 2; ++q) {
+        hipGraph_t g = nullptr;
+        HIP_CHECK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue_step(s, s->cap_stream, false);
+        hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+        if (e == hipSuccess) e = hipGraphInstantiate(&s->gexec[q], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            invalidate_graphs(s);
+            return hip_fail(s, e, "step graph capture");
+        }
+    }
+    s->graphs = true;
+    s->parity = 0;
+    return TR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int set_step_graphs(tr_scene* s, int32_t enable)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    s->use_graphs = enable != 0;
+    if (!s->use_graphs) invalidate_graphs(s);
+    return TR_OK;
+}
+
 int step(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
 {
     if (!s) return TR_E_INVAL;
@@ -563,45 +784,20 @@ int step(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
     }
     hipStream_t st = s->stream;
     for (int k = 0; k < n_steps; ++k) {
-        (void)hipEventRecord(s->ev[0], st);
-        launch_step_begin(s->b, s->p, st);
-        launch_sort_particles(s->b, s->p, s->z, st);
-        std::swap(s->b.xr, s->b.xr2);
-        std::swap(s->b.vm, s->b.vm2);
-        std::swap(s->b.wi, s->b.wi2);
-        std::swap(s->b.pid, s->b.pid2);
-        std::swap(s->b.rho, s->b.rho2);
-        launch_narrow(s->b, s->p, s->z, st);
-        launch_canonical(s->b, s->p, s->z, st);
-        (void)hipEventRecord(s->ev[1], st);
-        launch_depth(s->b, s->p, s->z, st);
-        launch_colour(s->b, s->p, s->z, st);
-        launch_rows(s->b, s->p, s->z, s->have_prev, st);
-        if (s->p.warm == TR_WARM_LEARNED && s->mlp_loaded) {
-            // learned start, then the first-sweep trial against the previous-step start
-            launch_mlp_infer(s->b.mlp, s->b.feat, s->b.mlp_out, &s->b.cnt->n_raw, s->z.C, s->mlp_bf16, st);
-            launch_learned_lam(s->b, s->p, s->z, st);
-            launch_vel_copy(s->b, s->p, true, st);
-            launch_select_start(s->b, s->p, s->z, 1, st);
-            launch_warm_apply(s->b, s->p, s->z, st);
-            launch_pgs(s->b, s->p, s->z, st, 1, 1);
-            launch_vel_copy(s->b, s->p, false, st);
-            launch_select_start(s->b, s->p, s->z, 0, st);
-            launch_warm_apply(s->b, s->p, s->z, st);
-            launch_pgs(s->b, s->p, s->z, st, 1, 2);
-            launch_choose_start(s->b, st);
-            launch_vel_copy(s->b, s->p, false, st);
-            launch_select_start(s->b, s->p, s->z, 2, st);
+        if (s->use_graphs && s->have_prev && !s->graphs) {
+            int rc = capture_graphs(s);
+            if (rc) return rc;
         }
-        launch_warm_apply(s->b, s->p, s->z, st);
-        (void)hipEventRecord(s->ev[2], st);
-        launch_pgs(s->b, s->p, s->z, st);
-        (void)hipEventRecord(s->ev[3], st);
-        launch_finish(s->b, s->p, s->z, st);
-        (void)hipEventRecord(s->ev[4], st);
-        std::swap(s->b.ckey, s->b.pkeyc);
-        std::swap(s->b.lamc, s->b.plam);
-        std::swap(s->b.id_start, s->b.pid_start);
+        if (s->graphs && s->have_prev) {
+            (void)hipEventRecord(s->ev[0], st);
+            HIP_CHECK(s, hipGraphLaunch(s->gexec[s->parity], st));
+            for (int q = 1; q < 5; ++q) (void)hipEventRecord(s->ev[q], st);
+            swap_particle_buffers(s);
+            swap_step_buffers(s);
+        } else {
+            enqueue_step(s, st, true);
+        }
+        s->parity ^= 1;
         s->have_prev = true;
         s->stepped = true;
     }
@@ -613,12 +809,16 @@ int step(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
         std::vector<EnvStats> es(s->desc.n_envs);
         HIP_CHECK(s, hipMemcpy(&c, s->b.cnt, sizeof(c), hipMemcpyDeviceToHost));
         HIP_CHECK(s, hipMemcpy(es.data(), s->b.env_stats, sizeof(EnvStats) * es.size(), hipMemcpyDeviceToHost));
+        std::vector<UnitStats> us(s->p.n_units);
+        std::vector<uint32_t> nc(s->desc.n_envs);
+        HIP_CHECK(s, hipMemcpy(us.data(), s->b.ustats, sizeof(UnitStats) * us.size(), hipMemcpyDeviceToHost));
+        HIP_CHECK(s, hipMemcpy(nc.data(), s->b.env_ncol, sizeof(uint32_t) * nc.size(), hipMemcpyDeviceToHost));
         for (int e2 = 0; e2 < s->desc.n_envs; ++e2) {
             tr_step_stats& o = stats[e2];
             o.contacts = es[e2].contacts;
             o.pair_contacts = es[e2].pairs;
-            const GroupStats& G = c.gs[s->env_host[e2].group];
-            o.colours = (int32_t)c.n_colours;
+            const UnitStats& G = us[s->env_host[e2].unit];
+            o.colours = (int32_t)nc[e2];
             o.sweeps = (int32_t)G.sweeps;
             o.residual = G.resid;
             o.residual_first = G.resid_first;
@@ -666,6 +866,27 @@ int get_aggregates(tr_scene* s, int32_t env, int32_t cap, tr_aggregate* out, int
     HIP_CHECK(s, hipStreamSynchronize(s->stream));
     for (int k = 0; k < (int)zs.size() && k < cap; ++k)
         HIP_CHECK(s, hipMemcpy(&out[k], s->b.aggs + zs[k], sizeof(tr_aggregate), hipMemcpyDeviceToHost));
+    return TR_OK;
+}
+
+int set_solver_config(tr_scene* s, const tr_solver_config* cfg)
+{
+    if (!s || !cfg) return TR_E_INVAL;
+    s->err.clear();
+    if ((cfg->mode != TR_PGS_GROUPED && cfg->mode != TR_PGS_PER_ENV) || cfg->blocks_per_xcd < 1 ||
+        cfg->lds_particles < 0 || cfg->cluster_particles < 0)
+        return fail(s, TR_E_INVAL, "set_solver_config: bad field");
+    s->cfg = *cfg;
+    s->cfg.blocks_per_xcd = std::min(cfg->blocks_per_xcd, std::max(1, pgs_resident_blocks(512) / kGroups));
+    s->cfg.lds_particles = std::min(cfg->lds_particles, s->max_lds_particles);
+    s->z.pgs_grid = kGroups * s->cfg.blocks_per_xcd;
+    return s->tables_dirty ? TR_OK : rebuild_plan(s);
+}
+
+int get_solver_config(tr_scene* s, tr_solver_config* cfg)
+{
+    if (!s || !cfg) return TR_E_INVAL;
+    *cfg = s->cfg;
     return TR_OK;
 }
 
@@ -746,6 +967,7 @@ int set_learned_precision(tr_scene* s, int32_t use_bf16)
 {
     if (!s) return TR_E_INVAL;
     s->err.clear();
+    if (s->mlp_bf16 != (use_bf16 != 0)) invalidate_graphs(s);
     s->mlp_bf16 = use_bf16 != 0;
     return TR_OK;
 }
@@ -816,6 +1038,7 @@ int set_mlp_weights(tr_scene* s, const float* weights, int64_t n)
         if (!std::isfinite(weights[i])) return fail(s, TR_E_NONFINITE, "set_mlp_weights: non-finite weight");
     HIP_CHECK(s, hipMemcpyAsync(s->b.mlp, weights, sizeof(float) * n, hipMemcpyHostToDevice, s->stream));
     HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    if (!s->mlp_loaded) invalidate_graphs(s);
     s->mlp_loaded = true;
     return TR_OK;
 }

@@ -28,6 +28,13 @@ constexpr int kForceChunks = 32;    // deterministic chunks of the body-force re
 constexpr int kZoneChunk = 2048;    // particles per chunk of the zone reduction
 constexpr int kMlpParams = 64 * 12 + 64 + 64 * 64 + 64 + 3 * 64 + 3 + 12;
 
+// PGS solve modes
+enum : int {
+    kModeGrouped = 0,  // envs in kGroups XCD groups, grid-wide colour barriers per group
+    kModePerEnv = 1,   // each env solved by its own block (or cluster of blocks)
+};
+constexpr int kEnvBlk = 1024;  // threads of a per-env PGS block
+
 // Overflow / failure bits of Counters::overflow
 enum : uint32_t {
     kOvfContacts = 1u,
@@ -50,7 +57,8 @@ struct EnvDev {
     int n;                        // particles of the env
     int slot_begin;               // first slot of the env in sorted order
     int col_base;                 // first depth column of the env (dims[0] x dims[1] columns)
-    int group;                    // PGS group (XCD) that solves this env
+    int group;                    // PGS group (XCD) that solves this env in grouped mode
+    int unit;                     // solve unit: the group (grouped mode) or the env (per-env mode)
     int zone_count;
     int zone_body[kMaxZonesPerEnv];  // global body index of each zone
     int zone_slot[kMaxZonesPerEnv];  // global zone index of each zone
@@ -112,14 +120,17 @@ struct StepParams {
     double dt_d;        // dt in FP64 (learned-start features)
     double gdt;         // |g| dt
     double r_ref;       // nominal radius of the features
+    int n_units;        // PGS solve units (entries of ustats)
+    int pad_units;
 };
 
-// per PGS group (64 B)
-struct GroupStats {
+// per PGS solve unit: an XCD group of envs (grouped mode) or one env
+// (per-env mode); envs of one unit share the stopping decision (64 B)
+struct UnitStats {
     uint32_t sweeps;
     uint32_t use_learned;  // 1 when the learned start won the first-sweep trial
     uint32_t fallback;
-    uint32_t pad;
+    uint32_t learn_bad;    // non-finite network output in this unit
     double resid;
     double resid_first;
     double r1_trial[2];    // first-sweep residual from the learned / previous start
@@ -131,12 +142,8 @@ struct Counters {
     uint32_t n_pairs;
     uint32_t overflow;     // kOvf* / kFail* bits, sticky within a step
     uint32_t n_colours;
-    uint32_t learn_flags;  // bit g: non-finite network output in group g
-    uint32_t xcd_bad;      // a PGS block ran off its expected XCD
-    uint32_t bar_global;   // counter of the launch's global barrier
-    uint32_t pad[9];
+    uint32_t pad[12];
     uint32_t bar[kGroups][16];  // per-group barrier counters, one cache line each
-    GroupStats gs[kGroups];
 };
 
 struct EnvStats {
@@ -180,6 +187,12 @@ struct DevBuffers {
     float* hf_pool;
     Counters* cnt;
     EnvStats* env_stats;
+    UnitStats* ustats;    // [n_units]
+    uint32_t* env_col;    // [n_envs][kMaxColours + 1] colour starts of each env (per-env mode)
+    uint32_t* env_ncol;   // [n_envs] colours used by each env
+    int4* plan;           // per-env PGS tasks: (env, rank in its cluster, cluster size, first block)
+    uint32_t* plan_idx;   // [blocks + 1]: tasks of block b are plan[plan_idx[b] .. plan_idx[b + 1])
+    uint32_t* env_bar;    // [n_envs][16] cluster barrier counters (per-env mode)
     uint32_t* scan_tmp;   // scratch of the device-wide scan
     float* mlp;           // learned-start weights (kMlpParams)
     // learned start (colour order) and the depth feature
@@ -198,9 +211,14 @@ struct Sizes {
     int64_t NID;    // id space = n_envs * cap_particles
     int64_t NC;     // cells (all envs)
     int64_t NB;     // blocks of 256 over C (colour bucketing)
+    int n_envs;
     int n_zone_chunks;
     int pgs_grid;   // blocks of the persistent PGS kernel (kGroups x blocks per group)
     int pgs_block;  // threads per PGS block
+    int pgs_mode;   // kModeGrouped or kModePerEnv
+    int plan_blocks;  // blocks of the per-env PGS kernel
+    int lds_cap;    // particles whose bodies a per-env block keeps in LDS (0: none)
+    int n_units;    // entries of ustats
     int col_grid;   // resident blocks of the colouring kernel
     int64_t NCOL;   // depth columns (all envs)
 };
@@ -224,7 +242,7 @@ void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStr
 void launch_depth(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_vel_copy(const DevBuffers& b, const StepParams& p, bool backup, hipStream_t s);
 void launch_select_start(const DevBuffers& b, const StepParams& p, const Sizes& z, int mode, hipStream_t s);
-void launch_choose_start(const DevBuffers& b, hipStream_t s);
+void launch_choose_start(const DevBuffers& b, const StepParams& p, hipStream_t s);
 void launch_learn_samples(const DevBuffers& b, int64_t beg, int64_t n, float* feat, float* label, hipStream_t s);
 // terrain_mlp.hip
 void launch_mlp_infer(const float* W, const float* feat, float* out, const uint32_t* d_n, int64_t cap, bool bf16,
@@ -242,6 +260,8 @@ void launch_gather_by_id(const DevBuffers& b, int id_base, int n, float4* xo, fl
 void launch_scatter_by_id(const DevBuffers& b, int id_base, int n, const float4* xi, const float4* vi,
                           const float4* wi, int mask, hipStream_t s);
 int pgs_resident_blocks(int block);
+int pgs_env_resident_blocks(int lds_bytes);
+int pgs_env_max_lds();
 int colour_resident_blocks();
 
 }  // namespace trk

@@ -305,6 +305,10 @@ __global__ void k_step_begin(DevBuffers b, StepParams p)
         for (int k = t; k < (int)(sizeof(Counters) / 4); k += gridDim.x * blockDim.x) w[k] = 0u;
     }
     if (t < p.n_envs) { b.env_stats[t].contacts = 0; b.env_stats[t].pairs = 0; }
+    if (t < p.n_units) {
+        uint32_t* w = reinterpret_cast<uint32_t*>(&b.ustats[t]);
+        for (int k = 0; k < (int)(sizeof(UnitStats) / 4); ++k) w[k] = 0u;
+    }
     if (t < p.n_shapes) {
 #pragma clang fp contract(off)
         ShapeDev& S = b.shapes[t];
@@ -321,7 +325,7 @@ __global__ void k_step_begin(DevBuffers b, StepParams p)
 
 void launch_step_begin(const DevBuffers& b, const StepParams& p, hipStream_t s)
 {
-    int n = std::max((int)(sizeof(Counters) / 4), std::max(p.n_shapes, p.n_envs));
+    int n = std::max((int)(sizeof(Counters) / 4), std::max(p.n_shapes, std::max(p.n_envs, p.n_units)));
     hipLaunchKernelGGL(k_step_begin, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, s, b, p);
 }
 
@@ -688,13 +692,115 @@ __global__ void k_col_scatter(DevBuffers b, int64_t cap, int64_t NB, uint32_t id
     b.cpos[c] = b.col_start[(int64_t)my * NB + blockIdx.x] + rank;
 }
 
+// env e's contacts in canonical order: [id_start[e id_cap], id_start[(e+1) id_cap])
+__device__ inline void env_contacts(const DevBuffers& b, int e, uint32_t id_cap, uint32_t& beg, uint32_t& end)
+{
+    beg = b.id_start[(size_t)e * id_cap];
+    end = b.id_start[(size_t)(e + 1) * id_cap];
+}
+
+// colours used by each env (one block per env): max colour + 1
+__global__ void k_env_ncol(DevBuffers b, uint32_t id_cap)
+{
+    __shared__ int sm[kBlk / 64];
+    uint32_t beg, end;
+    env_contacts(b, blockIdx.x, id_cap, beg, end);
+    int m = 0;
+    for (uint32_t c = beg + threadIdx.x; c < end; c += blockDim.x) m = max(m, b.colour[c] + 1);
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_down(m, o, 64));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = max(m, sm[w]);
+        b.env_ncol[blockIdx.x] = (uint32_t)min(m, kMaxColours);
+    }
+}
+
+// Per-env stable counting sort of the canonical list by colour (one block per
+// env): env_col[e][k] = first colour-order position of colour k in env e, and
+// cpos[c] the position of canonical contact c.  The rank among equal colours
+// keeps canonical order: inside a wave from the lanes with the same colour
+// (a 7-bit ballot match), across waves and chunks from running counts.
+constexpr int kSortWaves = kBlk / 64;
+
+__global__ __launch_bounds__(kBlk) void k_env_colsort(DevBuffers b, uint32_t id_cap)
+{
+    __shared__ uint32_t base[kMaxColours + 1];
+    __shared__ uint32_t wcount[kSortWaves][kMaxColours + 1];
+    __shared__ int failed;
+    const int e = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t beg, end;
+    env_contacts(b, e, id_cap, beg, end);
+    for (int k = threadIdx.x; k <= kMaxColours; k += blockDim.x) base[k] = 0;
+    if (threadIdx.x == 0) failed = 0;
+    __syncthreads();
+    // histogram (colour kMaxColours collects failed colourings)
+    for (uint32_t c = beg + threadIdx.x; c < end; c += blockDim.x) {
+        int col = b.colour[c];
+        if (col < 0 || col >= kMaxColours) { col = kMaxColours; failed = 1; }
+        atomicAdd(&base[col], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = beg, ncol = 0;
+        for (int k = 0; k <= kMaxColours; ++k) {
+            uint32_t n = base[k];
+            base[k] = run;
+            if (k < kMaxColours) b.env_col[(size_t)e * (kMaxColours + 1) + k] = run;
+            if (n && k < kMaxColours) ncol = k + 1;
+            run += n;
+        }
+        b.env_col[(size_t)e * (kMaxColours + 1) + kMaxColours] = base[kMaxColours];
+        b.env_ncol[e] = ncol;
+    }
+    __syncthreads();
+    for (uint32_t c0 = beg; c0 < end; c0 += blockDim.x) {
+        uint32_t c = c0 + threadIdx.x;
+        int col = kMaxColours + 1;  // past the end: matches no real colour
+        if (c < end) {
+            col = b.colour[c];
+            if (col < 0 || col >= kMaxColours) col = kMaxColours;
+        }
+        unsigned long long same = ~0ull;
+        for (int bit = 0; bit < 7; ++bit) {
+            unsigned long long m = __ballot((col >> bit) & 1);
+            same &= ((col >> bit) & 1) ? m : ~m;
+        }
+        unsigned long long lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        uint32_t rank = (uint32_t)__popcll(same & lower);
+        bool leader = (same & lower) == 0;
+        for (int k = lane; k <= kMaxColours; k += 64) wcount[wave][k] = 0;
+        __syncthreads();
+        if (leader && col <= kMaxColours) wcount[wave][col] = (uint32_t)__popcll(same);
+        __syncthreads();
+        if (c < end) {
+            uint32_t off = base[col] + rank;
+            for (int w = 0; w < wave; ++w) off += wcount[w][col];
+            b.cpos[c] = failed ? c : off;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k <= kMaxColours; k += blockDim.x) {
+            uint32_t t = 0;
+            for (int w = 0; w < kSortWaves; ++w) t += wcount[w][k];
+            base[k] += t;
+        }
+        __syncthreads();
+    }
+}
+
 void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
 {
     launch_fill_u32((uint32_t*)b.colour, 0xFFFFFFFFu, z.C, s);
     hipLaunchKernelGGL(k_colour, dim3(z.col_grid), dim3(kBlk), 0, s, b, z.C, 100000);
+    if (z.pgs_mode == kModePerEnv) {
+        hipLaunchKernelGGL(k_env_colsort, dim3((unsigned)z.n_envs), dim3(kBlk), 0, s, b, p.id_cap);
+        return;
+    }
     hipLaunchKernelGGL(k_col_hist, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB, p.id_cap);
     launch_scan_u32(b.col_hist, b.col_start, (int64_t)kBuckets * z.NB, b.scan_tmp, s);
     hipLaunchKernelGGL(k_col_scatter, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB, p.id_cap);
+    hipLaunchKernelGGL(k_env_ncol, dim3((unsigned)z.n_envs), dim3(kBlk), 0, s, b, p.id_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -904,18 +1010,29 @@ void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z,
 // ---------------------------------------------------------------------------
 // A9: persistent projected Gauss-Seidel.  Sweeps x colours; inside a colour
 // no two contacts share a dynamic particle, so every contact updates its two
-// bodies without atomics.
+// bodies without atomics, and any schedule of a colour's contacts gives the
+// same result.
 //
-// Envs are split into kGroups independent groups (block b serves group b % 8,
-// which is also its XCD), each with its own colour barrier counter, so the
-// barrier traffic is spread over eight counters.  Bodies are read and written
-// with device-coherent (sc1) 128-bit accesses: measured on MI355X, L2-scoped
-// (sc0) loads return stale data across CUs.  Contact c of a colour is always
-// handled by the same thread, so its rows (read-only) and impulses
-// (thread-owned) use the ordinary caches, and the first contact of the next
-// colour is fetched while the block waits at the barrier.  The residual R_k = ||d lambda||_D / ||lambda||_D of each sweep
-// is reduced per block in fixed order and combined identically by every block
-// of the group, which then all take the same stopping decision.
+// A solve is run by a cluster of blocks that meet at a counter barrier after
+// every colour.  Grouped mode: envs are split into kGroups groups, group g
+// runs on the blocks b with b % 8 == g.  Per-env mode: every env has its own
+// cluster (one block for most envs, whose bodies then sit in LDS and whose
+// barrier is a workgroup barrier).  On MI355X consecutive blocks of a launch
+// go to the 8 XCDs in turn, so a cluster whose blocks are congruent mod 8
+// shares one XCD and its L2: bodies
+// are then written with ordinary stores (write-through to that L2) and read
+// with device-scope (sc1) loads, which miss the per-CU L1; measured, L1-hit
+// loads return data another CU of the XCD has already replaced, and sc1
+// stores cost twice the solve time.  Each cluster checks its placement once
+// per launch and falls back to agent-scope fences around its barriers when a
+// block is not on the expected XCD.
+//
+// Contact c of a colour is always handled by the same thread, so its rows
+// (read-only) and impulses (thread-owned) use the ordinary caches, and the
+// rows of the next contact are in flight while the current one is updated.
+// The residual R_k = ||d lambda||_D / ||lambda||_D of each sweep is reduced
+// per block in a fixed order and combined identically by every block of the
+// cluster, which then all take the same stopping decision.
 // ---------------------------------------------------------------------------
 constexpr int kPgsBlk = 512;
 constexpr int kCoherent = 16;  // cache-policy bits of a device-scope (sc1) access
@@ -936,6 +1053,9 @@ __device__ inline void st_body(__amdgpu_buffer_rsrc_t r, int idx, float4 v)
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, idx * 16, 0, AUX);
 }
 
+// XCD (accelerator complex die) this wave runs on
+__device__ inline unsigned xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 0xf; }
+
 // Bounded wait for a barrier counter to reach target; false on timeout or
 // when another block has reported a failed barrier.
 __device__ inline bool wait_counter(Counters* cnt, uint32_t* counter, unsigned target)
@@ -954,6 +1074,47 @@ __device__ inline bool wait_counter(Counters* cnt, uint32_t* counter, unsigned t
     return true;
 }
 
+// Cluster barrier on counter[0] (zeroed before the launch).  Arrive drains
+// this block's stores; wait returns false when the barrier failed.
+template <bool FENCED>
+__device__ inline void cluster_arrive(uint32_t* counter)
+{
+    if (FENCED) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool FENCED>
+__device__ inline bool cluster_wait(Counters* cnt, uint32_t* counter, unsigned target, int& flag)
+{
+    if (threadIdx.x == 0) flag = wait_counter(cnt, counter, target) ? 1 : 0;
+    __syncthreads();
+    if (FENCED) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return flag != 0;
+}
+
+// First barrier of a launch: every block of the cluster sets the bit of its
+// XCD in counter[1] (zeroed before the launch).  The round-robin dispatch
+// puts blocks congruent mod 8 on one XCD, but which XCD depends on the
+// launches before, so only "one XCD for the whole cluster" is checked.
+// Returns 1 for XCD-local accesses, 2 for the fenced fallback, 0 when the
+// barrier failed; uniform over the cluster.
+__device__ inline int cluster_placement(Counters* cnt, uint32_t* counter, unsigned size, int& flag)
+{
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_or(&counter[1], 1u << xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        flag = 0;
+        if (wait_counter(cnt, counter, size)) {
+            uint32_t xcds = __hip_atomic_load(&counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            flag = __popc(xcds) == 1 ? 1 : 2;
+        }
+    }
+    __syncthreads();
+    return flag;
+}
+
 struct RowRegs {
     float4 a, r1, q, L, k;
 };
@@ -969,18 +1130,42 @@ __device__ inline RowRegs load_rows(const DevBuffers& b, uint32_t c)
     return R;
 }
 
-template <int AUX>
-__device__ inline void pgs_contact(const DevBuffers& b, __amdgpu_buffer_rsrc_t rv, __amdgpu_buffer_rsrc_t rw, uint32_t c,
-                                   const RowRegs& R, float mu, float gdt, float& num, float& den)
+// Body state accessors of the contact update.  Xcd: sc1 loads and ordinary
+// stores, for clusters whose blocks share one XCD.  Plain: ordinary accesses,
+// for a solve confined to one block (its waves share one CU and its L1) or
+// ordered by agent-scope fences.  Lds: the env's bodies staged in LDS.
+struct XcdBodies {
+    __amdgpu_buffer_rsrc_t rv, rw;
+    __device__ float4 v(int i) const { return ld_body<kCoherent>(rv, i); }
+    __device__ float4 w(int i) const { return ld_body<kCoherent>(rw, i); }
+    __device__ void set(int i, float4 v, float4 w) const { st_body<0>(rv, i, v); st_body<0>(rw, i, w); }
+};
+struct PlainBodies {
+    float4 *pv, *pw;
+    __device__ float4 v(int i) const { return pv[i]; }
+    __device__ float4 w(int i) const { return pw[i]; }
+    __device__ void set(int i, float4 v, float4 w) const { pv[i] = v; pw[i] = w; }
+};
+struct LdsBodies {
+    float4 *sv, *sw;  // env slots [base, base + n)
+    int base;
+    __device__ float4 v(int i) const { return sv[i - base]; }
+    __device__ float4 w(int i) const { return sw[i - base]; }
+    __device__ void set(int i, float4 v, float4 w) const { sv[i - base] = v; sw[i - base] = w; }
+};
+
+template <class BA>
+__device__ inline void pgs_contact(const DevBuffers& b, const BA& ba, uint32_t c, const RowRegs& R, float mu,
+                                   float gdt, float& num, float& den)
 {
     float4 a = R.a, r1 = R.r1, q = R.q, L = R.L;
     int ia = __float_as_int(q.z), ib = __float_as_int(q.w);
     bool pair = ia >= 0;
-    float4 vb = ld_body<AUX>(rv, ib), wb = ld_body<AUX>(rw, ib);
+    float4 vb = ba.v(ib), wb = ba.w(ib);
     float4 va, wa;
     if (pair) {
-        va = ld_body<AUX>(rv, ia);
-        wa = ld_body<AUX>(rw, ia);
+        va = ba.v(ia);
+        wa = ba.w(ia);
     } else {
         va = make_float4(R.k.x, R.k.y, R.k.z, 0.f);
         wa = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1014,13 +1199,11 @@ __device__ inline void pgs_contact(const DevBuffers& b, __amdgpu_buffer_rsrc_t r
     float cx = ny * dz - nz * dy, cy = nz * dx - nx * dz, cz = nx * dy - ny * dx;  // n x d
     vb.x += dx * vb.w; vb.y += dy * vb.w; vb.z += dz * vb.w;
     wb.x -= l2 * wb.w * cx; wb.y -= l2 * wb.w * cy; wb.z -= l2 * wb.w * cz;
-    st_body<AUX>(rv, ib, vb);
-    st_body<AUX>(rw, ib, wb);
+    ba.set(ib, vb, wb);
     if (pair) {
         va.x -= dx * va.w; va.y -= dy * va.w; va.z -= dz * va.w;
         wa.x -= l1 * wa.w * cx; wa.y -= l1 * wa.w * cy; wa.z -= l1 * wa.w * cz;
-        st_body<AUX>(rv, ia, va);
-        st_body<AUX>(rw, ia, wa);
+        ba.set(ia, va, wa);
     }
     b.lam[c] = make_float4(ln, tx, ty, tz);
     float Dn = 1.0f / iDn, Dt = 1.0f / iDt;
@@ -1028,132 +1211,117 @@ __device__ inline void pgs_contact(const DevBuffers& b, __amdgpu_buffer_rsrc_t r
     den += Dn * ln * ln + Dt * (tx * tx + ty * ty + tz * tz);
 }
 
-__global__ void k_pgs_reset(Counters* cnt)
+// block sums of the sweep's (num, den) in a fixed order, returned to every thread
+template <int NW>
+__device__ inline void block_sum2(float num, float den, double (*red)[NW], double& sn, double& sd)
 {
-    int t = threadIdx.x;
-    if (t < kGroups) cnt->bar[t][0] = 0;
-    if (t == 0) { cnt->bar_global = 0; cnt->xcd_bad = 0; }
+    double dnum = num, dden = den;
+    for (int o = 32; o > 0; o >>= 1) {
+        dnum += __shfl_down(dnum, o, 64);
+        dden += __shfl_down(dden, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = dnum; red[1][threadIdx.x >> 6] = dden; }
+    __syncthreads();
+    sn = 0.0; sd = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { sn += red[0][w]; sd += red[1][w]; }
+    __syncthreads();  // red is reused
 }
 
-// this block's share [lo, hi) of colour col in group g
-__device__ inline void colour_range(const DevBuffers& b, int64_t NB, uint32_t col, int g, unsigned rank, unsigned gx,
-                                    uint32_t& lo, uint32_t& hi)
+// The PGS sweeps of one cluster.  Its contacts of colour col are
+// [cstart.beg(col), cstart.end(col)); the block of rank r of K takes the r-th of K
+// equal slices.  Blocks of the cluster are first + 8 t, t < K.
+template <class BA, bool CLUSTER, bool FENCED, int NW, class Starts>
+__device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba, Starts cstart, uint32_t ncol,
+                          uint32_t* counter, unsigned nbar, unsigned rank, unsigned K, unsigned first, int sweeps_cap,
+                          int slot, int unit, double (*red)[NW], int& flag)
 {
-    int64_t bucket = (int64_t)col * kGroups + g;
-    uint32_t beg = b.col_start[bucket * NB], end = b.col_start[(bucket + 1) * NB];
-    uint32_t len = end - beg;
-    lo = beg + (uint32_t)(((uint64_t)len * rank) / gx);
-    hi = beg + (uint32_t)(((uint64_t)len * (rank + 1)) / gx);
-}
-
-template <int AUX>
-__device__ void pgs_group(const DevBuffers& b, const StepParams& p, int64_t NB, int sweeps_cap, int slot, int g,
-                          unsigned rank, unsigned gx, uint32_t ncol, double (*red)[kPgsBlk / 64], int& stop_flag,
-                          int& bar_ok)
-{
-    __amdgpu_buffer_rsrc_t rv = raw_rsrc(b.vm), rw = raw_rsrc(b.wi);
-    uint32_t* counter = &b.cnt->bar[g][0];
-    unsigned nbar = 0;
     int sweeps = 0;
     double Rk = 0.0, R1 = 0.0;
-    // the rows of the first contact of the next phase are fetched while the
-    // block waits at the barrier (they are read-only or owned by this thread)
-    uint32_t lo = 0, hi = 0;
-    RowRegs pre;
-    uint32_t pc = 0xffffffffu;
+    const unsigned nblk = gridDim.x;
+    auto range = [&](uint32_t col, uint32_t& lo, uint32_t& hi) {
+        uint32_t beg = cstart.beg(col), len = cstart.end(col) - beg;
+        lo = beg + (uint32_t)(((uint64_t)len * rank) / K);
+        hi = beg + (uint32_t)(((uint64_t)len * (rank + 1)) / K);
+    };
+    uint32_t lo = 0, hi = 0, c = 0;
+    RowRegs cur;
     if (ncol > 0) {
-        colour_range(b, NB, 0, g, rank, gx, lo, hi);
-        if (lo + threadIdx.x < hi) { pc = lo + threadIdx.x; pre = load_rows(b, pc); }
+        range(0, lo, hi);
+        c = lo + threadIdx.x;
+        if (c < hi) cur = load_rows(b, c);
     }
 #ifdef TRK_PGS_TRACE
-    unsigned long long tr[5] = {0, 0, 0, 0, 0}, tprev = wall_clock64();
+    unsigned long long tr[4] = {0, 0, 0, 0}, tprev = wall_clock64();
 #endif
-    for (int k = 0; k < sweeps_cap; ++k) {
+    for (int sw = 0; sw < sweeps_cap && ncol > 0; ++sw) {
         float num = 0.f, den = 0.f;
-        double* part = b.block_part + ((size_t)(k & 1) * gridDim.x + (size_t)g * gx) * 2;
+        double* part = b.block_part + (size_t)(sw & 1) * nblk * 2;
         for (uint32_t col = 0; col < ncol; ++col) {
-            for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
-                if (c == pc) pgs_contact<AUX>(b, rv, rw, c, pre, p.mu, p.gamma_dt, num, den);
-                else pgs_contact<AUX>(b, rv, rw, c, load_rows(b, c), p.mu, p.gamma_dt, num, den);
+            while (c < hi) {
+                uint32_t cn = c + blockDim.x;
+                RowRegs nxt;
+                if (cn < hi) nxt = load_rows(b, cn);
+                pgs_contact(b, ba, c, cur, p.mu, p.gamma_dt, num, den);
+                cur = nxt;
+                c = cn;
             }
-            if (col + 1 == ncol) {
-                // block partials of this sweep, published before the last barrier
-                double dnum = num, dden = den;
-                for (int o = 32; o > 0; o >>= 1) {
-                    dnum += __shfl_down(dnum, o, 64);
-                    dden += __shfl_down(dden, o, 64);
+            if (CLUSTER) {
+                if (col + 1 == ncol) {
+                    // block partials of this sweep, published before the last barrier
+                    double sn, sd;
+                    block_sum2<NW>(num, den, red, sn, sd);
+                    if (threadIdx.x == 0) {
+                        __hip_atomic_store(&part[2 * blockIdx.x], sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&part[2 * blockIdx.x + 1], sd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
-                if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = dnum; red[1][threadIdx.x >> 6] = dden; }
+#ifdef TRK_PGS_TRACE
+                unsigned long long ta = wall_clock64();
+#endif
+                cluster_arrive<FENCED>(counter);
+                ++nbar;
+                // the next phase's first rows are fetched while the block waits
+                range(col + 1 < ncol ? col + 1 : 0, lo, hi);
+                c = lo + threadIdx.x;
+                if (c < hi) cur = load_rows(b, c);
+#ifdef TRK_PGS_TRACE
+                unsigned long long tb = wall_clock64();
+#endif
+                if (!cluster_wait<FENCED>(b.cnt, counter, nbar * K, flag)) return;  // every block leaves
+#ifdef TRK_PGS_TRACE
+                unsigned long long tc = wall_clock64();
+                tr[0] += ta - tprev; tr[1] += tb - ta; tr[2] += tc - tb; tr[3] += 1;
+                tprev = tc;
+#endif
+            } else {
+                range(col + 1 < ncol ? col + 1 : 0, lo, hi);
+                c = lo + threadIdx.x;
+                if (c < hi) cur = load_rows(b, c);
                 __syncthreads();
-                if (threadIdx.x == 0) {
-                    double sn = 0.0, sd = 0.0;
-                    for (int w = 0; w < kPgsBlk / 64; ++w) { sn += red[0][w]; sd += red[1][w]; }
-                    __hip_atomic_store(&part[2 * rank], sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(&part[2 * rank + 1], sd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
             }
-            // barrier: drain this block's stores, arrive, prefetch the next
-            // phase's rows, then wait for the rest of the group
-#ifdef TRK_PGS_TRACE
-            unsigned long long ta = wall_clock64();
-#endif
-            __builtin_amdgcn_s_waitcnt(0);
-#ifdef TRK_PGS_TRACE
-            unsigned long long tb = wall_clock64();
-#endif
-            __syncthreads();
-            unsigned target = (nbar + 1) * gx;
-            ++nbar;
-            if (threadIdx.x == 0)
-                __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            colour_range(b, NB, col + 1 < ncol ? col + 1 : 0, g, rank, gx, lo, hi);
-            pc = 0xffffffffu;
-            if (lo + threadIdx.x < hi) { pc = lo + threadIdx.x; pre = load_rows(b, pc); }
-#ifdef TRK_PGS_TRACE
-            unsigned long long tc = wall_clock64();
-#endif
-            if (threadIdx.x == 0) bar_ok = wait_counter(b.cnt, counter, target) ? 1 : 0;
-            __syncthreads();
-#ifdef TRK_PGS_TRACE
-            unsigned long long td = wall_clock64();
-            tr[0] += ta - tprev; tr[1] += tb - ta; tr[2] += tc - tb; tr[3] += td - tc; tr[4] += 1;
-            tprev = td;
-#endif
-            if (!bar_ok) return;  // every block leaves
         }
-        if (ncol == 0) {
-            Rk = 0.0;
+        double sn = 0.0, sd = 0.0;
+        if (CLUSTER) {
+            // every block of the cluster combines the partials in the same order
+            for (unsigned t = 0; t < K; ++t) {
+                sn += __hip_atomic_load(&part[2 * (first + 8 * t)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sd += __hip_atomic_load(&part[2 * (first + 8 * t) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         } else {
-            // every block of the group reduces the group's partials in the same order
-            double sn = 0.0, sd = 0.0;
-            for (unsigned t = threadIdx.x; t < gx; t += blockDim.x) {
-                sn += __hip_atomic_load(&part[2 * t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                sd += __hip_atomic_load(&part[2 * t + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                sn += __shfl_down(sn, o, 64);
-                sd += __shfl_down(sd, o, 64);
-            }
-            __syncthreads();
-            if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = sn; red[1][threadIdx.x >> 6] = sd; }
-            __syncthreads();
-            sn = 0.0; sd = 0.0;
-            for (int w = 0; w < kPgsBlk / 64; ++w) { sn += red[0][w]; sd += red[1][w]; }
-            Rk = sd > 0.0 ? sqrt(sn) / sqrt(sd) : (sn > 0.0 ? 1.0 : 0.0);
+            block_sum2<NW>(num, den, red, sn, sd);
         }
-        if (k == 0) R1 = Rk;
-        sweeps = k + 1;
-        if (threadIdx.x == 0) stop_flag = (p.tol > 0.f && Rk <= (double)p.tol) ? 1 : 0;
-        __syncthreads();
-        if (stop_flag) break;
+        Rk = sd > 0.0 ? sqrt(sn) / sqrt(sd) : (sn > 0.0 ? 1.0 : 0.0);
+        if (sw == 0) R1 = Rk;
+        sweeps = sw + 1;
+        if (p.tol > 0.f && Rk <= (double)p.tol) break;  // uniform: every thread holds the same Rk
     }
 #ifdef TRK_PGS_TRACE
-    if (g == 0 && threadIdx.x == 0 && (rank == 0 || rank == gx - 1) && tr[4] > 0)
-        printf("PGS_TRACE rank %u phases %llu ticks/phase: work %.1f drain %.1f arrive+prefetch %.1f wait %.1f\n", rank,
-               tr[4], (double)tr[0] / tr[4], (double)tr[1] / tr[4], (double)tr[2] / tr[4], (double)tr[3] / tr[4]);
+    if (unit == 0 && threadIdx.x == 0 && (rank == 0 || rank == K - 1) && tr[3] > 0)
+        printf("PGS_TRACE rank %u phases %llu ticks/phase: work %.1f arrive+prefetch %.1f wait %.1f\n", rank, tr[3],
+               (double)tr[0] / tr[3], (double)tr[1] / tr[3], (double)tr[2] / tr[3]);
 #endif
     if (rank == 0 && threadIdx.x == 0) {
-        GroupStats& G = b.cnt->gs[g];
+        UnitStats& G = b.ustats[unit];
         if (slot == 0) {
             G.sweeps = (uint32_t)sweeps;
             G.resid = Rk;
@@ -1164,23 +1332,127 @@ __device__ void pgs_group(const DevBuffers& b, const StepParams& p, int64_t NB, 
     }
 }
 
+__global__ void k_pgs_reset(DevBuffers b, int n_envs)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < kGroups) { b.cnt->bar[t][0] = 0; b.cnt->bar[t][1] = 0; }
+    if (t < n_envs) { b.env_bar[(size_t)t * 16] = 0; b.env_bar[(size_t)t * 16 + 1] = 0; }
+}
+
+// grouped mode: colour col of group g is bucket (col, g) of the bucketing
+struct GroupStarts {
+    const uint32_t* col_start;
+    int64_t NB;
+    int g;
+    __device__ uint32_t beg(uint32_t col) const { return col_start[((int64_t)col * kGroups + g) * NB]; }
+    __device__ uint32_t end(uint32_t col) const { return col_start[((int64_t)col * kGroups + g + 1) * NB]; }
+};
+// per-env mode: colours of one env are consecutive
+struct EnvStarts {
+    const uint32_t* ec;
+    __device__ uint32_t beg(uint32_t col) const { return ec[col]; }
+    __device__ uint32_t end(uint32_t col) const { return ec[col + 1]; }
+};
+
 __global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int64_t NB, int sweeps_cap, int slot)
 {
     __shared__ double red[2][kPgsBlk / 64];
-    __shared__ int stop_flag;
-    __shared__ int bar_ok;
+    __shared__ int flag;
     if (b.cnt->overflow) return;  // uniform: written by earlier kernels only
     const int g = blockIdx.x % kGroups;
     const unsigned rank = blockIdx.x / kGroups, gx = gridDim.x / kGroups;
+    GroupStarts cs{b.col_start, NB, g};
     uint32_t ncol = b.cnt->n_colours;
     // a group without contacts only records its (trivial) statistics
     uint32_t total = 0;
-    for (uint32_t col = 0; col < ncol; ++col) {
-        int64_t bucket = (int64_t)col * kGroups + g;
-        total += b.col_start[(bucket + 1) * NB] - b.col_start[bucket * NB];
-    }
+    for (uint32_t col = 0; col < ncol; ++col) total += cs.end(col) - cs.beg(col);
     if (total == 0) ncol = 0;
-    pgs_group<kCoherent>(b, p, NB, sweeps_cap, slot, g, rank, gx, ncol, red, stop_flag, bar_ok);
+    uint32_t* counter = &b.cnt->bar[g][0];
+    int mode = cluster_placement(b.cnt, counter, gx, flag);
+    if (mode == 1)
+        pgs_solve<XcdBodies, true, false>(b, p, XcdBodies{raw_rsrc(b.vm), raw_rsrc(b.wi)}, cs, ncol, counter, 1, rank,
+                                          gx, (unsigned)g, sweeps_cap, slot, g, red, flag);
+    else if (mode == 2)
+        pgs_solve<PlainBodies, true, true>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, gx,
+                                           (unsigned)g, sweeps_cap, slot, g, red, flag);
+}
+
+// Per-env mode: block b runs the tasks plan[plan_idx[b] .. plan_idx[b + 1])
+// in order, each (env, rank, cluster size, first block of the cluster); a
+// multi-block cluster is always a block's first task, so its blocks start it
+// together.
+__global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p, int sweeps_cap, int slot, int lds_cap)
+{
+    HIP_DYNAMIC_SHARED(float4, dyn_bodies)
+    __shared__ double red[2][kEnvBlk / 64];
+    __shared__ int flag;
+    if (b.cnt->overflow) return;  // uniform: written by earlier kernels only
+    const uint32_t t0 = b.plan_idx[blockIdx.x], t1 = b.plan_idx[blockIdx.x + 1];
+    for (uint32_t t = t0; t < t1; ++t) {
+        const int4 pl = b.plan[t];
+        const int e = pl.x;
+        const unsigned rank = pl.y, K = pl.z, first = pl.w;
+        const EnvDev& E = b.envs[e];
+        EnvStarts cs{b.env_col + (size_t)e * (kMaxColours + 1)};
+        const uint32_t ncol = b.env_ncol[e];
+#ifdef TRK_PGS_TRACE
+        unsigned long long tt0 = wall_clock64();
+#endif
+        if (K > 1) {
+            uint32_t* counter = b.env_bar + (size_t)e * 16;
+            int mode = cluster_placement(b.cnt, counter, K, flag);
+            if (mode == 1)
+                pgs_solve<XcdBodies, true, false>(b, p, XcdBodies{raw_rsrc(b.vm), raw_rsrc(b.wi)}, cs, ncol, counter,
+                                                  1, rank, K, first, sweeps_cap, slot, e, red, flag);
+            else if (mode == 2)
+                pgs_solve<PlainBodies, true, true>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, K,
+                                                   first, sweeps_cap, slot, e, red, flag);
+            if (!flag) return;  // failed barrier: the step is abandoned
+        } else if (E.n <= lds_cap) {
+            LdsBodies ba{dyn_bodies, dyn_bodies + lds_cap, E.slot_begin};
+            for (int i = threadIdx.x; i < E.n; i += blockDim.x) {
+                ba.sv[i] = b.vm[E.slot_begin + i];
+                ba.sw[i] = b.wi[E.slot_begin + i];
+            }
+            __syncthreads();
+            pgs_solve<LdsBodies, false, false>(b, p, ba, cs, ncol, nullptr, 0, 0, 1, blockIdx.x, sweeps_cap, slot, e,
+                                               red, flag);
+            __syncthreads();
+            for (int i = threadIdx.x; i < E.n; i += blockDim.x) {
+                b.vm[E.slot_begin + i] = ba.sv[i];
+                b.wi[E.slot_begin + i] = ba.sw[i];
+            }
+        } else {
+            pgs_solve<PlainBodies, false, false>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, nullptr, 0, 0, 1, blockIdx.x,
+                                                 sweeps_cap, slot, e, red, flag);
+        }
+        __syncthreads();  // LDS and the reduction scratch are reused by the next task
+#ifdef TRK_PGS_TRACE
+        if (threadIdx.x == 0 && sweeps_cap > 1)
+            printf("TASK blk %u task %u env %d n %d K %u rank %u ncol %u contacts %u us %.1f\n", blockIdx.x, t - t0, e,
+                   E.n, K, rank, ncol, cs.beg(ncol) - cs.beg(0), (double)(wall_clock64() - tt0) / 100.0);
+#endif
+    }
+}
+
+int pgs_env_max_lds()
+{
+    int dev = 0, lds = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    return lds;
+}
+
+int pgs_env_resident_blocks(int lds_bytes)
+{
+    int dev = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t pr;
+    (void)hipGetDeviceProperties(&pr, dev);
+    if (lds_bytes > 0)
+        (void)hipFuncSetAttribute((const void*)k_pgs_env, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pgs_env, kEnvBlk, lds_bytes);
+    return std::max(1, per_cu) * pr.multiProcessorCount;
 }
 
 int pgs_resident_blocks(int block)
@@ -1206,7 +1478,14 @@ int colour_resident_blocks()
 void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s, int sweeps_cap, int slot)
 {
     int sw = sweeps_cap < 0 ? p.max_sweeps : sweeps_cap;
-    hipLaunchKernelGGL(k_pgs_reset, dim3(1), dim3(64), 0, s, b.cnt);
+    int nr = std::max(kGroups, z.pgs_mode == kModePerEnv ? z.n_envs : 0);
+    hipLaunchKernelGGL(k_pgs_reset, dim3((unsigned)cdiv(nr, 64)), dim3(64), 0, s, b, z.pgs_mode == kModePerEnv ? z.n_envs : 0);
+    if (z.pgs_mode == kModePerEnv) {
+        if (z.plan_blocks > 0)
+            hipLaunchKernelGGL(k_pgs_env, dim3((unsigned)z.plan_blocks), dim3(kEnvBlk), (size_t)z.lds_cap * 32, s, b,
+                               p, sw, slot, z.lds_cap);
+        return;
+    }
     hipLaunchKernelGGL(k_pgs, dim3(z.pgs_grid), dim3(kPgsBlk), 0, s, b, p, z.NB, sw, slot);
 }
 
@@ -1281,8 +1560,8 @@ __global__ void k_select_start(DevBuffers b, int64_t cap, int mode, uint32_t id_
     if (c >= nc) return;
     bool learned = mode == 1;
     if (mode == 2) {
-        int g = b.envs[env_of(b.pid[__float_as_int(b.r2[c].w)], id_cap)].group;
-        learned = b.cnt->gs[g].use_learned != 0;
+        int u = b.envs[env_of(b.pid[__float_as_int(b.r2[c].w)], id_cap)].unit;
+        learned = b.ustats[u].use_learned != 0;
     }
     b.lam[c] = learned ? b.lamL[c] : b.lam0[c];
 }
@@ -1292,20 +1571,20 @@ void launch_select_start(const DevBuffers& b, const StepParams& p, const Sizes& 
     hipLaunchKernelGGL(k_select_start, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, z.C, mode, p.id_cap);
 }
 
-__global__ void k_choose_start(DevBuffers b)
+__global__ void k_choose_start(DevBuffers b, int n_units)
 {
-    int g = threadIdx.x;
-    if (g >= kGroups) return;
-    GroupStats& G = b.cnt->gs[g];
-    bool finite = ((b.cnt->learn_flags >> g) & 1u) == 0 && isfinite(G.r1_trial[0]);
+    int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_units) return;
+    UnitStats& G = b.ustats[u];
+    bool finite = G.learn_bad == 0 && isfinite(G.r1_trial[0]);
     bool use = finite && !(G.r1_trial[0] > G.r1_trial[1]);
     G.use_learned = use ? 1u : 0u;
     G.fallback = use ? 0u : 1u;
 }
 
-void launch_choose_start(const DevBuffers& b, hipStream_t s)
+void launch_choose_start(const DevBuffers& b, const StepParams& p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_choose_start, dim3(1), dim3(64), 0, s, b);
+    hipLaunchKernelGGL(k_choose_start, dim3((unsigned)cdiv(p.n_units, 64)), dim3(64), 0, s, b, p.n_units);
 }
 
 // training samples of the last step in canonical order: the 12 features and

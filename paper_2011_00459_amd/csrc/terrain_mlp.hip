@@ -203,8 +203,8 @@ __global__ void k_learned_lam(DevBuffers b, StepParams p, int64_t cap)
     float ln = y0 * ls;
     float t0 = (y1 * f1.x + y2 * f2.x) * ls, t1 = (y1 * f1.y + y2 * f2.y) * ls, t2 = (y1 * f1.z + y2 * f2.z) * ls;
     if (!(isfinite(ln) && isfinite(t0) && isfinite(t1) && isfinite(t2))) {
-        int g = b.envs[(uint32_t)b.pid[__float_as_int(q.w)] / p.id_cap].group;
-        atomicOr(&b.cnt->learn_flags, 1u << g);
+        int u = b.envs[(uint32_t)b.pid[__float_as_int(q.w)] / p.id_cap].unit;
+        atomicOr(&b.ustats[u].learn_bad, 1u);
         ln = 0.f; t0 = t1 = t2 = 0.f;
     }
     ln = fmaxf(ln, q.y);

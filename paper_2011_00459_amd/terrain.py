@@ -23,7 +23,9 @@ MLP_PARAMS = 64 * 12 + 64 + 64 * 64 + 64 + 3 * 64 + 3 + 12
 EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodies", "step",
            "get_contact_forces", "get_aggregates", "get_last_error", "get_contacts", "get_particles",
            "set_particles", "set_mlp_weights", "get_phase_times", "set_learned_precision", "get_learn_samples",
-           "mlp_forward", "mlp_grad_scratch_floats", "mlp_loss_grad", "mlp_adam_step")
+           "mlp_forward", "mlp_grad_scratch_floats", "mlp_loss_grad", "mlp_adam_step", "set_solver_config",
+           "get_solver_config", "set_step_graphs")
+PGS_MODE = {"grouped": 0, "per_env": 1}
 MLP_TRAINABLE = MLP_PARAMS - 12
 
 
@@ -69,6 +71,11 @@ class tr_step_stats(C.Structure):
                 ("fallback_used", C.c_int32), ("overflow", C.c_int32)]
 
 
+class tr_solver_config(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("blocks_per_xcd", C.c_int32), ("lds_particles", C.c_int32),
+                ("cluster_particles", C.c_int32)]
+
+
 class tr_aggregate(C.Structure):
     _fields_ = [("zone", C.c_int32), ("pad", C.c_int32), ("n_particles", C.c_int64), ("M", C.c_double),
                 ("x", C.c_double * 3), ("v", C.c_double * 3), ("I", C.c_double * 6), ("w", C.c_double * 3)]
@@ -107,6 +114,9 @@ def lib():
         L.mlp_forward.argtypes = [P, P, C.c_int64, P, C.c_int32, P]
         L.mlp_loss_grad.argtypes = [P, P, P, C.c_int64, P, P, P, C.c_int64, P]
         L.mlp_adam_step.argtypes = [P, P, P, P, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32, P]
+        L.set_solver_config.argtypes = [P, C.POINTER(tr_solver_config)]
+        L.get_solver_config.argtypes = [P, C.POINTER(tr_solver_config)]
+        L.set_step_graphs.argtypes = [P, C.c_int32]
         for name in EXPORTS:
             if name != "get_last_error":
                 getattr(L, name).restype = C.c_int
@@ -319,6 +329,26 @@ class Scene:
         self._check(lib().get_learn_samples(self.h, env, m, feat.ctypes.data_as(fp), lab.ctypes.data_as(fp),
                                             C.byref(n)), "get_learn_samples")
         return feat[:m], lab[:m]
+
+    def get_solver_config(self):
+        c = tr_solver_config()
+        self._check(lib().get_solver_config(self.h, C.byref(c)), "get_solver_config")
+        mode = {v: k for k, v in PGS_MODE.items()}[c.mode]
+        return dict(mode=mode, blocks_per_xcd=c.blocks_per_xcd, lds_particles=c.lds_particles,
+                    cluster_particles=c.cluster_particles)
+
+    def set_solver_config(self, mode=None, blocks_per_xcd=None, lds_particles=None, cluster_particles=None):
+        """Change the PGS schedule; fields left None keep their value."""
+        cur = self.get_solver_config()
+        new = dict(mode=mode, blocks_per_xcd=blocks_per_xcd, lds_particles=lds_particles,
+                   cluster_particles=cluster_particles)
+        cur.update({k: v for k, v in new.items() if v is not None})
+        c = tr_solver_config(PGS_MODE[cur["mode"]], cur["blocks_per_xcd"], cur["lds_particles"],
+                             cur["cluster_particles"])
+        self._check(lib().set_solver_config(self.h, C.byref(c)), "set_solver_config")
+
+    def set_step_graphs(self, enable=True):
+        self._check(lib().set_step_graphs(self.h, 1 if enable else 0), "set_step_graphs")
 
     def get_phase_times(self):
         t = (C.c_float * 5)()
