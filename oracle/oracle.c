@@ -991,7 +991,7 @@ int64_t orc_step(const orc_params* P,
     int sweeps_done = 0;
     double R = 1.0;
     int fallback = 0, learned_used = 0;
-    double r1 = 0.0;
+    double r1 = 0.0, r1_trial[2] = {0.0, 0.0};
 
     /* warm start (A8): cold, previous-step, or learned with fallback */
     for (int64_t c = 0; c < nc; ++c) { rows[c].ln = 0.0; rows[c].lt[0] = rows[c].lt[1] = rows[c].lt[2] = 0.0; }
@@ -1015,9 +1015,14 @@ int64_t orc_step(const orc_params* P,
         row* rl = (row*)malloc((size_t)nc * sizeof(row));
         memcpy(rl, rows, (size_t)nc * sizeof(row));
         for (int64_t c = 0; c < nc; ++c) {
+            /* residual form: the output corrects the previous-step impulse
+             * (inputs 3-5, in the contact frame), so a zero output gives the
+             * previous-step start */
             double ls = lsc[c];
-            rl[c].ln = y[3 * c] * ls;
-            for (int k = 0; k < 3; ++k) rl[c].lt[k] = (y[3 * c + 1] * fr[c][k] + y[3 * c + 2] * fr[c][3 + k]) * ls;
+            const double* f = &F[12 * c];
+            double yn = f[3] + y[3 * c], y1 = f[4] + y[3 * c + 1], y2 = f[5] + y[3 * c + 2];
+            rl[c].ln = yn * ls;
+            for (int k = 0; k < 3; ++k) rl[c].lt[k] = (y1 * fr[c][k] + y2 * fr[c][3 + k]) * ls;
             if (!isfinite(rl[c].ln) || !isfinite(rl[c].lt[0]) || !isfinite(rl[c].lt[1]) || !isfinite(rl[c].lt[2])) finite = 0;
         }
         double* vl = (double*)malloc((size_t)n * 3 * sizeof(double));
@@ -1033,6 +1038,8 @@ int64_t orc_step(const orc_params* P,
         /* reference: previous-step start (cold when there is no cache) */
         apply_start(rows, nc, &M, v, w);
         double r1p = sweep(rows, nc, ncol, cstart, corder, &M, v, w, gamma_dt);
+        r1_trial[0] = r1l;
+        r1_trial[1] = r1p;
         if (finite && !(r1l > r1p)) {
             memcpy(rows, rl, (size_t)nc * sizeof(row));
             memcpy(v, vl, (size_t)n * 3 * sizeof(double));
@@ -1117,6 +1124,8 @@ int64_t orc_step(const orc_params* P,
         st->fallback_used = fallback;
         st->learned_used = learned_used;
         st->r1_first = r1;
+        st->r1_trial[0] = r1_trial[0];
+        st->r1_trial[1] = r1_trial[1];
     }
     free(ltprev); free(lnprev); free(v0);
     free(cstart); free(corder); free(rows);

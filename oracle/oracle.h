@@ -106,6 +106,7 @@ typedef struct orc_stats {
     int32_t fallback_used;
     int32_t learned_used;
     double r1_first;     /* residual after the first sweep */
+    double r1_trial[2];  /* learned start: first-sweep residual of the learned / previous-step start */
 } orc_stats;
 
 typedef struct orc_aggregate {

@@ -67,7 +67,7 @@ class Mlp(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("contacts", C.c_int64), ("pair_contacts", C.c_int64), ("colours", C.c_int32),
                 ("sweeps", C.c_int32), ("residual", C.c_double), ("fallback_used", C.c_int32),
-                ("learned_used", C.c_int32), ("r1_first", C.c_double)]
+                ("learned_used", C.c_int32), ("r1_first", C.c_double), ("r1_trial", C.c_double * 2)]
 
 
 class Aggregate(C.Structure):
@@ -82,7 +82,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        src = os.path.join(HERE, "oracle.c")
+        if not os.path.exists(LIB_PATH) or (os.path.exists(src) and os.path.getmtime(src) > os.path.getmtime(LIB_PATH)):
             build()
         L = C.CDLL(LIB_PATH)
         dp = C.POINTER(C.c_double)
@@ -292,7 +293,7 @@ class OracleScene:
         self.last = dict(keys=keys[:nc].copy(), lam=lam[:nc].copy(), colour=col[:nc].copy(),
                          contacts=st.contacts, pair_contacts=st.pair_contacts, colours=st.colours,
                          sweeps=st.sweeps, residual=st.residual, fallback_used=st.fallback_used,
-                         learned_used=st.learned_used, r1=st.r1_first,
+                         learned_used=st.learned_used, r1=st.r1_first, r1_trial=tuple(st.r1_trial),
                          resid=resid[: st.sweeps].copy(), body_ft=ft[:nb].copy(), aggregates=aggs)
         return self.last
 

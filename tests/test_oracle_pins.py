@@ -545,3 +545,55 @@ def test_mlp_gradient_matches_finite_differences():
             flat[idx] = orig
             fd = (lp - lm) / (2 * eps)
             assert grads[name].reshape(-1)[idx] == pytest.approx(fd, rel=1e-6, abs=1e-10), (name, idx)
+
+
+# --------------------------------------------------------------------------
+# Learned start (residual form): special cases that reduce to the previous-
+# step start
+# --------------------------------------------------------------------------
+def _fork(src, spec, mlp=None, **kw):
+    """A scene in src's state (positions, velocities, contact cache)."""
+    from helpers import with_
+    o = O.OracleScene(with_(spec, **kw), mlp=mlp)
+    o.x, o.v, o.w = src.x.copy(), src.v.copy(), src.w.copy()
+    o.prev_keys, o.prev_lam = src.prev_keys.copy(), src.prev_lam.copy()
+    return o
+
+
+def _zero_net():
+    net = random_mlp(3)
+    net["W3"] = np.zeros((3, 64))
+    net["b3"] = np.zeros(3)
+    return net
+
+
+def test_learned_start_with_zero_output_is_the_previous_step_start():
+    from helpers import settled_column, with_
+    spec = with_(settled_column(seed=31, n=250, footprint=0.5), max_sweeps=30)
+    src = O.OracleScene(with_(spec, warm_start="prev"))
+    src.step()  # builds the contact cache
+    a = _fork(src, spec, warm_start="prev")
+    b = _fork(src, spec, mlp=_zero_net(), warm_start="learned")
+    oa, ob = a.step(), b.step()
+    assert np.array_equal(oa["keys"], ob["keys"]) and oa["sweeps"] == ob["sweeps"]
+    # both trial starts are the previous-step impulses: equal first-sweep residuals
+    r1l, r1p = ob["r1_trial"]
+    assert r1p > 0 and abs(r1l - r1p) <= 1e-12 * r1p
+    scale = max(np.max(np.abs(a.v)), 1e-9)
+    assert np.max(np.abs(a.v - b.v)) <= 1e-12 * scale
+    assert np.max(np.abs(oa["lam"] - ob["lam"])) <= 1e-12 * max(np.max(np.abs(oa["lam"])), 1e-12)
+
+
+def test_learned_start_nonfinite_output_falls_back_to_previous_step_exactly():
+    from helpers import settled_column, with_
+    spec = with_(settled_column(seed=32, n=250, footprint=0.5), max_sweeps=20)
+    src = O.OracleScene(with_(spec, warm_start="prev"))
+    src.step()
+    net = _zero_net()
+    net["b3"] = np.array([np.inf, 0.0, 0.0])
+    a = _fork(src, spec, warm_start="prev")
+    b = _fork(src, spec, mlp=net, warm_start="learned")
+    oa, ob = a.step(), b.step()
+    assert ob["fallback_used"] == 1 and ob["learned_used"] == 0
+    assert np.array_equal(a.v, b.v) and np.array_equal(a.w, b.w)
+    assert np.array_equal(oa["lam"], ob["lam"])
