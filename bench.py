@@ -166,9 +166,70 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
-def tol_rate(sc, mode, k, cap):
-    """steps/s of the same bed stepping to R_k <= 1e-4 (cap sweeps)."""
-    return None
+def mlp_throughput(n=1 << 22):
+    """The learned-start network on MFMA (BF16 inference) and the FP32
+    training kernels: device time per call from HIP events, TFLOP/s."""
+    from paper_2011_00459_amd import learn as LN
+    from paper_2011_00459_amd.devmem import DeviceArray
+    rng = np.random.default_rng(0)
+    w = LN.flatten(LN.init_weights(0))
+    W = DeviceArray.from_host(w)
+    F = DeviceArray.from_host(rng.normal(0, 1, (n, 12)).astype(np.float32))
+    Y = DeviceArray((n, 3))
+    out = {}
+    flops_fwd = 2 * (12 * 64 + 64 * 64 + 64 * 3)
+    for name, bf16 in (("bf16_mfma_forward", True), ("fp32_forward", False)):
+        T.mlp_forward(W.ptr, F.ptr, n, Y.ptr, bf16=bf16)
+        device_sync()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            T.mlp_forward(W.ptr, F.ptr, n, Y.ptr, bf16=bf16)
+        device_sync()
+        dt = (time.perf_counter() - t0) / 5
+        tf = flops_fwd * n / dt / 1e12
+        peak = 2500.0 if bf16 else 157.3
+        out[name] = dict(samples=n, ms=1e3 * dt, tflops=tf, peak_tflops=peak, frac=tf / peak)
+    B = 1 << 16
+    ns = T.mlp_grad_scratch_floats(B)
+    G, L, S = DeviceArray(T.MLP_TRAINABLE), DeviceArray(1), DeviceArray(ns)
+    lab = DeviceArray.from_host(rng.normal(0, 1, (B, 3)).astype(np.float32))
+    T.mlp_loss_grad(W.ptr, F.ptr, lab.ptr, B, G.ptr, L.ptr, S.ptr, ns)
+    device_sync()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        T.mlp_loss_grad(W.ptr, F.ptr, lab.ptr, B, G.ptr, L.ptr, S.ptr, ns)
+    device_sync()
+    dt = (time.perf_counter() - t0) / 10
+    tf = 3 * flops_fwd * B / dt / 1e12  # forward + backward ~ 3x the forward
+    out["fp32_train_step"] = dict(samples=B, ms=1e3 * dt, tflops=tf, peak_tflops=157.3, frac=tf / 157.3)
+    return out
+
+
+def learned_eval(args):
+    """Train the learned start on the GPU (column trajectories of the plain
+    solver) and measure steps/s and sweeps to R_k <= 1e-4 with the cold,
+    previous-step and learned starts, each from one shared settled state."""
+    from paper_2011_00459_amd import learn as LN
+    t0 = time.perf_counter()
+    feat, label = LN.gen_dataset(n_envs=16, steps=120, cap=1_000_000, seed=100)
+    tr = LN.Trainer(LN.init_weights(0, LN.input_scale(feat)), feat, LN.residual_targets(feat, label), batch=4096)
+    hist = tr.fit(epochs=20, lr=3e-3, lr_end=2e-4)
+    w = tr.weights()
+    train_s = time.perf_counter() - t0
+    res = {"training": dict(samples=len(feat), epochs=20, loss_first=hist[0], loss_last=hist[-1],
+                            seconds=train_s)}
+    cols = LN.column_batch(8, seed=900)
+    res["columns_1000"] = LN.sweeps_to_tol(cols, weights=w, settle=60, steps=10, tol=1e-4, max_sweeps=4000)
+    specs = SG.batch_specs(seed=3000, n_envs=args.eval_envs, sweeps=100)
+    mat = specs[0]["material"]
+    specs = [dict(s, material=mat) for s in specs]
+    res[f"batched_{args.eval_envs}"] = LN.sweeps_to_tol(specs, weights=w, settle=40, steps=4, tol=1e-4,
+                                                       max_sweeps=3000)
+    for k in ("columns_1000", f"batched_{args.eval_envs}"):
+        r = res[k]
+        r["learned_vs_cold_steps_per_s"] = r["learned"]["steps_per_s"] / r["cold"]["steps_per_s"]
+        r["learned_vs_prev_steps_per_s"] = r["learned"]["steps_per_s"] / r["prev"]["steps_per_s"]
+    return res
 
 
 def main():
@@ -184,6 +245,8 @@ def main():
     ap.add_argument("--workload", choices=("bed", "batched"), default="bed")
     ap.add_argument("--envs", type=int, default=256)
     ap.add_argument("--schedule", default="", help="PGS schedule as JSON (set_solver_config fields)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-start training and evaluation")
+    ap.add_argument("--eval-envs", type=int, default=64, help="batched beds of the warm-start evaluation")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is design-only",
@@ -241,6 +304,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_pgs (persistent colour-synchronous PGS)"},
     }
+    if not args.no_learned:
+        line["mlp"] = mlp_throughput()
+        line["warm_start_to_1e-4"] = learned_eval(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(line), flush=True)

@@ -223,7 +223,9 @@ int set_particles(tr_scene* s, int32_t env, const double* pos, const double* vel
 /* Loads the learned warm-start network (12 -> 64 -> 64 -> 3, SiLU): n = 5199
  * floats laid out W1[64][12], b1[64], W2[64][64], b2[64], W3[3][64], b3[3],
  * in_scale[12] (inputs are multiplied by in_scale).  With warm_start
- * TR_WARM_LEARNED, each step predicts lambda^0, projects it onto the bounds,
+ * TR_WARM_LEARNED, each step predicts lambda^0 in residual form (the three
+ * outputs are added to the previous-step impulse in the contact frame, inputs
+ * 3-5, before scaling by m_eff g dt), projects it onto the bounds,
  * and keeps it only when it is finite and its first-sweep residual does not
  * exceed the previous-step start's (else PREV, or COLD without a cache;
  * step_stats.fallback_used).  Without weights LEARNED behaves as PREV.
@@ -299,6 +301,18 @@ int get_solver_config(tr_scene* s, tr_solver_config* cfg);
  * enable = 0 launches every step eagerly.  With graphs, the phase times of
  * get_phase_times are all recorded around the whole step. */
 int set_step_graphs(tr_scene* s, int32_t enable);
+
+/* Warm start of the following steps (TR_WARM_COLD / PREV / LEARNED). */
+int set_warm_start(tr_scene* s, int32_t mode);
+
+/* Snapshot of the scene's state: particle state and order, the previous-step
+ * contact cache, body poses and flags.  save_state with buf == NULL (or cap
+ * too small: TR_E_CAPACITY) writes only *size.  load_state restores a
+ * snapshot into a scene built with the same envs, particle counts, bodies and
+ * capacities (else TR_E_STATE); the scene then steps exactly as the saved one
+ * would.  Both synchronise. */
+int save_state(tr_scene* s, void* buf, int64_t cap, int64_t* size);
+int load_state(tr_scene* s, const void* buf, int64_t size);
 
 /* Device time (ms, from HIP events on the scene's stream) of the last step's
  * phases: [0] detection+ordering, [1] rows+colouring+warm start, [2] PGS,

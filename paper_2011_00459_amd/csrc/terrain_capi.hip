@@ -1043,6 +1043,137 @@ int set_mlp_weights(tr_scene* s, const float* weights, int64_t n)
     return TR_OK;
 }
 
+int set_warm_start(tr_scene* s, int32_t mode)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (mode < TR_WARM_COLD || mode > TR_WARM_LEARNED) return fail(s, TR_E_INVAL, "set_warm_start: mode");
+    if (s->p.warm != mode) invalidate_graphs(s);
+    s->p.warm = mode;
+    s->desc.warm_start = mode;
+    return TR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Snapshot layout: header, then the arrays that persist across steps, each
+// as raw bytes in this order.
+struct StateHeader {
+    char magic[8];         // "TRSTATE1"
+    int32_t n_envs;
+    int32_t n_bodies;
+    int64_t cap_particles;
+    int64_t cap_contacts;
+    int64_t n_total;
+    int64_t n_cache;       // previous-step contacts
+    int32_t have_prev;
+    int32_t stepped;
+};
+
+struct Span {
+    void* dev;
+    size_t bytes;
+};
+
+// the device arrays of the state, in snapshot order (n_cache known)
+std::vector<Span> state_spans(tr_scene* s, int64_t n_cache)
+{
+    const int64_t n = s->n_total;
+    return {{s->b.xr, sizeof(float4) * n},
+            {s->b.vm, sizeof(float4) * n},
+            {s->b.wi, sizeof(float4) * n},
+            {s->b.pid, sizeof(int) * n},
+            {s->b.rho, sizeof(float) * n},
+            {s->b.id2slot, sizeof(int) * s->z.NID},
+            {s->b.pid_start, sizeof(uint32_t) * (s->z.NID + 1)},
+            {s->b.pkeyc, sizeof(unsigned long long) * n_cache},
+            {s->b.plam, sizeof(float4) * n_cache},
+            {s->b.bodies, sizeof(BodyDev) * s->body_host.size()}};
+}
+
+int64_t state_bytes(tr_scene* s, int64_t n_cache)
+{
+    int64_t t = sizeof(StateHeader) + sizeof(int64_t) * s->desc.n_envs;
+    for (const Span& sp : state_spans(s, n_cache)) t += (int64_t)sp.bytes;
+    return t;
+}
+}  // namespace
+
+extern "C" {
+
+int save_state(tr_scene* s, void* buf, int64_t cap, int64_t* size)
+{
+    if (!s || !size || cap < 0 || (cap > 0 && !buf)) return TR_E_INVAL;
+    s->err.clear();
+    if (s->tables_dirty) {
+        int rc = rebuild_tables(s);
+        if (rc) return rc;
+    }
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    uint32_t n_cache = 0;
+    if (s->have_prev)
+        HIP_CHECK(s, hipMemcpy(&n_cache, s->b.pid_start + s->z.NID, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    *size = state_bytes(s, n_cache);
+    if (!buf) return TR_OK;
+    if (cap < *size) return fail(s, TR_E_CAPACITY, "save_state: buffer too small");
+    char* o = (char*)buf;
+    StateHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, "TRSTATE1", 8);
+    h.n_envs = s->desc.n_envs;
+    h.n_bodies = (int32_t)s->body_host.size();
+    h.cap_particles = s->desc.cap_particles;
+    h.cap_contacts = s->desc.cap_contacts;
+    h.n_total = s->n_total;
+    h.n_cache = n_cache;
+    h.have_prev = s->have_prev ? 1 : 0;
+    h.stepped = s->stepped ? 1 : 0;
+    memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    for (int e = 0; e < s->desc.n_envs; ++e, o += sizeof(int64_t)) memcpy(o, &s->envs[e].n, sizeof(int64_t));
+    for (const Span& sp : state_spans(s, n_cache)) {
+        if (sp.bytes) HIP_CHECK(s, hipMemcpy(o, sp.dev, sp.bytes, hipMemcpyDeviceToHost));
+        o += sp.bytes;
+    }
+    return TR_OK;
+}
+
+int load_state(tr_scene* s, const void* buf, int64_t size)
+{
+    if (!s || !buf || size < (int64_t)sizeof(StateHeader)) return TR_E_INVAL;
+    s->err.clear();
+    StateHeader h;
+    memcpy(&h, buf, sizeof(h));
+    if (memcmp(h.magic, "TRSTATE1", 8) != 0) return fail(s, TR_E_INVAL, "load_state: not a state snapshot");
+    if (s->tables_dirty) {
+        int rc = rebuild_tables(s);
+        if (rc) return rc;
+    }
+    const char* o = (const char*)buf + sizeof(h);
+    bool same = h.n_envs == s->desc.n_envs && h.n_bodies == (int32_t)s->body_host.size() &&
+                h.cap_particles == s->desc.cap_particles && h.cap_contacts == s->desc.cap_contacts &&
+                h.n_total == s->n_total && h.n_cache >= 0 && h.n_cache <= s->z.C &&
+                size == state_bytes(s, h.n_cache);
+    for (int e = 0; same && e < s->desc.n_envs; ++e) {
+        int64_t n;
+        memcpy(&n, o + sizeof(int64_t) * e, sizeof(n));
+        same = n == s->envs[e].n;
+    }
+    if (!same) return fail(s, TR_E_STATE, "load_state: snapshot of a scene with other envs, bodies or capacities");
+    o += sizeof(int64_t) * s->desc.n_envs;
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    for (const Span& sp : state_spans(s, h.n_cache)) {
+        if (sp.bytes) HIP_CHECK(s, hipMemcpy(sp.dev, o, sp.bytes, hipMemcpyHostToDevice));
+        o += sp.bytes;
+    }
+    // the host copy of the body table follows the restored poses
+    HIP_CHECK(s, hipMemcpy(s->body_host.data(), s->b.bodies, sizeof(BodyDev) * s->body_host.size(), hipMemcpyDeviceToHost));
+    s->have_prev = h.have_prev != 0;
+    s->stepped = h.stepped != 0;
+    return TR_OK;
+}
+
 int get_phase_times(tr_scene* s, float* ms, int32_t cap)
 {
     if (!s || !ms || cap < 0) return TR_E_INVAL;

@@ -189,8 +189,9 @@ void launch_mlp_infer(const float* W, const float* feat, float* out, const uint3
 }
 
 // ---------------------------------------------------------------------------
-// lambda^0 of the learned start (colour order): world impulse from the network
-// output in the contact frame, projected onto {ln >= lo, |lt| <= mu |ln|}
+// lambda^0 of the learned start (colour order): world impulse from the
+// previous-step impulse plus the network output in the contact frame, projected
+// onto {ln >= lo, |lt| <= mu |ln|}
 // ---------------------------------------------------------------------------
 __global__ void k_learned_lam(DevBuffers b, StepParams p, int64_t cap)
 {
@@ -198,7 +199,11 @@ __global__ void k_learned_lam(DevBuffers b, StepParams p, int64_t cap)
     uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc || b.cnt->overflow) return;
     float4 f1 = b.frm1[c], f2 = b.frm2[c], a = b.r0[c], q = b.r2[c];
-    float y0 = b.mlp_out[3 * (size_t)c], y1 = b.mlp_out[3 * (size_t)c + 1], y2 = b.mlp_out[3 * (size_t)c + 2];
+    // residual form: the output corrects the previous-step impulse in the
+    // contact frame (inputs 3-5), so a zero output is the previous-step start
+    const float* fc = b.feat + (size_t)c * 12;
+    float y0 = fc[3] + b.mlp_out[3 * (size_t)c], y1 = fc[4] + b.mlp_out[3 * (size_t)c + 1],
+          y2 = fc[5] + b.mlp_out[3 * (size_t)c + 2];
     float ls = f1.w;
     float ln = y0 * ls;
     float t0 = (y1 * f1.x + y2 * f2.x) * ls, t1 = (y1 * f1.y + y2 * f2.y) * ls, t2 = (y1 * f1.z + y2 * f2.z) * ls;

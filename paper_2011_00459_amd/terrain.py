@@ -24,7 +24,7 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "get_contact_forces", "get_aggregates", "get_last_error", "get_contacts", "get_particles",
            "set_particles", "set_mlp_weights", "get_phase_times", "set_learned_precision", "get_learn_samples",
            "mlp_forward", "mlp_grad_scratch_floats", "mlp_loss_grad", "mlp_adam_step", "set_solver_config",
-           "get_solver_config", "set_step_graphs")
+           "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state")
 PGS_MODE = {"grouped": 0, "per_env": 1}
 MLP_TRAINABLE = MLP_PARAMS - 12
 
@@ -117,6 +117,9 @@ def lib():
         L.set_solver_config.argtypes = [P, C.POINTER(tr_solver_config)]
         L.get_solver_config.argtypes = [P, C.POINTER(tr_solver_config)]
         L.set_step_graphs.argtypes = [P, C.c_int32]
+        L.set_warm_start.argtypes = [P, C.c_int32]
+        L.save_state.argtypes = [P, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
+        L.load_state.argtypes = [P, C.c_void_p, C.c_int64]
         for name in EXPORTS:
             if name != "get_last_error":
                 getattr(L, name).restype = C.c_int
@@ -141,28 +144,12 @@ MATERIAL_DEFAULTS = dict(rho=2000.0, mu_t=0.6, mu_r=0.0, c_p=1000.0, E=1e9, nu=0
                          tau_n=0.0, gamma_t=0.0, kappa_c=0.025, kappa_min=1e-4)
 
 
-class _TorchMemory:
-    """Device memory and stream from PyTorch's caching allocator."""
-
-    def __init__(self):
-        import torch  # noqa: F401  (only when the caller asks for it)
-        self.torch = torch
-        self.alloc_cb = ALLOC_FN(self._alloc)
-        self.free_cb = FREE_FN(self._free)
-
-    def _alloc(self, ctx, nbytes, stream):
-        return self.torch.cuda.caching_allocator_alloc(int(nbytes), stream=stream or None)
-
-    def _free(self, ctx, ptr, stream):
-        self.torch.cuda.caching_allocator_delete(ptr)
-
-
 class Scene:
     """One libterrain scene (n_envs independent environments)."""
 
     def __init__(self, n_envs=1, dt=1.0 / 60.0, gravity=(0.0, 0.0, -9.81), max_sweeps=100, tol=0.0,
                  warm_start="cold", material=None, cap_particles=1024, cap_contacts=16384, env_bounds=None,
-                 r_ref=0.0, torch_memory=False, stream=None):
+                 r_ref=0.0, stream=None):
         L = lib()
         d = tr_scene_desc()
         d.n_envs = n_envs
@@ -181,13 +168,7 @@ class Scene:
         self._bounds = np.ascontiguousarray(np.asarray(env_bounds, dtype=np.float64).reshape(n_envs, 6))
         d.env_bounds = self._bounds.ctypes.data_as(C.POINTER(C.c_double))
         d.r_ref = r_ref
-        self._mem = None
-        if torch_memory:
-            self._mem = _TorchMemory()
-            d.alloc_fn = self._mem.alloc_cb
-            d.free_fn = self._mem.free_cb
-            d.stream = self._mem.torch.cuda.current_stream().cuda_stream
-        elif stream is not None:
+        if stream is not None:
             d.stream = stream
         self.n_envs = n_envs
         self.max_sweeps = max_sweeps
@@ -346,6 +327,21 @@ class Scene:
         c = tr_solver_config(PGS_MODE[cur["mode"]], cur["blocks_per_xcd"], cur["lds_particles"],
                              cur["cluster_particles"])
         self._check(lib().set_solver_config(self.h, C.byref(c)), "set_solver_config")
+
+    def set_warm_start(self, mode):
+        self._check(lib().set_warm_start(self.h, WARM[mode] if isinstance(mode, str) else int(mode)), "set_warm_start")
+
+    def save_state(self):
+        """The scene's state as bytes (see load_state)."""
+        n = C.c_int64()
+        self._check(lib().save_state(self.h, None, 0, C.byref(n)), "save_state")
+        buf = C.create_string_buffer(n.value)
+        self._check(lib().save_state(self.h, buf, n.value, C.byref(n)), "save_state")
+        return buf.raw[:n.value]
+
+    def load_state(self, state):
+        buf = C.create_string_buffer(bytes(state), len(state))
+        self._check(lib().load_state(self.h, buf, len(state)), "load_state")
 
     def set_step_graphs(self, enable=True):
         self._check(lib().set_step_graphs(self.h, 1 if enable else 0), "set_step_graphs")

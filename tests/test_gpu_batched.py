@@ -150,3 +150,27 @@ def test_graph_replay_matches_eager_steps(sched, warm):
     gb.step(2)
     for e in range(len(specs)):
         assert np.array_equal(ga.get_particles(e)["v"], gb.get_particles(e)["v"])
+
+
+def test_save_load_state_resumes_exactly():
+    specs = batch(seed0=80, max_sweeps=20, warm_start="prev")
+    g, _ = scene(specs, "per_env_lds")
+    g.step(3)
+    snap = g.save_state()
+    g.step(2)
+    ref = [g.get_particles(e)["v"].copy() for e in range(len(specs))]
+    g.load_state(snap)
+    g.step(2)
+    for e in range(len(specs)):
+        assert np.array_equal(g.get_particles(e)["v"], ref[e])
+    # a fresh scene of the same layout (another schedule) resumes the same way
+    g2, _ = scene(specs, "grouped")
+    g2.load_state(snap)
+    g2.step(2)
+    for e in range(len(specs)):
+        assert np.array_equal(g2.get_particles(e)["v"], ref[e])
+    # a scene with other envs refuses the snapshot
+    g3, _ = scene(specs[:3], "grouped")
+    with pytest.raises(T.TerrainError) as ei:
+        g3.load_state(snap)
+    assert ei.value.code == T.TR_E_STATE
