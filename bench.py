@@ -32,6 +32,20 @@ from paper_2011_00459_amd import terrain as T  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 PAIR_BYTES, BOUND_BYTES = 176, 128
+# HBM traffic of one k_pgs launch on this workload, from the FETCH_SIZE and
+# WRITE_SIZE counter runs scaled by a copy kernel of known size (see
+# profiles/k_pgs_bed50k_hbm_traffic.md); valid only for the kernel source it
+# was measured on, else reported as null.
+PGS_TRAFFIC = {"kernels_sha256_prefix": "46ceeaf37b90b187", "bytes_per_launch": 3.109233e9,
+               "profile": "profiles/k_pgs_bed50k_hbm_traffic.md"}
+
+
+def pgs_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2011_00459_amd", "csrc", "terrain_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return PGS_TRAFFIC["bytes_per_launch"] if sha == PGS_TRAFFIC["kernels_sha256_prefix"] else None
 
 
 def device_sync():
@@ -166,6 +180,26 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_copy(args):
+    """Calibration workload for the HBM traffic counters: device-to-device
+    copies of a known size (the runtime's copy kernel), 256 MiB each."""
+    from paper_2011_00459_amd.devmem import DeviceArray, hip
+    nbytes = 256 << 20
+    a, b = DeviceArray(nbytes // 4), DeviceArray(nbytes // 4)
+    a.zero()
+    h = hip()
+    device_sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rc = h.hipMemcpy(ctypes.c_void_p(b.ptr), ctypes.c_void_p(a.ptr), nbytes, 3)
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpy D2D failed ({rc})")
+    device_sync()
+    wall = time.perf_counter() - t0
+    print(json.dumps({"workload": "copy", "bytes_per_copy": nbytes, "copies": args.steps,
+                      "read_plus_write_GBps": 2 * nbytes * args.steps / wall / 1e9}), flush=True)
+
+
 def mlp_throughput(n=1 << 22):
     """The learned-start network on MFMA (BF16 inference) and the FP32
     training kernels: device time per call from HIP events, TFLOP/s."""
@@ -242,7 +276,7 @@ def main():
     ap.add_argument("--settle", type=int, default=150)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("bed", "batched"), default="bed")
+    ap.add_argument("--workload", choices=("bed", "batched", "copy"), default="bed")
     ap.add_argument("--envs", type=int, default=256)
     ap.add_argument("--schedule", default="", help="PGS schedule as JSON (set_solver_config fields)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start training and evaluation")
@@ -256,6 +290,9 @@ def main():
         args.sweeps = 100 if args.workload == "batched" else 150
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "copy":
+        bench_copy(args)
         return
 
     sc, spec, blade, est_top = build_bed(args)
@@ -301,7 +338,8 @@ def main():
                    "phase_ms": phases,
                    "blade_force_x_N": float(f[0])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": pgs_traffic(),
+                     "algorithmic_bytes_per_launch": pgs_bytes / args.steps,
                      "kernel": "k_pgs (persistent colour-synchronous PGS)"},
     }
     if not args.no_learned:
