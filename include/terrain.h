@@ -287,6 +287,9 @@ typedef struct tr_solver_config {
     int32_t blocks_per_xcd;    /* grouped: >= 1, clamped to the resident limit */
     int32_t lds_particles;     /* per-env: >= 0, clamped to what LDS holds */
     int32_t cluster_particles; /* per-env: T, or 0 for the automatic choice */
+    int32_t dataflow;          /* 1: inside a multi-block solve the colour order of each sphere's
+                                  updates is kept by per-sphere update counters instead of a
+                                  barrier after every colour (same results); 0: barriers */
 } tr_solver_config;
 
 /* Set / read the schedule.  Takes effect at the next step; TR_E_INVAL on a bad

@@ -225,7 +225,10 @@ int rebuild_plan(tr_scene* s)
         if (!alloc_n(s, s->b.plan_idx, (int64_t)plan_idx.size())) return fail(s, TR_E_NOMEM, "PGS plan");
         s->plan_idx_alloc = (int64_t)plan_idx.size();
     }
-    int64_t parts = 4 * std::max<int64_t>(s->z.pgs_grid, blocks);
+    // block partials: two sweeps (barrier order) or one slot per sweep (counter order)
+    s->z.part_sweeps = std::min(std::max(s->desc.max_sweeps, 2), 8192);
+    s->z.flow = s->cfg.dataflow ? 1 : 0;
+    int64_t parts = 2 * std::max<int64_t>(s->z.pgs_grid, blocks) * s->z.part_sweeps;
     if (parts > s->part_alloc) {
         dfree(s, s->b.block_part);
         if (!alloc_n(s, s->b.block_part, parts)) return fail(s, TR_E_NOMEM, "PGS partials");
@@ -501,6 +504,7 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
     s->cfg.blocks_per_xcd = 32;
     s->cfg.lds_particles = s->max_lds_particles;
     s->cfg.cluster_particles = 0;
+    s->cfg.dataflow = 0;
     z.pgs_grid = kGroups * std::max(1, std::min(s->cfg.blocks_per_xcd, pgs_resident_blocks(512) / kGroups));
     z.col_grid = std::min(colour_resident_blocks(), 2048);
     DevBuffers& b = s->b;
@@ -519,7 +523,7 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
               alloc_n(s, b.lam, z.C) && alloc_n(s, b.lam0, z.C) &&
               alloc_n(s, b.envs, d->n_envs) && alloc_n(s, b.ustats, s->p.n_units) &&
               alloc_n(s, b.env_col, (int64_t)d->n_envs * (kMaxColours + 1)) && alloc_n(s, b.env_ncol, d->n_envs) &&
-              alloc_n(s, b.env_bar, (int64_t)d->n_envs * 16) &&
+              alloc_n(s, b.env_bar, (int64_t)d->n_envs * 16) && alloc_n(s, b.ver, z.P) &&
               alloc_n(s, b.cnt, 1) && alloc_n(s, b.env_stats, d->n_envs) && alloc_n(s, b.mlp, kMlpParams) &&
               alloc_n(s, s->staging, 12 * z.P) && alloc_n(s, b.feat, 12 * z.C) && alloc_n(s, b.frm1, z.C) &&
               alloc_n(s, b.frm2, z.C) && alloc_n(s, b.lamL, z.C) && alloc_n(s, b.mlp_out, 3 * z.C) &&
@@ -874,7 +878,7 @@ int set_solver_config(tr_scene* s, const tr_solver_config* cfg)
     if (!s || !cfg) return TR_E_INVAL;
     s->err.clear();
     if ((cfg->mode != TR_PGS_GROUPED && cfg->mode != TR_PGS_PER_ENV) || cfg->blocks_per_xcd < 1 ||
-        cfg->lds_particles < 0 || cfg->cluster_particles < 0)
+        cfg->lds_particles < 0 || cfg->cluster_particles < 0 || (cfg->dataflow != 0 && cfg->dataflow != 1))
         return fail(s, TR_E_INVAL, "set_solver_config: bad field");
     s->cfg = *cfg;
     s->cfg.blocks_per_xcd = std::min(cfg->blocks_per_xcd, std::max(1, pgs_resident_blocks(512) / kGroups));

@@ -9,7 +9,8 @@
 //     raw detection output  rkey[C] u64, rpair[C] int2
 //     canonical (key order) ckey[C] u64, cpair[C] int2, lamc[C] float4
 //     colour order rows     r0 (n, l1), r1 (l2, 1/Dn, 1/Dt, Sigma),
-//                           r2 (q, lo, body1, body2), rk (kinematic velocity), lam (impulses)
+//                           r2 (q, lo, body1, body2), rk (kinematic velocity, update-sequence
+//                           bits), lam (impulses)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -193,6 +194,7 @@ struct DevBuffers {
     int4* plan;           // per-env PGS tasks: (env, rank in its cluster, cluster size, first block)
     uint32_t* plan_idx;   // [blocks + 1]: tasks of block b are plan[plan_idx[b] .. plan_idx[b + 1])
     uint32_t* env_bar;    // [n_envs][16] cluster barrier counters (per-env mode)
+    uint32_t* ver;        // [P] updates applied to each sphere in the current PGS launch
     uint32_t* scan_tmp;   // scratch of the device-wide scan
     float* mlp;           // learned-start weights (kMlpParams)
     // learned start (colour order) and the depth feature
@@ -219,6 +221,8 @@ struct Sizes {
     int plan_blocks;  // blocks of the per-env PGS kernel
     int lds_cap;    // particles whose bodies a per-env block keeps in LDS (0: none)
     int n_units;    // entries of ustats
+    int flow;       // colour order kept by per-sphere update counters instead of barriers
+    int part_sweeps;  // sweeps of block partials held (flow: one slot per sweep)
     int col_grid;   // resident blocks of the colouring kernel
     int64_t NCOL;   // depth columns (all envs)
 };

@@ -304,7 +304,7 @@ __global__ void k_step_begin(DevBuffers b, StepParams p)
         uint32_t* w = reinterpret_cast<uint32_t*>(b.cnt);
         for (int k = t; k < (int)(sizeof(Counters) / 4); k += gridDim.x * blockDim.x) w[k] = 0u;
     }
-    if (t < p.n_envs) { b.env_stats[t].contacts = 0; b.env_stats[t].pairs = 0; }
+    if (t < p.n_envs) { b.env_stats[t].contacts = 0; b.env_stats[t].pairs = 0; b.env_ncol[t] = 0; }
     if (t < p.n_units) {
         uint32_t* w = reinterpret_cast<uint32_t*>(&b.ustats[t]);
         for (int k = 0; k < (int)(sizeof(UnitStats) / 4); ++k) w[k] = 0u;
@@ -699,20 +699,29 @@ __device__ inline void env_contacts(const DevBuffers& b, int e, uint32_t id_cap,
     end = b.id_start[(size_t)(e + 1) * id_cap];
 }
 
-// colours used by each env (one block per env): max colour + 1
-__global__ void k_env_ncol(DevBuffers b, uint32_t id_cap)
+// colours used by each env (zeroed at the step's start): max colour + 1 over
+// the canonical list; a block whose contacts all belong to one env (the
+// list is in env order) reduces first and updates once
+__global__ void k_env_ncol(DevBuffers b, int64_t cap, uint32_t id_cap)
 {
     __shared__ int sm[kBlk / 64];
-    uint32_t beg, end;
-    env_contacts(b, blockIdx.x, id_cap, beg, end);
-    int m = 0;
-    for (uint32_t c = beg + threadIdx.x; c < end; c += blockDim.x) m = max(m, b.colour[c] + 1);
+    uint32_t nc = n_contacts(b, cap);
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c0 = blockIdx.x * blockDim.x;
+    if (c0 >= nc) return;
+    uint32_t c1 = min(nc, c0 + blockDim.x) - 1;
+    int e0 = (int)env_of((int)(b.ckey[c0] >> 32), id_cap), e1 = (int)env_of((int)(b.ckey[c1] >> 32), id_cap);
+    int m = c < nc ? b.colour[c] + 1 : 0;
+    if (e0 != e1) {
+        if (c < nc && m > 0) atomicMax(&b.env_ncol[env_of((int)(b.ckey[c] >> 32), id_cap)], (uint32_t)min(m, kMaxColours));
+        return;
+    }
     for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_down(m, o, 64));
     if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = max(m, sm[w]);
-        b.env_ncol[blockIdx.x] = (uint32_t)min(m, kMaxColours);
+        if (m > 0) atomicMax(&b.env_ncol[e0], (uint32_t)min(m, kMaxColours));
     }
 }
 
@@ -800,7 +809,7 @@ void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hip
     hipLaunchKernelGGL(k_col_hist, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB, p.id_cap);
     launch_scan_u32(b.col_hist, b.col_start, (int64_t)kBuckets * z.NB, b.scan_tmp, s);
     hipLaunchKernelGGL(k_col_scatter, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB, p.id_cap);
-    hipLaunchKernelGGL(k_env_ncol, dim3((unsigned)z.n_envs), dim3(kBlk), 0, s, b, p.id_cap);
+    hipLaunchKernelGGL(k_env_ncol, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, p.id_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -957,7 +966,24 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     b.r0[pos] = make_float4(nf[0], nf[1], nf[2], (float)l1);
     b.r1[pos] = make_float4((float)l2, (float)(1.0 / Dn), (float)(1.0 / Dt), (float)Sig);
     b.r2[pos] = make_float4((float)q, (float)lo, __int_as_float(ia), __int_as_float(ib));
-    b.rk[pos] = make_float4((float)vk[0], (float)vk[1], (float)vk[2], (float)Dn);
+    // the contact's place in the colour-ordered update sequence of each of its
+    // spheres (position among the sphere's contacts, and their count), for
+    // the counter-ordered PGS
+    uint32_t seq = 0;
+    {
+        const int col = b.colour[c];
+        uint32_t pa = 0, da = 0, pb = 0, db = 0;
+        auto place = [&](int sl, uint32_t& pr, uint32_t& dg) {
+            uint32_t beg = b.inc_start[sl], end = b.inc_start[sl + 1];
+            dg = end - beg;
+            for (uint32_t t = beg; t < end; ++t) pr += b.colour[b.inc[t]] < col ? 1u : 0u;
+        };
+        if (ia >= 0) place(ia, pa, da);
+        place(ib, pb, db);
+        if (da > 255 || db > 255) atomicOr(&b.cnt->overflow, kOvfHits);
+        seq = pa | (pb << 8) | (da << 16) | (db << 24);
+    }
+    b.rk[pos] = make_float4((float)vk[0], (float)vk[1], (float)vk[2], __uint_as_float(seq));
     b.lam[pos] = L;
     b.lam0[pos] = L;
 }
@@ -1227,10 +1253,35 @@ __device__ inline void block_sum2(float num, float den, double (*red)[NW], doubl
     __syncthreads();  // red is reused
 }
 
+// Counter-ordered updates: contact c is update number s deg_j + pos_j of
+// sphere j in sweep s (pos_j: its rank among j's contacts by colour), so it
+// may run once j's counter shows that many updates; afterwards it drains its
+// stores and advances the counters.  This keeps the colour order of every
+// sphere's updates without barriers between colours.  The waits are bounded
+// and give up when another wait has failed.
+__device__ inline bool flow_wait(Counters* cnt, const uint32_t* ver, int j, uint32_t want)
+{
+    long spins = 0;
+    while (__hip_atomic_load(&ver[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 255) == 0) {
+            if (__hip_atomic_load(&cnt->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFailBarrier)
+                return false;
+            if (spins > kBarrierSpins) {
+                atomicOr(&cnt->overflow, kFailBarrier);
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
 // The PGS sweeps of one cluster.  Its contacts of colour col are
 // [cstart.beg(col), cstart.end(col)); the block of rank r of K takes the r-th of K
-// equal slices.  Blocks of the cluster are first + 8 t, t < K.
-template <class BA, bool CLUSTER, bool FENCED, int NW, class Starts>
+// equal slices.  Blocks of the cluster are first + 8 t, t < K.  FLOW: colours
+// are ordered by the per-sphere counters (clusters only); a barrier remains at
+// the end of a sweep when a residual tolerance is set, and once at the end.
+template <class BA, bool CLUSTER, bool FENCED, bool FLOW, int NW, class Starts>
 __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba, Starts cstart, uint32_t ncol,
                           uint32_t* counter, unsigned nbar, unsigned rank, unsigned K, unsigned first, int sweeps_cap,
                           int slot, int unit, double (*red)[NW], int& flag)
@@ -1238,11 +1289,21 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
     int sweeps = 0;
     double Rk = 0.0, R1 = 0.0;
     const unsigned nblk = gridDim.x;
+    bool alive = true;
     auto range = [&](uint32_t col, uint32_t& lo, uint32_t& hi) {
         uint32_t beg = cstart.beg(col), len = cstart.end(col) - beg;
         lo = beg + (uint32_t)(((uint64_t)len * rank) / K);
         hi = beg + (uint32_t)(((uint64_t)len * (rank + 1)) / K);
     };
+    auto combine = [&](int sw, double& sn, double& sd) {
+        const double* part = b.block_part + (size_t)(FLOW ? sw : (sw & 1)) * nblk * 2;
+        sn = 0.0; sd = 0.0;
+        for (unsigned t = 0; t < K; ++t) {
+            sn += __hip_atomic_load(&part[2 * (first + 8 * t)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sd += __hip_atomic_load(&part[2 * (first + 8 * t) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    };
+    auto resid = [](double sn, double sd) { return sd > 0.0 ? sqrt(sn) / sqrt(sd) : (sn > 0.0 ? 1.0 : 0.0); };
     uint32_t lo = 0, hi = 0, c = 0;
     RowRegs cur;
     if (ncol > 0) {
@@ -1255,17 +1316,33 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
 #endif
     for (int sw = 0; sw < sweeps_cap && ncol > 0; ++sw) {
         float num = 0.f, den = 0.f;
-        double* part = b.block_part + (size_t)(sw & 1) * nblk * 2;
+        double* part = b.block_part + (size_t)(FLOW ? sw : (sw & 1)) * nblk * 2;
         for (uint32_t col = 0; col < ncol; ++col) {
             while (c < hi) {
                 uint32_t cn = c + blockDim.x;
                 RowRegs nxt;
                 if (cn < hi) nxt = load_rows(b, cn);
-                pgs_contact(b, ba, c, cur, p.mu, p.gamma_dt, num, den);
+                if (FLOW) {
+                    const uint32_t seq = __float_as_uint(cur.k.w);
+                    const int ia = __float_as_int(cur.q.z), ib = __float_as_int(cur.q.w);
+                    const uint32_t wa = (uint32_t)sw * ((seq >> 16) & 255u) + (seq & 255u);
+                    const uint32_t wb = (uint32_t)sw * (seq >> 24) + ((seq >> 8) & 255u);
+                    if (alive) alive = flow_wait(b.cnt, b.ver, ib, wb) && (ia < 0 || flow_wait(b.cnt, b.ver, ia, wa));
+                    if (alive) {
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // body loads after the counters
+                        pgs_contact(b, ba, c, cur, p.mu, p.gamma_dt, num, den);
+                        __builtin_amdgcn_s_waitcnt(0);  // the sphere state has reached the XCD's L2
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                        __hip_atomic_store(&b.ver[ib], wb + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (ia >= 0) __hip_atomic_store(&b.ver[ia], wa + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                } else {
+                    pgs_contact(b, ba, c, cur, p.mu, p.gamma_dt, num, den);
+                }
                 cur = nxt;
                 c = cn;
             }
-            if (CLUSTER) {
+            if (CLUSTER && !FLOW) {
                 if (col + 1 == ncol) {
                     // block partials of this sweep, published before the last barrier
                     double sn, sd;
@@ -1297,23 +1374,46 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
                 c = lo + threadIdx.x;
                 if (c < hi) cur = load_rows(b, c);
-                __syncthreads();
+                if (!CLUSTER) __syncthreads();
             }
         }
         double sn = 0.0, sd = 0.0;
-        if (CLUSTER) {
-            // every block of the cluster combines the partials in the same order
-            for (unsigned t = 0; t < K; ++t) {
-                sn += __hip_atomic_load(&part[2 * (first + 8 * t)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                sd += __hip_atomic_load(&part[2 * (first + 8 * t) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        } else {
+        if (FLOW) {
             block_sum2<NW>(num, den, red, sn, sd);
+            if (threadIdx.x == 0) {
+                __hip_atomic_store(&part[2 * blockIdx.x], sn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&part[2 * blockIdx.x + 1], sd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            sweeps = sw + 1;
+            if (p.tol > 0.f) {
+                // the stopping test needs every block's partial of this sweep
+                cluster_arrive<false>(counter);
+                ++nbar;
+                if (!cluster_wait<false>(b.cnt, counter, nbar * K, flag)) return;
+                combine(sw, sn, sd);
+                Rk = resid(sn, sd);
+                if (sw == 0) R1 = Rk;
+                if (Rk <= (double)p.tol) break;  // uniform: every block holds the same Rk
+            }
+            continue;
         }
-        Rk = sd > 0.0 ? sqrt(sn) / sqrt(sd) : (sn > 0.0 ? 1.0 : 0.0);
+        if (CLUSTER) combine(sw, sn, sd);
+        else block_sum2<NW>(num, den, red, sn, sd);
+        Rk = resid(sn, sd);
         if (sw == 0) R1 = Rk;
         sweeps = sw + 1;
         if (p.tol > 0.f && Rk <= (double)p.tol) break;  // uniform: every thread holds the same Rk
+    }
+    if (FLOW && ncol > 0 && !(p.tol > 0.f)) {
+        // fixed sweep count: the first and last residuals once every block is done
+        cluster_arrive<false>(counter);
+        ++nbar;
+        if (!cluster_wait<false>(b.cnt, counter, nbar * K, flag)) return;
+        double sn, sd;
+        combine(0, sn, sd);
+        R1 = resid(sn, sd);
+        combine(sweeps - 1, sn, sd);
+        Rk = resid(sn, sd);
     }
 #ifdef TRK_PGS_TRACE
     if (unit == 0 && threadIdx.x == 0 && (rank == 0 || rank == K - 1) && tr[3] > 0)
@@ -1354,7 +1454,8 @@ struct EnvStarts {
     __device__ uint32_t end(uint32_t col) const { return ec[col + 1]; }
 };
 
-__global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int64_t NB, int sweeps_cap, int slot)
+__global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int64_t NB, int sweeps_cap, int slot,
+                                                   int flow)
 {
     __shared__ double red[2][kPgsBlk / 64];
     __shared__ int flag;
@@ -1369,19 +1470,26 @@ __global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int
     if (total == 0) ncol = 0;
     uint32_t* counter = &b.cnt->bar[g][0];
     int mode = cluster_placement(b.cnt, counter, gx, flag);
-    if (mode == 1)
-        pgs_solve<XcdBodies, true, false>(b, p, XcdBodies{raw_rsrc(b.vm), raw_rsrc(b.wi)}, cs, ncol, counter, 1, rank,
-                                          gx, (unsigned)g, sweeps_cap, slot, g, red, flag);
+    if (mode == 1) {
+        XcdBodies ba{raw_rsrc(b.vm), raw_rsrc(b.wi)};
+        if (flow)
+            pgs_solve<XcdBodies, true, false, true>(b, p, ba, cs, ncol, counter, 1, rank, gx, (unsigned)g, sweeps_cap,
+                                                    slot, g, red, flag);
+        else
+            pgs_solve<XcdBodies, true, false, false>(b, p, ba, cs, ncol, counter, 1, rank, gx, (unsigned)g,
+                                                     sweeps_cap, slot, g, red, flag);
+    }
     else if (mode == 2)
-        pgs_solve<PlainBodies, true, true>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, gx,
-                                           (unsigned)g, sweeps_cap, slot, g, red, flag);
+        pgs_solve<PlainBodies, true, true, false>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, gx,
+                                                  (unsigned)g, sweeps_cap, slot, g, red, flag);
 }
 
 // Per-env mode: block b runs the tasks plan[plan_idx[b] .. plan_idx[b + 1])
 // in order, each (env, rank, cluster size, first block of the cluster); a
 // multi-block cluster is always a block's first task, so its blocks start it
 // together.
-__global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p, int sweeps_cap, int slot, int lds_cap)
+__global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p, int sweeps_cap, int slot, int lds_cap,
+                                                      int flow)
 {
     HIP_DYNAMIC_SHARED(float4, dyn_bodies)
     __shared__ double red[2][kEnvBlk / 64];
@@ -1401,12 +1509,16 @@ __global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p,
         if (K > 1) {
             uint32_t* counter = b.env_bar + (size_t)e * 16;
             int mode = cluster_placement(b.cnt, counter, K, flag);
-            if (mode == 1)
-                pgs_solve<XcdBodies, true, false>(b, p, XcdBodies{raw_rsrc(b.vm), raw_rsrc(b.wi)}, cs, ncol, counter,
-                                                  1, rank, K, first, sweeps_cap, slot, e, red, flag);
+            XcdBodies xb{raw_rsrc(b.vm), raw_rsrc(b.wi)};
+            if (mode == 1 && flow)
+                pgs_solve<XcdBodies, true, false, true>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap,
+                                                        slot, e, red, flag);
+            else if (mode == 1)
+                pgs_solve<XcdBodies, true, false, false>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap,
+                                                         slot, e, red, flag);
             else if (mode == 2)
-                pgs_solve<PlainBodies, true, true>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, K,
-                                                   first, sweeps_cap, slot, e, red, flag);
+                pgs_solve<PlainBodies, true, true, false>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank,
+                                                          K, first, sweeps_cap, slot, e, red, flag);
             if (!flag) return;  // failed barrier: the step is abandoned
         } else if (E.n <= lds_cap) {
             LdsBodies ba{dyn_bodies, dyn_bodies + lds_cap, E.slot_begin};
@@ -1415,16 +1527,16 @@ __global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p,
                 ba.sw[i] = b.wi[E.slot_begin + i];
             }
             __syncthreads();
-            pgs_solve<LdsBodies, false, false>(b, p, ba, cs, ncol, nullptr, 0, 0, 1, blockIdx.x, sweeps_cap, slot, e,
-                                               red, flag);
+            pgs_solve<LdsBodies, false, false, false>(b, p, ba, cs, ncol, nullptr, 0, 0, 1, blockIdx.x, sweeps_cap,
+                                                      slot, e, red, flag);
             __syncthreads();
             for (int i = threadIdx.x; i < E.n; i += blockDim.x) {
                 b.vm[E.slot_begin + i] = ba.sv[i];
                 b.wi[E.slot_begin + i] = ba.sw[i];
             }
         } else {
-            pgs_solve<PlainBodies, false, false>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, nullptr, 0, 0, 1, blockIdx.x,
-                                                 sweeps_cap, slot, e, red, flag);
+            pgs_solve<PlainBodies, false, false, false>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, nullptr, 0, 0, 1,
+                                                        blockIdx.x, sweeps_cap, slot, e, red, flag);
         }
         __syncthreads();  // LDS and the reduction scratch are reused by the next task
 #ifdef TRK_PGS_TRACE
@@ -1480,13 +1592,16 @@ void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStr
     int sw = sweeps_cap < 0 ? p.max_sweeps : sweeps_cap;
     int nr = std::max(kGroups, z.pgs_mode == kModePerEnv ? z.n_envs : 0);
     hipLaunchKernelGGL(k_pgs_reset, dim3((unsigned)cdiv(nr, 64)), dim3(64), 0, s, b, z.pgs_mode == kModePerEnv ? z.n_envs : 0);
+    // counter-ordered solves keep one partial slot per sweep
+    int flow = z.flow && sw <= z.part_sweeps ? 1 : 0;
+    if (flow && p.n_particles > 0) launch_fill_u32(b.ver, 0u, p.n_particles, s);
     if (z.pgs_mode == kModePerEnv) {
         if (z.plan_blocks > 0)
             hipLaunchKernelGGL(k_pgs_env, dim3((unsigned)z.plan_blocks), dim3(kEnvBlk), (size_t)z.lds_cap * 32, s, b,
-                               p, sw, slot, z.lds_cap);
+                               p, sw, slot, z.lds_cap, flow);
         return;
     }
-    hipLaunchKernelGGL(k_pgs, dim3(z.pgs_grid), dim3(kPgsBlk), 0, s, b, p, z.NB, sw, slot);
+    hipLaunchKernelGGL(k_pgs, dim3(z.pgs_grid), dim3(kPgsBlk), 0, s, b, p, z.NB, sw, slot, flow);
 }
 
 // ---------------------------------------------------------------------------

@@ -73,7 +73,7 @@ class tr_step_stats(C.Structure):
 
 class tr_solver_config(C.Structure):
     _fields_ = [("mode", C.c_int32), ("blocks_per_xcd", C.c_int32), ("lds_particles", C.c_int32),
-                ("cluster_particles", C.c_int32)]
+                ("cluster_particles", C.c_int32), ("dataflow", C.c_int32)]
 
 
 class tr_aggregate(C.Structure):
@@ -316,16 +316,17 @@ class Scene:
         self._check(lib().get_solver_config(self.h, C.byref(c)), "get_solver_config")
         mode = {v: k for k, v in PGS_MODE.items()}[c.mode]
         return dict(mode=mode, blocks_per_xcd=c.blocks_per_xcd, lds_particles=c.lds_particles,
-                    cluster_particles=c.cluster_particles)
+                    cluster_particles=c.cluster_particles, dataflow=c.dataflow)
 
-    def set_solver_config(self, mode=None, blocks_per_xcd=None, lds_particles=None, cluster_particles=None):
+    def set_solver_config(self, mode=None, blocks_per_xcd=None, lds_particles=None, cluster_particles=None,
+                          dataflow=None):
         """Change the PGS schedule; fields left None keep their value."""
         cur = self.get_solver_config()
         new = dict(mode=mode, blocks_per_xcd=blocks_per_xcd, lds_particles=lds_particles,
-                   cluster_particles=cluster_particles)
+                   cluster_particles=cluster_particles, dataflow=None if dataflow is None else int(dataflow))
         cur.update({k: v for k, v in new.items() if v is not None})
         c = tr_solver_config(PGS_MODE[cur["mode"]], cur["blocks_per_xcd"], cur["lds_particles"],
-                             cur["cluster_particles"])
+                             cur["cluster_particles"], cur["dataflow"])
         self._check(lib().set_solver_config(self.h, C.byref(c)), "set_solver_config")
 
     def set_warm_start(self, mode):

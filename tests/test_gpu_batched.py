@@ -19,10 +19,12 @@ pytestmark = pytest.mark.gpu
 T = pytest.importorskip("paper_2011_00459_amd.terrain")
 
 SCHEDULES = {
-    "grouped": dict(mode="grouped", blocks_per_xcd=4),
+    "grouped": dict(mode="grouped", blocks_per_xcd=4, dataflow=0),
+    "grouped_flow": dict(mode="grouped", blocks_per_xcd=4, dataflow=1),
     "per_env_lds": dict(mode="per_env", lds_particles=100000, cluster_particles=0),
     "per_env_global": dict(mode="per_env", lds_particles=0, cluster_particles=0),
-    "per_env_clusters": dict(mode="per_env", lds_particles=350, cluster_particles=150),
+    "per_env_clusters": dict(mode="per_env", lds_particles=350, cluster_particles=150, dataflow=0),
+    "per_env_clusters_flow": dict(mode="per_env", lds_particles=350, cluster_particles=150, dataflow=1),
 }
 
 
@@ -80,7 +82,7 @@ def test_schedules_give_bitwise_identical_states():
                 assert np.array_equal(a, b), (sched, e)
 
 
-@pytest.mark.parametrize("sched", ["per_env_lds", "per_env_clusters"])
+@pytest.mark.parametrize("sched", ["per_env_lds", "per_env_clusters", "per_env_clusters_flow"])
 def test_per_env_tolerance_stops_each_env_on_its_own_residual(sched):
     specs = batch(seed0=50, tol=5e-3, max_sweeps=400)
     g, cap = scene(specs, sched)
@@ -121,6 +123,8 @@ def test_solver_config_validation():
         g.set_solver_config(blocks_per_xcd=0)
     with pytest.raises(T.TerrainError):
         g.set_solver_config(lds_particles=-1)
+    with pytest.raises(T.TerrainError):
+        g.set_solver_config(dataflow=2)
     g.set_solver_config(mode="per_env", lds_particles=10 ** 9)
     c = g.get_solver_config()
     assert c["mode"] == "per_env" and 0 < c["lds_particles"] < 10 ** 9  # clamped to what LDS holds

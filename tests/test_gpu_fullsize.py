@@ -1,0 +1,87 @@
+"""Parity at the workloads' full sizes, in the launch configuration bench.py times.
+
+  - 50,400-sphere jammed bed with a blade (the bulldozing bed's size, 150 sweeps,
+    grouped schedule): one step against the FP64 oracle — contact lists bit-exact,
+    velocities to the one-step bar;
+  - 500,000-sphere jammed bed (the excavation bed's size and radius): the contact
+    list of a step bit-exact against the oracle's detection, and the momentum
+    balance of the step (pair impulses cancel: the change of total momentum is
+    the gravity impulse plus the boundary impulses the library reports);
+  - blade force on a jammed bed with a moving blade: the first step in every
+    component, and the mean draft force over 1 s (60 steps) within 1 % of the
+    oracle's.
+"""
+import numpy as np
+import pytest
+
+import pyoracle as O
+from helpers import jammed_bed, vel_tol, with_
+
+pytestmark = pytest.mark.gpu
+
+T = pytest.importorskip("paper_2011_00459_amd.terrain")
+
+
+def test_bed50k_one_step_matches_oracle():
+    spec = jammed_bed(seed=21, nx=60, ny=30, nz=28, r0=0.03, sweeps=150)
+    n = len(spec["x"])
+    assert n == 50400
+    g = T.scene_from_specs(spec, cap_contacts=16 * n)
+    assert g.get_solver_config()["mode"] == "grouped"
+    st = g.step(1)[0]
+    o = O.OracleScene(spec)
+    oo = o.step()
+    keys, lam = g.get_contacts(0)
+    assert st["contacts"] == oo["contacts"] > 100000
+    assert np.array_equal(keys, oo["keys"])
+    assert st["colours"] == oo["colours"] and st["sweeps"] == oo["sweeps"] == 150
+    p = g.get_particles(0)
+    assert np.max(np.abs(p["v"] - o.v)) <= vel_tol(o.v)
+    lt = 1e-3 * np.max(np.abs(oo["lam"]))
+    assert np.max(np.abs(lam - oo["lam"])) <= lt
+
+
+def test_bed500k_contacts_bit_exact_and_momentum_balance():
+    spec = jammed_bed(seed=5, nx=100, ny=50, nz=100, r0=0.02, sweeps=200, blade=True)
+    n = len(spec["x"])
+    assert n == 500000
+    g = T.scene_from_specs(spec, cap_contacts=8 * n)
+    before = g.get_particles(0)
+    st = g.step(1)[0]
+    keys, _ = g.get_contacts(0)
+    # the oracle's detection on the same FP32 start state
+    okeys, _ = O.detect(spec, O.CELLS)
+    assert st["contacts"] == len(okeys) > 1_000_000
+    assert np.array_equal(keys, okeys)
+    # pair impulses cancel, so the change of total momentum is the gravity
+    # impulse minus the impulses the kinematic bodies received (FP64 sums)
+    after = g.get_particles(0)
+    r = before["r"].astype(np.float64)
+    m = spec["material"]["rho"] * (4.0 / 3.0) * np.pi * r ** 3
+    dp = np.sum(m[:, None] * (after["v"] - before["v"]), axis=0)
+    grav = np.sum(m) * np.asarray(spec["gravity"], dtype=np.float64) * spec["dt"]
+    fb = sum(np.asarray(g.get_contact_forces(0, b)[0]) for b in range(len(spec["bodies"])))
+    resid = dp - (grav - spec["dt"] * fb)
+    assert np.linalg.norm(resid) <= 1e-3 * np.linalg.norm(grav), (dp, grav, spec["dt"] * fb)
+
+
+def test_blade_force_over_one_second_matches_oracle():
+    # the first step (identical start) to a tight bound in every component; the
+    # mean over 1 s (60 steps: the FP32 and FP64 trajectories separate) to 1 %
+    # in the draft force, the component along the blade's travel (x)
+    spec = jammed_bed(seed=23, nx=30, ny=16, nz=10, r0=0.03, sweeps=150, blade=True)
+    g = T.scene_from_specs(spec)
+    o = O.OracleScene(spec)
+    fg, fo = [], []
+    for k in range(60):
+        g.step(1, stats=False)
+        oo = o.step()
+        f, _ = g.get_contact_forces(0, 1)
+        fg.append(f)
+        fo.append(oo["body_ft"][1][:3])
+        if k == 0:
+            assert np.linalg.norm(fg[0] - fo[0]) <= 1e-3 * np.linalg.norm(fo[0]), (fg[0], fo[0])
+    fg, fo = np.mean(fg, axis=0), np.mean(fo, axis=0)
+    print(f"mean blade force over 1 s: GPU {fg}, oracle {fo}")
+    assert fo[0] < -100.0  # the bed resists the blade moving along +x
+    assert abs(fg[0] - fo[0]) <= 0.01 * abs(fo[0]), (fg, fo)
