@@ -146,6 +146,9 @@ def bench_batched(args):
     sc.step(args.settle, stats=False)
     for e, b in enumerate(moving):
         sc.set_kinematic_bodies(e, b)
+    sc.step(1)
+    if not args.schedule and not args.no_autotune:
+        sc.autotune(steps=2)
     for _ in range(args.warmup):
         sc.step(1)
     device_sync()
@@ -280,6 +283,7 @@ def main():
     ap.add_argument("--envs", type=int, default=256)
     ap.add_argument("--schedule", default="", help="PGS schedule as JSON (set_solver_config fields)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start training and evaluation")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default PGS schedule")
     ap.add_argument("--eval-envs", type=int, default=64, help="batched beds of the warm-start evaluation")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -306,6 +310,10 @@ def main():
     moving["linvel"] = (1.0, 0.0, 0.0)
     bodies = [dict(spec["bodies"][0], id=0), dict(moving, id=1)]
     sc.set_kinematic_bodies(0, bodies)
+    tuned = None
+    if not args.schedule and not args.no_autotune:
+        tuned = sc.autotune(steps=3)  # times the candidate schedules from this state, then restores it
+        sc.set_step_graphs(False)
     for _ in range(args.warmup):
         sc.step(1)
     wall, tot_cs, pgs_bytes, pgs_ms, stats = timed_steps(sc, args.steps)
@@ -335,6 +343,7 @@ def main():
                    "contacts_per_step": last["contacts"], "pair_contacts": last["pair_contacts"],
                    "colours": last["colours"], "sweeps": last["sweeps"],
                    "pgs_ms_per_step": pgs_launch_ms,
+                   "schedule": sc.get_solver_config(), "autotune_ms_per_step": tuned[1] if tuned else None,
                    "phase_ms": phases,
                    "blade_force_x_N": float(f[0])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

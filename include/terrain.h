@@ -305,6 +305,18 @@ int get_solver_config(tr_scene* s, tr_solver_config* cfg);
  * get_phase_times are all recorded around the whole step. */
 int set_step_graphs(tr_scene* s, int32_t enable);
 
+/* Autotuner of the PGS schedule.  Times candidate schedules (grouped with 32,
+ * 16 or 8 blocks per XCD; per-env with automatic, 8192- and 16384-sphere
+ * clusters; per-env without LDS; grouped is left out when a residual
+ * tolerance is set with more than 8 envs, where it would let envs share their
+ * stopping test) over `steps` eager steps each, every
+ * candidate from the scene's current state (saved and restored, so the scene
+ * is left as it was), and keeps the fastest.  With cache_path, a matching
+ * entry (device architecture, log2 of envs, log2 of spheres) is applied
+ * without timing, and a new result is appended as one JSON object per line.
+ * chosen and best_ms (ms per step; -1 from the cache) may be NULL. */
+int autotune(tr_scene* s, int32_t steps, const char* cache_path, tr_solver_config* chosen, float* best_ms);
+
 /* Warm start of the following steps (TR_WARM_COLD / PREV / LEARNED). */
 int set_warm_start(tr_scene* s, int32_t mode);
 

@@ -13,6 +13,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
+    # references inside the library bind to its own definitions (the C-ABI's
+    # `step` shares its name with a C-library function)
+    "-Wl,-Bsymbolic",
 ]
 
 

@@ -777,7 +777,14 @@ int set_step_graphs(tr_scene* s, int32_t enable)
     return TR_OK;
 }
 
-int step(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
+// Library-internal callers use step_scene: the exported name `step` is also a
+// (legacy regex) function of the C library, which a call through the PLT
+// could bind to.
+static int step_scene(tr_scene* s, int32_t n_steps, tr_step_stats* stats);
+
+int step(tr_scene* s, int32_t n_steps, tr_step_stats* stats) { return step_scene(s, n_steps, stats); }
+
+static int step_scene(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
 {
     if (!s) return TR_E_INVAL;
     s->err.clear();
@@ -1175,6 +1182,140 @@ int load_state(tr_scene* s, const void* buf, int64_t size)
     HIP_CHECK(s, hipMemcpy(s->body_host.data(), s->b.bodies, sizeof(BodyDev) * s->body_host.size(), hipMemcpyDeviceToHost));
     s->have_prev = h.have_prev != 0;
     s->stepped = h.stepped != 0;
+    return TR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// autotuner cache: one JSON object per line, keyed by the device architecture
+// and the scene's size bucket (log2 of envs and of spheres)
+struct TuneKey {
+    std::string arch;
+    int envs_log2;
+    int particles_log2;
+};
+
+TuneKey tune_key(tr_scene* s)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t pr;
+    (void)hipGetDeviceProperties(&pr, dev);
+    TuneKey k;
+    k.arch = pr.gcnArchName;
+    for (char& ch : k.arch)
+        if (ch == '"' || ch == '\\' || ch == '\n') ch = '_';
+    k.envs_log2 = ceil_log2(std::max(1, s->desc.n_envs));
+    k.particles_log2 = ceil_log2((int)std::max<int64_t>(1, s->n_total));
+    return k;
+}
+
+bool tune_lookup(const char* path, const TuneKey& k, tr_solver_config* cfg)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        char arch[128];
+        int el, pl;
+        tr_solver_config c;
+        double ms;
+        if (sscanf(line,
+                   "{\"arch\": \"%127[^\"]\", \"envs_log2\": %d, \"particles_log2\": %d, \"mode\": %d, "
+                   "\"blocks_per_xcd\": %d, \"lds_particles\": %d, \"cluster_particles\": %d, \"dataflow\": %d, "
+                   "\"step_ms\": %lf}",
+                   arch, &el, &pl, &c.mode, &c.blocks_per_xcd, &c.lds_particles, &c.cluster_particles, &c.dataflow,
+                   &ms) == 9 &&
+            k.arch == arch && el == k.envs_log2 && pl == k.particles_log2) {
+            *cfg = c;  // the last entry for the key wins
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void tune_store(const char* path, const TuneKey& k, const tr_solver_config& c, double ms)
+{
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f,
+            "{\"arch\": \"%s\", \"envs_log2\": %d, \"particles_log2\": %d, \"mode\": %d, \"blocks_per_xcd\": %d, "
+            "\"lds_particles\": %d, \"cluster_particles\": %d, \"dataflow\": %d, \"step_ms\": %.4f}\n",
+            k.arch.c_str(), k.envs_log2, k.particles_log2, c.mode, c.blocks_per_xcd, c.lds_particles,
+            c.cluster_particles, c.dataflow, ms);
+    fclose(f);
+}
+}  // namespace
+
+extern "C" {
+
+int autotune(tr_scene* s, int32_t steps, const char* cache_path, tr_solver_config* chosen, float* best_ms)
+{
+    if (!s || steps < 1) return TR_E_INVAL;
+    s->err.clear();
+    if (s->tables_dirty) {
+        int rc = rebuild_tables(s);
+        if (rc) return rc;
+    }
+    const TuneKey key = tune_key(s);
+    tr_solver_config c;
+    if (cache_path && tune_lookup(cache_path, key, &c)) {
+        int rc = set_solver_config(s, &c);
+        if (rc) return rc;
+        if (chosen) *chosen = s->cfg;
+        if (best_ms) *best_ms = -1.f;
+        return TR_OK;
+    }
+    // every candidate steps from the same state (restored after each)
+    int64_t size = 0;
+    int rc = save_state(s, nullptr, 0, &size);
+    if (rc) return rc;
+    std::vector<char> snap((size_t)size);
+    rc = save_state(s, snap.data(), size, &size);
+    if (rc) return rc;
+    const tr_solver_config base = s->cfg;
+    const bool graphs = s->use_graphs;
+    s->use_graphs = false;
+    std::vector<tr_solver_config> cands;
+    // grouped mode shares the stopping test of a group's envs: not offered when
+    // that would change results (a residual tolerance with more than 8 envs)
+    if (!(s->desc.tol > 0.0 && s->desc.n_envs > kGroups))
+        for (int bpx : {32, 16, 8}) cands.push_back({TR_PGS_GROUPED, bpx, s->max_lds_particles, 0, 0});
+    for (int cp : {0, 8192, 16384}) cands.push_back({TR_PGS_PER_ENV, 32, s->max_lds_particles, cp, 0});
+    cands.push_back({TR_PGS_PER_ENV, 32, 0, 0, 0});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_CHECK(s, hipEventCreate(&e0));
+    HIP_CHECK(s, hipEventCreate(&e1));
+    int best = -1;
+    float best_t = 0.f;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        if (set_solver_config(s, &cands[i]) != TR_OK || load_state(s, snap.data(), size) != TR_OK) continue;
+        if (step_scene(s, 1, nullptr) != TR_OK) continue;  // warm-up
+        (void)hipEventRecord(e0, s->stream);
+        if (step_scene(s, steps, nullptr) != TR_OK) continue;
+        (void)hipEventRecord(e1, s->stream);
+        std::vector<tr_step_stats> st(s->desc.n_envs);
+        if (step_scene(s, 1, st.data()) != TR_OK) continue;  // synchronises; fails on a capacity or barrier failure
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) continue;
+        ms /= (float)steps;
+        if (best < 0 || ms < best_t) { best = (int)i; best_t = ms; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    s->err.clear();
+    tr_solver_config pick = best >= 0 ? cands[best] : base;
+    rc = set_solver_config(s, &pick);
+    if (rc == TR_OK) rc = load_state(s, snap.data(), size);
+    s->use_graphs = graphs;
+    if (rc) return rc;
+    if (best < 0) return fail(s, TR_E_STATE, "autotune: no candidate schedule completed");
+    if (cache_path) tune_store(cache_path, key, s->cfg, best_t);
+    if (chosen) *chosen = s->cfg;
+    if (best_ms) *best_ms = best_t;
     return TR_OK;
 }
 

@@ -24,7 +24,7 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "get_contact_forces", "get_aggregates", "get_last_error", "get_contacts", "get_particles",
            "set_particles", "set_mlp_weights", "get_phase_times", "set_learned_precision", "get_learn_samples",
            "mlp_forward", "mlp_grad_scratch_floats", "mlp_loss_grad", "mlp_adam_step", "set_solver_config",
-           "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state")
+           "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state", "autotune")
 PGS_MODE = {"grouped": 0, "per_env": 1}
 MLP_TRAINABLE = MLP_PARAMS - 12
 
@@ -120,6 +120,7 @@ def lib():
         L.set_warm_start.argtypes = [P, C.c_int32]
         L.save_state.argtypes = [P, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
         L.load_state.argtypes = [P, C.c_void_p, C.c_int64]
+        L.autotune.argtypes = [P, C.c_int32, C.c_char_p, C.POINTER(tr_solver_config), C.POINTER(C.c_float)]
         for name in EXPORTS:
             if name != "get_last_error":
                 getattr(L, name).restype = C.c_int
@@ -343,6 +344,14 @@ class Scene:
     def load_state(self, state):
         buf = C.create_string_buffer(bytes(state), len(state))
         self._check(lib().load_state(self.h, buf, len(state)), "load_state")
+
+    def autotune(self, steps=3, cache_path=None):
+        """Pick the fastest PGS schedule (see the C header); returns (config, ms per step or -1 if cached)."""
+        c = tr_solver_config()
+        ms = C.c_float()
+        path = None if cache_path is None else os.fspath(cache_path).encode()
+        self._check(lib().autotune(self.h, steps, path, C.byref(c), C.byref(ms)), "autotune")
+        return self.get_solver_config(), float(ms.value)
 
     def set_step_graphs(self, enable=True):
         self._check(lib().set_step_graphs(self.h, 1 if enable else 0), "set_step_graphs")

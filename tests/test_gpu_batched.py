@@ -178,3 +178,25 @@ def test_save_load_state_resumes_exactly():
     with pytest.raises(T.TerrainError) as ei:
         g3.load_state(snap)
     assert ei.value.code == T.TR_E_STATE
+
+
+def test_autotune_keeps_state_caches_and_changes_nothing(tmp_path):
+    specs = batch(seed0=90, max_sweeps=20, warm_start="prev")
+    cache = tmp_path / "tune.jsonl"
+    g, _ = scene(specs, "grouped")
+    g.step(2)
+    before = [g.get_particles(e)["v"].copy() for e in range(len(specs))]
+    cfg, ms = g.autotune(steps=2, cache_path=cache)
+    assert ms > 0.0 and cache.exists()
+    for e in range(len(specs)):  # the scene is left as it was
+        assert np.array_equal(g.get_particles(e)["v"], before[e])
+    g2, _ = scene(specs, "per_env_lds")
+    g2.step(2)
+    cfg2, ms2 = g2.autotune(steps=2, cache_path=cache)
+    assert ms2 == -1.0 and cfg2 == cfg  # taken from the cache
+    # a tuned schedule gives the same states as any other
+    g.step(2)
+    g3, _ = scene(specs, "grouped")
+    g3.step(4)
+    for e in range(len(specs)):
+        assert np.array_equal(g.get_particles(e)["v"], g3.get_particles(e)["v"])
