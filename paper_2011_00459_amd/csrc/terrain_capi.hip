@@ -148,11 +148,11 @@ void invalidate_graphs(tr_scene* s)
     s->graphs = false;
 }
 
-// PGS schedule: the solve unit of every env and, in per-env mode, the task
-// plan of the resident blocks.  Envs larger than T particles per block get a
-// cluster of ceil(n / T) blocks in one XCD lane (indices congruent mod 8, so
-// they share an XCD); the others, largest first, go to the least loaded block
-// and run there one after another.
+// PGS schedule: the solve unit of every env and, in per-env mode, the plan of
+// the resident blocks.  Envs larger than T spheres per block get a cluster of
+// ceil(n / T) blocks in one XCD lane (indices congruent mod 8, so they share
+// an XCD); the others are packed into sets that one block solves at once,
+// each env on its own waves.
 int rebuild_plan(tr_scene* s)
 {
     invalidate_graphs(s);
@@ -168,41 +168,81 @@ int rebuild_plan(tr_scene* s)
         int B = std::max(kGroups, pgs_env_resident_blocks(lds_cap * 32));
         B -= B % kGroups;
         const int per_lane = B / kGroups;
+        const int waves = kEnvBlk / 64;
         double total = 0.0;
         for (int e = 0; e < E; ++e) total += (double)s->envs[e].n;
-        // particles per block: envs above it are split into clusters
-        double T = s->cfg.cluster_particles > 0 ? (double)s->cfg.cluster_particles : std::max(total / B, 4096.0);
         std::vector<int> order;
         for (int e = 0; e < E; ++e)
             if (s->envs[e].n > 0) order.push_back(e);
         std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return s->envs[a].n > s->envs[c].n; });
+        // T: spheres per block (the mean load).  Envs above T get ceil(n / T)
+        // blocks of one XCD lane; the rest are packed (first fit, largest first)
+        // into sets of at most T spheres and 16 envs, each solved by one block at
+        // once, placed largest first on the least loaded block (a cluster share
+        // counts twice its spheres: measured, a block of a multi-block solve is
+        // about half as fast per sphere as one solving a set from LDS).
+        const double T = s->cfg.cluster_particles > 0 ? (double)s->cfg.cluster_particles
+                                                       : std::max(total / B, 4096.0);
         std::vector<std::vector<int4>> tasks(B);
         std::vector<double> load(B, 0.0);
         std::vector<int> lane_next(kGroups, 0);
+        std::vector<std::vector<int>> sets;
+        std::vector<double> fill;
         for (int e : order) {
-            int64_t n = s->envs[e].n;
-            int K = (int)std::min<double>(std::ceil((double)n / T), (double)per_lane);
+            const double n = (double)s->envs[e].n;
+            int K = (int)std::min<double>(std::ceil(n / T), (double)per_lane);
             int lane = 0;
             for (int x = 1; x < kGroups; ++x)
                 if (lane_next[x] < lane_next[lane]) lane = x;
             K = std::min(K, per_lane - lane_next[lane]);
             if (K >= 2) {
-                // a cluster: K blocks of one lane (block indices congruent mod 8)
-                int first = lane + kGroups * lane_next[lane];
+                const int first = lane + kGroups * lane_next[lane];
                 for (int r = 0; r < K; ++r) {
-                    int blk = first + kGroups * r;
-                    tasks[blk].push_back(make_int4(e, r, K, first));
-                    load[blk] += (double)n / K;
+                    tasks[first + kGroups * r].push_back(make_int4(e, r, K, first));
+                    load[first + kGroups * r] += 2.0 * n / K;
                 }
                 lane_next[lane] += K;
                 continue;
             }
-            // a single-block task onto the least loaded block
-            int best = 0;
-            for (int blk = 1; blk < B; ++blk)
-                if (load[blk] < load[best]) best = blk;
-            tasks[best].push_back(make_int4(e, 0, 1, best));
-            load[best] += (double)n;
+            size_t k = 0;
+            while (k < sets.size() && (fill[k] + n > T || (int)sets[k].size() >= waves)) ++k;
+            if (k == sets.size()) {
+                sets.emplace_back();
+                fill.push_back(0.0);
+            }
+            sets[k].push_back(e);
+            fill[k] += n;
+        }
+        std::vector<size_t> sorder(sets.size());
+        for (size_t k = 0; k < sets.size(); ++k) sorder[k] = k;
+        std::stable_sort(sorder.begin(), sorder.end(), [&](size_t a, size_t c) { return fill[a] > fill[c]; });
+        for (size_t k : sorder) {
+            const std::vector<int>& st = sets[k];
+            int blk = 0;
+            for (int i = 1; i < B; ++i)
+                if (load[i] < load[blk]) blk = i;
+            load[blk] += fill[k];
+            // waves in proportion to the envs' spheres, at least one each
+            std::vector<int> w(st.size(), 1);
+            int left = waves - (int)st.size();
+            while (left > 0) {
+                size_t best = 0;
+                double bv = -1.0;
+                for (size_t i = 0; i < st.size(); ++i) {
+                    double v = (double)s->envs[st[i]].n / w[i];
+                    if (v > bv) { bv = v; best = i; }
+                }
+                ++w[best];
+                --left;
+            }
+            int wb = 0, off = 0;
+            for (size_t i = 0; i < st.size(); ++i) {
+                int n = (int)s->envs[st[i]].n;
+                int lo = off + n <= lds_cap ? off : -1;  // LDS while the set's bodies fit
+                if (lo >= 0) off += n;
+                tasks[blk].push_back(make_int4(st[i], wb | ((wb + w[i]) << 8), 1, lo));
+                wb += w[i];
+            }
         }
         plan_idx.assign(B + 1, 0);
         for (int blk = 0; blk < B; ++blk) {

@@ -1484,10 +1484,108 @@ __global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int
                                                   (unsigned)g, sweeps_cap, slot, g, red, flag);
 }
 
-// Per-env mode: block b runs the tasks plan[plan_idx[b] .. plan_idx[b + 1])
-// in order, each (env, rank, cluster size, first block of the cluster); a
-// multi-block cluster is always a block's first task, so its blocks start it
-// together.
+// Per-env mode, a set of small envs solved at once by one block: env j of the
+// set runs on waves [wb, we) with its bodies in LDS at offset off (global
+// memory when off < 0).  The envs share the workgroup barrier after every
+// colour (up to the largest colour count of the set) but reduce their own
+// residual, stop on their own and record their own statistics.
+__device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const int4* tasks, int ntask, int sweeps_cap,
+                              int slot, float4* dyn, int lds_cap, double (*red)[kEnvBlk / 64])
+{
+    const int wave = threadIdx.x >> 6;
+    int j = -1;
+    uint32_t maxcol = 0;
+    for (int t = 0; t < ntask; ++t) {
+        const int4 q = tasks[t];
+        const int wb = q.y & 255, we = (q.y >> 8) & 255;
+        if (wave >= wb && wave < we) j = t;
+        maxcol = max(maxcol, b.env_ncol[q.x]);
+    }
+    int e = -1, wb = 0, we = 1, off = -1;
+    if (j >= 0) {
+        const int4 q = tasks[j];
+        e = q.x; wb = q.y & 255; we = (q.y >> 8) & 255; off = q.w;
+    }
+    const uint32_t nthr = 64u * (uint32_t)(we - wb), lt = threadIdx.x - 64u * (uint32_t)wb;
+    const int sb = e >= 0 ? b.envs[e].slot_begin : 0, n = e >= 0 ? b.envs[e].n : 0;
+    LdsBodies lb{dyn + (off >= 0 ? off : 0), dyn + lds_cap + (off >= 0 ? off : 0), sb};
+    PlainBodies gb{b.vm, b.wi};
+    if (off >= 0)
+        for (int i = (int)lt; i < n; i += (int)nthr) {
+            lb.sv[i] = b.vm[sb + i];
+            lb.sw[i] = b.wi[sb + i];
+        }
+    __syncthreads();
+    const uint32_t* ec = b.env_col + (size_t)(e >= 0 ? e : 0) * (kMaxColours + 1);
+    const uint32_t ncol = e >= 0 ? b.env_ncol[e] : 0;
+    bool active = ncol > 0;  // uniform over the env's waves
+    int sweeps = 0;
+    double Rk = 0.0, R1 = 0.0;
+    uint32_t c = 1, hi = 0;
+    RowRegs cur;
+    auto start_col = [&](uint32_t col) {
+        c = ec[col] + lt;
+        hi = ec[col + 1];
+        if (c < hi) cur = load_rows(b, c);
+    };
+    if (active) start_col(0);
+    for (int sw = 0; sw < sweeps_cap; ++sw) {
+        if (!__syncthreads_or(active)) break;
+        float num = 0.f, den = 0.f;
+        for (uint32_t col = 0; col < maxcol; ++col) {
+            if (active && col < ncol) {
+                while (c < hi) {
+                    uint32_t cn = c + nthr;
+                    RowRegs nxt;
+                    if (cn < hi) nxt = load_rows(b, cn);
+                    if (off >= 0) pgs_contact(b, lb, c, cur, p.mu, p.gamma_dt, num, den);
+                    else pgs_contact(b, gb, c, cur, p.mu, p.gamma_dt, num, den);
+                    cur = nxt;
+                    c = cn;
+                }
+                start_col(col + 1 < ncol ? col + 1 : 0);  // the next phase's first rows
+            }
+            __syncthreads();
+        }
+        // the env's residual from its waves' partials, in wave order
+        double dnum = num, dden = den;
+        for (int o = 32; o > 0; o >>= 1) {
+            dnum += __shfl_down(dnum, o, 64);
+            dden += __shfl_down(dden, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) { red[0][wave] = dnum; red[1][wave] = dden; }
+        __syncthreads();
+        if (active) {
+            double sn = 0.0, sd = 0.0;
+            for (int w = wb; w < we; ++w) { sn += red[0][w]; sd += red[1][w]; }
+            Rk = sd > 0.0 ? sqrt(sn) / sqrt(sd) : (sn > 0.0 ? 1.0 : 0.0);
+            if (sw == 0) R1 = Rk;
+            sweeps = sw + 1;
+            if (p.tol > 0.f && Rk <= (double)p.tol) active = false;
+        }
+        __syncthreads();  // red is reused
+    }
+    if (off >= 0)
+        for (int i = (int)lt; i < n; i += (int)nthr) {
+            b.vm[sb + i] = lb.sv[i];
+            b.wi[sb + i] = lb.sw[i];
+        }
+    if (e >= 0 && lt == 0) {
+        UnitStats& G = b.ustats[e];
+        if (slot == 0) {
+            G.sweeps = (uint32_t)sweeps;
+            G.resid = Rk;
+            G.resid_first = R1;
+        } else {
+            G.r1_trial[slot - 1] = R1;
+        }
+    }
+}
+
+// Per-env mode: block b runs plan[plan_idx[b] .. plan_idx[b + 1]) in order: at
+// most one share (env, rank, cluster size K >= 2, first block) of a
+// multi-block cluster, first, then sets of small envs solved at once (entries
+// (env, waves wb | we << 8, 1, LDS offset); a set starts at wb == 0).
 __global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p, int sweeps_cap, int slot, int lds_cap,
                                                       int flow)
 {
@@ -1496,54 +1594,36 @@ __global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p,
     __shared__ int flag;
     if (b.cnt->overflow) return;  // uniform: written by earlier kernels only
     const uint32_t t0 = b.plan_idx[blockIdx.x], t1 = b.plan_idx[blockIdx.x + 1];
-    for (uint32_t t = t0; t < t1; ++t) {
+    uint32_t t = t0;
+    while (t < t1) {
         const int4 pl = b.plan[t];
+        if (pl.z < 2) {
+            uint32_t u = t + 1;
+            while (u < t1 && b.plan[u].z < 2 && (b.plan[u].y & 255) != 0) ++u;
+            pgs_local_set(b, p, b.plan + t, (int)(u - t), sweeps_cap, slot, dyn_bodies, lds_cap, red);
+            __syncthreads();  // LDS and the reduction scratch are reused
+            t = u;
+            continue;
+        }
         const int e = pl.x;
         const unsigned rank = pl.y, K = pl.z, first = pl.w;
-        const EnvDev& E = b.envs[e];
         EnvStarts cs{b.env_col + (size_t)e * (kMaxColours + 1)};
         const uint32_t ncol = b.env_ncol[e];
-#ifdef TRK_PGS_TRACE
-        unsigned long long tt0 = wall_clock64();
-#endif
-        if (K > 1) {
-            uint32_t* counter = b.env_bar + (size_t)e * 16;
-            int mode = cluster_placement(b.cnt, counter, K, flag);
-            XcdBodies xb{raw_rsrc(b.vm), raw_rsrc(b.wi)};
-            if (mode == 1 && flow)
-                pgs_solve<XcdBodies, true, false, true>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap,
-                                                        slot, e, red, flag);
-            else if (mode == 1)
-                pgs_solve<XcdBodies, true, false, false>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap,
-                                                         slot, e, red, flag);
-            else if (mode == 2)
-                pgs_solve<PlainBodies, true, true, false>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank,
-                                                          K, first, sweeps_cap, slot, e, red, flag);
-            if (!flag) return;  // failed barrier: the step is abandoned
-        } else if (E.n <= lds_cap) {
-            LdsBodies ba{dyn_bodies, dyn_bodies + lds_cap, E.slot_begin};
-            for (int i = threadIdx.x; i < E.n; i += blockDim.x) {
-                ba.sv[i] = b.vm[E.slot_begin + i];
-                ba.sw[i] = b.wi[E.slot_begin + i];
-            }
-            __syncthreads();
-            pgs_solve<LdsBodies, false, false, false>(b, p, ba, cs, ncol, nullptr, 0, 0, 1, blockIdx.x, sweeps_cap,
-                                                      slot, e, red, flag);
-            __syncthreads();
-            for (int i = threadIdx.x; i < E.n; i += blockDim.x) {
-                b.vm[E.slot_begin + i] = ba.sv[i];
-                b.wi[E.slot_begin + i] = ba.sw[i];
-            }
-        } else {
-            pgs_solve<PlainBodies, false, false, false>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, nullptr, 0, 0, 1,
-                                                        blockIdx.x, sweeps_cap, slot, e, red, flag);
-        }
-        __syncthreads();  // LDS and the reduction scratch are reused by the next task
-#ifdef TRK_PGS_TRACE
-        if (threadIdx.x == 0 && sweeps_cap > 1)
-            printf("TASK blk %u task %u env %d n %d K %u rank %u ncol %u contacts %u us %.1f\n", blockIdx.x, t - t0, e,
-                   E.n, K, rank, ncol, cs.beg(ncol) - cs.beg(0), (double)(wall_clock64() - tt0) / 100.0);
-#endif
+        uint32_t* counter = b.env_bar + (size_t)e * 16;
+        int mode = cluster_placement(b.cnt, counter, K, flag);
+        XcdBodies xb{raw_rsrc(b.vm), raw_rsrc(b.wi)};
+        if (mode == 1 && flow)
+            pgs_solve<XcdBodies, true, false, true>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap, slot,
+                                                    e, red, flag);
+        else if (mode == 1)
+            pgs_solve<XcdBodies, true, false, false>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap, slot,
+                                                     e, red, flag);
+        else if (mode == 2)
+            pgs_solve<PlainBodies, true, true, false>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, K,
+                                                      first, sweeps_cap, slot, e, red, flag);
+        if (!flag) return;  // failed barrier: the step is abandoned
+        __syncthreads();
+        ++t;
     }
 }
 
