@@ -320,7 +320,10 @@ typedef struct {
     double p[3];         /* contact point */
     double vk[3];        /* kinematic velocity at p (boundary contacts) */
     double Wn, Wt, Dn, Dt, Sig, q, lo, mu;
+    double Wr, rlim;     /* rolling rows: 1/I_1 + 1/I_2, and r mu_r (0: no rolling rows) */
+    double wk[3];        /* angular velocity of the kinematic side (boundary contacts) */
     double ln, lt[3];    /* impulses */
+    double lr[3];        /* rolling (torque) impulse, on body 2; -lr on body 1 */
     int persistent;
     int colour;
 } row;
@@ -440,6 +443,12 @@ static void build_rows(const orc_params* P, const int64_t* id, const double* r, 
         R->Dt = R->Wt + m->gamma_t / dt;
         R->lo = -m->c_p * PI * rmin * rmin * dt;
         R->mu = m->mu_t;
+        /* rolling resistance (Eq. signCoul3): zero relative angular velocity,
+         * the torque impulse bounded by r mu_r |lambda_n|, r the smaller radius */
+        R->Wr = iIa + iIb;
+        R->rlim = m->mu_r * rmin;
+        if (R->a < 0)
+            for (int k = 0; k < 3; ++k) R->wk[k] = bodies[R->body].angvel[k];
     }
 }
 
@@ -457,8 +466,28 @@ static void project(const row* R, double* ln, double lt[3])
     }
 }
 
+/* Project lr onto the disk {|lr| <= r mu_r |ln|}. */
+static void project_r(const row* R, double lr[3])
+{
+    double lim = R->rlim * fabs(R->ln);
+    double m = sqrt(dot3(lr, lr));
+    if (m > lim) {
+        double s = m > 0.0 ? lim / m : 0.0;
+        for (int k = 0; k < 3; ++k) lr[k] *= s;
+    }
+}
+
+/* Apply the torque impulse L (on body 2; -L on body 1). */
+static void apply_torque(const row* R, const inv_mass* M, double* w, const double L[3])
+{
+    for (int k = 0; k < 3; ++k) w[3 * R->b + k] += M->iI[R->b] * L[k];
+    if (R->a >= 0)
+        for (int k = 0; k < 3; ++k) w[3 * R->a + k] -= M->iI[R->a] * L[k];
+}
+
 /* One projected Gauss-Seidel update of one contact (normal row, then the
- * tangential disk row).  Adds the D-weighted change and value to acc. */
+ * tangential disk row, then the rolling row when mu_r > 0).  Adds the
+ * D-weighted change and value to acc. */
 static void pgs_contact(row* R, const inv_mass* M, double* v, double* w, double gamma_dt, double acc[2])
 {
     double u[3];
@@ -488,6 +517,19 @@ static void pgs_contact(row* R, const inv_mass* M, double* v, double* w, double 
     apply_impulse(R, M, v, w, dtv);
     acc[0] += R->Dn * dn * dn + R->Dt * dot3(dtv, dtv);
     acc[1] += R->Dn * R->ln * R->ln + R->Dt * dot3(R->lt, R->lt);
+    if (R->rlim > 0.0) {
+        /* rolling row: relative angular velocity, body 2 minus body 1 */
+        double ur[3];
+        for (int k = 0; k < 3; ++k) ur[k] = w[3 * R->b + k] - (R->a >= 0 ? w[3 * R->a + k] : R->wk[k]);
+        double lr[3];
+        for (int k = 0; k < 3; ++k) lr[k] = R->lr[k] - ur[k] / R->Wr;
+        project_r(R, lr);
+        double dr[3] = {lr[0] - R->lr[0], lr[1] - R->lr[1], lr[2] - R->lr[2]};
+        for (int k = 0; k < 3; ++k) R->lr[k] = lr[k];
+        apply_torque(R, M, w, dr);
+        acc[0] += R->Wr * dot3(dr, dr);
+        acc[1] += R->Wr * dot3(R->lr, R->lr);
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -921,6 +963,12 @@ static void apply_start(row* rows, int64_t nc, const inv_mass* M, double* v, dou
         double J[3];
         for (int k = 0; k < 3; ++k) J[k] = R->ln * R->n[k] + R->lt[k];
         apply_impulse(R, M, v, w, J);
+        if (R->rlim > 0.0) {
+            project_r(R, R->lr);
+            apply_torque(R, M, w, R->lr);
+        } else {
+            R->lr[0] = R->lr[1] = R->lr[2] = 0.0;
+        }
     }
 }
 
@@ -929,13 +977,13 @@ int64_t orc_step(const orc_params* P,
                  double* x, double* v, double* w,
                  int32_t nb, orc_body* bodies,
                  int32_t ns, const orc_shape* shapes,
-                 int64_t nprev, const uint64_t* prev_keys, const double* prev_lam,
+                 int64_t nprev, const uint64_t* prev_keys, const double* prev_lam, const double* prev_lr,
                  const orc_mlp* mlp,
-                 int64_t cap, uint64_t* keys_out, double* lam_out, int32_t* colour_out,
+                 int64_t cap, uint64_t* keys_out, double* lam_out, double* lr_out, int32_t* colour_out,
                  orc_stats* st, double* body_ft,
                  orc_aggregate* agg, int32_t* n_agg, double* resid)
 {
-    if (P->m.mu_r != 0.0 || P->m.restitution != 0.0) return -1;
+    if (P->m.mu_r < 0.0 || P->m.restitution != 0.0) return -1;
     double dt = P->dt;
     inv_mass M;
     make_inv_mass(P, n, r, rho, &M);
@@ -956,9 +1004,12 @@ int64_t orc_step(const orc_params* P,
     /* previous-step impulses, matched by key */
     double* ltprev = (double*)calloc((size_t)(nc > 0 ? nc : 1) * 3, sizeof(double));
     double* lnprev = (double*)calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+    double* lrprev = (double*)calloc((size_t)(nc > 0 ? nc : 1) * 3, sizeof(double));
     for (int64_t c = 0; c < nc; ++c) {
         int64_t k = nprev > 0 ? find_prev(nprev, prev_keys, rows[c].key) : -1;
         rows[c].persistent = k >= 0;
+        if (k >= 0 && prev_lr)
+            for (int j = 0; j < 3; ++j) lrprev[3 * c + j] = prev_lr[3 * k + j];
         if (k >= 0) {
             lnprev[c] = prev_lam[4 * k];
             for (int j = 0; j < 3; ++j) ltprev[3 * c + j] = prev_lam[4 * k + 1 + j];
@@ -994,13 +1045,17 @@ int64_t orc_step(const orc_params* P,
     double r1 = 0.0, r1_trial[2] = {0.0, 0.0};
 
     /* warm start (A8): cold, previous-step, or learned with fallback */
-    for (int64_t c = 0; c < nc; ++c) { rows[c].ln = 0.0; rows[c].lt[0] = rows[c].lt[1] = rows[c].lt[2] = 0.0; }
+    for (int64_t c = 0; c < nc; ++c) {
+        rows[c].ln = 0.0;
+        for (int j = 0; j < 3; ++j) rows[c].lt[j] = rows[c].lr[j] = 0.0;
+    }
     int have_prev = 0;
     for (int64_t c = 0; c < nc; ++c) have_prev |= rows[c].persistent;
     if (P->warm == ORC_PREV || P->warm == ORC_LEARNED) {
         for (int64_t c = 0; c < nc; ++c) {
             rows[c].ln = lnprev[c];
             for (int j = 0; j < 3; ++j) rows[c].lt[j] = ltprev[3 * c + j];
+            for (int j = 0; j < 3; ++j) rows[c].lr[j] = lrprev[3 * c + j];
         }
     }
     if (P->warm == ORC_LEARNED && mlp && nc > 0 && P->max_sweeps > 0) {
@@ -1083,6 +1138,7 @@ int64_t orc_step(const orc_params* P,
             for (int k = 0; k < 3; ++k) f[k] = -(Rw->ln * Rw->n[k] + Rw->lt[k]) / dt;
             for (int k = 0; k < 3; ++k) arm[k] = Rw->p[k] - B->pos[k];
             cross3(arm, f, t);
+            for (int k = 0; k < 3; ++k) t[k] -= Rw->lr[k] / dt;  /* the rolling couple */
             for (int k = 0; k < 3; ++k) { body_ft[6 * Rw->body + k] += f[k]; body_ft[6 * Rw->body + 3 + k] += t[k]; }
         }
     }
@@ -1111,6 +1167,8 @@ int64_t orc_step(const orc_params* P,
             lam_out[4 * c] = rows[c].ln;
             for (int k = 0; k < 3; ++k) lam_out[4 * c + 1 + k] = rows[c].lt[k];
         }
+        if (lr_out)
+            for (int k = 0; k < 3; ++k) lr_out[3 * c + k] = rows[c].lr[k];
         if (colour_out) colour_out[c] = rows[c].colour;
     }
     if (st) {
@@ -1127,7 +1185,7 @@ int64_t orc_step(const orc_params* P,
         st->r1_trial[0] = r1_trial[0];
         st->r1_trial[1] = r1_trial[1];
     }
-    free(ltprev); free(lnprev); free(v0);
+    free(ltprev); free(lnprev); free(lrprev); free(v0);
     free(cstart); free(corder); free(rows);
     free(M.im); free(M.iI);
     return nc;

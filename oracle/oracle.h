@@ -37,7 +37,7 @@ enum { ORC_BRUTE = 0, ORC_CELLS = 1 };
 typedef struct orc_material {
     double rho;         /* particle density [kg/m^3] (used when rho array is NULL) */
     double mu_t;        /* Coulomb friction coefficient */
-    double mu_r;        /* rolling resistance (must be 0: rows not modelled) */
+    double mu_r;        /* rolling resistance coefficient (Eq. signCoul3), >= 0 */
     double c_p;         /* particle cohesion [Pa] */
     double E;           /* Young's modulus [Pa] */
     double nu;          /* Poisson's ratio */
@@ -132,19 +132,21 @@ int64_t orc_detect(const orc_params* P, int64_t n, const int64_t* id,
 
 /* One full step.  x, v, w (3n each) and the body poses are updated in place.
  * prev_keys/prev_lam (4 per contact: lambda_n, lambda_t xyz) is the previous
- * step's cache (may be empty).  Outputs: keys_out, lam_out (4 per contact),
- * colour_out (per contact), body_ft (6 per body: force, torque about the body
- * origin, as impulse/dt), agg (one per body that owns a zone, in body order,
- * count returned in *n_agg), resid (one per sweep done).
+ * step's cache (may be empty), prev_lr (3 per cached contact, may be NULL) its
+ * rolling impulses.  Outputs: keys_out, lam_out (4 per contact), lr_out (3 per
+ * contact: the rolling torque impulse on body 2, may be NULL), colour_out
+ * (per contact), body_ft (6 per body: force, torque about the body origin, as
+ * impulse/dt), agg (one per body that owns a zone, in body order, count
+ * returned in *n_agg), resid (one per sweep done).
  * Returns the contact count or a negative error. */
 int64_t orc_step(const orc_params* P,
                  int64_t n, const int64_t* id, const double* r, const double* rho,
                  double* x, double* v, double* w,
                  int32_t nb, orc_body* bodies,
                  int32_t ns, const orc_shape* shapes,
-                 int64_t nprev, const uint64_t* prev_keys, const double* prev_lam,
+                 int64_t nprev, const uint64_t* prev_keys, const double* prev_lam, const double* prev_lr,
                  const orc_mlp* mlp,
-                 int64_t cap, uint64_t* keys_out, double* lam_out, int32_t* colour_out,
+                 int64_t cap, uint64_t* keys_out, double* lam_out, double* lr_out, int32_t* colour_out,
                  orc_stats* st, double* body_ft,
                  orc_aggregate* agg, int32_t* n_agg, double* resid);
 

@@ -95,8 +95,8 @@ def lib():
         L.orc_step.restype = C.c_int64
         L.orc_step.argtypes = [C.POINTER(Params), C.c_int64, i64p, dp, dp, dp, dp, dp,
                                C.c_int32, C.POINTER(Body), C.c_int32, C.POINTER(Shape),
-                               C.c_int64, u64p, dp, C.POINTER(Mlp),
-                               C.c_int64, u64p, dp, C.POINTER(C.c_int32), C.POINTER(Stats), dp,
+                               C.c_int64, u64p, dp, dp, C.POINTER(Mlp),
+                               C.c_int64, u64p, dp, dp, C.POINTER(C.c_int32), C.POINTER(Stats), dp,
                                C.POINTER(Aggregate), C.POINTER(C.c_int32), dp]
         L.orc_aggregates.restype = C.c_int32
         L.orc_aggregates.argtypes = [C.c_int64, dp, dp, dp, dp, dp, C.c_int32, C.POINTER(Body),
@@ -252,6 +252,7 @@ class OracleScene:
         self.bb = _Bodies(spec.get("bodies", []))
         self.prev_keys = np.zeros(0, dtype=np.uint64)
         self.prev_lam = np.zeros((0, 4), dtype=np.float64)
+        self.prev_lr = np.zeros((0, 3), dtype=np.float64)
         self.mlp = None
         if mlp is not None:
             self.mlp, self._mlp_keep = mlp_struct(mlp)
@@ -263,6 +264,7 @@ class OracleScene:
         cap = self.cap
         keys = np.zeros(cap, dtype=np.uint64)
         lam = np.zeros((cap, 4), dtype=np.float64)
+        lr = np.zeros((cap, 3), dtype=np.float64)
         col = np.zeros(cap, dtype=np.int32)
         st = Stats()
         nb = self.bb.nb
@@ -274,23 +276,25 @@ class OracleScene:
         mlp_p = C.byref(self.mlp) if self.mlp is not None else C.POINTER(Mlp)()
         pk = np.ascontiguousarray(self.prev_keys)
         pl = np.ascontiguousarray(self.prev_lam)
+        plr = np.ascontiguousarray(self.prev_lr if len(self.prev_lr) == len(pk) else np.zeros((len(pk), 3)))
         nc = L.orc_step(C.byref(self.P), self.n, self.ids.ctypes.data_as(C.POINTER(C.c_int64)),
                         _dp(self.r), rho_p, _dp(self.x), _dp(self.v), _dp(self.w),
                         nb, self.bb.bodies, self.bb.ns, self.bb.shapes,
-                        len(pk), pk.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(pl), mlp_p,
-                        cap, keys.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(lam),
+                        len(pk), pk.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(pl), _dp(plr), mlp_p,
+                        cap, keys.ctypes.data_as(C.POINTER(C.c_uint64)), _dp(lam), _dp(lr),
                         col.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(st), _dp(ft),
                         agg, C.byref(nagg), _dp(resid))
         if nc < 0:
             raise RuntimeError(f"orc_step failed ({nc})")
         self.prev_keys = keys[:nc].copy()
         self.prev_lam = lam[:nc].copy()
+        self.prev_lr = lr[:nc].copy()
         aggs = []
         for a in agg[: nagg.value]:
             aggs.append(dict(zone=a.zone, n_particles=a.n_particles, M=a.M, x=np.array(a.x[:]),
                              v=np.array(a.v[:]), I=np.array(a.I[:]), w=np.array(a.w[:]),
                              L=np.array(a.L[:])))
-        self.last = dict(keys=keys[:nc].copy(), lam=lam[:nc].copy(), colour=col[:nc].copy(),
+        self.last = dict(keys=keys[:nc].copy(), lam=lam[:nc].copy(), lr=lr[:nc].copy(), colour=col[:nc].copy(),
                          contacts=st.contacts, pair_contacts=st.pair_contacts, colours=st.colours,
                          sweeps=st.sweeps, residual=st.residual, fallback_used=st.fallback_used,
                          learned_used=st.learned_used, r1=st.r1_first, r1_trial=tuple(st.r1_trial),

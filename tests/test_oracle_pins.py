@@ -597,3 +597,103 @@ def test_learned_start_nonfinite_output_falls_back_to_previous_step_exactly():
     assert ob["fallback_used"] == 1 and ob["learned_used"] == 0
     assert np.array_equal(a.v, b.v) and np.array_equal(a.w, b.w)
     assert np.array_equal(oa["lam"], ob["lam"])
+
+
+# --------------------------------------------------------------------------
+# Rolling resistance (Eq. signCoul3): closed forms of one sphere, conservation
+# --------------------------------------------------------------------------
+def test_rolling_resistance_decelerates_a_rolling_sphere():
+    r, mu_t, mu_r, v0 = 0.05, 0.5, 0.1, 1.5
+    m = sphere_mass(r)
+    I = 0.4 * m * r * r
+    kn = ESTAR * math.sqrt(2 * r) / 3.0
+    d0 = (m * G / kn) ** (2.0 / 3.0)
+    l = r - d0 / 2
+    spec = base_spec([[0.0, 0.0, r - d0]], [r], [floor_body()], mu=mu_t, v=[[v0, 0.0, 0.0]],
+                     w=[[0.0, v0 / l, 0.0]], sweeps=400, mu_r=mu_r)
+    sc = O.OracleScene(spec)
+    # the rolling couple r mu_r lambda_n (lambda_n = m g dt) against the rolling
+    # inertia about the contact point: dv = -l r mu_r m g dt / (I + m l^2)
+    expect = -l * r * mu_r * m * G * DT / (I + m * l * l)
+    assert expect == pytest.approx(-5.0 / 7.0 * mu_r * G * DT, rel=2e-3)
+    vprev = v0
+    for k in range(25):
+        out = sc.step()
+        assert sc.v[0, 0] - vprev == pytest.approx(expect, rel=1e-6), k
+        assert abs(sc.v[0, 0] - l * sc.w[0, 1]) < 1e-9  # still rolling without slip
+        lr = out["lr"][0]
+        assert np.linalg.norm(lr) == pytest.approx(r * mu_r * m * G * DT, rel=1e-6)  # the bound is active
+        vprev = sc.v[0, 0]
+
+
+def test_rolling_resistance_stops_a_spinning_sphere():
+    # spin about the contact normal: no slip at the contact point, only the
+    # rolling row acts: d omega_z = -r mu_r m g dt / I = -(5/2) mu_r g dt / r
+    r, mu_r, w0 = 0.05, 0.2, 30.0
+    m = sphere_mass(r)
+    kn = ESTAR * math.sqrt(2 * r) / 3.0
+    d0 = (m * G / kn) ** (2.0 / 3.0)
+    spec = base_spec([[0.0, 0.0, r - d0]], [r], [floor_body()], mu=0.5, w=[[0.0, 0.0, w0]], sweeps=5, mu_r=mu_r)
+    sc = O.OracleScene(spec)
+    step = 2.5 * mu_r * G * DT / r
+    wprev = w0
+    for k in range(int(w0 / step) + 3):
+        sc.step()
+        expect = max(wprev - step, 0.0)
+        assert sc.w[0, 2] == pytest.approx(expect, rel=1e-9, abs=1e-9), k
+        wprev = sc.w[0, 2]
+    assert sc.w[0, 2] == 0.0 or abs(sc.w[0, 2]) < 1e-9
+
+
+@pytest.mark.parametrize("mu_r,tan_t,rolls", [(0.3, 0.2, False), (0.1, 0.5, True)])
+def test_rolling_resistance_on_an_incline(mu_r, tan_t, rolls):
+    th = math.atan(tan_t)
+    r = 0.05
+    m = sphere_mass(r)
+    I = 0.4 * m * r * r
+    kn = ESTAR * math.sqrt(2 * r) / 3.0
+    d0 = (m * G * math.cos(th) / kn) ** (2.0 / 3.0)
+    nrm = np.array([math.sin(th), 0.0, math.cos(th)])
+    x0 = (r - d0) * nrm
+    spec = base_spec([x0], [r], [incline_hfield(tan_t)], mu=0.8, sweeps=400, mu_r=mu_r)
+    sc = O.OracleScene(spec)
+    sdir = np.array([math.cos(th), 0.0, -math.sin(th)])
+    l = r - d0 / 2
+    a = (m * G * math.sin(th) * DT - r * mu_r * m * G * math.cos(th) * DT / l) / (m + I / (l * l))
+    assert (a > 0) == rolls
+    vs_prev = 0.0
+    for k in range(15):
+        sc.step()
+        vs = float(sc.v[0] @ sdir)
+        if rolls:
+            assert vs - vs_prev == pytest.approx(a, rel=1e-5), k
+        else:
+            assert abs(vs) < 1e-9 * G * DT, k  # held by the rolling couple
+        vs_prev = vs
+
+
+def test_rolling_couples_conserve_angular_momentum():
+    # two overlapping spheres in free space with opposite spins: the rolling
+    # couples are equal and opposite, friction forces act at a shared point
+    r = 0.05
+    x = [[0.0, 0.0, 0.0], [2 * r - 2e-4, 0.0, 0.0]]
+    w = [[3.0, 5.0, -2.0], [-4.0, 1.0, 6.0]]
+    v = [[0.1, 0.0, 0.2], [-0.1, 0.05, 0.0]]
+    spec = base_spec(x, [r, r], [], mu=0.5, g=(0.0, 0.0, 0.0), v=v, w=w, sweeps=20, mu_r=0.2)
+    sc = O.OracleScene(spec)
+    m = sphere_mass(r)
+    I = 0.4 * m * r * r
+
+    def ang():
+        return sum(m * np.cross(sc.x[i], sc.v[i]) + I * sc.w[i] for i in range(2))
+    for k in range(3):
+        L0 = ang()
+        out = sc.step()
+        if k == 0:  # in contact on the first step (they separate afterwards)
+            assert np.linalg.norm(out["lr"][0]) > 0.0
+        # positions advanced with the new velocities: compare at the same positions
+        x_new = sc.x.copy()
+        sc.x = x_new - DT * sc.v
+        L1 = ang()
+        sc.x = x_new
+        assert np.allclose(L1, L0, rtol=0, atol=1e-12 * (np.linalg.norm(L0) + 1e-9))
