@@ -62,7 +62,7 @@ enum tr_shape_type { TR_PLANE = 0, TR_BOX = 1, TR_HEIGHTFIELD = 2 };
 typedef struct tr_material {
     double rho;         /* particle density [kg/m^3], used when add_particles gets no density */
     double mu_t;        /* Coulomb friction coefficient */
-    double mu_r;        /* rolling resistance; must be 0 (rows not modelled) */
+    double mu_r;        /* rolling resistance (Eq. signCoul3), >= 0; 0 = no rolling rows */
     double c_p;         /* particle cohesion [Pa]; 0 disables cohesion and its range */
     double E;           /* Young's modulus [Pa] */
     double nu;          /* Poisson's ratio */
@@ -162,7 +162,7 @@ typedef struct tr_scene tr_scene;
 
 /* Creates a scene from *d (copied, env_bounds included).  Allocates all
  * device buffers at their capacities.  TR_E_INVAL for bad sizes or options
- * (mu_r or restitution nonzero), TR_E_NOMEM, TR_E_DEVICE. */
+ * (mu_r negative, restitution nonzero), TR_E_NOMEM, TR_E_DEVICE. */
 int create_scene(const tr_scene_desc* d, tr_scene** out);
 
 /* Releases every buffer of the scene.  NULL is accepted. */
@@ -209,6 +209,12 @@ const char* get_last_error(tr_scene* s);
  * (lambda_n, lambda_t xyz) of the step.  Writes min(cap, count) entries and
  * the count to *n.  impulse4 may be NULL.  Synchronises. */
 int get_contacts(tr_scene* s, int32_t env, int64_t cap, uint64_t* keys, float* impulse4, int64_t* n);
+
+/* Rolling-resistance impulses of the last step (Eq. signCoul3), in the order
+ * of get_contacts: 3 floats per contact, the torque impulse on body 2 (the
+ * higher id; -impulse on body 1), zero when mu_r == 0.  Writes min(cap,
+ * count) entries and the count to *n.  Synchronises. */
+int get_rolling_impulses(tr_scene* s, int32_t env, int64_t cap, float* impulse3, int64_t* n);
 
 /* Particle state of env in id order (any output may be NULL): pos, vel,
  * angvel 3n each, radius n.  *n receives the env's particle count.

@@ -486,6 +486,7 @@ void fill_params(tr_scene* s)
     p.dt = (float)dt;
     for (int k = 0; k < 3; ++k) p.g[k] = (float)d.gravity[k];
     p.mu = (float)m.mu_t;
+    p.mu_r = (float)m.mu_r;
     p.gamma_dt = (float)(m.gamma_t / dt);
     p.kappa_c = m.c_p > 0.0 ? m.kappa_c : 0.0;
     p.kappa_min = m.kappa_min;
@@ -516,7 +517,7 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
     if (d->n_envs < 1 || d->dt <= 0.0 || d->max_sweeps < 0 || d->cap_particles < 1 || d->cap_contacts < 1 ||
         !d->env_bounds)
         return TR_E_INVAL;
-    if (d->material.mu_r != 0.0 || d->material.restitution != 0.0) return TR_E_INVAL;
+    if (!(d->material.mu_r >= 0.0) || d->material.restitution != 0.0) return TR_E_INVAL;
     if (d->warm_start < TR_WARM_COLD || d->warm_start > TR_WARM_LEARNED) return TR_E_INVAL;
     if ((int64_t)d->n_envs * d->cap_particles >= ((int64_t)1 << 31) ||
         (int64_t)d->n_envs * d->cap_contacts >= ((int64_t)1 << 31))
@@ -534,6 +535,7 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
     z.C = (int64_t)d->n_envs * d->cap_contacts;
     z.NID = z.P;
     z.NB = (z.C + 255) / 256;
+    z.roll_C = d->material.mu_r > 0.0 ? z.C : 1;  // rolling rows only when mu_r > 0
     z.n_envs = d->n_envs;
     z.pgs_block = 512;
     s->p.n_units = std::max(kGroups, d->n_envs);
@@ -560,6 +562,8 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
               alloc_n(s, b.colour, z.C) && alloc_n(s, b.col_hist, (int64_t)kBuckets * z.NB) &&
               alloc_n(s, b.col_start, (int64_t)kBuckets * z.NB + 1) && alloc_n(s, b.cpos, z.C) &&
               alloc_n(s, b.r0, z.C) && alloc_n(s, b.r1, z.C) && alloc_n(s, b.r2, z.C) && alloc_n(s, b.rk, z.C) &&
+              alloc_n(s, b.r3, z.roll_C) && alloc_n(s, b.lamr, z.roll_C) && alloc_n(s, b.lamr0, z.roll_C) &&
+              alloc_n(s, b.lamrc, z.roll_C) && alloc_n(s, b.plamr, z.roll_C) &&
               alloc_n(s, b.lam, z.C) && alloc_n(s, b.lam0, z.C) &&
               alloc_n(s, b.envs, d->n_envs) && alloc_n(s, b.ustats, s->p.n_units) &&
               alloc_n(s, b.env_col, (int64_t)d->n_envs * (kMaxColours + 1)) && alloc_n(s, b.env_ncol, d->n_envs) &&
@@ -737,6 +741,7 @@ void swap_step_buffers(tr_scene* s)
 {
     std::swap(s->b.ckey, s->b.pkeyc);
     std::swap(s->b.lamc, s->b.plam);
+    std::swap(s->b.lamrc, s->b.plamr);
     std::swap(s->b.id_start, s->b.pid_start);
 }
 
@@ -967,6 +972,36 @@ int get_contacts(tr_scene* s, int32_t env, int64_t cap, uint64_t* keys, float* i
     return TR_OK;
 }
 
+int get_rolling_impulses(tr_scene* s, int32_t env, int64_t cap, float* impulse3, int64_t* n)
+{
+    if (!s || !n || cap < 0 || (cap > 0 && !impulse3)) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "get_rolling_impulses: env");
+    *n = 0;
+    if (!s->stepped) return TR_OK;
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    int64_t base = (int64_t)env * s->desc.cap_particles;
+    uint32_t r[2];
+    HIP_CHECK(s, hipMemcpy(&r[0], s->b.pid_start + base, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    HIP_CHECK(s, hipMemcpy(&r[1], s->b.pid_start + base + s->desc.cap_particles, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    int64_t cnt = (int64_t)r[1] - (int64_t)r[0];
+    *n = cnt;
+    int64_t m = std::min(cnt, cap);
+    if (m <= 0) return TR_OK;
+    if (!(s->desc.material.mu_r > 0.0)) {
+        for (int64_t i = 0; i < 3 * m; ++i) impulse3[i] = 0.f;
+        return TR_OK;
+    }
+    std::vector<float4> h((size_t)m);
+    HIP_CHECK(s, hipMemcpy(h.data(), s->b.plamr + r[0], sizeof(float4) * m, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m; ++i) {
+        impulse3[3 * i] = h[i].x;
+        impulse3[3 * i + 1] = h[i].y;
+        impulse3[3 * i + 2] = h[i].z;
+    }
+    return TR_OK;
+}
+
 int get_particles(tr_scene* s, int32_t env, double* pos, double* vel, double* angvel, double* radius, int64_t* n)
 {
     if (!s) return TR_E_INVAL;
@@ -1140,6 +1175,7 @@ std::vector<Span> state_spans(tr_scene* s, int64_t n_cache)
             {s->b.pid_start, sizeof(uint32_t) * (s->z.NID + 1)},
             {s->b.pkeyc, sizeof(unsigned long long) * n_cache},
             {s->b.plam, sizeof(float4) * n_cache},
+            {s->b.plamr, s->desc.material.mu_r > 0.0 ? sizeof(float4) * n_cache : 0},
             {s->b.bodies, sizeof(BodyDev) * s->body_host.size()}};
 }
 

@@ -121,6 +121,8 @@ struct StepParams {
     double dt_d;        // dt in FP64 (learned-start features)
     double gdt;         // |g| dt
     double r_ref;       // nominal radius of the features
+    float mu_r;         // rolling resistance (0: no rolling rows)
+    int pad_roll;
     int n_units;        // PGS solve units (entries of ustats)
     int pad_units;
 };
@@ -172,6 +174,9 @@ struct DevBuffers {
     uint32_t *col_hist, *col_start;                 // [kBuckets*NB], [kBuckets*NB+1]
     uint32_t* cpos;                                 // canonical -> colour position
     float4 *r0, *r1, *r2, *rk, *lam, *lam0;         // colour order
+    // rolling rows (allocated when mu_r > 0): r3 = (1/W_r, r mu_r, kinematic body, 0),
+    // lamr = (lambda_r, 0) and its start value, canonical current / previous caches
+    float4 *r3, *lamr, *lamr0, *lamrc, *plamr;
     // reductions
     double* resid_acc;    // [max_sweeps * 2] per-sweep numerator / denominator... (block partials)
     double* block_part;   // [2 parities][grid][2]
@@ -213,6 +218,7 @@ struct Sizes {
     int64_t NID;    // id space = n_envs * cap_particles
     int64_t NC;     // cells (all envs)
     int64_t NB;     // blocks of 256 over C (colour bucketing)
+    int64_t roll_C; // entries of the rolling-row arrays (C when mu_r > 0, else 1)
     int n_envs;
     int n_zone_chunks;
     int pgs_grid;   // blocks of the persistent PGS kernel (kGroups x blocks per group)

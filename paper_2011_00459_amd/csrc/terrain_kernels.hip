@@ -817,6 +817,17 @@ void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hip
 // impulses matched by key, re-projected onto the tangent plane and onto the
 // feasible set).  Geometry in FP64, stored in FP32.
 // ---------------------------------------------------------------------------
+// lambda_r onto the disk |lambda_r| <= lim
+__device__ inline float4 project_roll(float4 Lr, float lim)
+{
+    float m2 = Lr.x * Lr.x + Lr.y * Lr.y + Lr.z * Lr.z;
+    if (m2 > lim * lim) {
+        float sc = m2 > 0.f ? lim * rsqrtf(m2) : 0.f;
+        Lr.x *= sc; Lr.y *= sc; Lr.z *= sc;
+    }
+    return Lr;
+}
+
 __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
 {
     uint32_t nc = n_contacts(b, cap);
@@ -891,12 +902,18 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
 
     // warm start: previous-step impulses of the same key
     float4 L = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 Lr = make_float4(0.f, 0.f, 0.f, 0.f);
     bool persistent = false;
     if (use_prev) {
         uint32_t a = (uint32_t)(key >> 32);
         uint32_t beg = b.pid_start[a], end = b.pid_start[a + 1];
         for (uint32_t t = beg; t < end; ++t)
-            if (b.pkeyc[t] == key) { L = b.plam[t]; persistent = true; break; }
+            if (b.pkeyc[t] == key) {
+                L = b.plam[t];
+                if (p.mu_r > 0.f) Lr = b.plamr[t];
+                persistent = true;
+                break;
+            }
     }
     uint32_t pos = b.cpos[c];
     // learned-start features (12), contact frame and impulse scale, in FP64
@@ -986,6 +1003,18 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     b.rk[pos] = make_float4((float)vk[0], (float)vk[1], (float)vk[2], __uint_as_float(seq));
     b.lam[pos] = L;
     b.lam0[pos] = L;
+    if (p.mu_r > 0.f) {
+        // rolling row (Eq. signCoul3): 1/(1/I_1 + 1/I_2), r mu_r with r the
+        // smaller radius, the kinematic body of a boundary contact; the start
+        // impulse projected onto |lambda_r| <= r mu_r |lambda_n|
+        float rlim = (float)((double)p.mu_r * rmin);
+        int kb = ia >= 0 ? -1 : b.shapes[-1 - ia].body;
+        b.r3[pos] = make_float4((float)(1.0 / (iI1 + iI2)), rlim, __int_as_float(kb), 0.f);
+        if (p.warm == TR_WARM_COLD) Lr = make_float4(0.f, 0.f, 0.f, 0.f);
+        Lr.w = 0.f;
+        b.lamr0[pos] = Lr;  // unprojected: the start's lambda_n decides the bound
+        b.lamr[pos] = project_roll(Lr, rlim * fabsf(L.x));
+    }
 }
 
 void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, hipStream_t s)
@@ -1010,7 +1039,7 @@ __global__ void k_warm_apply(DevBuffers b, StepParams p)
     for (uint32_t t = beg; t < end; ++t) {
         uint32_t pos = b.cpos[b.inc[t]];
         float4 L = b.lam[pos];
-        if (L.x == 0.f && L.y == 0.f && L.z == 0.f && L.w == 0.f) continue;
+        if (L.x == 0.f && L.y == 0.f && L.z == 0.f && L.w == 0.f && !(p.mu_r > 0.f)) continue;
         float4 a = b.r0[pos];
         float4 q = b.r2[pos];
         float J0 = L.x * a.x + L.y, J1 = L.x * a.y + L.z, J2 = L.x * a.z + L.w;
@@ -1021,6 +1050,10 @@ __global__ void k_warm_apply(DevBuffers b, StepParams p)
         float c0 = lev * (a.y * J2 - a.z * J1), c1 = lev * (a.z * J0 - a.x * J2), c2 = lev * (a.x * J1 - a.y * J0);
         v.x += sgn * v.w * J0; v.y += sgn * v.w * J1; v.z += sgn * v.w * J2;
         w.x += sgn * w.w * c0; w.y += sgn * w.w * c1; w.z += sgn * w.w * c2;
+        if (p.mu_r > 0.f) {
+            float4 Lr = b.lamr[pos];
+            w.x += sgn * w.w * Lr.x; w.y += sgn * w.w * Lr.y; w.z += sgn * w.w * Lr.z;
+        }
     }
     b.vm[s] = v;
     b.wi[s] = w;
@@ -1143,9 +1176,10 @@ __device__ inline int cluster_placement(Counters* cnt, uint32_t* counter, unsign
 
 struct RowRegs {
     float4 a, r1, q, L, k;
+    float4 r3, Lr;  // rolling rows (loaded when mu_r > 0)
 };
 
-__device__ inline RowRegs load_rows(const DevBuffers& b, uint32_t c)
+__device__ inline RowRegs load_rows(const DevBuffers& b, uint32_t c, bool roll)
 {
     RowRegs R;
     R.a = b.r0[c];
@@ -1153,6 +1187,10 @@ __device__ inline RowRegs load_rows(const DevBuffers& b, uint32_t c)
     R.q = b.r2[c];
     R.L = b.lam[c];
     R.k = b.rk[c];
+    if (roll) {
+        R.r3 = b.r3[c];
+        R.Lr = b.lamr[c];
+    }
     return R;
 }
 
@@ -1182,7 +1220,7 @@ struct LdsBodies {
 
 template <class BA>
 __device__ inline void pgs_contact(const DevBuffers& b, const BA& ba, uint32_t c, const RowRegs& R, float mu,
-                                   float gdt, float& num, float& den)
+                                   float gdt, float& num, float& den, bool roll)
 {
     float4 a = R.a, r1 = R.r1, q = R.q, L = R.L;
     int ia = __float_as_int(q.z), ib = __float_as_int(q.w);
@@ -1225,16 +1263,42 @@ __device__ inline void pgs_contact(const DevBuffers& b, const BA& ba, uint32_t c
     float cx = ny * dz - nz * dy, cy = nz * dx - nx * dz, cz = nx * dy - ny * dx;  // n x d
     vb.x += dx * vb.w; vb.y += dy * vb.w; vb.z += dz * vb.w;
     wb.x -= l2 * wb.w * cx; wb.y -= l2 * wb.w * cy; wb.z -= l2 * wb.w * cz;
-    ba.set(ib, vb, wb);
     if (pair) {
         va.x -= dx * va.w; va.y -= dy * va.w; va.z -= dz * va.w;
         wa.x -= l1 * wa.w * cx; wa.y -= l1 * wa.w * cy; wa.z -= l1 * wa.w * cz;
-        ba.set(ia, va, wa);
     }
-    b.lam[c] = make_float4(ln, tx, ty, tz);
     float Dn = 1.0f / iDn, Dt = 1.0f / iDt;
     num += Dn * dn * dn + Dt * (dx * dx + dy * dy + dz * dz);
     den += Dn * ln * ln + Dt * (tx * tx + ty * ty + tz * tz);
+    if (roll) {
+        // rolling row (Eq. signCoul3): zero relative angular velocity, the
+        // torque impulse on the disk |lambda_r| <= r mu_r |lambda_n|
+        float4 Lr = R.Lr;
+        float ox = 0.f, oy = 0.f, oz = 0.f;
+        if (pair) { ox = wa.x; oy = wa.y; oz = wa.z; }
+        else {
+            const BodyDev& K = b.bodies[__float_as_int(R.r3.z)];
+            ox = (float)K.angvel[0]; oy = (float)K.angvel[1]; oz = (float)K.angvel[2];
+        }
+        float iWr = R.r3.x;
+        float rx = Lr.x - (wb.x - ox) * iWr, ry = Lr.y - (wb.y - oy) * iWr, rz = Lr.z - (wb.z - oz) * iWr;
+        float rlim = R.r3.y * fabsf(ln);
+        float r2 = rx * rx + ry * ry + rz * rz;
+        if (r2 > rlim * rlim) {
+            float sc = r2 > 0.f ? rlim * rsqrtf(r2) : 0.f;
+            rx *= sc; ry *= sc; rz *= sc;
+        }
+        float ex = rx - Lr.x, ey = ry - Lr.y, ez = rz - Lr.z;
+        wb.x += wb.w * ex; wb.y += wb.w * ey; wb.z += wb.w * ez;
+        if (pair) { wa.x -= wa.w * ex; wa.y -= wa.w * ey; wa.z -= wa.w * ez; }
+        b.lamr[c] = make_float4(rx, ry, rz, 0.f);
+        float Wr = 1.0f / iWr;
+        num += Wr * (ex * ex + ey * ey + ez * ez);
+        den += Wr * (rx * rx + ry * ry + rz * rz);
+    }
+    ba.set(ib, vb, wb);
+    if (pair) ba.set(ia, va, wa);
+    b.lam[c] = make_float4(ln, tx, ty, tz);
 }
 
 // block sums of the sweep's (num, den) in a fixed order, returned to every thread
@@ -1309,7 +1373,7 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
     if (ncol > 0) {
         range(0, lo, hi);
         c = lo + threadIdx.x;
-        if (c < hi) cur = load_rows(b, c);
+        if (c < hi) cur = load_rows(b, c, p.mu_r > 0.f);
     }
 #ifdef TRK_PGS_TRACE
     unsigned long long tr[4] = {0, 0, 0, 0}, tprev = wall_clock64();
@@ -1321,7 +1385,7 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
             while (c < hi) {
                 uint32_t cn = c + blockDim.x;
                 RowRegs nxt;
-                if (cn < hi) nxt = load_rows(b, cn);
+                if (cn < hi) nxt = load_rows(b, cn, p.mu_r > 0.f);
                 if (FLOW) {
                     const uint32_t seq = __float_as_uint(cur.k.w);
                     const int ia = __float_as_int(cur.q.z), ib = __float_as_int(cur.q.w);
@@ -1330,14 +1394,14 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                     if (alive) alive = flow_wait(b.cnt, b.ver, ib, wb) && (ia < 0 || flow_wait(b.cnt, b.ver, ia, wa));
                     if (alive) {
                         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // body loads after the counters
-                        pgs_contact(b, ba, c, cur, p.mu, p.gamma_dt, num, den);
+                        pgs_contact(b, ba, c, cur, p.mu, p.gamma_dt, num, den, p.mu_r > 0.f);
                         __builtin_amdgcn_s_waitcnt(0);  // the sphere state has reached the XCD's L2
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                         __hip_atomic_store(&b.ver[ib], wb + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if (ia >= 0) __hip_atomic_store(&b.ver[ia], wa + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 } else {
-                    pgs_contact(b, ba, c, cur, p.mu, p.gamma_dt, num, den);
+                    pgs_contact(b, ba, c, cur, p.mu, p.gamma_dt, num, den, p.mu_r > 0.f);
                 }
                 cur = nxt;
                 c = cn;
@@ -1360,7 +1424,7 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                 // the next phase's first rows are fetched while the block waits
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
                 c = lo + threadIdx.x;
-                if (c < hi) cur = load_rows(b, c);
+                if (c < hi) cur = load_rows(b, c, p.mu_r > 0.f);
 #ifdef TRK_PGS_TRACE
                 unsigned long long tb = wall_clock64();
 #endif
@@ -1373,7 +1437,7 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
             } else {
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
                 c = lo + threadIdx.x;
-                if (c < hi) cur = load_rows(b, c);
+                if (c < hi) cur = load_rows(b, c, p.mu_r > 0.f);
                 if (!CLUSTER) __syncthreads();
             }
         }
@@ -1526,7 +1590,7 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
     auto start_col = [&](uint32_t col) {
         c = ec[col] + lt;
         hi = ec[col + 1];
-        if (c < hi) cur = load_rows(b, c);
+        if (c < hi) cur = load_rows(b, c, p.mu_r > 0.f);
     };
     if (active) start_col(0);
     for (int sw = 0; sw < sweeps_cap; ++sw) {
@@ -1537,9 +1601,9 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
                 while (c < hi) {
                     uint32_t cn = c + nthr;
                     RowRegs nxt;
-                    if (cn < hi) nxt = load_rows(b, cn);
-                    if (off >= 0) pgs_contact(b, lb, c, cur, p.mu, p.gamma_dt, num, den);
-                    else pgs_contact(b, gb, c, cur, p.mu, p.gamma_dt, num, den);
+                    if (cn < hi) nxt = load_rows(b, cn, p.mu_r > 0.f);
+                    if (off >= 0) pgs_contact(b, lb, c, cur, p.mu, p.gamma_dt, num, den, p.mu_r > 0.f);
+                    else pgs_contact(b, gb, c, cur, p.mu, p.gamma_dt, num, den, p.mu_r > 0.f);
                     cur = nxt;
                     c = cn;
                 }
@@ -1748,7 +1812,7 @@ void launch_vel_copy(const DevBuffers& b, const StepParams& p, bool backup, hipS
                        backup ? 1 : 0);
 }
 
-__global__ void k_select_start(DevBuffers b, int64_t cap, int mode, uint32_t id_cap)
+__global__ void k_select_start(DevBuffers b, int64_t cap, int mode, uint32_t id_cap, float mu_r)
 {
     uint32_t nc = n_contacts(b, cap);
     uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1758,12 +1822,14 @@ __global__ void k_select_start(DevBuffers b, int64_t cap, int mode, uint32_t id_
         int u = b.envs[env_of(b.pid[__float_as_int(b.r2[c].w)], id_cap)].unit;
         learned = b.ustats[u].use_learned != 0;
     }
-    b.lam[c] = learned ? b.lamL[c] : b.lam0[c];
+    float4 L = learned ? b.lamL[c] : b.lam0[c];
+    b.lam[c] = L;
+    if (mu_r > 0.f) b.lamr[c] = project_roll(b.lamr0[c], b.r3[c].y * fabsf(L.x));
 }
 
 void launch_select_start(const DevBuffers& b, const StepParams& p, const Sizes& z, int mode, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_select_start, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, z.C, mode, p.id_cap);
+    hipLaunchKernelGGL(k_select_start, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, z.C, mode, p.id_cap, p.mu_r);
 }
 
 __global__ void k_choose_start(DevBuffers b, int n_units)
@@ -1807,12 +1873,13 @@ void launch_learn_samples(const DevBuffers& b, int64_t beg, int64_t n, float* fe
 // finish: canonical impulses, body forces (A11), integration (A10), poses,
 // zone aggregates (A12), env stats
 // ---------------------------------------------------------------------------
-__global__ void k_lam_back(DevBuffers b, int64_t cap)
+__global__ void k_lam_back(DevBuffers b, int64_t cap, float mu_r)
 {
     uint32_t nc = n_contacts(b, cap);
     uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
     b.lamc[c] = b.cnt->overflow ? make_float4(0.f, 0.f, 0.f, 0.f) : b.lam[b.cpos[c]];
+    if (mu_r > 0.f) b.lamrc[c] = b.cnt->overflow ? make_float4(0.f, 0.f, 0.f, 0.f) : b.lamr[b.cpos[c]];
 }
 
 __device__ inline double block_sum_d(double v, double* sh)
@@ -1862,6 +1929,12 @@ __global__ __launch_bounds__(kRedBlk) void k_force_part(DevBuffers b, StepParams
         acc[3] += arm[1] * f[2] - arm[2] * f[1];
         acc[4] += arm[2] * f[0] - arm[0] * f[2];
         acc[5] += arm[0] * f[1] - arm[1] * f[0];
+        if (p.mu_r > 0.f) {  // the rolling couple
+            float4 Lr = b.lamr[pos];
+            acc[3] -= (double)Lr.x / p.dt;
+            acc[4] -= (double)Lr.y / p.dt;
+            acc[5] -= (double)Lr.z / p.dt;
+        }
     }
     for (int k = 0; k < 6; ++k) {
         double s = block_sum_d(acc[k], sh);
@@ -2062,7 +2135,7 @@ __global__ void k_env_stats(DevBuffers b, StepParams p)
 
 void launch_finish(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lam_back, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, z.C);
+    hipLaunchKernelGGL(k_lam_back, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, z.C, p.mu_r);
     if (p.n_bodies > 0) {
         hipLaunchKernelGGL(k_force_part, dim3(p.n_bodies * kForceChunks), dim3(kRedBlk), 0, s, b, p, z.C);
         hipLaunchKernelGGL(k_force_final, dim3((unsigned)cdiv(p.n_bodies, kBlk)), dim3(kBlk), 0, s, b, p);

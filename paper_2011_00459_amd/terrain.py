@@ -24,7 +24,8 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "get_contact_forces", "get_aggregates", "get_last_error", "get_contacts", "get_particles",
            "set_particles", "set_mlp_weights", "get_phase_times", "set_learned_precision", "get_learn_samples",
            "mlp_forward", "mlp_grad_scratch_floats", "mlp_loss_grad", "mlp_adam_step", "set_solver_config",
-           "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state", "autotune")
+           "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state", "autotune",
+           "get_rolling_impulses")
 PGS_MODE = {"grouped": 0, "per_env": 1}
 MLP_TRAINABLE = MLP_PARAMS - 12
 
@@ -121,6 +122,7 @@ def lib():
         L.save_state.argtypes = [P, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
         L.load_state.argtypes = [P, C.c_void_p, C.c_int64]
         L.autotune.argtypes = [P, C.c_int32, C.c_char_p, C.POINTER(tr_solver_config), C.POINTER(C.c_float)]
+        L.get_rolling_impulses.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_int64)]
         for name in EXPORTS:
             if name != "get_last_error":
                 getattr(L, name).restype = C.c_int
@@ -280,6 +282,14 @@ class Scene:
                                        lam.ctypes.data_as(C.POINTER(C.c_float)), C.byref(n)), "get_contacts")
         m = min(n.value, cap)
         return keys[:m], lam[:m]
+
+    def get_rolling_impulses(self, env):
+        n = C.c_int64()
+        self._check(lib().get_rolling_impulses(self.h, env, 0, None, C.byref(n)), "get_rolling_impulses")
+        out = np.zeros((max(n.value, 1), 3), dtype=np.float32)
+        self._check(lib().get_rolling_impulses(self.h, env, n.value, out.ctypes.data_as(C.POINTER(C.c_float)),
+                                               C.byref(n)), "get_rolling_impulses")
+        return out[:n.value]
 
     def get_particles(self, env):
         n = C.c_int64()

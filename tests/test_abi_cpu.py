@@ -68,9 +68,12 @@ def test_invalid_arguments_rejected_without_device_work():
     import numpy as np
     b = np.array([0, 0, 0, 1, 1, 1.0])
     d.env_bounds = b.ctypes.data_as(C.POINTER(C.c_double))
-    d.material.mu_r = 0.1
-    assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_INVAL  # rolling resistance not modelled
+    d.material.mu_r = -0.1
+    assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_INVAL  # negative rolling resistance
     d.material.mu_r = 0.0
+    d.material.restitution = 0.3
+    assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_INVAL  # no impact stage
+    d.material.restitution = 0.0
     bn = np.array([0, 0, 0, 1, np.nan, 1.0])
     d.env_bounds = bn.ctypes.data_as(C.POINTER(C.c_double))
     assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_NONFINITE
