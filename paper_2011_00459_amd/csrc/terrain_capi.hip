@@ -541,7 +541,7 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
     s->p.n_units = std::max(kGroups, d->n_envs);
     // default schedule: grouped for a few envs (XCD groups of 32 blocks, one
     // per CU), per-env blocks with LDS-resident bodies for many envs
-    s->max_lds_particles = std::max(0, (pgs_env_max_lds() - 1024) / 32);
+    s->max_lds_particles = std::max(0, pgs_env_max_lds() / 32);
     s->cfg.mode = d->n_envs > kGroups ? TR_PGS_PER_ENV : TR_PGS_GROUPED;
     s->cfg.blocks_per_xcd = 32;
     s->cfg.lds_particles = s->max_lds_particles;
@@ -1359,7 +1359,7 @@ int autotune(tr_scene* s, int32_t steps, const char* cache_path, tr_solver_confi
     // grouped mode shares the stopping test of a group's envs: not offered when
     // that would change results (a residual tolerance with more than 8 envs)
     if (!(s->desc.tol > 0.0 && s->desc.n_envs > kGroups))
-        for (int bpx : {32, 16, 8}) cands.push_back({TR_PGS_GROUPED, bpx, s->max_lds_particles, 0, 0});
+        for (int bpx : {64, 32, 16, 8}) cands.push_back({TR_PGS_GROUPED, bpx, s->max_lds_particles, 0, 0});
     for (int cp : {0, 8192, 16384}) cands.push_back({TR_PGS_PER_ENV, 32, s->max_lds_particles, cp, 0});
     cands.push_back({TR_PGS_PER_ENV, 32, 0, 0, 0});
     hipEvent_t e0 = nullptr, e1 = nullptr;

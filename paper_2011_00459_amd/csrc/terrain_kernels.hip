@@ -1218,19 +1218,36 @@ struct LdsBodies {
     __device__ void set(int i, float4 v, float4 w) const { sv[i - base] = v; sw[i - base] = w; }
 };
 
+// the two bodies of a contact, loaded ahead of the update (the update
+// replaces body 1 of a boundary contact by the boundary's velocity)
+struct BodyRegs {
+    float4 va, wa, vb, wb;
+};
+
+// unconditional loads (a boundary contact reads its sphere twice): no
+// divergent branch between the loads and their use
 template <class BA>
-__device__ inline void pgs_contact(const DevBuffers& b, const BA& ba, uint32_t c, const RowRegs& R, float mu,
-                                   float gdt, float& num, float& den, bool roll)
+__device__ inline BodyRegs load_bodies(const BA& ba, const RowRegs& R)
+{
+    BodyRegs B;
+    const int ia = __float_as_int(R.q.z), ib = __float_as_int(R.q.w);
+    const int ja = ia >= 0 ? ia : ib;
+    B.vb = ba.v(ib);
+    B.wb = ba.w(ib);
+    B.va = ba.v(ja);
+    B.wa = ba.w(ja);
+    return B;
+}
+
+template <class BA>
+__device__ inline void pgs_contact(const DevBuffers& b, const BA& ba, uint32_t c, const RowRegs& R, BodyRegs B,
+                                   float mu, float gdt, float& num, float& den, bool roll)
 {
     float4 a = R.a, r1 = R.r1, q = R.q, L = R.L;
     int ia = __float_as_int(q.z), ib = __float_as_int(q.w);
     bool pair = ia >= 0;
-    float4 vb = ba.v(ib), wb = ba.w(ib);
-    float4 va, wa;
-    if (pair) {
-        va = ba.v(ia);
-        wa = ba.w(ia);
-    } else {
+    float4 vb = B.vb, wb = B.wb, va = B.va, wa = B.wa;
+    if (!pair) {
         va = make_float4(R.k.x, R.k.y, R.k.z, 0.f);
         wa = make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -1267,7 +1284,8 @@ __device__ inline void pgs_contact(const DevBuffers& b, const BA& ba, uint32_t c
         va.x -= dx * va.w; va.y -= dy * va.w; va.z -= dz * va.w;
         wa.x -= l1 * wa.w * cx; wa.y -= l1 * wa.w * cy; wa.z -= l1 * wa.w * cz;
     }
-    float Dn = 1.0f / iDn, Dt = 1.0f / iDt;
+    // residual weights (the stopping test only): hardware reciprocals
+    float Dn = __builtin_amdgcn_rcpf(iDn), Dt = __builtin_amdgcn_rcpf(iDt);
     num += Dn * dn * dn + Dt * (dx * dx + dy * dy + dz * dz);
     den += Dn * ln * ln + Dt * (tx * tx + ty * ty + tz * tz);
     if (roll) {
@@ -1292,7 +1310,7 @@ __device__ inline void pgs_contact(const DevBuffers& b, const BA& ba, uint32_t c
         wb.x += wb.w * ex; wb.y += wb.w * ey; wb.z += wb.w * ez;
         if (pair) { wa.x -= wa.w * ex; wa.y -= wa.w * ey; wa.z -= wa.w * ez; }
         b.lamr[c] = make_float4(rx, ry, rz, 0.f);
-        float Wr = 1.0f / iWr;
+        float Wr = __builtin_amdgcn_rcpf(iWr);
         num += Wr * (ex * ex + ey * ey + ez * ez);
         den += Wr * (rx * rx + ry * ry + rz * rz);
     }
@@ -1345,27 +1363,62 @@ __device__ inline bool flow_wait(Counters* cnt, const uint32_t* ver, int j, uint
 // equal slices.  Blocks of the cluster are first + 8 t, t < K.  FLOW: colours
 // are ordered by the per-sphere counters (clusters only); a barrier remains at
 // the end of a sweep when a residual tolerance is set, and once at the end.
-template <class BA, bool CLUSTER, bool FENCED, bool FLOW, int NW, class Starts>
+template <class BA, bool CLUSTER, bool FENCED, bool FLOW, bool ROLL, int NW, class Starts>
 __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba, Starts cstart, uint32_t ncol,
                           uint32_t* counter, unsigned nbar, unsigned rank, unsigned K, unsigned first, int sweeps_cap,
-                          int slot, int unit, double (*red)[NW], int& flag)
+                          int slot, int unit, double (*red)[NW], uint32_t (*cb)[kMaxColours], int& flag)
 {
     int sweeps = 0;
     double Rk = 0.0, R1 = 0.0;
     const unsigned nblk = gridDim.x;
+    constexpr uint32_t kThreads = NW * 64;  // the launch's block size (a constant stride)
     bool alive = true;
+    // Trailing colours of at most one block's threads each are solved by the
+    // rank-0 block alone, with workgroup barriers between them and a single
+    // cluster barrier after the last (same colour order, same results).
+    // colour bounds staged in LDS (cb: the kernel's) once: no global load
+    // between a barrier and the next colour's row prefetch
+    uint32_t* cbeg = cb[0];
+    uint32_t* clen = cb[1];
+    for (uint32_t q = threadIdx.x; q < ncol; q += blockDim.x) {
+        cbeg[q] = cstart.beg(q);
+        clen[q] = cstart.end(q) - cbeg[q];
+    }
+    __syncthreads();
+    uint32_t tail = ncol;
+    if (CLUSTER && !FLOW)
+        while (tail > 0 && clen[tail - 1] <= kThreads) --tail;
     auto range = [&](uint32_t col, uint32_t& lo, uint32_t& hi) {
-        uint32_t beg = cstart.beg(col), len = cstart.end(col) - beg;
+        uint32_t beg = cbeg[col], len = clen[col];
+        if (col >= tail) {
+            lo = beg;
+            hi = rank == 0 ? beg + len : beg;
+            return;
+        }
         lo = beg + (uint32_t)(((uint64_t)len * rank) / K);
         hi = beg + (uint32_t)(((uint64_t)len * (rank + 1)) / K);
     };
+    // The cluster's (num, den) of sweep sw, the same value in every thread of
+    // every block: wave 0 loads the K block partials in parallel and sums them
+    // in a fixed tree order, the result is broadcast through LDS.
     auto combine = [&](int sw, double& sn, double& sd) {
         const double* part = b.block_part + (size_t)(FLOW ? sw : (sw & 1)) * nblk * 2;
-        sn = 0.0; sd = 0.0;
-        for (unsigned t = 0; t < K; ++t) {
-            sn += __hip_atomic_load(&part[2 * (first + 8 * t)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sd += __hip_atomic_load(&part[2 * (first + 8 * t) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x < 64) {
+            double a = 0.0, d = 0.0;
+            for (unsigned t = threadIdx.x; t < K; t += 64) {
+                a += __hip_atomic_load(&part[2 * (first + 8 * t)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                d += __hip_atomic_load(&part[2 * (first + 8 * t) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                a += __shfl_down(a, o, 64);
+                d += __shfl_down(d, o, 64);
+            }
+            if (threadIdx.x == 0) { red[0][0] = a; red[1][0] = d; }
         }
+        __syncthreads();
+        sn = red[0][0];
+        sd = red[1][0];
+        __syncthreads();  // red is reused
     };
     auto resid = [](double sn, double sd) { return sd > 0.0 ? sqrt(sn) / sqrt(sd) : (sn > 0.0 ? 1.0 : 0.0); };
     uint32_t lo = 0, hi = 0, c = 0;
@@ -1373,19 +1426,24 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
     if (ncol > 0) {
         range(0, lo, hi);
         c = lo + threadIdx.x;
-        if (c < hi) cur = load_rows(b, c, p.mu_r > 0.f);
+        if (c < hi) cur = load_rows(b, c, ROLL);
     }
 #ifdef TRK_PGS_TRACE
-    unsigned long long tr[4] = {0, 0, 0, 0}, tprev = wall_clock64();
+    unsigned long long tr[4] = {0, 0, 0, 0}, tprev = wall_clock64(), tw[12] = {}, ta2[12] = {}, tw2[12] = {};
 #endif
     for (int sw = 0; sw < sweeps_cap && ncol > 0; ++sw) {
         float num = 0.f, den = 0.f;
         double* part = b.block_part + (size_t)(FLOW ? sw : (sw & 1)) * nblk * 2;
         for (uint32_t col = 0; col < ncol; ++col) {
+            // the rows prefetched for this colour: settled here, outside the
+            // loop, so that the loop waits only for its own loads
+            if (!FLOW) __builtin_amdgcn_s_waitcnt(0);
             while (c < hi) {
-                uint32_t cn = c + blockDim.x;
+                uint32_t cn = c + kThreads;
+                BodyRegs B;
+                if (!FLOW) B = load_bodies(ba, cur);
                 RowRegs nxt;
-                if (cn < hi) nxt = load_rows(b, cn, p.mu_r > 0.f);
+                if (cn < hi) nxt = load_rows(b, cn, ROLL);
                 if (FLOW) {
                     const uint32_t seq = __float_as_uint(cur.k.w);
                     const int ia = __float_as_int(cur.q.z), ib = __float_as_int(cur.q.w);
@@ -1394,20 +1452,28 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                     if (alive) alive = flow_wait(b.cnt, b.ver, ib, wb) && (ia < 0 || flow_wait(b.cnt, b.ver, ia, wa));
                     if (alive) {
                         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // body loads after the counters
-                        pgs_contact(b, ba, c, cur, p.mu, p.gamma_dt, num, den, p.mu_r > 0.f);
+                        pgs_contact(b, ba, c, cur, load_bodies(ba, cur), p.mu, p.gamma_dt, num, den, ROLL);
                         __builtin_amdgcn_s_waitcnt(0);  // the sphere state has reached the XCD's L2
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                         __hip_atomic_store(&b.ver[ib], wb + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if (ia >= 0) __hip_atomic_store(&b.ver[ia], wa + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 } else {
-                    pgs_contact(b, ba, c, cur, p.mu, p.gamma_dt, num, den, p.mu_r > 0.f);
+                    pgs_contact(b, ba, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
                 }
                 cur = nxt;
                 c = cn;
             }
-            if (CLUSTER && !FLOW) {
-                if (col + 1 == ncol) {
+            if (CLUSTER && !FLOW && col >= tail && col + 1 < ncol) {
+                // inside the tail: the block's stores drained, then a workgroup
+                // barrier orders the rank-0 block's colours
+                __builtin_amdgcn_s_waitcnt(0);
+                range(col + 1, lo, hi);
+                c = lo + threadIdx.x;
+                if (c < hi) cur = load_rows(b, c, ROLL);
+                __syncthreads();
+            } else if (CLUSTER && !FLOW) {
+                if (col + 1 == ncol && (p.tol > 0.f || sw == 0 || sw + 1 == sweeps_cap)) {
                     // block partials of this sweep, published before the last barrier
                     double sn, sd;
                     block_sum2<NW>(num, den, red, sn, sd);
@@ -1424,7 +1490,7 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                 // the next phase's first rows are fetched while the block waits
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
                 c = lo + threadIdx.x;
-                if (c < hi) cur = load_rows(b, c, p.mu_r > 0.f);
+                if (c < hi) cur = load_rows(b, c, ROLL);
 #ifdef TRK_PGS_TRACE
                 unsigned long long tb = wall_clock64();
 #endif
@@ -1432,12 +1498,13 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
 #ifdef TRK_PGS_TRACE
                 unsigned long long tc = wall_clock64();
                 tr[0] += ta - tprev; tr[1] += tb - ta; tr[2] += tc - tb; tr[3] += 1;
+                if (col < 12) { tw[col] += ta - tprev; ta2[col] += tb - ta; tw2[col] += tc - tb; }
                 tprev = tc;
 #endif
             } else {
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
                 c = lo + threadIdx.x;
-                if (c < hi) cur = load_rows(b, c, p.mu_r > 0.f);
+                if (c < hi) cur = load_rows(b, c, ROLL);
                 if (!CLUSTER) __syncthreads();
             }
         }
@@ -1461,8 +1528,14 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
             }
             continue;
         }
-        if (CLUSTER) combine(sw, sn, sd);
-        else block_sum2<NW>(num, den, red, sn, sd);
+        if (CLUSTER) {
+            // without a tolerance only the first and last residuals are reported
+            sweeps = sw + 1;
+            if (!(p.tol > 0.f) && sw != 0 && sw + 1 != sweeps_cap) continue;
+            combine(sw, sn, sd);
+        } else {
+            block_sum2<NW>(num, den, red, sn, sd);
+        }
         Rk = resid(sn, sd);
         if (sw == 0) R1 = Rk;
         sweeps = sw + 1;
@@ -1480,9 +1553,14 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
         Rk = resid(sn, sd);
     }
 #ifdef TRK_PGS_TRACE
-    if (unit == 0 && threadIdx.x == 0 && (rank == 0 || rank == K - 1) && tr[3] > 0)
-        printf("PGS_TRACE rank %u phases %llu ticks/phase: work %.1f arrive+prefetch %.1f wait %.1f\n", rank, tr[3],
-               (double)tr[0] / tr[3], (double)tr[1] / tr[3], (double)tr[2] / tr[3]);
+    if (threadIdx.x == 0 && (rank == 0 || rank == K - 1) && tr[3] > 0) {
+        printf("PGS_TRACE unit %d rank %u phases %llu ticks/phase: work %.1f arrive+prefetch %.1f wait %.1f\n", unit,
+               rank, tr[3], (double)tr[0] / tr[3], (double)tr[1] / tr[3], (double)tr[2] / tr[3]);
+        for (uint32_t q = 0; q < ncol && q < 12; ++q)
+            printf("PGS_TRACE unit %d rank %u colour %u size %u work %.1f arrive %.1f wait %.1f\n", unit, rank, q,
+                   cstart.end(q) - cstart.beg(q), (double)tw[q] / sweeps, (double)ta2[q] / sweeps,
+                   (double)tw2[q] / sweeps);
+    }
 #endif
     if (rank == 0 && threadIdx.x == 0) {
         UnitStats& G = b.ustats[unit];
@@ -1518,10 +1596,12 @@ struct EnvStarts {
     __device__ uint32_t end(uint32_t col) const { return ec[col + 1]; }
 };
 
+template <bool ROLL>
 __global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int64_t NB, int sweeps_cap, int slot,
                                                    int flow)
 {
     __shared__ double red[2][kPgsBlk / 64];
+    __shared__ uint32_t cb[2][kMaxColours];
     __shared__ int flag;
     if (b.cnt->overflow) return;  // uniform: written by earlier kernels only
     const int g = blockIdx.x % kGroups;
@@ -1537,15 +1617,15 @@ __global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int
     if (mode == 1) {
         XcdBodies ba{raw_rsrc(b.vm), raw_rsrc(b.wi)};
         if (flow)
-            pgs_solve<XcdBodies, true, false, true>(b, p, ba, cs, ncol, counter, 1, rank, gx, (unsigned)g, sweeps_cap,
-                                                    slot, g, red, flag);
+            pgs_solve<XcdBodies, true, false, true, ROLL>(b, p, ba, cs, ncol, counter, 1, rank, gx, (unsigned)g, sweeps_cap,
+                                                    slot, g, red, cb, flag);
         else
-            pgs_solve<XcdBodies, true, false, false>(b, p, ba, cs, ncol, counter, 1, rank, gx, (unsigned)g,
-                                                     sweeps_cap, slot, g, red, flag);
+            pgs_solve<XcdBodies, true, false, false, ROLL>(b, p, ba, cs, ncol, counter, 1, rank, gx, (unsigned)g,
+                                                     sweeps_cap, slot, g, red, cb, flag);
     }
     else if (mode == 2)
-        pgs_solve<PlainBodies, true, true, false>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, gx,
-                                                  (unsigned)g, sweeps_cap, slot, g, red, flag);
+        pgs_solve<PlainBodies, true, true, false, ROLL>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, gx,
+                                                  (unsigned)g, sweeps_cap, slot, g, red, cb, flag);
 }
 
 // Per-env mode, a set of small envs solved at once by one block: env j of the
@@ -1553,6 +1633,7 @@ __global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int
 // memory when off < 0).  The envs share the workgroup barrier after every
 // colour (up to the largest colour count of the set) but reduce their own
 // residual, stop on their own and record their own statistics.
+template <bool ROLL>
 __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const int4* tasks, int ntask, int sweeps_cap,
                               int slot, float4* dyn, int lds_cap, double (*red)[kEnvBlk / 64])
 {
@@ -1590,7 +1671,7 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
     auto start_col = [&](uint32_t col) {
         c = ec[col] + lt;
         hi = ec[col + 1];
-        if (c < hi) cur = load_rows(b, c, p.mu_r > 0.f);
+        if (c < hi) cur = load_rows(b, c, ROLL);
     };
     if (active) start_col(0);
     for (int sw = 0; sw < sweeps_cap; ++sw) {
@@ -1600,10 +1681,11 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
             if (active && col < ncol) {
                 while (c < hi) {
                     uint32_t cn = c + nthr;
+                    BodyRegs B = off >= 0 ? load_bodies(lb, cur) : load_bodies(gb, cur);
                     RowRegs nxt;
-                    if (cn < hi) nxt = load_rows(b, cn, p.mu_r > 0.f);
-                    if (off >= 0) pgs_contact(b, lb, c, cur, p.mu, p.gamma_dt, num, den, p.mu_r > 0.f);
-                    else pgs_contact(b, gb, c, cur, p.mu, p.gamma_dt, num, den, p.mu_r > 0.f);
+                    if (cn < hi) nxt = load_rows(b, cn, ROLL);
+                    if (off >= 0) pgs_contact(b, lb, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
+                    else pgs_contact(b, gb, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
                     cur = nxt;
                     c = cn;
                 }
@@ -1650,11 +1732,13 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
 // most one share (env, rank, cluster size K >= 2, first block) of a
 // multi-block cluster, first, then sets of small envs solved at once (entries
 // (env, waves wb | we << 8, 1, LDS offset); a set starts at wb == 0).
+template <bool ROLL>
 __global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p, int sweeps_cap, int slot, int lds_cap,
                                                       int flow)
 {
     HIP_DYNAMIC_SHARED(float4, dyn_bodies)
     __shared__ double red[2][kEnvBlk / 64];
+    __shared__ uint32_t cb[2][kMaxColours];
     __shared__ int flag;
     if (b.cnt->overflow) return;  // uniform: written by earlier kernels only
     const uint32_t t0 = b.plan_idx[blockIdx.x], t1 = b.plan_idx[blockIdx.x + 1];
@@ -1664,7 +1748,7 @@ __global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p,
         if (pl.z < 2) {
             uint32_t u = t + 1;
             while (u < t1 && b.plan[u].z < 2 && (b.plan[u].y & 255) != 0) ++u;
-            pgs_local_set(b, p, b.plan + t, (int)(u - t), sweeps_cap, slot, dyn_bodies, lds_cap, red);
+            pgs_local_set<ROLL>(b, p, b.plan + t, (int)(u - t), sweeps_cap, slot, dyn_bodies, lds_cap, red);
             __syncthreads();  // LDS and the reduction scratch are reused
             t = u;
             continue;
@@ -1677,48 +1761,61 @@ __global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p,
         int mode = cluster_placement(b.cnt, counter, K, flag);
         XcdBodies xb{raw_rsrc(b.vm), raw_rsrc(b.wi)};
         if (mode == 1 && flow)
-            pgs_solve<XcdBodies, true, false, true>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap, slot,
-                                                    e, red, flag);
+            pgs_solve<XcdBodies, true, false, true, ROLL>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap, slot,
+                                                    e, red, cb, flag);
         else if (mode == 1)
-            pgs_solve<XcdBodies, true, false, false>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap, slot,
-                                                     e, red, flag);
+            pgs_solve<XcdBodies, true, false, false, ROLL>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap, slot,
+                                                     e, red, cb, flag);
         else if (mode == 2)
-            pgs_solve<PlainBodies, true, true, false>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, K,
-                                                      first, sweeps_cap, slot, e, red, flag);
+            pgs_solve<PlainBodies, true, true, false, ROLL>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, K,
+                                                      first, sweeps_cap, slot, e, red, cb, flag);
         if (!flag) return;  // failed barrier: the step is abandoned
         __syncthreads();
         ++t;
     }
 }
 
+// dynamic LDS one per-env block may take: the device's limit per block less
+// the larger static footprint of the two kernel instances
 int pgs_env_max_lds()
 {
     int dev = 0, lds = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    return lds;
+    hipFuncAttributes a0{}, a1{};
+    size_t st = 2048;  // if the attributes cannot be read
+    if (hipFuncGetAttributes(&a0, (const void*)k_pgs_env<false>) == hipSuccess &&
+        hipFuncGetAttributes(&a1, (const void*)k_pgs_env<true>) == hipSuccess)
+        st = std::max(a0.sharedSizeBytes, a1.sharedSizeBytes);
+    return std::max(0, lds - (int)((st + 255) / 256 * 256));
 }
 
+// blocks of either PGS instance (plain or with rolling rows) resident at once:
+// the persistent solves rely on every block of a cluster being resident
 int pgs_env_resident_blocks(int lds_bytes)
 {
-    int dev = 0, per_cu = 0;
+    int dev = 0, c0 = 0, c1 = 0;
     (void)hipGetDevice(&dev);
     hipDeviceProp_t pr;
     (void)hipGetDeviceProperties(&pr, dev);
-    if (lds_bytes > 0)
-        (void)hipFuncSetAttribute((const void*)k_pgs_env, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pgs_env, kEnvBlk, lds_bytes);
-    return std::max(1, per_cu) * pr.multiProcessorCount;
+    if (lds_bytes > 0) {
+        (void)hipFuncSetAttribute((const void*)k_pgs_env<false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        (void)hipFuncSetAttribute((const void*)k_pgs_env<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    }
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&c0, k_pgs_env<false>, kEnvBlk, lds_bytes);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&c1, k_pgs_env<true>, kEnvBlk, lds_bytes);
+    return std::max(1, std::min(c0, c1)) * pr.multiProcessorCount;
 }
 
 int pgs_resident_blocks(int block)
 {
-    int dev = 0, per_cu = 0;
+    int dev = 0, c0 = 0, c1 = 0;
     (void)hipGetDevice(&dev);
     hipDeviceProp_t pr;
     (void)hipGetDeviceProperties(&pr, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pgs, block, 0);
-    return std::max(1, per_cu) * pr.multiProcessorCount;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&c0, k_pgs<false>, block, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&c1, k_pgs<true>, block, 0);
+    return std::max(1, std::min(c0, c1)) * pr.multiProcessorCount;
 }
 
 int colour_resident_blocks()
@@ -1740,12 +1837,18 @@ void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStr
     int flow = z.flow && sw <= z.part_sweeps ? 1 : 0;
     if (flow && p.n_particles > 0) launch_fill_u32(b.ver, 0u, p.n_particles, s);
     if (z.pgs_mode == kModePerEnv) {
-        if (z.plan_blocks > 0)
-            hipLaunchKernelGGL(k_pgs_env, dim3((unsigned)z.plan_blocks), dim3(kEnvBlk), (size_t)z.lds_cap * 32, s, b,
-                               p, sw, slot, z.lds_cap, flow);
+        const dim3 grid((unsigned)z.plan_blocks), blk(kEnvBlk);
+        const size_t lds = (size_t)z.lds_cap * 32;
+        if (z.plan_blocks > 0 && p.mu_r > 0.f)
+            hipLaunchKernelGGL(k_pgs_env<true>, grid, blk, lds, s, b, p, sw, slot, z.lds_cap, flow);
+        else if (z.plan_blocks > 0)
+            hipLaunchKernelGGL(k_pgs_env<false>, grid, blk, lds, s, b, p, sw, slot, z.lds_cap, flow);
         return;
     }
-    hipLaunchKernelGGL(k_pgs, dim3(z.pgs_grid), dim3(kPgsBlk), 0, s, b, p, z.NB, sw, slot, flow);
+    if (p.mu_r > 0.f)
+        hipLaunchKernelGGL(k_pgs<true>, dim3(z.pgs_grid), dim3(kPgsBlk), 0, s, b, p, z.NB, sw, slot, flow);
+    else
+        hipLaunchKernelGGL(k_pgs<false>, dim3(z.pgs_grid), dim3(kPgsBlk), 0, s, b, p, z.NB, sw, slot, flow);
 }
 
 // ---------------------------------------------------------------------------
