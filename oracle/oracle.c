@@ -320,6 +320,7 @@ typedef struct {
     double p[3];         /* contact point */
     double vk[3];        /* kinematic velocity at p (boundary contacts) */
     double Wn, Wt, Dn, Dt, Sig, q, lo, mu;
+    double qg;           /* the overlap part of q (q = qg + Upsilon G_n v) */
     double Wr, rlim;     /* rolling rows: 1/I_1 + 1/I_2, and r mu_r (0: no rolling rows) */
     double wk[3];        /* angular velocity of the kinematic side (boundary contacts) */
     double ln, lt[3];    /* impulses */
@@ -434,7 +435,8 @@ static void build_rows(const orc_params* P, const int64_t* id, const double* r, 
         double u[3];
         rel_vel(R, v, w, u);
         double un = dot3(R->n, u);
-        R->q = -a_coef * gq + b_coef * un;
+        R->qg = -a_coef * gq;
+        R->q = R->qg + b_coef * un;
         double ima = R->a >= 0 ? M->im[R->a] : 0.0, imb = M->im[b];
         double iIa = R->a >= 0 ? M->iI[R->a] : 0.0, iIb = M->iI[b];
         R->Wn = ima + imb;
@@ -972,6 +974,59 @@ static void apply_start(row* rows, int64_t nc, const inv_mass* M, double* v, dou
     }
 }
 
+/* Impact stage, solved before the main solve (the paper's separation of
+ * impacts from resting contacts).  A contact whose normal velocity at the
+ * start of the step approaches faster than v_imp is an impact and gets the
+ * Newton law G_n v+ = -e G_n v-; every other contact keeps its velocity-level
+ * constraints G v+ = 0: a unilateral normal row, Coulomb friction and the
+ * rolling bound, with the stage's own impulses.  The rows are the step's
+ * rows without compliance, regularisation or cohesion, cold-started and
+ * swept in the same colour order as the main solve, with its sweep cap and
+ * tolerance.  v, w are updated in place; the stage's impulses are returned
+ * in li (4 per contact) and lri (3 per contact).  Returns the number of
+ * impacts (0: nothing was done). */
+static int64_t impact_stage(const orc_params* P, const row* rows, int64_t nc, int ncol, const int64_t* cstart,
+                            const int64_t* corder, const inv_mass* M, double* v, double* w, double* li,
+                            double* lri, int* sweeps_out)
+{
+    *sweeps_out = 0;
+    if (!(P->m.v_imp > 0.0) || nc == 0) return 0;
+    int64_t nimp = 0;
+    row* ri = (row*)malloc((size_t)nc * sizeof(row));
+    memcpy(ri, rows, (size_t)nc * sizeof(row));
+    for (int64_t c = 0; c < nc; ++c) {
+        row* R = &ri[c];
+        double u[3];
+        rel_vel(R, v, w, u);
+        double un = dot3(R->n, u);
+        int impact = un < -P->m.v_imp;
+        nimp += impact;
+        R->Sig = 0.0;
+        R->Dn = R->Wn;
+        R->Dt = R->Wt;
+        R->lo = 0.0;
+        R->q = impact ? -P->m.restitution * un : 0.0;
+        R->ln = 0.0;
+        for (int k = 0; k < 3; ++k) R->lt[k] = R->lr[k] = 0.0;
+    }
+    if (nimp > 0) {
+        int k = 0;
+        double Rk = 1.0;
+        while (k < P->max_sweeps) {
+            if (k > 0 && P->tol > 0.0 && Rk <= P->tol) break;
+            Rk = sweep(ri, nc, ncol, cstart, corder, M, v, w, 0.0);
+            ++k;
+        }
+        *sweeps_out = k;
+        for (int64_t c = 0; c < nc; ++c) {
+            li[4 * c] = ri[c].ln;
+            for (int j = 0; j < 3; ++j) { li[4 * c + 1 + j] = ri[c].lt[j]; lri[3 * c + j] = ri[c].lr[j]; }
+        }
+    }
+    free(ri);
+    return nimp;
+}
+
 int64_t orc_step(const orc_params* P,
                  int64_t n, const int64_t* id, const double* r, const double* rho,
                  double* x, double* v, double* w,
@@ -983,7 +1038,7 @@ int64_t orc_step(const orc_params* P,
                  orc_stats* st, double* body_ft,
                  orc_aggregate* agg, int32_t* n_agg, double* resid)
 {
-    if (P->m.mu_r < 0.0 || P->m.restitution != 0.0) return -1;
+    if (P->m.mu_r < 0.0 || !(P->m.restitution >= 0.0 && P->m.restitution <= 1.0)) return -1;
     double dt = P->dt;
     inv_mass M;
     make_inv_mass(P, n, r, rho, &M);
@@ -1019,11 +1074,11 @@ int64_t orc_step(const orc_params* P,
         }
     }
 
-    /* 6. prediction v* = v + dt g */
+    /* start-of-step velocities (the learned start's inputs) */
     double* v0 = (double*)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
+    double* w0 = (double*)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
     memcpy(v0, v, (size_t)n * 3 * sizeof(double));
-    for (int64_t i = 0; i < n; ++i)
-        for (int k = 0; k < 3; ++k) v[3 * i + k] += dt * P->g[k];
+    memcpy(w0, w, (size_t)n * 3 * sizeof(double));
 
     /* colouring and colour-ordered contact list */
     int ncol = colour_contacts(rows, nc, n);
@@ -1037,6 +1092,26 @@ int64_t orc_step(const orc_params* P,
         for (int64_t c = 0; c < nc; ++c) corder[f[rows[c].colour]++] = c;
         free(f);
     }
+
+    /* impact stage on the start-of-step velocities; the main rows' velocity
+     * term then takes the post-impact velocities */
+    double* li = (double*)calloc((size_t)(nc > 0 ? nc : 1) * 4, sizeof(double));
+    double* lri = (double*)calloc((size_t)(nc > 0 ? nc : 1) * 3, sizeof(double));
+    int impact_sweeps = 0;
+    int64_t nimp = impact_stage(P, rows, nc, ncol, cstart, corder, &M, v, w, li, lri, &impact_sweeps);
+    if (nimp > 0) {
+        double tau = P->m.tau_n > 0.0 ? P->m.tau_n : 2.0 * dt;
+        double Ups = 1.0 / (1.0 + 4.0 * tau / dt);
+        for (int64_t c = 0; c < nc; ++c) {
+            double u[3];
+            rel_vel(&rows[c], v, w, u);
+            rows[c].q = rows[c].qg + Ups * dot3(rows[c].n, u);
+        }
+    }
+
+    /* 6. prediction v* = v + dt g */
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) v[3 * i + k] += dt * P->g[k];
 
     double gamma_dt = P->m.gamma_t / dt;
     int sweeps_done = 0;
@@ -1064,7 +1139,7 @@ int64_t orc_step(const orc_params* P,
         double (*fr)[6] = malloc((size_t)nc * sizeof(double[6]));
         double* lsc = (double*)malloc((size_t)nc * sizeof(double));
         double* y = (double*)malloc((size_t)nc * 3 * sizeof(double));
-        learned_features(P, n, x, r, v0, w, rows, nc, lnprev, ltprev, F, fr, lsc);
+        learned_features(P, n, x, r, v0, w0, rows, nc, lnprev, ltprev, F, fr, lsc);
         orc_mlp_forward(mlp, nc, F, y);
         int finite = 1;
         row* rl = (row*)malloc((size_t)nc * sizeof(row));
@@ -1135,10 +1210,12 @@ int64_t orc_step(const orc_params* P,
             if (Rw->a >= 0) continue;
             const orc_body* B = &bodies[Rw->body];
             double f[3], arm[3], t[3];
-            for (int k = 0; k < 3; ++k) f[k] = -(Rw->ln * Rw->n[k] + Rw->lt[k]) / dt;
+            /* the step's impulses: main solve and impact stage */
+            double ln = Rw->ln + li[4 * c];
+            for (int k = 0; k < 3; ++k) f[k] = -(ln * Rw->n[k] + Rw->lt[k] + li[4 * c + 1 + k]) / dt;
             for (int k = 0; k < 3; ++k) arm[k] = Rw->p[k] - B->pos[k];
             cross3(arm, f, t);
-            for (int k = 0; k < 3; ++k) t[k] -= Rw->lr[k] / dt;  /* the rolling couple */
+            for (int k = 0; k < 3; ++k) t[k] -= (Rw->lr[k] + lri[3 * c + k]) / dt;  /* the rolling couple */
             for (int k = 0; k < 3; ++k) { body_ft[6 * Rw->body + k] += f[k]; body_ft[6 * Rw->body + 3 + k] += t[k]; }
         }
     }
@@ -1184,8 +1261,10 @@ int64_t orc_step(const orc_params* P,
         st->r1_first = r1;
         st->r1_trial[0] = r1_trial[0];
         st->r1_trial[1] = r1_trial[1];
+        st->impacts = (int32_t)nimp;
+        st->impact_sweeps = impact_sweeps;
     }
-    free(ltprev); free(lnprev); free(lrprev); free(v0);
+    free(ltprev); free(lnprev); free(lrprev); free(v0); free(w0); free(li); free(lri);
     free(cstart); free(corder); free(rows);
     free(M.im); free(M.iI);
     return nc;

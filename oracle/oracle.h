@@ -41,11 +41,13 @@ typedef struct orc_material {
     double c_p;         /* particle cohesion [Pa] */
     double E;           /* Young's modulus [Pa] */
     double nu;          /* Poisson's ratio */
-    double restitution; /* must be 0 (no impact stage) */
+    double restitution; /* Newton restitution e in [0, 1] of the impact stage */
     double tau_n;       /* normal damping time [s]; <= 0 means 2 dt */
     double gamma_t;     /* tangential regularisation (0 = ideal Coulomb) */
     double kappa_c;     /* cohesive range as a fraction of the summed radii */
     double kappa_min;   /* floor of the overlap used in the compliance */
+    double v_imp;       /* impact threshold [m/s]: a contact approaching faster is an
+                           impact; <= 0 disables the impact stage */
 } orc_material;
 
 typedef struct orc_params {
@@ -107,6 +109,8 @@ typedef struct orc_stats {
     int32_t learned_used;
     double r1_first;     /* residual after the first sweep */
     double r1_trial[2];  /* learned start: first-sweep residual of the learned / previous-step start */
+    int32_t impacts;       /* contacts treated as impacts (0: no impact stage this step) */
+    int32_t impact_sweeps; /* sweeps of the impact stage */
 } orc_stats;
 
 typedef struct orc_aggregate {

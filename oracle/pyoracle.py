@@ -37,7 +37,7 @@ def build(verbose: bool = False) -> str:
 class Material(C.Structure):
     _fields_ = [(k, C.c_double) for k in
                 ("rho", "mu_t", "mu_r", "c_p", "E", "nu", "restitution", "tau_n",
-                 "gamma_t", "kappa_c", "kappa_min")]
+                 "gamma_t", "kappa_c", "kappa_min", "v_imp")]
 
 
 class Params(C.Structure):
@@ -67,7 +67,8 @@ class Mlp(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("contacts", C.c_int64), ("pair_contacts", C.c_int64), ("colours", C.c_int32),
                 ("sweeps", C.c_int32), ("residual", C.c_double), ("fallback_used", C.c_int32),
-                ("learned_used", C.c_int32), ("r1_first", C.c_double), ("r1_trial", C.c_double * 2)]
+                ("learned_used", C.c_int32), ("r1_first", C.c_double), ("r1_trial", C.c_double * 2),
+                ("impacts", C.c_int32), ("impact_sweeps", C.c_int32)]
 
 
 class Aggregate(C.Structure):
@@ -128,7 +129,7 @@ def _c64(a):
 
 
 DEFAULT_MATERIAL = dict(rho=2000.0, mu_t=0.6, mu_r=0.0, c_p=1000.0, E=1e9, nu=0.15, restitution=0.0,
-                        tau_n=0.0, gamma_t=0.0, kappa_c=0.025, kappa_min=1e-4)
+                        tau_n=0.0, gamma_t=0.0, kappa_c=0.025, kappa_min=1e-4, v_imp=0.0)
 
 
 def make_params(spec: dict, detect: int = CELLS) -> Params:
@@ -298,6 +299,7 @@ class OracleScene:
                          contacts=st.contacts, pair_contacts=st.pair_contacts, colours=st.colours,
                          sweeps=st.sweeps, residual=st.residual, fallback_used=st.fallback_used,
                          learned_used=st.learned_used, r1=st.r1_first, r1_trial=tuple(st.r1_trial),
+                         impacts=st.impacts, impact_sweeps=st.impact_sweeps,
                          resid=resid[: st.sweeps].copy(), body_ft=ft[:nb].copy(), aggregates=aggs)
         return self.last
 

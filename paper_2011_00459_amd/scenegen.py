@@ -28,7 +28,7 @@ def fp32(a):
 
 def material(mu=0.6, c=1000.0, rho=2000.0, **kw):
     m = dict(rho=rho, mu_t=mu, mu_r=0.0, c_p=c, E=1e9, nu=0.15, restitution=0.0,
-             tau_n=0.0, gamma_t=0.0, kappa_c=0.025, kappa_min=1e-4)
+             tau_n=0.0, gamma_t=0.0, kappa_c=0.025, kappa_min=1e-4, v_imp=0.0)
     m.update(kw)
     return m
 

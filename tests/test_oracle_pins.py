@@ -697,3 +697,152 @@ def test_rolling_couples_conserve_angular_momentum():
         L1 = ang()
         sc.x = x_new
         assert np.allclose(L1, L0, rtol=0, atol=1e-12 * (np.linalg.norm(L0) + 1e-9))
+
+
+# --------------------------------------------------------------------------
+# Impact stage (Newton law before the main solve): closed forms of collisions
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("e", [0.25, 0.5, 1.0])
+def test_impact_stage_bounce_off_the_floor(e):
+    # a sphere touching the floor approaches at v0 > v_imp: it leaves at e v0,
+    # then gravity acts over the step (the separating contact carries no load)
+    r, v0 = 0.05, 3.0
+    m = sphere_mass(r)
+    spec = base_spec([[0.0, 0.0, r - 1e-6]], [r], [floor_body()], mu=0.5, v=[[0.0, 0.0, -v0]], sweeps=20,
+                     restitution=e, v_imp=1.0)
+    sc = O.OracleScene(spec)
+    out = sc.step()
+    assert out["impacts"] == 1 and out["impact_sweeps"] == 20
+    assert sc.v[0, 2] == pytest.approx(e * v0 - G * DT, rel=1e-12)
+    assert abs(sc.v[0, 0]) < 1e-15 and abs(sc.v[0, 1]) < 1e-15
+    # the floor received the impact impulse m (1 + e) v0 (reported as impulse / dt)
+    assert out["body_ft"][0][2] == pytest.approx(-m * (1.0 + e) * v0 / DT, rel=1e-12)
+
+
+def test_impact_stage_threshold_and_disabled_agree_below_threshold():
+    # no contact approaches faster than v_imp: the step is the plain step, bit for bit
+    spec = SG.column_scene(seed=4, n=300, sweeps=15, footprint=0.5, c=0.0, mu=0.5)
+    plain = O.OracleScene(spec)
+    gated = O.OracleScene(dict(spec, material=dict(spec["material"], restitution=0.5, v_imp=50.0)))
+    for _ in range(3):
+        a, b = plain.step(), gated.step()
+        assert b["impacts"] == 0 and b["impact_sweeps"] == 0
+        assert np.array_equal(plain.v, gated.v) and np.array_equal(plain.w, gated.w)
+        assert np.array_equal(a["lam"], b["lam"])
+
+
+@pytest.mark.parametrize("e", [0.0, 0.3, 1.0])
+def test_impact_stage_head_on_pair(e):
+    # two spheres of different mass, approaching along their line of centres:
+    # Newton's law with momentum conservation, and (e = 1) kinetic energy kept
+    r1, r2, U1, U2 = 0.05, 0.04, 1.5, 0.7
+    m1, m2 = sphere_mass(r1), sphere_mass(r2)
+    spec = base_spec([[0.0, 0.0, 0.0], [r1 + r2 - 1e-6, 0.0, 0.0]], [r1, r2], [], mu=0.4, g=(0.0, 0.0, 0.0),
+                     v=[[U1, 0.0, 0.0], [-U2, 0.0, 0.0]], sweeps=10, restitution=e, v_imp=0.5)
+    sc = O.OracleScene(spec)
+    out = sc.step()
+    assert out["impacts"] == 1
+    P = (1.0 + e) * (U1 + U2) / (1.0 / m1 + 1.0 / m2)
+    if e > 0.0:
+        # separating after the impact: the main solve adds nothing
+        assert sc.v[0, 0] == pytest.approx(U1 - P / m1, rel=1e-12)
+        assert sc.v[1, 0] == pytest.approx(-U2 + P / m2, rel=1e-12)
+        assert sc.v[1, 0] - sc.v[0, 0] == pytest.approx(e * (U1 + U2), rel=1e-12)
+    assert m1 * sc.v[0, 0] + m2 * sc.v[1, 0] == pytest.approx(m1 * U1 - m2 * U2, rel=1e-12)
+    if e == 1.0:
+        ke0 = 0.5 * (m1 * U1 ** 2 + m2 * U2 ** 2)
+        ke1 = 0.5 * (m1 * sc.v[0, 0] ** 2 + m2 * sc.v[1, 0] ** 2)
+        assert ke1 == pytest.approx(ke0, rel=1e-12)
+
+
+@pytest.mark.parametrize("vx,mu,sticks", [(0.4, 0.5, True), (4.0, 0.2, False)])
+def test_impact_stage_oblique_impact_with_friction(vx, mu, sticks):
+    # a non-spinning sphere hits the floor obliquely: normal impulse P_n = m (1+e) v0;
+    # the friction impulse stops the slip when that needs no more than mu P_n
+    # (then v_x' = v_x (m l^2/I) / (1 + m l^2/I), 5/7 v_x for l = r), else slides
+    r, v0, e = 0.05, 2.0, 0.4
+    m = sphere_mass(r)
+    I = 0.4 * m * r * r
+    d0 = 1e-6
+    l = r - d0 / 2
+    spec = base_spec([[0.0, 0.0, r - d0]], [r], [floor_body()], mu=mu, v=[[vx, 0.0, -v0]], sweeps=20,
+                     restitution=e, v_imp=1.0)
+    sc = O.OracleScene(spec)
+    sc.step()
+    Pn = m * (1.0 + e) * v0
+    Pstick = vx / (1.0 / m + l * l / I)
+    assert (Pstick <= mu * Pn) == sticks
+    Pt = Pstick if sticks else mu * Pn
+    assert sc.v[0, 0] == pytest.approx(vx - Pt / m, rel=1e-12)
+    assert sc.w[0, 1] == pytest.approx(l * Pt / I, rel=1e-12)
+    assert sc.v[0, 2] == pytest.approx(e * v0 - G * DT, rel=1e-12)
+    if sticks:
+        assert sc.v[0, 0] == pytest.approx(vx * (m * l * l / I) / (1.0 + m * l * l / I), rel=1e-12)
+        assert abs(sc.v[0, 0] - l * sc.w[0, 1]) < 1e-12  # rolling without slip
+
+
+def test_impact_stage_conserves_momentum_in_a_cluster():
+    # a jittered cluster flying apart and together in free space: the impact
+    # stage and the main solve exchange only pair impulses and couples
+    rng = np.random.default_rng(12)
+    r = 0.05
+    g = np.stack(np.meshgrid(*[np.arange(3)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    x = SG.fp32(g * (2 * r - 0.004) + rng.uniform(-0.001, 0.001, (27, 3)))
+    v = SG.fp32(rng.normal(0.0, 2.0, (27, 3)))
+    w = SG.fp32(rng.normal(0.0, 5.0, (27, 3)))
+    spec = base_spec(x, [r] * 27, [], mu=0.5, g=(0.0, 0.0, 0.0), v=v, w=w, sweeps=30, restitution=0.4,
+                     v_imp=0.5, mu_r=0.1)
+    sc = O.OracleScene(spec)
+    m = sphere_mass(r)
+    I = 0.4 * m * r * r
+    p0 = m * np.sum(sc.v, axis=0)
+    L0 = np.sum(m * np.cross(sc.x, sc.v) + I * sc.w, axis=0)
+    out = sc.step()
+    assert out["impacts"] > 0
+    p1 = m * np.sum(sc.v, axis=0)
+    assert np.allclose(p1, p0, rtol=0, atol=1e-12 * m * np.sum(np.abs(v)))
+    xs = sc.x - DT * sc.v  # the start-of-step positions
+    L1 = np.sum(m * np.cross(xs, sc.v) + I * sc.w, axis=0)
+    assert np.allclose(L1, L0, rtol=0, atol=1e-12 * (np.linalg.norm(L0) + m * r))
+
+
+def test_restitution_outside_unit_interval_is_rejected():
+    spec = base_spec([[0.0, 0.0, 0.04]], [0.05], [floor_body()], restitution=1.5, v_imp=1.0)
+    with pytest.raises(RuntimeError):
+        O.OracleScene(spec).step()
+
+
+def test_impact_stage_inelastic_then_resting_row_uses_post_impact_velocity():
+    # e = 0: the impact stops the approach; the main solve's SPOOK row then sees
+    # the post-impact normal velocity 0 (its target is the overlap term alone),
+    # so one contact's closed form holds: v = v* + W (q - v*) / (W + Sigma),
+    # v* = -g dt, q = (4/dt) Ups 0.8 delta, Ups = 1/(1 + 4 tau/dt), tau = 2 dt
+    r, v0, d0 = 0.05, 3.0, 1e-6
+    m = sphere_mass(r)
+    spec = base_spec([[0.0, 0.0, r - d0]], [r], [floor_body()], mu=0.5, v=[[0.0, 0.0, -v0]], sweeps=20,
+                     restitution=0.0, v_imp=1.0)
+    sc = O.OracleScene(spec)
+    sc.step()
+    ups = 1.0 / (1.0 + 8.0)
+    kn = ESTAR * math.sqrt(2 * r) / 3.0
+    de = max(d0, 1e-4 * 2 * r)
+    sig = (4.0 / DT ** 2) * (4.0 / (5.0 * kn * math.sqrt(de))) * ups
+    q = (4.0 / DT) * ups * 0.8 * d0
+    vstar = -G * DT
+    W = 1.0 / m
+    expect = vstar + W * (q - vstar) / (W + sig)
+    assert sc.v[0, 2] == pytest.approx(expect, rel=1e-9)
+    assert abs(sc.v[0, 2]) < 0.01 * v0  # the approach v0 is gone, not a ninth of it
+
+
+def test_impact_stage_keeps_the_resting_contacts():
+    # sphere B falls on sphere A resting on the floor: the A-floor contact is no
+    # impact but keeps G_n v+ >= 0 in the stage, so A stays and B leaves at e v0
+    r, v0, e = 0.05, 2.0, 0.6
+    spec = base_spec([[0.0, 0.0, r - 1e-6], [0.0, 0.0, 3 * r - 3e-6]], [r, r], [floor_body()], mu=0.3,
+                     v=[[0.0, 0.0, 0.0], [0.0, 0.0, -v0]], sweeps=80, restitution=e, v_imp=1.0)
+    sc = O.OracleScene(spec)
+    out = sc.step()
+    assert out["impacts"] == 1 and out["contacts"] == 2
+    assert sc.v[1, 2] == pytest.approx(e * v0 - G * DT, rel=1e-9)
+    assert abs(sc.v[0, 2]) < 1e-3 * v0
