@@ -66,11 +66,18 @@ typedef struct tr_material {
     double c_p;         /* particle cohesion [Pa]; 0 disables cohesion and its range */
     double E;           /* Young's modulus [Pa] */
     double nu;          /* Poisson's ratio */
-    double restitution; /* must be 0 (no impact stage) */
+    double restitution; /* Newton restitution e in [0, 1] of the impact stage (unused when v_imp <= 0) */
     double tau_n;       /* normal damping time [s]; <= 0 means 2 dt */
     double gamma_t;     /* tangential regularisation [s]; 0 = ideal Coulomb */
     double kappa_c;     /* cohesive range: delta > -kappa_c (r1 + r2) keeps a contact */
     double kappa_min;   /* compliance uses max(delta, kappa_min (r1 + r2)) */
+    double v_imp;       /* impact threshold [m/s] (the impact stage before the main
+                           solve): a contact whose start-of-step normal velocity
+                           approaches faster than v_imp gets G_n v+ = -e G_n v-, the
+                           env's other contacts G v+ = 0 (unilateral normal, Coulomb
+                           and rolling bounds), solved by the same coloured sweeps
+                           without compliance or cohesion; the main solve then starts
+                           from v+.  <= 0 disables the stage. */
 } tr_material;
 
 /* Device memory callbacks: alloc returns device memory usable on `stream`
@@ -143,6 +150,8 @@ typedef struct tr_step_stats {
     double residual_first;   /* R_1 */
     int32_t fallback_used;   /* learned start rejected, PREV/COLD used */
     int32_t overflow;        /* nonzero when a capacity was exceeded (step aborted) */
+    int32_t impacts;         /* contacts treated as impacts (0: no impact stage in this env) */
+    int32_t impact_sweeps;   /* sweeps of the env's impact stage */
 } tr_step_stats;
 
 /* Aggregate body of one active zone (Eqs. aggregate_mass .. aggregate_rot_vel,
@@ -162,7 +171,7 @@ typedef struct tr_scene tr_scene;
 
 /* Creates a scene from *d (copied, env_bounds included).  Allocates all
  * device buffers at their capacities.  TR_E_INVAL for bad sizes or options
- * (mu_r negative, restitution nonzero), TR_E_NOMEM, TR_E_DEVICE. */
+ * (mu_r negative, restitution outside [0, 1], v_imp not finite), TR_E_NOMEM, TR_E_DEVICE. */
 int create_scene(const tr_scene_desc* d, tr_scene** out);
 
 /* Releases every buffer of the scene.  NULL is accepted. */

@@ -487,6 +487,8 @@ void fill_params(tr_scene* s)
     for (int k = 0; k < 3; ++k) p.g[k] = (float)d.gravity[k];
     p.mu = (float)m.mu_t;
     p.mu_r = (float)m.mu_r;
+    p.v_imp = m.v_imp > 0.0 ? (float)m.v_imp : 0.f;
+    p.restitution = (float)m.restitution;
     p.gamma_dt = (float)(m.gamma_t / dt);
     p.kappa_c = m.c_p > 0.0 ? m.kappa_c : 0.0;
     p.kappa_min = m.kappa_min;
@@ -517,7 +519,9 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
     if (d->n_envs < 1 || d->dt <= 0.0 || d->max_sweeps < 0 || d->cap_particles < 1 || d->cap_contacts < 1 ||
         !d->env_bounds)
         return TR_E_INVAL;
-    if (!(d->material.mu_r >= 0.0) || d->material.restitution != 0.0) return TR_E_INVAL;
+    if (!(d->material.mu_r >= 0.0) || !(d->material.restitution >= 0.0 && d->material.restitution <= 1.0) ||
+        !std::isfinite(d->material.v_imp))
+        return TR_E_INVAL;
     if (d->warm_start < TR_WARM_COLD || d->warm_start > TR_WARM_LEARNED) return TR_E_INVAL;
     if ((int64_t)d->n_envs * d->cap_particles >= ((int64_t)1 << 31) ||
         (int64_t)d->n_envs * d->cap_contacts >= ((int64_t)1 << 31))
@@ -536,6 +540,7 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
     z.NID = z.P;
     z.NB = (z.C + 255) / 256;
     z.roll_C = d->material.mu_r > 0.0 ? z.C : 1;  // rolling rows only when mu_r > 0
+    z.imp_C = d->material.v_imp > 0.0 ? z.C : 1;  // impact-stage rows only when v_imp > 0
     z.n_envs = d->n_envs;
     z.pgs_block = 512;
     s->p.n_units = std::max(kGroups, d->n_envs);
@@ -564,6 +569,8 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
               alloc_n(s, b.r0, z.C) && alloc_n(s, b.r1, z.C) && alloc_n(s, b.r2, z.C) && alloc_n(s, b.rk, z.C) &&
               alloc_n(s, b.r3, z.roll_C) && alloc_n(s, b.lamr, z.roll_C) && alloc_n(s, b.lamr0, z.roll_C) &&
               alloc_n(s, b.lamrc, z.roll_C) && alloc_n(s, b.plamr, z.roll_C) &&
+              alloc_n(s, b.ri1, z.imp_C) && alloc_n(s, b.ri2, z.imp_C) && alloc_n(s, b.lami, z.imp_C) &&
+              alloc_n(s, b.lamri, std::min(z.imp_C, z.roll_C)) && alloc_n(s, b.qg, z.imp_C) &&
               alloc_n(s, b.lam, z.C) && alloc_n(s, b.lam0, z.C) &&
               alloc_n(s, b.envs, d->n_envs) && alloc_n(s, b.ustats, s->p.n_units) &&
               alloc_n(s, b.env_col, (int64_t)d->n_envs * (kMaxColours + 1)) && alloc_n(s, b.env_ncol, d->n_envs) &&
@@ -760,6 +767,7 @@ void enqueue_step(tr_scene* s, hipStream_t st, bool events)
     launch_depth(s->b, s->p, s->z, st);
     launch_colour(s->b, s->p, s->z, st);
     launch_rows(s->b, s->p, s->z, s->have_prev, st);
+    launch_impact_stage(s->b, s->p, s->z, st);
     if (s->p.warm == TR_WARM_LEARNED && s->mlp_loaded) {
         // learned start, then the first-sweep trial against the previous-step start
         launch_mlp_infer(s->b.mlp, s->b.feat, s->b.mlp_out, &s->b.cnt->n_raw, s->z.C, s->mlp_bf16, st);
@@ -880,6 +888,8 @@ static int step_scene(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
             o.residual_first = G.resid_first;
             o.fallback_used = s->p.warm == TR_WARM_LEARNED && s->mlp_loaded ? (int32_t)G.fallback : 0;
             o.overflow = (int32_t)c.overflow;
+            o.impacts = (int32_t)es[e2].impacts;
+            o.impact_sweeps = es[e2].impacts > 0 ? (int32_t)G.imp_sweeps : 0;
         }
         if (c.overflow) {
             s->have_prev = false;

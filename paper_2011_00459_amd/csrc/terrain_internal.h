@@ -19,6 +19,7 @@
 
 namespace trk {
 
+constexpr int kSlotImpact = 3;     // PGS statistics slot of the impact stage
 constexpr int kMaxColours = 64;     // colours of the contact schedule (64-bit masks)
 constexpr int kGroups = 8;          // PGS groups: one per XCD of the MI355X (block b runs on XCD b % 8)
 constexpr int kBuckets = kMaxColours * kGroups;  // (colour, group) buckets of the PGS order
@@ -122,9 +123,9 @@ struct StepParams {
     double gdt;         // |g| dt
     double r_ref;       // nominal radius of the features
     float mu_r;         // rolling resistance (0: no rolling rows)
-    int pad_roll;
+    float v_imp;        // impact threshold (<= 0: no impact stage)
     int n_units;        // PGS solve units (entries of ustats)
-    int pad_units;
+    float restitution;  // Newton restitution of the impact stage
 };
 
 // per PGS solve unit: an XCD group of envs (grouped mode) or one env
@@ -137,7 +138,9 @@ struct UnitStats {
     double resid;
     double resid_first;
     double r1_trial[2];    // first-sweep residual from the learned / previous start
-    double pad2[2];
+    uint32_t imp_any;      // some contact of the unit is an impact this step
+    uint32_t imp_sweeps;   // sweeps of the unit's impact stage
+    uint32_t pad2[2];
 };
 
 struct Counters {
@@ -152,6 +155,7 @@ struct Counters {
 struct EnvStats {
     int64_t contacts;
     int64_t pairs;
+    unsigned long long impacts;  // contacts of the env treated as impacts this step
 };
 
 // Everything the kernels touch, as raw device pointers.
@@ -177,6 +181,11 @@ struct DevBuffers {
     // rolling rows (allocated when mu_r > 0): r3 = (1/W_r, r mu_r, kinematic body, 0),
     // lamr = (lambda_r, 0) and its start value, canonical current / previous caches
     float4 *r3, *lamr, *lamr0, *lamrc, *plamr;
+    // impact stage (allocated when v_imp > 0): its rows ri1 = (l2, 1/W_n, 1/W_t, 0)
+    // and ri2 = (target, 0, body 1, body 2), its impulses, and the overlap part
+    // of the main rows' q (q = qg + Upsilon G_n v)
+    float4 *ri1, *ri2, *lami, *lamri;
+    float* qg;
     // reductions
     double* resid_acc;    // [max_sweeps * 2] per-sweep numerator / denominator... (block partials)
     double* block_part;   // [2 parities][grid][2]
@@ -219,6 +228,7 @@ struct Sizes {
     int64_t NC;     // cells (all envs)
     int64_t NB;     // blocks of 256 over C (colour bucketing)
     int64_t roll_C; // entries of the rolling-row arrays (C when mu_r > 0, else 1)
+    int64_t imp_C;  // entries of the impact-stage arrays (C when v_imp > 0, else 1)
     int n_envs;
     int n_zone_chunks;
     int pgs_grid;   // blocks of the persistent PGS kernel (kGroups x blocks per group)
@@ -244,6 +254,9 @@ void launch_narrow(const DevBuffers& b, const StepParams& p, const Sizes& z, hip
 void launch_canonical(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, hipStream_t s);
+// impact stage: rows of envs without impacts neutralised, the stage's sweeps
+// (stats slot kSlotImpact), the main rows' q from the post-impact velocities
+void launch_impact_stage(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 // sweeps_cap < 0: the scene's max_sweeps; slot 0 writes the step stats,
 // slot 1/2 the first-sweep residual of the learned / previous-step trial

@@ -304,7 +304,12 @@ __global__ void k_step_begin(DevBuffers b, StepParams p)
         uint32_t* w = reinterpret_cast<uint32_t*>(b.cnt);
         for (int k = t; k < (int)(sizeof(Counters) / 4); k += gridDim.x * blockDim.x) w[k] = 0u;
     }
-    if (t < p.n_envs) { b.env_stats[t].contacts = 0; b.env_stats[t].pairs = 0; b.env_ncol[t] = 0; }
+    if (t < p.n_envs) {
+        b.env_stats[t].contacts = 0;
+        b.env_stats[t].pairs = 0;
+        b.env_stats[t].impacts = 0;
+        b.env_ncol[t] = 0;
+    }
     if (t < p.n_units) {
         uint32_t* w = reinterpret_cast<uint32_t*>(&b.ustats[t]);
         for (int k = 0; k < (int)(sizeof(UnitStats) / 4); ++k) w[k] = 0u;
@@ -1003,6 +1008,22 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     b.rk[pos] = make_float4((float)vk[0], (float)vk[1], (float)vk[2], __uint_as_float(seq));
     b.lam[pos] = L;
     b.lam0[pos] = L;
+    if (p.v_imp > 0.f) {
+        // impact stage (before the main solve): a contact whose start-of-step
+        // normal velocity approaches faster than v_imp gets the Newton law
+        // G_n v+ = -e G_n v-, every other contact G_n v+ >= 0; no compliance,
+        // regularisation or cohesion
+        const bool impact = un < -(double)p.v_imp;
+        b.ri1[pos] = make_float4((float)l2, (float)(1.0 / Wn), (float)(1.0 / Wt), 0.f);
+        b.ri2[pos] = make_float4(impact ? (float)(-(double)p.restitution * un) : 0.f, 0.f, __int_as_float(ia),
+                                 __int_as_float(ib));
+        b.qg[pos] = (float)(p.a_coef * (0.8 * delta));
+        if (impact) {
+            const int e = (int)((uint32_t)(key >> 32) / p.id_cap);
+            atomicAdd(&b.env_stats[e].impacts, 1ull);
+            atomicOr(&b.ustats[b.envs[e].unit].imp_any, 1u);
+        }
+    }
     if (p.mu_r > 0.f) {
         // rolling row (Eq. signCoul3): 1/(1/I_1 + 1/I_2), r mu_r with r the
         // smaller radius, the kinematic body of a boundary contact; the start
@@ -1020,6 +1041,68 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
 void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, hipStream_t s)
 {
     hipLaunchKernelGGL(k_rows, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, p, z.C, have_prev ? 1 : 0);
+}
+
+// Impact stage set-up: the stage's impulses start at zero, and the rows of an
+// env without impacts do nothing (zero inverse masses: the stage leaves that
+// env as it is, as if solved alone).
+__global__ void k_impact_prep(DevBuffers b, StepParams p, int64_t cap)
+{
+    uint32_t nc = n_contacts(b, cap);
+    uint32_t pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= nc) return;
+    if (b.cnt->overflow) return;
+    b.lami[pos] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p.mu_r > 0.f) b.lamri[pos] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int ib = __float_as_int(b.ri2[pos].w);
+    const int e = (int)((uint32_t)b.pid[ib] / p.id_cap);
+    if (b.env_stats[e].impacts == 0) {
+        float4 r = b.ri1[pos];
+        b.ri1[pos] = make_float4(r.x, 0.f, 0.f, 0.f);
+    }
+}
+
+// After the impact stage: the main rows' velocity term from the post-impact
+// velocities, q = qg + Upsilon G_n v+ (envs with impacts; the others keep q).
+__global__ void k_impact_q(DevBuffers b, StepParams p, int64_t cap)
+{
+    uint32_t nc = n_contacts(b, cap);
+    uint32_t pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= nc) return;
+    if (b.cnt->overflow) return;
+    float4 q = b.r2[pos];
+    const int ia = __float_as_int(q.z), ib = __float_as_int(q.w);
+    const int e = (int)((uint32_t)b.pid[ib] / p.id_cap);
+    if (b.env_stats[e].impacts == 0) return;
+    const float4 a = b.r0[pos], v2 = b.vm[ib];
+    double v1[3];
+    if (ia >= 0) {
+        const float4 t = b.vm[ia];
+        v1[0] = t.x; v1[1] = t.y; v1[2] = t.z;
+    } else {
+        const float4 k = b.rk[pos];
+        v1[0] = k.x; v1[1] = k.y; v1[2] = k.z;
+    }
+    double un = ((double)a.x * ((double)v2.x - v1[0]) + (double)a.y * ((double)v2.y - v1[1])) +
+                (double)a.z * ((double)v2.z - v1[2]);
+    q.x = (float)((double)b.qg[pos] + p.b_coef * un);
+    b.r2[pos] = q;
+}
+
+void launch_impact_stage(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+{
+    if (!(p.v_imp > 0.f)) return;
+    const dim3 g((unsigned)cdiv(z.C, kBlk));
+    hipLaunchKernelGGL(k_impact_prep, g, dim3(kBlk), 0, s, b, p, z.C);
+    DevBuffers bi = b;
+    bi.r1 = b.ri1;
+    bi.r2 = b.ri2;
+    bi.lam = b.lami;
+    bi.lamr = b.lamri;
+    StepParams pi = p;
+    pi.gamma_dt = 0.f;
+    launch_pgs(bi, pi, z, s, -1, kSlotImpact);
+    hipLaunchKernelGGL(k_impact_q, g, dim3(kBlk), 0, s, b, p, z.C);
 }
 
 // ---------------------------------------------------------------------------
@@ -1284,8 +1367,9 @@ __device__ inline void pgs_contact(const DevBuffers& b, const BA& ba, uint32_t c
         va.x -= dx * va.w; va.y -= dy * va.w; va.z -= dz * va.w;
         wa.x -= l1 * wa.w * cx; wa.y -= l1 * wa.w * cy; wa.z -= l1 * wa.w * cz;
     }
-    // residual weights (the stopping test only): hardware reciprocals
-    float Dn = __builtin_amdgcn_rcpf(iDn), Dt = __builtin_amdgcn_rcpf(iDt);
+    // residual weights (the stopping test only): hardware reciprocals; a row
+    // with zero inverse mass (a neutralised impact-stage row) weighs nothing
+    float Dn = iDn > 0.f ? __builtin_amdgcn_rcpf(iDn) : 0.f, Dt = iDt > 0.f ? __builtin_amdgcn_rcpf(iDt) : 0.f;
     num += Dn * dn * dn + Dt * (dx * dx + dy * dy + dz * dz);
     den += Dn * ln * ln + Dt * (tx * tx + ty * ty + tz * tz);
     if (roll) {
@@ -1568,6 +1652,8 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
             G.sweeps = (uint32_t)sweeps;
             G.resid = Rk;
             G.resid_first = R1;
+        } else if (slot == kSlotImpact) {
+            G.imp_sweeps = (uint32_t)sweeps;
         } else {
             G.r1_trial[slot - 1] = R1;
         }
@@ -1612,6 +1698,7 @@ __global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int
     uint32_t total = 0;
     for (uint32_t col = 0; col < ncol; ++col) total += cs.end(col) - cs.beg(col);
     if (total == 0) ncol = 0;
+    if (slot == kSlotImpact && !b.ustats[g].imp_any) ncol = 0;  // no impact in the group
     uint32_t* counter = &b.cnt->bar[g][0];
     int mode = cluster_placement(b.cnt, counter, gx, flag);
     if (mode == 1) {
@@ -1662,7 +1749,7 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
         }
     __syncthreads();
     const uint32_t* ec = b.env_col + (size_t)(e >= 0 ? e : 0) * (kMaxColours + 1);
-    const uint32_t ncol = e >= 0 ? b.env_ncol[e] : 0;
+    const uint32_t ncol = e >= 0 && !(slot == kSlotImpact && !b.ustats[e].imp_any) ? b.env_ncol[e] : 0;
     bool active = ncol > 0;  // uniform over the env's waves
     int sweeps = 0;
     double Rk = 0.0, R1 = 0.0;
@@ -1722,6 +1809,8 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
             G.sweeps = (uint32_t)sweeps;
             G.resid = Rk;
             G.resid_first = R1;
+        } else if (slot == kSlotImpact) {
+            G.imp_sweeps = (uint32_t)sweeps;
         } else {
             G.r1_trial[slot - 1] = R1;
         }
@@ -1756,7 +1845,7 @@ __global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p,
         const int e = pl.x;
         const unsigned rank = pl.y, K = pl.z, first = pl.w;
         EnvStarts cs{b.env_col + (size_t)e * (kMaxColours + 1)};
-        const uint32_t ncol = b.env_ncol[e];
+        const uint32_t ncol = slot == kSlotImpact && !b.ustats[e].imp_any ? 0u : b.env_ncol[e];
         uint32_t* counter = b.env_bar + (size_t)e * 16;
         int mode = cluster_placement(b.cnt, counter, K, flag);
         XcdBodies xb{raw_rsrc(b.vm), raw_rsrc(b.wi)};
@@ -2024,8 +2113,12 @@ __global__ __launch_bounds__(kRedBlk) void k_force_part(DevBuffers b, StepParams
         float4 a = b.r0[pos];
         double l2 = b.r1[pos].x;
         float4 x2 = b.xr[pr.y];
-        double f[3] = {-((double)L.x * a.x + L.y) / p.dt, -((double)L.x * a.y + L.z) / p.dt,
-                       -((double)L.x * a.z + L.w) / p.dt};
+        double J[4] = {L.x, L.y, L.z, L.w};
+        if (p.v_imp > 0.f) {  // the step's impulses include the impact stage's
+            const float4 Li = b.lami[pos];
+            J[0] += Li.x; J[1] += Li.y; J[2] += Li.z; J[3] += Li.w;
+        }
+        double f[3] = {-(J[0] * a.x + J[1]) / p.dt, -(J[0] * a.y + J[2]) / p.dt, -(J[0] * a.z + J[3]) / p.dt};
         double arm[3] = {(double)x2.x - l2 * a.x - B.pos[0], (double)x2.y - l2 * a.y - B.pos[1],
                          (double)x2.z - l2 * a.z - B.pos[2]};
         acc[0] += f[0]; acc[1] += f[1]; acc[2] += f[2];
@@ -2034,9 +2127,14 @@ __global__ __launch_bounds__(kRedBlk) void k_force_part(DevBuffers b, StepParams
         acc[5] += arm[0] * f[1] - arm[1] * f[0];
         if (p.mu_r > 0.f) {  // the rolling couple
             float4 Lr = b.lamr[pos];
-            acc[3] -= (double)Lr.x / p.dt;
-            acc[4] -= (double)Lr.y / p.dt;
-            acc[5] -= (double)Lr.z / p.dt;
+            double R[3] = {Lr.x, Lr.y, Lr.z};
+            if (p.v_imp > 0.f) {
+                const float4 Li = b.lamri[pos];
+                R[0] += Li.x; R[1] += Li.y; R[2] += Li.z;
+            }
+            acc[3] -= R[0] / p.dt;
+            acc[4] -= R[1] / p.dt;
+            acc[5] -= R[2] / p.dt;
         }
     }
     for (int k = 0; k < 6; ++k) {

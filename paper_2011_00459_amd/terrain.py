@@ -38,7 +38,8 @@ class TerrainError(RuntimeError):
 
 class tr_material(C.Structure):
     _fields_ = [(k, C.c_double) for k in
-                ("rho", "mu_t", "mu_r", "c_p", "E", "nu", "restitution", "tau_n", "gamma_t", "kappa_c", "kappa_min")]
+                ("rho", "mu_t", "mu_r", "c_p", "E", "nu", "restitution", "tau_n", "gamma_t", "kappa_c", "kappa_min",
+                 "v_imp")]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -69,7 +70,8 @@ class tr_body_desc(C.Structure):
 class tr_step_stats(C.Structure):
     _fields_ = [("contacts", C.c_int64), ("pair_contacts", C.c_int64), ("colours", C.c_int32),
                 ("sweeps", C.c_int32), ("residual", C.c_double), ("residual_first", C.c_double),
-                ("fallback_used", C.c_int32), ("overflow", C.c_int32)]
+                ("fallback_used", C.c_int32), ("overflow", C.c_int32), ("impacts", C.c_int32),
+                ("impact_sweeps", C.c_int32)]
 
 
 class tr_solver_config(C.Structure):
@@ -144,7 +146,7 @@ def _c64(a, shape=None):
 
 
 MATERIAL_DEFAULTS = dict(rho=2000.0, mu_t=0.6, mu_r=0.0, c_p=1000.0, E=1e9, nu=0.15, restitution=0.0,
-                         tau_n=0.0, gamma_t=0.0, kappa_c=0.025, kappa_min=1e-4)
+                         tau_n=0.0, gamma_t=0.0, kappa_c=0.025, kappa_min=1e-4, v_imp=0.0)
 
 
 class Scene:
@@ -257,7 +259,7 @@ class Scene:
         self._check(lib().step(self.h, n_steps, st), "step")
         return [dict(contacts=s.contacts, pair_contacts=s.pair_contacts, colours=s.colours, sweeps=s.sweeps,
                      residual=s.residual, residual_first=s.residual_first, fallback_used=s.fallback_used,
-                     overflow=s.overflow) for s in st]
+                     overflow=s.overflow, impacts=s.impacts, impact_sweeps=s.impact_sweeps) for s in st]
 
     def get_contact_forces(self, env, body_id):
         f = np.zeros(3)

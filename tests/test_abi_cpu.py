@@ -71,9 +71,12 @@ def test_invalid_arguments_rejected_without_device_work():
     d.material.mu_r = -0.1
     assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_INVAL  # negative rolling resistance
     d.material.mu_r = 0.0
-    d.material.restitution = 0.3
-    assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_INVAL  # no impact stage
+    d.material.restitution = 1.3
+    assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_INVAL  # restitution outside [0, 1]
     d.material.restitution = 0.0
+    d.material.v_imp = float("inf")
+    assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_INVAL  # impact threshold not finite
+    d.material.v_imp = 0.0
     bn = np.array([0, 0, 0, 1, np.nan, 1.0])
     d.env_bounds = bn.ctypes.data_as(C.POINTER(C.c_double))
     assert lib.create_scene(C.byref(d), C.byref(h)) == T.TR_E_NONFINITE
