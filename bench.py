@@ -219,10 +219,10 @@ def mlp_throughput(n=1 << 22):
         T.mlp_forward(W.ptr, F.ptr, n, Y.ptr, bf16=bf16)
         device_sync()
         t0 = time.perf_counter()
-        for _ in range(5):
+        for _ in range(20):
             T.mlp_forward(W.ptr, F.ptr, n, Y.ptr, bf16=bf16)
         device_sync()
-        dt = (time.perf_counter() - t0) / 5
+        dt = (time.perf_counter() - t0) / 20
         tf = flops_fwd * n / dt / 1e12
         peak = 2500.0 if bf16 else 157.3
         out[name] = dict(samples=n, ms=1e3 * dt, tflops=tf, peak_tflops=peak, frac=tf / peak)

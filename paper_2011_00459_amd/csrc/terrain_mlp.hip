@@ -37,113 +37,134 @@ __device__ inline float dsilu(float z)
     return s * (1.0f + z * (1.0f - s));
 }
 
-// round-to-nearest-even FP32 -> BF16 bits
-__device__ inline short to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
+// FP32 -> BF16 bits, round to nearest even (the hardware conversion)
+__device__ inline short to_bf16(float f) { return __builtin_bit_cast(short, (__bf16)f); }
+
+// SiLU of the BF16 inference: the hardware reciprocal (about 1 ulp) in place
+// of a full division
+__device__ inline float silu_fast(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// BF16 MFMA inference.  Block = 4 waves; each wave takes 32 contacts at a time.
-//   layer 1: X[32 x 16] (12 inputs padded) . W1^T[16 x 64]: 2 N-tiles x 2 K-steps
-//   layer 2: H1[32 x 64] . W2^T[64 x 64]: 2 N-tiles x 8 K-steps
+// BF16 MFMA inference.  Each wave works alone on tiles of 32 contacts (no
+// block barriers): the W1 and W2 operands stay in registers for the whole
+// launch, the input tile is read from global memory straight into the A
+// operand, and one per-wave LDS tile turns each layer's D layout into the
+// next layer's A layout.
+//   layer 1: X[32 x 16] (12 inputs padded) . W1^T[16 x 64]: 2 N-tiles x 1 K-step
+//   layer 2: H1[32 x 64] . W2^T[64 x 64]: 2 N-tiles x 4 K-steps
 //   layer 3: 3 outputs per contact on the vector ALU from H2 (FP32 in LDS)
-// Operand layouts of v_mfma_f32_32x32x8_bf16 (A 32x8, B 8x32, D 32x32):
-//   A[i][k] -> lane i + 32 (k / 4), element k % 4
-//   B[k][j] -> lane j + 32 (k / 4), element k % 4
+// Operand layouts of v_mfma_f32_32x32x16_bf16 (A 32x16, B 16x32, D 32x32):
+//   A[i][k] -> lane i + 32 (k / 8), element k % 8
+//   B[k][j] -> lane j + 32 (k / 8), element k % 8
 //   D[i][j] -> lane j + 32 ((i / 4) % 2), element (i % 4) + 4 (i / 8)
 // ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
 constexpr int kMlpWaves = 4;
+constexpr int kH1Pitch = kH + 8;   // BF16 transpose tile row (16-byte aligned rows)
+constexpr int kH2Pitch = kH + 1;   // FP32 layer-2 output row (floats)
+
+__device__ inline void wave_sync()
+{
+    // the LDS operations of one wave run in order; keep the compiler from
+    // moving them across this point
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_bf16(const float* __restrict__ W, const float* __restrict__ feat,
                                                               float* __restrict__ out, const uint32_t* d_n, int64_t cap)
 {
-    __shared__ short w1[kH][16];            // W1 rows, K padded to 16
-    __shared__ short w2[kH][kH];
     __shared__ float w3[kOut][kH];
-    __shared__ float b1[kH], b2[kH], b3[kOut], sc[kIn];
-    __shared__ short xs[kMlpWaves][32][16];
-    __shared__ short hs[kMlpWaves][32][kH + 4];
-    __shared__ float h2s[kMlpWaves][32][kH + 1];
+    __shared__ __attribute__((aligned(16))) __bf16 h1s[kMlpWaves][32][kH1Pitch];
+    __shared__ float h2s[kMlpWaves][32][kH2Pitch];
     const int tid = threadIdx.x;
-    for (int t = tid; t < kH * 16; t += blockDim.x) {
-        int j = t / 16, k = t % 16;
-        w1[j][k] = k < kIn ? to_bf16(W[oW1 + j * kIn + k]) : (short)0;
-    }
-    for (int t = tid; t < kH * kH; t += blockDim.x) w2[t / kH][t % kH] = to_bf16(W[oW2 + t]);
     for (int t = tid; t < kOut * kH; t += blockDim.x) w3[t / kH][t % kH] = W[oW3 + t];
-    for (int t = tid; t < kH; t += blockDim.x) { b1[t] = W[ob1 + t]; b2[t] = W[ob2 + t]; }
-    if (tid < kOut) b3[tid] = W[ob3 + tid];
-    if (tid < kIn) sc[tid] = W[oScale + tid];
-    __syncthreads();
+    __syncthreads();  // the only block barrier: w3 is read-only afterwards
 
-    uint64_t n = d_n ? (uint64_t)min((uint64_t)*d_n, (uint64_t)cap) : (uint64_t)cap;
     const int wave = tid >> 6, lane = tid & 63;
     const int half = lane >> 5, col = lane & 31;
-    uint64_t ntiles = (n + 31) / 32;
-    // every wave of the block runs the same number of iterations (barriers)
-    for (uint64_t base = (uint64_t)blockIdx.x * kMlpWaves; base < ntiles; base += (uint64_t)gridDim.x * kMlpWaves) {
-        uint64_t c0 = (base + wave) * 32;
-        // stage the 32 x 16 input tile (scaled features, BF16)
-        for (int t = lane; t < 32 * 16; t += 64) {
-            int i = t / 16, k = t % 16;
-            uint64_t c = c0 + i;
-            float v = (k < kIn && c < n) ? feat[c * kIn + k] * sc[k] : 0.0f;
-            xs[wave][i][k] = to_bf16(v);
+    // B operands of layers 1 and 2 and this lane's biases and input scales
+    bf16x8 B1[2], B2[2][4];
+    for (int nt = 0; nt < 2; ++nt) {
+        const int j = nt * 32 + col;
+        for (int q = 0; q < 8; ++q) {
+            const int k = half * 8 + q;
+            B1[nt][q] = (__bf16)(k < kIn ? W[oW1 + j * kIn + k] : 0.0f);
         }
-        __syncthreads();
+        for (int ks = 0; ks < 4; ++ks)
+            for (int q = 0; q < 8; ++q) B2[nt][ks][q] = (__bf16)W[oW2 + j * kH + ks * 16 + half * 8 + q];
+    }
+    const float bias1[2] = {W[ob1 + col], W[ob1 + 32 + col]};
+    const float bias2[2] = {W[ob2 + col], W[ob2 + 32 + col]};
+    const float b3v[kOut] = {W[ob3], W[ob3 + 1], W[ob3 + 2]};
+    float scl[8];  // scales of this lane's input columns 8 half .. 8 half + 7
+    for (int q = 0; q < 8; ++q) scl[q] = half * 8 + q < kIn ? W[oScale + half * 8 + q] : 0.0f;
+
+    const uint64_t n = d_n ? (uint64_t)min((uint64_t)*d_n, (uint64_t)cap) : (uint64_t)cap;
+    const uint64_t ntiles = (n + 31) / 32;
+    const uint64_t nwaves = (uint64_t)gridDim.x * kMlpWaves;
+    __bf16(*hs)[kH1Pitch] = h1s[wave];
+    float(*h2)[kH2Pitch] = h2s[wave];
+    // the input row of a tile: lane (col, half) holds features 8 half .. 8 half + 7
+    // (only 8 .. 11 of the second half are inside the 12)
+    auto load_x = [&](uint64_t tile, float4& x0, float4& x1) {
+        const uint64_t c = tile * 32 + col;
+        x0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        x1 = x0;
+        if (tile < ntiles && c < n) {
+            const float4* f = reinterpret_cast<const float4*>(feat + c * kIn);
+            x0 = f[2 * half];
+            if (half == 0) x1 = f[1];
+        }
+    };
+    uint64_t tile = (uint64_t)blockIdx.x * kMlpWaves + wave;
+    float4 x0, x1;
+    load_x(tile, x0, x1);
+    for (; tile < ntiles; tile += nwaves) {
+        bf16x8 A1;
+        A1[0] = (__bf16)(x0.x * scl[0]); A1[1] = (__bf16)(x0.y * scl[1]);
+        A1[2] = (__bf16)(x0.z * scl[2]); A1[3] = (__bf16)(x0.w * scl[3]);
+        A1[4] = (__bf16)(x1.x * scl[4]); A1[5] = (__bf16)(x1.y * scl[5]);
+        A1[6] = (__bf16)(x1.z * scl[6]); A1[7] = (__bf16)(x1.w * scl[7]);
+        load_x(tile + nwaves, x0, x1);  // the next tile's rows, in flight meanwhile
         // layer 1
         for (int nt = 0; nt < 2; ++nt) {
             floatx16 acc = {};
-            for (int ks = 0; ks < 2; ++ks) {
-                int k0 = ks * 8 + half * 4;
-                bf16x4 a, bb;
-                for (int e = 0; e < 4; ++e) { a[e] = xs[wave][col][k0 + e]; bb[e] = w1[nt * 32 + col][k0 + e]; }
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc, 0, 0, 0);
-            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B1[nt], acc, 0, 0, 0);
             for (int e = 0; e < 16; ++e) {
-                int i = (e & 3) + 8 * (e >> 2) + 4 * half;
-                int j = nt * 32 + col;
-                hs[wave][i][j] = to_bf16(silu(acc[e] + b1[j]));
+                const int i = (e & 3) + 8 * (e >> 2) + 4 * half;
+                hs[i][nt * 32 + col] = (__bf16)silu_fast(acc[e] + bias1[nt]);
             }
         }
-        __syncthreads();
+        wave_sync();
         // layer 2
+        bf16x8 A2[4];
+        for (int ks = 0; ks < 4; ++ks) A2[ks] = *reinterpret_cast<const bf16x8*>(&hs[col][ks * 16 + half * 8]);
         for (int nt = 0; nt < 2; ++nt) {
             floatx16 acc = {};
-            for (int ks = 0; ks < 8; ++ks) {
-                int k0 = ks * 8 + half * 4;
-                bf16x4 a, bb;
-                for (int e = 0; e < 4; ++e) { a[e] = hs[wave][col][k0 + e]; bb[e] = w2[nt * 32 + col][k0 + e]; }
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bb, acc, 0, 0, 0);
-            }
+            for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2[ks], B2[nt][ks], acc, 0, 0, 0);
             for (int e = 0; e < 16; ++e) {
-                int i = (e & 3) + 8 * (e >> 2) + 4 * half;
-                int j = nt * 32 + col;
-                h2s[wave][i][j] = silu(acc[e] + b2[j]);
+                const int i = (e & 3) + 8 * (e >> 2) + 4 * half;
+                h2[i][nt * 32 + col] = silu_fast(acc[e] + bias2[nt]);
             }
         }
-        __syncthreads();
+        wave_sync();
         // layer 3: lanes 0..31 own one contact each, the two halves split K
-        {
-            int i = col;
-            float y[kOut];
-            for (int o = 0; o < kOut; ++o) {
-                float s = 0.0f;
-                for (int k = half * 32; k < half * 32 + 32; ++k) s += w3[o][k] * h2s[wave][i][k];
-                s += __shfl_xor(s, 32, 64);
-                y[o] = s + b3[o];
-            }
-            uint64_t c = c0 + i;
-            if (half == 0 && c < n)
-                for (int o = 0; o < kOut; ++o) out[c * kOut + o] = y[o];
+        float y[kOut];
+        for (int o = 0; o < kOut; ++o) {
+            float s = 0.0f;
+            for (int k = half * 32; k < half * 32 + 32; ++k) s += w3[o][k] * h2[col][k];
+            s += __shfl_xor(s, 32, 64);
+            y[o] = s + b3v[o];
         }
-        __syncthreads();
+        const uint64_t c = tile * 32 + col;
+        if (half == 0 && c < n)
+            for (int o = 0; o < kOut; ++o) out[c * kOut + o] = y[o];
+        wave_sync();  // the tiles are rewritten by the next iteration
     }
 }
 
@@ -179,8 +200,18 @@ void launch_mlp_infer(const float* W, const float* feat, float* out, const uint3
 {
     if (cap <= 0) return;
     if (bf16) {
+        // one round of resident blocks, each wave looping over tiles
+        static int resident = 0;
+        if (!resident) {
+            int dev = 0, per_cu = 0;
+            (void)hipGetDevice(&dev);
+            hipDeviceProp_t pr;
+            (void)hipGetDeviceProperties(&pr, dev);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mlp_bf16, 64 * kMlpWaves, 0);
+            resident = std::max(1, per_cu) * pr.multiProcessorCount;
+        }
         int64_t tiles = (cap + 31) / 32;
-        int grid = (int)std::min<int64_t>((tiles + kMlpWaves - 1) / kMlpWaves, 2048);
+        int grid = (int)std::min<int64_t>((tiles + kMlpWaves - 1) / kMlpWaves, resident);
         hipLaunchKernelGGL(k_mlp_bf16, dim3(grid), dim3(64 * kMlpWaves), 0, s, W, feat, out, d_n, cap);
     } else {
         int grid = (int)std::min<int64_t>((cap + 255) / 256, 2048);

@@ -98,6 +98,41 @@ def test_network_forward_fp32_bf16_against_oracle():
         b.free()
 
 
+def _bf16(a):
+    """Round FP32 values to BF16 (nearest, ties to even), returned as float64."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("n", [1000, 70001])
+def test_bf16_forward_matches_its_rounding_model(n):
+    # the same rounding as the MFMA path (inputs x scale, W1, W2 and the first
+    # hidden layer in BF16; FP32 sums, FP32 second hidden layer and output
+    # layer) evaluated in FP64: only summation order and exp differ, so a
+    # misplaced operand element or a wrong tile shows as an O(1) error
+    w = random_weights(5)
+    rng = np.random.default_rng(6)
+    feat = rng.normal(0, 1.0, (n, 12)).astype(np.float32)
+    Wf = flat(w)
+    F, W, out = DevBuf(feat), DevBuf(Wf), DevBuf(np.zeros((n, 3)))
+    T.mlp_forward(W.ptr, F.ptr, n, out.ptr, bf16=True)
+    y = out.get()
+    sc = np.asarray(w["in_scale"], dtype=np.float32)
+    x = _bf16(feat * sc)
+    z1 = x @ _bf16(w["W1"]).T + np.asarray(w["b1"], dtype=np.float64)
+    h1 = _bf16((z1 / (1.0 + np.exp(-z1))).astype(np.float32))
+    z2 = h1 @ _bf16(w["W2"]).T + np.asarray(w["b2"], dtype=np.float64)
+    h2 = z2 / (1.0 + np.exp(-z2))
+    ref = h2 @ np.asarray(w["W3"], dtype=np.float64).T + np.asarray(w["b3"], dtype=np.float64)
+    scale = np.max(np.abs(ref))
+    err = np.abs(y - ref) / scale
+    assert np.max(err) <= 2e-3, np.max(err)
+    assert np.mean(err) <= 1e-4, np.mean(err)
+    for b in (F, W, out):
+        b.free()
+
+
 def test_training_gradients_match_oracle():
     w = random_weights(5)
     rng = np.random.default_rng(6)
