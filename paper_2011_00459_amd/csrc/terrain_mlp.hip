@@ -48,13 +48,13 @@ __device__ inline float silu_fast(float z) { return z * __builtin_amdgcn_rcpf(1.
 
 // ---------------------------------------------------------------------------
 // BF16 MFMA inference.  Each wave works alone on tiles of 32 contacts (no
-// block barriers): the W1 and W2 operands stay in registers for the whole
-// launch, the input tile is read from global memory straight into the A
-// operand, and one per-wave LDS tile turns each layer's D layout into the
-// next layer's A layout.
+// block barrier after the weights are staged): the block's weights sit in LDS
+// as B operands, the input tile is read from global memory straight into the
+// A operand (the next tile's rows in flight meanwhile), and one per-wave LDS
+// tile turns each layer's D layout into the next layer's A layout.
 //   layer 1: X[32 x 16] (12 inputs padded) . W1^T[16 x 64]: 2 N-tiles x 1 K-step
 //   layer 2: H1[32 x 64] . W2^T[64 x 64]: 2 N-tiles x 4 K-steps
-//   layer 3: 3 outputs per contact on the vector ALU from H2 (FP32 in LDS)
+//   layer 3: H2[32 x 64] . W3^T[64 x 32] (3 of 32 columns used): 4 K-steps
 // Operand layouts of v_mfma_f32_32x32x16_bf16 (A 32x16, B 16x32, D 32x32):
 //   A[i][k] -> lane i + 32 (k / 8), element k % 8
 //   B[k][j] -> lane j + 32 (k / 8), element k % 8
@@ -63,8 +63,7 @@ __device__ inline float silu_fast(float z) { return z * __builtin_amdgcn_rcpf(1.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMlpWaves = 4;
-constexpr int kH1Pitch = kH + 8;   // BF16 transpose tile row (16-byte aligned rows)
-constexpr int kH2Pitch = kH + 1;   // FP32 layer-2 output row (floats)
+constexpr int kHPitch = kH + 8;    // BF16 rows of 64 + 8 (16-byte aligned)
 
 __device__ inline void wave_sync()
 {
@@ -78,37 +77,37 @@ __device__ inline void wave_sync()
 __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_bf16(const float* __restrict__ W, const float* __restrict__ feat,
                                                               float* __restrict__ out, const uint32_t* d_n, int64_t cap)
 {
-    __shared__ float w3[kOut][kH];
-    __shared__ __attribute__((aligned(16))) __bf16 h1s[kMlpWaves][32][kH1Pitch];
-    __shared__ float h2s[kMlpWaves][32][kH2Pitch];
+    // B operands: row j holds the weights into unit j (W1 padded to K = 16,
+    // W3 padded to 32 rows), so lane (j, half) reads 8 consecutive K values
+    __shared__ __attribute__((aligned(16))) __bf16 w1s[kH][16];
+    __shared__ __attribute__((aligned(16))) __bf16 w2s[kH][kHPitch];
+    __shared__ __attribute__((aligned(16))) __bf16 w3s[32][kHPitch];
+    __shared__ __attribute__((aligned(16))) __bf16 hts[kMlpWaves][32][kHPitch];
     const int tid = threadIdx.x;
-    for (int t = tid; t < kOut * kH; t += blockDim.x) w3[t / kH][t % kH] = W[oW3 + t];
-    __syncthreads();  // the only block barrier: w3 is read-only afterwards
+    for (int t = tid; t < kH * 16; t += blockDim.x) {
+        const int j = t / 16, k = t % 16;
+        w1s[j][k] = (__bf16)(k < kIn ? W[oW1 + j * kIn + k] : 0.0f);
+    }
+    for (int t = tid; t < kH * kH; t += blockDim.x) w2s[t / kH][t % kH] = (__bf16)W[oW2 + t];
+    for (int t = tid; t < 32 * kH; t += blockDim.x) {
+        const int j = t / kH, k = t % kH;
+        w3s[j][k] = (__bf16)(j < kOut ? W[oW3 + j * kH + k] : 0.0f);
+    }
+    __syncthreads();  // the only block barrier: the weights are read-only afterwards
 
     const int wave = tid >> 6, lane = tid & 63;
     const int half = lane >> 5, col = lane & 31;
-    // B operands of layers 1 and 2 and this lane's biases and input scales
-    bf16x8 B1[2], B2[2][4];
-    for (int nt = 0; nt < 2; ++nt) {
-        const int j = nt * 32 + col;
-        for (int q = 0; q < 8; ++q) {
-            const int k = half * 8 + q;
-            B1[nt][q] = (__bf16)(k < kIn ? W[oW1 + j * kIn + k] : 0.0f);
-        }
-        for (int ks = 0; ks < 4; ++ks)
-            for (int q = 0; q < 8; ++q) B2[nt][ks][q] = (__bf16)W[oW2 + j * kH + ks * 16 + half * 8 + q];
-    }
     const float bias1[2] = {W[ob1 + col], W[ob1 + 32 + col]};
     const float bias2[2] = {W[ob2 + col], W[ob2 + 32 + col]};
-    const float b3v[kOut] = {W[ob3], W[ob3 + 1], W[ob3 + 2]};
+    const float bias3 = col < kOut ? W[ob3 + col] : 0.0f;
     float scl[8];  // scales of this lane's input columns 8 half .. 8 half + 7
     for (int q = 0; q < 8; ++q) scl[q] = half * 8 + q < kIn ? W[oScale + half * 8 + q] : 0.0f;
 
     const uint64_t n = d_n ? (uint64_t)min((uint64_t)*d_n, (uint64_t)cap) : (uint64_t)cap;
     const uint64_t ntiles = (n + 31) / 32;
     const uint64_t nwaves = (uint64_t)gridDim.x * kMlpWaves;
-    __bf16(*hs)[kH1Pitch] = h1s[wave];
-    float(*h2)[kH2Pitch] = h2s[wave];
+    __bf16(*ht)[kHPitch] = hts[wave];
+    auto brow = [&](const __bf16* row, int k0) { return *reinterpret_cast<const bf16x8*>(row + k0 + half * 8); };
     // the input row of a tile: lane (col, half) holds features 8 half .. 8 half + 7
     // (only 8 .. 11 of the second half are inside the 12)
     auto load_x = [&](uint64_t tile, float4& x0, float4& x1) {
@@ -121,50 +120,54 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_bf16(const float* __rest
             if (half == 0) x1 = f[1];
         }
     };
+    // D tile (+ bias, SiLU) -> BF16 rows of ht, N-tile nt
+    auto store_h = [&](const floatx16& acc, float bias, int nt) {
+        for (int e = 0; e < 16; ++e) {
+            const int i = (e & 3) + 8 * (e >> 2) + 4 * half;
+            ht[i][nt * 32 + col] = (__bf16)silu_fast(acc[e] + bias);
+        }
+    };
     uint64_t tile = (uint64_t)blockIdx.x * kMlpWaves + wave;
     float4 x0, x1;
     load_x(tile, x0, x1);
     for (; tile < ntiles; tile += nwaves) {
-        bf16x8 A1;
-        A1[0] = (__bf16)(x0.x * scl[0]); A1[1] = (__bf16)(x0.y * scl[1]);
-        A1[2] = (__bf16)(x0.z * scl[2]); A1[3] = (__bf16)(x0.w * scl[3]);
-        A1[4] = (__bf16)(x1.x * scl[4]); A1[5] = (__bf16)(x1.y * scl[5]);
-        A1[6] = (__bf16)(x1.z * scl[6]); A1[7] = (__bf16)(x1.w * scl[7]);
+        bf16x8 A;
+        A[0] = (__bf16)(x0.x * scl[0]); A[1] = (__bf16)(x0.y * scl[1]);
+        A[2] = (__bf16)(x0.z * scl[2]); A[3] = (__bf16)(x0.w * scl[3]);
+        A[4] = (__bf16)(x1.x * scl[4]); A[5] = (__bf16)(x1.y * scl[5]);
+        A[6] = (__bf16)(x1.z * scl[6]); A[7] = (__bf16)(x1.w * scl[7]);
         load_x(tile + nwaves, x0, x1);  // the next tile's rows, in flight meanwhile
         // layer 1
-        for (int nt = 0; nt < 2; ++nt) {
-            floatx16 acc = {};
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, B1[nt], acc, 0, 0, 0);
-            for (int e = 0; e < 16; ++e) {
-                const int i = (e & 3) + 8 * (e >> 2) + 4 * half;
-                hs[i][nt * 32 + col] = (__bf16)silu_fast(acc[e] + bias1[nt]);
-            }
-        }
+        floatx16 d0 = {}, d1 = {};
+        d0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, brow(w1s[col], 0), d0, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, brow(w1s[32 + col], 0), d1, 0, 0, 0);
+        store_h(d0, bias1[0], 0);
+        store_h(d1, bias1[1], 1);
         wave_sync();
-        // layer 2
+        // layer 2 (its A operands read before the tile is overwritten)
         bf16x8 A2[4];
-        for (int ks = 0; ks < 4; ++ks) A2[ks] = *reinterpret_cast<const bf16x8*>(&hs[col][ks * 16 + half * 8]);
-        for (int nt = 0; nt < 2; ++nt) {
-            floatx16 acc = {};
-            for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2[ks], B2[nt][ks], acc, 0, 0, 0);
+        for (int ks = 0; ks < 4; ++ks) A2[ks] = brow(ht[col], ks * 16);
+        wave_sync();
+        d0 = {}; d1 = {};
+        for (int ks = 0; ks < 4; ++ks) {
+            d0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2[ks], brow(w2s[col], ks * 16), d0, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2[ks], brow(w2s[32 + col], ks * 16), d1, 0, 0, 0);
+        }
+        store_h(d0, bias2[0], 0);
+        store_h(d1, bias2[1], 1);
+        wave_sync();
+        // layer 3: columns 0..2 of D are the outputs
+        for (int ks = 0; ks < 4; ++ks) A2[ks] = brow(ht[col], ks * 16);
+        floatx16 d3 = {};
+        for (int ks = 0; ks < 4; ++ks)
+            d3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A2[ks], brow(w3s[col], ks * 16), d3, 0, 0, 0);
+        if (col < kOut)
             for (int e = 0; e < 16; ++e) {
                 const int i = (e & 3) + 8 * (e >> 2) + 4 * half;
-                h2[i][nt * 32 + col] = silu_fast(acc[e] + bias2[nt]);
+                const uint64_t c = tile * 32 + i;
+                if (c < n) out[c * kOut + col] = d3[e] + bias3;
             }
-        }
-        wave_sync();
-        // layer 3: lanes 0..31 own one contact each, the two halves split K
-        float y[kOut];
-        for (int o = 0; o < kOut; ++o) {
-            float s = 0.0f;
-            for (int k = half * 32; k < half * 32 + 32; ++k) s += w3[o][k] * h2[col][k];
-            s += __shfl_xor(s, 32, 64);
-            y[o] = s + b3v[o];
-        }
-        const uint64_t c = tile * 32 + col;
-        if (half == 0 && c < n)
-            for (int o = 0; o < kOut; ++o) out[c * kOut + o] = y[o];
-        wave_sync();  // the tiles are rewritten by the next iteration
+        wave_sync();  // the tile is rewritten by the next iteration
     }
 }
 

@@ -107,10 +107,10 @@ def _bf16(a):
 
 @pytest.mark.parametrize("n", [1000, 70001])
 def test_bf16_forward_matches_its_rounding_model(n):
-    # the same rounding as the MFMA path (inputs x scale, W1, W2 and the first
-    # hidden layer in BF16; FP32 sums, FP32 second hidden layer and output
-    # layer) evaluated in FP64: only summation order and exp differ, so a
-    # misplaced operand element or a wrong tile shows as an O(1) error
+    # the same rounding as the MFMA path (inputs x scale, the weight matrices
+    # and both hidden layers in BF16, FP32 sums and biases) evaluated in FP64:
+    # only summation order, exp and the reciprocal differ, so a misplaced
+    # operand element or a wrong tile shows as an O(1) error
     w = random_weights(5)
     rng = np.random.default_rng(6)
     feat = rng.normal(0, 1.0, (n, 12)).astype(np.float32)
@@ -123,8 +123,8 @@ def test_bf16_forward_matches_its_rounding_model(n):
     z1 = x @ _bf16(w["W1"]).T + np.asarray(w["b1"], dtype=np.float64)
     h1 = _bf16((z1 / (1.0 + np.exp(-z1))).astype(np.float32))
     z2 = h1 @ _bf16(w["W2"]).T + np.asarray(w["b2"], dtype=np.float64)
-    h2 = z2 / (1.0 + np.exp(-z2))
-    ref = h2 @ np.asarray(w["W3"], dtype=np.float64).T + np.asarray(w["b3"], dtype=np.float64)
+    h2 = _bf16((z2 / (1.0 + np.exp(-z2))).astype(np.float32))
+    ref = h2 @ _bf16(w["W3"]).T + np.asarray(w["b3"], dtype=np.float64)
     scale = np.max(np.abs(ref))
     err = np.abs(y - ref) / scale
     assert np.max(err) <= 2e-3, np.max(err)
