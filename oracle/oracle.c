@@ -864,8 +864,153 @@ static int64_t find_prev(int64_t nprev, const uint64_t* keys, uint64_t k)
  * them; sums over particles only, with the spheres' own inertia 2/5 m r^2
  * and spin (the inertia formula as printed is read as the standard
  * parallel-axis sum about x_A). */
-int32_t orc_aggregates(int64_t n, const double* r, const double* inv_m, const double* x, const double* v,
-                       const double* w, int32_t nb, const orc_body* bodies, orc_aggregate* agg)
+/* Height and gradient of a heightfield at (x, y): Eq. surface, the grid
+ * heights interpolated linearly in each direction (bilinear), clamped to the
+ * border cells. */
+static double hf_eval(const orc_shape* s, double x, double y, double* hx, double* hy)
+{
+    double inv = 1.0 / s->l0;
+    double fx = (x - s->ox) * inv;
+    double fy = (y - s->oy) * inv;
+    double fi = floor(fx), fj = floor(fy);
+    if (fi < 0.0) fi = 0.0;
+    if (fi > (double)(s->nx - 2)) fi = (double)(s->nx - 2);
+    if (fj < 0.0) fj = 0.0;
+    if (fj > (double)(s->ny - 2)) fj = (double)(s->ny - 2);
+    int i = (int)fi, j = (int)fj;
+    double t = fx - fi, u = fy - fj;
+    double h00 = s->h[j * s->nx + i], h10 = s->h[j * s->nx + i + 1];
+    double h01 = s->h[(j + 1) * s->nx + i], h11 = s->h[(j + 1) * s->nx + i + 1];
+    *hx = ((h10 - h00) * (1.0 - u) + (h11 - h01) * u) * inv;
+    *hy = ((h01 - h00) * (1.0 - t) + (h11 - h10) * t) * inv;
+    return (h00 * (1.0 - t) + h10 * t) * (1.0 - u) + (h01 * (1.0 - t) + h11 * t) * u;
+}
+
+static void normalize3(double* a)
+{
+    double m = sqrt(dot3(a, a));
+    for (int k = 0; k < 3; ++k) a[k] /= m;
+}
+
+/* The active zone of a cutting edge: for each lateral slice, the wedge
+ * between the separation plate through the edge and the failure plane that
+ * rises from the edge at theta(phi, beta) = pi/2 - (phi + beta)/2 against
+ * the terrain surface (Eq. failure_plane), up to where it meets the surface
+ * (plus the heap allowance), between the slice's lateral planes.  beta is the
+ * angle from the surface to the separation plate, both taken in the plane
+ * normal to the edge; the plate's normal is interpolated between the primary
+ * plate and the inner face by the fill ratio. */
+int32_t orc_predict_wedges(const orc_tool* t, const orc_body* bodies, const orc_shape* terrain, orc_wedge* out)
+{
+    if (t->n_wedges < 1 || t->n_wedges > ORC_MAX_WEDGES || !(t->fill >= 0.0 && t->fill <= 1.0)) return -1;
+    const orc_body* B = &bodies[t->body];
+    double R[3][3];
+    quat_matrix(B->quat, R);
+    double E0[3], E1[3], nc[3], ntc[3];
+    for (int k = 0; k < 3; ++k) {
+        E0[k] = B->pos[k] + ((R[k][0] * t->edge0[0] + R[k][1] * t->edge0[1]) + R[k][2] * t->edge0[2]);
+        E1[k] = B->pos[k] + ((R[k][0] * t->edge1[0] + R[k][1] * t->edge1[1]) + R[k][2] * t->edge1[2]);
+        nc[k] = (R[k][0] * t->n_c[0] + R[k][1] * t->n_c[1]) + R[k][2] * t->n_c[2];
+        ntc[k] = (R[k][0] * t->n_tc[0] + R[k][1] * t->n_tc[1]) + R[k][2] * t->n_tc[2];
+    }
+    for (int w = 0; w < t->n_wedges; ++w) out[w].n = 0;
+    if (!terrain) return t->n_wedges;
+    if (t->v_min > 0.0) {
+        /* a deformer resolves its zone only while its edge moves fast enough */
+        double mid[3], arm[3], ve[3];
+        for (int k = 0; k < 3; ++k) { mid[k] = 0.5 * (E0[k] + E1[k]); arm[k] = mid[k] - B->pos[k]; }
+        cross3(B->angvel, arm, ve);
+        for (int k = 0; k < 3; ++k) ve[k] += B->linvel[k];
+        if (!(sqrt(dot3(ve, ve)) > t->v_min)) return t->n_wedges;
+    }
+    double nf[3], L[3], l[3];
+    for (int k = 0; k < 3; ++k) {
+        nf[k] = (1.0 - t->fill) * nc[k] + t->fill * ntc[k];
+        L[k] = E1[k] - E0[k];
+        l[k] = L[k];
+    }
+    normalize3(nf);
+    normalize3(l);
+    const double zh[3] = {0.0, 0.0, 1.0};
+    double u[3], p[3];
+    cross3(zh, l, u);        /* horizontal, normal to the edge */
+    normalize3(u);
+    if (dot3(u, nf) < 0.0) for (int k = 0; k < 3; ++k) u[k] = -u[k];
+    cross3(l, nf, p);        /* the plate's direction away from the edge */
+    normalize3(p);
+    if (p[2] < 0.0) for (int k = 0; k < 3; ++k) p[k] = -p[k];
+    for (int w = 0; w < t->n_wedges; ++w) {
+        double a[3], b[3], m[3];
+        double fa = (double)w / t->n_wedges, fb = (double)(w + 1) / t->n_wedges, fm = (w + 0.5) / t->n_wedges;
+        for (int k = 0; k < 3; ++k) { a[k] = E0[k] + L[k] * fa; b[k] = E0[k] + L[k] * fb; m[k] = E0[k] + L[k] * fm; }
+        double hx, hy;
+        double h0 = hf_eval(terrain, m[0], m[1], &hx, &hy);
+        if (!(m[2] < h0)) continue;  /* the edge is not below the surface */
+        /* surface tangent and its upward normal in the plane normal to the edge */
+        double s[3] = {u[0], u[1], u[2] + (hx * u[0] + hy * u[1])};
+        double sl = dot3(s, l);
+        for (int k = 0; k < 3; ++k) s[k] -= sl * l[k];
+        normalize3(s);
+        double ns[3];
+        cross3(l, s, ns);
+        if (ns[2] < 0.0) for (int k = 0; k < 3; ++k) ns[k] = -ns[k];
+        double beta = atan2(dot3(p, ns), dot3(p, s));
+        double theta = 0.5 * PI - 0.5 * (t->phi + beta);
+        if (!(theta > 0.0 && theta < 0.5 * PI)) continue;
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = cos(theta) * s[k] + sin(theta) * ns[k];
+        /* where the failure line from the edge meets the surface: bracket by
+         * doubling from one grid spacing, then 60 bisections */
+        double lo = 0.0, hi = terrain->l0;
+        int found = 0;
+        for (int it = 0; it < 40; ++it) {
+            double q[3] = {m[0] + hi * d[0], m[1] + hi * d[1], m[2] + hi * d[2]};
+            if (q[2] - hf_eval(terrain, q[0], q[1], &hx, &hy) >= 0.0) { found = 1; break; }
+            lo = hi;
+            hi *= 2.0;
+        }
+        if (!found) continue;
+        for (int it = 0; it < 60; ++it) {
+            double mid = 0.5 * (lo + hi);
+            double q[3] = {m[0] + mid * d[0], m[1] + mid * d[1], m[2] + mid * d[2]};
+            if (q[2] - hf_eval(terrain, q[0], q[1], &hx, &hy) >= 0.0) hi = mid;
+            else lo = mid;
+        }
+        double ztop = (m[2] + hi * d[2]) + t->heap;
+        double c[3];
+        cross3(l, d, c);
+        normalize3(c);
+        if (dot3(c, p) > 0.0) for (int k = 0; k < 3; ++k) c[k] = -c[k];
+        orc_wedge* W = &out[w];
+        for (int k = 0; k < 3; ++k) {
+            W->planes[0][k] = -nf[k];   /* in front of the separation plate */
+            W->planes[1][k] = c[k];     /* above the failure plane */
+            W->planes[2][k] = zh[k];    /* below the top */
+            W->planes[3][k] = -l[k];    /* between the slice's lateral planes */
+            W->planes[4][k] = l[k];
+        }
+        W->planes[0][3] = -dot3(nf, m);
+        W->planes[1][3] = dot3(c, m);
+        W->planes[2][3] = ztop;
+        W->planes[3][3] = -dot3(l, a);
+        W->planes[4][3] = dot3(l, b);
+        W->n = 5;
+    }
+    return t->n_wedges;
+}
+
+static int in_planes(const double (*pl)[4], int np, const double* x)
+{
+    for (int p = 0; p < np; ++p)
+        if (dot3(pl[p], x) - pl[p][3] > 0.0) return 0;
+    return 1;
+}
+
+/* Aggregates with, per body, either its half-space zone or the union of its
+ * tool's wedges (wedges[b] non-NULL, nw[b] of them). */
+static int32_t aggregates_impl(int64_t n, const double* r, const double* inv_m, const double* x, const double* v,
+                               const double* w, int32_t nb, const orc_body* bodies, orc_wedge* const* wedges,
+                               const int32_t* nw, orc_aggregate* agg)
 {
     int32_t na = 0;
     int32_t* zone_of = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
@@ -884,15 +1029,18 @@ int32_t orc_aggregates(int64_t n, const double* r, const double* inv_m, const do
     for (int64_t i = 0; i < n; ++i) {
         zone_of[i] = -1;
         for (int32_t b = 0; b < nb && zone_of[i] < 0; ++b) {
-            if (bodies[b].nplanes <= 0) continue;
-            int in = 1;
-            for (int p = 0; p < bodies[b].nplanes; ++p)
-                if (dot3(wp[b][p], &x[3 * i]) - wp[b][p][3] > 0.0) { in = 0; break; }
+            int in = 0;
+            if (wedges && wedges[b]) {
+                for (int32_t k = 0; k < nw[b] && !in; ++k)
+                    in = wedges[b][k].n > 0 && in_planes(wedges[b][k].planes, wedges[b][k].n, &x[3 * i]);
+            } else if (bodies[b].nplanes > 0) {
+                in = in_planes(wp[b], bodies[b].nplanes, &x[3 * i]);
+            }
             if (in) zone_of[i] = b;
         }
     }
     for (int32_t b = 0; b < nb; ++b) {
-        if (bodies[b].nplanes <= 0) continue;
+        if (!(wedges && wedges[b]) && bodies[b].nplanes <= 0) continue;
         orc_aggregate* A = &agg[na++];
         memset(A, 0, sizeof(*A));
         A->zone = b;
@@ -940,6 +1088,34 @@ int32_t orc_aggregates(int64_t n, const double* r, const double* inv_m, const do
     }
     free(wp);
     free(zone_of);
+    return na;
+}
+
+int32_t orc_aggregates(int64_t n, const double* r, const double* inv_m, const double* x, const double* v,
+                       const double* w, int32_t nb, const orc_body* bodies, orc_aggregate* agg)
+{
+    return aggregates_impl(n, r, inv_m, x, v, w, nb, bodies, NULL, NULL, agg);
+}
+
+int32_t orc_aggregates_tools(int64_t n, const double* r, const double* inv_m, const double* x, const double* v,
+                             const double* w, int32_t nb, const orc_body* bodies, int32_t ntools,
+                             const orc_tool* tools, const orc_shape* terrain, orc_aggregate* agg)
+{
+    orc_wedge** wedges = (orc_wedge**)calloc((size_t)(nb > 0 ? nb : 1), sizeof(orc_wedge*));
+    int32_t* nw = (int32_t*)calloc((size_t)(nb > 0 ? nb : 1), sizeof(int32_t));
+    orc_wedge* pool = (orc_wedge*)calloc((size_t)(ntools > 0 ? ntools : 1) * ORC_MAX_WEDGES, sizeof(orc_wedge));
+    int32_t na = -1;
+    for (int32_t k = 0; k < ntools; ++k) {
+        const orc_tool* T = &tools[k];
+        if (T->body < 0 || T->body >= nb || wedges[T->body]) goto done;  /* one tool per body */
+        orc_wedge* W = pool + (size_t)k * ORC_MAX_WEDGES;
+        if (orc_predict_wedges(T, bodies, terrain, W) < 0) goto done;
+        wedges[T->body] = W;
+        nw[T->body] = T->n_wedges;
+    }
+    na = aggregates_impl(n, r, inv_m, x, v, w, nb, bodies, wedges, nw, agg);
+done:
+    free(pool); free(nw); free(wedges);
     return na;
 }
 
@@ -1235,7 +1411,16 @@ int64_t orc_step(const orc_params* P,
     }
 
     /* 10. aggregate bodies of the active zones (Eqs. aggregate_mass..rot_vel) */
-    if (agg && n_agg) *n_agg = orc_aggregates(n, r, M.im, x, v, w, nb, bodies, agg);
+    if (agg && n_agg) {
+        if (P->ntools > 0) {
+            const orc_shape* terrain = NULL;
+            for (int32_t k = 0; k < ns && !terrain; ++k)
+                if (shapes[k].type == ORC_HFIELD) terrain = &shapes[k];
+            *n_agg = orc_aggregates_tools(n, r, M.im, x, v, w, nb, bodies, P->ntools, P->tools, terrain, agg);
+        } else {
+            *n_agg = orc_aggregates(n, r, M.im, x, v, w, nb, bodies, agg);
+        }
+    }
 
     /* 11. outputs and the cache of this step */
     for (int64_t c = 0; c < nc; ++c) {

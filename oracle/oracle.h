@@ -61,6 +61,8 @@ typedef struct orc_params {
     int32_t warm;        /* ORC_COLD / ORC_PREV / ORC_LEARNED */
     int32_t detect;      /* ORC_BRUTE or ORC_CELLS */
     orc_material m;
+    int32_t ntools;      /* tools whose predicted wedges replace their bodies' zones */
+    const struct orc_tool* tools;
 } orc_params;
 
 /* Kinematic body: pose, velocities and an optional active zone given as up to
@@ -90,6 +92,38 @@ typedef struct orc_shape {
     double ox, oy, l0;
     const float* h;
 } orc_shape;
+
+/* Digging tool or soil deformer of a body, for the active-zone predictor
+ * (Eq. failure_plane with the lateral wedges, the fill-dependent secondary
+ * separation plate and the deformers' speed gate).  Geometry in the body
+ * frame.  The terrain surface is the env's first heightfield shape. */
+typedef struct orc_tool {
+    int32_t body;          /* index of the tool's body */
+    int32_t n_wedges;      /* lateral wedges along the cutting edge, 1..16 */
+    double edge0[3];       /* cutting edge end points */
+    double edge1[3];
+    double n_c[3];         /* normal of the primary separation plate, towards the zone */
+    double n_tc[3];        /* normal of the face from cutting edge to top edge (= n_c for a blade) */
+    double fill;           /* fill ratio of the inner shape, [0, 1] */
+    double phi;            /* soil internal friction angle [rad] */
+    double heap;           /* zone height above the point where the failure plane meets the surface [m] */
+    double v_min;          /* deformer: a zone only while the edge speed exceeds v_min (<= 0: always) */
+} orc_tool;
+
+#define ORC_MAX_WEDGES 16
+
+/* One wedge of a predicted zone: n half-spaces (world frame, inside iff
+ * planes[k][0..2] . x <= planes[k][3]); n = 0 for an empty wedge. */
+typedef struct orc_wedge {
+    int32_t n;
+    int32_t pad;
+    double planes[5][4];
+} orc_wedge;
+
+/* Wedges of one tool at the body's current pose, on the heightfield
+ * `terrain` (NULL: every wedge empty).  Writes t->n_wedges wedges; returns
+ * their count, or -1 for a bad tool. */
+int32_t orc_predict_wedges(const orc_tool* t, const orc_body* bodies, const orc_shape* terrain, orc_wedge* out);
 
 /* MLP 12 -> 64 -> 64 -> 3 with SiLU, weights row-major W[out][in]. */
 typedef struct orc_mlp {
@@ -159,6 +193,13 @@ int64_t orc_step(const orc_params* P,
  * particle.  Returns the number written to agg (one per body with a zone). */
 int32_t orc_aggregates(int64_t n, const double* r, const double* inv_m, const double* x, const double* v,
                        const double* w, int32_t nb, const orc_body* bodies, orc_aggregate* agg);
+
+/* As orc_aggregates, with the bodies of the tools (terrain: the first
+ * heightfield shape or NULL) taking the union of their predicted wedges as
+ * their zone. */
+int32_t orc_aggregates_tools(int64_t n, const double* r, const double* inv_m, const double* x, const double* v,
+                             const double* w, int32_t nb, const orc_body* bodies, int32_t ntools,
+                             const struct orc_tool* tools, const orc_shape* terrain, orc_aggregate* agg);
 
 /* Learned-start features (12 per canonical contact), the contact frame
  * (t1, t2: 6 per contact) and the impulse scale m_eff g dt (1 per contact)

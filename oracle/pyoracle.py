@@ -40,10 +40,42 @@ class Material(C.Structure):
                  "gamma_t", "kappa_c", "kappa_min", "v_imp")]
 
 
+class Tool(C.Structure):
+    _fields_ = [("body", C.c_int32), ("n_wedges", C.c_int32), ("edge0", C.c_double * 3), ("edge1", C.c_double * 3),
+                ("n_c", C.c_double * 3), ("n_tc", C.c_double * 3), ("fill", C.c_double), ("phi", C.c_double),
+                ("heap", C.c_double), ("v_min", C.c_double)]
+
+
+class Wedge(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pad", C.c_int32), ("planes", (C.c_double * 4) * 5)]
+
+
+MAX_WEDGES = 16
+
+
 class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("g", C.c_double * 3), ("grid_lo", C.c_double * 3),
                 ("grid_hi", C.c_double * 3), ("r_ref", C.c_double), ("max_sweeps", C.c_int32), ("tol", C.c_double),
-                ("warm", C.c_int32), ("detect", C.c_int32), ("m", Material)]
+                ("warm", C.c_int32), ("detect", C.c_int32), ("m", Material), ("ntools", C.c_int32),
+                ("tools", C.POINTER(Tool))]
+
+
+def tool_struct(t: dict) -> Tool:
+    """A tool dict (body index, n_wedges, edge0, edge1, n_c, n_tc, fill, phi,
+    heap, v_min; geometry in the body frame) as the oracle's struct."""
+    T = Tool()
+    T.body = int(t["body"])
+    T.n_wedges = int(t.get("n_wedges", 1))
+    for k in range(3):
+        T.edge0[k] = t["edge0"][k]
+        T.edge1[k] = t["edge1"][k]
+        T.n_c[k] = t["n_c"][k]
+        T.n_tc[k] = t.get("n_tc", t["n_c"])[k]
+    T.fill = t.get("fill", 0.0)
+    T.phi = t["phi"]
+    T.heap = t.get("heap", 0.0)
+    T.v_min = t.get("v_min", 0.0)
+    return T
 
 
 class Body(C.Structure):
@@ -114,6 +146,8 @@ def lib():
         L.orc_mlp_forward.argtypes = [C.POINTER(Mlp), C.c_int64, dp, dp]
         L.orc_mlp_loss_grad.restype = C.c_double
         L.orc_mlp_loss_grad.argtypes = [C.POINTER(Mlp), C.c_int64, dp, dp, dp]
+        L.orc_predict_wedges.restype = C.c_int32
+        L.orc_predict_wedges.argtypes = [C.POINTER(Tool), C.POINTER(Body), C.POINTER(Shape), C.POINTER(Wedge)]
         L.orc_failure_angle.restype = C.c_double
         L.orc_failure_angle.argtypes = [C.c_double, C.c_double]
         _lib = L
@@ -148,6 +182,12 @@ def make_params(spec: dict, detect: int = CELLS) -> Params:
     mat.update(spec.get("material", {}))
     for k, v in mat.items():
         setattr(P.m, k, v)
+    tools = spec.get("tools", [])
+    if tools:
+        arr = (Tool * len(tools))(*[tool_struct(t) for t in tools])
+        P.ntools = len(tools)
+        P.tools = C.cast(arr, C.POINTER(Tool))
+        P._tools_keep = arr  # the array lives as long as the params
     return P
 
 
@@ -287,6 +327,8 @@ class OracleScene:
                         agg, C.byref(nagg), _dp(resid))
         if nc < 0:
             raise RuntimeError(f"orc_step failed ({nc})")
+        if nagg.value < 0:
+            raise RuntimeError("orc_step: a tool was rejected")
         self.prev_keys = keys[:nc].copy()
         self.prev_lam = lam[:nc].copy()
         self.prev_lr = lr[:nc].copy()
@@ -329,6 +371,35 @@ class OracleScene:
                                       _dp(self.r), rho_p, _dp(x), _dp(v), _dp(w),
                                       self.bb.nb, self.bb.bodies, self.bb.ns, self.bb.shapes,
                                       len(lam), _dp(lam))
+
+
+def predict_wedges(tool: dict, bodies: list):
+    """Wedges of a tool at its body's pose on the first heightfield of
+    `bodies`: a list (one per wedge) of (k x 4) plane arrays, k = 0 for an
+    empty wedge (world frame, inside iff n . x <= d for every row)."""
+    bb = _Bodies(bodies)
+    terrain = None
+    for k in range(bb.ns):
+        if bb.shapes[k].type == _SHAPE_CODES["hfield"]:
+            terrain = C.pointer(bb.shapes[k])
+            break
+    T = tool_struct(tool)
+    out = (Wedge * MAX_WEDGES)()
+    nw = lib().orc_predict_wedges(C.byref(T), bb.bodies, terrain if terrain is not None else C.POINTER(Shape)(), out)
+    if nw < 0:
+        raise ValueError("bad tool")
+    return [np.array([[out[w].planes[p][q] for q in range(4)] for p in range(out[w].n)]).reshape(-1, 4)
+            for w in range(nw)]
+
+
+def inside_wedges(wedges, x):
+    """Membership of points in the union of wedges."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    ok = np.zeros(len(x), dtype=bool)
+    for W in wedges:
+        if len(W):
+            ok |= np.all(x @ W[:, :3].T - W[:, 3] <= 0.0, axis=1)
+    return ok
 
 
 def aggregates(x, v, w, r, mass, bodies: list):
