@@ -141,6 +141,31 @@ typedef struct tr_body_desc {
     double planes[8][4];
 } tr_body_desc;
 
+/* Digging tool or soil deformer of a kinematic body: its active zone is
+ * predicted every step (after the pose update) from the env's terrain
+ * heightfield (its first TR_HEIGHTFIELD shape), replacing the body's
+ * half-space zone.  For each of n_wedges lateral slices of the cutting edge
+ * the zone is the wedge between the separation plate through the edge and
+ * the failure plane rising at theta(phi, beta) = pi/2 - (phi + beta)/2
+ * against the terrain surface (Eq. failure_plane; beta from the surface
+ * tangent to the plate, in the plane normal to the edge), up to where that
+ * plane meets the surface plus `heap`, between the slice's lateral planes.
+ * The plate normal is normalize((1 - fill) n_c + fill n_tc) (the secondary
+ * separation plate of a partly filled bucket).  Geometry in the body frame. */
+#define TR_MAX_WEDGES 16
+typedef struct tr_tool_desc {
+    int32_t n_wedges;        /* 1 .. TR_MAX_WEDGES */
+    int32_t pad;
+    double edge0[3];         /* cutting edge end points */
+    double edge1[3];
+    double n_c[3];           /* normal of the primary separation plate, towards the zone */
+    double n_tc[3];          /* normal of the face from cutting edge to top edge (= n_c: a blade) */
+    double fill;             /* fill ratio of the inner shape, [0, 1] */
+    double phi;              /* soil internal friction angle [rad], (0, pi/2) */
+    double heap;             /* zone height above where the failure plane meets the surface [m], >= 0 */
+    double v_min;            /* a deformer: a zone only while the edge speed exceeds v_min; <= 0: always */
+} tr_tool_desc;
+
 typedef struct tr_step_stats {
     int64_t contacts;        /* all contacts of the env (pairs + boundary) */
     int64_t pair_contacts;
@@ -190,6 +215,23 @@ int add_particles(tr_scene* s, int32_t env, int64_t n, const double* pos, const 
  * Eq. eqmotb's boundary terms) with b[0..n-1].  Shapes and heights are
  * copied. */
 int set_kinematic_bodies(tr_scene* s, int32_t env, int32_t n, const tr_body_desc* b);
+
+/* Attaches the active-zone predictor tool *t to the body with id body_id of
+ * env (replacing a previous tool of that body; NULL removes it).  The tool
+ * stays with the body id across set_kinematic_bodies.  TR_E_INVAL for an
+ * unknown env or body, n_wedges outside 1..TR_MAX_WEDGES, fill outside
+ * [0, 1], phi outside (0, pi/2), a negative heap, zero-length edge or zero
+ * normals; TR_E_CAPACITY when the env would have more than 4 zones. */
+int set_tool(tr_scene* s, int32_t env, int32_t body_id, const tr_tool_desc* t);
+
+/* The wedges the last step predicted for the tool of body body_id of env:
+ * counts[w] half-spaces (0: an empty wedge, e.g. the edge above the surface
+ * or a slow deformer) in planes[w*20 .. w*20 + 4 counts[w]) as (n, d), world
+ * frame, inside iff n . x <= d.  *n_wedges receives the tool's wedge count;
+ * cap is the room in counts (and planes / 20).  TR_E_STATE before the
+ * first step after a change; TR_E_INVAL when the body has no tool. */
+int get_zone_wedges(tr_scene* s, int32_t env, int32_t body_id, int32_t cap, double* planes, int32_t* counts,
+                    int32_t* n_wedges);
 
 /* Advances every env by n_steps steps.  Asynchronous on the scene's stream
  * when stats is NULL; otherwise waits and writes one tr_step_stats per env

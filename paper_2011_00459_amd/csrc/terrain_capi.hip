@@ -26,6 +26,7 @@ struct EnvHost {
     std::vector<tr_body_desc> bodies;             // shapes pointer unused (see shapes)
     std::vector<std::vector<tr_shape_desc>> shapes;
     std::vector<std::vector<std::vector<float>>> heights;
+    std::vector<std::pair<int32_t, tr_tool_desc>> tools;  // zone predictor tools by body id
 };
 
 }  // namespace
@@ -47,7 +48,8 @@ struct tr_scene {
     int64_t cells_alloc = 0;
     int64_t zone_chunk_alloc = 0;
     int64_t hf_alloc = 0;
-    int bodies_alloc = 0, shapes_alloc = 0, zones_alloc = 0;
+    int bodies_alloc = 0, shapes_alloc = 0, zones_alloc = 0, tools_alloc = 0;
+    std::vector<ToolDev> tool_host;  // last uploaded tool table
     std::vector<BodyDev> body_host;   // last uploaded body table (poses refreshed on download)
     std::vector<EnvDev> env_host;
     std::vector<std::vector<int>> zone_slots;  // per env: global zone index of each zone body
@@ -296,6 +298,7 @@ int rebuild_tables(tr_scene* s)
     std::vector<ShapeDev> sd;
     std::vector<float> pool;
     std::vector<int4> chunks;
+    std::vector<ToolDev> td;
     int64_t NC = 0;
     int64_t NCOL = 0;
     int n_zones = 0;
@@ -358,7 +361,25 @@ int rebuild_tables(tr_scene* s)
             X.nplanes = B.n_halfspaces;
             for (int k = 0; k < B.n_halfspaces; ++k)
                 for (int j = 0; j < 4; ++j) X.planes[k][j] = B.planes[k][j];
-            if (B.n_halfspaces > 0) {
+            X.tool = -1;
+            for (const auto& tl : H.tools)
+                if (tl.first == B.id) {
+                    const tr_tool_desc& T = tl.second;
+                    ToolDev Y;
+                    memset(&Y, 0, sizeof(Y));
+                    Y.body = gi;
+                    Y.env = e;
+                    Y.n_wedges = T.n_wedges;
+                    Y.terrain = -1;  // set once the env's shapes are known
+                    for (int k = 0; k < 3; ++k) {
+                        Y.edge0[k] = T.edge0[k]; Y.edge1[k] = T.edge1[k];
+                        Y.n_c[k] = T.n_c[k]; Y.n_tc[k] = T.n_tc[k];
+                    }
+                    Y.fill = T.fill; Y.phi = T.phi; Y.heap = T.heap; Y.v_min = T.v_min;
+                    X.tool = (int)td.size();
+                    td.push_back(Y);
+                }
+            if (B.n_halfspaces > 0 || X.tool >= 0) {
                 if (D.zone_count >= kMaxZonesPerEnv) return fail(s, TR_E_CAPACITY, "more than 4 zones in an env");
                 D.zone_body[D.zone_count] = gi;
                 D.zone_slot[D.zone_count] = n_zones;
@@ -390,6 +411,12 @@ int rebuild_tables(tr_scene* s)
         }
         D.body_end = (int)bd.size();
         D.shape_end = (int)sd.size();
+        // the terrain of the env's tools: its first heightfield
+        int terrain = -1;
+        for (int k = D.shape_begin; k < D.shape_end && terrain < 0; ++k)
+            if (sd[k].type == TR_HEIGHTFIELD) terrain = k;
+        for (ToolDev& Y : td)
+            if (Y.env == e) Y.terrain = terrain;
         for (int64_t b0 = slot; b0 < slot + H.n; b0 += kZoneChunk) {
             int64_t b1 = std::min<int64_t>(b0 + kZoneChunk, slot + H.n);
             chunks.push_back(make_int4(e, (int)b0, (int)b1, (int)(chunks.size() * kMaxZonesPerEnv)));
@@ -432,6 +459,13 @@ int rebuild_tables(tr_scene* s)
             return fail(s, TR_E_NOMEM, "zone chunks");
         s->zone_chunk_alloc = nch;
     }
+    if ((int)td.size() > s->tools_alloc) {
+        dfree(s, s->b.tools); dfree(s, s->b.wedges);
+        int nt = std::max<int>((int)td.size(), 1);
+        if (!alloc_n(s, s->b.tools, nt) || !alloc_n(s, s->b.wedges, (int64_t)nt * TR_MAX_WEDGES))
+            return fail(s, TR_E_NOMEM, "tool tables");
+        s->tools_alloc = nt;
+    }
     if ((int64_t)pool.size() > s->hf_alloc) {
         dfree(s, s->b.hf_pool);
         if (!alloc_n(s, s->b.hf_pool, (int64_t)pool.size())) return fail(s, TR_E_NOMEM, "heightfields");
@@ -441,10 +475,13 @@ int rebuild_tables(tr_scene* s)
     if (!bd.empty()) HIP_CHECK(s, hipMemcpyAsync(s->b.bodies, bd.data(), sizeof(BodyDev) * bd.size(), hipMemcpyHostToDevice, st));
     if (!sd.empty()) HIP_CHECK(s, hipMemcpyAsync(s->b.shapes, sd.data(), sizeof(ShapeDev) * sd.size(), hipMemcpyHostToDevice, st));
     if (!pool.empty()) HIP_CHECK(s, hipMemcpyAsync(s->b.hf_pool, pool.data(), sizeof(float) * pool.size(), hipMemcpyHostToDevice, st));
+    if (!td.empty()) HIP_CHECK(s, hipMemcpyAsync(s->b.tools, td.data(), sizeof(ToolDev) * td.size(), hipMemcpyHostToDevice, st));
     if (!chunks.empty()) HIP_CHECK(s, hipMemcpyAsync(s->b.zone_chunks, chunks.data(), sizeof(int4) * chunks.size(), hipMemcpyHostToDevice, st));
     HIP_CHECK(s, hipStreamSynchronize(st));  // host vectors die here
     s->body_host = bd;
     s->env_host = ed;
+    s->tool_host = td;
+    s->p.n_tools = (int)td.size();
     s->z.NC = NC;
     s->z.NCOL = NCOL;
     s->z.n_zone_chunks = (int)chunks.size();
@@ -915,6 +952,74 @@ int get_contact_forces(tr_scene* s, int32_t env, int32_t body_id, double force[3
     HIP_CHECK(s, hipStreamSynchronize(s->stream));
     HIP_CHECK(s, hipMemcpy(ft, s->b.body_ft + 6 * gi, sizeof(ft), hipMemcpyDeviceToHost));
     for (int k = 0; k < 3; ++k) { force[k] = ft[k]; torque[k] = ft[3 + k]; }
+    return TR_OK;
+}
+
+int set_tool(tr_scene* s, int32_t env, int32_t body_id, const tr_tool_desc* t)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "set_tool: env");
+    EnvHost& H = s->envs[env];
+    bool known = false;
+    for (const tr_body_desc& B : H.bodies) known |= B.id == body_id;
+    if (!known) return fail(s, TR_E_INVAL, "set_tool: unknown body");
+    auto it = std::find_if(H.tools.begin(), H.tools.end(), [&](const std::pair<int32_t, tr_tool_desc>& q) {
+        return q.first == body_id;
+    });
+    if (!t) {
+        if (it != H.tools.end()) H.tools.erase(it);
+        s->tables_dirty = true;
+        return TR_OK;
+    }
+    auto norm = [](const double* a) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); };
+    double de[3] = {t->edge1[0] - t->edge0[0], t->edge1[1] - t->edge0[1], t->edge1[2] - t->edge0[2]};
+    double fin[18] = {t->edge0[0], t->edge0[1], t->edge0[2], t->edge1[0], t->edge1[1], t->edge1[2],
+                      t->n_c[0], t->n_c[1], t->n_c[2], t->n_tc[0], t->n_tc[1], t->n_tc[2],
+                      t->fill, t->phi, t->heap, t->v_min, 0.0, 0.0};
+    if (!finite3(fin, 16)) return fail(s, TR_E_NONFINITE, "set_tool: non-finite value");
+    if (t->n_wedges < 1 || t->n_wedges > TR_MAX_WEDGES || !(t->fill >= 0.0 && t->fill <= 1.0) ||
+        !(t->phi > 0.0 && t->phi < 0.5 * M_PI) || !(t->heap >= 0.0) || !(norm(de) > 0.0) || !(norm(t->n_c) > 0.0) ||
+        !(norm(t->n_tc) > 0.0))
+        return fail(s, TR_E_INVAL, "set_tool: bad tool");
+    int zones = 0;
+    for (const tr_body_desc& B : H.bodies) {
+        bool has_tool = B.id == body_id;
+        for (const auto& q : H.tools) has_tool |= q.first == B.id;
+        zones += B.n_halfspaces > 0 || has_tool;
+    }
+    if (zones > kMaxZonesPerEnv) return fail(s, TR_E_CAPACITY, "set_tool: more than 4 zones in the env");
+    if (it != H.tools.end()) it->second = *t;
+    else H.tools.emplace_back(body_id, *t);
+    s->tables_dirty = true;
+    return TR_OK;
+}
+
+int get_zone_wedges(tr_scene* s, int32_t env, int32_t body_id, int32_t cap, double* planes, int32_t* counts,
+                    int32_t* n_wedges)
+{
+    if (!s || !n_wedges || cap < 0 || (cap > 0 && (!planes || !counts))) return TR_E_INVAL;
+    s->err.clear();
+    *n_wedges = 0;
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "get_zone_wedges: env");
+    if (s->tables_dirty || !s->stepped) return fail(s, TR_E_STATE, "get_zone_wedges: no step since the tools changed");
+    int ti = -1;
+    for (size_t i = 0; i < s->tool_host.size(); ++i) {
+        const BodyDev& B = s->body_host[s->tool_host[i].body];
+        if (B.env == env && B.user_id == body_id) ti = (int)i;
+    }
+    if (ti < 0) return fail(s, TR_E_INVAL, "get_zone_wedges: the body has no tool");
+    const int nw = s->tool_host[ti].n_wedges;
+    *n_wedges = nw;
+    std::vector<WedgeDev> w(nw);
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    HIP_CHECK(s, hipMemcpy(w.data(), s->b.wedges + (size_t)ti * TR_MAX_WEDGES, sizeof(WedgeDev) * nw,
+                           hipMemcpyDeviceToHost));
+    for (int k = 0; k < nw && k < cap; ++k) {
+        counts[k] = w[k].n;
+        for (int p = 0; p < 5; ++p)
+            for (int q = 0; q < 4; ++q) planes[k * 20 + p * 4 + q] = p < w[k].n ? w[k].planes[p][q] : 0.0;
+    }
     return TR_OK;
 }
 

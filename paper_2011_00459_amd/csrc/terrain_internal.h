@@ -77,7 +77,24 @@ struct BodyDev {
     int env;
     int nplanes;
     int user_id;
+    int tool;             // index of its zone predictor tool, or -1
+};
+
+// zone predictor tool (the tr_tool_desc of a body), global body and terrain indices
+struct ToolDev {
+    int body;
+    int env;
+    int n_wedges;
+    int terrain;          // global shape index of the env's first heightfield, or -1
+    double edge0[3], edge1[3], n_c[3], n_tc[3];
+    double fill, phi, heap, v_min;
+};
+
+// one predicted wedge: n half-spaces, world frame (0: empty)
+struct WedgeDev {
+    int n;
     int pad;
+    double planes[5][4];
 };
 
 struct ShapeDev {
@@ -126,6 +143,8 @@ struct StepParams {
     float v_imp;        // impact threshold (<= 0: no impact stage)
     int n_units;        // PGS solve units (entries of ustats)
     float restitution;  // Newton restitution of the impact stage
+    int n_tools;        // zone predictor tools (all envs)
+    int pad_tools;
 };
 
 // per PGS solve unit: an XCD group of envs (grouped mode) or one env
@@ -200,6 +219,8 @@ struct DevBuffers {
     BodyDev* bodies;
     ShapeDev* shapes;
     float* hf_pool;
+    ToolDev* tools;       // [n_tools]
+    WedgeDev* wedges;     // [n_tools][TR_MAX_WEDGES]
     Counters* cnt;
     EnvStats* env_stats;
     UnitStats* ustats;    // [n_units]

@@ -2197,6 +2197,168 @@ __global__ void k_bodies_end(DevBuffers b, StepParams p)
 }
 
 // zone moments of one chunk of an env's particles (sorted slots), per zone
+// Zone membership of a world point: the union of the body's predicted
+// wedges when it has a tool, else its half-spaces (end-of-step pose).
+__device__ inline bool in_body_zone(const DevBuffers& b, const BodyDev& B, const double* x)
+{
+    if (B.tool >= 0) {
+        const ToolDev& T = b.tools[B.tool];
+        for (int w = 0; w < T.n_wedges; ++w) {
+            const WedgeDev& W = b.wedges[(size_t)B.tool * TR_MAX_WEDGES + w];
+            bool in = W.n > 0;
+            for (int k = 0; k < W.n && in; ++k)
+                if (W.planes[k][0] * x[0] + W.planes[k][1] * x[1] + W.planes[k][2] * x[2] - W.planes[k][3] > 0.0)
+                    in = false;
+            if (in) return true;
+        }
+        return false;
+    }
+    bool in = B.nplanes > 0;
+    for (int k = 0; k < B.nplanes && in; ++k)
+        if (B.wplanes[k][0] * x[0] + B.wplanes[k][1] * x[1] + B.wplanes[k][2] * x[2] - B.wplanes[k][3] > 0.0)
+            in = false;
+    return in;
+}
+
+// height and gradient of a heightfield shape (Eq. surface: bilinear between
+// the grid heights, clamped to the border cells)
+__device__ inline double hf_height(const ShapeDev& S, const float* hf, double x, double y, double& hx, double& hy)
+{
+#pragma clang fp contract(off)
+    double fx = (x - S.ox) * S.inv_l0;
+    double fy = (y - S.oy) * S.inv_l0;
+    double fi = floor(fx), fj = floor(fy);
+    if (fi < 0.0) fi = 0.0;
+    if (fi > (double)(S.nx - 2)) fi = (double)(S.nx - 2);
+    if (fj < 0.0) fj = 0.0;
+    if (fj > (double)(S.ny - 2)) fj = (double)(S.ny - 2);
+    int i = (int)fi, j = (int)fj;
+    double t = fx - fi, u = fy - fj;
+    const float* h = hf + S.hf_off;
+    double h00 = h[j * S.nx + i], h10 = h[j * S.nx + i + 1];
+    double h01 = h[(j + 1) * S.nx + i], h11 = h[(j + 1) * S.nx + i + 1];
+    hx = ((h10 - h00) * (1.0 - u) + (h11 - h01) * u) * S.inv_l0;
+    hy = ((h01 - h00) * (1.0 - t) + (h11 - h10) * t) * S.inv_l0;
+    return (h00 * (1.0 - t) + h10 * t) * (1.0 - u) + (h01 * (1.0 - t) + h11 * t) * u;
+}
+
+__device__ inline double dot3d(const double* a, const double* c) { return (a[0] * c[0] + a[1] * c[1]) + a[2] * c[2]; }
+__device__ inline void cross3d(const double* a, const double* c, double* o)
+{
+#pragma clang fp contract(off)
+    o[0] = a[1] * c[2] - a[2] * c[1];
+    o[1] = a[2] * c[0] - a[0] * c[2];
+    o[2] = a[0] * c[1] - a[1] * c[0];
+}
+__device__ inline void unit3d(double* a)
+{
+    double m = sqrt(dot3d(a, a));
+    a[0] /= m; a[1] /= m; a[2] /= m;
+}
+
+// Active-zone predictor (Eq. failure_plane): one thread per (tool, lateral
+// wedge), at the end-of-step pose.  The wedge lies in front of the separation
+// plate through the edge, above the failure plane rising at
+// theta = pi/2 - (phi + beta)/2 against the terrain surface, below where that
+// plane meets the surface (+ heap), between the slice's lateral planes.
+__global__ void k_predict_wedges(DevBuffers b, StepParams p)
+{
+#pragma clang fp contract(off)
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p.n_tools * TR_MAX_WEDGES) return;
+    const int ti = t / TR_MAX_WEDGES, w = t % TR_MAX_WEDGES;
+    const ToolDev& T = b.tools[ti];
+    if (w >= T.n_wedges) return;
+    WedgeDev& W = b.wedges[t];
+    W.n = 0;
+    if (T.terrain < 0) return;
+    const BodyDev& B = b.bodies[T.body];
+    const ShapeDev& S = b.shapes[T.terrain];
+    double R[9];
+    quat_to_R(B.quat, R);
+    double E0[3], E1[3], nc[3], ntc[3];
+    for (int k = 0; k < 3; ++k) {
+        E0[k] = B.pos[k] + ((R[k * 3 + 0] * T.edge0[0] + R[k * 3 + 1] * T.edge0[1]) + R[k * 3 + 2] * T.edge0[2]);
+        E1[k] = B.pos[k] + ((R[k * 3 + 0] * T.edge1[0] + R[k * 3 + 1] * T.edge1[1]) + R[k * 3 + 2] * T.edge1[2]);
+        nc[k] = (R[k * 3 + 0] * T.n_c[0] + R[k * 3 + 1] * T.n_c[1]) + R[k * 3 + 2] * T.n_c[2];
+        ntc[k] = (R[k * 3 + 0] * T.n_tc[0] + R[k * 3 + 1] * T.n_tc[1]) + R[k * 3 + 2] * T.n_tc[2];
+    }
+    if (T.v_min > 0.0) {
+        double mid[3], arm[3], ve[3];
+        for (int k = 0; k < 3; ++k) { mid[k] = 0.5 * (E0[k] + E1[k]); arm[k] = mid[k] - B.pos[k]; }
+        cross3d(B.angvel, arm, ve);
+        for (int k = 0; k < 3; ++k) ve[k] += B.linvel[k];
+        if (!(sqrt(dot3d(ve, ve)) > T.v_min)) return;
+    }
+    double nf[3], L[3], l[3];
+    for (int k = 0; k < 3; ++k) {
+        nf[k] = (1.0 - T.fill) * nc[k] + T.fill * ntc[k];
+        L[k] = E1[k] - E0[k];
+        l[k] = L[k];
+    }
+    unit3d(nf);
+    unit3d(l);
+    const double zh[3] = {0.0, 0.0, 1.0};
+    double u[3], pl[3];
+    cross3d(zh, l, u);
+    unit3d(u);
+    if (dot3d(u, nf) < 0.0) for (int k = 0; k < 3; ++k) u[k] = -u[k];
+    cross3d(l, nf, pl);
+    unit3d(pl);
+    if (pl[2] < 0.0) for (int k = 0; k < 3; ++k) pl[k] = -pl[k];
+    double a[3], c2[3], m[3];
+    const double fa = (double)w / T.n_wedges, fb = (double)(w + 1) / T.n_wedges, fm = (w + 0.5) / T.n_wedges;
+    for (int k = 0; k < 3; ++k) { a[k] = E0[k] + L[k] * fa; c2[k] = E0[k] + L[k] * fb; m[k] = E0[k] + L[k] * fm; }
+    double hx, hy;
+    const double h0 = hf_height(S, b.hf_pool, m[0], m[1], hx, hy);
+    if (!(m[2] < h0)) return;
+    double sv[3] = {u[0], u[1], u[2] + (hx * u[0] + hy * u[1])};
+    const double sl = dot3d(sv, l);
+    for (int k = 0; k < 3; ++k) sv[k] -= sl * l[k];
+    unit3d(sv);
+    double ns[3];
+    cross3d(l, sv, ns);
+    if (ns[2] < 0.0) for (int k = 0; k < 3; ++k) ns[k] = -ns[k];
+    const double beta = atan2(dot3d(pl, ns), dot3d(pl, sv));
+    const double theta = 0.5 * 3.14159265358979323846 - 0.5 * (T.phi + beta);
+    if (!(theta > 0.0 && theta < 0.5 * 3.14159265358979323846)) return;
+    double d[3];
+    for (int k = 0; k < 3; ++k) d[k] = cos(theta) * sv[k] + sin(theta) * ns[k];
+    double lo = 0.0, hi = S.l0;
+    bool found = false;
+    for (int it = 0; it < 40; ++it) {
+        const double q[3] = {m[0] + hi * d[0], m[1] + hi * d[1], m[2] + hi * d[2]};
+        if (q[2] - hf_height(S, b.hf_pool, q[0], q[1], hx, hy) >= 0.0) { found = true; break; }
+        lo = hi;
+        hi *= 2.0;
+    }
+    if (!found) return;
+    for (int it = 0; it < 60; ++it) {
+        const double md = 0.5 * (lo + hi);
+        const double q[3] = {m[0] + md * d[0], m[1] + md * d[1], m[2] + md * d[2]};
+        if (q[2] - hf_height(S, b.hf_pool, q[0], q[1], hx, hy) >= 0.0) hi = md;
+        else lo = md;
+    }
+    const double ztop = (m[2] + hi * d[2]) + T.heap;
+    double cf[3];
+    cross3d(l, d, cf);
+    unit3d(cf);
+    if (dot3d(cf, pl) > 0.0) for (int k = 0; k < 3; ++k) cf[k] = -cf[k];
+    for (int k = 0; k < 3; ++k) {
+        W.planes[0][k] = -nf[k];
+        W.planes[1][k] = cf[k];
+        W.planes[2][k] = zh[k];
+        W.planes[3][k] = -l[k];
+        W.planes[4][k] = l[k];
+    }
+    W.planes[0][3] = -dot3d(nf, m);
+    W.planes[1][3] = dot3d(cf, m);
+    W.planes[2][3] = ztop;
+    W.planes[3][3] = -dot3d(l, a);
+    W.planes[4][3] = dot3d(l, c2);
+    W.n = 5;
+}
+
 __global__ __launch_bounds__(kRedBlk) void k_zone_part(DevBuffers b, StepParams p)
 {
     __shared__ double sh[kRedBlk / 64];
@@ -2211,14 +2373,8 @@ __global__ __launch_bounds__(kRedBlk) void k_zone_part(DevBuffers b, StepParams 
             double x[3] = {xf.x, xf.y, xf.z};
             // first zone (body order) containing x wins
             int zone = -1;
-            for (int zz = 0; zz < E.zone_count && zone < 0; ++zz) {
-                const BodyDev& Bz = b.bodies[E.zone_body[zz]];
-                bool in = Bz.nplanes > 0;
-                for (int k = 0; k < Bz.nplanes && in; ++k)
-                    if (Bz.wplanes[k][0] * x[0] + Bz.wplanes[k][1] * x[1] + Bz.wplanes[k][2] * x[2] - Bz.wplanes[k][3] > 0.0)
-                        in = false;
-                if (in) zone = zz;
-            }
+            for (int zz = 0; zz < E.zone_count && zone < 0; ++zz)
+                if (in_body_zone(b, b.bodies[E.zone_body[zz]], x)) zone = zz;
             if (zone != z) continue;
             double r = xf.w;
             double m = (double)b.rho[s] * (4.0 / 3.0) * 3.14159265358979323846 * r * r * r;
@@ -2314,12 +2470,7 @@ __global__ void k_zone_count(DevBuffers b, StepParams p)
     float4 xf = b.xr[s];
     double x[3] = {xf.x, xf.y, xf.z};
     for (int zz = 0; zz < E.zone_count; ++zz) {
-        const BodyDev& Bz = b.bodies[E.zone_body[zz]];
-        bool in = Bz.nplanes > 0;
-        for (int k = 0; k < Bz.nplanes && in; ++k)
-            if (Bz.wplanes[k][0] * x[0] + Bz.wplanes[k][1] * x[1] + Bz.wplanes[k][2] * x[2] - Bz.wplanes[k][3] > 0.0)
-                in = false;
-        if (in) {
+        if (in_body_zone(b, b.bodies[E.zone_body[zz]], x)) {
             atomicAdd((unsigned long long*)&b.aggs[E.zone_slot[zz]].n_particles, 1ull);
             break;
         }
@@ -2345,6 +2496,8 @@ void launch_finish(const DevBuffers& b, const StepParams& p, const Sizes& z, hip
         hipLaunchKernelGGL(k_integrate, dim3((unsigned)cdiv(p.n_particles, kBlk)), dim3(kBlk), 0, s, b, p);
     if (p.n_bodies > 0)
         hipLaunchKernelGGL(k_bodies_end, dim3((unsigned)cdiv(p.n_bodies, kBlk)), dim3(kBlk), 0, s, b, p);
+    if (p.n_tools > 0)  // the tools' zones at the end-of-step poses
+        hipLaunchKernelGGL(k_predict_wedges, dim3((unsigned)cdiv(p.n_tools * TR_MAX_WEDGES, 64)), dim3(64), 0, s, b, p);
     if (p.n_zones > 0 && z.n_zone_chunks > 0) {
         hipLaunchKernelGGL(k_zone_part, dim3(z.n_zone_chunks), dim3(kRedBlk), 0, s, b, p);
         hipLaunchKernelGGL(k_zone_final, dim3((unsigned)cdiv(p.n_zones, 64)), dim3(64), 0, s, b, p, z.n_zone_chunks);

@@ -25,7 +25,7 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "set_particles", "set_mlp_weights", "get_phase_times", "set_learned_precision", "get_learn_samples",
            "mlp_forward", "mlp_grad_scratch_floats", "mlp_loss_grad", "mlp_adam_step", "set_solver_config",
            "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state", "autotune",
-           "get_rolling_impulses")
+           "get_rolling_impulses", "set_tool", "get_zone_wedges")
 PGS_MODE = {"grouped": 0, "per_env": 1}
 MLP_TRAINABLE = MLP_PARAMS - 12
 
@@ -67,6 +67,15 @@ class tr_body_desc(C.Structure):
                 ("planes", (C.c_double * 4) * 8)]
 
 
+MAX_WEDGES = 16
+
+
+class tr_tool_desc(C.Structure):
+    _fields_ = [("n_wedges", C.c_int32), ("pad", C.c_int32), ("edge0", C.c_double * 3), ("edge1", C.c_double * 3),
+                ("n_c", C.c_double * 3), ("n_tc", C.c_double * 3), ("fill", C.c_double), ("phi", C.c_double),
+                ("heap", C.c_double), ("v_min", C.c_double)]
+
+
 class tr_step_stats(C.Structure):
     _fields_ = [("contacts", C.c_int64), ("pair_contacts", C.c_int64), ("colours", C.c_int32),
                 ("sweeps", C.c_int32), ("residual", C.c_double), ("residual_first", C.c_double),
@@ -102,6 +111,9 @@ def lib():
         L.set_kinematic_bodies.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(tr_body_desc)]
         L.step.argtypes = [P, C.c_int32, C.POINTER(tr_step_stats)]
         L.get_contact_forces.argtypes = [P, C.c_int32, C.c_int32, dp, dp]
+        L.set_tool.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(tr_tool_desc)]
+        L.get_zone_wedges.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, dp, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]
         L.get_aggregates.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(tr_aggregate), C.POINTER(C.c_int32)]
         L.get_last_error.argtypes = [P]
         L.get_last_error.restype = C.c_char_p
@@ -261,6 +273,35 @@ class Scene:
                      residual=s.residual, residual_first=s.residual_first, fallback_used=s.fallback_used,
                      overflow=s.overflow, impacts=s.impacts, impact_sweeps=s.impact_sweeps) for s in st]
 
+    def set_tool(self, env, body_id, tool):
+        """Attach a zone predictor tool (dict: n_wedges, edge0, edge1, n_c,
+        n_tc, fill, phi, heap, v_min; body frame) to a body; None removes it."""
+        if tool is None:
+            self._check(lib().set_tool(self.h, env, body_id, None), "set_tool")
+            return
+        T = tr_tool_desc()
+        T.n_wedges = int(tool.get("n_wedges", 1))
+        for k in range(3):
+            T.edge0[k] = tool["edge0"][k]
+            T.edge1[k] = tool["edge1"][k]
+            T.n_c[k] = tool["n_c"][k]
+            T.n_tc[k] = tool.get("n_tc", tool["n_c"])[k]
+        T.fill = tool.get("fill", 0.0)
+        T.phi = tool["phi"]
+        T.heap = tool.get("heap", 0.0)
+        T.v_min = tool.get("v_min", 0.0)
+        self._check(lib().set_tool(self.h, env, body_id, C.byref(T)), "set_tool")
+
+    def get_zone_wedges(self, env, body_id):
+        """The last step's wedges of a body's tool: a list of (k x 4) arrays of
+        half-spaces (n, d), world frame, k = 0 for an empty wedge."""
+        planes = np.zeros(MAX_WEDGES * 20)
+        counts = (C.c_int32 * MAX_WEDGES)()
+        n = C.c_int32()
+        self._check(lib().get_zone_wedges(self.h, env, body_id, MAX_WEDGES, _dp(planes), counts, C.byref(n)),
+                    "get_zone_wedges")
+        return [planes[w * 20:w * 20 + 4 * counts[w]].reshape(-1, 4) for w in range(n.value)]
+
     def get_contact_forces(self, env, body_id):
         f = np.zeros(3)
         t = np.zeros(3)
@@ -418,4 +459,6 @@ def scene_from_specs(specs, cap_particles=None, cap_contacts=None, **kw):
             sc.set_particles(e, w=s["w"])
         bodies = [dict(b, id=i) for i, b in enumerate(s.get("bodies", []))]  # id = body index
         sc.set_kinematic_bodies(e, bodies)
+        for t in s.get("tools", []):  # tools name their body by index (= id here)
+            sc.set_tool(e, int(t["body"]), t)
     return sc

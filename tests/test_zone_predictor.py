@@ -138,7 +138,7 @@ def test_oracle_step_aggregates_the_particles_in_the_wedges():
     tool = dict(body=1, n_wedges=3, edge0=(0.0, -0.5, 0.2), edge1=(0.0, 0.5, 0.2), n_c=(1, 0, 0), phi=phi, heap=0.1)
     spec = dict(x=x, r=np.full(400, 0.004), v=np.zeros((400, 3)), w=np.zeros((400, 3)), id=np.arange(400),
                 bodies=bodies, tools=[tool], material=SG.material(0.5, 0.0), dt=1.0 / 60.0, gravity=(0.0, 0.0, 0.0),
-                max_sweeps=0, tol=0.0, warm_start="cold", grid_lo=(-3.0, -3.0, -1.0), grid_hi=(3.0, 3.0, 2.0),
+                max_sweeps=0, tol=0.0, warm_start="cold", grid_lo=(-0.5, -0.8, 0.0), grid_hi=(1.2, 0.8, 1.0),
                 r_ref=0.05)
     out = O.OracleScene(spec).step()
     W = O.predict_wedges(tool, bodies)
