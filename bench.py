@@ -279,7 +279,8 @@ def main():
     ap.add_argument("--settle", type=int, default=150)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("bed", "batched", "copy"), default="bed")
+    ap.add_argument("--workload", choices=("bed", "batched", "copy", "mlp"), default="bed",
+                    help="mlp: the learned-start network's throughput alone (one JSON line)")
     ap.add_argument("--envs", type=int, default=256)
     ap.add_argument("--schedule", default="", help="PGS schedule as JSON (set_solver_config fields)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start training and evaluation")
@@ -297,6 +298,9 @@ def main():
         return
     if args.workload == "copy":
         bench_copy(args)
+        return
+    if args.workload == "mlp":
+        print(json.dumps({"workload": "learned-start network, 4,194,304 contacts", "mlp": mlp_throughput()}))
         return
 
     sc, spec, blade, est_top = build_bed(args)

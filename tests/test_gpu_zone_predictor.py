@@ -143,3 +143,34 @@ def test_layer_on_terrain_with_moving_blade_tool_matches_oracle():
         # boundary may flip for a particle or two
         assert abs(ga["n_particles"] - oa["n_particles"]) <= max(2, 0.01 * oa["n_particles"])
         assert ga["M"] == pytest.approx(oa["M"], rel=0.02)
+
+
+def test_graph_replay_with_impacts_rolling_and_tool():
+    # the step graphs capture the impact stage, the rolling rows and the
+    # predictor; every replay is checked against eagerly launched steps
+    r, surf = 0.03, 0.3
+    gx, gy, gz = np.meshgrid(np.arange(-0.4, 1.0, 2 * r), np.arange(-0.4, 0.4, 2 * r), np.arange(3), indexing="ij")
+    x = np.stack([gx.ravel(), gy.ravel(), surf + r + gz.ravel() * (2 * r - 2e-4) - 1e-4], 1)  # layers overlap
+    v = np.zeros_like(x)
+    v[x[:, 2] > surf + 3 * r, 2] = -2.0  # the top layer thrown down: impacts
+    bodies = [terrain(lambda x, y: 0 * x + 0 * y + surf), tool_body(pos=(-0.5, 0.0, -0.3), v=(1.5, 0.0, 0.0))]
+    tool = dict(body=1, n_wedges=3, edge0=(0.0, -0.6, 0.2), edge1=(0.0, 0.6, 0.2), n_c=(1, 0, 0),
+                phi=math.atan(0.6), heap=0.2)
+    spec = scene_spec(bodies, [tool], x=x, sweeps=20, g=(0.0, 0.0, -9.81))
+    spec.update(r=SG.fp32(np.full(len(x), r)), v=SG.fp32(v), warm_start="prev",
+                material=SG.material(0.6, 0.0, mu_r=0.1, restitution=0.3, v_imp=1.0))
+    ga, gb = T.scene_from_specs(spec), T.scene_from_specs(spec)
+    gb.set_step_graphs(False)
+    for k in range(4):
+        sa, sb = ga.step(1)[0], gb.step(1)[0]
+        assert sa["impacts"] == sb["impacts"] and sa["contacts"] == sb["contacts"]
+        if k == 0:
+            assert sa["impacts"] > 0
+        pa, pb = ga.get_particles(0), gb.get_particles(0)
+        for q in ("x", "v", "w"):
+            assert np.array_equal(pa[q], pb[q]), (k, q)
+        (aa,), (ab,) = ga.get_aggregates(0), gb.get_aggregates(0)
+        assert aa["n_particles"] == ab["n_particles"] and aa["M"] == ab["M"]
+        assert np.array_equal(ga.get_rolling_impulses(0), gb.get_rolling_impulses(0))
+        for wa, wb in zip(ga.get_zone_wedges(0, 1), gb.get_zone_wedges(0, 1)):
+            assert np.array_equal(wa, wb)
