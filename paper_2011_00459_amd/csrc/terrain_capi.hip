@@ -601,7 +601,7 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
               alloc_n(s, b.id_count, z.NID) && alloc_n(s, b.id_start, z.NID + 1) && alloc_n(s, b.id_fill, z.NID) &&
               alloc_n(s, b.pid_start, z.NID + 1) && alloc_n(s, b.inc_count, z.P) &&
               alloc_n(s, b.inc_start, z.P + 1) && alloc_n(s, b.inc_fill, z.P) && alloc_n(s, b.inc, 2 * z.C) &&
-              alloc_n(s, b.colour, z.C) && alloc_n(s, b.col_hist, (int64_t)kBuckets * z.NB) &&
+              alloc_n(s, b.colour, z.C) && alloc_n(s, b.col_wait, z.C) && alloc_n(s, b.col_hist, (int64_t)kBuckets * z.NB) &&
               alloc_n(s, b.col_start, (int64_t)kBuckets * z.NB + 1) && alloc_n(s, b.cpos, z.C) &&
               alloc_n(s, b.r0, z.C) && alloc_n(s, b.r1, z.C) && alloc_n(s, b.r2, z.C) && alloc_n(s, b.rk, z.C) &&
               alloc_n(s, b.r3, z.roll_C) && alloc_n(s, b.lamr, z.roll_C) && alloc_n(s, b.lamr0, z.roll_C) &&

@@ -194,6 +194,7 @@ struct DevBuffers {
     uint32_t *id_count, *id_start, *id_fill, *pid_start;  // [NID], [NID+1], [NID], [NID+1]
     uint32_t *inc_count, *inc_start, *inc_fill, *inc;     // [P], [P+1], [P], [2C]
     int* colour;                                    // [C]
+    uint32_t* col_wait;                             // [C] colouring: the neighbour that blocked a contact
     uint32_t *col_hist, *col_start;                 // [kBuckets*NB], [kBuckets*NB+1]
     uint32_t* cpos;                                 // canonical -> colour position
     float4 *r0, *r1, *r2, *rk, *lam, *lam0;         // colour order

@@ -617,6 +617,12 @@ __global__ __launch_bounds__(kBlk) void k_colour(DevBuffers b, int64_t cap, int 
         left = false;
         for (uint32_t c = first; c < nc; c += stride) {
             if (ld_colour(&b.colour[c]) >= 0) continue;
+            // the neighbour that blocked this contact last pass: while it is
+            // uncoloured the contact stays blocked (a full scan decides readiness)
+            if (pass > 0) {
+                const uint32_t wb = b.col_wait[c];
+                if (wb != ~0u && ld_colour(&b.colour[wb]) < 0) { left = true; continue; }
+            }
             unsigned long long key = b.ckey[c];
             unsigned long long h = splitmix64(key);
             int2 pr = b.cpair[c];
@@ -634,7 +640,11 @@ __global__ __launch_bounds__(kBlk) void k_colour(DevBuffers b, int64_t cap, int 
                     if (ce < 0) {
                         unsigned long long ke = b.ckey[e];
                         unsigned long long he = splitmix64(ke);
-                        if (he > h || (he == h && ke > key)) { ready = false; break; }
+                        if (he > h || (he == h && ke > key)) {
+                            ready = false;
+                            b.col_wait[c] = e;
+                            break;
+                        }
                     } else {
                         used |= 1ull << ce;
                     }
