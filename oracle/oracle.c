@@ -1539,3 +1539,97 @@ double orc_natural_residual(const orc_params* P,
 
 /* Eq. failure_plane: theta(phi, beta) = pi/2 - (phi + beta)/2. */
 double orc_failure_angle(double phi, double beta) { return 0.5 * PI - 0.5 * (phi + beta); }
+
+/* ------------------------------------------------------------------ */
+/* Mesoscale fields on voxels: coarse-graining (Eq. cg_velocity) and the */
+/* conserved advection of fluidized mass (Eq. advection)                 */
+/* ------------------------------------------------------------------ */
+static int grid_ok(const orc_voxel_grid* g)
+{
+    return g && g->l0 > 0.0 && g->nx > 0 && g->ny > 0 && g->nz > 0;
+}
+
+int32_t orc_coarse_grain(int64_t n, const double* x, const double* v, const double* m, const orc_voxel_grid* g,
+                         int32_t kernel, double R, double* rho, double* mom, double* u)
+{
+    if (!grid_ok(g) || (kernel != ORC_CG_HEAVISIDE && kernel != ORC_CG_GAUSS) ||
+        (kernel == ORC_CG_GAUSS && !(R > 0.0)))
+        return -1;
+    const int64_t nv = (int64_t)g->nx * g->ny * g->nz;
+    const double V0 = g->l0 * g->l0 * g->l0;
+    for (int64_t i = 0; i < nv; ++i) {
+        rho[i] = 0.0;
+        for (int k = 0; k < 3; ++k) mom[3 * i + k] = 0.0;
+    }
+    const int dims[3] = {g->nx, g->ny, g->nz};
+    for (int64_t a = 0; a < n; ++a) {
+        const double* xa = &x[3 * a];
+        if (kernel == ORC_CG_HEAVISIDE) {
+            int c[3], in = 1;
+            for (int k = 0; k < 3; ++k) {
+                double f = floor((xa[k] - g->origin[k]) / g->l0);
+                if (!(f >= 0.0 && f < (double)dims[k])) in = 0;
+                c[k] = in ? (int)f : 0;
+            }
+            if (!in) continue;
+            int64_t id = ((int64_t)c[2] * g->ny + c[1]) * g->nx + c[0];
+            rho[id] += m[a] / V0;
+            for (int k = 0; k < 3; ++k) mom[3 * id + k] += m[a] * v[3 * a + k] / V0;
+        } else {
+            const double norm = 1.0 / ((sqrt(2.0 * PI) * R) * (sqrt(2.0 * PI) * R) * (sqrt(2.0 * PI) * R));
+            int lo[3], hi[3];
+            for (int k = 0; k < 3; ++k) {
+                /* voxel centres within 3R of the particle */
+                double fl = ceil((xa[k] - 3.0 * R - g->origin[k]) / g->l0 - 0.5);
+                double fh = floor((xa[k] + 3.0 * R - g->origin[k]) / g->l0 - 0.5);
+                lo[k] = fl < 0.0 ? 0 : (int)fl;
+                hi[k] = fh > (double)(dims[k] - 1) ? dims[k] - 1 : (int)fh;
+            }
+            for (int kz = lo[2]; kz <= hi[2]; ++kz)
+                for (int jy = lo[1]; jy <= hi[1]; ++jy)
+                    for (int ix = lo[0]; ix <= hi[0]; ++ix) {
+                        double y[3] = {g->origin[0] + (ix + 0.5) * g->l0 - xa[0],
+                                       g->origin[1] + (jy + 0.5) * g->l0 - xa[1],
+                                       g->origin[2] + (kz + 0.5) * g->l0 - xa[2]};
+                        double r2 = dot3(y, y);
+                        if (r2 > 9.0 * R * R) continue;
+                        double z = norm * exp(-r2 / (2.0 * R * R));
+                        int64_t id = ((int64_t)kz * g->ny + jy) * g->nx + ix;
+                        rho[id] += m[a] * z;
+                        for (int k = 0; k < 3; ++k) mom[3 * id + k] += m[a] * v[3 * a + k] * z;
+                    }
+        }
+    }
+    if (u)
+        for (int64_t i = 0; i < nv; ++i)
+            for (int k = 0; k < 3; ++k) u[3 * i + k] = rho[i] > 0.0 ? mom[3 * i + k] / rho[i] : 0.0;
+    return 0;
+}
+
+double orc_advect(const orc_voxel_grid* g, double dt, const double* u, double* mf)
+{
+    if (!grid_ok(g)) return -1.0;
+    const int64_t nv = (int64_t)g->nx * g->ny * g->nz;
+    const int dims[3] = {g->nx, g->ny, g->nz};
+    const int64_t strides[3] = {1, g->nx, (int64_t)g->nx * g->ny};
+    double* out = (double*)malloc((size_t)nv * sizeof(double));
+    double cfl = 0.0;
+    for (int64_t i = 0; i < nv; ++i) out[i] = mf[i];
+    /* every interior face once: the flux leaves the donor and enters the other voxel */
+    for (int64_t i = 0; i < nv; ++i) {
+        int64_t c[3] = {i % g->nx, (i / g->nx) % g->ny, i / ((int64_t)g->nx * g->ny)};
+        for (int d = 0; d < 3; ++d) {
+            if (c[d] + 1 >= dims[d]) continue;  /* closed outer face */
+            int64_t j = i + strides[d];
+            double uf = 0.5 * (u[3 * i + d] + u[3 * j + d]);
+            double a = fabs(uf) * dt / g->l0;
+            if (a > cfl) cfl = a;
+            double phi = uf > 0.0 ? dt * uf * mf[i] / g->l0 : dt * uf * mf[j] / g->l0;  /* + : i -> j */
+            out[i] -= phi;
+            out[j] += phi;
+        }
+    }
+    for (int64_t i = 0; i < nv; ++i) mf[i] = out[i];
+    free(out);
+    return cfl;
+}

@@ -125,6 +125,36 @@ typedef struct orc_wedge {
  * their count, or -1 for a bad tool. */
 int32_t orc_predict_wedges(const orc_tool* t, const orc_body* bodies, const orc_shape* terrain, orc_wedge* out);
 
+/* Voxel grid of the mesoscale fields: voxel (i, j, k) spans
+ * origin + l0 [i, i+1) x [j, j+1) x [k, k+1), index (k ny + j) nx + i. */
+typedef struct orc_voxel_grid {
+    double origin[3];
+    double l0;
+    int32_t nx, ny, nz;
+    int32_t pad;
+} orc_voxel_grid;
+
+enum { ORC_CG_HEAVISIDE = 0, ORC_CG_GAUSS = 1 };
+
+/* Coarse-grained mass and momentum densities of particles (x, v: 3n, m: n)
+ * on the voxel grid (Eq. cg_velocity: rho = sum m zeta(x - x_a), p = sum m v
+ * zeta(x - x_a)).  HEAVISIDE: zeta = 1/l0^3 inside a particle's voxel (mass
+ * preserved exactly); GAUSS: zeta(y) = (sqrt(2 pi) R)^-3 exp(-|y|^2 / 2R^2)
+ * at the voxel centres, cut at |y| > 3R.  rho: one per voxel, mom: 3 per
+ * voxel, u = p / rho (0 where rho = 0): 3 per voxel (u may be NULL).
+ * Particles outside the grid are skipped (HEAVISIDE).  Returns 0, or -1 for a
+ * bad grid or kernel. */
+int32_t orc_coarse_grain(int64_t n, const double* x, const double* v, const double* m, const orc_voxel_grid* g,
+                         int32_t kernel, double R, double* rho, double* mom, double* u);
+
+/* One step of conserved advection of the fluidized mass per voxel mf (kg)
+ * with the voxel velocities u (3 per voxel), Eq. advection without sources:
+ * donor-cell fluxes through every interior face, phi = dt u_f mf_donor / l0
+ * with u_f the mean of the two voxels' normal velocities and the donor the
+ * upwind voxel; the grid's outer faces are closed.  mf is updated in place;
+ * the largest |u_f| dt / l0 (positivity needs <= 1) is returned. */
+double orc_advect(const orc_voxel_grid* g, double dt, const double* u, double* mf);
+
 /* MLP 12 -> 64 -> 64 -> 3 with SiLU, weights row-major W[out][in]. */
 typedef struct orc_mlp {
     const double* W1; const double* b1;  /* 64x12, 64 */

@@ -53,6 +53,20 @@ class Wedge(C.Structure):
 MAX_WEDGES = 16
 
 
+class VoxelGrid(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("l0", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("nz", C.c_int32), ("pad", C.c_int32)]
+
+
+def voxel_grid(origin, l0, dims) -> VoxelGrid:
+    g = VoxelGrid()
+    for k in range(3):
+        g.origin[k] = origin[k]
+    g.l0 = l0
+    g.nx, g.ny, g.nz = (int(d) for d in dims)
+    return g
+
+
 class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("g", C.c_double * 3), ("grid_lo", C.c_double * 3),
                 ("grid_hi", C.c_double * 3), ("r_ref", C.c_double), ("max_sweeps", C.c_int32), ("tol", C.c_double),
@@ -148,6 +162,10 @@ def lib():
         L.orc_mlp_loss_grad.argtypes = [C.POINTER(Mlp), C.c_int64, dp, dp, dp]
         L.orc_predict_wedges.restype = C.c_int32
         L.orc_predict_wedges.argtypes = [C.POINTER(Tool), C.POINTER(Body), C.POINTER(Shape), C.POINTER(Wedge)]
+        L.orc_coarse_grain.restype = C.c_int32
+        L.orc_coarse_grain.argtypes = [C.c_int64, dp, dp, dp, C.POINTER(VoxelGrid), C.c_int32, C.c_double, dp, dp, dp]
+        L.orc_advect.restype = C.c_double
+        L.orc_advect.argtypes = [C.POINTER(VoxelGrid), C.c_double, dp, dp]
         L.orc_failure_angle.restype = C.c_double
         L.orc_failure_angle.argtypes = [C.c_double, C.c_double]
         _lib = L
@@ -446,3 +464,34 @@ def mlp_loss_grad(weights: dict, feat: np.ndarray, label: np.ndarray):
 
 def failure_angle(phi: float, beta: float) -> float:
     return lib().orc_failure_angle(phi, beta)
+
+
+CG_KERNELS = {"heaviside": 0, "gauss": 1}
+
+
+def coarse_grain(x, v, m, origin, l0, dims, kernel="heaviside", R=0.0):
+    """Mass density, momentum density and velocity on a voxel grid (arrays
+    shaped (nz, ny, nx), (nz, ny, nx, 3), (nz, ny, nx, 3))."""
+    x = _c64(x).reshape(-1, 3)
+    v = _c64(v).reshape(-1, 3)
+    m = _c64(m)
+    g = voxel_grid(origin, l0, dims)
+    nv = int(np.prod(dims))
+    rho = np.zeros(nv); mom = np.zeros((nv, 3)); u = np.zeros((nv, 3))
+    rc = lib().orc_coarse_grain(len(x), _dp(x), _dp(v), _dp(m), C.byref(g), CG_KERNELS[kernel], R, _dp(rho),
+                                _dp(mom), _dp(u))
+    if rc != 0:
+        raise ValueError("bad grid or kernel")
+    sh = (dims[2], dims[1], dims[0])
+    return rho.reshape(sh), mom.reshape(sh + (3,)), u.reshape(sh + (3,))
+
+
+def advect(mf, u, origin, l0, dims, dt):
+    """One step of conserved donor-cell advection; returns (new mf, largest Courant number)."""
+    g = voxel_grid(origin, l0, dims)
+    m = _c64(mf).ravel().copy()
+    uu = _c64(u).reshape(-1, 3)
+    cfl = lib().orc_advect(C.byref(g), dt, _dp(uu), _dp(m))
+    if cfl < 0:
+        raise ValueError("bad grid")
+    return m.reshape(np.shape(mf)), cfl
