@@ -203,6 +203,95 @@ def bench_copy(args):
                       "read_plus_write_GBps": 2 * nbytes * args.steps / wall / 1e9}), flush=True)
 
 
+ADVECT_BYTES = 40  # per voxel: mf in (8), u in (24), mf out (8); neighbours' values are re-reads
+
+
+def bench_voxels(args):
+    """Mesoscale voxel step on a 256 x 256 x 128 dig-site grid (8.4 M voxels,
+    l0 = 0.05 m): one conserved advection step of the fluidized mass per
+    step, inputs resident in HBM.  The advection kernel's device time comes
+    from HIP events on the library's stream (the default stream here); the
+    coarse-graining of a 50,000-sphere bed onto its own grid is timed beside
+    it."""
+    from paper_2011_00459_amd.devmem import DeviceArray, hip
+    h = hip()
+    w = SG.voxel_workload(seed=11)
+    nv = int(np.prod(w["dims"]))
+    spec = SG.bed_scene(seed=2, n=args.n, r0=0.03, spread=0.1, lx=4.0, ly=2.0, mu=0.7, c=2000.0, sweeps=50,
+                        tool="none")
+    sc = T.scene_from_specs(spec, cap_contacts=16 * args.n)
+    sc.step(2)
+    mf = [DeviceArray.from_host(w["mf"], np.float64), DeviceArray(w["mf"].shape, np.float64)]
+    u = DeviceArray.from_host(w["u"], np.float64)
+    ev = [ctypes.c_void_p(), ctypes.c_void_p()]
+    for e in ev:
+        if h.hipEventCreate(ctypes.byref(e)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+
+    def advect(k):
+        a, b = mf[k % 2], mf[(k + 1) % 2]
+        return sc.advect_fluid(w["origin"], w["l0"], w["dims"], w["dt"], u.ptr, a.ptr, b.ptr)
+
+    for k in range(args.warmup):
+        advect(k)
+    device_sync()
+    dev_ms = 0.0
+    t0 = time.perf_counter()
+    cfl = 0.0
+    for k in range(args.steps):
+        h.hipEventRecord(ev[0], None)
+        cfl = advect(args.warmup + k)  # returns after the stream has drained
+        h.hipEventRecord(ev[1], None)
+        h.hipEventSynchronize(ev[1])
+        ms = ctypes.c_float()
+        h.hipEventElapsedTime(ctypes.byref(ms), ev[0], ev[1])
+        dev_ms += ms.value
+    device_sync()
+    wall = time.perf_counter() - t0
+    # coarse-graining of the bed (Heaviside and Gaussian), event-timed the same way
+    lo, l0c = (-2.1, -1.1, -0.05), 0.06
+    dims_c = (72, 38, 16)
+    nvc = int(np.prod(dims_c))
+    rho, mom, uc = DeviceArray((nvc,), np.float64), DeviceArray((nvc, 3), np.float64), DeviceArray((nvc, 3), np.float64)
+    cg = {}
+    for kern, R in (("heaviside", 0.0), ("gauss", 0.06)):
+        sc.coarse_grain(0, lo, l0c, dims_c, rho.ptr, mom.ptr, uc.ptr, kernel=kern, R=R)
+        device_sync()
+        h.hipEventRecord(ev[0], None)
+        for _ in range(10):
+            sc.coarse_grain(0, lo, l0c, dims_c, rho.ptr, mom.ptr, uc.ptr, kernel=kern, R=R)
+        h.hipEventRecord(ev[1], None)
+        h.hipEventSynchronize(ev[1])
+        ms = ctypes.c_float()
+        h.hipEventElapsedTime(ctypes.byref(ms), ev[0], ev[1])
+        cg[kern] = dict(ms=ms.value / 10, particles=args.n, voxels=nvc)
+    adv_ms = dev_ms / args.steps
+    achieved = ADVECT_BYTES * nv / (adv_ms * 1e-3) / 1e9
+    line = {
+        "metric": "voxel advection updates/s", "value": nv * args.steps / wall, "unit": "voxels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "mesoscale dig site: 256x256x128 voxels l0 0.05 m, fluidized soil 1600 kg/m3 in an "
+                               "ellipsoidal zone, swirl velocity at Courant <= 0.4, dt 1/60 s",
+                   "courant": cfl, "advect_device_ms": adv_ms, "coarse_grain_bed": cg},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": ADVECT_BYTES * nv, "kernel": "k_advect"},
+    }
+    if not args.no_cpu:
+        sys.path.insert(0, os.path.join(ROOT, "oracle"))
+        import pyoracle as O
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < min(args.cpu_seconds, 10.0):
+            O.advect(w["mf"], w["u"], w["origin"], w["l0"], w["dims"], w["dt"])
+            reps += 1
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": nv * reps / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{reps} oracle advection steps of the same 8.4 M-voxel grid"}
+    print(json.dumps(line), flush=True)
+
+
 def mlp_throughput(n=1 << 22):
     """The learned-start network on MFMA (BF16 inference) and the FP32
     training kernels: device time per call from HIP events, TFLOP/s."""
@@ -279,8 +368,9 @@ def main():
     ap.add_argument("--settle", type=int, default=150)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("bed", "batched", "copy", "mlp"), default="bed",
-                    help="mlp: the learned-start network's throughput alone (one JSON line)")
+    ap.add_argument("--workload", choices=("bed", "batched", "copy", "mlp", "voxels"), default="bed",
+                    help="mlp: the learned-start network's throughput alone (one JSON line); voxels: the "
+                         "mesoscale advection step")
     ap.add_argument("--envs", type=int, default=256)
     ap.add_argument("--schedule", default="", help="PGS schedule as JSON (set_solver_config fields)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start training and evaluation")
@@ -298,6 +388,9 @@ def main():
         return
     if args.workload == "copy":
         bench_copy(args)
+        return
+    if args.workload == "voxels":
+        bench_voxels(args)
         return
     if args.workload == "mlp":
         print(json.dumps({"workload": "learned-start network, 4,194,304 contacts", "mlp": mlp_throughput()}))

@@ -152,6 +152,17 @@ typedef struct tr_body_desc {
  * plane meets the surface plus `heap`, between the slice's lateral planes.
  * The plate normal is normalize((1 - fill) n_c + fill n_tc) (the secondary
  * separation plate of a partly filled bucket).  Geometry in the body frame. */
+/* Voxel grid of the mesoscale fields: voxel (i, j, k) spans origin +
+ * l0 [i, i+1) x [j, j+1) x [k, k+1); arrays are indexed (k ny + j) nx + i. */
+typedef struct tr_voxel_grid {
+    double origin[3];
+    double l0;               /* voxel edge [m], > 0 */
+    int32_t nx, ny, nz;      /* > 0 */
+    int32_t pad;
+} tr_voxel_grid;
+
+enum { TR_CG_HEAVISIDE = 0, TR_CG_GAUSS = 1 };
+
 #define TR_MAX_WEDGES 16
 typedef struct tr_tool_desc {
     int32_t n_wedges;        /* 1 .. TR_MAX_WEDGES */
@@ -232,6 +243,30 @@ int set_tool(tr_scene* s, int32_t env, int32_t body_id, const tr_tool_desc* t);
  * first step after a change; TR_E_INVAL when the body has no tool. */
 int get_zone_wedges(tr_scene* s, int32_t env, int32_t body_id, int32_t cap, double* planes, int32_t* counts,
                     int32_t* n_wedges);
+
+/* Coarse-grained fields of env's particles (their state after the last
+ * step) on grid g, Eq. cg_velocity: rho = sum_a m_a zeta(x - x_a), mom =
+ * sum_a m_a v_a zeta(x - x_a), u = mom / rho (0 where rho = 0).
+ * TR_CG_HEAVISIDE: zeta = 1/l0^3 in the particle's own voxel (mass preserved
+ * exactly; particles outside the grid are skipped); TR_CG_GAUSS: zeta(y) =
+ * (sqrt(2 pi) R)^-3 exp(-|y|^2 / 2R^2) at the voxel centres, cut at |y| > 3R.
+ * rho (1 per voxel), mom and u (3 per voxel; u may be NULL) are device
+ * arrays of the caller, written on the scene's stream (sums in FP64 with
+ * atomics: the order of the additions is not fixed).  TR_E_INVAL for a bad
+ * env, grid, kernel or R. */
+int coarse_grain(tr_scene* s, int32_t env, const tr_voxel_grid* g, int32_t kernel, double R, double* rho,
+                 double* mom, double* u);
+
+/* One step of conserved advection of the fluidized mass per voxel (kg),
+ * Eq. advection without sources: each interior face carries
+ * phi = dt u_f mf_donor / l0 from the upwind voxel, u_f the mean of the two
+ * voxels' normal velocities; the grid's outer faces are closed, so the total
+ * is conserved to rounding.  u (3 per voxel), mf_in, mf_out: device arrays
+ * (mf_out must not alias mf_in).  *cfl receives the largest |u_f| dt / l0
+ * (positivity needs <= 1; the call synchronises the stream to read it).
+ * TR_E_INVAL for a bad grid or pointers. */
+int advect_fluid(tr_scene* s, const tr_voxel_grid* g, double dt, const double* u, const double* mf_in,
+                 double* mf_out, double* cfl);
 
 /* Advances every env by n_steps steps.  Asynchronous on the scene's stream
  * when stats is NULL; otherwise waits and writes one tr_step_stats per env

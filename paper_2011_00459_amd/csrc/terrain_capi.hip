@@ -1023,6 +1023,49 @@ int get_zone_wedges(tr_scene* s, int32_t env, int32_t body_id, int32_t cap, doub
     return TR_OK;
 }
 
+static bool voxel_grid_ok(const tr_voxel_grid* g)
+{
+    if (!g || !(g->l0 > 0.0) || !std::isfinite(g->l0) || g->nx <= 0 || g->ny <= 0 || g->nz <= 0) return false;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(g->origin[k])) return false;
+    return (int64_t)g->nx * g->ny * g->nz <= ((int64_t)1 << 31);
+}
+
+int coarse_grain(tr_scene* s, int32_t env, const tr_voxel_grid* g, int32_t kernel, double R, double* rho,
+                 double* mom, double* u)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "coarse_grain: env");
+    if (!voxel_grid_ok(g)) return fail(s, TR_E_INVAL, "coarse_grain: grid");
+    if (kernel != TR_CG_HEAVISIDE && kernel != TR_CG_GAUSS) return fail(s, TR_E_INVAL, "coarse_grain: kernel");
+    if (kernel == TR_CG_GAUSS && !(R > 0.0 && std::isfinite(R))) return fail(s, TR_E_INVAL, "coarse_grain: R");
+    if (!rho || !mom) return fail(s, TR_E_INVAL, "coarse_grain: null output");
+    if (s->tables_dirty) return fail(s, TR_E_STATE, "coarse_grain: no step since the bodies changed");
+    launch_coarse_grain(s->b, s->env_host[env], *g, kernel, R, rho, mom, u, s->stream);
+    HIP_CHECK(s, hipGetLastError());
+    return TR_OK;
+}
+
+int advect_fluid(tr_scene* s, const tr_voxel_grid* g, double dt, const double* u, const double* mf_in,
+                 double* mf_out, double* cfl)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (!voxel_grid_ok(g)) return fail(s, TR_E_INVAL, "advect_fluid: grid");
+    if (!(dt >= 0.0 && std::isfinite(dt))) return fail(s, TR_E_INVAL, "advect_fluid: dt");
+    if (!u || !mf_in || !mf_out || !cfl) return fail(s, TR_E_INVAL, "advect_fluid: null pointer");
+    if (mf_in == mf_out) return fail(s, TR_E_INVAL, "advect_fluid: mf_out aliases mf_in");
+    unsigned long long* bits = (unsigned long long*)s->staging;  // at least 12 floats: one uint64 fits
+    launch_advect(*g, dt, u, mf_in, mf_out, bits, s->stream);
+    HIP_CHECK(s, hipGetLastError());
+    unsigned long long h = 0;
+    HIP_CHECK(s, hipMemcpyAsync(&h, bits, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    memcpy(cfl, &h, sizeof(double));
+    return TR_OK;
+}
+
 int get_aggregates(tr_scene* s, int32_t env, int32_t cap, tr_aggregate* out, int32_t* n_out)
 {
     if (!s || !n_out || cap < 0 || (cap > 0 && !out)) return TR_E_INVAL;

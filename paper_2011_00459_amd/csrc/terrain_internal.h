@@ -276,6 +276,12 @@ void launch_narrow(const DevBuffers& b, const StepParams& p, const Sizes& z, hip
 void launch_canonical(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, hipStream_t s);
+// mesoscale voxel fields (device arrays of the caller); cfl_bits: one
+// device uint64 receiving the largest Courant number's bits
+void launch_coarse_grain(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, int kernel, double R,
+                         double* rho, double* mom, double* u, hipStream_t s);
+void launch_advect(const tr_voxel_grid& g, double dt, const double* u, const double* mf_in, double* mf_out,
+                   unsigned long long* cfl_bits, hipStream_t s);
 // impact stage: rows of envs without impacts neutralised, the stage's sweeps
 // (stats slot kSlotImpact), the main rows' q from the post-impact velocities
 void launch_impact_stage(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);

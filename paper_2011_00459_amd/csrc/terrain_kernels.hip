@@ -2555,4 +2555,126 @@ void launch_scatter_by_id(const DevBuffers& b, int id_base, int n, const float4*
                        mask);
 }
 
+// ---------------------------------------------------------------------------
+// Mesoscale voxel fields: coarse-graining (Eq. cg_velocity) and the conserved
+// advection of fluidized mass (Eq. advection)
+// ---------------------------------------------------------------------------
+__global__ void k_fill_f64(double* a, int64_t n, double v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// one thread per particle of the env: its mass and momentum into the voxels
+__global__ void k_coarse_grain(DevBuffers b, EnvDev E, tr_voxel_grid g, int kernel, double R, double* rho,
+                               double* mom)
+{
+#pragma clang fp contract(off)
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= E.n) return;
+    const int sl = E.slot_begin + a;
+    const float4 xf = b.xr[sl], vf = b.vm[sl];
+    const double x[3] = {xf.x, xf.y, xf.z}, v[3] = {vf.x, vf.y, vf.z};
+    const double r = xf.w;
+    const double m = (double)b.rho[sl] * (4.0 / 3.0) * 3.14159265358979323846 * r * r * r;
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    if (kernel == TR_CG_HEAVISIDE) {
+        const double V0 = g.l0 * g.l0 * g.l0;
+        int c[3];
+        for (int k = 0; k < 3; ++k) {
+            const double f = floor((x[k] - g.origin[k]) / g.l0);
+            if (!(f >= 0.0 && f < (double)dims[k])) return;
+            c[k] = (int)f;
+        }
+        const int64_t id = ((int64_t)c[2] * g.ny + c[1]) * g.nx + c[0];
+        atomicAdd(&rho[id], m / V0);
+        for (int k = 0; k < 3; ++k) atomicAdd(&mom[3 * id + k], m * v[k] / V0);
+        return;
+    }
+    const double sq = sqrt(2.0 * 3.14159265358979323846) * R;
+    const double norm = 1.0 / (sq * sq * sq);
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        const double fl = ceil((x[k] - 3.0 * R - g.origin[k]) / g.l0 - 0.5);
+        const double fh = floor((x[k] + 3.0 * R - g.origin[k]) / g.l0 - 0.5);
+        lo[k] = fl < 0.0 ? 0 : (int)fl;
+        hi[k] = fh > (double)(dims[k] - 1) ? dims[k] - 1 : (int)fh;
+    }
+    for (int kz = lo[2]; kz <= hi[2]; ++kz)
+        for (int jy = lo[1]; jy <= hi[1]; ++jy)
+            for (int ix = lo[0]; ix <= hi[0]; ++ix) {
+                const double y[3] = {g.origin[0] + (ix + 0.5) * g.l0 - x[0], g.origin[1] + (jy + 0.5) * g.l0 - x[1],
+                                     g.origin[2] + (kz + 0.5) * g.l0 - x[2]};
+                const double r2 = (y[0] * y[0] + y[1] * y[1]) + y[2] * y[2];
+                if (r2 > 9.0 * R * R) continue;
+                const double z = norm * exp(-r2 / (2.0 * R * R));
+                const int64_t id = ((int64_t)kz * g.ny + jy) * g.nx + ix;
+                atomicAdd(&rho[id], m * z);
+                for (int k = 0; k < 3; ++k) atomicAdd(&mom[3 * id + k], m * v[k] * z);
+            }
+}
+
+__global__ void k_cg_velocity(int64_t nv, const double* rho, const double* mom, double* u)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    for (int k = 0; k < 3; ++k) u[3 * i + k] = rho[i] > 0.0 ? mom[3 * i + k] / rho[i] : 0.0;
+}
+
+void launch_coarse_grain(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, int kernel, double R,
+                         double* rho, double* mom, double* u, hipStream_t s)
+{
+    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, rho, nv, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)cdiv(3 * nv, kBlk)), dim3(kBlk), 0, s, mom, 3 * nv, 0.0);
+    if (E.n > 0)
+        hipLaunchKernelGGL(k_coarse_grain, dim3((unsigned)cdiv(E.n, kBlk)), dim3(kBlk), 0, s, b, E, g, kernel, R, rho,
+                           mom);
+    if (u) hipLaunchKernelGGL(k_cg_velocity, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, nv, rho, mom, u);
+}
+
+// flux through the face between voxels i and j = i + e_d (+: from i to j),
+// the same operations as every other evaluation of that face
+__device__ inline double face_flux(const tr_voxel_grid& g, double dt, const double* u, const double* mf, int64_t i,
+                                   int64_t j, int d, double& courant)
+{
+#pragma clang fp contract(off)
+    const double uf = 0.5 * (u[3 * i + d] + u[3 * j + d]);
+    courant = fabs(uf) * dt / g.l0;
+    return uf > 0.0 ? dt * uf * mf[i] / g.l0 : dt * uf * mf[j] / g.l0;
+}
+
+__global__ void k_advect(tr_voxel_grid g, double dt, const double* u, const double* mf, double* out,
+                         unsigned long long* cfl_bits)
+{
+#pragma clang fp contract(off)
+    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    const int64_t c[3] = {i % g.nx, (i / g.nx) % g.ny, i / ((int64_t)g.nx * g.ny)};
+    const int64_t dims[3] = {g.nx, g.ny, g.nz};
+    const int64_t strides[3] = {1, g.nx, (int64_t)g.nx * g.ny};
+    // inflow through the lower faces, then outflow through the upper ones,
+    // each face's donors in increasing voxel order (the sum's order is that
+    // of a sweep over the faces by their lower voxel)
+    double m = mf[i], cmax = 0.0, cr;
+    for (int d = 2; d >= 0; --d)
+        if (c[d] > 0) m += face_flux(g, dt, u, mf, i - strides[d], i, d, cr);
+    for (int d = 0; d < 3; ++d)
+        if (c[d] + 1 < dims[d]) {
+            m -= face_flux(g, dt, u, mf, i, i + strides[d], d, cr);
+            cmax = fmax(cmax, cr);
+        }
+    out[i] = m;
+    if (cmax > 0.0) atomicMax(cfl_bits, (unsigned long long)__double_as_longlong(cmax));  // >= 0: bits order as values
+}
+
+void launch_advect(const tr_voxel_grid& g, double dt, const double* u, const double* mf_in, double* mf_out,
+                   unsigned long long* cfl_bits, hipStream_t s)
+{
+    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, (double*)cfl_bits, (int64_t)1, 0.0);  // bits of +0
+    hipLaunchKernelGGL(k_advect, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, g, dt, u, mf_in, mf_out, cfl_bits);
+}
+
 }  // namespace trk

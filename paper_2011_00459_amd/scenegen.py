@@ -194,3 +194,24 @@ def jammed_bed(seed=21, nx=40, ny=20, nz=12, r0=0.03, spread=0.002, jitter=0.001
         bodies.append(box_blade(-lx / 2 + 0.2, top - 0.1, width=0.6 * ly, height=0.4, vx=1.0))
     bounds = ((-lx / 2 - 2 * s, -ly / 2 - 2 * s, -2 * s), (lx / 2 + 2 * s, ly / 2 + 2 * s, top + 0.6))
     return _spec(x, r, bodies, material(mu, c), dt, sweeps, bounds, r0)
+
+
+def voxel_workload(seed=11, dims=(256, 256, 128), l0=0.05, dt=1.0 / 60.0, rho_f=1600.0, courant=0.4):
+    """Mesoscale grid of a dig site: fluidized soil (bulk density rho_f, in
+    kg per voxel) filling an ellipsoidal zone ahead of a tool with a ragged
+    fill fraction, zero elsewhere; the velocity is a swirl about the zone's
+    axis plus noise, everywhere on the grid, scaled so that no face's Courant
+    number exceeds `courant`.  Arrays shaped (nz, ny, nx) and (nz, ny, nx, 3)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = dims
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    q = ((x - 0.5 * nx) / (0.3 * nx)) ** 2 + ((y - 0.5 * ny) / (0.2 * ny)) ** 2 + ((z - 0.3 * nz) / (0.25 * nz)) ** 2
+    fill = np.clip(rng.uniform(0.0, 1.2, q.shape), 0.0, 1.0) * (q < 1.0)
+    mf = rho_f * l0 ** 3 * fill
+    u = np.empty(q.shape + (3,))
+    u[..., 0] = -(y - 0.5 * ny) / ny + 0.2
+    u[..., 1] = (x - 0.5 * nx) / nx
+    u[..., 2] = 0.3 * np.sin(2 * np.pi * x / nx)
+    u += rng.normal(0.0, 0.1, u.shape)
+    u *= courant * l0 / dt / np.max(np.abs(u))  # a face's |u_f| is at most the larger of its two voxels'
+    return dict(mf=mf, u=u, origin=(0.0, 0.0, 0.0), l0=l0, dims=dims, dt=dt)

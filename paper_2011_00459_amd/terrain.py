@@ -25,7 +25,8 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "set_particles", "set_mlp_weights", "get_phase_times", "set_learned_precision", "get_learn_samples",
            "mlp_forward", "mlp_grad_scratch_floats", "mlp_loss_grad", "mlp_adam_step", "set_solver_config",
            "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state", "autotune",
-           "get_rolling_impulses", "set_tool", "get_zone_wedges")
+           "get_rolling_impulses", "set_tool", "get_zone_wedges", "coarse_grain", "advect_fluid")
+CG_KERNEL = {"heaviside": 0, "gauss": 1}
 PGS_MODE = {"grouped": 0, "per_env": 1}
 MLP_TRAINABLE = MLP_PARAMS - 12
 
@@ -74,6 +75,20 @@ class tr_tool_desc(C.Structure):
     _fields_ = [("n_wedges", C.c_int32), ("pad", C.c_int32), ("edge0", C.c_double * 3), ("edge1", C.c_double * 3),
                 ("n_c", C.c_double * 3), ("n_tc", C.c_double * 3), ("fill", C.c_double), ("phi", C.c_double),
                 ("heap", C.c_double), ("v_min", C.c_double)]
+
+
+class tr_voxel_grid(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("l0", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("nz", C.c_int32), ("pad", C.c_int32)]
+
+
+def voxel_grid(origin, l0, dims):
+    g = tr_voxel_grid()
+    for k in range(3):
+        g.origin[k] = origin[k]
+    g.l0 = l0
+    g.nx, g.ny, g.nz = (int(d) for d in dims)
+    return g
 
 
 class tr_step_stats(C.Structure):
@@ -137,6 +152,8 @@ def lib():
         L.load_state.argtypes = [P, C.c_void_p, C.c_int64]
         L.autotune.argtypes = [P, C.c_int32, C.c_char_p, C.POINTER(tr_solver_config), C.POINTER(C.c_float)]
         L.get_rolling_impulses.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_int64)]
+        L.coarse_grain.argtypes = [P, C.c_int32, C.POINTER(tr_voxel_grid), C.c_int32, C.c_double, P, P, P]
+        L.advect_fluid.argtypes = [P, C.POINTER(tr_voxel_grid), C.c_double, P, P, P, C.POINTER(C.c_double)]
         for name in EXPORTS:
             if name != "get_last_error":
                 getattr(L, name).restype = C.c_int
@@ -301,6 +318,23 @@ class Scene:
         self._check(lib().get_zone_wedges(self.h, env, body_id, MAX_WEDGES, _dp(planes), counts, C.byref(n)),
                     "get_zone_wedges")
         return [planes[w * 20:w * 20 + 4 * counts[w]].reshape(-1, 4) for w in range(n.value)]
+
+    def coarse_grain(self, env, origin, l0, dims, rho_ptr, mom_ptr, u_ptr=None, kernel="heaviside", R=0.0):
+        """Density, momentum density and velocity of env's particles on a voxel
+        grid (dims = (nx, ny, nz)), into caller-owned device arrays given as
+        pointers (nx ny nz doubles for rho, three times that for mom and u)."""
+        g = voxel_grid(origin, l0, dims)
+        self._check(lib().coarse_grain(self.h, env, C.byref(g), CG_KERNEL[kernel], R, rho_ptr, mom_ptr, u_ptr),
+                    "coarse_grain")
+
+    def advect_fluid(self, origin, l0, dims, dt, u_ptr, mf_in_ptr, mf_out_ptr):
+        """One conserved donor-cell step of the fluidized mass on device arrays;
+        returns the largest Courant number."""
+        g = voxel_grid(origin, l0, dims)
+        cfl = C.c_double()
+        self._check(lib().advect_fluid(self.h, C.byref(g), dt, u_ptr, mf_in_ptr, mf_out_ptr, C.byref(cfl)),
+                    "advect_fluid")
+        return cfl.value
 
     def get_contact_forces(self, env, body_id):
         f = np.zeros(3)

@@ -39,9 +39,9 @@ def test_struct_layouts_match_header():
     code = r'''
 #include <stdio.h>
 #include "terrain.h"
-int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(tr_material), sizeof(tr_scene_desc),
+int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(tr_material), sizeof(tr_scene_desc),
  sizeof(tr_shape_desc), sizeof(tr_body_desc), sizeof(tr_step_stats), sizeof(tr_aggregate),
- sizeof(tr_solver_config), sizeof(tr_tool_desc));return 0;}
+ sizeof(tr_solver_config), sizeof(tr_tool_desc), sizeof(tr_voxel_grid));return 0;}
 '''
     with tempfile.TemporaryDirectory() as d:
         srcf = os.path.join(d, "s.c")
@@ -51,7 +51,7 @@ int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(tr_material), 
         sizes = [int(v) for v in subprocess.check_output([exe]).split()]
     mine = [C.sizeof(T.tr_material), C.sizeof(T.tr_scene_desc), C.sizeof(T.tr_shape_desc),
             C.sizeof(T.tr_body_desc), C.sizeof(T.tr_step_stats), C.sizeof(T.tr_aggregate),
-            C.sizeof(T.tr_solver_config), C.sizeof(T.tr_tool_desc)]
+            C.sizeof(T.tr_solver_config), C.sizeof(T.tr_tool_desc), C.sizeof(T.tr_voxel_grid)]
     assert sizes == mine
 
 
