@@ -1537,6 +1537,130 @@ double orc_natural_residual(const orc_params* P,
     return num > 0.0 ? 1.0 : 0.0;
 }
 
+/* ------------------------------------------------------------------ */
+/* Conversion between resting solid and fluidized mass (the passage on   */
+/* converting overlapping soil, Eq. surface)                            */
+/* ------------------------------------------------------------------ */
+static int grid_ok(const orc_voxel_grid* g);
+
+int32_t orc_surface_heights(const orc_voxel_grid* g, const double* phi, double* h)
+{
+    if (!grid_ok(g)) return -1;
+    const int64_t nxy = (int64_t)g->nx * g->ny;
+    for (int64_t c = 0; c < nxy; ++c) {
+        h[c] = g->origin[2];
+        for (int k = g->nz - 1; k >= 0; --k) {
+            double f = phi[(int64_t)k * nxy + c];
+            if (f > 0.0) {
+                double zc = g->origin[2] + (k + 0.5) * g->l0;  /* the voxel's centre */
+                h[c] = zc + (f - 0.5) * g->l0;
+                break;
+            }
+        }
+    }
+    return 0;
+}
+
+/* The z interval of the vertical line through (x, y) inside one wedge; 0 if
+ * the line misses it or the wedge has no lower bound there. */
+static int wedge_vertical(const orc_wedge* w, double x, double y, double* zlo, double* zhi)
+{
+    double lo = -INFINITY, hi = INFINITY;
+    if (w->n == 0) return 0;
+    for (int p = 0; p < w->n; ++p) {
+        const double* P = w->planes[p];
+        double a = P[2], b = P[3] - P[0] * x - P[1] * y;  /* a z <= b */
+        if (a > 0.0) { double z = b / a; if (z < hi) hi = z; }
+        else if (a < 0.0) { double z = b / a; if (z > lo) lo = z; }
+        else if (b < 0.0) return 0;
+    }
+    if (!(lo <= hi) || lo == -INFINITY) return 0;
+    *zlo = lo;
+    *zhi = hi;
+    return 1;
+}
+
+static int inside_any_wedge(int32_t nw, const orc_wedge* w, const double x[3])
+{
+    for (int k = 0; k < nw; ++k) {
+        if (w[k].n == 0) continue;
+        int in = 1;
+        for (int p = 0; p < w[k].n && in; ++p)
+            if (w[k].planes[p][0] * x[0] + w[k].planes[p][1] * x[1] + w[k].planes[p][2] * x[2] - w[k].planes[p][3] > 0.0)
+                in = 0;
+        if (in) return 1;
+    }
+    return 0;
+}
+
+double orc_convert_cut(const orc_voxel_grid* g, double rho_b, int32_t n_wedges, const orc_wedge* wedges,
+                       double* phi, const double* wc, double* mf)
+{
+    if (!grid_ok(g) || n_wedges < 0) return -1.0;
+    const int64_t nxy = (int64_t)g->nx * g->ny;
+    const double V0 = g->l0 * g->l0 * g->l0;
+    double total = 0.0;
+    for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i) {
+            double x = g->origin[0] + (i + 0.5) * g->l0, y = g->origin[1] + (j + 0.5) * g->l0;
+            double zcut = INFINITY, lo, hi;
+            for (int w = 0; w < n_wedges; ++w)
+                if (wedge_vertical(&wedges[w], x, y, &lo, &hi) && lo < zcut) zcut = lo;
+            if (zcut == INFINITY) continue;
+            for (int k = 0; k < g->nz; ++k) {
+                int64_t id = (int64_t)k * nxy + (int64_t)j * g->nx + i;
+                double t = (zcut - (g->origin[2] + k * g->l0)) / g->l0;  /* occupancy below the cut */
+                if (t < 0.0) t = 0.0;
+                if (t > 1.0) t = 1.0;
+                if (phi[id] > t) {
+                    double dm = wc[id] * rho_b * V0 * (phi[id] - t);
+                    mf[id] += dm;
+                    total += dm;
+                    phi[id] = t;
+                }
+            }
+        }
+    return total;
+}
+
+double orc_convert_deposit(const orc_voxel_grid* g, double rho_b, double w_dep, int32_t n_wedges,
+                           const orc_wedge* wedges, const double* rho_p, double* phi, double* wc, double* mf)
+{
+    if (!grid_ok(g) || n_wedges < 0 || !(w_dep > 0.0)) return -1.0;
+    const int64_t nxy = (int64_t)g->nx * g->ny;
+    const double V0 = g->l0 * g->l0 * g->l0;
+    double total = 0.0;
+    for (int j = 0; j < g->ny; ++j)
+        for (int i = 0; i < g->nx; ++i) {
+            const int64_t c = (int64_t)j * g->nx + i;
+            for (int k = 0; k < g->nz; ++k) {
+                const int64_t src = (int64_t)k * nxy + c;
+                double x[3] = {g->origin[0] + (i + 0.5) * g->l0, g->origin[1] + (j + 0.5) * g->l0,
+                               g->origin[2] + (k + 0.5) * g->l0};
+                if (!(mf[src] > 0.0) || rho_p[src] != 0.0 || inside_any_wedge(n_wedges, wedges, x)) continue;
+                double m = mf[src];
+                mf[src] = 0.0;
+                /* the first voxel of the column that is not full */
+                int kk = 0;
+                while (kk < g->nz && phi[(int64_t)kk * nxy + c] >= 1.0) ++kk;
+                while (m > 0.0 && kk < g->nz) {
+                    const int64_t id = (int64_t)kk * nxy + c;
+                    double cap = (1.0 - phi[id]) * w_dep * rho_b * V0;
+                    double take = m < cap ? m : cap;
+                    double f = take == cap ? 1.0 : phi[id] + take / (w_dep * rho_b * V0);
+                    double before = wc[id] * rho_b * V0 * phi[id];
+                    wc[id] = phi[id] > 0.0 ? (before + take) / (rho_b * V0 * f) : w_dep;
+                    phi[id] = f;
+                    total += take;
+                    m -= take;
+                    ++kk;
+                }
+                mf[src] += m;  /* a full column: the rest stays fluid */
+            }
+        }
+    return total;
+}
+
 /* Eq. failure_plane: theta(phi, beta) = pi/2 - (phi + beta)/2. */
 double orc_failure_angle(double phi, double beta) { return 0.5 * PI - 0.5 * (phi + beta); }
 

@@ -155,6 +155,34 @@ int32_t orc_coarse_grain(int64_t n, const double* x, const double* v, const doub
  * the largest |u_f| dt / l0 (positivity needs <= 1) is returned. */
 double orc_advect(const orc_voxel_grid* g, double dt, const double* u, double* mf);
 
+/* Conversion between resting solid and fluidized mass on the voxel grid.
+ * Per voxel: phi (solid occupancy in [0, 1]), wc (compaction: the solid mass
+ * is wc phi rho_b l0^3), mf (fluidized mass, kg).  Every column is full
+ * below its surface voxel, empty above it. */
+
+/* Eq. surface: h = z' + (phi' - 1/2) l0 for the top-most voxel with solid
+ * (z' its centre), origin[2] for an empty column; h: nx ny values, index
+ * j nx + i.  Returns 0, or -1 for a bad grid. */
+int32_t orc_surface_heights(const orc_voxel_grid* g, const double* phi, double* h);
+
+/* Solid of the columns under active-zone wedges is liberated down to the
+ * zone's bottom: for the vertical line through a column's centre, each wedge
+ * it crosses bounds z from below (the failure plane, a plate leaning over the
+ * column); the column's new surface is the lowest such bound where it is
+ * below the surface.  The liberated solid becomes fluidized mass in the
+ * voxel that held it.  Returns the liberated mass, or -1 for a bad grid. */
+double orc_convert_cut(const orc_voxel_grid* g, double rho_b, int32_t n_wedges, const orc_wedge* wedges,
+                       double* phi, const double* wc, double* mf);
+
+/* Fluidized mass in a voxel that holds no particles (rho_p == 0) and whose
+ * centre lies outside every wedge falls to its column's surface and becomes
+ * solid of compaction w_dep (the loose state of soil that has flowed), raising
+ * the surface; a voxel being filled gets the mass-weighted compaction; mass
+ * that finds the column full stays fluid where it was.  Returns the deposited
+ * mass, or -1 for a bad grid or w_dep. */
+double orc_convert_deposit(const orc_voxel_grid* g, double rho_b, double w_dep, int32_t n_wedges,
+                           const orc_wedge* wedges, const double* rho_p, double* phi, double* wc, double* mf);
+
 /* MLP 12 -> 64 -> 64 -> 3 with SiLU, weights row-major W[out][in]. */
 typedef struct orc_mlp {
     const double* W1; const double* b1;  /* 64x12, 64 */

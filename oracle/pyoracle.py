@@ -166,6 +166,13 @@ def lib():
         L.orc_coarse_grain.argtypes = [C.c_int64, dp, dp, dp, C.POINTER(VoxelGrid), C.c_int32, C.c_double, dp, dp, dp]
         L.orc_advect.restype = C.c_double
         L.orc_advect.argtypes = [C.POINTER(VoxelGrid), C.c_double, dp, dp]
+        L.orc_surface_heights.restype = C.c_int32
+        L.orc_surface_heights.argtypes = [C.POINTER(VoxelGrid), dp, dp]
+        L.orc_convert_cut.restype = C.c_double
+        L.orc_convert_cut.argtypes = [C.POINTER(VoxelGrid), C.c_double, C.c_int32, C.POINTER(Wedge), dp, dp, dp]
+        L.orc_convert_deposit.restype = C.c_double
+        L.orc_convert_deposit.argtypes = [C.POINTER(VoxelGrid), C.c_double, C.c_double, C.c_int32, C.POINTER(Wedge),
+                                          dp, dp, dp, dp]
         L.orc_failure_angle.restype = C.c_double
         L.orc_failure_angle.argtypes = [C.c_double, C.c_double]
         _lib = L
@@ -495,3 +502,50 @@ def advect(mf, u, origin, l0, dims, dt):
     if cfl < 0:
         raise ValueError("bad grid")
     return m.reshape(np.shape(mf)), cfl
+
+
+def _wedge_array(wedges):
+    arr = (Wedge * max(1, len(wedges)))()
+    for k, W in enumerate(wedges):
+        W = np.asarray(W, dtype=np.float64).reshape(-1, 4)
+        arr[k].n = len(W)
+        for p in range(len(W)):
+            for q in range(4):
+                arr[k].planes[p][q] = W[p, q]
+    return arr
+
+
+def surface_heights(phi, origin, l0, dims):
+    """Eq. surface per column: (ny, nx) heights of the solid occupancy phi (nz, ny, nx)."""
+    g = voxel_grid(origin, l0, dims)
+    f = _c64(phi).ravel()
+    h = np.zeros(dims[0] * dims[1])
+    if lib().orc_surface_heights(C.byref(g), _dp(f), _dp(h)) != 0:
+        raise ValueError("bad grid")
+    return h.reshape(dims[1], dims[0])
+
+
+def convert_cut(phi, wc, mf, wedges, origin, l0, dims, rho_b):
+    """Liberate the solid above the zone's bottom into fluidized mass; returns
+    (phi, mf, liberated mass) (new arrays)."""
+    g = voxel_grid(origin, l0, dims)
+    f, w, m = _c64(phi).ravel().copy(), _c64(wc).ravel().copy(), _c64(mf).ravel().copy()
+    tot = lib().orc_convert_cut(C.byref(g), rho_b, len(wedges), _wedge_array(wedges), _dp(f), _dp(w), _dp(m))
+    if tot < 0:
+        raise ValueError("bad grid")
+    sh = np.shape(phi)
+    return f.reshape(sh), m.reshape(sh), tot
+
+
+def convert_deposit(phi, wc, mf, rho_p, wedges, origin, l0, dims, rho_b, w_dep):
+    """Deposit particle-free fluidized mass outside the zones onto the column
+    surfaces; returns (phi, wc, mf, deposited mass) (new arrays)."""
+    g = voxel_grid(origin, l0, dims)
+    f, w, m = _c64(phi).ravel().copy(), _c64(wc).ravel().copy(), _c64(mf).ravel().copy()
+    rp = _c64(rho_p).ravel()
+    tot = lib().orc_convert_deposit(C.byref(g), rho_b, w_dep, len(wedges), _wedge_array(wedges), _dp(rp), _dp(f),
+                                    _dp(w), _dp(m))
+    if tot < 0:
+        raise ValueError("bad grid or w_dep")
+    sh = np.shape(phi)
+    return f.reshape(sh), w.reshape(sh), m.reshape(sh), tot

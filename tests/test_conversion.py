@@ -1,0 +1,163 @@
+"""Conversion between resting solid and fluidized mass in the oracle (the
+passage on converting overlapping soil; Eq. surface).
+
+Pins, each against geometry or arithmetic fixed outside the oracle's code:
+  - Eq. surface on hand-built columns (full, partial, empty);
+  - a hand-written Rankine wedge over level ground: the liberated mass is the
+    sum over the cut columns of rho_b l0^2 (h0 - z_fail(x)), the new surface
+    is z_fail there, every other column keeps h0;
+  - a deposit raises the surface by m / (w_dep rho_b l0^2), whatever the voxel
+    boundaries crossed, with the mass-weighted compaction of a voxel being
+    filled; fluid beside particles or inside a zone stays; a full column
+    keeps what does not fit;
+  - cut followed by deposit with no zone and no particles is the identity;
+  - solid plus fluid mass is conserved to rounding on random terrain with the
+    predictor's wedges.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import pyoracle as O
+
+L0 = 0.1
+DIMS = (24, 10, 12)  # nx, ny, nz
+ORIGIN = (-1.0, -0.5, 0.0)
+RHO_B = 1800.0
+V0 = L0 ** 3
+
+
+def columns(h):
+    """Occupancy of columns filled to the heights h (ny, nx) from the grid's bottom."""
+    zb = ORIGIN[2] + L0 * np.arange(DIMS[2])
+    return np.clip((np.asarray(h)[None, :, :] - zb[:, None, None]) / L0, 0.0, 1.0)
+
+
+def solid_mass(phi, wc):
+    return float(np.sum(wc * phi) * RHO_B * V0)
+
+
+def test_surface_heights_closed_forms():
+    phi = np.zeros((DIMS[2], DIMS[1], DIMS[0]))
+    phi[:3, 0, 0] = 1.0
+    phi[3, 0, 0] = 0.25       # three full voxels and a quarter
+    phi[:, 1, 0] = 1.0        # a full column
+    phi[0, 2, 0] = 0.5        # half a voxel
+    h = O.surface_heights(phi, ORIGIN, L0, DIMS)
+    assert h[0, 0] == pytest.approx(ORIGIN[2] + 3.25 * L0, abs=1e-15)
+    assert h[1, 0] == pytest.approx(ORIGIN[2] + DIMS[2] * L0, abs=1e-15)
+    assert h[2, 0] == pytest.approx(ORIGIN[2] + 0.5 * L0, abs=1e-15)
+    assert h[3, 0] == ORIGIN[2]  # empty column: the grid's bottom
+    hh = np.random.default_rng(1).uniform(0.05, 1.15, (DIMS[1], DIMS[0]))
+    assert np.allclose(O.surface_heights(columns(hh), ORIGIN, L0, DIMS), hh, rtol=0, atol=1e-14)
+
+
+def rankine_wedge(ex, ez, theta, top, half_width):
+    # in front of the plate x >= ex, above the failure line z >= ez + (x - ex) tan(theta),
+    # below the top, between the lateral planes
+    t = math.tan(theta)
+    return np.array([[-1.0, 0.0, 0.0, -ex],
+                     [t, 0.0, -1.0, t * ex - ez],
+                     [0.0, 0.0, 1.0, top],
+                     [0.0, 1.0, 0.0, half_width],
+                     [0.0, -1.0, 0.0, half_width]])
+
+
+def test_cut_of_level_ground_by_a_rankine_wedge():
+    h0, ex, ez, theta, top, hw = 0.83, -0.35, 0.41, math.radians(27.5), 0.9, 0.25
+    phi = columns(np.full((DIMS[1], DIMS[0]), h0))
+    wc = np.ones_like(phi)
+    mf = np.zeros_like(phi)
+    W = rankine_wedge(ex, ez, theta, top, hw)
+    phi2, mf2, lib = O.convert_cut(phi, wc, mf, [W], ORIGIN, L0, DIMS, RHO_B)
+    xc = ORIGIN[0] + L0 * (np.arange(DIMS[0]) + 0.5)
+    yc = ORIGIN[1] + L0 * (np.arange(DIMS[1]) + 0.5)
+    zf = ez + (xc - ex) * math.tan(theta)
+    cut_x = (xc >= ex) & (zf <= top)
+    cut_y = np.abs(yc) <= hw
+    expect_h = np.full((DIMS[1], DIMS[0]), h0)
+    for j in np.nonzero(cut_y)[0]:
+        for i in np.nonzero(cut_x)[0]:
+            expect_h[j, i] = min(h0, zf[i])
+    assert np.sum(expect_h < h0) > 10
+    h = O.surface_heights(phi2, ORIGIN, L0, DIMS)
+    assert np.allclose(h, expect_h, rtol=0, atol=1e-13)
+    assert lib == pytest.approx(RHO_B * L0 ** 2 * np.sum(h0 - expect_h), rel=1e-12)
+    # the liberated mass sits in the voxels that held it
+    assert np.sum(mf2) == pytest.approx(lib, rel=1e-14)
+    assert np.all(mf2[phi2 >= phi] == 0.0)
+    assert solid_mass(phi2, wc) + np.sum(mf2) == pytest.approx(solid_mass(phi, wc), rel=1e-14)
+
+
+def test_deposit_raises_the_surface():
+    h0, w_dep = 0.43, 0.8
+    phi = columns(np.full((DIMS[1], DIMS[0]), h0))
+    wc = np.ones_like(phi)
+    mf = np.zeros_like(phi)
+    rho_p = np.zeros_like(phi)
+    m = 2.5 * w_dep * RHO_B * L0 ** 2 * L0  # 2.5 voxels' worth at the loose density
+    mf[9, 3, 5] = m                          # high above the surface, no particles
+    mf[9, 4, 5] = 1.0
+    rho_p[9, 4, 5] = 10.0                    # beside particles: stays
+    mf[9, 5, 5] = 1.0                        # inside a zone: stays
+    W = np.array([[1.0, 0, 0, ORIGIN[0] + 5.9 * L0], [-1.0, 0, 0, -(ORIGIN[0] + 5.1 * L0)],
+                  [0, 1.0, 0, ORIGIN[1] + 5.9 * L0], [0, -1.0, 0, -(ORIGIN[1] + 5.1 * L0)],
+                  [0, 0, -1.0, -0.0]])
+    phi2, wc2, mf2, dep = O.convert_deposit(phi, wc, mf, rho_p, [W], ORIGIN, L0, DIMS, RHO_B, w_dep)
+    h = O.surface_heights(phi2, ORIGIN, L0, DIMS)
+    assert dep == pytest.approx(m, rel=1e-14)
+    assert h[3, 5] == pytest.approx(h0 + m / (w_dep * RHO_B * L0 ** 2), rel=1e-13)
+    assert mf2[9, 3, 5] == 0.0 and mf2[9, 4, 5] == 1.0 and mf2[9, 5, 5] == 1.0
+    # the voxel that was partly full holds the mass-weighted compaction
+    k = int((h0 - ORIGIN[2]) // L0)
+    f0 = (h0 - ORIGIN[2]) / L0 - k
+    assert wc2[k, 3, 5] == pytest.approx((f0 * 1.0 + (1 - f0) * w_dep) / 1.0, rel=1e-13)
+    assert wc2[k + 1, 3, 5] == pytest.approx(w_dep, rel=1e-15)
+    assert solid_mass(phi2, wc2) + np.sum(mf2) == pytest.approx(solid_mass(phi, wc) + np.sum(mf), rel=1e-14)
+    # a full column keeps the rest as fluid
+    full = np.ones_like(phi)
+    mf3 = np.zeros_like(phi)
+    mf3[-1, 0, 0] = 3.0
+    phi4, _, mf4, dep4 = O.convert_deposit(full, wc, mf3, rho_p, [], ORIGIN, L0, DIMS, RHO_B, w_dep)
+    assert dep4 == 0.0 and mf4[-1, 0, 0] == 3.0 and np.array_equal(phi4, full)
+
+
+def test_cut_then_deposit_is_the_identity():
+    rng = np.random.default_rng(4)
+    h0 = rng.uniform(0.3, 1.0, (DIMS[1], DIMS[0]))
+    phi = columns(h0)
+    wc = np.ones_like(phi)
+    W = rankine_wedge(-0.6, 0.2, math.radians(30), 1.1, 0.3)
+    phi2, mf2, lib = O.convert_cut(phi, wc, np.zeros_like(phi), [W], ORIGIN, L0, DIMS, RHO_B)
+    assert lib > 0
+    phi3, wc3, mf3, dep = O.convert_deposit(phi2, wc, mf2, np.zeros_like(phi), [], ORIGIN, L0, DIMS, RHO_B, 1.0)
+    assert dep == pytest.approx(lib, rel=1e-13) and not mf3.any()
+    assert np.allclose(O.surface_heights(phi3, ORIGIN, L0, DIMS), h0, rtol=0, atol=1e-13)
+    assert np.allclose(wc3, 1.0, rtol=1e-13)
+
+
+def test_mass_conserved_with_predicted_wedges():
+    rng = np.random.default_rng(9)
+    nx, ny = DIMS[0], DIMS[1]
+    hh = 0.6 + 0.08 * np.sin(np.linspace(0, 3, nx))[None, :] + 0.02 * rng.normal(size=(ny, nx))
+    # the heightfield of the predictor shares the columns' centres
+    terrain = dict(pos=(0, 0, 0), quat=(1, 0, 0, 0), linvel=(0, 0, 0), angvel=(0, 0, 0),
+                   shapes=[dict(type="hfield", nx=nx, ny=ny, ox=ORIGIN[0] + 0.5 * L0, oy=ORIGIN[1] + 0.5 * L0, l0=L0,
+                                h=np.float32(hh).ravel())])
+    blade = dict(pos=(0, 0, 0), quat=(1, 0, 0, 0), linvel=(1.0, 0, 0), angvel=(0, 0, 0), shapes=[])
+    tool = dict(body=1, n_wedges=4, edge0=(-0.5, -0.3, 0.35), edge1=(-0.5, 0.3, 0.35), n_c=(1, 0, 0),
+                phi=math.radians(33), heap=0.1)
+    wedges = O.predict_wedges(tool, [terrain, blade])
+    assert sum(len(w) > 0 for w in wedges) == 4
+    phi = columns(np.float32(hh).astype(np.float64))
+    wc = rng.uniform(0.8, 1.0, phi.shape)
+    mf = np.where(rng.uniform(size=phi.shape) < 0.1, rng.uniform(0, 0.5, phi.shape), 0.0)
+    m0 = solid_mass(phi, wc) + np.sum(mf)
+    phi2, mf2, lib = O.convert_cut(phi, wc, mf, wedges, ORIGIN, L0, DIMS, RHO_B)
+    assert lib > 0.5
+    rho_p = np.where(rng.uniform(size=phi.shape) < 0.3, 1.0, 0.0)
+    phi3, wc3, mf3, dep = O.convert_deposit(phi2, wc, mf2, rho_p, wedges, ORIGIN, L0, DIMS, RHO_B, 0.85)
+    assert dep > 0
+    assert solid_mass(phi3, wc3) + np.sum(mf3) == pytest.approx(m0, rel=1e-13)
+    assert np.all(phi3 >= 0.0) and np.all(phi3 <= 1.0) and np.all(mf3 >= 0.0)

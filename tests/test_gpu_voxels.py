@@ -30,10 +30,16 @@ def particle_masses(r, rho):
 
 
 def stepped_column(seed=3, n=2000):
+    """A scene whose particle state is set from seeded inputs after one step
+    (the step builds the library's tables); both sides take the FP32 values."""
     spec = SG.column_scene(seed=seed, n=n, footprint=0.6, sweeps=20)
     g = T.scene_from_specs(spec)
-    g.step(2)
-    p = g.get_particles(0)
+    g.step(1)
+    rng = np.random.default_rng(seed)
+    x = SG.fp32(np.asarray(spec["x"]) + rng.uniform(-0.01, 0.01, (n, 3)))
+    v = SG.fp32(rng.normal(0.0, 0.5, (n, 3)))
+    g.set_particles(0, x=x, v=v, w=np.zeros((n, 3)))
+    p = dict(x=x, v=v, r=np.asarray(SG.fp32(spec["r"]), dtype=np.float64))
     return g, spec, p
 
 
