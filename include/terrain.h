@@ -257,13 +257,53 @@ int get_zone_wedges(tr_scene* s, int32_t env, int32_t body_id, int32_t cap, doub
 int coarse_grain(tr_scene* s, int32_t env, const tr_voxel_grid* g, int32_t kernel, double R, double* rho,
                  double* mom, double* u);
 
+/* Conversion between resting solid and fluidized mass on a voxel grid
+ * (the passage on converting overlapping soil).  Per voxel, device arrays of
+ * the caller: phi (solid occupancy in [0, 1]), wc (compaction: solid mass
+ * wc phi rho_b l0^3), mf (fluidized mass, kg); every column is full below its
+ * surface voxel.  Wedges: n_wedges wedges of counts[w] half-spaces each
+ * (host arrays; planes holds 5 x 4 doubles per wedge, inside iff
+ * n . x <= d), or, with planes NULL, the wedges the last step predicted for
+ * every tool of env.  A total pointer, when not NULL, receives the converted
+ * mass (the call then synchronises the stream); with NULL the call only
+ * enqueues work on the scene's stream.  TR_E_INVAL for a bad env, grid,
+ * density or wedge count (at most 128 caller wedges, 8 tools), TR_E_STATE for
+ * predicted wedges before a step. */
+
+/* Eq. surface per column: h = z' + (phi' - 1/2) l0 of the top-most voxel with
+ * solid (the grid's bottom for an empty column) into h (nx ny device doubles,
+ * index j nx + i; may be NULL).  With body_id >= 0 the heights also become
+ * the FP32 heights of that body's first heightfield in env, whose grid points
+ * must be the column centres (nx, ny, l0 equal; origin + l0/2); the contacts
+ * and the zone predictor of later steps use them.  TR_E_INVAL otherwise. */
+int terrain_from_voxels(tr_scene* s, int32_t env, int32_t body_id, const tr_voxel_grid* g, const double* phi,
+                        double* h);
+
+/* Cut: for the vertical line through each column's centre, every wedge it
+ * crosses bounds z from below; the column's surface drops to the lowest such
+ * bound and the solid above it becomes fluidized mass in the voxel that held
+ * it. */
+int convert_cut(tr_scene* s, int32_t env, const tr_voxel_grid* g, double rho_b, int32_t n_wedges,
+                const int32_t* counts, const double* planes, double* phi, const double* wc, double* mf,
+                double* liberated);
+
+/* Deposit: fluidized mass in a voxel with no particles (rho_p == 0, e.g. the
+ * coarse-grained density) whose centre is outside every wedge falls to its
+ * column's surface and becomes solid of compaction w_dep > 0, raising it; a
+ * voxel being filled takes the mass-weighted compaction; mass that finds the
+ * column full stays fluid where it was. */
+int convert_deposit(tr_scene* s, int32_t env, const tr_voxel_grid* g, double rho_b, double w_dep, int32_t n_wedges,
+                    const int32_t* counts, const double* planes, const double* rho_p, double* phi, double* wc,
+                    double* mf, double* deposited);
+
 /* One step of conserved advection of the fluidized mass per voxel (kg),
  * Eq. advection without sources: each interior face carries
  * phi = dt u_f mf_donor / l0 from the upwind voxel, u_f the mean of the two
  * voxels' normal velocities; the grid's outer faces are closed, so the total
  * is conserved to rounding.  u (3 per voxel), mf_in, mf_out: device arrays
- * (mf_out must not alias mf_in).  *cfl receives the largest |u_f| dt / l0
- * (positivity needs <= 1; the call synchronises the stream to read it).
+ * (mf_out must not alias mf_in).  *cfl, when cfl is not NULL, receives the
+ * largest |u_f| dt / l0 (positivity needs <= 1; the call then synchronises
+ * the stream to read it; with NULL it only enqueues the step).
  * TR_E_INVAL for a bad grid or pointers. */
 int advect_fluid(tr_scene* s, const tr_voxel_grid* g, double dt, const double* u, const double* mf_in,
                  double* mf_out, double* cfl);

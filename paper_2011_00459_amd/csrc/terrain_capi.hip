@@ -51,6 +51,9 @@ struct tr_scene {
     int bodies_alloc = 0, shapes_alloc = 0, zones_alloc = 0, tools_alloc = 0;
     std::vector<ToolDev> tool_host;  // last uploaded tool table
     std::vector<BodyDev> body_host;   // last uploaded body table (poses refreshed on download)
+    std::vector<ShapeDev> shape_host; // last uploaded shape table
+    WedgeDev* conv_wedges = nullptr;  // caller wedges of the conversion entry points (device)
+    double* conv_total = nullptr;     // one device double: the converted mass
     std::vector<EnvDev> env_host;
     std::vector<std::vector<int>> zone_slots;  // per env: global zone index of each zone body
     hipEvent_t ev[5] = {};
@@ -481,6 +484,7 @@ int rebuild_tables(tr_scene* s)
     s->body_host = bd;
     s->env_host = ed;
     s->tool_host = td;
+    s->shape_host = sd;
     s->p.n_tools = (int)td.size();
     s->z.NC = NC;
     s->z.NCOL = NCOL;
@@ -1054,16 +1058,149 @@ int advect_fluid(tr_scene* s, const tr_voxel_grid* g, double dt, const double* u
     s->err.clear();
     if (!voxel_grid_ok(g)) return fail(s, TR_E_INVAL, "advect_fluid: grid");
     if (!(dt >= 0.0 && std::isfinite(dt))) return fail(s, TR_E_INVAL, "advect_fluid: dt");
-    if (!u || !mf_in || !mf_out || !cfl) return fail(s, TR_E_INVAL, "advect_fluid: null pointer");
+    if (!u || !mf_in || !mf_out) return fail(s, TR_E_INVAL, "advect_fluid: null pointer");
     if (mf_in == mf_out) return fail(s, TR_E_INVAL, "advect_fluid: mf_out aliases mf_in");
     unsigned long long* bits = (unsigned long long*)s->staging;  // at least 12 floats: one uint64 fits
     launch_advect(*g, dt, u, mf_in, mf_out, bits, s->stream);
     HIP_CHECK(s, hipGetLastError());
+    if (!cfl) return TR_OK;
     unsigned long long h = 0;
     HIP_CHECK(s, hipMemcpyAsync(&h, bits, sizeof(h), hipMemcpyDeviceToHost, s->stream));
     HIP_CHECK(s, hipStreamSynchronize(s->stream));
     memcpy(cfl, &h, sizeof(double));
     return TR_OK;
+}
+
+static constexpr int kMaxCallerWedges = 128;
+
+// the wedges of a conversion call: the caller's (copied to the device) or the
+// last step's predictions for env's tools
+static int conversion_wedges(tr_scene* s, int32_t env, int32_t n_wedges, const int32_t* counts,
+                             const double* planes, WedgeSet& ws, const char* what)
+{
+    memset(&ws, 0, sizeof(ws));
+    if (planes) {
+        if (n_wedges < 0 || n_wedges > kMaxCallerWedges || (n_wedges > 0 && !counts))
+            return fail(s, TR_E_INVAL, std::string(what) + ": wedge count");
+        if (n_wedges == 0) return TR_OK;
+        std::vector<WedgeDev> w(n_wedges);
+        for (int k = 0; k < n_wedges; ++k) {
+            if (counts[k] < 0 || counts[k] > 5) return fail(s, TR_E_INVAL, std::string(what) + ": wedge planes");
+            memset(&w[k], 0, sizeof(WedgeDev));
+            w[k].n = counts[k];
+            for (int p = 0; p < counts[k]; ++p)
+                for (int q = 0; q < 4; ++q) {
+                    w[k].planes[p][q] = planes[k * 20 + p * 4 + q];
+                    if (!std::isfinite(w[k].planes[p][q])) return fail(s, TR_E_NONFINITE, std::string(what) + ": plane");
+                }
+        }
+        if (!s->conv_wedges && !alloc_n(s, s->conv_wedges, kMaxCallerWedges))
+            return fail(s, TR_E_NOMEM, std::string(what) + ": wedges");
+        HIP_CHECK(s, hipMemcpyAsync(s->conv_wedges, w.data(), sizeof(WedgeDev) * n_wedges, hipMemcpyHostToDevice,
+                                    s->stream));
+        HIP_CHECK(s, hipStreamSynchronize(s->stream));  // the host vector dies here
+        ws.base = s->conv_wedges;
+        ws.n_ranges = 1;
+        ws.cnt[0] = n_wedges;
+        return TR_OK;
+    }
+    if (s->tables_dirty || !s->stepped) return fail(s, TR_E_STATE, std::string(what) + ": no predicted wedges yet");
+    ws.base = s->b.wedges;
+    for (size_t t = 0; t < s->tool_host.size(); ++t) {
+        if (s->body_host[s->tool_host[t].body].env != env) continue;
+        if (ws.n_ranges == kMaxConvRanges) return fail(s, TR_E_INVAL, std::string(what) + ": more than 8 tools");
+        ws.off[ws.n_ranges] = (int)t * TR_MAX_WEDGES;
+        ws.cnt[ws.n_ranges] = s->tool_host[t].n_wedges;
+        ++ws.n_ranges;
+    }
+    return TR_OK;
+}
+
+static int read_total(tr_scene* s, double* out)
+{
+    if (!out) return TR_OK;
+    HIP_CHECK(s, hipMemcpyAsync(out, s->conv_total, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    return TR_OK;
+}
+
+int terrain_from_voxels(tr_scene* s, int32_t env, int32_t body_id, const tr_voxel_grid* g, const double* phi,
+                        double* h)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "terrain_from_voxels: env");
+    if (!voxel_grid_ok(g) || !phi) return fail(s, TR_E_INVAL, "terrain_from_voxels: grid");
+    float* hf = nullptr;
+    int bi = -1, si = -1;
+    if (body_id >= 0) {
+        if (s->tables_dirty) return fail(s, TR_E_STATE, "terrain_from_voxels: no step since the bodies changed");
+        const EnvHost& H = s->envs[env];
+        for (size_t k = 0; k < H.bodies.size(); ++k)
+            if (H.bodies[k].id == body_id) bi = (int)k;
+        if (bi < 0) return fail(s, TR_E_INVAL, "terrain_from_voxels: no such body");
+        for (size_t k = 0; k < H.shapes[bi].size() && si < 0; ++k)
+            if (H.shapes[bi][k].type == TR_HEIGHTFIELD) si = (int)k;
+        if (si < 0) return fail(s, TR_E_INVAL, "terrain_from_voxels: the body has no heightfield");
+        const tr_shape_desc& S = H.shapes[bi][si];
+        const double tol = 1e-9 * g->l0;
+        if (S.nx != g->nx || S.ny != g->ny || std::fabs(S.l0 - g->l0) > tol ||
+            std::fabs(S.origin[0] - (g->origin[0] + 0.5 * g->l0)) > tol ||
+            std::fabs(S.origin[1] - (g->origin[1] + 0.5 * g->l0)) > tol)
+            return fail(s, TR_E_INVAL, "terrain_from_voxels: the heightfield's points are not the column centres");
+        const int gi = s->env_host[env].body_begin + bi;
+        int k = 0;
+        for (const ShapeDev& Y : s->shape_host) {
+            if (Y.body != gi || Y.type != TR_HEIGHTFIELD) continue;
+            if (k++ == 0) hf = s->b.hf_pool + Y.hf_off;
+        }
+        if (!hf) return fail(s, TR_E_STATE, "terrain_from_voxels: heightfield table");
+    }
+    launch_surface(*g, phi, h, hf, s->stream);
+    HIP_CHECK(s, hipGetLastError());
+    if (hf) {  // the host copy rebuilds the tables
+        std::vector<float>& hh = s->envs[env].heights[bi][si];
+        HIP_CHECK(s, hipMemcpyAsync(hh.data(), hf, sizeof(float) * hh.size(), hipMemcpyDeviceToHost, s->stream));
+        HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    }
+    return TR_OK;
+}
+
+int convert_cut(tr_scene* s, int32_t env, const tr_voxel_grid* g, double rho_b, int32_t n_wedges,
+                const int32_t* counts, const double* planes, double* phi, const double* wc, double* mf,
+                double* liberated)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "convert_cut: env");
+    if (!voxel_grid_ok(g) || !phi || !wc || !mf) return fail(s, TR_E_INVAL, "convert_cut: grid or arrays");
+    if (!(rho_b > 0.0 && std::isfinite(rho_b))) return fail(s, TR_E_INVAL, "convert_cut: rho_b");
+    WedgeSet ws;
+    int rc = conversion_wedges(s, env, n_wedges, counts, planes, ws, "convert_cut");
+    if (rc != TR_OK) return rc;
+    if (!s->conv_total && !alloc_n(s, s->conv_total, 1)) return fail(s, TR_E_NOMEM, "convert_cut");
+    launch_convert_cut(*g, rho_b, ws, phi, wc, mf, liberated ? s->conv_total : nullptr, s->stream);
+    HIP_CHECK(s, hipGetLastError());
+    return read_total(s, liberated);
+}
+
+int convert_deposit(tr_scene* s, int32_t env, const tr_voxel_grid* g, double rho_b, double w_dep, int32_t n_wedges,
+                    const int32_t* counts, const double* planes, const double* rho_p, double* phi, double* wc,
+                    double* mf, double* deposited)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "convert_deposit: env");
+    if (!voxel_grid_ok(g) || !phi || !wc || !mf || !rho_p) return fail(s, TR_E_INVAL, "convert_deposit: grid or arrays");
+    if (!(rho_b > 0.0 && std::isfinite(rho_b)) || !(w_dep > 0.0 && std::isfinite(w_dep)))
+        return fail(s, TR_E_INVAL, "convert_deposit: rho_b or w_dep");
+    WedgeSet ws;
+    int rc = conversion_wedges(s, env, n_wedges, counts, planes, ws, "convert_deposit");
+    if (rc != TR_OK) return rc;
+    if (!s->conv_total && !alloc_n(s, s->conv_total, 1)) return fail(s, TR_E_NOMEM, "convert_deposit");
+    launch_convert_deposit(*g, rho_b, w_dep, ws, rho_p, phi, wc, mf, deposited ? s->conv_total : nullptr, s->stream);
+    HIP_CHECK(s, hipGetLastError());
+    return read_total(s, deposited);
 }
 
 int get_aggregates(tr_scene* s, int32_t env, int32_t cap, tr_aggregate* out, int32_t* n_out)

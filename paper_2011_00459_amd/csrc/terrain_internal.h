@@ -276,6 +276,21 @@ void launch_narrow(const DevBuffers& b, const StepParams& p, const Sizes& z, hip
 void launch_canonical(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, hipStream_t s);
+// wedges of a conversion call: ranges of a wedge table
+constexpr int kMaxConvRanges = 8;
+struct WedgeSet {
+    const WedgeDev* base;
+    int n_ranges;
+    int off[kMaxConvRanges];
+    int cnt[kMaxConvRanges];
+};
+// conversion between resting solid and fluidized mass (device arrays of the
+// caller); total: one device double accumulating the converted mass
+void launch_surface(const tr_voxel_grid& g, const double* phi, double* h, float* hf, hipStream_t s);
+void launch_convert_cut(const tr_voxel_grid& g, double rho_b, const WedgeSet& ws, double* phi, const double* wc,
+                        double* mf, double* total, hipStream_t s);
+void launch_convert_deposit(const tr_voxel_grid& g, double rho_b, double w_dep, const WedgeSet& ws,
+                            const double* rho_p, double* phi, double* wc, double* mf, double* total, hipStream_t s);
 // mesoscale voxel fields (device arrays of the caller); cfl_bits: one
 // device uint64 receiving the largest Courant number's bits
 void launch_coarse_grain(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, int kernel, double R,

@@ -2677,4 +2677,151 @@ void launch_advect(const tr_voxel_grid& g, double dt, const double* u, const dou
     hipLaunchKernelGGL(k_advect, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, g, dt, u, mf_in, mf_out, cfl_bits);
 }
 
+// ---------------------------------------------------------------------------
+// Conversion between resting solid and fluidized mass: one thread per column,
+// its voxels in increasing height (the columns are independent)
+// ---------------------------------------------------------------------------
+__global__ void k_surface(tr_voxel_grid g, const double* phi, double* h, float* hf)
+{
+#pragma clang fp contract(off)
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nxy) return;
+    double z = g.origin[2];
+    for (int k = g.nz - 1; k >= 0; --k) {  // Eq. surface at the top-most voxel with solid
+        const double f = phi[(int64_t)k * nxy + c];
+        if (f > 0.0) {
+            const double zc = g.origin[2] + (k + 0.5) * g.l0;
+            z = zc + (f - 0.5) * g.l0;
+            break;
+        }
+    }
+    if (h) h[c] = z;
+    if (hf) hf[c] = (float)z;
+}
+
+// the z range of the vertical line through (x, y) inside a wedge: its lower bound
+__device__ inline bool wedge_bottom(const WedgeDev& w, double x, double y, double& zlo)
+{
+#pragma clang fp contract(off)
+    double lo = -INFINITY, hi = INFINITY;
+    if (w.n == 0) return false;
+    for (int p = 0; p < w.n; ++p) {
+        const double a = w.planes[p][2], b = w.planes[p][3] - w.planes[p][0] * x - w.planes[p][1] * y;
+        if (a > 0.0) hi = fmin(hi, b / a);
+        else if (a < 0.0) lo = fmax(lo, b / a);
+        else if (b < 0.0) return false;
+    }
+    if (!(lo <= hi) || lo == -INFINITY) return false;
+    zlo = lo;
+    return true;
+}
+
+__device__ inline bool in_wedge_set(const WedgeSet& ws, double x, double y, double z)
+{
+#pragma clang fp contract(off)
+    for (int r = 0; r < ws.n_ranges; ++r)
+        for (int k = 0; k < ws.cnt[r]; ++k) {
+            const WedgeDev& w = ws.base[ws.off[r] + k];
+            if (w.n == 0) continue;
+            bool in = true;
+            for (int p = 0; p < w.n && in; ++p)
+                if (w.planes[p][0] * x + w.planes[p][1] * y + w.planes[p][2] * z - w.planes[p][3] > 0.0) in = false;
+            if (in) return true;
+        }
+    return false;
+}
+
+__global__ void k_convert_cut(tr_voxel_grid g, double rho_b, WedgeSet ws, double* phi, const double* wc, double* mf,
+                              double* total)
+{
+#pragma clang fp contract(off)
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nxy) return;
+    const int i = (int)(c % g.nx), j = (int)(c / g.nx);
+    const double x = g.origin[0] + (i + 0.5) * g.l0, y = g.origin[1] + (j + 0.5) * g.l0;
+    double zcut = INFINITY, lo;
+    for (int r = 0; r < ws.n_ranges; ++r)
+        for (int k = 0; k < ws.cnt[r]; ++k)
+            if (wedge_bottom(ws.base[ws.off[r] + k], x, y, lo)) zcut = fmin(zcut, lo);
+    if (zcut == INFINITY) return;
+    const double V0 = g.l0 * g.l0 * g.l0;
+    double sum = 0.0;
+    for (int k = 0; k < g.nz; ++k) {
+        const int64_t id = (int64_t)k * nxy + c;
+        double t = (zcut - (g.origin[2] + k * g.l0)) / g.l0;  // occupancy below the cut
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        const double f = phi[id];
+        if (f > t) {
+            const double dm = wc[id] * rho_b * V0 * (f - t);
+            mf[id] += dm;
+            sum += dm;
+            phi[id] = t;
+        }
+    }
+    if (total && sum > 0.0) atomicAdd(total, sum);
+}
+
+__global__ void k_convert_deposit(tr_voxel_grid g, double rho_b, double w_dep, WedgeSet ws, const double* rho_p,
+                                  double* phi, double* wc, double* mf, double* total)
+{
+#pragma clang fp contract(off)
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nxy) return;
+    const int i = (int)(c % g.nx), j = (int)(c / g.nx);
+    const double x = g.origin[0] + (i + 0.5) * g.l0, y = g.origin[1] + (j + 0.5) * g.l0;
+    const double V0 = g.l0 * g.l0 * g.l0;
+    double sum = 0.0;
+    for (int k = 0; k < g.nz; ++k) {
+        const int64_t src = (int64_t)k * nxy + c;
+        const double msrc = mf[src];
+        if (!(msrc > 0.0) || rho_p[src] != 0.0 || in_wedge_set(ws, x, y, g.origin[2] + (k + 0.5) * g.l0)) continue;
+        double m = msrc;
+        mf[src] = 0.0;
+        int kk = 0;  // the first voxel of the column that is not full
+        while (kk < g.nz && phi[(int64_t)kk * nxy + c] >= 1.0) ++kk;
+        while (m > 0.0 && kk < g.nz) {
+            const int64_t id = (int64_t)kk * nxy + c;
+            const double f0 = phi[id];
+            const double cap = (1.0 - f0) * w_dep * rho_b * V0;
+            const double take = m < cap ? m : cap;
+            const double f = take == cap ? 1.0 : f0 + take / (w_dep * rho_b * V0);
+            const double before = wc[id] * rho_b * V0 * f0;
+            wc[id] = f0 > 0.0 ? (before + take) / (rho_b * V0 * f) : w_dep;
+            phi[id] = f;
+            sum += take;
+            m -= take;
+            ++kk;
+        }
+        mf[src] += m;  // a full column: the rest stays fluid
+    }
+    if (total && sum > 0.0) atomicAdd(total, sum);
+}
+
+void launch_surface(const tr_voxel_grid& g, const double* phi, double* h, float* hf, hipStream_t s)
+{
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    hipLaunchKernelGGL(k_surface, dim3((unsigned)cdiv(nxy, kBlk)), dim3(kBlk), 0, s, g, phi, h, hf);
+}
+
+void launch_convert_cut(const tr_voxel_grid& g, double rho_b, const WedgeSet& ws, double* phi, const double* wc,
+                        double* mf, double* total, hipStream_t s)
+{
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    if (total) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, total, (int64_t)1, 0.0);
+    hipLaunchKernelGGL(k_convert_cut, dim3((unsigned)cdiv(nxy, kBlk)), dim3(kBlk), 0, s, g, rho_b, ws, phi, wc, mf,
+                       total);
+}
+
+void launch_convert_deposit(const tr_voxel_grid& g, double rho_b, double w_dep, const WedgeSet& ws,
+                            const double* rho_p, double* phi, double* wc, double* mf, double* total, hipStream_t s)
+{
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    if (total) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, total, (int64_t)1, 0.0);
+    hipLaunchKernelGGL(k_convert_deposit, dim3((unsigned)cdiv(nxy, kBlk)), dim3(kBlk), 0, s, g, rho_b, w_dep, ws,
+                       rho_p, phi, wc, mf, total);
+}
+
 }  // namespace trk

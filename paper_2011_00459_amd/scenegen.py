@@ -215,3 +215,29 @@ def voxel_workload(seed=11, dims=(256, 256, 128), l0=0.05, dt=1.0 / 60.0, rho_f=
     u += rng.normal(0.0, 0.1, u.shape)
     u *= courant * l0 / dt / np.max(np.abs(u))  # a face's |u_f| is at most the larger of its two voxels'
     return dict(mf=mf, u=u, origin=(0.0, 0.0, 0.0), l0=l0, dims=dims, dt=dt)
+
+
+def voxel_terrain(seed=12, dims=(256, 256, 128), l0=0.05, fluid_share=0.05, particle_share=0.3):
+    """Resting soil on the voxel grid: columns filled to a rolling terrain
+    height (a broad mound, ripples and noise, between 40 % and 75 % of the
+    grid's height), compaction U(0.85, 1), fluidized mass (kg) in a random
+    `fluid_share` of the voxels above the surface, and a particle density
+    marker (1 where particles are, 0 elsewhere) in a random `particle_share`
+    of those.  phi: the occupancy of columns filled to h from the grid's
+    bottom.  Arrays shaped (nz, ny, nx); h (ny, nx)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = dims
+    y, x = np.meshgrid((np.arange(ny) + 0.5) / ny, (np.arange(nx) + 0.5) / nx, indexing="ij")
+    top = nz * l0
+    h = top * (0.55 + 0.12 * np.exp(-((x - 0.6) ** 2 + (y - 0.4) ** 2) / 0.05) + 0.04 * np.sin(9 * x) * np.cos(7 * y))
+    h = np.clip(h + rng.normal(0.0, 0.2 * l0, h.shape), 0.4 * top, 0.75 * top)
+    h = np.asarray(h, dtype=np.float32).astype(np.float64)  # the heights a heightfield holds
+    zb = l0 * np.arange(nz)
+    phi = np.clip((h[None, :, :] - zb[:, None, None]) / l0, 0.0, 1.0)
+    wc = rng.uniform(0.85, 1.0, phi.shape)
+    above = phi == 0.0
+    mf = np.where(above & (rng.uniform(size=phi.shape) < fluid_share), rng.uniform(0.0, 0.25, phi.shape), 0.0)
+    rho_p = np.where((mf > 0) & (rng.uniform(size=phi.shape) < particle_share), 1.0, 0.0)
+    return dict(phi=phi, wc=wc, mf=mf, rho_p=rho_p, h=h, origin=(0.0, 0.0, 0.0), l0=l0, dims=dims, rho_b=1800.0,
+                w_dep=0.85)
+

@@ -25,7 +25,8 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "set_particles", "set_mlp_weights", "get_phase_times", "set_learned_precision", "get_learn_samples",
            "mlp_forward", "mlp_grad_scratch_floats", "mlp_loss_grad", "mlp_adam_step", "set_solver_config",
            "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state", "autotune",
-           "get_rolling_impulses", "set_tool", "get_zone_wedges", "coarse_grain", "advect_fluid")
+           "get_rolling_impulses", "set_tool", "get_zone_wedges", "coarse_grain", "advect_fluid",
+           "terrain_from_voxels", "convert_cut", "convert_deposit")
 CG_KERNEL = {"heaviside": 0, "gauss": 1}
 PGS_MODE = {"grouped": 0, "per_env": 1}
 MLP_TRAINABLE = MLP_PARAMS - 12
@@ -154,6 +155,11 @@ def lib():
         L.get_rolling_impulses.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_int64)]
         L.coarse_grain.argtypes = [P, C.c_int32, C.POINTER(tr_voxel_grid), C.c_int32, C.c_double, P, P, P]
         L.advect_fluid.argtypes = [P, C.POINTER(tr_voxel_grid), C.c_double, P, P, P, C.POINTER(C.c_double)]
+        L.terrain_from_voxels.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(tr_voxel_grid), P, P]
+        L.convert_cut.argtypes = [P, C.c_int32, C.POINTER(tr_voxel_grid), C.c_double, C.c_int32,
+                                  C.POINTER(C.c_int32), dp, P, P, P, C.POINTER(C.c_double)]
+        L.convert_deposit.argtypes = [P, C.c_int32, C.POINTER(tr_voxel_grid), C.c_double, C.c_double, C.c_int32,
+                                      C.POINTER(C.c_int32), dp, P, P, P, P, C.POINTER(C.c_double)]
         for name in EXPORTS:
             if name != "get_last_error":
                 getattr(L, name).restype = C.c_int
@@ -327,14 +333,56 @@ class Scene:
         self._check(lib().coarse_grain(self.h, env, C.byref(g), CG_KERNEL[kernel], R, rho_ptr, mom_ptr, u_ptr),
                     "coarse_grain")
 
-    def advect_fluid(self, origin, l0, dims, dt, u_ptr, mf_in_ptr, mf_out_ptr):
+    def advect_fluid(self, origin, l0, dims, dt, u_ptr, mf_in_ptr, mf_out_ptr, sync=True):
         """One conserved donor-cell step of the fluidized mass on device arrays;
-        returns the largest Courant number."""
+        returns the largest Courant number (None with sync=False: the step is
+        only enqueued)."""
         g = voxel_grid(origin, l0, dims)
         cfl = C.c_double()
-        self._check(lib().advect_fluid(self.h, C.byref(g), dt, u_ptr, mf_in_ptr, mf_out_ptr, C.byref(cfl)),
-                    "advect_fluid")
-        return cfl.value
+        self._check(lib().advect_fluid(self.h, C.byref(g), dt, u_ptr, mf_in_ptr, mf_out_ptr,
+                                       C.byref(cfl) if sync else None), "advect_fluid")
+        return cfl.value if sync else None
+
+    def terrain_from_voxels(self, env, origin, l0, dims, phi_ptr, h_ptr=None, body_id=-1):
+        """Eq. surface per column into h (device, may be None) and, with a body
+        id, into that body's heightfield."""
+        g = voxel_grid(origin, l0, dims)
+        self._check(lib().terrain_from_voxels(self.h, env, body_id, C.byref(g), phi_ptr, h_ptr),
+                    "terrain_from_voxels")
+
+    @staticmethod
+    def _wedge_args(wedges):
+        if wedges is None:
+            return 0, None, None
+        counts = (C.c_int32 * max(1, len(wedges)))()
+        planes = np.zeros(max(1, len(wedges)) * 20)
+        for k, W in enumerate(wedges):
+            W = np.asarray(W, dtype=np.float64).reshape(-1, 4)
+            counts[k] = len(W)
+            planes[k * 20:k * 20 + W.size] = W.ravel()
+        return len(wedges), counts, planes
+
+    def convert_cut(self, env, origin, l0, dims, rho_b, phi_ptr, wc_ptr, mf_ptr, wedges=None, sync=True):
+        """Liberate the solid above the zones' bottoms (wedges: a list of (k x 4)
+        plane arrays, or None for the last step's predicted wedges of env's
+        tools); returns the liberated mass (None with sync=False)."""
+        g = voxel_grid(origin, l0, dims)
+        n, counts, planes = self._wedge_args(wedges)
+        tot = C.c_double()
+        self._check(lib().convert_cut(self.h, env, C.byref(g), rho_b, n, counts, _dp(planes), phi_ptr, wc_ptr, mf_ptr,
+                                      C.byref(tot) if sync else None), "convert_cut")
+        return tot.value if sync else None
+
+    def convert_deposit(self, env, origin, l0, dims, rho_b, w_dep, rho_p_ptr, phi_ptr, wc_ptr, mf_ptr, wedges=None,
+                        sync=True):
+        """Deposit particle-free fluidized mass outside the zones onto the
+        column surfaces; returns the deposited mass (None with sync=False)."""
+        g = voxel_grid(origin, l0, dims)
+        n, counts, planes = self._wedge_args(wedges)
+        tot = C.c_double()
+        self._check(lib().convert_deposit(self.h, env, C.byref(g), rho_b, w_dep, n, counts, _dp(planes), rho_p_ptr,
+                                          phi_ptr, wc_ptr, mf_ptr, C.byref(tot) if sync else None), "convert_deposit")
+        return tot.value if sync else None
 
     def get_contact_forces(self, env, body_id):
         f = np.zeros(3)
