@@ -1661,6 +1661,56 @@ double orc_convert_deposit(const orc_voxel_grid* g, double rho_b, double w_dep, 
     return total;
 }
 
+static int64_t voxel_of(const orc_voxel_grid* g, const double* x)
+{
+    const int dims[3] = {g->nx, g->ny, g->nz};
+    int c[3];
+    for (int k = 0; k < 3; ++k) {
+        double f = floor((x[k] - g->origin[k]) / g->l0);
+        if (!(f >= 0.0 && f < (double)dims[k])) return -1;
+        c[k] = (int)f;
+    }
+    return ((int64_t)c[2] * g->ny + c[1]) * g->nx + c[0];
+}
+
+double orc_grow_particles(int64_t n, const double* x, double* r, double rho, const orc_voxel_grid* g, double dt,
+                          double dprime_max, double d_max, double* mf)
+{
+    if (!grid_ok(g) || !(rho > 0.0) || !(dt >= 0.0) || !(dprime_max >= 0.0) || !(d_max > 0.0)) return -1.0;
+    const int64_t nv = (int64_t)g->nx * g->ny * g->nz;
+    double* cap_sum = (double*)calloc((size_t)nv, sizeof(double));
+    double* cap = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    const double k_m = rho * (4.0 / 3.0) * PI;  /* m = k_m r^3 */
+    const double m_max = k_m * (0.5 * d_max) * (0.5 * d_max) * (0.5 * d_max);
+    /* each particle's bound over dt, summed per voxel */
+    for (int64_t a = 0; a < n; ++a) {
+        cap[a] = 0.0;
+        int64_t v = voxel_of(g, &x[3 * a]);
+        if (v < 0) continue;
+        double m = k_m * r[a] * r[a] * r[a];
+        double c = 3.0 * m * dprime_max * dt / (2.0 * r[a]);
+        if (m + c > m_max) c = m_max > m ? m_max - m : 0.0;
+        cap[a] = c;
+        cap_sum[v] += c;
+    }
+    double total = 0.0;
+    double* used = (double*)calloc((size_t)nv, sizeof(double));
+    for (int64_t a = 0; a < n; ++a) {
+        if (cap[a] <= 0.0) continue;
+        int64_t v = voxel_of(g, &x[3 * a]);
+        double A = mf[v] > 0.0 ? mf[v] : 0.0;
+        double share = cap_sum[v] <= A ? cap[a] : cap[a] * (A / cap_sum[v]);
+        if (!(share > 0.0)) continue;  /* a particle that gains nothing keeps its radius */
+        double m = k_m * r[a] * r[a] * r[a];
+        r[a] = cbrt((m + share) / k_m);
+        used[v] += share;
+        total += share;
+    }
+    for (int64_t v = 0; v < nv; ++v) mf[v] -= used[v];
+    free(cap_sum); free(cap); free(used);
+    return total;
+}
+
 /* Eq. failure_plane: theta(phi, beta) = pi/2 - (phi + beta)/2. */
 double orc_failure_angle(double phi, double beta) { return 0.5 * PI - 0.5 * (phi + beta); }
 

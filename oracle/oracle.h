@@ -183,6 +183,17 @@ double orc_convert_cut(const orc_voxel_grid* g, double rho_b, int32_t n_wedges, 
 double orc_convert_deposit(const orc_voxel_grid* g, double rho_b, double w_dep, int32_t n_wedges,
                            const orc_wedge* wedges, const double* rho_p, double* phi, double* wc, double* mf);
 
+/* Growth of particles from the fluidized mass of their voxel (Eq. eqmotmb
+ * with the solid's share already turned into fluid): over dt a particle of
+ * mass m and diameter d may gain at most 3 m d'_max dt / d, and no more than
+ * takes it to the diameter d_max; where the voxel's fluid A falls short of
+ * the sum C of these bounds, each gains its bound times A / C.  The fluid
+ * pays for exactly what the particles gain.  x: 3n, r: n (updated), the
+ * particles' density rho; particles outside the grid do not grow.  Returns
+ * the mass grown, or -1 for a bad grid or parameter. */
+double orc_grow_particles(int64_t n, const double* x, double* r, double rho, const orc_voxel_grid* g, double dt,
+                          double dprime_max, double d_max, double* mf);
+
 /* MLP 12 -> 64 -> 64 -> 3 with SiLU, weights row-major W[out][in]. */
 typedef struct orc_mlp {
     const double* W1; const double* b1;  /* 64x12, 64 */

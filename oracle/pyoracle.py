@@ -170,6 +170,9 @@ def lib():
         L.orc_surface_heights.argtypes = [C.POINTER(VoxelGrid), dp, dp]
         L.orc_convert_cut.restype = C.c_double
         L.orc_convert_cut.argtypes = [C.POINTER(VoxelGrid), C.c_double, C.c_int32, C.POINTER(Wedge), dp, dp, dp]
+        L.orc_grow_particles.restype = C.c_double
+        L.orc_grow_particles.argtypes = [C.c_int64, dp, dp, C.c_double, C.POINTER(VoxelGrid), C.c_double, C.c_double,
+                                         C.c_double, dp]
         L.orc_convert_deposit.restype = C.c_double
         L.orc_convert_deposit.argtypes = [C.POINTER(VoxelGrid), C.c_double, C.c_double, C.c_int32, C.POINTER(Wedge),
                                           dp, dp, dp, dp]
@@ -549,3 +552,17 @@ def convert_deposit(phi, wc, mf, rho_p, wedges, origin, l0, dims, rho_b, w_dep):
         raise ValueError("bad grid or w_dep")
     sh = np.shape(phi)
     return f.reshape(sh), w.reshape(sh), m.reshape(sh), tot
+
+
+def grow_particles(x, r, rho, mf, origin, l0, dims, dt, dprime_max, d_max):
+    """Particles grow from their voxel's fluidized mass (Eq. eqmotmb); returns
+    (new radii, new mf, grown mass) (new arrays)."""
+    g = voxel_grid(origin, l0, dims)
+    x = _c64(x).reshape(-1, 3)
+    rr = _c64(r).copy()
+    m = _c64(mf).ravel().copy()
+    tot = lib().orc_grow_particles(len(x), _dp(x), _dp(rr), rho, C.byref(g), dt, dprime_max, d_max, _dp(m))
+    if tot < 0:
+        raise ValueError("bad grid or parameter")
+    return rr, m.reshape(np.shape(mf)), tot
+

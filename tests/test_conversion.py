@@ -12,7 +12,11 @@ Pins, each against geometry or arithmetic fixed outside the oracle's code:
     keeps what does not fit;
   - cut followed by deposit with no zone and no particles is the identity;
   - solid plus fluid mass is conserved to rounding on random terrain with the
-    predictor's wedges.
+    predictor's wedges;
+  - particle growth (Eq. eqmotmb): the mass bound 3 m d'_max / d is a diameter
+    rate d'_max (Taylor expansion), growth stops at d_max and outside the
+    grid, scarce fluid is used up and shared in the ratio of the bounds
+    ((r1/r2)^2), particle plus fluid mass is conserved.
 """
 import math
 
@@ -161,3 +165,63 @@ def test_mass_conserved_with_predicted_wedges():
     assert dep > 0
     assert solid_mass(phi3, wc3) + np.sum(mf3) == pytest.approx(m0, rel=1e-13)
     assert np.all(phi3 >= 0.0) and np.all(phi3 <= 1.0) and np.all(mf3 >= 0.0)
+
+
+RHO_P = 2000.0
+
+
+def pmass(r):
+    return RHO_P * 4.0 / 3.0 * math.pi * np.asarray(r) ** 3
+
+
+def test_growth_rate_is_the_diameter_rate():
+    # ample fluid: over a short dt the diameter grows by d'_max dt (to first order)
+    mf = np.zeros((DIMS[2], DIMS[1], DIMS[0]))
+    x = np.array([[0.05, 0.05, 0.55]])
+    v = (5, 5, 10)  # its voxel (k, j, i)
+    mf[v] = 10.0
+    for dt in (1e-3, 1e-5):
+        r2, mf2, grown = O.grow_particles(x, [0.02], RHO_P, mf, ORIGIN, L0, DIMS, dt, 0.1, 0.2)
+        # a mass rate 3 m d' / d is a diameter rate d': (1 + 3 e)^(1/3) = 1 + e - e^2 + ..., e = d' dt / d
+        e = 0.1 * dt / 0.04
+        assert (2 * r2[0] - 0.04) / (0.1 * dt) == pytest.approx(1.0 - e, abs=2 * e * e + 1e-9)
+        assert grown == pytest.approx(pmass(r2[0]) - pmass(0.02), rel=1e-9)
+        assert mf[v] - mf2[v] == pytest.approx(grown, rel=1e-12)
+
+
+def test_growth_stops_at_d_max_and_outside():
+    mf = np.full((DIMS[2], DIMS[1], DIMS[0]), 5.0)
+    x = np.array([[0.05, 0.05, 0.55], [5.0, 0.0, 0.0], [0.25, 0.05, 0.55]])
+    r = np.array([0.0299, 0.02, 0.01])
+    r2, mf2, grown = O.grow_particles(x, r, RHO_P, mf, ORIGIN, L0, DIMS, 1.0, 1.0, 0.06)
+    assert r2[0] == pytest.approx(0.03, rel=1e-14)   # reached d_max / 2
+    assert r2[1] == 0.02                               # outside the grid
+    assert r2[2] == pytest.approx(0.03, rel=1e-14)
+    assert grown == pytest.approx(pmass(0.03) * 2 - pmass(0.0299) - pmass(0.01), rel=1e-10)
+
+
+def test_scarce_fluid_is_shared_by_the_bounds():
+    # two particles in one voxel: the bound 3 m d' dt / d grows as r^2, so the
+    # gains are in the ratio (r1 / r2)^2 and the voxel's fluid is used up
+    mf = np.zeros((DIMS[2], DIMS[1], DIMS[0]))
+    v = (5, 5, 10)
+    mf[v] = 1e-4
+    x = np.array([[0.03, 0.02, 0.53], [0.07, 0.08, 0.57]])
+    r = np.array([0.01, 0.02])
+    r2, mf2, grown = O.grow_particles(x, r, RHO_P, mf, ORIGIN, L0, DIMS, 0.1, 0.5, 1.0)
+    g = pmass(r2) - pmass(r)
+    assert grown == pytest.approx(1e-4, rel=1e-12)
+    assert abs(mf2[v]) <= 1e-18
+    assert g[0] / g[1] == pytest.approx((0.01 / 0.02) ** 2, rel=1e-9)
+
+
+def test_growth_conserves_mass():
+    rng = np.random.default_rng(6)
+    n = 3000
+    x = rng.uniform(ORIGIN, np.add(ORIGIN, np.multiply(DIMS, L0)), (n, 3))
+    r = rng.uniform(0.01, 0.03, n)
+    mf = np.where(rng.uniform(size=(DIMS[2], DIMS[1], DIMS[0])) < 0.5, rng.uniform(0, 2e-3, (DIMS[2], DIMS[1], DIMS[0])), 0.0)
+    r2, mf2, grown = O.grow_particles(x, r, RHO_P, mf, ORIGIN, L0, DIMS, 1.0 / 60, 0.2, 0.07)
+    assert grown > 0 and np.all(r2 >= r) and np.all(r2 <= 0.035 * (1 + 1e-15))
+    assert np.all(mf2 >= -1e-18)
+    assert np.sum(pmass(r2)) + np.sum(mf2) == pytest.approx(np.sum(pmass(r)) + np.sum(mf), rel=1e-13)
