@@ -296,6 +296,20 @@ int convert_deposit(tr_scene* s, int32_t env, const tr_voxel_grid* g, double rho
                     const int32_t* counts, const double* planes, const double* rho_p, double* phi, double* wc,
                     double* mf, double* deposited);
 
+/* Growth of env's particles from the fluidized mass mf of the voxel holding
+ * each centre (Eq. eqmotmb): over dt a particle of mass m and diameter d
+ * gains at most 3 m d'_max dt / d, not past the diameter d_max; where a
+ * voxel's fluid is less than the sum of its particles' bounds, each gains its
+ * bound times their ratio.  Radii, masses and inertias change in place
+ * (radii in FP32); mf is charged exactly the mass the new radii hold.  d_max
+ * may not exceed the env's largest diameter at its last table build (the
+ * cell size of detection).  work: 2 nx ny nz device doubles of scratch.
+ * *grown, when not NULL, receives the mass grown (the call then
+ * synchronises the stream).  TR_E_INVAL for a bad env, grid or parameter,
+ * TR_E_STATE before the first step since the bodies or particles changed. */
+int grow_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double dt, double dprime_max, double d_max,
+                   double* mf, double* work, double* grown);
+
 /* One step of conserved advection of the fluidized mass per voxel (kg),
  * Eq. advection without sources: each interior face carries
  * phi = dt u_f mf_donor / l0 from the upwind voxel, u_f the mean of the two

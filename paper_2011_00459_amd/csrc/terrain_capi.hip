@@ -1203,6 +1203,25 @@ int convert_deposit(tr_scene* s, int32_t env, const tr_voxel_grid* g, double rho
     return read_total(s, deposited);
 }
 
+int grow_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double dt, double dprime_max, double d_max,
+                   double* mf, double* work, double* grown)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "grow_particles: env");
+    if (!voxel_grid_ok(g) || !mf || !work) return fail(s, TR_E_INVAL, "grow_particles: grid or arrays");
+    if (!(dt >= 0.0 && std::isfinite(dt)) || !(dprime_max >= 0.0 && std::isfinite(dprime_max)) || !(d_max > 0.0))
+        return fail(s, TR_E_INVAL, "grow_particles: dt, d'_max or d_max");
+    if (s->tables_dirty) return fail(s, TR_E_STATE, "grow_particles: no step since the bodies changed");
+    if (0.5 * d_max > s->envs[env].rmax)
+        return fail(s, TR_E_INVAL, "grow_particles: d_max exceeds the env's largest diameter");
+    if (!s->conv_total && !alloc_n(s, s->conv_total, 1)) return fail(s, TR_E_NOMEM, "grow_particles");
+    launch_grow(s->b, s->env_host[env], *g, dt, dprime_max, d_max, mf, work, grown ? s->conv_total : nullptr,
+                s->stream);
+    HIP_CHECK(s, hipGetLastError());
+    return read_total(s, grown);
+}
+
 int get_aggregates(tr_scene* s, int32_t env, int32_t cap, tr_aggregate* out, int32_t* n_out)
 {
     if (!s || !n_out || cap < 0 || (cap > 0 && !out)) return TR_E_INVAL;

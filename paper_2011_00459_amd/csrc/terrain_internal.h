@@ -291,6 +291,9 @@ void launch_convert_cut(const tr_voxel_grid& g, double rho_b, const WedgeSet& ws
                         double* mf, double* total, hipStream_t s);
 void launch_convert_deposit(const tr_voxel_grid& g, double rho_b, double w_dep, const WedgeSet& ws,
                             const double* rho_p, double* phi, double* wc, double* mf, double* total, hipStream_t s);
+// particle growth from the voxels' fluidized mass; work: 2 nx ny nz doubles
+void launch_grow(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, double dt, double dprime_max,
+                 double d_max, double* mf, double* work, double* total, hipStream_t s);
 // mesoscale voxel fields (device arrays of the caller); cfl_bits: one
 // device uint64 receiving the largest Courant number's bits
 void launch_coarse_grain(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, int kernel, double R,

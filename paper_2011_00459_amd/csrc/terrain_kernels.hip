@@ -2824,4 +2824,107 @@ void launch_convert_deposit(const tr_voxel_grid& g, double rho_b, double w_dep, 
                        rho_p, phi, wc, mf, total);
 }
 
+// ---------------------------------------------------------------------------
+// Particle growth from the fluidized mass of the particle's voxel (Eq. eqmotmb):
+// bounds summed per voxel, shares applied, the fluid charged per voxel
+// ---------------------------------------------------------------------------
+__device__ inline int64_t voxel_index(const tr_voxel_grid& g, const float4& xr)
+{
+#pragma clang fp contract(off)
+    const double x[3] = {xr.x, xr.y, xr.z};
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    int c[3];
+    for (int k = 0; k < 3; ++k) {
+        const double f = floor((x[k] - g.origin[k]) / g.l0);
+        if (!(f >= 0.0 && f < (double)dims[k])) return -1;
+        c[k] = (int)f;
+    }
+    return ((int64_t)c[2] * g.ny + c[1]) * g.nx + c[0];
+}
+
+// the most a particle may gain over dt: 3 m d' dt / d, not past d_max
+__device__ inline double growth_bound(double km, double r, double dt, double dpm, double d_max)
+{
+#pragma clang fp contract(off)
+    const double m = km * r * r * r;
+    const double m_max = km * (0.5 * d_max) * (0.5 * d_max) * (0.5 * d_max);
+    double c = 3.0 * m * dpm * dt / (2.0 * r);
+    if (m + c > m_max) c = m_max > m ? m_max - m : 0.0;
+    return c;
+}
+
+__global__ void k_grow_caps(DevBuffers b, EnvDev E, tr_voxel_grid g, double dt, double dpm, double d_max,
+                            double* cap_sum)
+{
+#pragma clang fp contract(off)
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= E.n) return;
+    const int sl = E.slot_begin + a;
+    const float4 xr = b.xr[sl];
+    const int64_t v = voxel_index(g, xr);
+    if (v < 0) return;
+    const double km = (double)b.rho[sl] * (4.0 / 3.0) * 3.14159265358979323846;
+    const double c = growth_bound(km, (double)xr.w, dt, dpm, d_max);
+    if (c > 0.0) atomicAdd(&cap_sum[v], c);
+}
+
+__global__ void k_grow_apply(DevBuffers b, EnvDev E, tr_voxel_grid g, double dt, double dpm, double d_max,
+                             const double* cap_sum, const double* mf, double* used)
+{
+#pragma clang fp contract(off)
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= E.n) return;
+    const int sl = E.slot_begin + a;
+    float4 xr = b.xr[sl];
+    const int64_t v = voxel_index(g, xr);
+    if (v < 0) return;
+    const double km = (double)b.rho[sl] * (4.0 / 3.0) * 3.14159265358979323846;
+    const double r = xr.w;
+    const double c = growth_bound(km, r, dt, dpm, d_max);
+    if (!(c > 0.0)) return;
+    const double A = mf[v] > 0.0 ? mf[v] : 0.0;
+    const double share = cap_sum[v] <= A ? c : c * (A / cap_sum[v]);
+    if (!(share > 0.0)) return;
+    const double m = km * r * r * r;
+    const float r_new = fminf((float)cbrt((m + share) / km), (float)(0.5 * d_max));
+    if (!(r_new > xr.w)) return;
+    // the fluid pays for what the FP32 radius holds
+    const double rn = r_new;
+    const double m_new = km * rn * rn * rn;
+    atomicAdd(&used[v], m_new - m);
+    xr.w = r_new;
+    b.xr[sl] = xr;
+    b.vm[sl].w = (float)(1.0 / m_new);
+    b.wi[sl].w = (float)(1.0 / (0.4 * m_new * rn * rn));
+}
+
+__global__ void k_grow_fluid(int64_t nv, double* mf, const double* used, double* total)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    const double u = used[i];
+    if (u > 0.0) {
+        mf[i] -= u;
+        if (total) atomicAdd(total, u);
+    }
+}
+
+void launch_grow(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, double dt, double dprime_max,
+                 double d_max, double* mf, double* work, double* total, hipStream_t s)
+{
+    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
+    double* cap_sum = work;
+    double* used = work + nv;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)cdiv(2 * nv, kBlk)), dim3(kBlk), 0, s, work, 2 * nv, 0.0);
+    if (total) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, total, (int64_t)1, 0.0);
+    if (E.n > 0) {
+        const unsigned nb = (unsigned)cdiv(E.n, kBlk);
+        hipLaunchKernelGGL(k_grow_caps, dim3(nb), dim3(kBlk), 0, s, b, E, g, dt, dprime_max, d_max, cap_sum);
+        hipLaunchKernelGGL(k_grow_apply, dim3(nb), dim3(kBlk), 0, s, b, E, g, dt, dprime_max, d_max, cap_sum, mf,
+                           used);
+    }
+    hipLaunchKernelGGL(k_grow_fluid, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, nv, mf, used, total);
+}
+
 }  // namespace trk
+

@@ -192,3 +192,60 @@ def test_predicted_wedges_and_terrain_update():
         if len(a):
             # FP32 heights on both sides; the cut differs by the wedges' 1e-9
             assert np.max(np.abs(a - b)) <= 1e-5 * (1.0 + np.max(np.abs(b)))
+
+
+def grow_scene(seed=5, n=3000):
+    """Particles of seeded radii and positions (FP32 on both sides) and a
+    seeded fluid field; the scene is stepped once (to build its tables) and
+    its particles then set back to the inputs."""
+    rng = np.random.default_rng(seed)
+    origin, l0, dims = (-0.5, -0.5, 0.0), 0.1, (10, 10, 8)
+    x = rng.uniform((-0.48, -0.48, 0.02), (0.48, 0.48, 0.78), (n, 3))
+    x[:20, 0] += 1.0  # outside the voxel grid: no growth
+    x = SG.fp32(x)
+    r = rng.uniform(0.008, 0.02, n)
+    r[0] = 0.024      # the env's largest radius: d_max may reach it
+    r = SG.fp32(r)
+    spec = dict(x=x, r=r, v=np.zeros((n, 3)), w=np.zeros((n, 3)), id=np.arange(n), bodies=[],
+                material=SG.material(0.5, 0.0, rho=2100.0), dt=DT, gravity=(0.0, 0.0, 0.0), max_sweeps=0, tol=0.0,
+                warm_start="cold", grid_lo=(-1.0, -1.0, -0.5), grid_hi=(2.0, 1.0, 1.5), r_ref=0.05)
+    g = T.scene_from_specs(spec)
+    g.step(1)
+    g.set_particles(0, x=x, v=np.zeros((n, 3)), w=np.zeros((n, 3)))
+    sh = (dims[2], dims[1], dims[0])
+    mf = np.where(rng.uniform(size=sh) < 0.7, rng.uniform(0.0, 2e-3, sh), 0.0)
+    return g, spec, dict(origin=origin, l0=l0, dims=dims, mf=mf)
+
+
+@pytest.mark.parametrize("dpm,d_max", [(0.05, 0.048), (2.0, 0.04)])
+def test_particle_growth_matches_oracle(dpm, d_max):
+    g, spec, w = grow_scene()
+    rho = float(np.float32(spec["material"]["rho"]))
+    nv = int(np.prod(w["dims"]))
+    mf = dev(w["mf"])
+    work = D.DeviceArray((2 * nv,), np.float64)
+    grown = g.grow_particles(0, w["origin"], w["l0"], w["dims"], DT, dpm, d_max, mf.ptr, work.ptr)
+    p = g.get_particles(0)
+    r_ref, mf_ref, grown_ref = O.grow_particles(spec["x"], spec["r"], rho, w["mf"], w["origin"], w["l0"], w["dims"],
+                                                DT, dpm, d_max)
+    assert grown_ref > 0
+    # FP32 radii: one rounding of the oracle's FP64 radius
+    assert np.all(np.abs(p["r"] - r_ref) <= 1.2e-7 * r_ref)
+    assert np.all(p["r"] >= spec["r"]) and np.all(p["r"] <= np.maximum(spec["r"], float(np.float32(0.5 * d_max))))
+    assert np.array_equal(p["r"][:20], spec["r"][:20])
+    km = rho * (4.0 / 3.0) * math.pi
+    m0, m1 = km * spec["r"] ** 3, km * p["r"] ** 3
+    got_mf = mf.get()
+    # the fluid pays exactly what the FP32 radii hold
+    assert np.sum(m1) + np.sum(got_mf) == pytest.approx(np.sum(m0) + np.sum(w["mf"]), rel=1e-13)
+    assert grown == pytest.approx(np.sum(m1 - m0), rel=1e-9)
+    assert grown == pytest.approx(grown_ref, rel=1e-5)
+    # per voxel the fluid differs by the FP32 rounding of its particles' new radii
+    cell = np.floor((spec["x"] - w["origin"]) / w["l0"]).astype(int)
+    ok = np.all((cell >= 0) & (cell < w["dims"]), axis=1)
+    vox = np.zeros(w["mf"].shape)
+    np.add.at(vox, (cell[ok, 2], cell[ok, 1], cell[ok, 0]), m1[ok])
+    assert np.all(np.abs(got_mf - mf_ref) <= 3 * 2.0 ** -23 * vox + 1e-15)
+    # d_max past the env's largest diameter is refused
+    with pytest.raises(T.TerrainError):
+        g.grow_particles(0, w["origin"], w["l0"], w["dims"], DT, dpm, 0.06, mf.ptr, work.ptr)
