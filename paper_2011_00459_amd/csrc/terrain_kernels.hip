@@ -2644,12 +2644,17 @@ __device__ inline double face_flux(const tr_voxel_grid& g, double dt, const doub
     return uf > 0.0 ? dt * uf * mf[i] / g.l0 : dt * uf * mf[j] / g.l0;
 }
 
+// Consecutive blocks of a launch go to the 8 XCDs in turn; each XCD is given
+// a contiguous run of rows instead (block b -> run b % 8, position b / 8), so
+// the neighbouring rows and planes a voxel reads were loaded into that XCD's
+// L2 shortly before.
 __global__ void k_advect(tr_voxel_grid g, double dt, const double* u, const double* mf, double* out,
-                         unsigned long long* cfl_bits)
+                         unsigned long long* cfl_bits, int blocks_per_xcd)
 {
 #pragma clang fp contract(off)
     const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t lb = (int64_t)(blockIdx.x % 8) * blocks_per_xcd + blockIdx.x / 8;
+    const int64_t i = lb * blockDim.x + threadIdx.x;
     if (i >= nv) return;
     const int64_t c[3] = {i % g.nx, (i / g.nx) % g.ny, i / ((int64_t)g.nx * g.ny)};
     const int64_t dims[3] = {g.nx, g.ny, g.nz};
@@ -2674,7 +2679,8 @@ void launch_advect(const tr_voxel_grid& g, double dt, const double* u, const dou
 {
     const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, (double*)cfl_bits, (int64_t)1, 0.0);  // bits of +0
-    hipLaunchKernelGGL(k_advect, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, g, dt, u, mf_in, mf_out, cfl_bits);
+    const int per = (int)cdiv(cdiv(nv, kBlk), 8);
+    hipLaunchKernelGGL(k_advect, dim3((unsigned)(8 * per)), dim3(kBlk), 0, s, g, dt, u, mf_in, mf_out, cfl_bits, per);
 }
 
 // ---------------------------------------------------------------------------
