@@ -1,0 +1,419 @@
+// terrain_voxels.hip -- gfx950 kernels of the mesoscale voxel workload.
+//
+// Fields on a voxel grid beside the particle step:
+//   coarse-grain      particle mass and momentum into voxel densities (FP64
+//                     atomics), velocity u = p / rho (Eq. cg_velocity)
+//   advect            conserved donor-cell advection of fluidized mass
+//                     (Eq. advection), one thread per voxel, XCD-contiguous
+//                     runs of rows
+//   convert cut       solid above the predicted zone's bottom becomes fluid
+//   convert deposit   particle-free fluid outside the zones becomes solid at
+//                     the column's surface
+//   surface           Eq. surface per column, into the terrain heightfield
+//   grow              particles grow from their voxel's fluid (Eq. eqmotmb)
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "terrain_internal.h"
+
+namespace trk {
+
+constexpr int kBlk = 256;
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Mesoscale voxel fields: coarse-graining (Eq. cg_velocity) and the conserved
+// advection of fluidized mass (Eq. advection)
+// ---------------------------------------------------------------------------
+__global__ void k_fill_f64(double* a, int64_t n, double v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// one thread per particle of the env: its mass and momentum into the voxels
+__global__ void k_coarse_grain(DevBuffers b, EnvDev E, tr_voxel_grid g, int kernel, double R, double* rho,
+                               double* mom)
+{
+#pragma clang fp contract(off)
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= E.n) return;
+    const int sl = E.slot_begin + a;
+    const float4 xf = b.xr[sl], vf = b.vm[sl];
+    const double x[3] = {xf.x, xf.y, xf.z}, v[3] = {vf.x, vf.y, vf.z};
+    const double r = xf.w;
+    const double m = (double)b.rho[sl] * (4.0 / 3.0) * 3.14159265358979323846 * r * r * r;
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    if (kernel == TR_CG_HEAVISIDE) {
+        const double V0 = g.l0 * g.l0 * g.l0;
+        int c[3];
+        for (int k = 0; k < 3; ++k) {
+            const double f = floor((x[k] - g.origin[k]) / g.l0);
+            if (!(f >= 0.0 && f < (double)dims[k])) return;
+            c[k] = (int)f;
+        }
+        const int64_t id = ((int64_t)c[2] * g.ny + c[1]) * g.nx + c[0];
+        atomicAdd(&rho[id], m / V0);
+        for (int k = 0; k < 3; ++k) atomicAdd(&mom[3 * id + k], m * v[k] / V0);
+        return;
+    }
+    const double sq = sqrt(2.0 * 3.14159265358979323846) * R;
+    const double norm = 1.0 / (sq * sq * sq);
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        const double fl = ceil((x[k] - 3.0 * R - g.origin[k]) / g.l0 - 0.5);
+        const double fh = floor((x[k] + 3.0 * R - g.origin[k]) / g.l0 - 0.5);
+        lo[k] = fl < 0.0 ? 0 : (int)fl;
+        hi[k] = fh > (double)(dims[k] - 1) ? dims[k] - 1 : (int)fh;
+    }
+    for (int kz = lo[2]; kz <= hi[2]; ++kz)
+        for (int jy = lo[1]; jy <= hi[1]; ++jy)
+            for (int ix = lo[0]; ix <= hi[0]; ++ix) {
+                const double y[3] = {g.origin[0] + (ix + 0.5) * g.l0 - x[0], g.origin[1] + (jy + 0.5) * g.l0 - x[1],
+                                     g.origin[2] + (kz + 0.5) * g.l0 - x[2]};
+                const double r2 = (y[0] * y[0] + y[1] * y[1]) + y[2] * y[2];
+                if (r2 > 9.0 * R * R) continue;
+                const double z = norm * exp(-r2 / (2.0 * R * R));
+                const int64_t id = ((int64_t)kz * g.ny + jy) * g.nx + ix;
+                atomicAdd(&rho[id], m * z);
+                for (int k = 0; k < 3; ++k) atomicAdd(&mom[3 * id + k], m * v[k] * z);
+            }
+}
+
+__global__ void k_cg_velocity(int64_t nv, const double* rho, const double* mom, double* u)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    for (int k = 0; k < 3; ++k) u[3 * i + k] = rho[i] > 0.0 ? mom[3 * i + k] / rho[i] : 0.0;
+}
+
+void launch_coarse_grain(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, int kernel, double R,
+                         double* rho, double* mom, double* u, hipStream_t s)
+{
+    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, rho, nv, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)cdiv(3 * nv, kBlk)), dim3(kBlk), 0, s, mom, 3 * nv, 0.0);
+    if (E.n > 0)
+        hipLaunchKernelGGL(k_coarse_grain, dim3((unsigned)cdiv(E.n, kBlk)), dim3(kBlk), 0, s, b, E, g, kernel, R, rho,
+                           mom);
+    if (u) hipLaunchKernelGGL(k_cg_velocity, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, nv, rho, mom, u);
+}
+
+// flux through the face between voxels i and j = i + e_d (+: from i to j),
+// the same operations as every other evaluation of that face
+__device__ inline double face_flux(const tr_voxel_grid& g, double dt, const double* u, const double* mf, int64_t i,
+                                   int64_t j, int d, double& courant)
+{
+#pragma clang fp contract(off)
+    const double uf = 0.5 * (u[3 * i + d] + u[3 * j + d]);
+    courant = fabs(uf) * dt / g.l0;
+    return uf > 0.0 ? dt * uf * mf[i] / g.l0 : dt * uf * mf[j] / g.l0;
+}
+
+// Consecutive blocks of a launch go to the 8 XCDs in turn; each XCD is given
+// a contiguous run of rows instead (block b -> run b % 8, position b / 8), so
+// the neighbouring rows and planes a voxel reads were loaded into that XCD's
+// L2 shortly before.
+__global__ void k_advect(tr_voxel_grid g, double dt, const double* u, const double* mf, double* out,
+                         unsigned long long* cfl_bits, int blocks_per_xcd)
+{
+#pragma clang fp contract(off)
+    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;  // < 2^31: 32-bit index arithmetic below
+    const int64_t lb = (int64_t)(blockIdx.x % 8) * blocks_per_xcd + blockIdx.x / 8;
+    const int64_t i = lb * blockDim.x + threadIdx.x;
+    double cmax = 0.0;
+    if (i < nv) {
+        const uint32_t i32 = (uint32_t)i, row = i32 / (uint32_t)g.nx;
+        const int64_t c[3] = {i32 - row * (uint32_t)g.nx, row % (uint32_t)g.ny, row / (uint32_t)g.ny};
+        const int64_t dims[3] = {g.nx, g.ny, g.nz};
+        const int64_t strides[3] = {1, g.nx, (int64_t)g.nx * g.ny};
+        // inflow through the lower faces, then outflow through the upper ones,
+        // each face's donors in increasing voxel order (the sum's order is that
+        // of a sweep over the faces by their lower voxel)
+        double m = mf[i], cr;
+        for (int d = 2; d >= 0; --d)
+            if (c[d] > 0) m += face_flux(g, dt, u, mf, i - strides[d], i, d, cr);
+        for (int d = 0; d < 3; ++d)
+            if (c[d] + 1 < dims[d]) {
+                m -= face_flux(g, dt, u, mf, i, i + strides[d], d, cr);
+                cmax = fmax(cmax, cr);
+            }
+        out[i] = m;
+    }
+    // the block's largest Courant number, then one atomic per block (values
+    // >= 0: their bit patterns order as the values)
+    __shared__ double wmax[kBlk / 64];
+    for (int o = 32; o > 0; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = cmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) cmax = fmax(cmax, wmax[w]);
+        if (cmax > 0.0) atomicMax(cfl_bits, (unsigned long long)__double_as_longlong(cmax));
+    }
+}
+
+void launch_advect(const tr_voxel_grid& g, double dt, const double* u, const double* mf_in, double* mf_out,
+                   unsigned long long* cfl_bits, hipStream_t s)
+{
+    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, (double*)cfl_bits, (int64_t)1, 0.0);  // bits of +0
+    const int per = (int)cdiv(cdiv(nv, kBlk), 8);
+    hipLaunchKernelGGL(k_advect, dim3((unsigned)(8 * per)), dim3(kBlk), 0, s, g, dt, u, mf_in, mf_out, cfl_bits, per);
+}
+
+// ---------------------------------------------------------------------------
+// Conversion between resting solid and fluidized mass: one thread per column,
+// its voxels in increasing height (the columns are independent)
+// ---------------------------------------------------------------------------
+__global__ void k_surface(tr_voxel_grid g, const double* phi, double* h, float* hf)
+{
+#pragma clang fp contract(off)
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nxy) return;
+    double z = g.origin[2];
+    for (int k = g.nz - 1; k >= 0; --k) {  // Eq. surface at the top-most voxel with solid
+        const double f = phi[(int64_t)k * nxy + c];
+        if (f > 0.0) {
+            const double zc = g.origin[2] + (k + 0.5) * g.l0;
+            z = zc + (f - 0.5) * g.l0;
+            break;
+        }
+    }
+    if (h) h[c] = z;
+    if (hf) hf[c] = (float)z;
+}
+
+// the z range of the vertical line through (x, y) inside a wedge: its lower bound
+__device__ inline bool wedge_bottom(const WedgeDev& w, double x, double y, double& zlo)
+{
+#pragma clang fp contract(off)
+    double lo = -INFINITY, hi = INFINITY;
+    if (w.n == 0) return false;
+    for (int p = 0; p < w.n; ++p) {
+        const double a = w.planes[p][2], b = w.planes[p][3] - w.planes[p][0] * x - w.planes[p][1] * y;
+        if (a > 0.0) hi = fmin(hi, b / a);
+        else if (a < 0.0) lo = fmax(lo, b / a);
+        else if (b < 0.0) return false;
+    }
+    if (!(lo <= hi) || lo == -INFINITY) return false;
+    zlo = lo;
+    return true;
+}
+
+__device__ inline bool in_wedge_set(const WedgeSet& ws, double x, double y, double z)
+{
+#pragma clang fp contract(off)
+    for (int r = 0; r < ws.n_ranges; ++r)
+        for (int k = 0; k < ws.cnt[r]; ++k) {
+            const WedgeDev& w = ws.base[ws.off[r] + k];
+            if (w.n == 0) continue;
+            bool in = true;
+            for (int p = 0; p < w.n && in; ++p)
+                if (w.planes[p][0] * x + w.planes[p][1] * y + w.planes[p][2] * z - w.planes[p][3] > 0.0) in = false;
+            if (in) return true;
+        }
+    return false;
+}
+
+__global__ void k_convert_cut(tr_voxel_grid g, double rho_b, WedgeSet ws, double* phi, const double* wc, double* mf,
+                              double* total)
+{
+#pragma clang fp contract(off)
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nxy) return;
+    const int i = (int)(c % g.nx), j = (int)(c / g.nx);
+    const double x = g.origin[0] + (i + 0.5) * g.l0, y = g.origin[1] + (j + 0.5) * g.l0;
+    double zcut = INFINITY, lo;
+    for (int r = 0; r < ws.n_ranges; ++r)
+        for (int k = 0; k < ws.cnt[r]; ++k)
+            if (wedge_bottom(ws.base[ws.off[r] + k], x, y, lo)) zcut = fmin(zcut, lo);
+    if (zcut == INFINITY) return;
+    const double V0 = g.l0 * g.l0 * g.l0;
+    double sum = 0.0;
+    for (int k = 0; k < g.nz; ++k) {
+        const int64_t id = (int64_t)k * nxy + c;
+        double t = (zcut - (g.origin[2] + k * g.l0)) / g.l0;  // occupancy below the cut
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        const double f = phi[id];
+        if (f > t) {
+            const double dm = wc[id] * rho_b * V0 * (f - t);
+            mf[id] += dm;
+            sum += dm;
+            phi[id] = t;
+        }
+    }
+    if (total && sum > 0.0) atomicAdd(total, sum);
+}
+
+__global__ void k_convert_deposit(tr_voxel_grid g, double rho_b, double w_dep, WedgeSet ws, const double* rho_p,
+                                  double* phi, double* wc, double* mf, double* total)
+{
+#pragma clang fp contract(off)
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nxy) return;
+    const int i = (int)(c % g.nx), j = (int)(c / g.nx);
+    const double x = g.origin[0] + (i + 0.5) * g.l0, y = g.origin[1] + (j + 0.5) * g.l0;
+    const double V0 = g.l0 * g.l0 * g.l0;
+    double sum = 0.0;
+    // the first voxel of the column that is not full: fills only raise the
+    // occupancy, so it never moves down and each search resumes from the last
+    int kfree = -1;
+    for (int k = 0; k < g.nz; ++k) {
+        const int64_t src = (int64_t)k * nxy + c;
+        const double msrc = mf[src];
+        if (!(msrc > 0.0) || rho_p[src] != 0.0 || in_wedge_set(ws, x, y, g.origin[2] + (k + 0.5) * g.l0)) continue;
+        double m = msrc;
+        mf[src] = 0.0;
+        int kk = kfree < 0 ? 0 : kfree;
+        while (kk < g.nz && phi[(int64_t)kk * nxy + c] >= 1.0) ++kk;
+        kfree = kk;
+        while (m > 0.0 && kk < g.nz) {
+            const int64_t id = (int64_t)kk * nxy + c;
+            const double f0 = phi[id];
+            const double cap = (1.0 - f0) * w_dep * rho_b * V0;
+            const double take = m < cap ? m : cap;
+            const double f = take == cap ? 1.0 : f0 + take / (w_dep * rho_b * V0);
+            const double before = wc[id] * rho_b * V0 * f0;
+            wc[id] = f0 > 0.0 ? (before + take) / (rho_b * V0 * f) : w_dep;
+            phi[id] = f;
+            sum += take;
+            m -= take;
+            ++kk;
+        }
+        mf[src] += m;  // a full column: the rest stays fluid
+    }
+    if (total && sum > 0.0) atomicAdd(total, sum);
+}
+
+void launch_surface(const tr_voxel_grid& g, const double* phi, double* h, float* hf, hipStream_t s)
+{
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    hipLaunchKernelGGL(k_surface, dim3((unsigned)cdiv(nxy, kBlk)), dim3(kBlk), 0, s, g, phi, h, hf);
+}
+
+void launch_convert_cut(const tr_voxel_grid& g, double rho_b, const WedgeSet& ws, double* phi, const double* wc,
+                        double* mf, double* total, hipStream_t s)
+{
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    if (total) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, total, (int64_t)1, 0.0);
+    hipLaunchKernelGGL(k_convert_cut, dim3((unsigned)cdiv(nxy, kBlk)), dim3(kBlk), 0, s, g, rho_b, ws, phi, wc, mf,
+                       total);
+}
+
+void launch_convert_deposit(const tr_voxel_grid& g, double rho_b, double w_dep, const WedgeSet& ws,
+                            const double* rho_p, double* phi, double* wc, double* mf, double* total, hipStream_t s)
+{
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    if (total) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, total, (int64_t)1, 0.0);
+    hipLaunchKernelGGL(k_convert_deposit, dim3((unsigned)cdiv(nxy, kBlk)), dim3(kBlk), 0, s, g, rho_b, w_dep, ws,
+                       rho_p, phi, wc, mf, total);
+}
+
+// ---------------------------------------------------------------------------
+// Particle growth from the fluidized mass of the particle's voxel (Eq. eqmotmb):
+// bounds summed per voxel, shares applied, the fluid charged per voxel
+// ---------------------------------------------------------------------------
+__device__ inline int64_t voxel_index(const tr_voxel_grid& g, const float4& xr)
+{
+#pragma clang fp contract(off)
+    const double x[3] = {xr.x, xr.y, xr.z};
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    int c[3];
+    for (int k = 0; k < 3; ++k) {
+        const double f = floor((x[k] - g.origin[k]) / g.l0);
+        if (!(f >= 0.0 && f < (double)dims[k])) return -1;
+        c[k] = (int)f;
+    }
+    return ((int64_t)c[2] * g.ny + c[1]) * g.nx + c[0];
+}
+
+// the most a particle may gain over dt: 3 m d' dt / d, not past d_max
+__device__ inline double growth_bound(double km, double r, double dt, double dpm, double d_max)
+{
+#pragma clang fp contract(off)
+    const double m = km * r * r * r;
+    const double m_max = km * (0.5 * d_max) * (0.5 * d_max) * (0.5 * d_max);
+    double c = 3.0 * m * dpm * dt / (2.0 * r);
+    if (m + c > m_max) c = m_max > m ? m_max - m : 0.0;
+    return c;
+}
+
+__global__ void k_grow_caps(DevBuffers b, EnvDev E, tr_voxel_grid g, double dt, double dpm, double d_max,
+                            double* cap_sum)
+{
+#pragma clang fp contract(off)
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= E.n) return;
+    const int sl = E.slot_begin + a;
+    const float4 xr = b.xr[sl];
+    const int64_t v = voxel_index(g, xr);
+    if (v < 0) return;
+    const double km = (double)b.rho[sl] * (4.0 / 3.0) * 3.14159265358979323846;
+    const double c = growth_bound(km, (double)xr.w, dt, dpm, d_max);
+    if (c > 0.0) atomicAdd(&cap_sum[v], c);
+}
+
+__global__ void k_grow_apply(DevBuffers b, EnvDev E, tr_voxel_grid g, double dt, double dpm, double d_max,
+                             const double* cap_sum, const double* mf, double* used)
+{
+#pragma clang fp contract(off)
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= E.n) return;
+    const int sl = E.slot_begin + a;
+    float4 xr = b.xr[sl];
+    const int64_t v = voxel_index(g, xr);
+    if (v < 0) return;
+    const double km = (double)b.rho[sl] * (4.0 / 3.0) * 3.14159265358979323846;
+    const double r = xr.w;
+    const double c = growth_bound(km, r, dt, dpm, d_max);
+    if (!(c > 0.0)) return;
+    const double A = mf[v] > 0.0 ? mf[v] : 0.0;
+    const double share = cap_sum[v] <= A ? c : c * (A / cap_sum[v]);
+    if (!(share > 0.0)) return;
+    const double m = km * r * r * r;
+    const float r_new = fminf((float)cbrt((m + share) / km), (float)(0.5 * d_max));
+    if (!(r_new > xr.w)) return;
+    // the fluid pays for what the FP32 radius holds
+    const double rn = r_new;
+    const double m_new = km * rn * rn * rn;
+    atomicAdd(&used[v], m_new - m);
+    xr.w = r_new;
+    b.xr[sl] = xr;
+    b.vm[sl].w = (float)(1.0 / m_new);
+    b.wi[sl].w = (float)(1.0 / (0.4 * m_new * rn * rn));
+}
+
+__global__ void k_grow_fluid(int64_t nv, double* mf, const double* used, double* total)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    const double u = used[i];
+    if (u > 0.0) {
+        mf[i] -= u;
+        if (total) atomicAdd(total, u);
+    }
+}
+
+void launch_grow(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, double dt, double dprime_max,
+                 double d_max, double* mf, double* work, double* total, hipStream_t s)
+{
+    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
+    double* cap_sum = work;
+    double* used = work + nv;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)cdiv(2 * nv, kBlk)), dim3(kBlk), 0, s, work, 2 * nv, 0.0);
+    if (total) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, total, (int64_t)1, 0.0);
+    if (E.n > 0) {
+        const unsigned nb = (unsigned)cdiv(E.n, kBlk);
+        hipLaunchKernelGGL(k_grow_caps, dim3(nb), dim3(kBlk), 0, s, b, E, g, dt, dprime_max, d_max, cap_sum);
+        hipLaunchKernelGGL(k_grow_apply, dim3(nb), dim3(kBlk), 0, s, b, E, g, dt, dprime_max, d_max, cap_sum, mf,
+                           used);
+    }
+    hipLaunchKernelGGL(k_grow_fluid, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, nv, mf, used, total);
+}
+
+}  // namespace trk
