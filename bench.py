@@ -40,6 +40,19 @@ PGS_TRAFFIC = {"kernels_sha256_prefix": "5d6dc0bfd68b6d0b", "bytes_per_launch": 
                "profile": "profiles/k_pgs_bed50k_hbm_traffic.md"}
 
 
+# The same for k_advect on the 256 x 256 x 128 voxel grid
+# (profiles/k_advect_voxels256_kernel_trace.md), keyed to terrain_voxels.hip.
+ADVECT_TRAFFIC = {"kernels_sha256_prefix": "c9d7008606489e9d", "bytes_per_launch": 4.757144e8,
+                  "profile": "profiles/k_advect_voxels256_kernel_trace.md"}
+
+
+def source_traffic(entry, source):
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2011_00459_amd", "csrc", source), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return entry["bytes_per_launch"] if sha == entry["kernels_sha256_prefix"] else None
+
+
 def pgs_traffic():
     import hashlib
     src = os.path.join(ROOT, "paper_2011_00459_amd", "csrc", "terrain_kernels.hip")
@@ -312,7 +325,8 @@ def bench_voxels(args):
                    "courant": cfl, "advect_device_ms": adv_ms, "mass_drift_rel": abs(m1 - m0) / m0,
                    "coarse_grain_bed": cg},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": source_traffic(ADVECT_TRAFFIC, "terrain_voxels.hip"),
                      "algorithmic_bytes_per_launch": ADVECT_BYTES * nv, "kernel": "k_advect"},
     }
     if not args.no_cpu:

@@ -54,6 +54,7 @@ struct tr_scene {
     std::vector<ShapeDev> shape_host; // last uploaded shape table
     WedgeDev* conv_wedges = nullptr;  // caller wedges of the conversion entry points (device)
     double* conv_total = nullptr;     // one device double: the converted mass
+    double* adv_bmax = nullptr;       // per-block Courant maxima of the advection
     std::vector<EnvDev> env_host;
     std::vector<std::vector<int>> zone_slots;  // per env: global zone index of each zone body
     hipEvent_t ev[5] = {};
@@ -1061,7 +1062,8 @@ int advect_fluid(tr_scene* s, const tr_voxel_grid* g, double dt, const double* u
     if (!u || !mf_in || !mf_out) return fail(s, TR_E_INVAL, "advect_fluid: null pointer");
     if (mf_in == mf_out) return fail(s, TR_E_INVAL, "advect_fluid: mf_out aliases mf_in");
     unsigned long long* bits = (unsigned long long*)s->staging;  // at least 12 floats: one uint64 fits
-    launch_advect(*g, dt, u, mf_in, mf_out, bits, s->stream);
+    if (!s->adv_bmax && !alloc_n(s, s->adv_bmax, advect_max_blocks())) return fail(s, TR_E_NOMEM, "advect_fluid");
+    launch_advect(*g, dt, u, mf_in, mf_out, s->adv_bmax, bits, s->stream);
     HIP_CHECK(s, hipGetLastError());
     if (!cfl) return TR_OK;
     unsigned long long h = 0;

@@ -13,6 +13,7 @@
 //   grow              particles grow from their voxel's fluid (Eq. eqmotmb)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "terrain_internal.h"
@@ -101,66 +102,99 @@ void launch_coarse_grain(const DevBuffers& b, const EnvDev& E, const tr_voxel_gr
     if (u) hipLaunchKernelGGL(k_cg_velocity, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, nv, rho, mom, u);
 }
 
-// flux through the face between voxels i and j = i + e_d (+: from i to j),
-// the same operations as every other evaluation of that face
-__device__ inline double face_flux(const tr_voxel_grid& g, double dt, const double* u, const double* mf, int64_t i,
-                                   int64_t j, int d, double& courant)
-{
-#pragma clang fp contract(off)
-    const double uf = 0.5 * (u[3 * i + d] + u[3 * j + d]);
-    courant = fabs(uf) * dt / g.l0;
-    return uf > 0.0 ? dt * uf * mf[i] / g.l0 : dt * uf * mf[j] / g.l0;
-}
-
 // Consecutive blocks of a launch go to the 8 XCDs in turn; each XCD is given
-// a contiguous run of rows instead (block b -> run b % 8, position b / 8), so
-// the neighbouring rows and planes a voxel reads were loaded into that XCD's
-// L2 shortly before.
-__global__ void k_advect(tr_voxel_grid g, double dt, const double* u, const double* mf, double* out,
-                         unsigned long long* cfl_bits, int blocks_per_xcd)
+// a contiguous run of 256-voxel tiles instead (block b serves run b % 8), its
+// blocks stepping through the run together, so the neighbouring rows and
+// planes a voxel reads were loaded into that XCD's L2 shortly before.  Each
+// block leaves the largest Courant number it met in bmax[b]; one block
+// reduces them (device-scope atomics to one address cost about 10 ns each).
+__global__ void k_advect(tr_voxel_grid g, double dt, const double* u, const double* mf, double* out, double* bmax,
+                         int tiles_per_run, int blocks_per_run)
 {
 #pragma clang fp contract(off)
     const int64_t nv = (int64_t)g.nx * g.ny * g.nz;  // < 2^31: 32-bit index arithmetic below
-    const int64_t lb = (int64_t)(blockIdx.x % 8) * blocks_per_xcd + blockIdx.x / 8;
-    const int64_t i = lb * blockDim.x + threadIdx.x;
+    const int run = blockIdx.x % 8, pos = blockIdx.x / 8;
     double cmax = 0.0;
-    if (i < nv) {
+    for (int t = pos; t < tiles_per_run; t += blocks_per_run) {
+        const int64_t i = ((int64_t)run * tiles_per_run + t) * blockDim.x + threadIdx.x;
+        if (i >= nv) continue;
         const uint32_t i32 = (uint32_t)i, row = i32 / (uint32_t)g.nx;
         const int64_t c[3] = {i32 - row * (uint32_t)g.nx, row % (uint32_t)g.ny, row / (uint32_t)g.ny};
         const int64_t dims[3] = {g.nx, g.ny, g.nz};
         const int64_t strides[3] = {1, g.nx, (int64_t)g.nx * g.ny};
+        // every operand loaded before any is used (a missing neighbour reads
+        // the voxel itself and its face is skipped)
+        bool lo[3], hi[3];
+        double ui[3], um[3], up[3], mm[3], mp[3];
+        const double mi = mf[i];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = c[d] > 0;
+            hi[d] = c[d] + 1 < dims[d];
+            const int64_t jm = lo[d] ? i - strides[d] : i, jp = hi[d] ? i + strides[d] : i;
+            ui[d] = u[3 * i + d];
+            um[d] = u[3 * jm + d];
+            up[d] = u[3 * jp + d];
+            mm[d] = mf[jm];
+            mp[d] = mf[jp];
+        }
         // inflow through the lower faces, then outflow through the upper ones,
         // each face's donors in increasing voxel order (the sum's order is that
-        // of a sweep over the faces by their lower voxel)
-        double m = mf[i], cr;
+        // of a sweep over the faces by their lower voxel); per face (lower
+        // voxel a, upper b): u_f = (u_a + u_b) / 2, flux dt u_f m_donor / l0
+        double m = mi;
+#pragma unroll
         for (int d = 2; d >= 0; --d)
-            if (c[d] > 0) m += face_flux(g, dt, u, mf, i - strides[d], i, d, cr);
+            if (lo[d]) {
+                const double uf = 0.5 * (um[d] + ui[d]);
+                m += dt * uf * (uf > 0.0 ? mm[d] : mi) / g.l0;
+            }
+#pragma unroll
         for (int d = 0; d < 3; ++d)
-            if (c[d] + 1 < dims[d]) {
-                m -= face_flux(g, dt, u, mf, i, i + strides[d], d, cr);
-                cmax = fmax(cmax, cr);
+            if (hi[d]) {
+                const double uf = 0.5 * (ui[d] + up[d]);
+                m -= dt * uf * (uf > 0.0 ? mi : mp[d]) / g.l0;
+                cmax = fmax(cmax, fabs(uf) * dt / g.l0);
             }
         out[i] = m;
     }
-    // the block's largest Courant number, then one atomic per block (values
-    // >= 0: their bit patterns order as the values)
     __shared__ double wmax[kBlk / 64];
     for (int o = 32; o > 0; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = cmax;
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) cmax = fmax(cmax, wmax[w]);
-        if (cmax > 0.0) atomicMax(cfl_bits, (unsigned long long)__double_as_longlong(cmax));
+        bmax[blockIdx.x] = cmax;
     }
 }
 
+// one block: the largest of n per-block maxima, as its bit pattern
+__global__ void k_max_reduce(const double* bmax, int n, unsigned long long* bits)
+{
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) v = fmax(v, bmax[k]);
+    __shared__ double wmax[kBlk / 64];
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmax(v, wmax[w]);
+        *bits = (unsigned long long)__double_as_longlong(v);
+    }
+}
+
+int advect_max_blocks() { return 8 * kAdvectBlocksPerRun; }
+
 void launch_advect(const tr_voxel_grid& g, double dt, const double* u, const double* mf_in, double* mf_out,
-                   unsigned long long* cfl_bits, hipStream_t s)
+                   double* bmax, unsigned long long* cfl_bits, hipStream_t s)
 {
     const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, (double*)cfl_bits, (int64_t)1, 0.0);  // bits of +0
-    const int per = (int)cdiv(cdiv(nv, kBlk), 8);
-    hipLaunchKernelGGL(k_advect, dim3((unsigned)(8 * per)), dim3(kBlk), 0, s, g, dt, u, mf_in, mf_out, cfl_bits, per);
+    const int tiles_per_run = (int)cdiv(cdiv(nv, kBlk), 8);
+    const int blocks_per_run = std::min(tiles_per_run, kAdvectBlocksPerRun);
+    const int nb = 8 * blocks_per_run;
+    hipLaunchKernelGGL(k_advect, dim3((unsigned)nb), dim3(kBlk), 0, s, g, dt, u, mf_in, mf_out, bmax, tiles_per_run,
+                       blocks_per_run);
+    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kBlk), 0, s, bmax, nb, cfl_bits);
 }
 
 // ---------------------------------------------------------------------------
@@ -262,32 +296,172 @@ __global__ void k_convert_deposit(tr_voxel_grid g, double rho_b, double w_dep, W
     double sum = 0.0;
     // the first voxel of the column that is not full: fills only raise the
     // occupancy, so it never moves down and each search resumes from the last
-    int kfree = -1;
-    for (int k = 0; k < g.nz; ++k) {
-        const int64_t src = (int64_t)k * nxy + c;
-        const double msrc = mf[src];
-        if (!(msrc > 0.0) || rho_p[src] != 0.0 || in_wedge_set(ws, x, y, g.origin[2] + (k + 0.5) * g.l0)) continue;
-        double m = msrc;
-        mf[src] = 0.0;
-        int kk = kfree < 0 ? 0 : kfree;
-        while (kk < g.nz && phi[(int64_t)kk * nxy + c] >= 1.0) ++kk;
-        kfree = kk;
-        while (m > 0.0 && kk < g.nz) {
-            const int64_t id = (int64_t)kk * nxy + c;
-            const double f0 = phi[id];
-            const double cap = (1.0 - f0) * w_dep * rho_b * V0;
-            const double take = m < cap ? m : cap;
-            const double f = take == cap ? 1.0 : f0 + take / (w_dep * rho_b * V0);
-            const double before = wc[id] * rho_b * V0 * f0;
-            wc[id] = f0 > 0.0 ? (before + take) / (rho_b * V0 * f) : w_dep;
-            phi[id] = f;
-            sum += take;
-            m -= take;
-            ++kk;
+    int kfree = 0;
+    int kc = -1;               // the last voxel filled, its occupancy and compaction as written
+    double fc = 0.0, wcc = 0.0;
+    // the column is read kChunk voxels at a time (independent loads in
+    // flight); a voxel's own deposit changes only phi and wc, and mf of that
+    // voxel alone, so the values read ahead stay current
+    constexpr int kChunk = 8;
+    for (int k0 = 0; k0 < g.nz; k0 += kChunk) {
+        double mc[kChunk], rc[kChunk];
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) {
+            const bool in = k0 + t < g.nz;
+            mc[t] = in ? mf[(int64_t)(k0 + t) * nxy + c] : 0.0;
+            rc[t] = in ? rho_p[(int64_t)(k0 + t) * nxy + c] : 0.0;
         }
-        mf[src] += m;  // a full column: the rest stays fluid
+        for (int t = 0; t < kChunk; ++t) {
+            const int k = k0 + t;
+            if (!(mc[t] > 0.0) || rc[t] != 0.0 || in_wedge_set(ws, x, y, g.origin[2] + (k + 0.5) * g.l0)) continue;
+            double m = mc[t];
+            int kk = kfree;
+            // the last voxel filled is held as written: when it is the first
+            // non-full voxel no search is needed
+            for (bool found = kk == kc && fc < 1.0; !found && kk < g.nz;) {  // kChunk at a time
+                double pc[kChunk];
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) pc[q] = kk + q < g.nz ? phi[(int64_t)(kk + q) * nxy + c] : 0.0;
+                int q = 0;
+                while (q < kChunk && pc[q] >= 1.0) ++q;
+                found = q < kChunk;
+                kk += q;
+            }
+            kk = kk < g.nz ? kk : g.nz;
+            kfree = kk;
+            while (m > 0.0 && kk < g.nz) {
+                const int64_t id = (int64_t)kk * nxy + c;
+                const bool held = kk == kc;
+                const double f0 = held ? fc : phi[id];
+                const double w0 = held ? wcc : wc[id];
+                const double cap = (1.0 - f0) * w_dep * rho_b * V0;
+                const double take = m < cap ? m : cap;
+                const double f = take == cap ? 1.0 : f0 + take / (w_dep * rho_b * V0);
+                const double before = w0 * rho_b * V0 * f0;
+                const double wn = f0 > 0.0 ? (before + take) / (rho_b * V0 * f) : w_dep;
+                wc[id] = wn;
+                phi[id] = f;
+                kc = kk;
+                fc = f;
+                wcc = wn;
+                sum += take;
+                m -= take;
+                ++kk;
+            }
+            // every voxel below the last one filled is full
+            if (kc >= kfree) kfree = fc < 1.0 ? kc : kc + 1;
+            mf[(int64_t)k * nxy + c] = 0.0 + m;  // what finds the column full stays fluid
+        }
     }
     if (total && sum > 0.0) atomicAdd(total, sum);
+}
+
+// The deposit with one wave per column (columns of at most kDepositNz
+// voxels): the wave loads the column's occupancy, compaction and fluid into
+// LDS and marks the voxels whose fluid falls (in parallel, 64 at a time); one
+// lane then takes the marked voxels in increasing height through the same
+// fills as the per-thread kernel, on LDS; the wave writes back what changed.
+constexpr int kDepositNz = 256;
+constexpr int kDepositWaves = kBlk / 64;
+
+__global__ void __launch_bounds__(kBlk) k_convert_deposit_col(tr_voxel_grid g, double rho_b, double w_dep, WedgeSet ws,
+                                                              const double* rho_p, double* phi, double* wc,
+                                                              double* mf, double* total)
+{
+#pragma clang fp contract(off)
+    __shared__ double sphi[kDepositWaves][kDepositNz], swc[kDepositWaves][kDepositNz], smf[kDepositWaves][kDepositNz];
+    __shared__ unsigned long long smask[kDepositWaves][kDepositNz / 64];
+    __shared__ int srange[kDepositWaves][2];
+    __shared__ double ssum[kDepositWaves];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t c = (int64_t)blockIdx.x * kDepositWaves + wv;
+    const bool live = c < nxy;  // (uniform across the wave)
+    double* P = sphi[wv];
+    double* W = swc[wv];
+    double* M = smf[wv];
+    const int nz = g.nz;
+    const int nchunk = (nz + 63) / 64;
+    if (live) {
+        const int i = (int)(c % g.nx), j = (int)(c / g.nx);
+        const double x = g.origin[0] + (i + 0.5) * g.l0, y = g.origin[1] + (j + 0.5) * g.l0;
+        for (int q = 0; q < nchunk; ++q) {
+            const int k = q * 64 + lane;
+            bool cand = false;
+            if (k < nz) {
+                const int64_t id = (int64_t)k * nxy + c;
+                const double m = mf[id];
+                P[k] = phi[id];
+                W[k] = wc[id];
+                M[k] = m;
+                cand = m > 0.0 && rho_p[id] == 0.0 && !in_wedge_set(ws, x, y, g.origin[2] + (k + 0.5) * g.l0);
+            }
+            const unsigned long long b = __ballot(cand);
+            if (lane == 0) smask[wv][q] = b;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (live && lane == 0) {
+        const double V0 = g.l0 * g.l0 * g.l0;
+        double sum = 0.0;
+        int kfree = 0, klo = nz, khi = -1;
+        for (int q = 0; q < nchunk; ++q) {
+            unsigned long long mk = smask[wv][q];
+            while (mk) {
+                const int k = q * 64 + (__ffsll((long long)mk) - 1);
+                mk &= mk - 1;
+                double m = M[k];
+                int kk = kfree;
+                while (kk < nz && P[kk] >= 1.0) ++kk;  // the first voxel that is not full
+                kfree = kk;
+                klo = kk < klo ? kk : klo;
+                while (m > 0.0 && kk < nz) {
+                    const double f0 = P[kk];
+                    const double cap = (1.0 - f0) * w_dep * rho_b * V0;
+                    const double take = m < cap ? m : cap;
+                    const double f = take == cap ? 1.0 : f0 + take / (w_dep * rho_b * V0);
+                    const double before = W[kk] * rho_b * V0 * f0;
+                    W[kk] = f0 > 0.0 ? (before + take) / (rho_b * V0 * f) : w_dep;
+                    P[kk] = f;
+                    khi = kk > khi ? kk : khi;
+                    sum += take;
+                    m -= take;
+                    ++kk;
+                }
+                M[k] = 0.0 + m;  // what finds the column full stays fluid
+            }
+        }
+        srange[wv][0] = klo;
+        srange[wv][1] = khi;
+        ssum[wv] = sum;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (live) {
+        const int klo = srange[wv][0], khi = srange[wv][1];
+        for (int q = 0; q < nchunk; ++q) {
+            const int k = q * 64 + lane;
+            if (k >= nz) continue;
+            const int64_t id = (int64_t)k * nxy + c;
+            if ((smask[wv][q] >> lane) & 1ull) mf[id] = M[k];
+            if (k >= klo && k <= khi) {
+                phi[id] = P[k];
+                wc[id] = W[k];
+            }
+        }
+    }
+    if (total) {  // one atomic per block
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kDepositWaves; ++w)
+                if ((int64_t)blockIdx.x * kDepositWaves + w < nxy) s += ssum[w];
+            if (s > 0.0) atomicAdd(total, s);
+        }
+    }
 }
 
 void launch_surface(const tr_voxel_grid& g, const double* phi, double* h, float* hf, hipStream_t s)
@@ -310,8 +484,12 @@ void launch_convert_deposit(const tr_voxel_grid& g, double rho_b, double w_dep, 
 {
     const int64_t nxy = (int64_t)g.nx * g.ny;
     if (total) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, total, (int64_t)1, 0.0);
-    hipLaunchKernelGGL(k_convert_deposit, dim3((unsigned)cdiv(nxy, kBlk)), dim3(kBlk), 0, s, g, rho_b, w_dep, ws,
-                       rho_p, phi, wc, mf, total);
+    if (g.nz <= kDepositNz)
+        hipLaunchKernelGGL(k_convert_deposit_col, dim3((unsigned)cdiv(nxy, kDepositWaves)), dim3(kBlk), 0, s, g, rho_b,
+                           w_dep, ws, rho_p, phi, wc, mf, total);
+    else
+        hipLaunchKernelGGL(k_convert_deposit, dim3((unsigned)cdiv(nxy, kBlk)), dim3(kBlk), 0, s, g, rho_b, w_dep, ws,
+                           rho_p, phi, wc, mf, total);
 }
 
 // ---------------------------------------------------------------------------

@@ -106,9 +106,11 @@ def check_exact(got, ref):
     assert got["dep"] == pytest.approx(ref["dep"], rel=1e-12, abs=1e-12)
 
 
-@pytest.mark.parametrize("seed", [1, 2])
-def test_cut_deposit_surface_bit_exact_on_a_ragged_grid(seed):
-    st, wedges = ragged_state(seed)
+# columns of up to 256 voxels take the wave-per-column deposit, taller ones the
+# thread-per-column one
+@pytest.mark.parametrize("seed,dims", [(1, (37, 29, 23)), (2, (37, 29, 23)), (3, (9, 7, 300))])
+def test_cut_deposit_surface_bit_exact_on_a_ragged_grid(seed, dims):
+    st, wedges = ragged_state(seed, dims)
     got = run_gpu(any_scene(), st, wedges)
     ref = run_oracle(st, wedges)
     assert ref["lib"] > 1.0 and ref["dep"] > 0.1
