@@ -1711,6 +1711,41 @@ double orc_grow_particles(int64_t n, const double* x, double* r, double rho, con
     return total;
 }
 
+int64_t orc_form_particles(const orc_voxel_grid* g, double rho, double d_min, double d_max, double phi_max,
+                           int32_t n_wedges, const orc_wedge* wedges, const double* rho_p, const double* u,
+                           double* mf, int64_t cap, int64_t* voxel, double* x, double* v, double* r)
+{
+    if (!grid_ok(g) || !(rho > 0.0) || !(d_min > 0.0) || !(d_max >= d_min) || !(phi_max > 0.0) || n_wedges < 0)
+        return -1;
+    const int64_t nxy = (int64_t)g->nx * g->ny;
+    const double V0 = g->l0 * g->l0 * g->l0;
+    const double k_m = rho * PI / 6.0;  /* m = k_m d^3 */
+    const double m_min = k_m * d_min * d_min * d_min;
+    int64_t n = 0;
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                const int64_t id = (int64_t)k * nxy + (int64_t)j * g->nx + i;
+                if (!(mf[id] >= m_min)) continue;
+                double c[3] = {g->origin[0] + (i + 0.5) * g->l0, g->origin[1] + (j + 0.5) * g->l0,
+                               g->origin[2] + (k + 0.5) * g->l0};
+                if (!inside_any_wedge(n_wedges, wedges, c)) continue;
+                double d = cbrt(mf[id] / k_m);
+                if (d > d_max) d = d_max;
+                double m = k_m * d * d * d;
+                /* room for the new particle: particle volume fraction after it */
+                if (rho_p[id] / rho + m / (rho * V0) > phi_max) continue;
+                mf[id] -= m;
+                if (n < cap) {
+                    voxel[n] = id;
+                    for (int q = 0; q < 3; ++q) { x[3 * n + q] = c[q]; v[3 * n + q] = u[3 * id + q]; }
+                    r[n] = 0.5 * d;
+                }
+                ++n;
+            }
+    return n;
+}
+
 /* Eq. failure_plane: theta(phi, beta) = pi/2 - (phi + beta)/2. */
 double orc_failure_angle(double phi, double beta) { return 0.5 * PI - 0.5 * (phi + beta); }
 

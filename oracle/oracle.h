@@ -194,6 +194,19 @@ double orc_convert_deposit(const orc_voxel_grid* g, double rho_b, double w_dep, 
 double orc_grow_particles(int64_t n, const double* x, double* r, double rho, const orc_voxel_grid* g, double dt,
                           double dprime_max, double d_max, double* mf);
 
+/* Forming new particles from fluidized mass inside the zones: a voxel whose
+ * centre is inside a wedge, whose fluid mf is at least the mass of a
+ * particle of diameter d_min (density rho), and whose particle volume
+ * fraction rho_p / rho (rho_p the coarse-grained particle mass density)
+ * leaves room for one more particle below phi_max, forms one particle of
+ * diameter min(d_max, the diameter holding all its fluid) at its centre with
+ * the voxel velocity u; the voxel's fluid pays its mass.  Writes up to cap
+ * particles in increasing voxel order (voxel index, centre 3, velocity 3,
+ * radius), returns their count (-1 for a bad grid or parameter). */
+int64_t orc_form_particles(const orc_voxel_grid* g, double rho, double d_min, double d_max, double phi_max,
+                           int32_t n_wedges, const orc_wedge* wedges, const double* rho_p, const double* u,
+                           double* mf, int64_t cap, int64_t* voxel, double* x, double* v, double* r);
+
 /* MLP 12 -> 64 -> 64 -> 3 with SiLU, weights row-major W[out][in]. */
 typedef struct orc_mlp {
     const double* W1; const double* b1;  /* 64x12, 64 */

@@ -170,6 +170,10 @@ def lib():
         L.orc_surface_heights.argtypes = [C.POINTER(VoxelGrid), dp, dp]
         L.orc_convert_cut.restype = C.c_double
         L.orc_convert_cut.argtypes = [C.POINTER(VoxelGrid), C.c_double, C.c_int32, C.POINTER(Wedge), dp, dp, dp]
+        L.orc_form_particles.restype = C.c_int64
+        L.orc_form_particles.argtypes = [C.POINTER(VoxelGrid), C.c_double, C.c_double, C.c_double, C.c_double,
+                                         C.c_int32, C.POINTER(Wedge), dp, dp, dp, C.c_int64,
+                                         C.POINTER(C.c_int64), dp, dp, dp]
         L.orc_grow_particles.restype = C.c_double
         L.orc_grow_particles.argtypes = [C.c_int64, dp, dp, C.c_double, C.POINTER(VoxelGrid), C.c_double, C.c_double,
                                          C.c_double, dp]
@@ -565,4 +569,22 @@ def grow_particles(x, r, rho, mf, origin, l0, dims, dt, dprime_max, d_max):
     if tot < 0:
         raise ValueError("bad grid or parameter")
     return rr, m.reshape(np.shape(mf)), tot
+
+
+def form_particles(mf, rho_p, u, wedges, origin, l0, dims, rho, d_min, d_max, phi_max):
+    """New particles from the fluid inside the zones; returns (new mf, dict of
+    voxel, x, v, r arrays in increasing voxel order)."""
+    g = voxel_grid(origin, l0, dims)
+    m = _c64(mf).ravel().copy()
+    rp = _c64(rho_p).ravel()
+    uu = _c64(u).reshape(-1, 3)
+    cap = int(np.count_nonzero(m > 0)) + 1
+    vox = np.zeros(cap, dtype=np.int64)
+    x = np.zeros((cap, 3)); v = np.zeros((cap, 3)); r = np.zeros(cap)
+    n = lib().orc_form_particles(C.byref(g), rho, d_min, d_max, phi_max, len(wedges), _wedge_array(wedges), _dp(rp),
+                                 _dp(uu), _dp(m), cap, vox.ctypes.data_as(C.POINTER(C.c_int64)), _dp(x), _dp(v),
+                                 _dp(r))
+    if n < 0:
+        raise ValueError("bad grid or parameter")
+    return m.reshape(np.shape(mf)), dict(voxel=vox[:n], x=x[:n], v=v[:n], r=r[:n])
 

@@ -225,3 +225,40 @@ def test_growth_conserves_mass():
     assert grown > 0 and np.all(r2 >= r) and np.all(r2 <= 0.035 * (1 + 1e-15))
     assert np.all(mf2 >= -1e-18)
     assert np.sum(pmass(r2)) + np.sum(mf2) == pytest.approx(np.sum(pmass(r)) + np.sum(mf), rel=1e-13)
+
+
+def test_particle_formation():
+    # a zone over the grid's middle; fluid in four voxels of it and one outside
+    W = np.array([[1.0, 0, 0, 0.5], [-1.0, 0, 0, 0.5], [0, 1.0, 0, 0.3], [0, -1.0, 0, 0.3], [0, 0, 1.0, 1.0]])
+    sh = (DIMS[2], DIMS[1], DIMS[0])
+    mf = np.zeros(sh)
+    rho_p = np.zeros(sh)
+    u = np.zeros(sh + (3,))
+    d_min, d_max, phi_max = 0.02, 0.05, 0.6
+    m_of = lambda d: RHO_P * math.pi / 6 * d ** 3
+    mf[2, 5, 10] = 3 * m_of(d_max)           # plenty: a d_max particle
+    u[2, 5, 10] = (0.1, -0.2, 0.3)
+    mf[3, 5, 10] = 0.5 * (m_of(d_min) + m_of(d_max))  # all of it in one particle
+    mf[4, 5, 10] = 0.9 * m_of(d_min)         # too little
+    mf[5, 5, 10] = m_of(d_max)
+    rho_p[5, 5, 10] = 0.55 * RHO_P           # no room: 0.55 + 0.065 > 0.6
+    mf[2, 5, 20] = m_of(d_max)               # outside the zone (x = 1.05)
+    mf2, P = O.form_particles(mf, rho_p, u, [W], ORIGIN, L0, DIMS, RHO_P, d_min, d_max, phi_max)
+    assert len(P["r"]) == 2
+    vox = [np.ravel_multi_index(t, sh) for t in ((2, 5, 10), (3, 5, 10))]
+    assert list(P["voxel"]) == vox
+    assert P["r"][0] == pytest.approx(0.5 * d_max, rel=1e-15)
+    assert np.allclose(P["x"][0], [ORIGIN[0] + 10.5 * L0, ORIGIN[1] + 5.5 * L0, ORIGIN[2] + 2.5 * L0], rtol=0, atol=1e-15)
+    assert np.allclose(P["v"][0], [0.1, -0.2, 0.3], rtol=0, atol=0)
+    assert mf2[2, 5, 10] == pytest.approx(2 * m_of(d_max), rel=1e-14)
+    assert m_of(2 * P["r"][1]) == pytest.approx(mf[3, 5, 10], rel=1e-14) and abs(mf2[3, 5, 10]) <= 1e-15
+    for t in ((4, 5, 10), (5, 5, 10), (2, 5, 20)):
+        assert mf2[t] == mf[t]
+    # conservation on a random field
+    rng = np.random.default_rng(8)
+    mfr = np.where(rng.uniform(size=sh) < 0.3, rng.uniform(0, 2 * m_of(d_max), sh), 0.0)
+    rpr = np.where(rng.uniform(size=sh) < 0.3, rng.uniform(0, 0.6 * RHO_P, sh), 0.0)
+    mf3, P3 = O.form_particles(mfr, rpr, np.zeros(sh + (3,)), [W], ORIGIN, L0, DIMS, RHO_P, d_min, d_max, phi_max)
+    assert len(P3["r"]) > 10 and np.all(np.diff(P3["voxel"]) > 0)
+    assert np.all((2 * P3["r"] >= d_min * (1 - 1e-12)) & (2 * P3["r"] <= d_max))
+    assert np.sum(mf3) + np.sum(m_of(2 * P3["r"])) == pytest.approx(np.sum(mfr), rel=1e-13)
