@@ -310,6 +310,22 @@ int convert_deposit(tr_scene* s, int32_t env, const tr_voxel_grid* g, double rho
 int grow_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double dt, double dprime_max, double d_max,
                    double* mf, double* work, double* grown);
 
+/* Forming new particles in env from the fluidized mass inside the zones: a
+ * voxel whose centre is inside a wedge, whose fluid mf is at least the mass
+ * of a particle of diameter d_min (the material density), and whose particle
+ * volume fraction rho_p / rho (rho_p: the coarse-grained particle mass
+ * density) stays at or below phi_max with one more particle, forms one
+ * particle at its centre with the voxel velocity u (3 per voxel); its
+ * diameter holds all the voxel's fluid, capped at d_max; the fluid is charged
+ * exactly the mass the FP32 radius holds.  The particles are appended in
+ * increasing voxel order as add_particles does (the next step rebuilds the
+ * tables); *n_formed receives their count.  Wedges as for convert_cut.  No
+ * change and TR_E_CAPACITY when more than max_new particles, or more than the
+ * env can hold, would form; TR_E_INVAL for bad arguments. */
+int form_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double d_min, double d_max, double phi_max,
+                   int32_t n_wedges, const int32_t* counts, const double* planes, const double* rho_p,
+                   const double* u, double* mf, int64_t max_new, int64_t* n_formed);
+
 /* One step of conserved advection of the fluidized mass per voxel (kg),
  * Eq. advection without sources: each interior face carries
  * phi = dt u_f mf_donor / l0 from the upwind voxel, u_f the mean of the two

@@ -55,6 +55,8 @@ struct tr_scene {
     WedgeDev* conv_wedges = nullptr;  // caller wedges of the conversion entry points (device)
     double* conv_total = nullptr;     // one device double: the converted mass
     double* adv_bmax = nullptr;       // per-block Courant maxima of the advection
+    FormEntry* form_list = nullptr;   // candidates of form_particles
+    int64_t form_cap = 0;
     std::vector<EnvDev> env_host;
     std::vector<std::vector<int>> zone_slots;  // per env: global zone index of each zone body
     hipEvent_t ev[5] = {};
@@ -1203,6 +1205,56 @@ int convert_deposit(tr_scene* s, int32_t env, const tr_voxel_grid* g, double rho
     launch_convert_deposit(*g, rho_b, w_dep, ws, rho_p, phi, wc, mf, deposited ? s->conv_total : nullptr, s->stream);
     HIP_CHECK(s, hipGetLastError());
     return read_total(s, deposited);
+}
+
+int form_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double d_min, double d_max, double phi_max,
+                   int32_t n_wedges, const int32_t* counts, const double* planes, const double* rho_p,
+                   const double* u, double* mf, int64_t max_new, int64_t* n_formed)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (n_formed) *n_formed = 0;
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "form_particles: env");
+    if (!voxel_grid_ok(g) || !rho_p || !u || !mf) return fail(s, TR_E_INVAL, "form_particles: grid or arrays");
+    if (!(d_min > 0.0) || !(d_max >= d_min) || !std::isfinite(d_max) || !(phi_max > 0.0) || max_new < 0)
+        return fail(s, TR_E_INVAL, "form_particles: d_min, d_max, phi_max or max_new");
+    WedgeSet ws;
+    int rc = conversion_wedges(s, env, n_wedges, counts, planes, ws, "form_particles");
+    if (rc != TR_OK) return rc;
+    const int64_t room = std::min<int64_t>(max_new, s->desc.cap_particles - s->envs[env].n);
+    if (room > s->form_cap) {
+        dfree(s, s->form_list);
+        s->form_list = nullptr;
+        s->form_cap = 0;
+        if (!alloc_n(s, s->form_list, room)) return fail(s, TR_E_NOMEM, "form_particles: list");
+        s->form_cap = room;
+    }
+    if (!s->conv_total && !alloc_n(s, s->conv_total, 1)) return fail(s, TR_E_NOMEM, "form_particles");
+    unsigned long long* cnt = (unsigned long long*)s->conv_total;
+    const double rho = s->desc.material.rho;
+    launch_form_candidates(*g, rho, d_min, d_max, phi_max, ws, rho_p, u, mf, s->form_list, cnt, room, s->stream);
+    HIP_CHECK(s, hipGetLastError());
+    unsigned long long n = 0;
+    HIP_CHECK(s, hipMemcpyAsync(&n, cnt, sizeof(n), hipMemcpyDeviceToHost, s->stream));
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    if ((int64_t)n > room) return fail(s, TR_E_CAPACITY, "form_particles: more particles would form than allowed");
+    if (n == 0) return TR_OK;
+    std::vector<FormEntry> e(n);
+    HIP_CHECK(s, hipMemcpy(e.data(), s->form_list, sizeof(FormEntry) * n, hipMemcpyDeviceToHost));
+    std::sort(e.begin(), e.end(), [](const FormEntry& a, const FormEntry& b) { return a.voxel < b.voxel; });
+    std::vector<double> pos(3 * n), vel(3 * n), rad(n);
+    for (size_t a = 0; a < n; ++a) {
+        for (int q = 0; q < 3; ++q) { pos[3 * a + q] = e[a].x[q]; vel[3 * a + q] = e[a].v[q]; }
+        rad[a] = (double)(float)e[a].r;
+    }
+    int64_t first = 0;
+    rc = add_particles(s, env, (int64_t)n, pos.data(), vel.data(), rad.data(), nullptr, &first);
+    if (rc != TR_OK) return rc;
+    launch_form_pay(s->form_list, (int64_t)n, rho, mf, s->stream);
+    HIP_CHECK(s, hipGetLastError());
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    if (n_formed) *n_formed = (int64_t)n;
+    return TR_OK;
 }
 
 int grow_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double dt, double dprime_max, double d_max,

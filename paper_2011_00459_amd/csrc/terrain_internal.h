@@ -291,6 +291,18 @@ void launch_convert_cut(const tr_voxel_grid& g, double rho_b, const WedgeSet& ws
                         double* mf, double* total, hipStream_t s);
 void launch_convert_deposit(const tr_voxel_grid& g, double rho_b, double w_dep, const WedgeSet& ws,
                             const double* rho_p, double* phi, double* wc, double* mf, double* total, hipStream_t s);
+// forming particles from fluid inside the zones: candidates into list (8
+// doubles each: voxel, centre 3, velocity 3, radius), *count their number
+// (all of them are counted, at most cap written); then the fluid pays
+struct FormEntry {
+    double voxel;  // index, exact in a double below 2^53
+    double x[3], v[3];
+    double r;
+};
+void launch_form_candidates(const tr_voxel_grid& g, double rho, double d_min, double d_max, double phi_max,
+                            const WedgeSet& ws, const double* rho_p, const double* u, const double* mf,
+                            FormEntry* list, unsigned long long* count, int64_t cap, hipStream_t s);
+void launch_form_pay(const FormEntry* list, int64_t n, double rho, double* mf, hipStream_t s);
 // particle growth from the voxels' fluidized mass; work: 2 nx ny nz doubles
 void launch_grow(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, double dt, double dprime_max,
                  double d_max, double* mf, double* work, double* total, hipStream_t s);

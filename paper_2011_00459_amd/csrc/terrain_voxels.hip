@@ -594,4 +594,65 @@ void launch_grow(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, d
     hipLaunchKernelGGL(k_grow_fluid, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, nv, mf, used, total);
 }
 
+// ---------------------------------------------------------------------------
+// Forming new particles from the fluid inside the zones: one thread per
+// voxel marks a candidate (the list's order is fixed by the host afterwards),
+// then the fluid of each listed voxel pays the mass its FP32 radius holds
+// ---------------------------------------------------------------------------
+__global__ void k_form_candidates(tr_voxel_grid g, double rho, double d_min, double d_max, double phi_max, WedgeSet ws,
+                                  const double* rho_p, const double* u, const double* mf, FormEntry* list,
+                                  unsigned long long* count, int64_t cap)
+{
+#pragma clang fp contract(off)
+    const int64_t nxy = (int64_t)g.nx * g.ny, nv = nxy * g.nz;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nv) return;
+    const double km = rho * 3.14159265358979323846 / 6.0;  // m = km d^3
+    const double m_min = km * d_min * d_min * d_min;
+    const double f = mf[id];
+    if (!(f >= m_min)) return;
+    const int k = (int)(id / nxy), j = (int)((id % nxy) / g.nx), i = (int)(id % g.nx);
+    const double c[3] = {g.origin[0] + (i + 0.5) * g.l0, g.origin[1] + (j + 0.5) * g.l0, g.origin[2] + (k + 0.5) * g.l0};
+    if (!in_wedge_set(ws, c[0], c[1], c[2])) return;
+    double d = cbrt(f / km);
+    d = d > d_max ? d_max : d;
+    const double m = km * d * d * d;
+    const double V0 = g.l0 * g.l0 * g.l0;
+    if (rho_p[id] / rho + m / (rho * V0) > phi_max) return;  // no room for one more particle
+    const unsigned long long slot = atomicAdd(count, 1ull);
+    if ((int64_t)slot >= cap) return;
+    FormEntry e;
+    e.voxel = (double)id;
+    for (int q = 0; q < 3; ++q) { e.x[q] = c[q]; e.v[q] = u[3 * id + q]; }
+    e.r = 0.5 * d;
+    list[slot] = e;
+}
+
+// the library's particle mass: FP32 density and radius, FP64 arithmetic
+__global__ void k_form_pay(const FormEntry* list, int64_t n, double rho, double* mf)
+{
+#pragma clang fp contract(off)
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const double r = (double)(float)list[a].r;
+    const double m = (double)(float)rho * (4.0 / 3.0) * 3.14159265358979323846 * r * r * r;
+    mf[(int64_t)list[a].voxel] -= m;  // one entry per voxel
+}
+
+void launch_form_candidates(const tr_voxel_grid& g, double rho, double d_min, double d_max, double phi_max,
+                            const WedgeSet& ws, const double* rho_p, const double* u, const double* mf,
+                            FormEntry* list, unsigned long long* count, int64_t cap, hipStream_t s)
+{
+    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, (double*)count, (int64_t)1, 0.0);  // bits of 0
+    hipLaunchKernelGGL(k_form_candidates, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, g, rho, d_min, d_max,
+                       phi_max, ws, rho_p, u, mf, list, count, cap);
+}
+
+void launch_form_pay(const FormEntry* list, int64_t n, double rho, double* mf, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_form_pay, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, s, list, n, rho, mf);
+}
+
 }  // namespace trk
+

@@ -251,3 +251,45 @@ def test_particle_growth_matches_oracle(dpm, d_max):
     # d_max past the env's largest diameter is refused
     with pytest.raises(T.TerrainError):
         g.grow_particles(0, w["origin"], w["l0"], w["dims"], DT, dpm, 0.06, mf.ptr, work.ptr)
+
+
+def test_particle_formation_matches_oracle():
+    rng = np.random.default_rng(21)
+    origin, l0, dims = (-0.5, -0.5, 0.0), 0.1, (10, 10, 8)
+    sh = (dims[2], dims[1], dims[0])
+    m_of = lambda d: 2100.0 * math.pi / 6 * d ** 3
+    d_min, d_max, phi_max = 0.02, 0.05, 0.6
+    mf = np.where(rng.uniform(size=sh) < 0.4, rng.uniform(0, 2.5 * m_of(d_max), sh), 0.0)
+    rho_p = np.where(rng.uniform(size=sh) < 0.3, rng.uniform(0, 0.65 * 2100.0, sh), 0.0)
+    u = rng.normal(0, 0.3, sh + (3,))
+    W = np.array([[1.0, 0, 0, 0.3], [-1.0, 0, 0, 0.2], [0, 1.0, 0, 0.35], [0, -1.0, 0, 0.25], [0, 0, 1.0, 0.6]])
+    n0 = 5
+    x0 = SG.fp32([[0.45, 0.45, 0.75 - 0.05 * k] for k in range(n0)])
+    spec = dict(x=x0, r=SG.fp32(np.full(n0, 0.02)), v=np.zeros((n0, 3)), w=np.zeros((n0, 3)), id=np.arange(n0),
+                bodies=[], material=SG.material(0.5, 0.0, rho=2100.0), dt=DT, gravity=(0.0, 0.0, 0.0), max_sweeps=0,
+                tol=0.0, warm_start="cold", grid_lo=(-0.6, -0.6, -0.1), grid_hi=(0.6, 0.6, 0.9), r_ref=0.05)
+    g = T.scene_from_specs(spec, cap_particles=400)
+    g.step(1)
+    mfd, rpd, ud = dev(mf), dev(rho_p), dev(u)
+    a = (origin, l0, dims)
+    # too small a budget: refused, nothing changed
+    with pytest.raises(T.TerrainError):
+        g.form_particles(0, *a, d_min, d_max, phi_max, rpd.ptr, ud.ptr, mfd.ptr, 1, wedges=[W])
+    assert np.array_equal(mfd.get(), mf)
+    n = g.form_particles(0, *a, d_min, d_max, phi_max, rpd.ptr, ud.ptr, mfd.ptr, 400, wedges=[W])
+    mf_ref, P = O.form_particles(mf, rho_p, u, [W], *a, 2100.0, d_min, d_max, phi_max)
+    assert n == len(P["r"]) and n > 5
+    p = g.get_particles(0)
+    assert len(p["r"]) == n0 + n
+    # appended in increasing voxel order: centres and velocities as FP32 values of the oracle's
+    assert np.array_equal(p["x"][n0:], SG.fp32(P["x"]))
+    assert np.array_equal(p["v"][n0:], SG.fp32(P["v"]))
+    assert np.all(np.abs(p["r"][n0:] - P["r"]) <= 6e-8 * P["r"])
+    # the fluid pays exactly what the FP32 radii hold
+    km = float(np.float32(2100.0)) * 4.0 / 3.0 * math.pi
+    got = mfd.get()
+    held = km * p["r"][n0:] ** 3
+    assert np.sum(got) + np.sum(held) == pytest.approx(np.sum(mf), rel=1e-13)
+    assert np.max(np.abs(got - mf_ref)) <= 4e-7 * m_of(d_max)
+    g.step(1)  # the new particles step with the rest
+    assert len(g.get_particles(0)["r"]) == n0 + n
