@@ -1746,6 +1746,24 @@ int64_t orc_form_particles(const orc_voxel_grid* g, double rho, double d_min, do
     return n;
 }
 
+double orc_settle_particles(int64_t n, const double* x, const double* v, const double* m, const orc_voxel_grid* g,
+                            double v_rest, int32_t n_wedges, const orc_wedge* wedges, double* mf, int32_t* gone)
+{
+    if (!grid_ok(g) || !(v_rest >= 0.0) || n_wedges < 0) return -1.0;
+    double total = 0.0;
+    for (int64_t a = 0; a < n; ++a) {
+        gone[a] = 0;
+        const double* va = &v[3 * a];
+        if (!(sqrt(dot3(va, va)) < v_rest)) continue;
+        int64_t vox = voxel_of(g, &x[3 * a]);
+        if (vox < 0 || inside_any_wedge(n_wedges, wedges, &x[3 * a])) continue;
+        mf[vox] += m[a];
+        total += m[a];
+        gone[a] = 1;
+    }
+    return total;
+}
+
 /* Eq. failure_plane: theta(phi, beta) = pi/2 - (phi + beta)/2. */
 double orc_failure_angle(double phi, double beta) { return 0.5 * PI - 0.5 * (phi + beta); }
 

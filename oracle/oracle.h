@@ -207,6 +207,14 @@ int64_t orc_form_particles(const orc_voxel_grid* g, double rho, double d_min, do
                            int32_t n_wedges, const orc_wedge* wedges, const double* rho_p, const double* u,
                            double* mf, int64_t cap, int64_t* voxel, double* x, double* v, double* r);
 
+/* Particles at rest outside the zones turn back into resting soil: a particle
+ * (x, v: 3n, mass m: n) with speed below v_rest whose centre is inside the
+ * grid and outside every wedge gives its mass to the fluid of its voxel (the
+ * deposit then makes it solid) and leaves the particle set: gone[a] = 1.
+ * Returns the mass converted, or -1 for a bad grid or v_rest. */
+double orc_settle_particles(int64_t n, const double* x, const double* v, const double* m, const orc_voxel_grid* g,
+                            double v_rest, int32_t n_wedges, const orc_wedge* wedges, double* mf, int32_t* gone);
+
 /* MLP 12 -> 64 -> 64 -> 3 with SiLU, weights row-major W[out][in]. */
 typedef struct orc_mlp {
     const double* W1; const double* b1;  /* 64x12, 64 */

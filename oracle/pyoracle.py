@@ -170,6 +170,9 @@ def lib():
         L.orc_surface_heights.argtypes = [C.POINTER(VoxelGrid), dp, dp]
         L.orc_convert_cut.restype = C.c_double
         L.orc_convert_cut.argtypes = [C.POINTER(VoxelGrid), C.c_double, C.c_int32, C.POINTER(Wedge), dp, dp, dp]
+        L.orc_settle_particles.restype = C.c_double
+        L.orc_settle_particles.argtypes = [C.c_int64, dp, dp, dp, C.POINTER(VoxelGrid), C.c_double, C.c_int32,
+                                           C.POINTER(Wedge), dp, C.POINTER(C.c_int32)]
         L.orc_form_particles.restype = C.c_int64
         L.orc_form_particles.argtypes = [C.POINTER(VoxelGrid), C.c_double, C.c_double, C.c_double, C.c_double,
                                          C.c_int32, C.POINTER(Wedge), dp, dp, dp, C.c_int64,
@@ -587,4 +590,20 @@ def form_particles(mf, rho_p, u, wedges, origin, l0, dims, rho, d_min, d_max, ph
     if n < 0:
         raise ValueError("bad grid or parameter")
     return m.reshape(np.shape(mf)), dict(voxel=vox[:n], x=x[:n], v=v[:n], r=r[:n])
+
+
+def settle_particles(x, v, m, mf, wedges, origin, l0, dims, v_rest):
+    """Particles at rest outside the zones give their mass to their voxel's
+    fluid; returns (new mf, removed mask, converted mass)."""
+    g = voxel_grid(origin, l0, dims)
+    x = _c64(x).reshape(-1, 3)
+    v = _c64(v).reshape(-1, 3)
+    mm = _c64(m)
+    f = _c64(mf).ravel().copy()
+    gone = np.zeros(len(x), dtype=np.int32)
+    tot = lib().orc_settle_particles(len(x), _dp(x), _dp(v), _dp(mm), C.byref(g), v_rest, len(wedges),
+                                     _wedge_array(wedges), _dp(f), gone.ctypes.data_as(C.POINTER(C.c_int32)))
+    if tot < 0:
+        raise ValueError("bad grid or v_rest")
+    return f.reshape(np.shape(mf)), gone.astype(bool), tot
 

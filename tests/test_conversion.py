@@ -262,3 +262,26 @@ def test_particle_formation():
     assert len(P3["r"]) > 10 and np.all(np.diff(P3["voxel"]) > 0)
     assert np.all((2 * P3["r"] >= d_min * (1 - 1e-12)) & (2 * P3["r"] <= d_max))
     assert np.sum(mf3) + np.sum(m_of(2 * P3["r"])) == pytest.approx(np.sum(mfr), rel=1e-13)
+
+
+def test_particles_at_rest_outside_the_zone_settle():
+    # slow particles outside the zone give their mass to their voxel's fluid;
+    # with no particle left there, the deposit turns it into solid: the
+    # column rises by m / (w_dep rho_b l0^2)
+    W = np.array([[1.0, 0, 0, 0.0], [-1.0, 0, 0, 0.5], [0, 0, 1.0, 1.0]])  # -0.5 <= x <= 0, z <= 1
+    x = np.array([[0.55, 0.05, 0.45], [0.55, 0.05, 0.47], [-0.25, 0.05, 0.45], [0.35, 0.05, 0.45], [5.0, 0, 0]])
+    v = np.array([[0.0, 0.01, 0.0], [0.02, 0.0, 0.0], [0.0, 0.0, 0.0], [0.5, 0.0, 0.0], [0, 0, 0]])
+    m = np.array([0.3, 0.2, 0.4, 0.5, 0.6])
+    sh = (DIMS[2], DIMS[1], DIMS[0])
+    mf = np.zeros(sh)
+    mf2, gone, tot = O.settle_particles(x, v, m, mf, [W], ORIGIN, L0, DIMS, 0.05)
+    # 0, 1: slow, outside the zone, same voxel; 2: inside the zone; 3: moving; 4: outside the grid
+    assert list(gone) == [True, True, False, False, False]
+    assert tot == pytest.approx(0.5, rel=1e-15) and mf2[4, 5, 15] == pytest.approx(0.5, rel=1e-15)
+    h0 = 0.23
+    phi = columns(np.full((DIMS[1], DIMS[0]), h0))
+    wc = np.ones_like(phi)
+    phi3, wc3, mf3, dep = O.convert_deposit(phi, wc, mf2, np.zeros(sh), [W], ORIGIN, L0, DIMS, RHO_B, 0.8)
+    assert dep == pytest.approx(0.5, rel=1e-14) and not mf3.any()
+    h = O.surface_heights(phi3, ORIGIN, L0, DIMS)
+    assert h[5, 15] == pytest.approx(h0 + 0.5 / (0.8 * RHO_B * L0 ** 2), rel=1e-13)
