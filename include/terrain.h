@@ -326,6 +326,23 @@ int form_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double d_mi
                    int32_t n_wedges, const int32_t* counts, const double* planes, const double* rho_p,
                    const double* u, double* mf, int64_t max_new, int64_t* n_formed);
 
+/* Removes the listed particles (ids of env, each once) from the scene; the
+ * env's remaining particles keep their order and are renumbered from the
+ * env's first id without gaps.  Clears the warm-start cache; the next step
+ * rebuilds the tables.  TR_E_INVAL for an id outside env or repeated. */
+int remove_particles(tr_scene* s, int32_t env, int64_t n, const int64_t* ids);
+
+/* Particles of env at rest outside the zones turn back into soil: a particle
+ * whose speed is below v_rest and whose centre is inside the grid and
+ * outside every wedge adds its mass to the fluidized mass mf (device, one per
+ * voxel) of its voxel and is removed as by remove_particles (a later
+ * convert_deposit, given particle densities without it, makes the fluid
+ * solid).  Wedges as for convert_cut.  *n_settled and *mass (both may be
+ * NULL) receive the number of particles and their mass.  TR_E_STATE before
+ * the first step since the particles or bodies changed. */
+int settle_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double v_rest, int32_t n_wedges,
+                     const int32_t* counts, const double* planes, double* mf, int64_t* n_settled, double* mass);
+
 /* One step of conserved advection of the fluidized mass per voxel (kg),
  * Eq. advection without sources: each interior face carries
  * phi = dt u_f mf_donor / l0 from the upwind voxel, u_f the mean of the two

@@ -55,6 +55,7 @@ struct tr_scene {
     WedgeDev* conv_wedges = nullptr;  // caller wedges of the conversion entry points (device)
     double* conv_total = nullptr;     // one device double: the converted mass
     double* adv_bmax = nullptr;       // per-block Courant maxima of the advection
+    int* settle_list = nullptr;       // ids of settle_particles (cap_particles)
     FormEntry* form_list = nullptr;   // candidates of form_particles
     int64_t form_cap = 0;
     std::vector<EnvDev> env_host;
@@ -1182,7 +1183,7 @@ int convert_cut(tr_scene* s, int32_t env, const tr_voxel_grid* g, double rho_b, 
     WedgeSet ws;
     int rc = conversion_wedges(s, env, n_wedges, counts, planes, ws, "convert_cut");
     if (rc != TR_OK) return rc;
-    if (!s->conv_total && !alloc_n(s, s->conv_total, 1)) return fail(s, TR_E_NOMEM, "convert_cut");
+    if (!s->conv_total && !alloc_n(s, s->conv_total, 2)) return fail(s, TR_E_NOMEM, "convert_cut");
     launch_convert_cut(*g, rho_b, ws, phi, wc, mf, liberated ? s->conv_total : nullptr, s->stream);
     HIP_CHECK(s, hipGetLastError());
     return read_total(s, liberated);
@@ -1201,7 +1202,7 @@ int convert_deposit(tr_scene* s, int32_t env, const tr_voxel_grid* g, double rho
     WedgeSet ws;
     int rc = conversion_wedges(s, env, n_wedges, counts, planes, ws, "convert_deposit");
     if (rc != TR_OK) return rc;
-    if (!s->conv_total && !alloc_n(s, s->conv_total, 1)) return fail(s, TR_E_NOMEM, "convert_deposit");
+    if (!s->conv_total && !alloc_n(s, s->conv_total, 2)) return fail(s, TR_E_NOMEM, "convert_deposit");
     launch_convert_deposit(*g, rho_b, w_dep, ws, rho_p, phi, wc, mf, deposited ? s->conv_total : nullptr, s->stream);
     HIP_CHECK(s, hipGetLastError());
     return read_total(s, deposited);
@@ -1229,7 +1230,7 @@ int form_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double d_mi
         if (!alloc_n(s, s->form_list, room)) return fail(s, TR_E_NOMEM, "form_particles: list");
         s->form_cap = room;
     }
-    if (!s->conv_total && !alloc_n(s, s->conv_total, 1)) return fail(s, TR_E_NOMEM, "form_particles");
+    if (!s->conv_total && !alloc_n(s, s->conv_total, 2)) return fail(s, TR_E_NOMEM, "form_particles");
     unsigned long long* cnt = (unsigned long long*)s->conv_total;
     const double rho = s->desc.material.rho;
     launch_form_candidates(*g, rho, d_min, d_max, phi_max, ws, rho_p, u, mf, s->form_list, cnt, room, s->stream);
@@ -1257,6 +1258,99 @@ int form_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double d_mi
     return TR_OK;
 }
 
+int remove_particles(tr_scene* s, int32_t env, int64_t n, const int64_t* ids)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs || n < 0 || (n > 0 && !ids)) return fail(s, TR_E_INVAL, "remove_particles: arguments");
+    if (n == 0) return TR_OK;
+    EnvHost& H = s->envs[env];
+    const int64_t id0 = (int64_t)env * s->desc.cap_particles;
+    std::vector<char> gone(H.n, 0);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t q = ids[k] - id0;
+        if (q < 0 || q >= H.n || gone[q]) return fail(s, TR_E_INVAL, "remove_particles: id not in env or repeated");
+        gone[q] = 1;
+    }
+    int rc = sync_poses(s);
+    if (rc) return rc;
+    // the env's remaining ids in order: 0, 1, ...
+    std::vector<int> renum(H.n, -1);
+    int64_t kept = 0;
+    for (int64_t q = 0; q < H.n; ++q)
+        if (!gone[q]) renum[q] = (int)(id0 + kept++);
+    const int64_t N = s->n_total;
+    std::vector<float4> xr(N), vm(N), wi(N);
+    std::vector<int> pid(N);
+    std::vector<float> rho(N);
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    HIP_CHECK(s, hipMemcpy(xr.data(), s->b.xr, sizeof(float4) * N, hipMemcpyDeviceToHost));
+    HIP_CHECK(s, hipMemcpy(vm.data(), s->b.vm, sizeof(float4) * N, hipMemcpyDeviceToHost));
+    HIP_CHECK(s, hipMemcpy(wi.data(), s->b.wi, sizeof(float4) * N, hipMemcpyDeviceToHost));
+    HIP_CHECK(s, hipMemcpy(pid.data(), s->b.pid, sizeof(int) * N, hipMemcpyDeviceToHost));
+    HIP_CHECK(s, hipMemcpy(rho.data(), s->b.rho, sizeof(float) * N, hipMemcpyDeviceToHost));
+    // compact the slots in their order, renumbering env's ids
+    int64_t w = 0;
+    for (int64_t sl = 0; sl < N; ++sl) {
+        const int64_t q = (int64_t)pid[sl] - id0;
+        if (q >= 0 && q < H.n) {
+            if (gone[q]) continue;
+            pid[sl] = renum[q];
+        }
+        xr[w] = xr[sl]; vm[w] = vm[sl]; wi[w] = wi[sl]; pid[w] = pid[sl]; rho[w] = rho[sl];
+        ++w;
+    }
+    std::vector<int> id2s(s->z.NID, 0);
+    for (int64_t sl = 0; sl < w; ++sl) id2s[pid[sl]] = (int)sl;
+    HIP_CHECK(s, hipMemcpy(s->b.xr, xr.data(), sizeof(float4) * w, hipMemcpyHostToDevice));
+    HIP_CHECK(s, hipMemcpy(s->b.vm, vm.data(), sizeof(float4) * w, hipMemcpyHostToDevice));
+    HIP_CHECK(s, hipMemcpy(s->b.wi, wi.data(), sizeof(float4) * w, hipMemcpyHostToDevice));
+    HIP_CHECK(s, hipMemcpy(s->b.pid, pid.data(), sizeof(int) * w, hipMemcpyHostToDevice));
+    HIP_CHECK(s, hipMemcpy(s->b.rho, rho.data(), sizeof(float) * w, hipMemcpyHostToDevice));
+    HIP_CHECK(s, hipMemcpy(s->b.id2slot, id2s.data(), sizeof(int) * s->z.NID, hipMemcpyHostToDevice));
+    H.n = kept;
+    s->n_total = w;
+    s->p.n_particles = (int)w;
+    s->have_prev = false;
+    s->tables_dirty = true;
+    return TR_OK;
+}
+
+int settle_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double v_rest, int32_t n_wedges,
+                     const int32_t* counts, const double* planes, double* mf, int64_t* n_settled, double* mass)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (n_settled) *n_settled = 0;
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "settle_particles: env");
+    if (!voxel_grid_ok(g) || !mf) return fail(s, TR_E_INVAL, "settle_particles: grid or arrays");
+    if (!(v_rest >= 0.0) || !std::isfinite(v_rest)) return fail(s, TR_E_INVAL, "settle_particles: v_rest");
+    if (s->tables_dirty) return fail(s, TR_E_STATE, "settle_particles: no step since the particles or bodies changed");
+    WedgeSet ws;
+    int rc = conversion_wedges(s, env, n_wedges, counts, planes, ws, "settle_particles");
+    if (rc != TR_OK) return rc;
+    if (!s->conv_total && !alloc_n(s, s->conv_total, 2)) return fail(s, TR_E_NOMEM, "settle_particles");
+    if (!s->settle_list && !alloc_n(s, s->settle_list, s->desc.cap_particles))
+        return fail(s, TR_E_NOMEM, "settle_particles: list");
+    unsigned long long* cnt = (unsigned long long*)s->conv_total;
+    launch_settle(s->b, s->env_host[env], *g, v_rest, ws, mf, s->settle_list, cnt, mass ? s->conv_total + 1 : nullptr,
+                  s->stream);
+    HIP_CHECK(s, hipGetLastError());
+    unsigned long long n = 0;
+    HIP_CHECK(s, hipMemcpyAsync(&n, cnt, sizeof(n), hipMemcpyDeviceToHost, s->stream));
+    if (mass) HIP_CHECK(s, hipMemcpyAsync(mass, s->conv_total + 1, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    if (n == 0) return TR_OK;
+    std::vector<int> ids32(n);
+    HIP_CHECK(s, hipMemcpy(ids32.data(), s->settle_list, sizeof(int) * n, hipMemcpyDeviceToHost));
+    std::vector<int64_t> ids(ids32.begin(), ids32.end());
+    std::sort(ids.begin(), ids.end());
+    rc = remove_particles(s, env, (int64_t)n, ids.data());
+    if (rc != TR_OK) return rc;
+    if (n_settled) *n_settled = (int64_t)n;
+    return TR_OK;
+}
+
 int grow_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double dt, double dprime_max, double d_max,
                    double* mf, double* work, double* grown)
 {
@@ -1269,7 +1363,7 @@ int grow_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double dt, 
     if (s->tables_dirty) return fail(s, TR_E_STATE, "grow_particles: no step since the bodies changed");
     if (0.5 * d_max > s->envs[env].rmax)
         return fail(s, TR_E_INVAL, "grow_particles: d_max exceeds the env's largest diameter");
-    if (!s->conv_total && !alloc_n(s, s->conv_total, 1)) return fail(s, TR_E_NOMEM, "grow_particles");
+    if (!s->conv_total && !alloc_n(s, s->conv_total, 2)) return fail(s, TR_E_NOMEM, "grow_particles");
     launch_grow(s->b, s->env_host[env], *g, dt, dprime_max, d_max, mf, work, grown ? s->conv_total : nullptr,
                 s->stream);
     HIP_CHECK(s, hipGetLastError());

@@ -303,6 +303,10 @@ void launch_form_candidates(const tr_voxel_grid& g, double rho, double d_min, do
                             const WedgeSet& ws, const double* rho_p, const double* u, const double* mf,
                             FormEntry* list, unsigned long long* count, int64_t cap, hipStream_t s);
 void launch_form_pay(const FormEntry* list, int64_t n, double rho, double* mf, hipStream_t s);
+// particles of env at rest outside the zones: their mass into mf, their ids
+// into list (*count of them)
+void launch_settle(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, double v_rest, const WedgeSet& ws,
+                   double* mf, int* list, unsigned long long* count, double* total, hipStream_t s);
 // particle growth from the voxels' fluidized mass; work: 2 nx ny nz doubles
 void launch_grow(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, double dt, double dprime_max,
                  double d_max, double* mf, double* work, double* total, hipStream_t s);

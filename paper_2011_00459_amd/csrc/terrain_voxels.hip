@@ -654,5 +654,38 @@ void launch_form_pay(const FormEntry* list, int64_t n, double rho, double* mf, h
     if (n > 0) hipLaunchKernelGGL(k_form_pay, dim3((unsigned)cdiv(n, kBlk)), dim3(kBlk), 0, s, list, n, rho, mf);
 }
 
+// ---------------------------------------------------------------------------
+// Particles at rest outside the zones: their mass joins their voxel's fluid
+// (FP64 atomics) and their ids are listed for removal
+// ---------------------------------------------------------------------------
+__global__ void k_settle(DevBuffers b, EnvDev E, tr_voxel_grid g, double v_rest, WedgeSet ws, double* mf, int* list,
+                         unsigned long long* count, double* total)
+{
+#pragma clang fp contract(off)
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= E.n) return;
+    const int sl = E.slot_begin + a;
+    const float4 xr = b.xr[sl], vm = b.vm[sl];
+    const double v[3] = {vm.x, vm.y, vm.z};
+    if (!(sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]) < v_rest)) return;
+    const int64_t vox = voxel_index(g, xr);
+    if (vox < 0 || in_wedge_set(ws, xr.x, xr.y, xr.z)) return;
+    const double r = xr.w;
+    const double m = (double)b.rho[sl] * (4.0 / 3.0) * 3.14159265358979323846 * r * r * r;
+    atomicAdd(&mf[vox], m);
+    if (total) atomicAdd(total, m);
+    list[atomicAdd(count, 1ull)] = b.pid[sl];
+}
+
+void launch_settle(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, double v_rest, const WedgeSet& ws,
+                   double* mf, int* list, unsigned long long* count, double* total, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, (double*)count, (int64_t)1, 0.0);  // bits of 0
+    if (total) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, total, (int64_t)1, 0.0);
+    if (E.n > 0)
+        hipLaunchKernelGGL(k_settle, dim3((unsigned)cdiv(E.n, kBlk)), dim3(kBlk), 0, s, b, E, g, v_rest, ws, mf, list,
+                           count, total);
+}
+
 }  // namespace trk
 

@@ -26,7 +26,8 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "mlp_forward", "mlp_grad_scratch_floats", "mlp_loss_grad", "mlp_adam_step", "set_solver_config",
            "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state", "autotune",
            "get_rolling_impulses", "set_tool", "get_zone_wedges", "coarse_grain", "advect_fluid",
-           "terrain_from_voxels", "convert_cut", "convert_deposit", "grow_particles", "form_particles")
+           "terrain_from_voxels", "convert_cut", "convert_deposit", "grow_particles", "form_particles",
+           "remove_particles", "settle_particles")
 CG_KERNEL = {"heaviside": 0, "gauss": 1}
 PGS_MODE = {"grouped": 0, "per_env": 1}
 MLP_TRAINABLE = MLP_PARAMS - 12
@@ -155,6 +156,9 @@ def lib():
         L.get_rolling_impulses.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_int64)]
         L.coarse_grain.argtypes = [P, C.c_int32, C.POINTER(tr_voxel_grid), C.c_int32, C.c_double, P, P, P]
         L.advect_fluid.argtypes = [P, C.POINTER(tr_voxel_grid), C.c_double, P, P, P, C.POINTER(C.c_double)]
+        L.remove_particles.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_int64)]
+        L.settle_particles.argtypes = [P, C.c_int32, C.POINTER(tr_voxel_grid), C.c_double, C.c_int32,
+                                       C.POINTER(C.c_int32), dp, P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.form_particles.argtypes = [P, C.c_int32, C.POINTER(tr_voxel_grid), C.c_double, C.c_double, C.c_double,
                                      C.c_int32, C.POINTER(C.c_int32), dp, P, P, P, C.c_int64, C.POINTER(C.c_int64)]
         L.grow_particles.argtypes = [P, C.c_int32, C.POINTER(tr_voxel_grid), C.c_double, C.c_double, C.c_double, P,
@@ -346,6 +350,22 @@ class Scene:
         self._check(lib().advect_fluid(self.h, C.byref(g), dt, u_ptr, mf_in_ptr, mf_out_ptr,
                                        C.byref(cfl) if sync else None), "advect_fluid")
         return cfl.value if sync else None
+
+    def remove_particles(self, env, ids):
+        """Remove particles by id; env's remaining particles are renumbered in order."""
+        a = np.ascontiguousarray(ids, dtype=np.int64)
+        self._check(lib().remove_particles(self.h, env, len(a), a.ctypes.data_as(C.POINTER(C.c_int64))),
+                    "remove_particles")
+
+    def settle_particles(self, env, origin, l0, dims, v_rest, mf_ptr, wedges=None):
+        """Particles at rest outside the zones into their voxels' fluid (and out
+        of the scene); returns (count, mass)."""
+        g = voxel_grid(origin, l0, dims)
+        n, counts, planes = self._wedge_args(wedges)
+        cnt, mass = C.c_int64(), C.c_double()
+        self._check(lib().settle_particles(self.h, env, C.byref(g), v_rest, n, counts, _dp(planes), mf_ptr,
+                                           C.byref(cnt), C.byref(mass)), "settle_particles")
+        return cnt.value, mass.value
 
     def form_particles(self, env, origin, l0, dims, d_min, d_max, phi_max, rho_p_ptr, u_ptr, mf_ptr, max_new,
                        wedges=None):

@@ -293,3 +293,36 @@ def test_particle_formation_matches_oracle():
     assert np.max(np.abs(got - mf_ref)) <= 4e-7 * m_of(d_max)
     g.step(1)  # the new particles step with the rest
     assert len(g.get_particles(0)["r"]) == n0 + n
+
+
+def test_settle_particles_matches_oracle_and_steps_on():
+    rng = np.random.default_rng(33)
+    n = 2000
+    origin, l0, dims = (-0.5, -0.5, 0.0), 0.1, (10, 10, 8)
+    x = SG.fp32(rng.uniform((-0.6, -0.48, 0.02), (0.48, 0.48, 0.78), (n, 3)))  # some left of the grid
+    v = SG.fp32(rng.normal(0, 0.05, (n, 3)))
+    r = SG.fp32(rng.uniform(0.008, 0.012, n))
+    spec = dict(x=x, r=r, v=v, w=np.zeros((n, 3)), id=np.arange(n), bodies=[],
+                material=SG.material(0.5, 0.0, rho=2100.0), dt=DT, gravity=(0.0, 0.0, 0.0), max_sweeps=10, tol=0.0,
+                warm_start="cold", grid_lo=(-0.8, -0.6, -0.1), grid_hi=(0.6, 0.6, 0.9), r_ref=0.05)
+    g = T.scene_from_specs(spec)
+    g.step(1)
+    g.set_particles(0, x=x, v=v, w=np.zeros((n, 3)))
+    W = np.array([[1.0, 0, 0, 0.1], [-1.0, 0, 0, 0.3], [0, 0, 1.0, 0.7]])
+    sh = (dims[2], dims[1], dims[0])
+    mf0 = np.where(rng.uniform(size=sh) < 0.2, rng.uniform(0, 1e-2, sh), 0.0)
+    mf = dev(mf0)
+    cnt, mass = g.settle_particles(0, origin, l0, dims, 0.06, mf.ptr, wedges=[W])
+    m = float(np.float32(2100.0)) * (4.0 / 3.0) * math.pi * r * r * r
+    ref_mf, gone, ref_mass = O.settle_particles(x, v, m, mf0, [W], origin, l0, dims, 0.06)
+    assert cnt == int(gone.sum()) and 100 < cnt < n - 100
+    assert mass == pytest.approx(ref_mass, rel=1e-12)
+    assert np.max(np.abs(mf.get() - ref_mf)) <= 1e-15 * max(1.0, np.max(ref_mf))
+    # the rest keep their order, renumbered
+    p = g.get_particles(0)
+    assert len(p["r"]) == n - cnt
+    assert np.array_equal(p["x"], x[~gone]) and np.array_equal(p["r"], r[~gone])
+    g.step(2)
+    assert len(g.get_particles(0)["r"]) == n - cnt
+    with pytest.raises(T.TerrainError):
+        g.remove_particles(0, [n - cnt])  # past the env's last id
