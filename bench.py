@@ -42,7 +42,7 @@ PGS_TRAFFIC = {"kernels_sha256_prefix": "5d6dc0bfd68b6d0b", "bytes_per_launch": 
 
 # The same for k_advect on the 256 x 256 x 128 voxel grid
 # (profiles/k_advect_voxels256_kernel_trace.md), keyed to terrain_voxels.hip.
-ADVECT_TRAFFIC = {"kernels_sha256_prefix": "c9d7008606489e9d", "bytes_per_launch": 4.757144e8,
+ADVECT_TRAFFIC = {"kernels_sha256_prefix": "94e67407f6ab7331", "bytes_per_launch": 0.4738e9,
                   "profile": "profiles/k_advect_voxels256_kernel_trace.md"}
 
 
@@ -257,8 +257,9 @@ def bench_voxels(args):
     u = DeviceArray.from_host(w["u"], np.float64)
     hd = DeviceArray((ny, nx), np.float64)
     grid = (org, l0, w["dims"])
+    # five events per timed step: around the cut, the advection, the deposit and the surface
     ev = []
-    for _ in range(2 * (args.steps + 1)):
+    for _ in range(5 * (args.steps + 1)):
         e = ctypes.c_void_p()
         if h.hipEventCreate(ctypes.byref(e)) != 0:
             raise RuntimeError("hipEventCreate failed")
@@ -266,15 +267,20 @@ def bench_voxels(args):
 
     def meso_step(k, timed):
         a, b = mf[k % 2], mf[(k + 1) % 2]
+
+        def mark(q):
+            if timed is not None:
+                h.hipEventRecord(ev[5 * timed + q], None)
+        mark(0)
         sc.convert_cut(0, *grid, vt["rho_b"], phi.ptr, wc.ptr, a.ptr, wedges=None, sync=False)
-        if timed is not None:
-            h.hipEventRecord(ev[2 * timed], None)
+        mark(1)
         sc.advect_fluid(*grid, w["dt"], u.ptr, a.ptr, b.ptr, sync=False)
-        if timed is not None:
-            h.hipEventRecord(ev[2 * timed + 1], None)
+        mark(2)
         sc.convert_deposit(0, *grid, vt["rho_b"], vt["w_dep"], rho_p.ptr, phi.ptr, wc.ptr, b.ptr, wedges=None,
                            sync=False)
+        mark(3)
         sc.terrain_from_voxels(0, *grid, phi.ptr, hd.ptr)
+        mark(4)
 
     m0 = float(np.sum(vt["phi"] * vt["wc"]) * vt["rho_b"] * l0 ** 3 + np.sum(vt["mf"] + w["mf"]))
     for k in range(args.warmup):
@@ -285,11 +291,13 @@ def bench_voxels(args):
         meso_step(args.warmup + k, k)
     device_sync()
     wall = time.perf_counter() - t0
-    dev_ms = 0.0
+    op_ms = {"cut": 0.0, "advect": 0.0, "deposit": 0.0, "surface": 0.0}
     for k in range(args.steps):
-        ms = ctypes.c_float()
-        h.hipEventElapsedTime(ctypes.byref(ms), ev[2 * k], ev[2 * k + 1])
-        dev_ms += ms.value
+        for q, name in enumerate(op_ms):
+            ms = ctypes.c_float()
+            h.hipEventElapsedTime(ctypes.byref(ms), ev[5 * k + q], ev[5 * k + q + 1])
+            op_ms[name] += ms.value / args.steps
+    dev_ms = op_ms["advect"] * args.steps
     last = mf[(args.warmup + args.steps) % 2].get()
     m1 = float(np.sum(phi.get() * wc.get()) * vt["rho_b"] * l0 ** 3 + np.sum(last))
     cfl = sc.advect_fluid(*grid, w["dt"], u.ptr, mf[0].ptr, mf[1].ptr)
@@ -322,7 +330,8 @@ def bench_voxels(args):
         "config": {"workload": "mesoscale dig site: 256x256x128 voxels l0 0.05 m, rolling terrain, a blade's "
                                "8-wedge zone cutting 0.3-1.5 m deep, fluidized soil in an ellipsoidal zone, swirl "
                                "velocity at Courant <= 0.4, dt 1/60 s: cut + advection + deposit + surface",
-                   "courant": cfl, "advect_device_ms": adv_ms, "mass_drift_rel": abs(m1 - m0) / m0,
+                   "courant": cfl, "advect_device_ms": adv_ms, "op_device_ms": op_ms,
+                   "mass_drift_rel": abs(m1 - m0) / m0,
                    "coarse_grain_bed": cg},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

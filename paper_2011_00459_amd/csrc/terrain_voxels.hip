@@ -356,111 +356,136 @@ __global__ void k_convert_deposit(tr_voxel_grid g, double rho_b, double w_dep, W
     if (total && sum > 0.0) atomicAdd(total, sum);
 }
 
-// The deposit with one wave per column (columns of at most kDepositNz
-// voxels): the wave loads the column's occupancy, compaction and fluid into
-// LDS and marks the voxels whose fluid falls (in parallel, 64 at a time); one
-// lane then takes the marked voxels in increasing height through the same
-// fills as the per-thread kernel, on LDS; the wave writes back what changed.
-constexpr int kDepositNz = 256;
-constexpr int kDepositWaves = kBlk / 64;
+// The deposit on tiles of kTileCols neighbouring columns of at most kTileNz
+// voxels.  Columns are strided by nx ny in memory, so a column read by one
+// wave touches a cache line per voxel; the tile is read instead as whole
+// lines (each wave instruction: 16 columns at 4 heights) into LDS.  The
+// voxels whose fluid falls are marked in parallel (bit masks per column), as
+// is each column's first non-full voxel; one thread per column then replays
+// the fills over its marked voxels in increasing height, as the per-thread
+// kernel does, on LDS, and the block writes back what changed.
+constexpr int kTileCols = 16;
+constexpr int kTileNz = 128;
+constexpr int kTileRows = kBlk / kTileCols;  // heights per pass
+constexpr int kTileWords = kTileNz / 64;
 
-__global__ void __launch_bounds__(kBlk) k_convert_deposit_col(tr_voxel_grid g, double rho_b, double w_dep, WedgeSet ws,
-                                                              const double* rho_p, double* phi, double* wc,
-                                                              double* mf, double* total)
+__global__ void __launch_bounds__(kBlk) k_convert_deposit_tile(tr_voxel_grid g, double rho_b, double w_dep,
+                                                               WedgeSet ws, const double* rho_p, double* phi,
+                                                               double* wc, double* mf, double* total)
 {
 #pragma clang fp contract(off)
-    __shared__ double sphi[kDepositWaves][kDepositNz], swc[kDepositWaves][kDepositNz], smf[kDepositWaves][kDepositNz];
-    __shared__ unsigned long long smask[kDepositWaves][kDepositNz / 64];
-    __shared__ int srange[kDepositWaves][2];
-    __shared__ double ssum[kDepositWaves];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // (+1: a column's heights start two banks after the previous column's)
+    __shared__ double P[kTileCols][kTileNz + 1], W[kTileCols][kTileNz + 1], M[kTileCols][kTileNz + 1];
+    __shared__ unsigned long long mask[kTileCols][kTileWords];
+    __shared__ int first_free[kTileCols], range[kTileCols][2];
+    __shared__ double ssum[kTileCols];
     const int64_t nxy = (int64_t)g.nx * g.ny;
-    const int64_t c = (int64_t)blockIdx.x * kDepositWaves + wv;
-    const bool live = c < nxy;  // (uniform across the wave)
-    double* P = sphi[wv];
-    double* W = swc[wv];
-    double* M = smf[wv];
+    const int col = threadIdx.x % kTileCols, row = threadIdx.x / kTileCols;
+    const int64_t c = (int64_t)blockIdx.x * kTileCols + col;
+    const bool live = c < nxy;
     const int nz = g.nz;
-    const int nchunk = (nz + 63) / 64;
-    if (live) {
-        const int i = (int)(c % g.nx), j = (int)(c / g.nx);
-        const double x = g.origin[0] + (i + 0.5) * g.l0, y = g.origin[1] + (j + 0.5) * g.l0;
-        for (int q = 0; q < nchunk; ++q) {
-            const int k = q * 64 + lane;
-            bool cand = false;
-            if (k < nz) {
-                const int64_t id = (int64_t)k * nxy + c;
-                const double m = mf[id];
-                P[k] = phi[id];
-                W[k] = wc[id];
-                M[k] = m;
-                cand = m > 0.0 && rho_p[id] == 0.0 && !in_wedge_set(ws, x, y, g.origin[2] + (k + 0.5) * g.l0);
-            }
-            const unsigned long long b = __ballot(cand);
-            if (lane == 0) smask[wv][q] = b;
-        }
+    const double x = g.origin[0] + ((int)(c % g.nx) + 0.5) * g.l0, y = g.origin[1] + ((int)(c / g.nx) + 0.5) * g.l0;
+    if (threadIdx.x < kTileCols) {
+        for (int w = 0; w < kTileWords; ++w) mask[threadIdx.x][w] = 0ull;
+        first_free[threadIdx.x] = nz;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (live && lane == 0) {
-        const double V0 = g.l0 * g.l0 * g.l0;
-        double sum = 0.0;
-        int kfree = 0, klo = nz, khi = -1;
-        for (int q = 0; q < nchunk; ++q) {
-            unsigned long long mk = smask[wv][q];
-            while (mk) {
-                const int k = q * 64 + (__ffsll((long long)mk) - 1);
-                mk &= mk - 1;
-                double m = M[k];
-                int kk = kfree;
-                while (kk < nz && P[kk] >= 1.0) ++kk;  // the first voxel that is not full
-                kfree = kk;
-                klo = kk < klo ? kk : klo;
-                while (m > 0.0 && kk < nz) {
-                    const double f0 = P[kk];
-                    const double cap = (1.0 - f0) * w_dep * rho_b * V0;
-                    const double take = m < cap ? m : cap;
-                    const double f = take == cap ? 1.0 : f0 + take / (w_dep * rho_b * V0);
-                    const double before = W[kk] * rho_b * V0 * f0;
-                    W[kk] = f0 > 0.0 ? (before + take) / (rho_b * V0 * f) : w_dep;
-                    P[kk] = f;
-                    khi = kk > khi ? kk : khi;
-                    sum += take;
-                    m -= take;
-                    ++kk;
-                }
-                M[k] = 0.0 + m;  // what finds the column full stays fluid
-            }
-        }
-        srange[wv][0] = klo;
-        srange[wv][1] = khi;
-        ssum[wv] = sum;
+    __syncthreads();
+    // a thread's heights row, row + kTileRows, ...: all its loads in flight at once
+    constexpr int kPer = kTileNz / kTileRows;
+    double mv[kPer], rv[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int k = row + t * kTileRows;
+        mv[t] = live && k < nz ? mf[(int64_t)k * nxy + c] : 0.0;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (live) {
-        const int klo = srange[wv][0], khi = srange[wv][1];
-        for (int q = 0; q < nchunk; ++q) {
-            const int k = q * 64 + lane;
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int k = row + t * kTileRows;
+        rv[t] = mv[t] > 0.0 ? rho_p[(int64_t)k * nxy + c] : 1.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int k = row + t * kTileRows;
+        if (k >= nz) continue;
+        M[col][k] = mv[t];
+        if (mv[t] > 0.0 && rv[t] == 0.0 && !in_wedge_set(ws, x, y, g.origin[2] + (k + 0.5) * g.l0))
+            atomicOr(&mask[col][k >> 6], 1ull << (k & 63));
+    }
+    __syncthreads();
+    bool work = false;
+    for (int w = 0; w < kTileWords; ++w) work |= mask[col][w] != 0ull;
+    work &= live;
+    if (work) {
+        double pv[kPer], wv[kPer];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int k = row + t * kTileRows;
+            pv[t] = k < nz ? phi[(int64_t)k * nxy + c] : 1.0;
+            wv[t] = k < nz ? wc[(int64_t)k * nxy + c] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int k = row + t * kTileRows;
             if (k >= nz) continue;
+            P[col][k] = pv[t];
+            W[col][k] = wv[t];
+            if (!(pv[t] >= 1.0)) atomicMin(&first_free[col], k);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kTileCols) {
+        double sum = 0.0;
+        int klo = nz, khi = -1;
+        if (work) {
+            const double V0 = g.l0 * g.l0 * g.l0;
+            int kfree = first_free[col];  // the first voxel that is not full
+            for (int w = 0; w < kTileWords; ++w) {
+                unsigned long long mk = mask[col][w];
+                while (mk) {
+                    const int k = w * 64 + (__ffsll((long long)mk) - 1);
+                    mk &= mk - 1;
+                    double m = M[col][k];
+                    int kk = kfree;
+                    while (kk < nz && P[col][kk] >= 1.0) ++kk;
+                    kfree = kk;
+                    klo = kk < klo ? kk : klo;
+                    while (m > 0.0 && kk < nz) {
+                        const double f0 = P[col][kk];
+                        const double cap = (1.0 - f0) * w_dep * rho_b * V0;
+                        const double take = m < cap ? m : cap;
+                        const double f = take == cap ? 1.0 : f0 + take / (w_dep * rho_b * V0);
+                        const double before = W[col][kk] * rho_b * V0 * f0;
+                        W[col][kk] = f0 > 0.0 ? (before + take) / (rho_b * V0 * f) : w_dep;
+                        P[col][kk] = f;
+                        khi = kk > khi ? kk : khi;
+                        sum += take;
+                        m -= take;
+                        ++kk;
+                    }
+                    M[col][k] = 0.0 + m;  // what finds the column full stays fluid
+                }
+            }
+        }
+        range[col][0] = klo;
+        range[col][1] = khi;
+        ssum[col] = sum;
+    }
+    __syncthreads();
+    if (work) {
+        const int klo = range[col][0], khi = range[col][1];
+        for (int k = row; k < nz; k += kTileRows) {
             const int64_t id = (int64_t)k * nxy + c;
-            if ((smask[wv][q] >> lane) & 1ull) mf[id] = M[k];
+            if ((mask[col][k >> 6] >> (k & 63)) & 1ull) mf[id] = M[col][k];
             if (k >= klo && k <= khi) {
-                phi[id] = P[k];
-                wc[id] = W[k];
+                phi[id] = P[col][k];
+                wc[id] = W[col][k];
             }
         }
     }
-    if (total) {  // one atomic per block
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int w = 0; w < kDepositWaves; ++w)
-                if ((int64_t)blockIdx.x * kDepositWaves + w < nxy) s += ssum[w];
-            if (s > 0.0) atomicAdd(total, s);
-        }
+    if (total && threadIdx.x == 0) {  // one atomic per tile
+        double s = 0.0;
+        for (int q = 0; q < kTileCols; ++q) s += ssum[q];
+        if (s > 0.0) atomicAdd(total, s);
     }
 }
 
@@ -484,8 +509,8 @@ void launch_convert_deposit(const tr_voxel_grid& g, double rho_b, double w_dep, 
 {
     const int64_t nxy = (int64_t)g.nx * g.ny;
     if (total) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, total, (int64_t)1, 0.0);
-    if (g.nz <= kDepositNz)
-        hipLaunchKernelGGL(k_convert_deposit_col, dim3((unsigned)cdiv(nxy, kDepositWaves)), dim3(kBlk), 0, s, g, rho_b,
+    if (g.nz <= kTileNz)
+        hipLaunchKernelGGL(k_convert_deposit_tile, dim3((unsigned)cdiv(nxy, kTileCols)), dim3(kBlk), 0, s, g, rho_b,
                            w_dep, ws, rho_p, phi, wc, mf, total);
     else
         hipLaunchKernelGGL(k_convert_deposit, dim3((unsigned)cdiv(nxy, kBlk)), dim3(kBlk), 0, s, g, rho_b, w_dep, ws,

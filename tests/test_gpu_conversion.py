@@ -106,7 +106,7 @@ def check_exact(got, ref):
     assert got["dep"] == pytest.approx(ref["dep"], rel=1e-12, abs=1e-12)
 
 
-# columns of up to 256 voxels take the wave-per-column deposit, taller ones the
+# columns of up to 128 voxels take the tiled deposit (16 columns a block), taller ones the
 # thread-per-column one
 @pytest.mark.parametrize("seed,dims", [(1, (37, 29, 23)), (2, (37, 29, 23)), (3, (9, 7, 300))])
 def test_cut_deposit_surface_bit_exact_on_a_ragged_grid(seed, dims):
