@@ -55,6 +55,7 @@ struct tr_scene {
     WedgeDev* conv_wedges = nullptr;  // caller wedges of the conversion entry points (device)
     double* conv_total = nullptr;     // one device double: the converted mass
     double* adv_bmax = nullptr;       // per-block Courant maxima of the advection
+    int64_t adv_cap = 0;
     int* settle_list = nullptr;       // ids of settle_particles (cap_particles)
     FormEntry* form_list = nullptr;   // candidates of form_particles
     int64_t form_cap = 0;
@@ -1065,7 +1066,14 @@ int advect_fluid(tr_scene* s, const tr_voxel_grid* g, double dt, const double* u
     if (!u || !mf_in || !mf_out) return fail(s, TR_E_INVAL, "advect_fluid: null pointer");
     if (mf_in == mf_out) return fail(s, TR_E_INVAL, "advect_fluid: mf_out aliases mf_in");
     unsigned long long* bits = (unsigned long long*)s->staging;  // at least 12 floats: one uint64 fits
-    if (!s->adv_bmax && !alloc_n(s, s->adv_bmax, advect_max_blocks())) return fail(s, TR_E_NOMEM, "advect_fluid");
+    const int64_t nb = advect_blocks(*g);
+    if (nb > s->adv_cap) {
+        dfree(s, s->adv_bmax);
+        s->adv_bmax = nullptr;
+        s->adv_cap = 0;
+        if (!alloc_n(s, s->adv_bmax, nb)) return fail(s, TR_E_NOMEM, "advect_fluid");
+        s->adv_cap = nb;
+    }
     launch_advect(*g, dt, u, mf_in, mf_out, s->adv_bmax, bits, s->stream);
     HIP_CHECK(s, hipGetLastError());
     if (!cfl) return TR_OK;

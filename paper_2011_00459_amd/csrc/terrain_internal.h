@@ -314,8 +314,8 @@ void launch_grow(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, d
 // device uint64 receiving the largest Courant number's bits
 void launch_coarse_grain(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, int kernel, double R,
                          double* rho, double* mom, double* u, hipStream_t s);
-constexpr int kAdvectBlocksPerRun = 256;  // resident blocks of one XCD's run of tiles
-int advect_max_blocks();                  // size of the per-block maxima launch_advect needs
+constexpr int kAdvectTargetBlocks = 2048;  // about 8 blocks per CU
+int64_t advect_blocks(const tr_voxel_grid& g);  // size of the per-block maxima launch_advect needs
 void launch_advect(const tr_voxel_grid& g, double dt, const double* u, const double* mf_in, double* mf_out,
                    double* bmax, unsigned long long* cfl_bits, hipStream_t s);
 // impact stage: rows of envs without impacts neutralised, the stage's sweeps

@@ -102,61 +102,108 @@ void launch_coarse_grain(const DevBuffers& b, const EnvDev& E, const tr_voxel_gr
     if (u) hipLaunchKernelGGL(k_cg_velocity, dim3((unsigned)cdiv(nv, kBlk)), dim3(kBlk), 0, s, nv, rho, mom, u);
 }
 
-// Consecutive blocks of a launch go to the 8 XCDs in turn; each XCD is given
-// a contiguous run of 256-voxel tiles instead (block b serves run b % 8), its
-// blocks stepping through the run together, so the neighbouring rows and
-// planes a voxel reads were loaded into that XCD's L2 shortly before.  Each
-// block leaves the largest Courant number it met in bmax[b]; one block
+// A block takes a 16 x 16 tile of columns through a run of kc planes: each
+// plane of the tile (with a one-voxel halo in x and y) goes through LDS, and
+// the planes above and below stay in registers, so every voxel's mass and
+// velocity are read once (the halo aside).  The loads of plane k + 1 are in
+// flight while plane k is computed (two LDS buffers, one barrier per plane).
+// Each block leaves the largest Courant number it met in bmax[b]; one block
 // reduces them (device-scope atomics to one address cost about 10 ns each).
-__global__ void k_advect(tr_voxel_grid g, double dt, const double* u, const double* mf, double* out, double* bmax,
-                         int tiles_per_run, int blocks_per_run)
+constexpr int kAT = 16;  // tile edge (kAT * kAT == kBlk)
+
+struct PlaneRegs {
+    double mf, ux, uy, uz;  // the thread's own voxel
+    double hx_mf, hx_u;     // across the tile's x edge (tx == 0: i - 1, tx == kAT - 1: i + 1)
+    double hy_mf, hy_u;     // across the tile's y edge
+};
+
+__device__ inline void load_plane(const tr_voxel_grid& g, const double* u, const double* mf, int i, int j, int k,
+                                  int tx, int ty, PlaneRegs& r)
+{
+    r = PlaneRegs{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (k < 0 || k >= g.nz || i >= g.nx || j >= g.ny) return;
+    const int64_t plane = (int64_t)k * g.nx * g.ny;
+    const int64_t id = plane + (int64_t)j * g.nx + i;
+    r.mf = mf[id];
+    r.ux = u[3 * id];
+    r.uy = u[3 * id + 1];
+    r.uz = u[3 * id + 2];
+    const int hi_ = tx == 0 ? i - 1 : (tx == kAT - 1 ? i + 1 : -1);
+    if (hi_ >= 0 && hi_ < g.nx) {
+        const int64_t h = plane + (int64_t)j * g.nx + hi_;
+        r.hx_mf = mf[h];
+        r.hx_u = u[3 * h];
+    }
+    const int hj = ty == 0 ? j - 1 : (ty == kAT - 1 ? j + 1 : -1);
+    if (hj >= 0 && hj < g.ny) {
+        const int64_t h = plane + (int64_t)hj * g.nx + i;
+        r.hy_mf = mf[h];
+        r.hy_u = u[3 * h + 1];
+    }
+}
+
+__global__ void __launch_bounds__(kBlk) k_advect(tr_voxel_grid g, double dt, const double* u, const double* mf,
+                                                 double* out, double* bmax, int tiles_x, int tiles_y, int kc,
+                                                 int nblocks, int per)
 {
 #pragma clang fp contract(off)
-    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;  // < 2^31: 32-bit index arithmetic below
-    const int run = blockIdx.x % 8, pos = blockIdx.x / 8;
+    __shared__ double smf[2][kAT + 2][kAT + 2], sux[2][kAT + 2][kAT + 2], suy[2][kAT + 2][kAT + 2];
+    const int tx = threadIdx.x % kAT, ty = threadIdx.x / kAT;
+    // blocks go to the XCDs in turn; XCD x takes the contiguous run
+    // [x per, (x + 1) per) of (tile x, tile y, chunk) order, so neighbouring
+    // tiles, which read each other's edges as halo, share an L2
+    const int lb = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    const int bx = lb % tiles_x, by = (lb / tiles_x) % tiles_y, bz = lb / (tiles_x * tiles_y);
+    const int i = bx * kAT + tx, j = by * kAT + ty;
+    // (a block past the last tile has an empty run of planes)
+    const int k0 = bz * kc, k1 = lb < nblocks ? min(k0 + kc, g.nz) : k0;
+    const bool live = i < g.nx && j < g.ny;
+    PlaneRegs prv, cur, nxt;
+    load_plane(g, u, mf, i, j, k0 < k1 ? k0 - 1 : -1, tx, ty, prv);
+    load_plane(g, u, mf, i, j, k0 < k1 ? k0 : -1, tx, ty, cur);
     double cmax = 0.0;
-    for (int t = pos; t < tiles_per_run; t += blocks_per_run) {
-        const int64_t i = ((int64_t)run * tiles_per_run + t) * blockDim.x + threadIdx.x;
-        if (i >= nv) continue;
-        const uint32_t i32 = (uint32_t)i, row = i32 / (uint32_t)g.nx;
-        const int64_t c[3] = {i32 - row * (uint32_t)g.nx, row % (uint32_t)g.ny, row / (uint32_t)g.ny};
-        const int64_t dims[3] = {g.nx, g.ny, g.nz};
-        const int64_t strides[3] = {1, g.nx, (int64_t)g.nx * g.ny};
-        // every operand loaded before any is used (a missing neighbour reads
-        // the voxel itself and its face is skipped)
-        bool lo[3], hi[3];
-        double ui[3], um[3], up[3], mm[3], mp[3];
-        const double mi = mf[i];
+    for (int k = k0; k < k1; ++k) {
+        const int bf = k & 1;
+        smf[bf][ty + 1][tx + 1] = cur.mf;
+        sux[bf][ty + 1][tx + 1] = cur.ux;
+        suy[bf][ty + 1][tx + 1] = cur.uy;
+        if (tx == 0) { smf[bf][ty + 1][0] = cur.hx_mf; sux[bf][ty + 1][0] = cur.hx_u; }
+        if (tx == kAT - 1) { smf[bf][ty + 1][kAT + 1] = cur.hx_mf; sux[bf][ty + 1][kAT + 1] = cur.hx_u; }
+        if (ty == 0) { smf[bf][0][tx + 1] = cur.hy_mf; suy[bf][0][tx + 1] = cur.hy_u; }
+        if (ty == kAT - 1) { smf[bf][kAT + 1][tx + 1] = cur.hy_mf; suy[bf][kAT + 1][tx + 1] = cur.hy_u; }
+        load_plane(g, u, mf, i, j, k + 1, tx, ty, nxt);
+        __syncthreads();
+        if (live) {
+            // the same faces, operations and order as a voxel-by-voxel sweep:
+            // inflow through the lower faces (z, y, x), then outflow through the
+            // upper ones (x, y, z); per face (lower voxel a, upper b):
+            // u_f = (u_a + u_b) / 2, flux dt u_f m_donor / l0
+            const double mi = cur.mf;
+            const double ui[3] = {cur.ux, cur.uy, cur.uz};
+            const bool lo[3] = {i > 0, j > 0, k > 0};
+            const bool hi[3] = {i + 1 < g.nx, j + 1 < g.ny, k + 1 < g.nz};
+            const double um[3] = {sux[bf][ty + 1][tx], suy[bf][ty][tx + 1], prv.uz};
+            const double mm[3] = {smf[bf][ty + 1][tx], smf[bf][ty][tx + 1], prv.mf};
+            const double up[3] = {sux[bf][ty + 1][tx + 2], suy[bf][ty + 2][tx + 1], nxt.uz};
+            const double mp[3] = {smf[bf][ty + 1][tx + 2], smf[bf][ty + 2][tx + 1], nxt.mf};
+            double m = mi;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = c[d] > 0;
-            hi[d] = c[d] + 1 < dims[d];
-            const int64_t jm = lo[d] ? i - strides[d] : i, jp = hi[d] ? i + strides[d] : i;
-            ui[d] = u[3 * i + d];
-            um[d] = u[3 * jm + d];
-            up[d] = u[3 * jp + d];
-            mm[d] = mf[jm];
-            mp[d] = mf[jp];
+            for (int d = 2; d >= 0; --d)
+                if (lo[d]) {
+                    const double uf = 0.5 * (um[d] + ui[d]);
+                    m += dt * uf * (uf > 0.0 ? mm[d] : mi) / g.l0;
+                }
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                if (hi[d]) {
+                    const double uf = 0.5 * (ui[d] + up[d]);
+                    m -= dt * uf * (uf > 0.0 ? mi : mp[d]) / g.l0;
+                    cmax = fmax(cmax, fabs(uf) * dt / g.l0);
+                }
+            out[(int64_t)k * g.nx * g.ny + (int64_t)j * g.nx + i] = m;
         }
-        // inflow through the lower faces, then outflow through the upper ones,
-        // each face's donors in increasing voxel order (the sum's order is that
-        // of a sweep over the faces by their lower voxel); per face (lower
-        // voxel a, upper b): u_f = (u_a + u_b) / 2, flux dt u_f m_donor / l0
-        double m = mi;
-#pragma unroll
-        for (int d = 2; d >= 0; --d)
-            if (lo[d]) {
-                const double uf = 0.5 * (um[d] + ui[d]);
-                m += dt * uf * (uf > 0.0 ? mm[d] : mi) / g.l0;
-            }
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-            if (hi[d]) {
-                const double uf = 0.5 * (ui[d] + up[d]);
-                m -= dt * uf * (uf > 0.0 ? mi : mp[d]) / g.l0;
-                cmax = fmax(cmax, fabs(uf) * dt / g.l0);
-            }
-        out[i] = m;
+        prv = cur;
+        cur = nxt;
     }
     __shared__ double wmax[kBlk / 64];
     for (int o = 32; o > 0; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o));
@@ -183,18 +230,37 @@ __global__ void k_max_reduce(const double* bmax, int n, unsigned long long* bits
     }
 }
 
-int advect_max_blocks() { return 8 * kAdvectBlocksPerRun; }
+// tiles of kAT x kAT columns, each through chunks of kc planes: at most
+// kAdvectTargetBlocks blocks unless the tiles alone are more
+static void advect_shape(const tr_voxel_grid& g, int& tiles_x, int& tiles_y, int& kc, int& chunks)
+{
+    tiles_x = (int)cdiv(g.nx, kAT);
+    tiles_y = (int)cdiv(g.ny, kAT);
+    const int64_t tiles = (int64_t)tiles_x * tiles_y;
+    int64_t want = std::max<int64_t>(1, kAdvectTargetBlocks / tiles);
+    want = std::min<int64_t>(want, cdiv(g.nz, 16));  // at least 16 planes a chunk
+    want = std::max<int64_t>(want, 1);
+    kc = (int)cdiv(g.nz, want);
+    chunks = (int)cdiv(g.nz, kc);
+}
+
+int64_t advect_blocks(const tr_voxel_grid& g)
+{
+    int tx, ty, kc, ch;
+    advect_shape(g, tx, ty, kc, ch);
+    return 8 * cdiv((int64_t)tx * ty * ch, 8);
+}
 
 void launch_advect(const tr_voxel_grid& g, double dt, const double* u, const double* mf_in, double* mf_out,
                    double* bmax, unsigned long long* cfl_bits, hipStream_t s)
 {
-    const int64_t nv = (int64_t)g.nx * g.ny * g.nz;
-    const int tiles_per_run = (int)cdiv(cdiv(nv, kBlk), 8);
-    const int blocks_per_run = std::min(tiles_per_run, kAdvectBlocksPerRun);
-    const int nb = 8 * blocks_per_run;
-    hipLaunchKernelGGL(k_advect, dim3((unsigned)nb), dim3(kBlk), 0, s, g, dt, u, mf_in, mf_out, bmax, tiles_per_run,
-                       blocks_per_run);
-    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kBlk), 0, s, bmax, nb, cfl_bits);
+    int tiles_x, tiles_y, kc, chunks;
+    advect_shape(g, tiles_x, tiles_y, kc, chunks);
+    const int64_t nb = (int64_t)tiles_x * tiles_y * chunks;
+    const int per = (int)cdiv(nb, 8);
+    hipLaunchKernelGGL(k_advect, dim3((unsigned)(8 * per)), dim3(kBlk), 0, s, g, dt, u, mf_in, mf_out, bmax, tiles_x,
+                       tiles_y, kc, (int)nb, per);
+    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kBlk), 0, s, bmax, 8 * per, cfl_bits);
 }
 
 // ---------------------------------------------------------------------------
