@@ -425,23 +425,28 @@ __global__ void k_convert_deposit(tr_voxel_grid g, double rho_b, double w_dep, W
 // The deposit on tiles of kTileCols neighbouring columns of at most kTileNz
 // voxels.  Columns are strided by nx ny in memory, so a column read by one
 // wave touches a cache line per voxel; the tile is read instead as whole
-// lines (each wave instruction: 16 columns at 4 heights) into LDS.  The
-// voxels whose fluid falls are marked in parallel (bit masks per column), as
-// is each column's first non-full voxel; one thread per column then replays
-// the fills over its marked voxels in increasing height, as the per-thread
-// kernel does, on LDS, and the block writes back what changed.
+// lines (each wave instruction: 16 columns at 4 heights), with all of a
+// thread's loads in flight at once.  The voxels whose fluid falls are marked
+// in parallel (bit masks per column), as is each column's first non-full
+// voxel; one thread per column then replays the fills over its marked voxels
+// in increasing height, as the per-thread kernel does.  Fills start at the
+// first non-full voxel and rarely climb far: occupancy and compaction of the
+// kWin voxels from there are held in LDS (a fill beyond them reads and writes
+// memory directly), which keeps the block's LDS small enough for six blocks
+// per CU.  The block writes back what changed.
 constexpr int kTileCols = 16;
 constexpr int kTileNz = 128;
 constexpr int kTileRows = kBlk / kTileCols;  // heights per pass
 constexpr int kTileWords = kTileNz / 64;
+constexpr int kWin = 32;
 
 __global__ void __launch_bounds__(kBlk) k_convert_deposit_tile(tr_voxel_grid g, double rho_b, double w_dep,
                                                                WedgeSet ws, const double* rho_p, double* phi,
                                                                double* wc, double* mf, double* total)
 {
 #pragma clang fp contract(off)
-    // (+1: a column's heights start two banks after the previous column's)
-    __shared__ double P[kTileCols][kTileNz + 1], W[kTileCols][kTileNz + 1], M[kTileCols][kTileNz + 1];
+    // (+1: a column's entries start two banks after the previous column's)
+    __shared__ double M[kTileCols][kTileNz + 1], P[kTileCols][kWin + 1], W[kTileCols][kWin + 1];
     __shared__ unsigned long long mask[kTileCols][kTileWords];
     __shared__ int first_free[kTileCols], range[kTileCols][2];
     __shared__ double ssum[kTileCols];
@@ -481,8 +486,8 @@ __global__ void __launch_bounds__(kBlk) k_convert_deposit_tile(tr_voxel_grid g, 
     bool work = false;
     for (int w = 0; w < kTileWords; ++w) work |= mask[col][w] != 0ull;
     work &= live;
+    double pv[kPer], wv[kPer];
     if (work) {
-        double pv[kPer], wv[kPer];
 #pragma unroll
         for (int t = 0; t < kPer; ++t) {
             const int k = row + t * kTileRows;
@@ -492,10 +497,19 @@ __global__ void __launch_bounds__(kBlk) k_convert_deposit_tile(tr_voxel_grid g, 
 #pragma unroll
         for (int t = 0; t < kPer; ++t) {
             const int k = row + t * kTileRows;
-            if (k >= nz) continue;
-            P[col][k] = pv[t];
-            W[col][k] = wv[t];
-            if (!(pv[t] >= 1.0)) atomicMin(&first_free[col], k);
+            if (k < nz && !(pv[t] >= 1.0)) atomicMin(&first_free[col], k);
+        }
+    }
+    __syncthreads();
+    const int ff = first_free[col];
+    if (work) {
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int k = row + t * kTileRows;
+            if (k < nz && k >= ff && k < ff + kWin) {
+                P[col][k - ff] = pv[t];
+                W[col][k - ff] = wv[t];
+            }
         }
     }
     __syncthreads();
@@ -504,7 +518,9 @@ __global__ void __launch_bounds__(kBlk) k_convert_deposit_tile(tr_voxel_grid g, 
         int klo = nz, khi = -1;
         if (work) {
             const double V0 = g.l0 * g.l0 * g.l0;
-            int kfree = first_free[col];  // the first voxel that is not full
+            // occupancy and compaction of voxel kk: LDS inside the window, memory above it
+            auto pget = [&](int kk) { return kk < ff + kWin ? P[col][kk - ff] : phi[(int64_t)kk * nxy + c]; };
+            int kfree = ff;  // the first voxel that is not full
             for (int w = 0; w < kTileWords; ++w) {
                 unsigned long long mk = mask[col][w];
                 while (mk) {
@@ -512,17 +528,26 @@ __global__ void __launch_bounds__(kBlk) k_convert_deposit_tile(tr_voxel_grid g, 
                     mk &= mk - 1;
                     double m = M[col][k];
                     int kk = kfree;
-                    while (kk < nz && P[col][kk] >= 1.0) ++kk;
+                    while (kk < nz && pget(kk) >= 1.0) ++kk;
                     kfree = kk;
                     klo = kk < klo ? kk : klo;
                     while (m > 0.0 && kk < nz) {
-                        const double f0 = P[col][kk];
+                        const bool in_win = kk < ff + kWin;
+                        const int64_t id = (int64_t)kk * nxy + c;
+                        const double f0 = in_win ? P[col][kk - ff] : phi[id];
+                        const double w0 = in_win ? W[col][kk - ff] : wc[id];
                         const double cap = (1.0 - f0) * w_dep * rho_b * V0;
                         const double take = m < cap ? m : cap;
                         const double f = take == cap ? 1.0 : f0 + take / (w_dep * rho_b * V0);
-                        const double before = W[col][kk] * rho_b * V0 * f0;
-                        W[col][kk] = f0 > 0.0 ? (before + take) / (rho_b * V0 * f) : w_dep;
-                        P[col][kk] = f;
+                        const double before = w0 * rho_b * V0 * f0;
+                        const double wn = f0 > 0.0 ? (before + take) / (rho_b * V0 * f) : w_dep;
+                        if (in_win) {
+                            W[col][kk - ff] = wn;
+                            P[col][kk - ff] = f;
+                        } else {
+                            wc[id] = wn;
+                            phi[id] = f;
+                        }
                         khi = kk > khi ? kk : khi;
                         sum += take;
                         m -= take;
@@ -542,9 +567,9 @@ __global__ void __launch_bounds__(kBlk) k_convert_deposit_tile(tr_voxel_grid g, 
         for (int k = row; k < nz; k += kTileRows) {
             const int64_t id = (int64_t)k * nxy + c;
             if ((mask[col][k >> 6] >> (k & 63)) & 1ull) mf[id] = M[col][k];
-            if (k >= klo && k <= khi) {
-                phi[id] = P[col][k];
-                wc[id] = W[col][k];
+            if (k >= klo && k <= khi && k < ff + kWin) {  // (above the window: written by the fills)
+                phi[id] = P[col][k - ff];
+                wc[id] = W[col][k - ff];
             }
         }
     }

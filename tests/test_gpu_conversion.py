@@ -73,6 +73,10 @@ def ragged_state(seed, dims=(37, 29, 23), l0=0.05):
     wc = rng.uniform(0.8, 1.0, phi.shape)
     mf = np.where((phi == 0) & (rng.uniform(size=phi.shape) < 0.2), rng.uniform(0, 0.3, phi.shape), 0.0)
     rho_p = np.where(rng.uniform(size=phi.shape) < 0.25, 1.0, 0.0)
+    if nz >= 64:
+        # an empty column receives 60 voxels' worth of loose solid: its fills climb far
+        mf[nz - 1, 0, 0] = 60 * 0.9 * 1700.0 * l0 ** 3
+        rho_p[nz - 1, 0, 0] = 0.0
     top = nz * l0
     wedges = [rankine(0.3, 0.2 * top, math.radians(28), 0.95 * top, 0.1, 0.6),
               rankine(0.5, 0.3 * top, math.radians(35), 0.95 * top, 0.6, 1.2), np.zeros((0, 4))]
@@ -107,8 +111,9 @@ def check_exact(got, ref):
 
 
 # columns of up to 128 voxels take the tiled deposit (16 columns a block), taller ones the
-# thread-per-column one
-@pytest.mark.parametrize("seed,dims", [(1, (37, 29, 23)), (2, (37, 29, 23)), (3, (9, 7, 300))])
+# thread-per-column one; the 100-voxel columns include a fill that climbs past the tiled
+# kernel's LDS window of 32 voxels
+@pytest.mark.parametrize("seed,dims", [(1, (37, 29, 23)), (2, (37, 29, 23)), (4, (11, 9, 100)), (3, (9, 7, 300))])
 def test_cut_deposit_surface_bit_exact_on_a_ragged_grid(seed, dims):
     st, wedges = ragged_state(seed, dims)
     got = run_gpu(any_scene(), st, wedges)
