@@ -42,7 +42,7 @@ PGS_TRAFFIC = {"kernels_sha256_prefix": "5d6dc0bfd68b6d0b", "bytes_per_launch": 
 
 # The same for k_advect on the 256 x 256 x 128 voxel grid
 # (profiles/k_advect_voxels256_kernel_trace.md), keyed to terrain_voxels.hip.
-ADVECT_TRAFFIC = {"kernels_sha256_prefix": "d34aab49b5576b9b", "bytes_per_launch": 0.3758e9,
+ADVECT_TRAFFIC = {"kernels_sha256_prefix": "9a71cd6bece22f79", "bytes_per_launch": 0.3756e9,
                   "profile": "profiles/k_advect_voxels256_kernel_trace.md"}
 
 

@@ -4,13 +4,15 @@
 //   coarse-grain      particle mass and momentum into voxel densities (FP64
 //                     atomics), velocity u = p / rho (Eq. cg_velocity)
 //   advect            conserved donor-cell advection of fluidized mass
-//                     (Eq. advection), one thread per voxel, XCD-contiguous
-//                     runs of rows
+//                     (Eq. advection), 16 x 16-column tiles marching through
+//                     runs of planes
 //   convert cut       solid above the predicted zone's bottom becomes fluid
 //   convert deposit   particle-free fluid outside the zones becomes solid at
-//                     the column's surface
+//                     the column's surface (tiles of 16 columns on LDS)
 //   surface           Eq. surface per column, into the terrain heightfield
 //   grow              particles grow from their voxel's fluid (Eq. eqmotmb)
+//   form              new particles from the fluid inside the zones
+//   settle            particles at rest outside the zones back to fluid
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -274,13 +276,21 @@ __global__ void k_surface(tr_voxel_grid g, const double* phi, double* h, float* 
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nxy) return;
     double z = g.origin[2];
-    for (int k = g.nz - 1; k >= 0; --k) {  // Eq. surface at the top-most voxel with solid
-        const double f = phi[(int64_t)k * nxy + c];
-        if (f > 0.0) {
-            const double zc = g.origin[2] + (k + 0.5) * g.l0;
-            z = zc + (f - 0.5) * g.l0;
-            break;
-        }
+    // Eq. surface at the top-most voxel with solid, searched downwards kChunk
+    // voxels at a time with every load in flight
+    constexpr int kChunk = 8;
+    bool found = false;
+    for (int k1 = g.nz - 1; k1 >= 0 && !found; k1 -= kChunk) {
+        double fc[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) fc[q] = k1 - q >= 0 ? phi[(int64_t)(k1 - q) * nxy + c] : 0.0;
+        for (int q = 0; q < kChunk && !found; ++q)
+            if (fc[q] > 0.0) {
+                const int k = k1 - q;
+                const double zc = g.origin[2] + (k + 0.5) * g.l0;
+                z = zc + (fc[q] - 0.5) * g.l0;
+                found = true;
+            }
     }
     if (h) h[c] = z;
     if (hf) hf[c] = (float)z;
@@ -334,16 +344,35 @@ __global__ void k_convert_cut(tr_voxel_grid g, double rho_b, WedgeSet ws, double
     if (zcut == INFINITY) return;
     const double V0 = g.l0 * g.l0 * g.l0;
     double sum = 0.0;
-    for (int k = 0; k < g.nz; ++k) {
-        const int64_t id = (int64_t)k * nxy + c;
-        double t = (zcut - (g.origin[2] + k * g.l0)) / g.l0;  // occupancy below the cut
-        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-        const double f = phi[id];
-        if (f > t) {
-            const double dm = wc[id] * rho_b * V0 * (f - t);
-            mf[id] += dm;
-            sum += dm;
-            phi[id] = t;
+    // voxels a whole voxel or more below the cut keep their solid (occupancy
+    // is at most 1): start one voxel below the cut's, then read kChunk voxels
+    // at a time with every load in flight
+    const double kc = floor((zcut - g.origin[2]) / g.l0) - 1.0;
+    const int k_start = kc <= 0.0 ? 0 : (kc >= (double)g.nz ? g.nz : (int)kc);
+    constexpr int kChunk = 8;
+    for (int k0 = k_start; k0 < g.nz; k0 += kChunk) {
+        double fc[kChunk], wcc[kChunk], mc[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            const bool in = k0 + q < g.nz;
+            const int64_t id = (int64_t)(k0 + q) * nxy + c;
+            fc[q] = in ? phi[id] : 0.0;
+            wcc[q] = in ? wc[id] : 0.0;
+            mc[q] = in ? mf[id] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            const int k = k0 + q;
+            if (k >= g.nz) break;
+            double t = (zcut - (g.origin[2] + k * g.l0)) / g.l0;  // occupancy below the cut
+            t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+            if (fc[q] > t) {
+                const int64_t id = (int64_t)k * nxy + c;
+                const double dm = wcc[q] * rho_b * V0 * (fc[q] - t);
+                mf[id] = mc[q] + dm;
+                sum += dm;
+                phi[id] = t;
+            }
         }
     }
     if (total && sum > 0.0) atomicAdd(total, sum);
