@@ -331,3 +331,32 @@ def test_settle_particles_matches_oracle_and_steps_on():
     assert len(g.get_particles(0)["r"]) == n - cnt
     with pytest.raises(T.TerrainError):
         g.remove_particles(0, [n - cnt])  # past the env's last id
+
+
+def test_remove_particles_across_envs():
+    # three envs; removing from the middle one leaves the others as they were,
+    # renumbers it in order, and every env steps on
+    specs = [SG.column_scene(seed=40 + e, n=300 + 50 * e, footprint=0.6, sweeps=10) for e in range(3)]
+    g = T.scene_from_specs(specs)
+    g.step(1)
+    before = [g.get_particles(e) for e in range(3)]
+    n1 = len(before[1]["r"])
+    gone = np.zeros(n1, dtype=bool)
+    gone[[0, 5, 6, 7, 100, n1 - 1]] = True
+    g.remove_particles(1, np.nonzero(gone)[0] + g_first_id(g, 1))
+    after = [g.get_particles(e) for e in range(3)]
+    for e in (0, 2):
+        for q in ("x", "v", "w", "r"):
+            assert np.array_equal(after[e][q], before[e][q]), (e, q)
+    for q in ("x", "v", "w", "r"):
+        assert np.array_equal(after[1][q], before[1][q][~gone]), q
+    st = g.step(2)
+    assert [len(g.get_particles(e)["r"]) for e in range(3)] == [len(before[0]["r"]), n1 - 6, len(before[2]["r"])]
+    assert all(s["contacts"] > 0 for s in st)
+    with pytest.raises(T.TerrainError):
+        g.remove_particles(1, [g_first_id(g, 1), g_first_id(g, 1)])  # repeated
+
+
+def g_first_id(g, env):
+    # ids of env e start at e * cap_particles
+    return env * g._desc.cap_particles
