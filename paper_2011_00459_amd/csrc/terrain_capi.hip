@@ -1074,7 +1074,7 @@ int advect_fluid(tr_scene* s, const tr_voxel_grid* g, double dt, const double* u
         if (!alloc_n(s, s->adv_bmax, nb)) return fail(s, TR_E_NOMEM, "advect_fluid");
         s->adv_cap = nb;
     }
-    launch_advect(*g, dt, u, mf_in, mf_out, s->adv_bmax, bits, s->stream);
+    launch_advect(*g, dt, u, mf_in, mf_out, s->adv_bmax, cfl ? bits : nullptr, s->stream);  // no reduction unasked
     HIP_CHECK(s, hipGetLastError());
     if (!cfl) return TR_OK;
     unsigned long long h = 0;

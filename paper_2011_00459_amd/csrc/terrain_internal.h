@@ -311,7 +311,7 @@ void launch_settle(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g,
 void launch_grow(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, double dt, double dprime_max,
                  double d_max, double* mf, double* work, double* total, hipStream_t s);
 // mesoscale voxel fields (device arrays of the caller); cfl_bits: one
-// device uint64 receiving the largest Courant number's bits
+// device uint64 receiving the largest Courant number's bits (NULL: not reduced)
 void launch_coarse_grain(const DevBuffers& b, const EnvDev& E, const tr_voxel_grid& g, int kernel, double R,
                          double* rho, double* mom, double* u, hipStream_t s);
 constexpr int kAdvectTargetBlocks = 2048;  // about 8 blocks per CU

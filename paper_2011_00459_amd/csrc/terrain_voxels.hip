@@ -262,7 +262,7 @@ void launch_advect(const tr_voxel_grid& g, double dt, const double* u, const dou
     const int per = (int)cdiv(nb, 8);
     hipLaunchKernelGGL(k_advect, dim3((unsigned)(8 * per)), dim3(kBlk), 0, s, g, dt, u, mf_in, mf_out, bmax, tiles_x,
                        tiles_y, kc, (int)nb, per);
-    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kBlk), 0, s, bmax, 8 * per, cfl_bits);
+    if (cfl_bits) hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kBlk), 0, s, bmax, 8 * per, cfl_bits);
 }
 
 // ---------------------------------------------------------------------------
