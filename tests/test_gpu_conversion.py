@@ -62,7 +62,7 @@ def rankine(ex, ez, theta, top, y0, y1):
                      [0.0, 1.0, 0.0, y1], [0.0, -1.0, 0.0, -y0]])
 
 
-def ragged_state(seed, dims=(37, 29, 23), l0=0.05):
+def ragged_state(seed, dims=(37, 29, 23), l0=0.05, many=False):
     rng = np.random.default_rng(seed)
     nx, ny, nz = dims
     h = rng.uniform(0.2, 0.9, (ny, nx)) * nz * l0
@@ -80,6 +80,9 @@ def ragged_state(seed, dims=(37, 29, 23), l0=0.05):
     top = nz * l0
     wedges = [rankine(0.3, 0.2 * top, math.radians(28), 0.95 * top, 0.1, 0.6),
               rankine(0.5, 0.3 * top, math.radians(35), 0.95 * top, 0.6, 1.2), np.zeros((0, 4))]
+    if many:  # more wedges than the kernels stage in LDS: they read them from memory
+        wedges = [rankine(0.2 + 0.05 * q, (0.15 + 0.01 * q) * top, math.radians(25 + q), 0.95 * top, 0.06 * q,
+                          0.06 * q + 0.1) for q in range(20)]
     return dict(phi=phi, wc=wc, mf=mf, rho_p=rho_p, origin=(0.0, 0.0, 0.0), l0=l0, dims=dims, rho_b=1700.0,
                 w_dep=0.9), wedges
 
@@ -113,9 +116,10 @@ def check_exact(got, ref):
 # columns of up to 128 voxels take the tiled deposit (16 columns a block), taller ones the
 # thread-per-column one; the 100-voxel columns include a fill that climbs past the tiled
 # kernel's LDS window of 32 voxels
-@pytest.mark.parametrize("seed,dims", [(1, (37, 29, 23)), (2, (37, 29, 23)), (4, (11, 9, 100)), (3, (9, 7, 300))])
-def test_cut_deposit_surface_bit_exact_on_a_ragged_grid(seed, dims):
-    st, wedges = ragged_state(seed, dims)
+@pytest.mark.parametrize("seed,dims,many", [(1, (37, 29, 23), False), (2, (37, 29, 23), False), (5, (37, 29, 23), True),
+                                            (4, (11, 9, 100), False), (3, (9, 7, 300), False)])
+def test_cut_deposit_surface_bit_exact_on_a_ragged_grid(seed, dims, many):
+    st, wedges = ragged_state(seed, dims, many=many)
     got = run_gpu(any_scene(), st, wedges)
     ref = run_oracle(st, wedges)
     assert ref["lib"] > 1.0 and ref["dep"] > 0.1
