@@ -264,9 +264,12 @@ int coarse_grain(tr_scene* s, int32_t env, const tr_voxel_grid* g, int32_t kerne
  * surface voxel.  Wedges: n_wedges wedges of counts[w] half-spaces each
  * (host arrays; planes holds 5 x 4 doubles per wedge, inside iff
  * n . x <= d), or, with planes NULL, the wedges the last step predicted for
- * every tool of env.  A total pointer, when not NULL, receives the converted
- * mass (the call then synchronises the stream); with NULL the call only
- * enqueues work on the scene's stream.  TR_E_INVAL for a bad env, grid,
+ * every tool of env (caller wedges are copied to the device, which
+ * synchronises the stream).  A total pointer, when not NULL, receives the
+ * converted mass (the call then synchronises the stream); with predicted
+ * wedges and NULL totals the call only enqueues kernels on the scene's
+ * stream (no memset: it may be captured in a graph once the scene's one
+ * double of scratch exists, after a first call).  TR_E_INVAL for a bad env, grid,
  * density or wedge count (at most 128 caller wedges, 8 tools), TR_E_STATE for
  * predicted wedges before a step. */
 
@@ -350,8 +353,10 @@ int settle_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double v_
  * is conserved to rounding.  u (3 per voxel), mf_in, mf_out: device arrays
  * (mf_out must not alias mf_in).  *cfl, when cfl is not NULL, receives the
  * largest |u_f| dt / l0 (positivity needs <= 1; the call then synchronises
- * the stream to read it; with NULL it only enqueues the step).
- * TR_E_INVAL for a bad grid or pointers. */
+ * the stream to read it; with NULL it only enqueues the step).  The scene
+ * keeps a small array of per-block maxima, allocated on the first call and
+ * when a larger grid needs more blocks.  TR_E_INVAL for a bad grid or
+ * pointers, TR_E_NOMEM. */
 int advect_fluid(tr_scene* s, const tr_voxel_grid* g, double dt, const double* u, const double* mf_in,
                  double* mf_out, double* cfl);
 
