@@ -1516,11 +1516,19 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
     };
     auto resid = [](double sn, double sd) { return sd > 0.0 ? sqrt(sn) / sqrt(sd) : (sn > 0.0 ? 1.0 : 0.0); };
     uint32_t lo = 0, hi = 0, c = 0;
-    RowRegs cur;
+    // a thread's first contact of a colour and, when the colour needs a second
+    // pass, its second: both fetched ahead (while the block waits at a barrier)
+    // (512-thread blocks only: the 1024-thread instances have no registers to spare)
+    constexpr bool kPair = !FLOW && NW <= 8;
+    RowRegs cur, cur2;
+    auto fetch = [&]() {
+        if (c < hi) cur = load_rows(b, c, ROLL);
+        if (kPair && c + kThreads < hi) cur2 = load_rows(b, c + kThreads, ROLL);
+    };
     if (ncol > 0) {
         range(0, lo, hi);
         c = lo + threadIdx.x;
-        if (c < hi) cur = load_rows(b, c, ROLL);
+        fetch();
     }
 #ifdef TRK_PGS_TRACE
     unsigned long long tr[4] = {0, 0, 0, 0}, tprev = wall_clock64(), tw[12] = {}, ta2[12] = {}, tw2[12] = {};
@@ -1534,6 +1542,23 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
             if (!FLOW) __builtin_amdgcn_s_waitcnt(0);
             while (c < hi) {
                 uint32_t cn = c + kThreads;
+                if (kPair && cn < hi) {
+                    // two contacts of one colour share no sphere: both gathers
+                    // in flight before either update (same order of updates
+                    // and of the residual sums as one contact at a time)
+                    BodyRegs B1 = load_bodies(ba, cur);
+                    BodyRegs B2 = load_bodies(ba, cur2);
+                    const uint32_t c3 = cn + kThreads;
+                    RowRegs n1, n2;
+                    if (c3 < hi) n1 = load_rows(b, c3, ROLL);
+                    if (c3 + kThreads < hi) n2 = load_rows(b, c3 + kThreads, ROLL);
+                    pgs_contact(b, ba, c, cur, B1, p.mu, p.gamma_dt, num, den, ROLL);
+                    pgs_contact(b, ba, cn, cur2, B2, p.mu, p.gamma_dt, num, den, ROLL);
+                    cur = n1;
+                    cur2 = n2;
+                    c = c3;
+                    continue;
+                }
                 BodyRegs B;
                 if (!FLOW) B = load_bodies(ba, cur);
                 RowRegs nxt;
@@ -1564,7 +1589,7 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                 __builtin_amdgcn_s_waitcnt(0);
                 range(col + 1, lo, hi);
                 c = lo + threadIdx.x;
-                if (c < hi) cur = load_rows(b, c, ROLL);
+                fetch();
                 __syncthreads();
             } else if (CLUSTER && !FLOW) {
                 if (col + 1 == ncol && (p.tol > 0.f || sw == 0 || sw + 1 == sweeps_cap)) {
@@ -1584,7 +1609,7 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                 // the next phase's first rows are fetched while the block waits
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
                 c = lo + threadIdx.x;
-                if (c < hi) cur = load_rows(b, c, ROLL);
+                fetch();
 #ifdef TRK_PGS_TRACE
                 unsigned long long tb = wall_clock64();
 #endif
@@ -1598,7 +1623,7 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
             } else {
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
                 c = lo + threadIdx.x;
-                if (c < hi) cur = load_rows(b, c, ROLL);
+                fetch();
                 if (!CLUSTER) __syncthreads();
             }
         }

@@ -200,3 +200,25 @@ def test_autotune_keeps_state_caches_and_changes_nothing(tmp_path):
     g3.step(4)
     for e in range(len(specs)):
         assert np.array_equal(g.get_particles(e)["v"], g3.get_particles(e)["v"])
+
+
+def test_two_contacts_per_thread_colours_are_bitwise_identical():
+    # one block per XCD group: a colour of more than 512 contacts gives each
+    # thread two (gathered together); the per-env schedule takes them one at
+    # a time: the states must agree bit for bit, and with the oracle
+    spec = jammed_bed(seed=61, nx=24, ny=16, nz=8)
+    spec = with_(spec, max_sweeps=20, warm_start="prev")
+    states = {}
+    for name, cfg in (("grouped_1", dict(mode="grouped", blocks_per_xcd=1)), ("per_env", SCHEDULES["per_env_global"])):
+        g = T.scene_from_specs(spec)
+        g.set_solver_config(**cfg)
+        st = g.step(2)
+        states[name] = (g.get_particles(0), st[0])
+    a, b = states["grouped_1"], states["per_env"]
+    assert a[1]["contacts"] > 16 * 512  # colours of several hundred contacts
+    for q in ("x", "v", "w"):
+        assert np.array_equal(a[0][q], b[0][q]), q
+    o = O.OracleScene(spec)
+    o.step()
+    o.step()
+    assert np.max(np.abs(a[0]["v"] - o.v)) <= vel_tol(o.v) * 5
