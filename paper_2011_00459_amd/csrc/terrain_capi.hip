@@ -44,6 +44,7 @@ struct tr_scene {
     bool tables_dirty = true;
     bool have_prev = false;
     bool stepped = false;
+    bool graph_events = false;        // the step graphs record the phase events themselves
     std::vector<std::pair<void*, size_t>> allocs;
     int64_t cells_alloc = 0;
     int64_t zone_chunk_alloc = 0;
@@ -847,17 +848,26 @@ int capture_graphs(tr_scene* s)
 {
     invalidate_graphs(s);
     if (!s->cap_stream) HIP_CHECK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
-    for (int q = 0; q < 2; ++q) {
-        hipGraph_t g = nullptr;
-        HIP_CHECK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-        enqueue_step(s, s->cap_stream, false);
-        hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
-        if (e == hipSuccess) e = hipGraphInstantiate(&s->gexec[q], g, nullptr, nullptr, 0);
-        if (g) (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            invalidate_graphs(s);
-            return hip_fail(s, e, "step graph capture");
+    // the phase events are captured as event nodes, so that a replay times
+    // its own phases; a runtime that cannot capture them gets graphs without
+    // them (the events then bracket the whole replay)
+    for (int with_events = 1; with_events >= 0; --with_events) {
+        hipError_t e = hipSuccess;
+        for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+            hipGraph_t g = nullptr;
+            HIP_CHECK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+            enqueue_step(s, s->cap_stream, with_events != 0);
+            e = hipStreamEndCapture(s->cap_stream, &g);
+            if (e == hipSuccess) e = hipGraphInstantiate(&s->gexec[q], g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
         }
+        if (e == hipSuccess) {
+            s->graph_events = with_events != 0;
+            break;
+        }
+        invalidate_graphs(s);
+        (void)hipGetLastError();
+        if (!with_events) return hip_fail(s, e, "step graph capture");
     }
     s->graphs = true;
     s->parity = 0;
@@ -899,9 +909,10 @@ static int step_scene(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
             if (rc) return rc;
         }
         if (s->graphs && s->have_prev) {
-            (void)hipEventRecord(s->ev[0], st);
+            if (!s->graph_events) (void)hipEventRecord(s->ev[0], st);
             HIP_CHECK(s, hipGraphLaunch(s->gexec[s->parity], st));
-            for (int q = 1; q < 5; ++q) (void)hipEventRecord(s->ev[q], st);
+            if (!s->graph_events)
+                for (int q = 1; q < 5; ++q) (void)hipEventRecord(s->ev[q], st);
             swap_particle_buffers(s);
             swap_step_buffers(s);
         } else {
