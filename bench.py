@@ -77,11 +77,12 @@ def build_bed(args):
     spec["bodies"] = spec["bodies"] + [blade]
     spec["warm_start"] = "prev"
     sc = T.scene_from_specs(spec, cap_contacts=16 * args.n)
-    # eager launches (measured faster than step-graph replays for this bed:
-    # PGS 8.97 against 9.54-9.60 ms on one box); --graphs replays the step
-    # graphs, whose phase events are nodes of the graphs.  The HIP events time
-    # the PGS launch inside the timed region either way.
-    sc.set_step_graphs(args.graphs)
+    # eager launches (measured faster than step-graph replays: the bed's PGS
+    # 8.97 against 9.54-9.60 ms, the batch 1.52e10 against 1.48e10 contact
+    # sweeps/s, one box each); --launch graphs replays the step graphs, whose
+    # phase events are nodes of the graphs.  The HIP events time the PGS
+    # launch inside the timed region either way.
+    sc.set_step_graphs(args.launch == "graphs")
     return sc, spec, blade, est_top
 
 
@@ -165,6 +166,7 @@ def bench_batched(args):
     sc.step(1)
     if not args.schedule and not args.no_autotune:
         sc.autotune(steps=2)
+    sc.set_step_graphs(args.launch == "graphs")
     for _ in range(args.warmup):
         sc.step(1)
     device_sync()
@@ -176,7 +178,7 @@ def bench_batched(args):
     sc.step(args.steps, stats=False)
     device_sync()
     wall = time.perf_counter() - t0
-    # one eager step for the phase breakdown (graph replays are timed as a whole)
+    # one eager step for the phase breakdown
     sc.set_step_graphs(False)
     st2 = sc.step(1)
     ph = sc.get_phase_times()
@@ -191,7 +193,7 @@ def bench_batched(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batched: {len(specs)} independent beds, {n} spheres (log-uniform 500-20000 per "
                                f"bed), blade or bucket at U(0.3, 1.5) m/s, dt 1/60 s, {args.sweeps} sweeps, "
-                               f"prev warm start, step graphs",
+                               f"prev warm start, {'eager launches' if args.launch == 'eager' else 'step graphs'}",
                    "contacts_per_step": contacts, "steps_per_s": args.steps / wall,
                    "schedule": sc.get_solver_config(),
                    "eager_phase_ms": {k: float(v) for k, v in ph.items()}},
@@ -446,7 +448,8 @@ def main():
     ap.add_argument("--schedule", default="", help="PGS schedule as JSON (set_solver_config fields)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start training and evaluation")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default PGS schedule")
-    ap.add_argument("--graphs", action="store_true", help="bed: replay step graphs instead of launching every kernel")
+    ap.add_argument("--launch", choices=("eager", "graphs"), default="eager",
+                    help="launch every kernel of a step (measured faster here) or replay step graphs")
     ap.add_argument("--eval-envs", type=int, default=64, help="batched beds of the warm-start evaluation")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -482,7 +485,7 @@ def main():
     tuned = None
     if not args.schedule and not args.no_autotune:
         tuned = sc.autotune(steps=3)  # times the candidate schedules from this state, then restores it
-        sc.set_step_graphs(args.graphs)
+        sc.set_step_graphs(args.launch == "graphs")
     for _ in range(args.warmup):
         sc.step(1)
     wall, tot_cs, pgs_bytes, pgs_ms, stats = timed_steps(sc, args.steps)
