@@ -36,13 +36,13 @@ PAIR_BYTES, BOUND_BYTES = 176, 128
 # WRITE_SIZE counter runs scaled by a copy kernel of known size (see
 # profiles/k_pgs_bed50k_hbm_traffic.md); valid only for the kernel source it
 # was measured on, else reported as null.
-PGS_TRAFFIC = {"kernels_sha256_prefix": "1e6ccfe0883ec9f7", "bytes_per_launch": 3.161650e9,
+PGS_TRAFFIC = {"kernels_sha256_prefix": "1e6ccfe0883ec9f7", "bytes_per_launch": 3.136471e9,
                "profile": "profiles/k_pgs_bed50k_hbm_traffic.md"}
 
 
 # The same for k_advect on the 256 x 256 x 128 voxel grid
 # (profiles/k_advect_voxels256_kernel_trace.md), keyed to terrain_voxels.hip.
-ADVECT_TRAFFIC = {"kernels_sha256_prefix": "92ca9f936e1a6af0", "bytes_per_launch": 0.3755e9,
+ADVECT_TRAFFIC = {"kernels_sha256_prefix": "92ca9f936e1a6af0", "bytes_per_launch": 0.3757e9,
                   "profile": "profiles/k_advect_voxels256_kernel_trace.md"}
 
 
