@@ -482,7 +482,19 @@ __global__ __launch_bounds__(kBlk) void k_narrow(DevBuffers b, StepParams p, int
             b.rpair[idx] = make_int2(h, i);
         }
     }
-    if (npairs) atomicAdd((unsigned long long*)&b.env_stats[env].pairs, (unsigned long long)npairs);
+    // the pair count of the env: one atomic per wave when the wave's particles
+    // share an env (same-address atomics from every lane serialise: this one,
+    // per lane, took most of the kernel's time on a 50k-sphere bed)
+    {
+        const uint32_t env0 = __shfl(env, 0, 64);
+        if (__ballot(env != env0) == 0ull) {
+            unsigned long long t = (unsigned long long)npairs;
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+            if (lane == 0 && t) atomicAdd((unsigned long long*)&b.env_stats[env0].pairs, t);
+        } else if (npairs) {
+            atomicAdd((unsigned long long*)&b.env_stats[env].pairs, (unsigned long long)npairs);
+        }
+    }
     if (ovf) atomicOr(&b.cnt->overflow, kOvfContacts);
 }
 
@@ -659,7 +671,9 @@ __global__ __launch_bounds__(kBlk) void k_colour(DevBuffers b, int64_t cap, int 
         if (!__syncthreads_or(left)) break;
         __builtin_amdgcn_s_sleep(2);
     }
-    if (local_max) atomicMax(&b.cnt->n_colours, (uint32_t)local_max);
+    // one atomic per wave (same-address atomics from every lane serialise)
+    for (int o = 32; o > 0; o >>= 1) local_max = max(local_max, __shfl_xor(local_max, o, 64));
+    if ((threadIdx.x & 63) == 0 && local_max) atomicMax(&b.cnt->n_colours, (uint32_t)local_max);
     if (ovf) atomicOr(&b.cnt->overflow, kOvfColours);
     if (left) atomicOr(&b.cnt->overflow, kFailColouring);
 }
