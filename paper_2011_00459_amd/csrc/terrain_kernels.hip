@@ -617,6 +617,53 @@ __device__ inline int ld_colour(const int* p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+constexpr int kColChunk = 8;
+
+// Scans the conflicts of contact c.  Ready: returns true with the least
+// colour its coloured conflicts leave free (kMaxColours when none is).  Blocked by an uncoloured
+// conflict of higher priority: returns false with that conflict in wait.
+__device__ inline bool colour_try(const DevBuffers& b, uint32_t c, uint32_t& wait, int& col)
+{
+    unsigned long long key = b.ckey[c];
+    unsigned long long h = splitmix64(key);
+    int2 pr = b.cpair[c];
+    unsigned long long used = 0;
+    int parts[2] = {pr.y, pr.x};
+    for (int q = 0; q < 2; ++q) {
+        int s = parts[q];
+        if (s < 0) continue;
+        uint32_t beg = b.inc_start[s], end = b.inc_start[s + 1];
+        // eight incident contacts at a time, each round of loads in flight together
+        for (uint32_t t0 = beg; t0 < end; t0 += kColChunk) {
+            uint32_t e[kColChunk];
+            int ce[kColChunk];
+            unsigned long long ke[kColChunk];
+#pragma unroll
+            for (int j = 0; j < kColChunk; ++j) e[j] = t0 + j < end ? b.inc[t0 + j] : c;
+#pragma unroll
+            for (int j = 0; j < kColChunk; ++j) ce[j] = e[j] != c ? ld_colour(&b.colour[e[j]]) : kMaxColours;
+#pragma unroll
+            for (int j = 0; j < kColChunk; ++j) ke[j] = ce[j] < 0 ? b.ckey[e[j]] : 0ull;
+#pragma unroll
+            for (int j = 0; j < kColChunk; ++j) {
+                if (e[j] == c) continue;
+                if (ce[j] < 0) {
+                    unsigned long long he = splitmix64(ke[j]);
+                    if (he > h || (he == h && ke[j] > key)) { wait = e[j]; return false; }
+                } else {
+                    used |= 1ull << ce[j];
+                }
+            }
+        }
+    }
+    col = used == ~0ull ? kMaxColours : __builtin_ctzll(~used);
+    return true;
+}
+
+// contacts per thread whose state (coloured or not, the conflict that
+// blocked it) lives in registers; any further ones keep it in memory
+constexpr int kColRegs = 8;
+
 __global__ __launch_bounds__(kBlk) void k_colour(DevBuffers b, int64_t cap, int max_pass)
 {
     uint32_t nc = n_contacts(b, cap);
@@ -624,47 +671,44 @@ __global__ __launch_bounds__(kBlk) void k_colour(DevBuffers b, int64_t cap, int 
     uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
     int local_max = 0;
     bool ovf = false, left = true;
-    int pass = 0;
-    for (; pass < max_pass; ++pass) {
+    uint32_t done = 0;                       // bit k: contact first + k*stride is coloured
+    uint32_t wait[kColRegs];
+#pragma unroll
+    for (int k = 0; k < kColRegs; ++k) wait[k] = ~0u;
+    for (int pass = 0; pass < max_pass; ++pass) {
         left = false;
-        for (uint32_t c = first; c < nc; c += stride) {
+        // while the conflict that blocked a contact last pass is uncoloured the
+        // contact stays blocked: those colours are loaded together
+        int wc[kColRegs];
+#pragma unroll
+        for (int k = 0; k < kColRegs; ++k) {
+            uint32_t c = first + (uint32_t)k * stride;
+            wc[k] = (c < nc && !((done >> k) & 1u) && wait[k] != ~0u) ? ld_colour(&b.colour[wait[k]]) : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kColRegs; ++k) {
+            uint32_t c = first + (uint32_t)k * stride;
+            if (c >= nc || ((done >> k) & 1u)) continue;
+            if (wc[k] < 0) { left = true; continue; }
+            int col;
+            if (!colour_try(b, c, wait[k], col)) { left = true; continue; }
+            ovf |= col == kMaxColours;
+            col = min(col, kMaxColours - 1);
+            __hip_atomic_store(&b.colour[c], col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            done |= 1u << k;
+            local_max = max(local_max, col + 1);
+        }
+        for (uint32_t c = first + (uint32_t)kColRegs * stride; c < nc; c += stride) {
             if (ld_colour(&b.colour[c]) >= 0) continue;
-            // the neighbour that blocked this contact last pass: while it is
-            // uncoloured the contact stays blocked (a full scan decides readiness)
             if (pass > 0) {
                 const uint32_t wb = b.col_wait[c];
                 if (wb != ~0u && ld_colour(&b.colour[wb]) < 0) { left = true; continue; }
             }
-            unsigned long long key = b.ckey[c];
-            unsigned long long h = splitmix64(key);
-            int2 pr = b.cpair[c];
-            unsigned long long used = 0;
-            bool ready = true;
-            int parts[2] = {pr.y, pr.x};
-            for (int q = 0; q < 2 && ready; ++q) {
-                int s = parts[q];
-                if (s < 0) continue;
-                uint32_t beg = b.inc_start[s], end = b.inc_start[s + 1];
-                for (uint32_t t = beg; t < end; ++t) {
-                    uint32_t e = b.inc[t];
-                    if (e == c) continue;
-                    int ce = ld_colour(&b.colour[e]);
-                    if (ce < 0) {
-                        unsigned long long ke = b.ckey[e];
-                        unsigned long long he = splitmix64(ke);
-                        if (he > h || (he == h && ke > key)) {
-                            ready = false;
-                            b.col_wait[c] = e;
-                            break;
-                        }
-                    } else {
-                        used |= 1ull << ce;
-                    }
-                }
-            }
-            if (!ready) { left = true; continue; }
-            int col = __builtin_ctzll(~used);
-            if (used == ~0ull) { col = kMaxColours - 1; ovf = true; }
+            uint32_t w;
+            int col;
+            if (!colour_try(b, c, w, col)) { b.col_wait[c] = w; left = true; continue; }
+            ovf |= col == kMaxColours;
+            col = min(col, kMaxColours - 1);
             __hip_atomic_store(&b.colour[c], col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             local_max = max(local_max, col + 1);
         }
