@@ -660,10 +660,6 @@ __device__ inline bool colour_try(const DevBuffers& b, uint32_t c, uint32_t& wai
     return true;
 }
 
-// contacts per thread whose state (coloured or not, the conflict that
-// blocked it) lives in registers; any further ones keep it in memory
-constexpr int kColRegs = 8;
-
 __global__ __launch_bounds__(kBlk) void k_colour(DevBuffers b, int64_t cap, int max_pass)
 {
     uint32_t nc = n_contacts(b, cap);
@@ -671,35 +667,12 @@ __global__ __launch_bounds__(kBlk) void k_colour(DevBuffers b, int64_t cap, int 
     uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
     int local_max = 0;
     bool ovf = false, left = true;
-    uint32_t done = 0;                       // bit k: contact first + k*stride is coloured
-    uint32_t wait[kColRegs];
-#pragma unroll
-    for (int k = 0; k < kColRegs; ++k) wait[k] = ~0u;
     for (int pass = 0; pass < max_pass; ++pass) {
         left = false;
-        // while the conflict that blocked a contact last pass is uncoloured the
-        // contact stays blocked: those colours are loaded together
-        int wc[kColRegs];
-#pragma unroll
-        for (int k = 0; k < kColRegs; ++k) {
-            uint32_t c = first + (uint32_t)k * stride;
-            wc[k] = (c < nc && !((done >> k) & 1u) && wait[k] != ~0u) ? ld_colour(&b.colour[wait[k]]) : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < kColRegs; ++k) {
-            uint32_t c = first + (uint32_t)k * stride;
-            if (c >= nc || ((done >> k) & 1u)) continue;
-            if (wc[k] < 0) { left = true; continue; }
-            int col;
-            if (!colour_try(b, c, wait[k], col)) { left = true; continue; }
-            ovf |= col == kMaxColours;
-            col = min(col, kMaxColours - 1);
-            __hip_atomic_store(&b.colour[c], col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            done |= 1u << k;
-            local_max = max(local_max, col + 1);
-        }
-        for (uint32_t c = first + (uint32_t)kColRegs * stride; c < nc; c += stride) {
+        for (uint32_t c = first; c < nc; c += stride) {
             if (ld_colour(&b.colour[c]) >= 0) continue;
+            // the conflict that blocked this contact last pass: while it is
+            // uncoloured the contact stays blocked (a full scan decides readiness)
             if (pass > 0) {
                 const uint32_t wb = b.col_wait[c];
                 if (wb != ~0u && ld_colour(&b.colour[wb]) < 0) { left = true; continue; }
