@@ -514,22 +514,50 @@ __device__ inline uint32_t n_contacts(const DevBuffers& b, int64_t cap)
     return n < (uint64_t)cap ? n : (uint32_t)cap;
 }
 
+// atomicAdd(&counter[a], 1) for every active lane, as one atomic per run of
+// equal a in consecutive lanes (same-address atomics from many lanes
+// serialise); returns the lane's old value, as its own atomic would have
+// (lanes of a run take consecutive values).  Every lane of the wave calls it.
+__device__ inline uint32_t wave_run_inc(uint32_t* counter, uint32_t a, bool active)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t prev = __shfl_up(a, 1, 64);
+    const bool prev_active = __shfl_up((int)active, 1, 64) != 0;
+    const bool head = active && (lane == 0 || !prev_active || prev != a);
+    const unsigned long long bound = __ballot(head || !active);
+    const unsigned long long later = lane == 63 ? 0ull : bound >> (lane + 1);
+    const int len = later ? __builtin_ctzll(later) + 1 : 64 - lane;
+    uint32_t old = 0;
+    if (head) old = atomicAdd(&counter[a], (uint32_t)len);
+    const unsigned long long upto = bound & (~0ull >> (63 - lane));
+    const int h = 63 - __builtin_clzll(upto | 1ull);
+    return __shfl(old, h, 64) + (uint32_t)(lane - h);
+}
+
 __global__ void k_id_count(DevBuffers b, int64_t cap)
 {
     uint32_t nc = n_contacts(b, cap);
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x)
-        atomicAdd(&b.id_count[(uint32_t)(b.rkey[c] >> 32)], 1u);
+    for (uint32_t c0 = blockIdx.x * blockDim.x; c0 < nc; c0 += gridDim.x * blockDim.x) {
+        const uint32_t c = c0 + threadIdx.x;
+        const bool on = c < nc;
+        (void)wave_run_inc(b.id_count, on ? (uint32_t)(b.rkey[c] >> 32) : 0u, on);
+    }
 }
 
 __global__ void k_id_scatter(DevBuffers b, int64_t cap)
 {
     uint32_t nc = n_contacts(b, cap);
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
-        unsigned long long k = b.rkey[c];
-        uint32_t a = (uint32_t)(k >> 32);
-        uint32_t pos = b.id_start[a] + atomicAdd(&b.id_fill[a], 1u);
-        b.ckey[pos] = k;
-        b.cpair[pos] = b.rpair[c];
+    for (uint32_t c0 = blockIdx.x * blockDim.x; c0 < nc; c0 += gridDim.x * blockDim.x) {
+        const uint32_t c = c0 + threadIdx.x;
+        const bool on = c < nc;
+        const unsigned long long k = on ? b.rkey[c] : 0ull;
+        const uint32_t a = (uint32_t)(k >> 32);
+        const uint32_t r = wave_run_inc(b.id_fill, a, on);
+        if (on) {
+            const uint32_t pos = b.id_start[a] + r;
+            b.ckey[pos] = k;
+            b.cpair[pos] = b.rpair[c];
+        }
     }
 }
 
@@ -555,9 +583,11 @@ __global__ void k_id_sort(DevBuffers b, int64_t nid)
 __global__ void k_inc_count(DevBuffers b, int64_t cap)
 {
     uint32_t nc = n_contacts(b, cap);
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
-        int2 pr = b.cpair[c];
-        atomicAdd(&b.inc_count[pr.y], 1u);
+    for (uint32_t c0 = blockIdx.x * blockDim.x; c0 < nc; c0 += gridDim.x * blockDim.x) {
+        const uint32_t c = c0 + threadIdx.x;
+        const bool on = c < nc;
+        const int2 pr = on ? b.cpair[c] : make_int2(-1, 0);
+        (void)wave_run_inc(b.inc_count, (uint32_t)pr.y, on);
         if (pr.x >= 0) atomicAdd(&b.inc_count[pr.x], 1u);
     }
 }
@@ -565,9 +595,12 @@ __global__ void k_inc_count(DevBuffers b, int64_t cap)
 __global__ void k_inc_fill(DevBuffers b, int64_t cap)
 {
     uint32_t nc = n_contacts(b, cap);
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
-        int2 pr = b.cpair[c];
-        b.inc[b.inc_start[pr.y] + atomicAdd(&b.inc_fill[pr.y], 1u)] = c;
+    for (uint32_t c0 = blockIdx.x * blockDim.x; c0 < nc; c0 += gridDim.x * blockDim.x) {
+        const uint32_t c = c0 + threadIdx.x;
+        const bool on = c < nc;
+        const int2 pr = on ? b.cpair[c] : make_int2(-1, 0);
+        const uint32_t r = wave_run_inc(b.inc_fill, (uint32_t)pr.y, on);
+        if (on) b.inc[b.inc_start[pr.y] + r] = c;
         if (pr.x >= 0) b.inc[b.inc_start[pr.x] + atomicAdd(&b.inc_fill[pr.x], 1u)] = c;
     }
 }
