@@ -587,8 +587,11 @@ __global__ void k_inc_count(DevBuffers b, int64_t cap)
         const uint32_t c = c0 + threadIdx.x;
         const bool on = c < nc;
         const int2 pr = on ? b.cpair[c] : make_int2(-1, 0);
-        (void)wave_run_inc(b.inc_count, (uint32_t)pr.y, on);
-        if (pr.x >= 0) atomicAdd(&b.inc_count[pr.x], 1u);
+        // the particle whose id leads the key comes in runs: pr.x for a
+        // pair, pr.y for a boundary contact (pr.x < 0)
+        const int own = pr.x >= 0 ? pr.x : pr.y, other = pr.x >= 0 ? pr.y : -1;
+        (void)wave_run_inc(b.inc_count, (uint32_t)own, on);
+        if (other >= 0) atomicAdd(&b.inc_count[other], 1u);
     }
 }
 
@@ -599,9 +602,10 @@ __global__ void k_inc_fill(DevBuffers b, int64_t cap)
         const uint32_t c = c0 + threadIdx.x;
         const bool on = c < nc;
         const int2 pr = on ? b.cpair[c] : make_int2(-1, 0);
-        const uint32_t r = wave_run_inc(b.inc_fill, (uint32_t)pr.y, on);
-        if (on) b.inc[b.inc_start[pr.y] + r] = c;
-        if (pr.x >= 0) b.inc[b.inc_start[pr.x] + atomicAdd(&b.inc_fill[pr.x], 1u)] = c;
+        const int own = pr.x >= 0 ? pr.x : pr.y, other = pr.x >= 0 ? pr.y : -1;
+        const uint32_t r = wave_run_inc(b.inc_fill, (uint32_t)own, on);
+        if (on) b.inc[b.inc_start[own] + r] = c;
+        if (other >= 0) b.inc[b.inc_start[other] + atomicAdd(&b.inc_fill[other], 1u)] = c;
     }
 }
 
