@@ -36,7 +36,7 @@ PAIR_BYTES, BOUND_BYTES = 176, 128
 # WRITE_SIZE counter runs scaled by a copy kernel of known size (see
 # profiles/k_pgs_bed50k_hbm_traffic.md); valid only for the kernel source it
 # was measured on, else reported as null.
-PGS_TRAFFIC = {"kernels_sha256_prefix": "52d8e97c5c9edb6e", "bytes_per_launch": 3.151e9,
+PGS_TRAFFIC = {"kernels_sha256_prefix": "94dafd6c4e5392d2", "bytes_per_launch": 3.167e9,
                "profile": "profiles/k_pgs_bed50k_hbm_traffic.md"}
 
 
