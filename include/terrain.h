@@ -360,10 +360,14 @@ int settle_particles(tr_scene* s, int32_t env, const tr_voxel_grid* g, double v_
 int advect_fluid(tr_scene* s, const tr_voxel_grid* g, double dt, const double* u, const double* mf_in,
                  double* mf_out, double* cfl);
 
-/* Advances every env by n_steps steps.  Asynchronous on the scene's stream
- * when stats is NULL; otherwise waits and writes one tr_step_stats per env
- * (of the last step).  TR_E_CAPACITY when contacts, colours or cells
- * overflow: the step is abandoned before any particle state changes. */
+/* Advances every env by n_steps steps.  Enqueues the steps on the scene's
+ * stream, then waits for them and reads back the failure flags of every step
+ * of the call (a few bytes); with stats not NULL it also writes one
+ * tr_step_stats per env (of the last step).  TR_E_CAPACITY when contacts,
+ * colours or cells overflowed (or a multi-block solve timed out) in any step
+ * of the call: that step is abandoned before any particle state changes, the
+ * steps after it still run, and the warm-start cache is cleared.  n_steps = 0
+ * with stats NULL does nothing. */
 int step(tr_scene* s, int32_t n_steps, tr_step_stats* stats);
 
 /* Mean contact force and torque (about the body's position at the start of
@@ -387,6 +391,14 @@ const char* get_last_error(tr_scene* s);
  * (lambda_n, lambda_t xyz) of the step.  Writes min(cap, count) entries and
  * the count to *n.  impulse4 may be NULL.  Synchronises. */
 int get_contacts(tr_scene* s, int32_t env, int64_t cap, uint64_t* keys, float* impulse4, int64_t* n);
+
+/* Colour of each contact of env's last step, in the order of get_contacts:
+ * the deterministic graph colouring whose colour classes the PGS sweeps visit
+ * in increasing order (no two contacts of a colour share a sphere; Jones-
+ * Plassmann with the priority splitmix64(key), ties by key, each contact
+ * taking the smallest colour its already coloured neighbours leave free).
+ * Writes min(cap, count) entries and the count to *n.  Synchronises. */
+int get_colours(tr_scene* s, int32_t env, int64_t cap, int32_t* colours, int64_t* n);
 
 /* Rolling-resistance impulses of the last step (Eq. signCoul3), in the order
  * of get_contacts: 3 floats per contact, the torque impulse on body 2 (the

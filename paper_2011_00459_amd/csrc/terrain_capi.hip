@@ -924,11 +924,15 @@ static int step_scene(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(s, e, "step launch");
+    if (n_steps == 0 && !stats) return TR_OK;
+    // every call waits for its steps and reads the failure flags of all of
+    // them: the current step's word and the word earlier steps folded theirs into
+    HIP_CHECK(s, hipStreamSynchronize(st));
+    Counters c;
+    HIP_CHECK(s, hipMemcpy(&c, s->b.cnt, sizeof(c), hipMemcpyDeviceToHost));
+    const uint32_t bad = c.failed | c.overflow;
     if (stats) {
-        HIP_CHECK(s, hipStreamSynchronize(st));
-        Counters c;
         std::vector<EnvStats> es(s->desc.n_envs);
-        HIP_CHECK(s, hipMemcpy(&c, s->b.cnt, sizeof(c), hipMemcpyDeviceToHost));
         HIP_CHECK(s, hipMemcpy(es.data(), s->b.env_stats, sizeof(EnvStats) * es.size(), hipMemcpyDeviceToHost));
         std::vector<UnitStats> us(s->p.n_units);
         std::vector<uint32_t> nc(s->desc.n_envs);
@@ -944,16 +948,22 @@ static int step_scene(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
             o.residual = G.resid;
             o.residual_first = G.resid_first;
             o.fallback_used = s->p.warm == TR_WARM_LEARNED && s->mlp_loaded ? (int32_t)G.fallback : 0;
-            o.overflow = (int32_t)c.overflow;
+            o.overflow = (int32_t)bad;
             o.impacts = (int32_t)es[e2].impacts;
             o.impact_sweeps = es[e2].impacts > 0 ? (int32_t)G.imp_sweeps : 0;
         }
-        if (c.overflow) {
-            s->have_prev = false;
-            char msg[128];
-            snprintf(msg, sizeof msg, "step: capacity or schedule failure (flags 0x%x, %u contacts found)", c.overflow, c.n_raw);
-            return fail(s, TR_E_CAPACITY, msg);
-        }
+    }
+    if (bad) {
+        // the flags are reported once: clear both words for the next call
+        const uint32_t zero = 0u;
+        HIP_CHECK(s, hipMemcpy(&s->b.cnt->failed, &zero, sizeof(zero), hipMemcpyHostToDevice));
+        HIP_CHECK(s, hipMemcpy(&s->b.cnt->overflow, &zero, sizeof(zero), hipMemcpyHostToDevice));
+        s->have_prev = false;
+        char msg[160];
+        snprintf(msg, sizeof msg,
+                 "step: capacity or schedule failure in %s (flags 0x%x, %u contacts found in the last step)",
+                 c.overflow ? "the last step" : "an earlier step of this call", bad, c.n_raw);
+        return fail(s, TR_E_CAPACITY, msg);
     }
     return TR_OK;
 }
@@ -1450,6 +1460,27 @@ int get_contacts(tr_scene* s, int32_t env, int64_t cap, uint64_t* keys, float* i
         if (impulse4) HIP_CHECK(s, hipMemcpy(impulse4, s->b.plam + r[0], sizeof(float4) * m, hipMemcpyDeviceToHost));
     }
     // keys of boundary contacts carry the env-local shape index already
+    return TR_OK;
+}
+
+int get_colours(tr_scene* s, int32_t env, int64_t cap, int32_t* colours, int64_t* n)
+{
+    if (!s || !n || cap < 0 || (cap > 0 && !colours)) return TR_E_INVAL;
+    s->err.clear();
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "get_colours: env");
+    *n = 0;
+    if (!s->stepped) return TR_OK;
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    // the colours are indexed by the canonical position of the last step,
+    // whose id ranges now live in the "previous" buffers
+    int64_t base = (int64_t)env * s->desc.cap_particles;
+    uint32_t r[2];
+    HIP_CHECK(s, hipMemcpy(&r[0], s->b.pid_start + base, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    HIP_CHECK(s, hipMemcpy(&r[1], s->b.pid_start + base + s->desc.cap_particles, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    int64_t cnt = (int64_t)r[1] - (int64_t)r[0];
+    *n = cnt;
+    int64_t m = std::min(cnt, cap);
+    if (m > 0) HIP_CHECK(s, hipMemcpy(colours, s->b.colour + r[0], sizeof(int32_t) * m, hipMemcpyDeviceToHost));
     return TR_OK;
 }
 

@@ -167,7 +167,8 @@ struct Counters {
     uint32_t n_pairs;
     uint32_t overflow;     // kOvf* / kFail* bits, sticky within a step
     uint32_t n_colours;
-    uint32_t pad[12];
+    uint32_t failed;       // OR of the overflow bits of every step since the host last read it
+    uint32_t pad[11];
     uint32_t bar[kGroups][16];  // per-group barrier counters, one cache line each
 };
 

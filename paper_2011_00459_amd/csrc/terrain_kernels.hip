@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 
 #include "terrain_internal.h"
 
@@ -301,8 +302,17 @@ __global__ void k_step_begin(DevBuffers b, StepParams p)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     {
+        // every counter starts the step at zero except the failure word, into
+        // which one thread folds the previous step's flags before clearing them
         uint32_t* w = reinterpret_cast<uint32_t*>(b.cnt);
-        for (int k = t; k < (int)(sizeof(Counters) / 4); k += gridDim.x * blockDim.x) w[k] = 0u;
+        constexpr int kOvfWord = (int)(offsetof(Counters, overflow) / 4);
+        constexpr int kFailedWord = (int)(offsetof(Counters, failed) / 4);
+        for (int k = t; k < (int)(sizeof(Counters) / 4); k += gridDim.x * blockDim.x)
+            if (k != kOvfWord && k != kFailedWord) w[k] = 0u;
+        if (t == 0) {
+            w[kFailedWord] |= w[kOvfWord];
+            w[kOvfWord] = 0u;
+        }
     }
     if (t < p.n_envs) {
         b.env_stats[t].contacts = 0;
@@ -1598,9 +1608,6 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
         c = lo + threadIdx.x;
         fetch();
     }
-#ifdef TRK_PGS_TRACE
-    unsigned long long tr[4] = {0, 0, 0, 0}, tprev = wall_clock64(), tw[12] = {}, ta2[12] = {}, tw2[12] = {};
-#endif
     for (int sw = 0; sw < sweeps_cap && ncol > 0; ++sw) {
         float num = 0.f, den = 0.f;
         double* part = b.block_part + (size_t)(FLOW ? sw : (sw & 1)) * nblk * 2;
@@ -1669,25 +1676,13 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                         __hip_atomic_store(&part[2 * blockIdx.x + 1], sd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
-#ifdef TRK_PGS_TRACE
-                unsigned long long ta = wall_clock64();
-#endif
                 cluster_arrive<FENCED>(counter);
                 ++nbar;
                 // the next phase's first rows are fetched while the block waits
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
                 c = lo + threadIdx.x;
                 fetch();
-#ifdef TRK_PGS_TRACE
-                unsigned long long tb = wall_clock64();
-#endif
                 if (!cluster_wait<FENCED>(b.cnt, counter, nbar * K, flag)) return;  // every block leaves
-#ifdef TRK_PGS_TRACE
-                unsigned long long tc = wall_clock64();
-                tr[0] += ta - tprev; tr[1] += tb - ta; tr[2] += tc - tb; tr[3] += 1;
-                if (col < 12) { tw[col] += ta - tprev; ta2[col] += tb - ta; tw2[col] += tc - tb; }
-                tprev = tc;
-#endif
             } else {
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
                 c = lo + threadIdx.x;
@@ -1739,16 +1734,6 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
         combine(sweeps - 1, sn, sd);
         Rk = resid(sn, sd);
     }
-#ifdef TRK_PGS_TRACE
-    if (threadIdx.x == 0 && (rank == 0 || rank == K - 1) && tr[3] > 0) {
-        printf("PGS_TRACE unit %d rank %u phases %llu ticks/phase: work %.1f arrive+prefetch %.1f wait %.1f\n", unit,
-               rank, tr[3], (double)tr[0] / tr[3], (double)tr[1] / tr[3], (double)tr[2] / tr[3]);
-        for (uint32_t q = 0; q < ncol && q < 12; ++q)
-            printf("PGS_TRACE unit %d rank %u colour %u size %u work %.1f arrive %.1f wait %.1f\n", unit, rank, q,
-                   cstart.end(q) - cstart.beg(q), (double)tw[q] / sweeps, (double)ta2[q] / sweeps,
-                   (double)tw2[q] / sweeps);
-    }
-#endif
     if (rank == 0 && threadIdx.x == 0) {
         UnitStats& G = b.ustats[unit];
         if (slot == 0) {

@@ -2,7 +2,7 @@
 // that predicts each contact's initial impulses (lambda_n, lambda_t1,
 // lambda_t2) / (m_eff g dt) in the contact frame.
 //
-//   k_mlp_bf16    inference on MFMA (v_mfma_f32_32x32x8_bf16): one wave per 32
+//   k_mlp_bf16    inference on MFMA (v_mfma_f32_32x32x16_bf16): one wave per 32
 //                 contacts, weights and activations in BF16, FP32 accumulate
 //   k_mlp_f32     the same network in FP32 on the vector ALU (reference)
 //   k_learned_lam lambda^0 = frame x output x scale, projected onto the bounds

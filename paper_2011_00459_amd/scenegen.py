@@ -196,6 +196,17 @@ def jammed_bed(seed=21, nx=40, ny=20, nz=12, r0=0.03, spread=0.002, jitter=0.001
     return _spec(x, r, bodies, material(mu, c), dt, sweeps, bounds, r0)
 
 
+def ulp_nudge(x, seed):
+    """x (FP32 values held in float64) with every coordinate moved by one FP32
+    ulp up or down, the direction drawn per coordinate: an ensemble of starts
+    that FP32 cannot tell apart, for statistics of chaotic trajectories."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x32 = np.asarray(x, dtype=np.float32)
+    up = rng.integers(0, 2, x32.shape).astype(bool)
+    out = np.where(up, np.nextafter(x32, np.float32(np.inf)), np.nextafter(x32, np.float32(-np.inf)))
+    return out.astype(np.float64)
+
+
 def voxel_workload(seed=11, dims=(256, 256, 128), l0=0.05, dt=1.0 / 60.0, rho_f=1600.0, courant=0.4):
     """Mesoscale grid of a dig site: fluidized soil (bulk density rho_f, in
     kg per voxel) filling an ellipsoidal zone ahead of a tool with a ragged

@@ -27,7 +27,7 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state", "autotune",
            "get_rolling_impulses", "set_tool", "get_zone_wedges", "coarse_grain", "advect_fluid",
            "terrain_from_voxels", "convert_cut", "convert_deposit", "grow_particles", "form_particles",
-           "remove_particles", "settle_particles")
+           "remove_particles", "settle_particles", "get_colours")
 CG_KERNEL = {"heaviside": 0, "gauss": 1}
 PGS_MODE = {"grouped": 0, "per_env": 1}
 MLP_TRAINABLE = MLP_PARAMS - 12
@@ -154,6 +154,7 @@ def lib():
         L.load_state.argtypes = [P, C.c_void_p, C.c_int64]
         L.autotune.argtypes = [P, C.c_int32, C.c_char_p, C.POINTER(tr_solver_config), C.POINTER(C.c_float)]
         L.get_rolling_impulses.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_int64)]
+        L.get_colours.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.coarse_grain.argtypes = [P, C.c_int32, C.POINTER(tr_voxel_grid), C.c_int32, C.c_double, P, P, P]
         L.advect_fluid.argtypes = [P, C.POINTER(tr_voxel_grid), C.c_double, P, P, P, C.POINTER(C.c_double)]
         L.remove_particles.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_int64)]
@@ -451,6 +452,15 @@ class Scene:
                                        lam.ctypes.data_as(C.POINTER(C.c_float)), C.byref(n)), "get_contacts")
         m = min(n.value, cap)
         return keys[:m], lam[:m]
+
+    def get_colours(self, env):
+        """Colour of each contact of the last step, in get_contacts order."""
+        n = C.c_int64()
+        self._check(lib().get_colours(self.h, env, 0, None, C.byref(n)), "get_colours")
+        out = np.zeros(max(n.value, 1), dtype=np.int32)
+        self._check(lib().get_colours(self.h, env, n.value, out.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      C.byref(n)), "get_colours")
+        return out[:n.value]
 
     def get_rolling_impulses(self, env):
         n = C.c_int64()

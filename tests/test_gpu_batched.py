@@ -61,6 +61,7 @@ def test_schedule_matches_single_env_oracle(sched):
             assert np.array_equal(keys, oo["keys"]), (sched, k, e)
             assert st[e]["contacts"] == oo["contacts"]
             assert st[e]["colours"] == oo["colours"], (sched, e, st[e]["colours"], oo["colours"])
+            assert np.array_equal(g.get_colours(e), oo["colour"]), (sched, k, e)
             assert st[e]["sweeps"] == oo["sweeps"]
             p = g.get_particles(e)
             assert np.max(np.abs(p["v"] - o.v)) <= vel_tol(o.v) * (1 + 4 * k), (sched, k, e)
@@ -113,6 +114,7 @@ def test_many_small_envs_per_env_mode():
         keys, _ = g.get_contacts(e)
         assert np.array_equal(keys, oo["keys"])
         assert st[e]["colours"] == oo["colours"]
+        assert np.array_equal(g.get_colours(e), oo["colour"])
         assert np.max(np.abs(g.get_particles(e)["v"] - o.v)) <= vel_tol(o.v)
 
 

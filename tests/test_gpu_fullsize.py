@@ -35,6 +35,7 @@ def test_bed50k_one_step_matches_oracle():
     assert st["contacts"] == oo["contacts"] > 100000
     assert np.array_equal(keys, oo["keys"])
     assert st["colours"] == oo["colours"] and st["sweeps"] == oo["sweeps"] == 150
+    assert np.array_equal(g.get_colours(0), oo["colour"])
     p = g.get_particles(0)
     assert np.max(np.abs(p["v"] - o.v)) <= vel_tol(o.v)
     lt = 1e-3 * np.max(np.abs(oo["lam"]))

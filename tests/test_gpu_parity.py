@@ -39,6 +39,7 @@ def compare_step(spec, gpu_steps=1, rel=1e-4, check_lam=True, env=0, sc=None):
         assert st["contacts"] == oo["contacts"]
         assert st["pair_contacts"] == oo["pair_contacts"]
         assert st["colours"] == oo["colours"]
+        assert np.array_equal(g.get_colours(env), oo["colour"]), f"step {k}: colours differ"
         assert st["sweeps"] == oo["sweeps"]
         p = g.get_particles(env)
         tol = vel_tol(o.v, rel=rel) * (1 + 4 * k)
@@ -182,6 +183,7 @@ def test_batched_envs_match_single_env_oracle():
         oo = o.step()
         keys, lam = g.get_contacts(e)
         assert np.array_equal(keys, oo["keys"])
+        assert np.array_equal(g.get_colours(e), oo["colour"])
         assert st[e]["contacts"] == oo["contacts"]
         p = g.get_particles(e)
         # colours are shared across envs: the schedule of each env is its own
@@ -213,6 +215,26 @@ def test_contact_capacity_overflow_leaves_state_unchanged():
     after = g.get_particles(0)
     for k in ("x", "v", "w"):
         assert np.array_equal(before[k], after[k])
+
+
+def test_capacity_failure_is_reported_by_every_step_call():
+    # the failure flags of every step of a call are read back whether or not
+    # stats are asked for, and reported once
+    spec = settled_column(n=400, footprint=0.6)
+    g = gpu_scene(spec, cap_contacts=64)
+    before = g.get_particles(0)
+    for stats in (False, True):
+        with pytest.raises(T.TerrainError) as ei:
+            g.step(3, stats=stats)
+        assert ei.value.code == T.TR_E_CAPACITY
+    after = g.get_particles(0)
+    for k in ("x", "v", "w"):
+        assert np.array_equal(before[k], after[k])
+    # with few enough spheres left the steps succeed: no stale flag survives
+    g.remove_particles(0, np.arange(5, len(spec["x"])))
+    g.step(2, stats=False)
+    st = g.step(1)[0]
+    assert st["overflow"] == 0 and 0 < st["contacts"] <= 64
 
 
 def test_tolerance_stopping_matches_oracle():

@@ -39,6 +39,7 @@ def compare(spec, steps, g=None, env=0, rel=1e-4):
         keys, lam = g.get_contacts(env)
         assert np.array_equal(keys, oo["keys"]), k
         assert st["colours"] == oo["colours"] and st["sweeps"] == oo["sweeps"]
+        assert np.array_equal(g.get_colours(env), oo["colour"]), k
         p = g.get_particles(env)
         tol = vel_tol(o.v, rel=rel) * (1 + 4 * k)
         assert np.max(np.abs(p["v"] - o.v)) <= tol, (k, np.max(np.abs(p["v"] - o.v)), tol)
