@@ -458,6 +458,21 @@ int64_t mlp_grad_scratch_floats(int64_t B);
 int mlp_loss_grad(const float* weights, const float* feat, const float* label, int64_t B, float* grad, float* loss,
                   float* scratch, int64_t scratch_floats, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * loss and gradient as mlp_loss_grad, with the per-block gradient partials in
+ * a fixed device array the library holds on each GPU it runs on (until the
+ * process ends) instead of a caller workspace.  Calls no allocating routine.
+ * B is limited to TR_MLP_NOALLOC_MAX_BATCH: TR_E_CAPACITY
+ * above it, TR_E_INVAL for NULL pointers or B <= 0, TR_E_DEVICE when the
+ * array cannot be located on the current device.  Every call on one GPU uses
+ * that GPU's one array: calls that overlap on one GPU (different streams or
+ * threads without ordering between them) race and give wrong gradients.
+ * Asynchronous on `stream`. */
+#define TR_MLP_NOALLOC_MAX_BATCH 8192
+int mlp_loss_grad_noalloc(const float* weights, const float* feat, const float* label, int64_t B, float* grad,
+                          float* loss, void* stream);
+
 /* One Adam step (bias-corrected, step count t >= 1) on the 5187 trainable
  * weights in place; m and v are the moment buffers (device, 5187 each). */
 int mlp_adam_step(float* weights, const float* grad, float* m, float* v, float lr, float beta1, float beta2, float eps,

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "terrain_internal.h"
 
@@ -396,3 +397,47 @@ void launch_adam(float* W, const float* g, float* m, float* v, int n, float lr, 
 }
 
 }  // namespace trk
+
+// ---------------------------------------------------------------------------
+// Loss gradient without allocation: the per-block gradient partials live in a
+// file-scope device array of fixed size instead of a caller workspace.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kNoAllocMaxBatch = TR_MLP_NOALLOC_MAX_BATCH;
+constexpr int64_t kNoAllocFloats = ((kNoAllocMaxBatch + trk::kTrainB - 1) / trk::kTrainB) * (int64_t)(trk::kNP + 1);
+constexpr int kMaxDevices = 64;
+
+// One copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel: the device address of each GPU's copy comes from
+// hipGetSymbolAddress on that GPU.
+static __device__ __align__(256) float g_train_scratch[kNoAllocFloats];
+
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's copy (looked up once per device, with the
+// device current).  nullptr on failure.
+float* train_scratch_ptr(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_train_scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" int mlp_loss_grad_noalloc(const float* weights, const float* feat, const float* label, int64_t B,
+                                     float* grad, float* loss, void* stream)
+{
+    if (!weights || !feat || !label || !grad || B <= 0) return TR_E_INVAL;
+    if (B > kNoAllocMaxBatch) return TR_E_CAPACITY;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return TR_E_DEVICE;
+    float* scratch = train_scratch_ptr(dev);
+    if (!scratch) return TR_E_DEVICE;
+    trk::launch_mlp_grad(weights, feat, label, B, grad, loss, scratch, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? TR_OK : TR_E_DEVICE;
+}

@@ -27,7 +27,7 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state", "autotune",
            "get_rolling_impulses", "set_tool", "get_zone_wedges", "coarse_grain", "advect_fluid",
            "terrain_from_voxels", "convert_cut", "convert_deposit", "grow_particles", "form_particles",
-           "remove_particles", "settle_particles", "get_colours")
+           "remove_particles", "settle_particles", "get_colours", "mlp_loss_grad_noalloc")
 CG_KERNEL = {"heaviside": 0, "gauss": 1}
 PGS_MODE = {"grouped": 0, "per_env": 1}
 MLP_TRAINABLE = MLP_PARAMS - 12
@@ -145,6 +145,7 @@ def lib():
         L.get_learn_samples.argtypes = [P, C.c_int32, C.c_int64, fp, fp, C.POINTER(C.c_int64)]
         L.mlp_forward.argtypes = [P, P, C.c_int64, P, C.c_int32, P]
         L.mlp_loss_grad.argtypes = [P, P, P, C.c_int64, P, P, P, C.c_int64, P]
+        L.mlp_loss_grad_noalloc.argtypes = [P, P, P, C.c_int64, P, P, P]
         L.mlp_adam_step.argtypes = [P, P, P, P, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32, P]
         L.set_solver_config.argtypes = [P, C.POINTER(tr_solver_config)]
         L.get_solver_config.argtypes = [P, C.POINTER(tr_solver_config)]
@@ -563,6 +564,15 @@ def mlp_forward(weights_ptr, feat_ptr, B, out_ptr, bf16=True, stream=None):
 
 def mlp_grad_scratch_floats(B):
     return lib().mlp_grad_scratch_floats(B)
+
+
+MLP_NOALLOC_MAX_BATCH = 8192  # TR_MLP_NOALLOC_MAX_BATCH
+
+
+def mlp_loss_grad_noalloc(weights_ptr, feat_ptr, label_ptr, B, grad_ptr, loss_ptr, stream=None):
+    """mlp_loss_grad with the library's own fixed scratch (no allocation; B <= 8192)."""
+    _check_rc(lib().mlp_loss_grad_noalloc(weights_ptr, feat_ptr, label_ptr, B, grad_ptr, loss_ptr, stream),
+              "mlp_loss_grad_noalloc")
 
 
 def mlp_loss_grad(weights_ptr, feat_ptr, label_ptr, B, grad_ptr, loss_ptr, scratch_ptr, scratch_floats, stream=None):
