@@ -148,20 +148,21 @@ def batch_specs(seed=3000, n_envs=256, nmin=500, nmax=20000, sweeps=100, dt=1.0 
     footprint filled to 0.5 m at packing 0.6 (radius from N), mu 0.7,
     c 2 kPa, with a blade or an open bucket on a random heading, depth and
     speed."""
-    out = []
-    for e in range(n_envs):
-        rng = np.random.Generator(np.random.PCG64(seed + e))
-        ns = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
-        rs = (0.6 * 3.0 * 3.0 / (4.0 * math.pi * ns)) ** (1.0 / 3.0)
-        tool = "blade" if rng.uniform() < 0.5 else "bucket"
-        heading = math.radians(rng.uniform(-20.0, 20.0))
-        depth = rng.uniform(0.1, 0.3)
-        speed = rng.uniform(0.3, 1.5)
-        spec = bed_scene(seed=seed + e, n=ns, r0=rs, spread=0.1, lx=3.0, ly=2.0, mu=0.7, c=2000.0,
-                         sweeps=sweeps, dt=dt, tool=tool, tool_speed=speed, depth=depth,
-                         settled_top=0.5, tool_x=-1.1, heading=heading)
-        out.append(spec)
-    return out
+    return [batch_spec(seed, e, nmin, nmax, sweeps, dt) for e in range(n_envs)]
+
+
+def batch_spec(seed, e, nmin=500, nmax=20000, sweeps=100, dt=1.0 / 60.0):
+    """Bed e of batch_specs(seed, ...) alone."""
+    rng = np.random.Generator(np.random.PCG64(seed + e))
+    ns = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+    rs = (0.6 * 3.0 * 3.0 / (4.0 * math.pi * ns)) ** (1.0 / 3.0)
+    tool = "blade" if rng.uniform() < 0.5 else "bucket"
+    heading = math.radians(rng.uniform(-20.0, 20.0))
+    depth = rng.uniform(0.1, 0.3)
+    speed = rng.uniform(0.3, 1.5)
+    return bed_scene(seed=seed + e, n=ns, r0=rs, spread=0.1, lx=3.0, ly=2.0, mu=0.7, c=2000.0,
+                     sweeps=sweeps, dt=dt, tool=tool, tool_speed=speed, depth=depth,
+                     settled_top=0.5, tool_x=-1.1, heading=heading)
 
 
 def excavation_scene(seed=5, n=500000, sweeps=200, dt=1.0 / 60.0):
