@@ -717,10 +717,11 @@ static void contact_frame(const row* R, const double u[3], const double ltp[3], 
     cross3(R->n, t1, t2);
 }
 
-/* Column of a particle for the depth feature: the (x, y) cell of the env's
- * detection grid, evaluated in FP32 on the FP32 state (cell size
- * 2 r_max (1 + kappa_c) * 1.001 from the grid origin, clamped to the grid),
- * so that the GPU, whose grid this is, assigns every particle the same column. */
+/* Column of a particle for the depth feature (reading R42): the (x, y) index
+ * of the detection cell grid, cell width h = 2 r_max (1 + kappa_c) * 1.001
+ * from the grid's low corner, clamped to the grid.  The index is an integer
+ * decided by floating point, so it is taken in single precision on the
+ * single-precision state, the precision of the measured path. */
 static void column_of(const orc_params* P, double rmax, const double* x, int64_t* cx, int64_t* cy)
 {
     double h = 2.0 * rmax * (1.0 + (P->m.c_p > 0.0 ? P->m.kappa_c : 0.0)) * 1.001;
