@@ -607,24 +607,45 @@ static double dsilu(double z)
     return s * (1.0 + z * (1.0 - s));
 }
 
+/* bfloat16 rounding of a value held in single precision: the upper 16 bits
+ * of the IEEE binary32 pattern, rounded to nearest with ties to even (the
+ * published bfloat16 conversion; finite inputs only). */
+static double to_bf16(double a)
+{
+    float f = (float)a;
+    uint32_t u;
+    memcpy(&u, &f, sizeof u);
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    memcpy(&f, &u, sizeof f);
+    return (double)f;
+}
+
+/* The network 12 -> 64 -> 64 -> 3 with SiLU.  With net->bf16 the inference
+ * takes the precision the learned start is specified in: the scaled inputs,
+ * the three weight matrices and both hidden layers are bfloat16 values (the
+ * hidden layers first held in single precision), biases and sums in double. */
 void orc_mlp_forward(const orc_mlp* net, int64_t B, const double* feat, double* out)
 {
+    const int q = net->bf16;
     for (int64_t b = 0; b < B; ++b) {
         double x0[12], h1[64], h2[64];
-        for (int i = 0; i < 12; ++i) x0[i] = feat[12 * b + i] * net->in_scale[i];
+        for (int i = 0; i < 12; ++i) {
+            x0[i] = feat[12 * b + i] * net->in_scale[i];
+            if (q) x0[i] = to_bf16(x0[i]);
+        }
         for (int o = 0; o < 64; ++o) {
             double z = net->b1[o];
-            for (int i = 0; i < 12; ++i) z += net->W1[o * 12 + i] * x0[i];
-            h1[o] = silu(z);
+            for (int i = 0; i < 12; ++i) z += (q ? to_bf16(net->W1[o * 12 + i]) : net->W1[o * 12 + i]) * x0[i];
+            h1[o] = q ? to_bf16(silu(z)) : silu(z);
         }
         for (int o = 0; o < 64; ++o) {
             double z = net->b2[o];
-            for (int i = 0; i < 64; ++i) z += net->W2[o * 64 + i] * h1[i];
-            h2[o] = silu(z);
+            for (int i = 0; i < 64; ++i) z += (q ? to_bf16(net->W2[o * 64 + i]) : net->W2[o * 64 + i]) * h1[i];
+            h2[o] = q ? to_bf16(silu(z)) : silu(z);
         }
         for (int o = 0; o < 3; ++o) {
             double z = net->b3[o];
-            for (int i = 0; i < 64; ++i) z += net->W3[o * 64 + i] * h2[i];
+            for (int i = 0; i < 64; ++i) z += (q ? to_bf16(net->W3[o * 64 + i]) : net->W3[o * 64 + i]) * h2[i];
             out[3 * b + o] = z;
         }
     }

@@ -221,6 +221,8 @@ typedef struct orc_mlp {
     const double* W2; const double* b2;  /* 64x64, 64 */
     const double* W3; const double* b3;  /* 3x64,  3  */
     double in_scale[12];                  /* feature normalisation (multiplied) */
+    int32_t bf16;                         /* 1: BF16 inference (inputs, weight matrices and hidden
+                                             layers rounded to bfloat16, biases and sums wide) */
 } orc_mlp;
 
 typedef struct orc_stats {

@@ -107,7 +107,7 @@ class Mlp(C.Structure):
     _fields_ = [("W1", C.POINTER(C.c_double)), ("b1", C.POINTER(C.c_double)),
                 ("W2", C.POINTER(C.c_double)), ("b2", C.POINTER(C.c_double)),
                 ("W3", C.POINTER(C.c_double)), ("b3", C.POINTER(C.c_double)),
-                ("in_scale", C.c_double * 12)]
+                ("in_scale", C.c_double * 12), ("bf16", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -308,6 +308,7 @@ def mlp_struct(weights: dict):
     sc = np.asarray(weights.get("in_scale", np.ones(12)), dtype=np.float64)
     for i in range(12):
         m.in_scale[i] = sc[i]
+    m.bf16 = 1 if weights.get("bf16", False) else 0
     return m, keep
 
 

@@ -5,8 +5,9 @@
     the oracle's FP64 forward (same seeded weights);
   - FP32 gradients of the training kernels within 1e-4 (relative, per tensor)
     of the oracle's FP64 gradients on the same minibatch;
-  - a LEARNED step (FP32 inference) takes the same start decision as the oracle
-    and matches its velocities to the usual one-step bar.
+  - a LEARNED step (FP32 inference, and BF16 inference on the matrix cores
+    against the oracle's network at that precision) takes the same start
+    decision as the oracle and matches its velocities to the usual one-step bar.
 """
 import ctypes as C
 
@@ -183,6 +184,35 @@ def test_learned_step_matches_oracle(seed, scale):
         keys, _ = g.get_contacts(0)
         assert np.array_equal(keys, oo["keys"])
         assert st["fallback_used"] == oo["fallback_used"], (k, st, oo["r1"])
+        assert st["sweeps"] == oo["sweeps"]
+        p = g.get_particles(0)
+        assert np.max(np.abs(p["v"] - o.v)) <= vel_tol(o.v) * (1 + 4 * k)
+
+
+@pytest.mark.parametrize("seed,scale,kept", [(7, 1.0, None), (8, 0.0, None), (7, 0.2, True)])
+def test_bf16_learned_step_matches_the_oracles_bf16_network(seed, scale, kept):
+    # BF16 inference on the matrix cores against the oracle's network at the
+    # same precision (bfloat16 inputs, weight matrices and hidden layers, wide
+    # sums): the same start decision and velocities to the one-step bar.  In
+    # the kept case the first step has no previous impulses (the fallback is
+    # the cold start, whose first residual is 1) and the network predicts a
+    # compressive normal impulse, so the learned start is kept on both sides.
+    w = random_weights(seed, scale)
+    if kept:
+        w["b3"] = np.array([1.0, 0.0, 0.0])
+    spec = with_(settled_column(seed=12, n=400, footprint=0.6), warm_start="learned", max_sweeps=60)
+    g = T.scene_from_specs(spec)
+    g.set_mlp_weights(flat(w))
+    g.set_learned_precision(True)
+    o = O.OracleScene(spec, mlp=dict(w, bf16=True))
+    for k in range(1 if kept else 2):
+        st = g.step(1)[0]
+        oo = o.step()
+        keys, _ = g.get_contacts(0)
+        assert np.array_equal(keys, oo["keys"])
+        assert st["fallback_used"] == oo["fallback_used"], (k, st, oo["r1_trial"])
+        if kept:
+            assert oo["fallback_used"] == 0 and oo["learned_used"] == 1
         assert st["sweeps"] == oo["sweeps"]
         p = g.get_particles(0)
         assert np.max(np.abs(p["v"] - o.v)) <= vel_tol(o.v) * (1 + 4 * k)

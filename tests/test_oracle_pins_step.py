@@ -363,3 +363,37 @@ def test_depth_column_of_a_stack_and_the_column_decision():
     top3 = x2[7][2] + r
     assert F2[i[0]][6] * r == pytest.approx(top3 - x2[6][2], rel=1e-12)
     assert F2[i[0]][7] * r == pytest.approx(r, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# BF16 inference of the learned start (the precision the network runs in)
+# --------------------------------------------------------------------------
+def test_bf16_network_equals_a_torch_bfloat16_model():
+    # torch's own float32 -> bfloat16 conversion (round to nearest even) as the
+    # independent rounding: inputs x scale, weight matrices and hidden layers
+    # rounded, biases and sums in double
+    torch = pytest.importorskip("torch")
+
+    def bf(a):
+        t = torch.tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64)
+        return t.numpy()
+
+    rng = np.random.default_rng(12)
+    w = dict(W1=rng.normal(0, 0.4, (64, 12)), b1=rng.normal(0, 0.1, 64), W2=rng.normal(0, 0.2, (64, 64)),
+             b2=rng.normal(0, 0.1, 64), W3=rng.normal(0, 0.2, (3, 64)), b3=rng.normal(0, 0.1, 3),
+             in_scale=rng.uniform(0.5, 1.5, 12))
+    feat = rng.normal(0, 1.0, (500, 12))
+    x = bf(feat * w["in_scale"])
+    z1 = x @ bf(w["W1"]).T + w["b1"]
+    h1 = bf(z1 / (1.0 + np.exp(-z1)))
+    z2 = h1 @ bf(w["W2"]).T + w["b2"]
+    h2 = bf(z2 / (1.0 + np.exp(-z2)))
+    ref = h2 @ bf(w["W3"]).T + w["b3"]
+    got = O.mlp_forward(dict(w, bf16=True), feat)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
+    # and without the option the network is the plain double one
+    z1 = (feat * w["in_scale"]) @ w["W1"].T + w["b1"]
+    h1 = z1 / (1.0 + np.exp(-z1))
+    z2 = h1 @ w["W2"].T + w["b2"]
+    h2 = z2 / (1.0 + np.exp(-z2))
+    np.testing.assert_allclose(O.mlp_forward(w, feat), h2 @ w["W3"].T + w["b3"], rtol=1e-12, atol=1e-12)
