@@ -1995,6 +1995,12 @@ int pgs_resident_blocks(int block)
     return std::max(1, std::min(c0, c1)) * pr.multiProcessorCount;
 }
 
+// The colouring's blocks wait for each other's contacts, so all of them must
+// run at once.  The occupancy query reports 7 blocks of k_colour per CU on
+// MI355X, but a grid of exactly that many was measured not to be resident at
+// once (some blocks start only after others finish: a 578k-contact step
+// then gave up with contacts uncoloured), while one block per CU fewer
+// always is: keep that slack.
 int colour_resident_blocks()
 {
     int dev = 0, per_cu = 0;
@@ -2002,7 +2008,7 @@ int colour_resident_blocks()
     hipDeviceProp_t pr;
     (void)hipGetDeviceProperties(&pr, dev);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_colour, kBlk, 0);
-    return std::max(1, per_cu) * pr.multiProcessorCount;
+    return std::max(1, per_cu - 1) * pr.multiProcessorCount;
 }
 
 void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s, int sweeps_cap, int slot)
