@@ -1,23 +1,32 @@
 #!/usr/bin/env python3
-"""Benchmark: one full particle step (detection, canonical order, rows,
-colouring, warm start, PGS, integration, body forces, zone aggregates) of the
-50,000-sphere bulldozing bed on one MI355X.
+"""Benchmark of the agitated-soil particle step on one MI355X.
 
-Workload: 50k spheres r = 0.03 m U(0.9, 1.1), rho 2000, mu 0.7, c_p 2 kPa,
-poured over a 4 x 2 m floor with walls and settled on the GPU before timing;
-a 1.5 x 0.05 x 0.6 m box blade cuts 0.2 m below the settled surface at 1 m/s;
-dt = 1/60 s, 150 PGS sweeps, previous-step warm start.  Inputs are resident
-in HBM when the timed region starts.
+One step = detection, canonical order, rows, colouring, warm start, PGS,
+integration, body forces and zone aggregates, every phase on the GPU.  Inputs
+are resident in HBM when the timed region starts.
 
-Prints one JSON line.  value = contacts * PGS sweeps / s over the whole step.
-roofline: the persistent PGS kernel, algorithmic bytes (176 B per pair
-contact-sweep, 128 B per boundary contact-sweep) / its event-timed duration.
-cpu_baseline: the FP64 oracle (single thread) on a 50k-sphere jammed bed of the
-same radius, a bounded sample of about 10-30 s.
+Default line (the headline): 256 independent beds stepped together, particle
+counts log-uniform in [500, 20000] (1.21 M spheres, about 3.2 M contacts),
+each a 3 x 2 m bed with a blade or an open bucket on a random heading at
+U(0.3, 1.5) m/s, dt 1/60 s, 100 PGS sweeps, previous-step warm start, settled
+on the GPU before timing.  value = sum over the timed steps of contacts x PGS
+sweeps / wall time of those steps.
+
+roofline: the per-env PGS kernel (k_pgs_env): algorithmic bytes (176 B per
+pair contact-sweep, 128 B per boundary contact-sweep) / its HIP-event
+duration on the scene's stream, summed over the timed steps.
+cpu_baseline: the FP64 oracle as it stands on the same 256 beds (settled by
+the oracle itself), one process per host core, one step of each bed.
+
+Extra keys: the 50,000-sphere bulldozing bed (bed50k), the 500,000-sphere
+excavation with a bucket on a dig path (excavation500k), the network's
+throughput (mlp) and the sweeps / steps per second to R_k <= 1e-4 of the
+cold, previous-step and learned starts on the 256 beds (warm_start_to_1e-4).
 """
 import argparse
 import ctypes
 import json
+import math
 import os
 import sys
 import time
@@ -29,36 +38,33 @@ sys.path.insert(0, ROOT)
 
 from paper_2011_00459_amd import scenegen as SG  # noqa: E402
 from paper_2011_00459_amd import terrain as T  # noqa: E402
+from paper_2011_00459_amd import zones as Z  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 PAIR_BYTES, BOUND_BYTES = 176, 128
-# HBM traffic of one k_pgs launch on this workload, from the FETCH_SIZE and
-# WRITE_SIZE counter runs scaled by a copy kernel of known size (see
-# profiles/k_pgs_bed50k_hbm_traffic.md); valid only for the kernel source it
-# was measured on, else reported as null.
-PGS_TRAFFIC = {"kernels_sha256_prefix": "94dafd6c4e5392d2", "bytes_per_launch": 3.167e9,
-               "profile": "profiles/k_pgs_bed50k_hbm_traffic.md"}
 
-
+# HBM traffic of one PGS launch, from the FETCH_SIZE and WRITE_SIZE counter
+# runs scaled by a copy kernel of known size (profiles named below); valid
+# only for the kernel source it was measured on, else reported as null.
+PGS_TRAFFIC = {
+    "batched": {"kernels_sha256_prefix": "", "bytes_per_launch": None,
+                "profile": "profiles/k_pgs_env_batched256_hbm_traffic.md"},
+    "bed": {"kernels_sha256_prefix": "", "bytes_per_launch": None,
+            "profile": "profiles/k_pgs_bed50k_hbm_traffic.md"},
+}
 # The same for k_advect on the 256 x 256 x 128 voxel grid
 # (profiles/k_advect_voxels256_kernel_trace.md), keyed to terrain_voxels.hip.
 ADVECT_TRAFFIC = {"kernels_sha256_prefix": "92ca9f936e1a6af0", "bytes_per_launch": 0.3757e9,
                   "profile": "profiles/k_advect_voxels256_kernel_trace.md"}
 
 
-def source_traffic(entry, source):
+def source_traffic(entry, source="terrain_kernels.hip"):
     import hashlib
+    if entry.get("bytes_per_launch") is None:
+        return None
     with open(os.path.join(ROOT, "paper_2011_00459_amd", "csrc", source), "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
     return entry["bytes_per_launch"] if sha == entry["kernels_sha256_prefix"] else None
-
-
-def pgs_traffic():
-    import hashlib
-    src = os.path.join(ROOT, "paper_2011_00459_amd", "csrc", "terrain_kernels.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    return PGS_TRAFFIC["bytes_per_launch"] if sha == PGS_TRAFFIC["kernels_sha256_prefix"] else None
 
 
 def device_sync():
@@ -68,95 +74,64 @@ def device_sync():
         raise RuntimeError(f"hipDeviceSynchronize failed ({rc})")
 
 
-def build_bed(args):
-    spec = SG.bed_scene(seed=2, n=args.n, r0=0.03, spread=0.1, lx=4.0, ly=2.0, mu=0.7, c=2000.0,
-                        sweeps=args.sweeps, tool="none")
-    solids = float(np.sum(4.0 / 3.0 * np.pi * spec["r"] ** 3))
-    est_top = solids / (4.0 * 2.0 * 0.6)
-    blade = SG.box_blade(-1.6, est_top - 0.2, width=1.5, thick=0.05, height=0.6, vx=0.0)
-    spec["bodies"] = spec["bodies"] + [blade]
-    spec["warm_start"] = "prev"
-    sc = T.scene_from_specs(spec, cap_contacts=16 * args.n)
-    # eager launches (measured faster than step-graph replays: the bed's PGS
-    # 8.97 against 9.54-9.60 ms, the batch 1.52e10 against 1.48e10 contact
-    # sweeps/s, one box each); --launch graphs replays the step graphs, whose
-    # phase events are nodes of the graphs.  The HIP events time the PGS
-    # launch inside the timed region either way.
-    sc.set_step_graphs(args.launch == "graphs")
-    return sc, spec, blade, est_top
-
-
-def settle(sc, spec, blade, steps):
-    # pour and settle with fewer sweeps, blade static in place
-    sc.step(steps, stats=False)
-    st = sc.step(1)[0]
-    p = sc.get_particles(0)
-    top = float(np.percentile(p["x"][:, 2] + p["r"], 99.0))
-    return st, top
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 def timed_steps(sc, k):
-    """K steps, one at a time so that every step's contact count is known."""
+    """k steps, one call each (every call waits for its step and returns its
+    statistics): contacts x sweeps, the PGS's algorithmic bytes and its
+    HIP-event time per step, summed."""
     device_sync()
     t0 = time.perf_counter()
-    tot_cs = 0
-    tot_bytes_pgs = 0
-    pgs_ms = 0.0
-    stats = []
+    tot = dict(cs=0, bytes=0, pgs_ms=0.0, contacts=0, pairs=0, steps=0)
+    last = None
     for _ in range(k):
-        st = sc.step(1)[0]
+        st = sc.step(1)
         ph = sc.get_phase_times()
-        pairs, allc = st["pair_contacts"], st["contacts"]
-        tot_cs += allc * st["sweeps"]
-        tot_bytes_pgs += (pairs * PAIR_BYTES + (allc - pairs) * BOUND_BYTES) * st["sweeps"]
-        pgs_ms += ph["pgs"]
-        stats.append((st, ph))
+        for x in st:
+            tot["cs"] += x["contacts"] * x["sweeps"]
+            tot["bytes"] += (x["pair_contacts"] * PAIR_BYTES + (x["contacts"] - x["pair_contacts"]) * BOUND_BYTES) \
+                * x["sweeps"]
+        tot["pgs_ms"] += ph["pgs"]
+        tot["steps"] += 1
+        last = (st, ph)
     device_sync()
-    t1 = time.perf_counter()
-    return t1 - t0, tot_cs, tot_bytes_pgs, pgs_ms, stats
+    tot["wall"] = time.perf_counter() - t0
+    tot["last"] = last
+    return tot
 
 
-def cpu_baseline(args):
-    sys.path.insert(0, os.path.join(ROOT, "oracle"))
-    import pyoracle as O
-    nx, ny = 60, 30
-    nz = max(1, int(round(args.n / (nx * ny))))
-    spec = SG.jammed_bed(seed=21, nx=nx, ny=ny, nz=nz, r0=0.03, sweeps=args.sweeps)
-    o = O.OracleScene(spec)
-    t0 = time.perf_counter()
-    cs = 0
-    steps = 0
-    while True:
-        out = o.step()
-        cs += out["contacts"] * out["sweeps"]
-        steps += 1
-        if time.perf_counter() - t0 > args.cpu_seconds or steps >= 8:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=cs / dt, unit="contacts*sweeps/s", cores=1, kind="oracle",
-                sample=f"{steps} FP64 oracle steps (single thread) of a {len(spec['x'])}-sphere jammed bed, "
-                       f"r 0.03 m, {args.sweeps} sweeps, {out['contacts']} contacts/step")
+def roofline(tot, kernel, traffic_key):
+    ms = tot["pgs_ms"] / tot["steps"]
+    bpl = tot["bytes"] / tot["steps"]
+    achieved = bpl / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": source_traffic(PGS_TRAFFIC[traffic_key]),
+            "algorithmic_bytes_per_launch": bpl, "launch_ms": ms, "kernel": kernel}
 
 
-def build_batched(args):
-    specs = SG.batch_specs(seed=3000, n_envs=args.envs, sweeps=args.sweeps)
+# ---------------------------------------------------------------------------
+# config 3: 256 batched beds (the headline)
+# ---------------------------------------------------------------------------
+def build_batched(args, n_envs=None, sweeps=None):
+    specs = SG.batch_specs(seed=3000, n_envs=n_envs or args.envs, sweeps=sweeps or args.sweeps)
     mat = specs[0]["material"]
     specs = [dict(s, material=mat, warm_start="prev") for s in specs]
     nmax = max(len(s["x"]) for s in specs)
     sc = T.scene_from_specs(specs, cap_particles=nmax, cap_contacts=8 * nmax)
-    # tools held still while the beds settle
-    still = []
+    # the tools are held still while the beds settle
+    moving = []
     for e, s in enumerate(specs):
         b = [dict(x, id=i) for i, x in enumerate(s["bodies"])]
-        moving = [dict(x) for x in b]
+        moving.append([dict(x) for x in b])
         for x in b:
             x["linvel"] = (0.0, 0.0, 0.0)
         sc.set_kinematic_bodies(e, b)
-        still.append(moving)
-    return sc, specs, still
+    return sc, specs, moving
 
 
-def bench_batched(args):
+def leg_batched(args):
     sc, specs, moving = build_batched(args)
     if args.schedule:
         sc.set_solver_config(**json.loads(args.schedule))
@@ -164,41 +139,222 @@ def bench_batched(args):
     for e, b in enumerate(moving):
         sc.set_kinematic_bodies(e, b)
     sc.step(1)
+    tuned = None
     if not args.schedule and not args.no_autotune:
-        sc.autotune(steps=2)
+        tuned = sc.autotune(steps=2)
     sc.set_step_graphs(args.launch == "graphs")
-    for _ in range(args.warmup):
-        sc.step(1)
-    device_sync()
-    # stats of one step (synchronising), then the timed steps without host reads
-    st = sc.step(1)
-    cs_step = sum(x["contacts"] * x["sweeps"] for x in st)
-    device_sync()
-    t0 = time.perf_counter()
-    sc.step(args.steps, stats=False)
-    device_sync()
-    wall = time.perf_counter() - t0
-    # one eager step for the phase breakdown
-    sc.set_step_graphs(False)
-    st2 = sc.step(1)
-    ph = sc.get_phase_times()
+    sc.step(args.warmup, stats=False)
+    tot = timed_steps(sc, args.steps)
+    st, ph = tot["last"]
     n = sum(len(s["x"]) for s in specs)
-    contacts = sum(x["contacts"] for x in st2)
-    line = {
-        "metric": "contacts*PGS-sweeps/s (whole step)",
-        "value": cs_step * args.steps / wall,
-        "unit": "contacts*sweeps/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"batched: {len(specs)} independent beds, {n} spheres (log-uniform 500-20000 per "
-                               f"bed), blade or bucket at U(0.3, 1.5) m/s, dt 1/60 s, {args.sweeps} sweeps, "
-                               f"prev warm start, {'eager launches' if args.launch == 'eager' else 'step graphs'}",
-                   "contacts_per_step": contacts, "steps_per_s": args.steps / wall,
-                   "schedule": sc.get_solver_config(),
-                   "eager_phase_ms": {k: float(v) for k, v in ph.items()}},
-    }
-    print(json.dumps(line), flush=True)
+    out = dict(value=tot["cs"] / tot["wall"], ms_per_step=1e3 * tot["wall"] / args.steps,
+               steps_per_s=args.steps / tot["wall"], spheres=n, envs=len(specs),
+               contacts_per_step=sum(x["contacts"] for x in st), colours_max=max(x["colours"] for x in st),
+               sweeps=st[0]["sweeps"], schedule=sc.get_solver_config(),
+               autotune_ms_per_step=tuned[1] if tuned else None,
+               phase_ms_last_step={k: float(v) for k, v in ph.items()},
+               roofline=roofline(tot, "k_pgs_env (per-env persistent colour-synchronous PGS)", "batched"))
+    sc.close()
+    return out, specs
+
+
+# ---------------------------------------------------------------------------
+# config 2: the 50,000-sphere bulldozing bed
+# ---------------------------------------------------------------------------
+def leg_bed(args, n=50000, sweeps=150):
+    spec = SG.bed_scene(seed=2, n=n, r0=0.03, spread=0.1, lx=4.0, ly=2.0, mu=0.7, c=2000.0, sweeps=sweeps,
+                        tool="none")
+    solids = float(np.sum(4.0 / 3.0 * np.pi * spec["r"] ** 3))
+    est_top = solids / (4.0 * 2.0 * 0.6)
+    blade = SG.box_blade(-1.6, est_top - 0.2, width=1.5, thick=0.05, height=0.6, vx=0.0)
+    spec["bodies"] = spec["bodies"] + [blade]
+    spec["warm_start"] = "prev"
+    sc = T.scene_from_specs(spec, cap_contacts=16 * n)
+    if args.schedule:
+        sc.set_solver_config(**json.loads(args.schedule))
+    sc.step(args.settle, stats=False)
+    p = sc.get_particles(0)
+    top = float(np.percentile(p["x"][:, 2] + p["r"], 99.0))
+    # the blade 0.2 m below the settled surface, cutting along +x at 1 m/s,
+    # with its active zone (Eq. failure_plane wedge) aggregated every step
+    moving = dict(blade, pos=(-1.6, 0.0, top - 0.2 + 0.3), linvel=(1.0, 0.0, 0.0))
+    moving["zone_planes"] = Z.blade_zone(moving, 0.7, top)
+    sc.set_kinematic_bodies(0, [dict(spec["bodies"][0], id=0), dict(moving, id=1)])
+    tuned = None
+    if not args.schedule and not args.no_autotune:
+        tuned = sc.autotune(steps=3)
+    sc.set_step_graphs(args.launch == "graphs")
+    sc.step(args.warmup, stats=False)
+    tot = timed_steps(sc, args.steps)
+    st, ph = tot["last"]
+    f, _ = sc.get_contact_forces(0, 1)
+    agg = sc.get_aggregates(0)
+    out = dict(value=tot["cs"] / tot["wall"], ms_per_step=1e3 * tot["wall"] / args.steps, spheres=n,
+               contacts_per_step=st[0]["contacts"], pair_contacts=st[0]["pair_contacts"],
+               colours=st[0]["colours"], sweeps=st[0]["sweeps"], settled_top_m=top,
+               schedule=sc.get_solver_config(), autotune_ms_per_step=tuned[1] if tuned else None,
+               phase_ms_last_step={k: float(v) for k, v in ph.items()}, blade_force_N=[float(x) for x in f],
+               zone_particles=int(agg[0]["n_particles"]) if agg else 0,
+               zone_mass_kg=float(agg[0]["M"]) if agg else 0.0,
+               roofline=roofline(tot, "k_pgs (grouped persistent colour-synchronous PGS)", "bed"))
+    sc.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# config 5: the 500,000-sphere excavation with a bucket on a dig path
+# ---------------------------------------------------------------------------
+def leg_excavation(args, weights=None, n=500000, sweeps=200):
+    spec = SG.excavation_scene(seed=5, n=n, sweeps=sweeps)
+    floor, bucket = spec["bodies"][0], spec["bodies"][1]
+    lattice_top = float(spec["grid_hi"][2]) - 0.5
+    # settle with the bucket parked above the poured spheres
+    parked = dict(bucket, pos=(-3.0, 0.0, lattice_top + 0.5), linvel=(0.0, 0.0, 0.0))
+    spec = dict(spec, bodies=[floor, parked], warm_start="prev")
+    sc = T.scene_from_specs(spec, cap_contacts=8 * n)
+    t0 = time.perf_counter()
+    sc.step(args.settle_excavation, stats=False)
+    settle_s = time.perf_counter() - t0
+    p = sc.get_particles(0)
+    top = float(np.percentile(p["x"][:, 2] + p["r"], 99.0))
+    # dig path at 0.8 m/s: descend at 30 degrees until the bucket's bottom is
+    # 0.4 m below the surface, then drag along +x (the timed steps), as the
+    # excavation test of the paper digs with a bucket
+    hh = 0.4  # half height of the 0.8 m bucket
+    depth, speed = 0.4, 0.8
+    start_bottom = top + 0.05
+    descend = dict(parked, id=1, pos=(-3.0, 0.0, start_bottom + hh),
+                   linvel=(speed * math.cos(math.radians(30)), 0.0, -speed * math.sin(math.radians(30))))
+    zone = Z.wedge_planes(0.5, -hh, 1.2, top - (start_bottom + hh) + 0.3, Z.friction_angle(0.7))
+    descend["zone_planes"] = zone
+    drag = dict(descend, linvel=(speed, 0.0, 0.0))
+    n_desc = int(round((0.05 + depth) / (speed * math.sin(math.radians(30))) / spec["dt"]))
+    sc.set_kinematic_bodies(0, [dict(floor, id=0), descend])
+    sc.step(1)
+    if weights is not None:
+        sc.set_mlp_weights(weights)
+        sc.set_learned_precision(True)
+        sc.set_warm_start("learned")
+    sc.step(n_desc - 1, stats=False)
+    # drag: the bucket keeps the pose the descent reached
+    pose_z = start_bottom + hh - n_desc * spec["dt"] * speed * math.sin(math.radians(30))
+    pose_x = -3.0 + n_desc * spec["dt"] * speed * math.cos(math.radians(30))
+    drag = dict(drag, pos=(pose_x, 0.0, pose_z))
+    drag["zone_planes"] = Z.wedge_planes(0.5, -hh, 1.2, top - pose_z + 0.3, Z.friction_angle(0.7))
+    sc.set_kinematic_bodies(0, [dict(floor, id=0), drag])
+    tuned = None
+    if not args.schedule and not args.no_autotune:
+        tuned = sc.autotune(steps=2)
+    sc.set_step_graphs(args.launch == "graphs")
+    sc.step(args.warmup, stats=False)
+    tot = timed_steps(sc, args.steps)
+    st, ph = tot["last"]
+    f, _ = sc.get_contact_forces(0, 1)
+    agg = sc.get_aggregates(0)
+    out = dict(value=tot["cs"] / tot["wall"], ms_per_step=1e3 * tot["wall"] / args.steps, spheres=n,
+               contacts_per_step=st[0]["contacts"], pair_contacts=st[0]["pair_contacts"],
+               colours=st[0]["colours"], sweeps=st[0]["sweeps"], settled_top_m=top,
+               settle_steps=args.settle_excavation, settle_s=settle_s, descent_steps=n_desc,
+               warm_start="learned" if weights is not None else "prev",
+               learned_fallback_last_step=int(st[0]["fallback_used"]),
+               schedule=sc.get_solver_config(), autotune_ms_per_step=tuned[1] if tuned else None,
+               phase_ms_last_step={k: float(v) for k, v in ph.items()}, bucket_force_N=[float(x) for x in f],
+               zone_particles=int(agg[0]["n_particles"]) if agg else 0,
+               zone_mass_kg=float(agg[0]["M"]) if agg else 0.0,
+               roofline=roofline(tot, "k_pgs (grouped persistent colour-synchronous PGS)", "bed"))
+    sc.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the oracle on the host cores: the same 256 beds, one process per core
+# ---------------------------------------------------------------------------
+def _oracle_settle(job):
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import pyoracle as O
+    e, n_envs, settle, sweeps = job
+    spec = SG.batch_spec(3000, e, sweeps=sweeps)
+    spec = dict(spec, warm_start="prev", max_sweeps=10)
+    o = O.OracleScene(spec)
+    for _ in range(settle):
+        o.step()
+    return e, o.x, o.v, o.w, o.prev_keys, o.prev_lam
+
+
+def _oracle_step(job):
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import pyoracle as O
+    e, n_envs, sweeps, x, v, w, pk, pl = job
+    spec = SG.batch_spec(3000, e, sweeps=sweeps)
+    spec = dict(spec, x=x, v=v, w=w, warm_start="prev", max_sweeps=sweeps)
+    o = O.OracleScene(spec)
+    o.prev_keys, o.prev_lam = pk, pl
+    t0 = time.perf_counter()
+    out = o.step()
+    return e, out["contacts"] * out["sweeps"], time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_batched(args):
+    from multiprocessing import get_context
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    n_envs = args.envs
+    specs = SG.batch_specs(seed=3000, n_envs=n_envs, sweeps=args.sweeps)
+    order = sorted(range(n_envs), key=lambda e: -len(specs[e]["x"]))  # largest first
+    del specs
+    with get_context("fork").Pool(cores) as pool:
+        settled = pool.map(_oracle_settle, [(e, n_envs, args.cpu_settle, args.sweeps) for e in order], chunksize=1)
+        jobs = [(e, n_envs, args.sweeps, x, v, w, pk, pl) for e, x, v, w, pk, pl in settled]
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_step, jobs, chunksize=1)
+        wall = time.perf_counter() - t0
+    cs = sum(r[1] for r in res)
+    return dict(value=cs / wall, unit="contacts*sweeps/s", cores=cores, kind="oracle",
+                nproc=os.cpu_count(), cpu_model=cpu_model(),
+                sample=f"one FP64 oracle step ({args.sweeps} sweeps, previous-step start) of each of the same "
+                       f"{n_envs} beds, settled by the oracle for {args.cpu_settle} steps of 10 sweeps first "
+                       f"(untimed); {cores} worker processes, one bed at a time each, largest first; "
+                       f"{cs:.3e} contact-sweeps in {wall:.1f} s wall ({sum(r[2] for r in res):.1f} s of CPU)")
+
+
+# ---------------------------------------------------------------------------
+# learned warm start: training on the GPU, then sweeps to R_k <= 1e-4
+# ---------------------------------------------------------------------------
+def learned_eval(args):
+    from paper_2011_00459_amd import learn as LN
+    t0 = time.perf_counter()
+    feat, label = LN.gen_mixed_dataset(seed=100, cap=args.train_samples)
+    tr = LN.Trainer(LN.init_weights(0, LN.input_scale(feat)), feat, LN.residual_targets(feat, label), batch=4096)
+    hist = tr.fit(epochs=args.epochs, lr=3e-3, lr_end=2e-4)
+    w = tr.weights()
+    res = {"training": dict(samples=len(feat), epochs=args.epochs, loss_first=hist[0], loss_last=hist[-1],
+                            seconds=time.perf_counter() - t0)}
+    specs = SG.batch_specs(seed=3000, n_envs=args.envs, sweeps=100)
+    mat = specs[0]["material"]
+    specs = [dict(s, material=mat) for s in specs]
+    r = LN.sweeps_to_tol(specs, weights=w, settle=args.settle, steps=args.eval_steps, tol=1e-4,
+                         max_sweeps=5000, graphs=False)
+    r["learned_vs_cold_steps_per_s"] = r["learned"]["steps_per_s"] / r["cold"]["steps_per_s"]
+    r["learned_vs_prev_steps_per_s"] = r["learned"]["steps_per_s"] / r["prev"]["steps_per_s"]
+    r["prev_vs_cold_steps_per_s"] = r["prev"]["steps_per_s"] / r["cold"]["steps_per_s"]
+    res[f"batched_{args.envs}"] = r
+    cols = LN.column_batch(8, seed=900)
+    c = LN.sweeps_to_tol(cols, weights=w, settle=60, steps=10, tol=1e-4, max_sweeps=5000)
+    c["learned_vs_cold_steps_per_s"] = c["learned"]["steps_per_s"] / c["cold"]["steps_per_s"]
+    c["learned_vs_prev_steps_per_s"] = c["learned"]["steps_per_s"] / c["prev"]["steps_per_s"]
+    c["prev_vs_cold_steps_per_s"] = c["prev"]["steps_per_s"] / c["cold"]["steps_per_s"]
+    res["columns_1000"] = c
+    return res, w
 
 
 def bench_copy(args):
@@ -404,31 +560,6 @@ def mlp_throughput(n=1 << 22):
     return out
 
 
-def learned_eval(args):
-    """Train the learned start on the GPU (column trajectories of the plain
-    solver) and measure steps/s and sweeps to R_k <= 1e-4 with the cold,
-    previous-step and learned starts, each from one shared settled state."""
-    from paper_2011_00459_amd import learn as LN
-    t0 = time.perf_counter()
-    feat, label = LN.gen_dataset(n_envs=16, steps=120, cap=1_000_000, seed=100)
-    tr = LN.Trainer(LN.init_weights(0, LN.input_scale(feat)), feat, LN.residual_targets(feat, label), batch=4096)
-    hist = tr.fit(epochs=20, lr=3e-3, lr_end=2e-4)
-    w = tr.weights()
-    train_s = time.perf_counter() - t0
-    res = {"training": dict(samples=len(feat), epochs=20, loss_first=hist[0], loss_last=hist[-1],
-                            seconds=train_s)}
-    cols = LN.column_batch(8, seed=900)
-    res["columns_1000"] = LN.sweeps_to_tol(cols, weights=w, settle=60, steps=10, tol=1e-4, max_sweeps=4000)
-    specs = SG.batch_specs(seed=3000, n_envs=args.eval_envs, sweeps=100)
-    mat = specs[0]["material"]
-    specs = [dict(s, material=mat) for s in specs]
-    res[f"batched_{args.eval_envs}"] = LN.sweeps_to_tol(specs, weights=w, settle=40, steps=4, tol=1e-4,
-                                                       max_sweeps=3000)
-    for k in ("columns_1000", f"batched_{args.eval_envs}"):
-        r = res[k]
-        r["learned_vs_cold_steps_per_s"] = r["learned"]["steps_per_s"] / r["cold"]["steps_per_s"]
-        r["learned_vs_prev_steps_per_s"] = r["learned"]["steps_per_s"] / r["prev"]["steps_per_s"]
-    return res
 
 
 def main():
@@ -436,31 +567,33 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=50000)
-    ap.add_argument("--sweeps", type=int, default=None, help="PGS sweeps (150 for the bed, 100 batched)")
-    ap.add_argument("--settle", type=int, default=150)
+    ap.add_argument("--workload", choices=("batched", "bed", "excavation", "copy", "mlp", "voxels"),
+                    default="batched",
+                    help="batched: the headline line (256 beds) with the other workloads as extra keys; bed, "
+                         "excavation: that workload alone; mlp: the network's throughput; voxels: the "
+                         "mesoscale step; copy: the traffic-counter calibration")
+    ap.add_argument("--envs", type=int, default=256)
+    ap.add_argument("--sweeps", type=int, default=100, help="PGS sweeps of the batched beds")
+    ap.add_argument("--settle", type=int, default=150, help="settling steps of the beds before timing")
+    ap.add_argument("--settle-excavation", type=int, default=120)
+    ap.add_argument("--n", type=int, default=50000, help="spheres of the bulldozing bed (voxels workload too)")
+    ap.add_argument("--cpu-settle", type=int, default=30, help="oracle settling steps of each bed (untimed)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("bed", "batched", "copy", "mlp", "voxels"), default="bed",
-                    help="mlp: the learned-start network's throughput alone (one JSON line); voxels: the "
-                         "mesoscale advection step")
-    ap.add_argument("--envs", type=int, default=256)
-    ap.add_argument("--schedule", default="", help="PGS schedule as JSON (set_solver_config fields)")
+    ap.add_argument("--no-extras", action="store_true", help="headline only: no bed, excavation, mlp, warm start")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-start training and evaluation")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default PGS schedule")
+    ap.add_argument("--schedule", default="", help="PGS schedule as JSON (set_solver_config fields)")
     ap.add_argument("--launch", choices=("eager", "graphs"), default="eager",
                     help="launch every kernel of a step (measured faster here) or replay step graphs")
-    ap.add_argument("--eval-envs", type=int, default=64, help="batched beds of the warm-start evaluation")
+    ap.add_argument("--train-samples", type=int, default=2_000_000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--eval-steps", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is design-only",
               file=sys.stderr)
         sys.exit(2)
-    if args.sweeps is None:
-        args.sweeps = 100 if args.workload == "batched" else 150
-    if args.workload == "batched":
-        bench_batched(args)
-        return
     if args.workload == "copy":
         bench_copy(args)
         return
@@ -470,64 +603,65 @@ def main():
     if args.workload == "mlp":
         print(json.dumps({"workload": "learned-start network, 4,194,304 contacts", "mlp": mlp_throughput()}))
         return
+    base = {"metric": "contacts*PGS-sweeps/s (whole step)", "unit": "contacts*sweeps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    if args.workload == "bed":
+        r = leg_bed(args, n=args.n)
+        line = dict(base, value=r.pop("value"), ms_per_step=r.pop("ms_per_step"), roofline=r.pop("roofline"),
+                    config={"workload": f"bulldozing bed: {args.n} spheres r 0.03 m, 4x2 m, box blade "
+                                        "1.5x0.05x0.6 m at 1 m/s, 0.2 m deep, dt 1/60 s, 150 sweeps, prev warm "
+                                        "start, active zone aggregated every step", **r})
+        print(json.dumps(line), flush=True)
+        return
+    if args.workload == "excavation":
+        r = leg_excavation(args)
+        line = dict(base, value=r.pop("value"), ms_per_step=r.pop("ms_per_step"), roofline=r.pop("roofline"),
+                    config={"workload": "excavation: 500000 spheres r 0.02 m U(0.85, 1.15), 8x4 m bed, open bucket "
+                                        "1.2x1.0x0.8 m dragged at 0.8 m/s 0.4 m deep after a 30-degree descent, "
+                                        "dt 1/60 s, 200 sweeps, active zone aggregated every step", **r})
+        print(json.dumps(line), flush=True)
+        return
 
-    sc, spec, blade, est_top = build_bed(args)
-    if args.schedule:
-        sc.set_solver_config(**json.loads(args.schedule))
-    st0, top = settle(sc, spec, blade, args.settle)
-    print(f"# settled: {st0['contacts']} contacts, top {top:.3f} m (estimate {est_top:.3f})", file=sys.stderr,
-          flush=True)
-    moving = dict(blade)
-    moving["pos"] = (-1.6, 0.0, top - 0.2 + 0.3)
-    moving["linvel"] = (1.0, 0.0, 0.0)
-    bodies = [dict(spec["bodies"][0], id=0), dict(moving, id=1)]
-    sc.set_kinematic_bodies(0, bodies)
-    tuned = None
-    if not args.schedule and not args.no_autotune:
-        tuned = sc.autotune(steps=3)  # times the candidate schedules from this state, then restores it
-        sc.set_step_graphs(args.launch == "graphs")
-    for _ in range(args.warmup):
-        sc.step(1)
-    wall, tot_cs, pgs_bytes, pgs_ms, stats = timed_steps(sc, args.steps)
-    value = tot_cs / wall
-    ms_per_step = 1e3 * wall / args.steps
-    pgs_launch_ms = pgs_ms / args.steps
-    achieved = pgs_bytes / args.steps / (pgs_launch_ms * 1e-3) / 1e9 if pgs_launch_ms > 0 else 0.0
-    last = stats[-1][0]
-    phases = {k: float(np.mean([ph[k] for _, ph in stats])) for k in ("detect", "rows", "pgs", "finish", "step")}
-    f, _ = sc.get_contact_forces(0, 1)
-    aggs = sc.get_aggregates(0)
-    line = {
-        "metric": "contacts*PGS-sweeps/s (whole step)",
-        "value": value,
-        "unit": "contacts*sweeps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"bulldozing bed: {args.n} spheres r 0.03 m, 4x2 m, box blade 1.5x0.05x0.6 m "
-                               f"at 1 m/s, 0.2 m deep, dt 1/60 s, {args.sweeps} sweeps, prev warm start",
-                   "contacts_per_step": last["contacts"], "pair_contacts": last["pair_contacts"],
-                   "colours": last["colours"], "sweeps": last["sweeps"],
-                   "pgs_ms_per_step": pgs_launch_ms,
-                   "schedule": sc.get_solver_config(), "autotune_ms_per_step": tuned[1] if tuned else None,
-                   "phase_ms": phases,
-                   "blade_force_x_N": float(f[0])},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": pgs_traffic(),
-                     "algorithmic_bytes_per_launch": pgs_bytes / args.steps,
-                     "kernel": "k_pgs (persistent colour-synchronous PGS)"},
-    }
-    if not args.no_learned:
-        line["mlp"] = mlp_throughput()
-        line["warm_start_to_1e-4"] = learned_eval(args)
+    log("batched beds")
+    r, _ = leg_batched(args)
+    line = dict(base, value=r.pop("value"), ms_per_step=r.pop("ms_per_step"), roofline=r.pop("roofline"))
+    line["config"] = {"workload": f"batched: {r['envs']} independent beds, {r['spheres']} spheres (log-uniform "
+                                  "500-20000 per bed), blade or bucket at U(0.3, 1.5) m/s, dt 1/60 s, "
+                                  f"{args.sweeps} sweeps, prev warm start, "
+                                  f"{'eager launches' if args.launch == 'eager' else 'step graphs'}", **r}
+    weights = None
+
+    def extra(key, fn, *a, **kw):
+        # an extra workload that fails records its error; the headline stands
+        log(key)
+        t0 = time.perf_counter()
+        try:
+            out = fn(*a, **kw)
+        except Exception as e:  # noqa: BLE001
+            line[key] = {"error": f"{type(e).__name__}: {e}"}
+            out = None
+        log(f"{key}: {time.perf_counter() - t0:.1f} s")
+        return out
+
+    if not args.no_extras:
+        r = extra("mlp", mlp_throughput)
+        if r is not None:
+            line["mlp"] = r
+        if not args.no_learned:
+            r = extra("warm_start_to_1e-4", learned_eval, args)
+            if r is not None:
+                line["warm_start_to_1e-4"], weights = r
+        r = extra("bed50k", leg_bed, args)
+        if r is not None:
+            line["bed50k"] = r
+        r = extra("excavation500k", leg_excavation, args, weights=weights)
+        if r is not None:
+            line["excavation500k"] = r
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(args)
+        r = extra("cpu_baseline", cpu_baseline_batched, args)
+        if r is not None:
+            line["cpu_baseline"] = r
     print(json.dumps(line), flush=True)
 
 

@@ -99,6 +99,48 @@ def gen_dataset(n_envs=16, steps=120, skip=8, seed=100, tol=1e-5, max_sweeps=400
     return feat, label
 
 
+def gen_bed_dataset(n_envs=32, steps=60, skip=20, seed=7000, tol=1e-5, max_sweeps=4000, cap=2_000_000, log=None):
+    """Features and converged impulses from beds of the batched workload's
+    distribution (`scenegen.batch_specs` with seeds seed .. seed + n_envs - 1,
+    disjoint from the evaluation beds), their tools moving, stepped on the GPU
+    with the previous-step start and a tight residual tolerance; the first
+    `skip` steps (the pour) are not recorded."""
+    specs = SG.batch_specs(seed=seed, n_envs=n_envs, sweeps=max_sweeps)
+    mat = specs[0]["material"]
+    specs = [dict(s, material=mat, tol=tol, warm_start="prev") for s in specs]
+    nmax = max(len(s["x"]) for s in specs)
+    sc = T.scene_from_specs(specs, cap_particles=nmax, cap_contacts=8 * nmax)
+    feats, labels, total = [], [], 0
+    for k in range(steps):
+        st = sc.step(1)
+        if k < skip:
+            continue
+        for e in range(n_envs):
+            f, lab = sc.get_learn_samples(e)
+            feats.append(f)
+            labels.append(lab)
+            total += len(f)
+        if log and k % 10 == 0:
+            log(f"bed dataset step {k}: {total} samples, mean sweeps {np.mean([s['sweeps'] for s in st]):.0f}")
+    sc.close()
+    feat, label = np.concatenate(feats), np.concatenate(labels)
+    ok = np.all(np.isfinite(feat), axis=1) & np.all(np.isfinite(label), axis=1)
+    feat, label = feat[ok], label[ok]
+    if len(feat) > cap:
+        keep = np.sort(np.random.default_rng(seed).choice(len(feat), cap, replace=False))
+        feat, label = feat[keep], label[keep]
+    return feat, label
+
+
+def gen_mixed_dataset(seed=100, cap=2_000_000, log=None):
+    """Half the samples from column trajectories (the small workload), half
+    from beds of the batched workload's distribution: the contacts the plain
+    solver produces on the scenes the start is judged on."""
+    fc, lc = gen_dataset(seed=seed, cap=cap // 2, log=log)
+    fb, lb = gen_bed_dataset(seed=7000 + seed, cap=cap - len(fc), log=log)
+    return np.concatenate([fc, fb]), np.concatenate([lc, lb])
+
+
 def residual_targets(feat, label):
     """Training targets of the residual form: converged impulse minus the
     previous-step impulse (inputs 3-5), both in the contact frame / (m_eff g dt)."""
@@ -211,8 +253,14 @@ def sweeps_to_tol(specs, modes=("cold", "prev", "learned"), weights=None, settle
             sweeps.extend(x["sweeps"] for x in st)
             capped += sum(x["sweeps"] >= max_sweeps for x in st)
             fallback += sum(x["fallback_used"] for x in st)
+        edges = [0, 10, 30, 100, 300, 1000, 3000, max_sweeps, max_sweeps + 1]
+        hist, _ = np.histogram(sweeps, bins=edges)
         out[mode] = dict(mean_sweeps=float(np.mean(sweeps)), steps_per_s=steps / wall, capped=int(capped),
-                         fallback=int(fallback), steps=steps)
+                         capped_frac=float(capped) / max(len(sweeps), 1), fallback=int(fallback),
+                         env_steps=len(sweeps), steps=steps,
+                         sweep_histogram={"edges": edges, "counts": [int(c) for c in hist]})
+        if mode == "learned":
+            out[mode]["learned_kept"] = len(sweeps) - int(fallback)
     sc.close()
     return out
 
