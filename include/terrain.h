@@ -490,11 +490,17 @@ int mlp_adam_step(float* weights, const float* grad, float* m, float* v, float l
  *     LDS when it has at most lds_particles particles) or, when it has more
  *     than T particles, by a cluster of ceil(n / T) blocks; small envs share
  *     blocks and run on them one after another.  T = cluster_particles, or
- *     with 0 the mean particles per resident block (at least 4096). */
+ *     with 0 the mean particles per resident block (at least 4096).
+ *   TR_PGS_SPREAD: one env (n_envs must be 1) spread over all 8 XCDs: its
+ *     sorted spheres in eighths (compact regions of the Morton order), each
+ *     contact solved by the XCD group of its second sphere with
+ *     blocks_per_xcd blocks, all groups meeting after every colour; every
+ *     body store is written through to be seen across XCDs. */
 #define TR_PGS_GROUPED 0
 #define TR_PGS_PER_ENV 1
+#define TR_PGS_SPREAD 2
 typedef struct tr_solver_config {
-    int32_t mode;              /* TR_PGS_GROUPED or TR_PGS_PER_ENV */
+    int32_t mode;              /* TR_PGS_GROUPED, TR_PGS_PER_ENV or TR_PGS_SPREAD */
     int32_t blocks_per_xcd;    /* grouped: >= 1, clamped to the resident limit */
     int32_t lds_particles;     /* per-env: >= 0, clamped to what LDS holds */
     int32_t cluster_particles; /* per-env: T, or 0 for the automatic choice */
@@ -516,9 +522,10 @@ int get_solver_config(tr_scene* s, tr_solver_config* cfg);
  * get_phase_times are all recorded around the whole step. */
 int set_step_graphs(tr_scene* s, int32_t enable);
 
-/* Autotuner of the PGS schedule.  Times candidate schedules (grouped with 32,
- * 16 or 8 blocks per XCD; per-env with automatic, 8192- and 16384-sphere
- * clusters; per-env without LDS; grouped is left out when a residual
+/* Autotuner of the PGS schedule.  Times candidate schedules (grouped with 64,
+ * 32, 16 or 8 blocks per XCD; spread with 32 for a single env; per-env with
+ * automatic, 8192- and 16384-sphere clusters; per-env without LDS; grouped is
+ * left out when a residual
  * tolerance is set with more than 8 envs, where it would let envs share their
  * stopping test) over `steps` eager steps each, every
  * candidate from the scene's current state (saved and restored, so the scene

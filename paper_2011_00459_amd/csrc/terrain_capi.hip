@@ -289,6 +289,7 @@ int rebuild_plan(tr_scene* s)
     if (!plan_idx.empty())
         HIP_CHECK(s, hipMemcpyAsync(s->b.plan_idx, plan_idx.data(), sizeof(uint32_t) * plan_idx.size(), hipMemcpyHostToDevice, st));
     s->z.pgs_mode = s->cfg.mode;
+    s->p.spread = s->cfg.mode == TR_PGS_SPREAD ? 1 : 0;
     s->z.plan_blocks = blocks;
     s->z.lds_cap = lds_cap;
     HIP_CHECK(s, hipMemcpyAsync(s->b.envs, s->env_host.data(), sizeof(EnvDev) * E, hipMemcpyHostToDevice, st));
@@ -1420,9 +1421,12 @@ int set_solver_config(tr_scene* s, const tr_solver_config* cfg)
 {
     if (!s || !cfg) return TR_E_INVAL;
     s->err.clear();
-    if ((cfg->mode != TR_PGS_GROUPED && cfg->mode != TR_PGS_PER_ENV) || cfg->blocks_per_xcd < 1 ||
-        cfg->lds_particles < 0 || cfg->cluster_particles < 0 || (cfg->dataflow != 0 && cfg->dataflow != 1))
+    if ((cfg->mode != TR_PGS_GROUPED && cfg->mode != TR_PGS_PER_ENV && cfg->mode != TR_PGS_SPREAD) ||
+        cfg->blocks_per_xcd < 1 || cfg->lds_particles < 0 || cfg->cluster_particles < 0 ||
+        (cfg->dataflow != 0 && cfg->dataflow != 1))
         return fail(s, TR_E_INVAL, "set_solver_config: bad field");
+    if (cfg->mode == TR_PGS_SPREAD && (s->desc.n_envs != 1 || cfg->dataflow))
+        return fail(s, TR_E_INVAL, "set_solver_config: the spread schedule takes one env and barriers");
     s->cfg = *cfg;
     s->cfg.blocks_per_xcd = std::min(cfg->blocks_per_xcd, std::max(1, pgs_resident_blocks(512) / kGroups));
     s->cfg.lds_particles = std::min(cfg->lds_particles, s->max_lds_particles);
@@ -1872,6 +1876,7 @@ int autotune(tr_scene* s, int32_t steps, const char* cache_path, tr_solver_confi
     // that would change results (a residual tolerance with more than 8 envs)
     if (!(s->desc.tol > 0.0 && s->desc.n_envs > kGroups))
         for (int bpx : {64, 32, 16, 8}) cands.push_back({TR_PGS_GROUPED, bpx, s->max_lds_particles, 0, 0});
+    if (s->desc.n_envs == 1) cands.push_back({TR_PGS_SPREAD, 32, s->max_lds_particles, 0, 0});
     for (int cp : {0, 8192, 16384}) cands.push_back({TR_PGS_PER_ENV, 32, s->max_lds_particles, cp, 0});
     cands.push_back({TR_PGS_PER_ENV, 32, 0, 0, 0});
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -34,6 +34,7 @@ constexpr int kMlpParams = 64 * 12 + 64 + 64 * 64 + 64 + 3 * 64 + 3 + 12;
 enum : int {
     kModeGrouped = 0,  // envs in kGroups XCD groups, grid-wide colour barriers per group
     kModePerEnv = 1,   // each env solved by its own block (or cluster of blocks)
+    kModeSpread = 2,   // one env spread over the kGroups XCD groups by space, all groups meeting per colour
 };
 constexpr int kEnvBlk = 1024;  // threads of a per-env PGS block
 
@@ -144,7 +145,7 @@ struct StepParams {
     int n_units;        // PGS solve units (entries of ustats)
     float restitution;  // Newton restitution of the impact stage
     int n_tools;        // zone predictor tools (all envs)
-    int pad_tools;
+    int spread;         // 1: spread mode (the PGS groups split the env by space)
 };
 
 // per PGS solve unit: an XCD group of envs (grouped mode) or one env
@@ -170,6 +171,7 @@ struct Counters {
     uint32_t failed;       // OR of the overflow bits of every step since the host last read it
     uint32_t pad[11];
     uint32_t bar[kGroups][16];  // per-group barrier counters, one cache line each
+    uint32_t gbar[16];          // spread mode: arrivals of the groups at the colour barrier
 };
 
 struct EnvStats {
@@ -256,7 +258,7 @@ struct Sizes {
     int n_zone_chunks;
     int pgs_grid;   // blocks of the persistent PGS kernel (kGroups x blocks per group)
     int pgs_block;  // threads per PGS block
-    int pgs_mode;   // kModeGrouped or kModePerEnv
+    int pgs_mode;   // kModeGrouped, kModePerEnv or kModeSpread
     int plan_blocks;  // blocks of the per-env PGS kernel
     int lds_cap;    // particles whose bodies a per-env block keeps in LDS (0: none)
     int n_units;    // entries of ustats

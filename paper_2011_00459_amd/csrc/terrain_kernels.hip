@@ -748,7 +748,20 @@ __device__ inline int contact_group(const DevBuffers& b, unsigned long long key,
     return b.envs[env_of((int)(key >> 32), id_cap)].group;
 }
 
-__global__ void k_col_hist(DevBuffers b, int64_t cap, int64_t NB, uint32_t id_cap)
+// Spread mode: the XCD group of a sphere slot (its env's slots in eighths:
+// the sort keeps them in Morton order, so each eighth is a compact region) and
+// of a contact (that of its second sphere, a particle for every contact).
+__device__ inline int slot_part(const DevBuffers& b, int sl, uint32_t id_cap)
+{
+    const EnvDev& E = b.envs[env_of(b.pid[sl], id_cap)];
+    return (int)(((int64_t)(sl - E.slot_begin) * kGroups) / max(E.n, 1));
+}
+__device__ inline int contact_group_of(const DevBuffers& b, uint32_t c, uint32_t id_cap, int spread)
+{
+    return spread ? slot_part(b, b.cpair[c].y, id_cap) : contact_group(b, b.ckey[c], id_cap);
+}
+
+__global__ void k_col_hist(DevBuffers b, int64_t cap, int64_t NB, uint32_t id_cap, int spread)
 {
     __shared__ uint32_t h[kBuckets];
     uint32_t nc = n_contacts(b, cap);
@@ -757,13 +770,13 @@ __global__ void k_col_hist(DevBuffers b, int64_t cap, int64_t NB, uint32_t id_ca
     uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < nc) {
         int col = b.colour[c];
-        if (col >= 0 && col < kMaxColours) atomicAdd(&h[col * kGroups + contact_group(b, b.ckey[c], id_cap)], 1u);
+        if (col >= 0 && col < kMaxColours) atomicAdd(&h[col * kGroups + contact_group_of(b, c, id_cap, spread)], 1u);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) b.col_hist[(int64_t)k * NB + blockIdx.x] = h[k];
 }
 
-__global__ void k_col_scatter(DevBuffers b, int64_t cap, int64_t NB, uint32_t id_cap)
+__global__ void k_col_scatter(DevBuffers b, int64_t cap, int64_t NB, uint32_t id_cap, int spread)
 {
     __shared__ int bk[kBlk];
     uint32_t nc = n_contacts(b, cap);
@@ -771,7 +784,7 @@ __global__ void k_col_scatter(DevBuffers b, int64_t cap, int64_t NB, uint32_t id
     int my = -1;
     if (c < nc) {
         int col = b.colour[c];
-        if (col >= 0 && col < kMaxColours) my = col * kGroups + contact_group(b, b.ckey[c], id_cap);
+        if (col >= 0 && col < kMaxColours) my = col * kGroups + contact_group_of(b, c, id_cap, spread);
     }
     bk[threadIdx.x] = my;
     __syncthreads();
@@ -899,10 +912,12 @@ void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hip
         hipLaunchKernelGGL(k_env_colsort, dim3((unsigned)z.n_envs), dim3(kBlk), 0, s, b, p.id_cap);
         return;
     }
-    hipLaunchKernelGGL(k_col_hist, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB, p.id_cap);
+    const int spread = z.pgs_mode == kModeSpread ? 1 : 0;
+    hipLaunchKernelGGL(k_col_hist, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB, p.id_cap, spread);
     launch_scan_u32(b.col_hist, b.col_start, (int64_t)kBuckets * z.NB, b.scan_tmp, s);
-    hipLaunchKernelGGL(k_col_scatter, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB, p.id_cap);
+    hipLaunchKernelGGL(k_col_scatter, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, z.NB, p.id_cap, spread);
     hipLaunchKernelGGL(k_env_ncol, dim3((unsigned)z.NB), dim3(kBlk), 0, s, b, z.C, p.id_cap);
+
 }
 
 // ---------------------------------------------------------------------------
@@ -1323,6 +1338,35 @@ __device__ inline bool cluster_wait(Counters* cnt, uint32_t* counter, unsigned t
     return flag != 0;
 }
 
+// Spread mode: after each colour the eight groups meet.  The blocks of a group
+// arrive at its counter (cluster_arrive); the group's rank-0 block waits for
+// them, arrives at the global counter and waits for all groups, then releases
+// its group through the group's release word (counter[2]).  nbar counts the
+// group's barriers including the first (placement) one, which the global
+// counter does not see.  Returns false when a wait failed.
+template <bool FENCED>
+__device__ inline bool spread_wait(Counters* cnt, uint32_t* counter, unsigned nbar, unsigned K, unsigned rank,
+                                   int& flag)
+{
+    if (threadIdx.x == 0) {
+        bool ok;
+        if (rank == 0) {
+            ok = wait_counter(cnt, counter, nbar * K);
+            if (ok) {
+                __hip_atomic_fetch_add(&cnt->gbar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = wait_counter(cnt, &cnt->gbar[0], (nbar - 1) * (unsigned)kGroups);
+            }
+            if (ok) __hip_atomic_store(&counter[2], nbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = wait_counter(cnt, &counter[2], nbar);
+        }
+        flag = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (FENCED) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return flag != 0;
+}
+
 // First barrier of a launch: every block of the cluster sets the bit of its
 // XCD in counter[1] (zeroed before the launch).  The round-robin dispatch
 // puts blocks congruent mod 8 on one XCD, but which XCD depends on the
@@ -1374,6 +1418,19 @@ struct XcdBodies {
     __device__ float4 v(int i) const { return ld_body<kCoherent>(rv, i); }
     __device__ float4 w(int i) const { return ld_body<kCoherent>(rw, i); }
     __device__ void set(int i, float4 v, float4 w) const { st_body<0>(rv, i, v); st_body<0>(rw, i, w); }
+};
+// Spread mode: one env's contacts on all XCDs, so every body store is written
+// through (sc1) and every load is device-scope: measured on MI355X, such a
+// store is seen by another XCD's device-scope load once it has completed.
+struct SpreadBodies {
+    __amdgpu_buffer_rsrc_t rv, rw;
+    __device__ float4 v(int i) const { return ld_body<kCoherent>(rv, i); }
+    __device__ float4 w(int i) const { return ld_body<kCoherent>(rw, i); }
+    __device__ void set(int i, float4 v, float4 w) const
+    {
+        st_body<kCoherent>(rv, i, v);
+        st_body<kCoherent>(rw, i, w);
+    }
 };
 struct PlainBodies {
     float4 *pv, *pw;
@@ -1535,7 +1592,7 @@ __device__ inline bool flow_wait(Counters* cnt, const uint32_t* ver, int j, uint
 // equal slices.  Blocks of the cluster are first + 8 t, t < K.  FLOW: colours
 // are ordered by the per-sphere counters (clusters only); a barrier remains at
 // the end of a sweep when a residual tolerance is set, and once at the end.
-template <class BA, bool CLUSTER, bool FENCED, bool FLOW, bool ROLL, int NW, class Starts>
+template <class BA, bool CLUSTER, bool FENCED, bool FLOW, bool ROLL, int NW, class Starts, bool SPREAD = false>
 __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba, Starts cstart, uint32_t ncol,
                           uint32_t* counter, unsigned nbar, unsigned rank, unsigned K, unsigned first, int sweeps_cap,
                           int slot, int unit, double (*red)[NW], uint32_t (*cb)[kMaxColours], int& flag)
@@ -1558,7 +1615,7 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
     }
     __syncthreads();
     uint32_t tail = ncol;
-    if (CLUSTER && !FLOW)
+    if (CLUSTER && !FLOW && !SPREAD)
         while (tail > 0 && clen[tail - 1] <= kThreads) --tail;
     auto range = [&](uint32_t col, uint32_t& lo, uint32_t& hi) {
         uint32_t beg = cbeg[col], len = clen[col];
@@ -1577,9 +1634,12 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
         const double* part = b.block_part + (size_t)(FLOW ? sw : (sw & 1)) * nblk * 2;
         if (threadIdx.x < 64) {
             double a = 0.0, d = 0.0;
-            for (unsigned t = threadIdx.x; t < K; t += 64) {
-                a += __hip_atomic_load(&part[2 * (first + 8 * t)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                d += __hip_atomic_load(&part[2 * (first + 8 * t) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // spread mode: the partials of every block of every group
+            const unsigned nb = SPREAD ? nblk : K;
+            for (unsigned t = threadIdx.x; t < nb; t += 64) {
+                const unsigned blk = SPREAD ? t : first + 8 * t;
+                a += __hip_atomic_load(&part[2 * blk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                d += __hip_atomic_load(&part[2 * blk + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             for (int o = 32; o > 0; o >>= 1) {
                 a += __shfl_down(a, o, 64);
@@ -1682,7 +1742,11 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
                 c = lo + threadIdx.x;
                 fetch();
-                if (!cluster_wait<FENCED>(b.cnt, counter, nbar * K, flag)) return;  // every block leaves
+                if (SPREAD) {
+                    if (!spread_wait<FENCED>(b.cnt, counter, nbar, K, rank, flag)) return;  // every block leaves
+                } else if (!cluster_wait<FENCED>(b.cnt, counter, nbar * K, flag)) {
+                    return;  // every block leaves
+                }
             } else {
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
                 c = lo + threadIdx.x;
@@ -1734,7 +1798,7 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
         combine(sweeps - 1, sn, sd);
         Rk = resid(sn, sd);
     }
-    if (rank == 0 && threadIdx.x == 0) {
+    if (rank == 0 && threadIdx.x == 0 && (!SPREAD || first == 0)) {
         UnitStats& G = b.ustats[unit];
         if (slot == 0) {
             G.sweeps = (uint32_t)sweeps;
@@ -1751,7 +1815,8 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
 __global__ void k_pgs_reset(DevBuffers b, int n_envs)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < kGroups) { b.cnt->bar[t][0] = 0; b.cnt->bar[t][1] = 0; }
+    if (t < kGroups) { b.cnt->bar[t][0] = 0; b.cnt->bar[t][1] = 0; b.cnt->bar[t][2] = 0; }
+    if (t == 0) b.cnt->gbar[0] = 0;
     if (t < n_envs) { b.env_bar[(size_t)t * 16] = 0; b.env_bar[(size_t)t * 16 + 1] = 0; }
 }
 
@@ -1782,12 +1847,27 @@ __global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int
     const unsigned rank = blockIdx.x / kGroups, gx = gridDim.x / kGroups;
     GroupStarts cs{b.col_start, NB, g};
     uint32_t ncol = b.cnt->n_colours;
+    uint32_t* counter = &b.cnt->bar[g][0];
+    if (p.spread) {
+        // spread mode: the groups share one env (unit 0) and meet after every
+        // colour, so all of them run every colour, with or without contacts
+        if (slot == kSlotImpact && !b.ustats[0].imp_any) ncol = 0;  // no impact in the env
+        int mode = cluster_placement(b.cnt, counter, gx, flag);
+        if (mode == 1)
+            pgs_solve<SpreadBodies, true, false, false, ROLL, kPgsBlk / 64, GroupStarts, true>(
+                b, p, SpreadBodies{raw_rsrc(b.vm), raw_rsrc(b.wi)}, cs, ncol, counter, 1, rank, gx, (unsigned)g,
+                sweeps_cap, slot, 0, red, cb, flag);
+        else if (mode == 2)
+            pgs_solve<PlainBodies, true, true, false, ROLL, kPgsBlk / 64, GroupStarts, true>(
+                b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, gx, (unsigned)g, sweeps_cap, slot, 0, red,
+                cb, flag);
+        return;
+    }
     // a group without contacts only records its (trivial) statistics
     uint32_t total = 0;
     for (uint32_t col = 0; col < ncol; ++col) total += cs.end(col) - cs.beg(col);
     if (total == 0) ncol = 0;
     if (slot == kSlotImpact && !b.ustats[g].imp_any) ncol = 0;  // no impact in the group
-    uint32_t* counter = &b.cnt->bar[g][0];
     int mode = cluster_placement(b.cnt, counter, gx, flag);
     if (mode == 1) {
         XcdBodies ba{raw_rsrc(b.vm), raw_rsrc(b.wi)};

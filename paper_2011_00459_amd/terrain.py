@@ -29,7 +29,7 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "terrain_from_voxels", "convert_cut", "convert_deposit", "grow_particles", "form_particles",
            "remove_particles", "settle_particles", "get_colours", "mlp_loss_grad_noalloc")
 CG_KERNEL = {"heaviside": 0, "gauss": 1}
-PGS_MODE = {"grouped": 0, "per_env": 1}
+PGS_MODE = {"grouped": 0, "per_env": 1, "spread": 2}
 MLP_TRAINABLE = MLP_PARAMS - 12
 
 
