@@ -1882,3 +1882,279 @@ double orc_advect(const orc_voxel_grid* g, double dt, const double* u, double* m
     free(out);
     return cfl;
 }
+
+/* ------------------------------------------------------------------ */
+/* Macroscale model (section "Macroscale model"): the aggregate body A   */
+/* of a zone under Eq. mdb:eqAgg with the velocity constraints of Eqs.  */
+/* aggregateNormal and aggregateTangent at its interfaces to the        */
+/* equipment (AB) and the failure surface (AC), four points each.       */
+/* ------------------------------------------------------------------ */
+
+/* World-frame half-space p of body b: normal nw, offset dw (inside: nw.x <= dw). */
+static void zone_plane_world(const orc_body* B, int p, double nw[3], double* dw)
+{
+    double Rm[3][3];
+    quat_matrix(B->quat, Rm);
+    const double* pl = B->planes[p];
+    for (int k = 0; k < 3; ++k) nw[k] = (Rm[k][0] * pl[0] + Rm[k][1] * pl[1]) + Rm[k][2] * pl[2];
+    *dw = pl[3] + dot3(nw, B->pos);
+}
+
+/* In-plane axes of a plane with unit normal n: e1 the normalised projection
+ * of the world axis least aligned with n (the lower axis on ties), e2 = n x e1. */
+static void plane_axes(const double n[3], double e1[3], double e2[3])
+{
+    int k0 = 0;
+    for (int k = 1; k < 3; ++k) if (fabs(n[k]) < fabs(n[k0])) k0 = k;
+    double a[3] = {0.0, 0.0, 0.0};
+    a[k0] = 1.0;
+    double an = dot3(a, n);
+    for (int k = 0; k < 3; ++k) e1[k] = a[k] - an * n[k];
+    double m = sqrt(dot3(e1, e1));
+    for (int k = 0; k < 3; ++k) e1[k] /= m;
+    cross3(n, e1, e2);
+}
+
+int32_t orc_reduce4(int64_t n, const double* pts, const double nrm[3], int64_t idx[4])
+{
+    if (n <= 0) return 0;
+    double e1[3], e2[3];
+    plane_axes(nrm, e1, e2);
+    int64_t best[4] = {0, 0, 0, 0};
+    double bv[4];
+    for (int64_t i = 0; i < n; ++i) {
+        double s1 = dot3(&pts[3 * i], e1), s2 = dot3(&pts[3 * i], e2);
+        double val[4] = {s1, -s1, s2, -s2};
+        for (int d = 0; d < 4; ++d)
+            if (i == 0 || val[d] > bv[d]) { bv[d] = val[d]; best[d] = i; }  /* strict: ties keep the smaller index */
+    }
+    int32_t m = 0;
+    for (int d = 0; d < 4; ++d) {
+        int dup = 0;
+        for (int q = 0; q < m; ++q) dup |= idx[q] == best[d];
+        if (!dup) idx[m++] = best[d];
+    }
+    return m;
+}
+
+/* Inverse of a symmetric 3x3 matrix by cofactors. */
+static void inv3(const double A[3][3], double B[3][3])
+{
+    double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+    double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+    double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+    double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+    B[0][0] = c00 / det;
+    B[1][0] = c01 / det;
+    B[2][0] = c02 / det;
+    B[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+    B[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+    B[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+    B[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+    B[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+    B[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+}
+
+static void mat3_vec(const double A[3][3], const double x[3], double y[3])
+{
+    for (int k = 0; k < 3; ++k) y[k] = (A[k][0] * x[0] + A[k][1] * x[1]) + A[k][2] * x[2];
+}
+
+/* Velocity change of the point at arm rr per unit impulse along a, projected
+ * on b: (1/M) a.b + (rr x a) . Iinv (rr x b). */
+static double point_w(double invM, const double Iinv[3][3], const double rr[3], const double a[3], const double b[3])
+{
+    double ra[3], rb[3], t[3];
+    cross3(rr, a, ra);
+    cross3(rr, b, rb);
+    mat3_vec(Iinv, rb, t);
+    return invM * dot3(a, b) + dot3(ra, t);
+}
+
+int32_t orc_macro_step(const orc_params* P, int64_t n, const double* r, const double* rho,
+                       const double* x, const double* v, const double* w,
+                       int32_t nb, const orc_body* bodies, int32_t ns, const orc_shape* shapes,
+                       const orc_macro_params* mp, int32_t cap, orc_macro_out* out)
+{
+    const double dt = P->dt;
+    double* inv_m = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    for (int64_t i = 0; i < n; ++i) inv_m[i] = 1.0 / particle_mass(P, rho, i, r);
+    orc_aggregate* agg = (orc_aggregate*)calloc((size_t)(nb > 0 ? nb : 1), sizeof(orc_aggregate));
+    int32_t na = orc_aggregates(n, r, inv_m, x, v, w, nb, bodies, agg);
+    /* zone membership: the first body (in order) whose half-spaces all contain x */
+    int32_t* zone_of = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) {
+        zone_of[i] = -1;
+        for (int32_t b = 0; b < nb && zone_of[i] < 0; ++b) {
+            if (bodies[b].nplanes <= 0) continue;
+            int in = 1;
+            for (int p = 0; p < bodies[b].nplanes && in; ++p) {
+                double nw[3], dw;
+                zone_plane_world(&bodies[b], p, nw, &dw);
+                if (dot3(nw, &x[3 * i]) - dw > 0.0) in = 0;
+            }
+            if (in) zone_of[i] = b;
+        }
+    }
+    double* cand = (double*)malloc((size_t)(2 * n + 1) * 3 * sizeof(double));
+    int64_t* csrc = (int64_t*)malloc((size_t)(2 * n + 1) * sizeof(int64_t));
+    int32_t nout = 0;
+    for (int32_t ai = 0; ai < na && nout < cap; ++ai) {
+        const orc_aggregate* A = &agg[ai];
+        const int32_t b = A->zone;
+        const orc_body* B = &bodies[b];
+        if (B->nplanes < 2 || A->M <= 0.0) continue;
+        orc_macro_out* o = &out[nout++];
+        memset(o, 0, sizeof(*o));
+        o->zone = b;
+        o->M = A->M;
+        for (int k = 0; k < 3; ++k) { o->x[k] = A->x[k]; o->v0[k] = A->v[k]; o->w0[k] = A->w[k]; }
+        double I[3][3] = {{A->I[0], A->I[3], A->I[4]}, {A->I[3], A->I[1], A->I[5]}, {A->I[4], A->I[5], A->I[2]}};
+        double Iinv[3][3];
+        inv3(I, Iinv);
+        const double invM = 1.0 / A->M;
+        /* the aggregate's length scale: cube root of its solid volume */
+        double vol = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            if (zone_of[i] == b) vol += (4.0 / 3.0) * PI * r[i] * r[i] * r[i];
+        const double L = cbrt(vol);
+        double nsep[3], dsep, nfail[3], dfail;
+        zone_plane_world(B, 0, nsep, &dsep);
+        zone_plane_world(B, 1, nfail, &dfail);
+        for (int q = 0; q < 2; ++q) {
+            /* interface normals point from B or C into A: against the zone's
+             * outward normals of the separation plate and the failure plane */
+            double nI[3];
+            for (int k = 0; k < 3; ++k) nI[k] = -(q == 0 ? nsep[k] : nfail[k]);
+            int64_t nc = 0;
+            double area = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                if (zone_of[i] != b) continue;
+                if (q == 0) {
+                    for (int32_t s = 0; s < ns; ++s) {
+                        if (shapes[s].body != b) continue;
+                        double delta, nrm[3];
+                        if (!shape_touch(P, &shapes[s], bodies, &x[3 * i], r[i], &delta, nrm)) continue;
+                        double l2 = r[i] - 0.5 * delta;
+                        for (int k = 0; k < 3; ++k) cand[3 * nc + k] = x[3 * i + k] - l2 * nrm[k];
+                        csrc[nc++] = i;
+                        area += PI * r[i] * r[i];
+                    }
+                } else {
+                    double d = dot3(nfail, &x[3 * i]) - dfail;  /* <= 0 inside the zone */
+                    if (!(d >= -r[i])) continue;
+                    for (int k = 0; k < 3; ++k) cand[3 * nc + k] = x[3 * i + k] - d * nfail[k];
+                    csrc[nc++] = i;
+                    area += PI * r[i] * r[i];
+                }
+            }
+            o->n_cand[q] = nc;
+            o->area[q] = area;
+            int64_t idx[4];
+            int32_t m = orc_reduce4(nc, cand, nI, idx);
+            o->n_points[q] = m;
+            o->gamma[q] = area > 0.0 ? L / ((q == 0 ? mp->cas_ab : mp->cas_ac) * mp->E_b * area * dt) : 0.0;
+            for (int j = 0; j < m; ++j) {
+                for (int k = 0; k < 3; ++k) { o->p[4 * q + j][k] = cand[3 * idx[j] + k]; o->n[4 * q + j][k] = nI[k]; }
+                o->src[4 * q + j] = csrc[idx[j]];
+            }
+        }
+        /* Eq. mdb:eqAgg in impulse form: M (v+ - v) = dt M g + sum G^T lambda,
+         * I (w+ - w) = sum (p - x_A) x (G^T lambda); each point's normal row
+         * gamma lambda_n + n.u >= 0 with lambda_n >= -c_b A dt / points, its
+         * tangential rows gamma lambda_t + u_t = 0 on the disk
+         * |lambda_t| <= mu |lambda_n|, u the velocity of A at the point minus
+         * that of B (or 0 on the terrain).  Projected Gauss-Seidel, normal then
+         * tangential rows of each point in turn, until no impulse changes. */
+        double vv[3], ww[3];
+        for (int k = 0; k < 3; ++k) { vv[k] = A->v[k] + dt * P->g[k]; ww[k] = A->w[k]; }
+        int np = 0;
+        int map[8];
+        for (int q = 0; q < 2; ++q)
+            for (int j = 0; j < o->n_points[q]; ++j) map[np++] = 4 * q + j;
+        double rr[8][3], uo[8][3], Wn[8], Wt[8], lo[8], mu[8], gam[8], t1[8][3], t2[8][3];
+        for (int c = 0; c < np; ++c) {
+            int k8 = map[c], q = k8 / 4;
+            for (int k = 0; k < 3; ++k) rr[c][k] = o->p[k8][k] - A->x[k];
+            if (q == 0) {
+                double arm[3] = {o->p[k8][0] - B->pos[0], o->p[k8][1] - B->pos[1], o->p[k8][2] - B->pos[2]}, t[3];
+                cross3(B->angvel, arm, t);
+                for (int k = 0; k < 3; ++k) uo[c][k] = B->linvel[k] + t[k];
+            } else {
+                for (int k = 0; k < 3; ++k) uo[c][k] = 0.0;
+            }
+            plane_axes(o->n[k8], t1[c], t2[c]);
+            Wn[c] = point_w(invM, Iinv, rr[c], o->n[k8], o->n[k8]);
+            /* one scalar for both tangential rows (the disk's fixed point does
+             * not depend on it): their mean effective inverse mass */
+            Wt[c] = 0.5 * (point_w(invM, Iinv, rr[c], t1[c], t1[c]) + point_w(invM, Iinv, rr[c], t2[c], t2[c]));
+            lo[c] = -mp->c_b * o->area[q] * dt / (double)o->n_points[q];
+            mu[c] = q == 0 ? mp->mu_ab : mp->mu_ac;
+            gam[c] = o->gamma[q];
+        }
+        double lam[8][4];
+        memset(lam, 0, sizeof(lam));
+        int sweep = 0;
+        for (; sweep < 200000; ++sweep) {
+            double dmax = 0.0, lmax = 0.0;
+            for (int c = 0; c < np; ++c) {
+                const double* nn = o->n[map[c]];
+                for (int row = 0; row < 2; ++row) {
+                    double u[3], t[3];
+                    cross3(ww, rr[c], t);
+                    for (int k = 0; k < 3; ++k) u[k] = vv[k] + t[k] - uo[c][k];
+                    double J[3];
+                    if (row == 0) {
+                        double un = dot3(nn, u);
+                        double ln = lam[c][0] - (un + gam[c] * lam[c][0]) / (Wn[c] + gam[c]);
+                        if (ln < lo[c]) ln = lo[c];
+                        double d = ln - lam[c][0];
+                        lam[c][0] = ln;
+                        for (int k = 0; k < 3; ++k) J[k] = d * nn[k];
+                        if (fabs(d) > dmax) dmax = fabs(d);
+                    } else {
+                        double un = dot3(nn, u);
+                        double lt[3];
+                        for (int k = 0; k < 3; ++k) {
+                            double ut = u[k] - un * nn[k];
+                            lt[k] = lam[c][1 + k] - (ut + gam[c] * lam[c][1 + k]) / (Wt[c] + gam[c]);
+                        }
+                        double ltn = dot3(lt, nn);
+                        for (int k = 0; k < 3; ++k) lt[k] -= ltn * nn[k];
+                        double lim = mu[c] * fabs(lam[c][0]);
+                        double m2 = sqrt(dot3(lt, lt));
+                        if (m2 > lim) {
+                            double s = m2 > 0.0 ? lim / m2 : 0.0;
+                            for (int k = 0; k < 3; ++k) lt[k] *= s;
+                        }
+                        for (int k = 0; k < 3; ++k) {
+                            J[k] = lt[k] - lam[c][1 + k];
+                            if (fabs(J[k]) > dmax) dmax = fabs(J[k]);
+                            lam[c][1 + k] = lt[k];
+                        }
+                    }
+                    double tj[3], dw[3];
+                    cross3(rr[c], J, tj);
+                    mat3_vec(Iinv, tj, dw);
+                    for (int k = 0; k < 3; ++k) { vv[k] += invM * J[k]; ww[k] += dw[k]; }
+                }
+                for (int k = 0; k < 4; ++k) if (fabs(lam[c][k]) > lmax) lmax = fabs(lam[c][k]);
+            }
+            if (dmax <= 1e-15 * lmax || lmax == 0.0) { ++sweep; break; }
+        }
+        o->sweeps = sweep;
+        for (int k = 0; k < 3; ++k) { o->v[k] = vv[k]; o->w[k] = ww[k]; o->force_b[k] = 0.0; o->torque_b[k] = 0.0; }
+        for (int c = 0; c < np; ++c) {
+            int k8 = map[c];
+            for (int k = 0; k < 4; ++k) o->lam[k8][k] = lam[c][k];
+            if (k8 >= 4) continue;
+            double J[3], arm[3], t[3];
+            for (int k = 0; k < 3; ++k) J[k] = lam[c][0] * o->n[k8][k] + lam[c][1 + k];
+            for (int k = 0; k < 3; ++k) { o->force_b[k] -= J[k] / dt; arm[k] = o->p[k8][k] - B->pos[k]; }
+            cross3(arm, J, t);
+            for (int k = 0; k < 3; ++k) o->torque_b[k] -= t[k] / dt;
+        }
+    }
+    free(cand); free(csrc); free(zone_of); free(agg); free(inv_m);
+    return nout;
+}

@@ -250,6 +250,62 @@ typedef struct orc_aggregate {
     double L[3];
 } orc_aggregate;
 
+/* ---- Macroscale model: aggregate constraints and the aggregate's solve ----
+ * Section "Macroscale model": each active zone is aggregated into a rigid body
+ * A (Eqs. aggregate_mass .. aggregate_rot_vel) whose motion obeys Eq.
+ * mdb:eqAgg under the frictional-cohesive velocity constraints of Eqs.
+ * aggregateNormal and aggregateTangent at its interfaces to the equipment B
+ * (AB) and to the terrain's failure surface C (AC), each interface reduced to
+ * four contact points.  Readings (R44-R46 of the design notes): the zone's
+ * half-spaces follow the wedge convention (plane 0 the separation plate,
+ * plane 1 the failure plane); AB candidates are the zone's particles touching
+ * the zone body's shapes, AC candidates the zone's particles within their
+ * radius of the failure plane (projected onto it); each interface keeps its
+ * candidates extreme along +-e1 and +-e2 of its plane; A is the sum of the
+ * candidates' cross sections; gamma = L / (c_as E_b A dt) with L the cube
+ * root of the aggregate's solid volume; the equipment is kinematic and the
+ * terrain static; the small MCP is solved to machine precision. */
+typedef struct orc_macro_params {
+    double E_b;       /* bulk modulus [Pa] */
+    double c_b;       /* bulk cohesion [Pa] */
+    double mu_ab;     /* friction at the equipment interface */
+    double mu_ac;     /* friction in the failure surface (tan phi_b) */
+    double cas_ab;    /* aggregate stiffness multiplier at the equipment */
+    double cas_ac;    /* aggregate stiffness multiplier at the terrain */
+} orc_macro_params;
+
+typedef struct orc_macro_out {
+    int32_t zone;             /* body index */
+    int32_t n_points[2];      /* reduced points of AB, AC */
+    int64_t n_cand[2];        /* candidates of AB, AC */
+    double area[2];           /* A_AB, A_AC */
+    double gamma[2];          /* regularisation of AB, AC (velocity per impulse) */
+    double p[8][3];           /* points: AB in 0..3, AC in 4..7 */
+    double n[8][3];           /* normals, from B or C into A */
+    int64_t src[8];           /* particle index each point comes from */
+    double lam[8][4];         /* impulses on A: normal, tangential xyz */
+    double M, x[3], v0[3], w0[3];  /* the aggregate before the step */
+    double v[3], w[3];        /* its velocity after the step */
+    double force_b[3];        /* mean force of A on B (impulse / dt) */
+    double torque_b[3];       /* its torque about B's position */
+    int32_t sweeps;
+} orc_macro_out;
+
+/* Reduction of an interface's candidate points (n of them, 3 doubles each)
+ * with plane normal nrm to at most four: the candidates extreme along +e1,
+ * -e1, +e2, -e2 (e1 the normalised projection of the world axis least aligned
+ * with nrm, e2 = nrm x e1), ties to the smaller index, a candidate chosen
+ * twice kept once.  Writes the indices; returns their count. */
+int32_t orc_reduce4(int64_t n, const double* pts, const double nrm[3], int64_t idx[4]);
+
+/* One macroscale step of every zone (bodies with at least two half-spaces)
+ * for the state (x, v, w) and the bodies' poses and velocities.  Writes one
+ * orc_macro_out per zone; returns their count. */
+int32_t orc_macro_step(const orc_params* P, int64_t n, const double* r, const double* rho,
+                       const double* x, const double* v, const double* w,
+                       int32_t nb, const orc_body* bodies, int32_t ns, const orc_shape* shapes,
+                       const orc_macro_params* mp, int32_t cap, orc_macro_out* out);
+
 /* Contact detection only.  Writes the canonical (sorted) keys and the overlap
  * of each contact.  Key of a pair (lower id a, higher id b) is a<<32 | b; key of
  * a boundary contact with shape s is id<<32 | 0x80000000 | s.

@@ -123,6 +123,19 @@ class Aggregate(C.Structure):
                 ("w", C.c_double * 3), ("L", C.c_double * 3)]
 
 
+class MacroParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("E_b", "c_b", "mu_ab", "mu_ac", "cas_ab", "cas_ac")]
+
+
+class MacroOut(C.Structure):
+    _fields_ = [("zone", C.c_int32), ("n_points", C.c_int32 * 2), ("n_cand", C.c_int64 * 2),
+                ("area", C.c_double * 2), ("gamma", C.c_double * 2), ("p", (C.c_double * 3) * 8),
+                ("n", (C.c_double * 3) * 8), ("src", C.c_int64 * 8), ("lam", (C.c_double * 4) * 8),
+                ("M", C.c_double), ("x", C.c_double * 3), ("v0", C.c_double * 3), ("w0", C.c_double * 3),
+                ("v", C.c_double * 3), ("w", C.c_double * 3), ("force_b", C.c_double * 3),
+                ("torque_b", C.c_double * 3), ("sweeps", C.c_int32)]
+
+
 _lib = None
 
 
@@ -183,6 +196,12 @@ def lib():
         L.orc_convert_deposit.restype = C.c_double
         L.orc_convert_deposit.argtypes = [C.POINTER(VoxelGrid), C.c_double, C.c_double, C.c_int32, C.POINTER(Wedge),
                                           dp, dp, dp, dp]
+        L.orc_reduce4.restype = C.c_int32
+        L.orc_reduce4.argtypes = [C.c_int64, dp, dp, C.POINTER(C.c_int64)]
+        L.orc_macro_step.restype = C.c_int32
+        L.orc_macro_step.argtypes = [C.POINTER(Params), C.c_int64, dp, dp, dp, dp, dp, C.c_int32, C.POINTER(Body),
+                                     C.c_int32, C.POINTER(Shape), C.POINTER(MacroParams), C.c_int32,
+                                     C.POINTER(MacroOut)]
         L.orc_failure_angle.restype = C.c_double
         L.orc_failure_angle.argtypes = [C.c_double, C.c_double]
         _lib = L
@@ -608,3 +627,46 @@ def settle_particles(x, v, m, mf, wedges, origin, l0, dims, v_rest):
         raise ValueError("bad grid or v_rest")
     return f.reshape(np.shape(mf)), gone.astype(bool), tot
 
+
+
+def reduce4(points, normal):
+    """Indices of at most four of the points extreme along +-e1, +-e2 of the plane with this normal."""
+    pts = _c64(points).reshape(-1, 3)
+    nrm = _c64(normal)
+    idx = (C.c_int64 * 4)()
+    m = lib().orc_reduce4(len(pts), _dp(pts), _dp(nrm), idx)
+    return [int(idx[k]) for k in range(m)]
+
+
+MACRO_DEFAULTS = dict(E_b=1e7, c_b=0.0, mu_ab=0.4, mu_ac=0.7, cas_ab=1.0, cas_ac=0.001)
+
+
+def macro_step(spec: dict, x, v, w, bodies=None, **params):
+    """The oracle's macroscale step of every zone of spec's bodies for the
+    particle state (x, v, w): a list of dicts (zone, points, normals, impulses,
+    the aggregate's velocity after the step, the force on its body)."""
+    L = lib()
+    P = make_params(spec)
+    x = _c64(x).reshape(-1, 3); v = _c64(v).reshape(-1, 3); w = _c64(w).reshape(-1, 3)
+    r = _c64(spec["r"])
+    rho = None if spec.get("rho") is None else _c64(spec["rho"])
+    bb = _Bodies(bodies if bodies is not None else spec.get("bodies", []))
+    mp = MacroParams()
+    prm = dict(MACRO_DEFAULTS)
+    prm.update(params)
+    for k, val in prm.items():
+        setattr(mp, k, val)
+    out = (MacroOut * max(bb.nb, 1))()
+    m = L.orc_macro_step(C.byref(P), len(x), _dp(r), _dp(rho) if rho is not None else C.POINTER(C.c_double)(),
+                         _dp(x), _dp(v), _dp(w), bb.nb, bb.bodies, bb.ns, bb.shapes, C.byref(mp), bb.nb, out)
+    res = []
+    for o in out[:m]:
+        np_ = (o.n_points[0], o.n_points[1])
+        sel = list(range(np_[0])) + [4 + j for j in range(np_[1])]
+        res.append(dict(zone=o.zone, n_points=np_, n_cand=(o.n_cand[0], o.n_cand[1]), area=(o.area[0], o.area[1]),
+                        gamma=(o.gamma[0], o.gamma[1]), p=np.array([o.p[k][:] for k in sel]),
+                        n=np.array([o.n[k][:] for k in sel]), src=[o.src[k] for k in sel],
+                        lam=np.array([o.lam[k][:] for k in sel]), M=o.M, x=np.array(o.x[:]), v0=np.array(o.v0[:]),
+                        w0=np.array(o.w0[:]), v=np.array(o.v[:]), w=np.array(o.w[:]),
+                        force_b=np.array(o.force_b[:]), torque_b=np.array(o.torque_b[:]), sweeps=o.sweeps))
+    return res
