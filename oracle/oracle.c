@@ -6,7 +6,7 @@
  * names the passage of Servin, Berglund & Nystedt (arXiv 2011.00459) it
  * follows, and the readings taken where the paper is silent or garbled.
  *
- * Conventions (readings, each listed with its reason in the design notes):
+ * Conventions (readings taken where the paper is silent, ambiguous or garbled):
  *  - Contact normal n points from body 1 to body 2.  A pair is ordered by id
  *    (body 1 = lower id); for a boundary contact body 1 is the kinematic shape
  *    and body 2 the particle.
@@ -25,7 +25,7 @@
  *    lambda_n >= -c_p pi min(r1,r2)^2 dt.
  *  - Friction disk ||lambda_t|| <= mu |lambda_n| (Eq. signCoul2 literally).
  *  - Contact point at the middle of the overlap: lever arms l_i = r_i - delta/2.
- *  - tau_n = 2 dt for every contact; no impact stage (restitution 0).
+ *  - tau_n = 2 dt for every contact; the impact stage runs only when v_imp > 0.
  */
 #include "oracle.h"
 
@@ -2053,7 +2053,7 @@ int32_t orc_macro_step(const orc_params* P, int64_t n, const double* r, const do
             int64_t idx[4];
             int32_t m = orc_reduce4(nc, cand, nI, idx);
             o->n_points[q] = m;
-            o->gamma[q] = area > 0.0 ? L / ((q == 0 ? mp->cas_ab : mp->cas_ac) * mp->E_b * area * dt) : 0.0;
+            o->gamma[q] = area > 0.0 ? L / ((q == 0 ? mp->cas_ab : mp->cas_ac) * mp->E_b * area * dt * dt) : 0.0;
             for (int j = 0; j < m; ++j) {
                 for (int k = 0; k < 3; ++k) { o->p[4 * q + j][k] = cand[3 * idx[j] + k]; o->n[4 * q + j][k] = nI[k]; }
                 o->src[4 * q + j] = csrc[idx[j]];

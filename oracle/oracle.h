@@ -256,14 +256,17 @@ typedef struct orc_aggregate {
  * mdb:eqAgg under the frictional-cohesive velocity constraints of Eqs.
  * aggregateNormal and aggregateTangent at its interfaces to the equipment B
  * (AB) and to the terrain's failure surface C (AC), each interface reduced to
- * four contact points.  Readings (R44-R46 of the design notes): the zone's
+ * four contact points.  Readings where the paper is silent: the zone's
  * half-spaces follow the wedge convention (plane 0 the separation plate,
  * plane 1 the failure plane); AB candidates are the zone's particles touching
  * the zone body's shapes, AC candidates the zone's particles within their
  * radius of the failure plane (projected onto it); each interface keeps its
  * candidates extreme along +-e1 and +-e2 of its plane; A is the sum of the
- * candidates' cross sections; gamma = L / (c_as E_b A dt) with L the cube
- * root of the aggregate's solid volume; the equipment is kinematic and the
+ * candidates' cross sections; gamma = L / (c_as E_b A dt^2), the compliance
+ * of the bulk as a spring c_as E_b A / L regularising a velocity row over one
+ * step, with L the cube root of the aggregate's solid volume (the printed
+ * gamma_n = dt / (c_as E_b) lacks the geometric factor that makes it a
+ * velocity per impulse); the equipment is kinematic and the
  * terrain static; the small MCP is solved to machine precision. */
 typedef struct orc_macro_params {
     double E_b;       /* bulk modulus [Pa] */

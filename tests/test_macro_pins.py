@@ -99,11 +99,11 @@ def test_resting_aggregate_closed_form():
                                atol=1e-15)
     np.testing.assert_allclose(o["n"], np.tile([0.0, 0.0, 1.0], (4, 1)))
     # interface area (cross sections of the candidates) and the regularisation
-    # L / (c_as E_b A dt) with L the cube root of the solid volume
+    # L / (c_as E_b A dt^2) with L the cube root of the solid volume
     A = 9 * math.pi * R * R
     L = (n * 4.0 / 3.0 * math.pi * R ** 3) ** (1.0 / 3.0)
     assert o["area"][1] == pytest.approx(A, rel=1e-12)
-    gam = L / (0.001 * 1e7 * A * DT)
+    gam = L / (0.001 * 1e7 * A * DT * DT)
     assert o["gamma"][1] == pytest.approx(gam, rel=1e-12)
     # four equal normal impulses: gamma lam + v_z = 0 with M v_z = -dt M g + 4 lam
     lam = DT * M * G / (M * gam + 4.0)
