@@ -1974,7 +1974,8 @@ static double point_w(double invM, const double Iinv[3][3], const double rr[3], 
 int32_t orc_macro_step(const orc_params* P, int64_t n, const double* r, const double* rho,
                        const double* x, const double* v, const double* w,
                        int32_t nb, const orc_body* bodies, int32_t ns, const orc_shape* shapes,
-                       const orc_macro_params* mp, int32_t cap, orc_macro_out* out)
+                       const orc_macro_params* mp, int32_t neq, const orc_macro_equipment* eq,
+                       int32_t cap, orc_macro_out* out)
 {
     const double dt = P->dt;
     double* inv_m = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
@@ -2064,30 +2065,64 @@ int32_t orc_macro_step(const orc_params* P, int64_t n, const double* r, const do
          * gamma lambda_n + n.u >= 0 with lambda_n >= -c_b A dt / points, its
          * tangential rows gamma lambda_t + u_t = 0 on the disk
          * |lambda_t| <= mu |lambda_n|, u the velocity of A at the point minus
-         * that of B (or 0 on the terrain).  Projected Gauss-Seidel, normal then
-         * tangential rows of each point in turn, until no impulse changes. */
-        double vv[3], ww[3];
+         * that of B (or 0 on the terrain).  With the equipment dynamic (Eq.
+         * mdb:eqEq) B is a second body: M_B (v_B+ - v_B) = dt M_B g -
+         * sum_AB G^T lambda + lambda_d, I_B (w_B+ - w_B) = -sum_AB (p - x_B) x
+         * (G^T lambda) + tau_d, with the drive's rows gamma_d lambda_d +
+         * (v_B - v_target) = 0 per world axis (linear, then angular),
+         * |lambda_d| <= f_max dt (t_max dt).  Projected Gauss-Seidel, normal
+         * then tangential rows of each point in turn (AB, then AC), then the
+         * drive rows, until no impulse changes. */
+        const orc_macro_equipment* E = NULL;
+        for (int32_t k = 0; k < neq; ++k)
+            if (eq[k].body == b) E = &eq[k];
+        double vv[3], ww[3], vB[3], wB[3], IBinv[3][3], invMB = 0.0, ld[6] = {0, 0, 0, 0, 0, 0};
         for (int k = 0; k < 3; ++k) { vv[k] = A->v[k] + dt * P->g[k]; ww[k] = A->w[k]; }
+        memset(IBinv, 0, sizeof(IBinv));
+        if (E) {
+            invMB = 1.0 / E->mass;
+            double Rm[3][3], Iw[3][3];
+            quat_matrix(B->quat, Rm);
+            const double* J6 = E->inertia;
+            double Ib[3][3] = {{J6[0], J6[3], J6[4]}, {J6[3], J6[1], J6[5]}, {J6[4], J6[5], J6[2]}};
+            for (int p = 0; p < 3; ++p)          /* world inertia R I R^T */
+                for (int q = 0; q < 3; ++q) {
+                    double acc = 0.0;
+                    for (int k = 0; k < 3; ++k)
+                        for (int l = 0; l < 3; ++l) acc += Rm[p][k] * Ib[k][l] * Rm[q][l];
+                    Iw[p][q] = acc;
+                }
+            inv3(Iw, IBinv);
+            for (int k = 0; k < 3; ++k) { vB[k] = B->linvel[k] + dt * P->g[k]; wB[k] = B->angvel[k]; }
+        } else {
+            for (int k = 0; k < 3; ++k) { vB[k] = B->linvel[k]; wB[k] = B->angvel[k]; }
+        }
         int np = 0;
         int map[8];
         for (int q = 0; q < 2; ++q)
             for (int j = 0; j < o->n_points[q]; ++j) map[np++] = 4 * q + j;
-        double rr[8][3], uo[8][3], Wn[8], Wt[8], lo[8], mu[8], gam[8], t1[8][3], t2[8][3];
+        double rr[8][3], rb[8][3], uo[8][3], Wn[8], Wt[8], lo[8], mu[8], gam[8], t1[8][3], t2[8][3];
+        int onB[8];
         for (int c = 0; c < np; ++c) {
             int k8 = map[c], q = k8 / 4;
-            for (int k = 0; k < 3; ++k) rr[c][k] = o->p[k8][k] - A->x[k];
-            if (q == 0) {
-                double arm[3] = {o->p[k8][0] - B->pos[0], o->p[k8][1] - B->pos[1], o->p[k8][2] - B->pos[2]}, t[3];
-                cross3(B->angvel, arm, t);
+            onB[c] = q == 0 && E != NULL;
+            for (int k = 0; k < 3; ++k) { rr[c][k] = o->p[k8][k] - A->x[k]; rb[c][k] = o->p[k8][k] - B->pos[k]; }
+            for (int k = 0; k < 3; ++k) uo[c][k] = 0.0;
+            if (q == 0 && !E) {
+                double t[3];
+                cross3(B->angvel, rb[c], t);
                 for (int k = 0; k < 3; ++k) uo[c][k] = B->linvel[k] + t[k];
-            } else {
-                for (int k = 0; k < 3; ++k) uo[c][k] = 0.0;
             }
             plane_axes(o->n[k8], t1[c], t2[c]);
             Wn[c] = point_w(invM, Iinv, rr[c], o->n[k8], o->n[k8]);
             /* one scalar for both tangential rows (the disk's fixed point does
              * not depend on it): their mean effective inverse mass */
             Wt[c] = 0.5 * (point_w(invM, Iinv, rr[c], t1[c], t1[c]) + point_w(invM, Iinv, rr[c], t2[c], t2[c]));
+            if (onB[c]) {
+                Wn[c] += point_w(invMB, (const double(*)[3])IBinv, rb[c], o->n[k8], o->n[k8]);
+                Wt[c] += 0.5 * (point_w(invMB, (const double(*)[3])IBinv, rb[c], t1[c], t1[c]) +
+                                point_w(invMB, (const double(*)[3])IBinv, rb[c], t2[c], t2[c]));
+            }
             lo[c] = -mp->c_b * o->area[q] * dt / (double)o->n_points[q];
             mu[c] = q == 0 ? mp->mu_ab : mp->mu_ac;
             gam[c] = o->gamma[q];
@@ -2103,6 +2138,10 @@ int32_t orc_macro_step(const orc_params* P, int64_t n, const double* r, const do
                     double u[3], t[3];
                     cross3(ww, rr[c], t);
                     for (int k = 0; k < 3; ++k) u[k] = vv[k] + t[k] - uo[c][k];
+                    if (onB[c]) {
+                        cross3(wB, rb[c], t);
+                        for (int k = 0; k < 3; ++k) u[k] -= vB[k] + t[k];
+                    }
                     double J[3];
                     if (row == 0) {
                         double un = dot3(nn, u);
@@ -2137,21 +2176,47 @@ int32_t orc_macro_step(const orc_params* P, int64_t n, const double* r, const do
                     cross3(rr[c], J, tj);
                     mat3_vec(Iinv, tj, dw);
                     for (int k = 0; k < 3; ++k) { vv[k] += invM * J[k]; ww[k] += dw[k]; }
+                    if (onB[c]) {
+                        cross3(rb[c], J, tj);
+                        mat3_vec((const double(*)[3])IBinv, tj, dw);
+                        for (int k = 0; k < 3; ++k) { vB[k] -= invMB * J[k]; wB[k] -= dw[k]; }
+                    }
                 }
                 for (int k = 0; k < 4; ++k) if (fabs(lam[c][k]) > lmax) lmax = fabs(lam[c][k]);
+            }
+            if (E) {
+                for (int k = 0; k < 6; ++k) {
+                    const int ax = k % 3;
+                    const double u = k < 3 ? vB[ax] - E->v_target[ax] : wB[ax] - E->w_target[ax];
+                    const double W = k < 3 ? invMB : IBinv[ax][ax];
+                    const double lim = (k < 3 ? E->f_max : E->t_max) * dt;
+                    double l = ld[k] - (u + E->gamma_drive * ld[k]) / (W + E->gamma_drive);
+                    if (l > lim) l = lim;
+                    if (l < -lim) l = -lim;
+                    const double d = l - ld[k];
+                    ld[k] = l;
+                    if (k < 3) vB[ax] += invMB * d;
+                    else for (int j = 0; j < 3; ++j) wB[j] += IBinv[j][ax] * d;
+                    if (fabs(d) > dmax) dmax = fabs(d);
+                    if (fabs(l) > lmax) lmax = fabs(l);
+                }
             }
             if (dmax <= 1e-15 * lmax || lmax == 0.0) { ++sweep; break; }
         }
         o->sweeps = sweep;
-        for (int k = 0; k < 3; ++k) { o->v[k] = vv[k]; o->w[k] = ww[k]; o->force_b[k] = 0.0; o->torque_b[k] = 0.0; }
+        for (int k = 0; k < 3; ++k) {
+            o->v[k] = vv[k]; o->w[k] = ww[k]; o->force_b[k] = 0.0; o->torque_b[k] = 0.0;
+            o->v_b[k] = vB[k]; o->w_b[k] = wB[k];
+        }
+        for (int k = 0; k < 6; ++k) o->lam_drive[k] = ld[k];
         for (int c = 0; c < np; ++c) {
             int k8 = map[c];
             for (int k = 0; k < 4; ++k) o->lam[k8][k] = lam[c][k];
             if (k8 >= 4) continue;
-            double J[3], arm[3], t[3];
+            double J[3], t[3];
             for (int k = 0; k < 3; ++k) J[k] = lam[c][0] * o->n[k8][k] + lam[c][1 + k];
-            for (int k = 0; k < 3; ++k) { o->force_b[k] -= J[k] / dt; arm[k] = o->p[k8][k] - B->pos[k]; }
-            cross3(arm, J, t);
+            for (int k = 0; k < 3; ++k) o->force_b[k] -= J[k] / dt;
+            cross3(rb[c], J, t);
             for (int k = 0; k < 3; ++k) o->torque_b[k] -= t[k] / dt;
         }
     }

@@ -277,6 +277,20 @@ typedef struct orc_macro_params {
     double cas_ac;    /* aggregate stiffness multiplier at the terrain */
 } orc_macro_params;
 
+/* A dynamic equipment body in the macroscale step (Eq. mdb:eqEq): its mass,
+ * its inertia in the body frame, and the drive that holds and actuates it,
+ * a velocity target per world axis reached through rows of compliance
+ * gamma_drive with force (torque) limits f_max (t_max).  Bodies not named
+ * here are kinematic. */
+typedef struct orc_macro_equipment {
+    int32_t body;             /* body index */
+    double mass;
+    double inertia[6];        /* body frame: xx, yy, zz, xy, xz, yz */
+    double v_target[3], w_target[3];
+    double f_max, t_max;      /* [N], [N m] per world axis */
+    double gamma_drive;       /* velocity per impulse, > 0 */
+} orc_macro_equipment;
+
 typedef struct orc_macro_out {
     int32_t zone;             /* body index */
     int32_t n_points[2];      /* reduced points of AB, AC */
@@ -292,6 +306,8 @@ typedef struct orc_macro_out {
     double force_b[3];        /* mean force of A on B (impulse / dt) */
     double torque_b[3];       /* its torque about B's position */
     int32_t sweeps;
+    double v_b[3], w_b[3];    /* the equipment's velocity after the step (its own when kinematic) */
+    double lam_drive[6];      /* drive impulses on B: linear xyz, angular xyz (0 when kinematic) */
 } orc_macro_out;
 
 /* Reduction of an interface's candidate points (n of them, 3 doubles each)
@@ -302,12 +318,14 @@ typedef struct orc_macro_out {
 int32_t orc_reduce4(int64_t n, const double* pts, const double nrm[3], int64_t idx[4]);
 
 /* One macroscale step of every zone (bodies with at least two half-spaces)
- * for the state (x, v, w) and the bodies' poses and velocities.  Writes one
- * orc_macro_out per zone; returns their count. */
+ * for the state (x, v, w) and the bodies' poses and velocities; the bodies
+ * named in eq (neq of them, may be NULL when neq = 0) are dynamic, the others
+ * kinematic.  Writes one orc_macro_out per zone; returns their count. */
 int32_t orc_macro_step(const orc_params* P, int64_t n, const double* r, const double* rho,
                        const double* x, const double* v, const double* w,
                        int32_t nb, const orc_body* bodies, int32_t ns, const orc_shape* shapes,
-                       const orc_macro_params* mp, int32_t cap, orc_macro_out* out);
+                       const orc_macro_params* mp, int32_t neq, const orc_macro_equipment* eq,
+                       int32_t cap, orc_macro_out* out);
 
 /* Contact detection only.  Writes the canonical (sorted) keys and the overlap
  * of each contact.  Key of a pair (lower id a, higher id b) is a<<32 | b; key of

@@ -127,13 +127,20 @@ class MacroParams(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("E_b", "c_b", "mu_ab", "mu_ac", "cas_ab", "cas_ac")]
 
 
+class MacroEquipment(C.Structure):
+    _fields_ = [("body", C.c_int32), ("mass", C.c_double), ("inertia", C.c_double * 6),
+                ("v_target", C.c_double * 3), ("w_target", C.c_double * 3), ("f_max", C.c_double),
+                ("t_max", C.c_double), ("gamma_drive", C.c_double)]
+
+
 class MacroOut(C.Structure):
     _fields_ = [("zone", C.c_int32), ("n_points", C.c_int32 * 2), ("n_cand", C.c_int64 * 2),
                 ("area", C.c_double * 2), ("gamma", C.c_double * 2), ("p", (C.c_double * 3) * 8),
                 ("n", (C.c_double * 3) * 8), ("src", C.c_int64 * 8), ("lam", (C.c_double * 4) * 8),
                 ("M", C.c_double), ("x", C.c_double * 3), ("v0", C.c_double * 3), ("w0", C.c_double * 3),
                 ("v", C.c_double * 3), ("w", C.c_double * 3), ("force_b", C.c_double * 3),
-                ("torque_b", C.c_double * 3), ("sweeps", C.c_int32)]
+                ("torque_b", C.c_double * 3), ("sweeps", C.c_int32), ("v_b", C.c_double * 3),
+                ("w_b", C.c_double * 3), ("lam_drive", C.c_double * 6)]
 
 
 _lib = None
@@ -201,7 +208,7 @@ def lib():
         L.orc_macro_step.restype = C.c_int32
         L.orc_macro_step.argtypes = [C.POINTER(Params), C.c_int64, dp, dp, dp, dp, dp, C.c_int32, C.POINTER(Body),
                                      C.c_int32, C.POINTER(Shape), C.POINTER(MacroParams), C.c_int32,
-                                     C.POINTER(MacroOut)]
+                                     C.POINTER(MacroEquipment), C.c_int32, C.POINTER(MacroOut)]
         L.orc_failure_angle.restype = C.c_double
         L.orc_failure_angle.argtypes = [C.c_double, C.c_double]
         _lib = L
@@ -641,10 +648,13 @@ def reduce4(points, normal):
 MACRO_DEFAULTS = dict(E_b=1e7, c_b=0.0, mu_ab=0.4, mu_ac=0.7, cas_ab=1.0, cas_ac=0.001)
 
 
-def macro_step(spec: dict, x, v, w, bodies=None, **params):
+def macro_step(spec: dict, x, v, w, bodies=None, equipment=None, **params):
     """The oracle's macroscale step of every zone of spec's bodies for the
     particle state (x, v, w): a list of dicts (zone, points, normals, impulses,
-    the aggregate's velocity after the step, the force on its body)."""
+    the aggregate's velocity after the step, the force on its body).
+    equipment: dicts (body index, mass, inertia (xx, yy, zz, xy, xz, yz, body
+    frame), v_target, w_target, f_max, t_max, gamma_drive) of the bodies that
+    are dynamic; the others are kinematic."""
     L = lib()
     P = make_params(spec)
     x = _c64(x).reshape(-1, 3); v = _c64(v).reshape(-1, 3); w = _c64(w).reshape(-1, 3)
@@ -656,9 +666,23 @@ def macro_step(spec: dict, x, v, w, bodies=None, **params):
     prm.update(params)
     for k, val in prm.items():
         setattr(mp, k, val)
+    eqs = list(equipment or [])
+    eq = (MacroEquipment * max(len(eqs), 1))()
+    for k, e in enumerate(eqs):
+        eq[k].body = int(e["body"])
+        eq[k].mass = e["mass"]
+        for j in range(6):
+            eq[k].inertia[j] = e["inertia"][j]
+        for j in range(3):
+            eq[k].v_target[j] = e.get("v_target", (0.0, 0.0, 0.0))[j]
+            eq[k].w_target[j] = e.get("w_target", (0.0, 0.0, 0.0))[j]
+        eq[k].f_max = e.get("f_max", 0.0)
+        eq[k].t_max = e.get("t_max", 0.0)
+        eq[k].gamma_drive = e.get("gamma_drive", 1e-6)
     out = (MacroOut * max(bb.nb, 1))()
     m = L.orc_macro_step(C.byref(P), len(x), _dp(r), _dp(rho) if rho is not None else C.POINTER(C.c_double)(),
-                         _dp(x), _dp(v), _dp(w), bb.nb, bb.bodies, bb.ns, bb.shapes, C.byref(mp), bb.nb, out)
+                         _dp(x), _dp(v), _dp(w), bb.nb, bb.bodies, bb.ns, bb.shapes, C.byref(mp), len(eqs), eq,
+                         bb.nb, out)
     res = []
     for o in out[:m]:
         np_ = (o.n_points[0], o.n_points[1])
@@ -668,5 +692,6 @@ def macro_step(spec: dict, x, v, w, bodies=None, **params):
                         n=np.array([o.n[k][:] for k in sel]), src=[o.src[k] for k in sel],
                         lam=np.array([o.lam[k][:] for k in sel]), M=o.M, x=np.array(o.x[:]), v0=np.array(o.v0[:]),
                         w0=np.array(o.w0[:]), v=np.array(o.v[:]), w=np.array(o.w[:]),
-                        force_b=np.array(o.force_b[:]), torque_b=np.array(o.torque_b[:]), sweeps=o.sweeps))
+                        force_b=np.array(o.force_b[:]), torque_b=np.array(o.torque_b[:]), sweeps=o.sweeps,
+                        v_b=np.array(o.v_b[:]), w_b=np.array(o.w_b[:]), lam_drive=np.array(o.lam_drive[:])))
     return res

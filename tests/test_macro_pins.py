@@ -237,3 +237,136 @@ def test_mirror_symmetry():
     b = O.macro_step(spec, x * m, v * m, np.zeros((n, 3)))[0]
     np.testing.assert_allclose(b["v"], a["v"] * m, rtol=1e-9, atol=1e-13)
     np.testing.assert_allclose(b["force_b"], a["force_b"] * m, rtol=1e-9, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# a dynamic equipment body (Eq. mdb:eqEq): mass, inertia and a drive
+# ---------------------------------------------------------------------------
+def plate_on_top(zb, half=0.4):
+    """A horizontal plate whose bottom face (body z = -0.05) is the zone's
+    separation plate, and whose zone reaches down to the level failure plane
+    z = 0 (world); the plate is body 0 at height zb."""
+    zone = [[0.0, 0.0, 1.0, -0.05],            # separation plate: below the plate's bottom face
+            [0.0, 0.0, -1.0, zb],              # failure plane: world z >= 0
+            [1.0, 0.0, 0.0, half], [-1.0, 0.0, 0.0, half], [0.0, 1.0, 0.0, half], [0.0, -1.0, 0.0, half]]
+    return dict(pos=(0.0, 0.0, zb), quat=(1.0, 0.0, 0.0, 0.0), linvel=(0.0, 0.0, 0.0), angvel=(0.0, 0.0, 0.0),
+                shapes=[dict(type="box", half=(half, half, 0.05), off=(0.0, 0.0, 0.0))], zone_planes=zone)
+
+
+def box_inertia(m, a, b, c):
+    return (m * (b * b + c * c) / 12.0, m * (a * a + c * c) / 12.0, m * (a * a + b * b) / 12.0, 0.0, 0.0, 0.0)
+
+
+def stack(gap=0.004):
+    """Two crosses of spheres: the bottom one within R of z = 0 (AC), the top
+    one overlapping the plate's bottom face by `gap` (AB)."""
+    z0 = 0.9 * R
+    z1 = z0 + 3 * R
+    x = np.asarray(cross_layout(0.0, 0.0, z0) + cross_layout(0.0, 0.0, z1))
+    zb = z1 + R - gap + 0.05
+    return x, zb
+
+
+def test_drive_closed_forms_with_no_contact():
+    # the plate far above a resting aggregate: its drive alone sets its motion
+    x = resting_aggregate(cx=0.0, cy=0.0)
+    n = len(x)
+    mB, gd = 40.0, 1e-3
+    plate = dict(plate_on_top(2.0), linvel=(0.3, -0.2, 0.1), angvel=(0.5, 0.0, -0.4))
+    I = box_inertia(mB, 0.8, 0.8, 0.1)
+    vt, wt = (1.0, 0.0, -0.5), (0.0, 2.0, 0.0)
+    eq_free = dict(body=0, mass=mB, inertia=I, v_target=vt, w_target=wt, f_max=1e9, t_max=1e9, gamma_drive=gd)
+    spec = spec_of(x, [plate])
+    o = O.macro_step(spec, x, np.zeros((n, 3)), np.zeros((n, 3)), equipment=[eq_free])[0]
+    v0 = np.array(plate["linvel"]) + DT * np.array([0.0, 0.0, -G])
+    np.testing.assert_allclose(o["v_b"], (mB * v0 + np.array(vt) / gd) / (mB + 1.0 / gd), rtol=1e-12, atol=1e-15)
+    Id = np.array(I[:3])
+    np.testing.assert_allclose(o["w_b"], (Id * np.array(plate["angvel"]) + np.array(wt) / gd) / (Id + 1.0 / gd),
+                               rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(o["lam_drive"][:3], mB * (o["v_b"] - v0), rtol=1e-12, atol=1e-15)
+    # force-limited: each axis pushes at its limit toward the target
+    fm, tm = 5.0, 0.01
+    eq_lim = dict(eq_free, f_max=fm, t_max=tm)
+    o2 = O.macro_step(spec, x, np.zeros((n, 3)), np.zeros((n, 3)), equipment=[eq_lim])[0]
+    dirv = np.sign(np.array(vt) - v0)
+    np.testing.assert_allclose(o2["v_b"], v0 + dirv * fm * DT / mB, rtol=1e-12)
+    dirw = np.sign(np.array(wt) - np.array(plate["angvel"]))
+    np.testing.assert_allclose(o2["w_b"], np.array(plate["angvel"]) + dirw * tm * DT / Id, rtol=1e-12)
+    # the aggregate, touching only the terrain, is as with a kinematic plate
+    ok = O.macro_step(spec, x, np.zeros((n, 3)), np.zeros((n, 3)))[0]
+    np.testing.assert_allclose(o["v"], ok["v"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(o["lam"], ok["lam"], rtol=1e-12, atol=1e-15)
+
+
+def test_free_plate_dropped_on_a_resting_aggregate():
+    # drive off (zero limits): four equal AB impulses l1 between the plate and
+    # the aggregate, four equal AC impulses l2 below it, from rest:
+    #   M_A v_A = -M_A g dt - 4 l1 + 4 l2,   M_B v_B = -M_B g dt + 4 l1,
+    #   gamma_AB l1 = v_A - v_B,             gamma_AC l2 = -v_A
+    x, zb = stack()
+    n = len(x)
+    mB = 60.0
+    eq = dict(body=0, mass=mB, inertia=box_inertia(mB, 0.8, 0.8, 0.1), f_max=0.0, t_max=0.0, gamma_drive=1e-3)
+    spec = spec_of(x, [plate_on_top(zb)])
+    o = O.macro_step(spec, x, np.zeros((n, 3)), np.zeros((n, 3)), equipment=[eq], c_b=0.0)[0]
+    assert o["n_points"] == (4, 4)
+    np.testing.assert_allclose(o["n"][:4], np.tile([0.0, 0.0, -1.0], (4, 1)))
+    np.testing.assert_allclose(o["n"][4:], np.tile([0.0, 0.0, 1.0], (4, 1)))
+    MA = n * sphere_mass()
+    g1, g2 = o["gamma"]
+    # unknowns (v_A, v_B, l1, l2)
+    A = np.array([[MA, 0.0, 4.0, -4.0],
+                  [0.0, mB, -4.0, 0.0],
+                  [1.0, -1.0, -g1, 0.0],
+                  [1.0, 0.0, 0.0, g2]])
+    rhs = np.array([-MA * G * DT, -mB * G * DT, 0.0, 0.0])
+    vA, vB, l1, l2 = np.linalg.solve(A, rhs)
+    assert l1 > 0.0 and l2 > 0.0
+    np.testing.assert_allclose(o["lam"][:4, 0], l1, rtol=1e-10)
+    np.testing.assert_allclose(o["lam"][4:, 0], l2, rtol=1e-10)
+    np.testing.assert_allclose(o["lam"][:, 1:], 0.0, atol=1e-12 * l2)
+    np.testing.assert_allclose(o["v"], [0.0, 0.0, vA], atol=1e-12)
+    np.testing.assert_allclose(o["v_b"], [0.0, 0.0, vB], atol=1e-12)
+    np.testing.assert_allclose(o["w_b"], 0.0, atol=1e-12)
+    np.testing.assert_allclose(o["lam_drive"], 0.0, atol=0.0)
+    # the force of the aggregate on the plate: 4 l1 up
+    np.testing.assert_allclose(o["force_b"], [0.0, 0.0, 4.0 * l1 / DT], rtol=1e-10, atol=1e-9)
+
+
+def test_dynamic_equipment_momentum_balance_and_heavy_limit():
+    # a rotated blade pushing a block, driven toward 0.6 m/s with a force
+    # limit: the AB impulses cancel between the two bodies, so the momentum
+    # change of A and B together is gravity plus the terrain's and the drive's
+    # impulses
+    rng = np.random.default_rng(21)
+    s = 2.2 * R
+    x = np.asarray([[R - 0.01 + ix * s, iy * s, 0.9 * R + iz * s]
+                    for ix in range(4) for iy in range(-2, 3) for iz in range(3)]) + rng.uniform(-0.003, 0.003, (60, 3))
+    n = len(x)
+    c, sn = math.cos(0.05), math.sin(0.05)
+    bl = dict(blade(linvel=(0.5, 0.0, 0.0)), quat=(c, 0.0, 0.0, sn), angvel=(0.0, 0.0, 0.2))
+    mB = 30.0
+    eq = dict(body=0, mass=mB, inertia=box_inertia(mB, 0.1, 2.0, 1.0), v_target=(0.6, 0.0, 0.0),
+              w_target=(0.0, 0.0, 0.0), f_max=400.0, t_max=50.0, gamma_drive=1e-4)
+    spec = spec_of(x, [bl])
+    v = np.tile([0.1, 0.0, -0.1], (n, 1))
+    o = O.macro_step(spec, x, v, np.zeros((n, 3)), equipment=[eq], mu_ab=0.3, mu_ac=0.6, c_b=500.0)[0]
+    assert min(o["n_points"]) >= 3 and o["sweeps"] < 200000
+    M = o["M"]
+    gdt = DT * np.array([0.0, 0.0, -G])
+    J = o["lam"][:, :1] * o["n"] + o["lam"][:, 1:]
+    J_ac = J[o["n_points"][0]:].sum(axis=0)
+    dp = M * (o["v"] - o["v0"] - gdt) + mB * (o["v_b"] - np.array(bl["linvel"]) - gdt)
+    np.testing.assert_allclose(dp, J_ac + o["lam_drive"][:3], rtol=1e-9, atol=1e-9 * np.abs(J).max())
+    assert np.all(np.abs(o["lam_drive"][:3]) <= 400.0 * DT * (1 + 1e-12))
+    # a very heavy equipment driven at its own velocity is the kinematic case
+    # (without gravity, so that the drive only has to hold the target)
+    flat = dict(spec_of(x, [bl]), gravity=(0.0, 0.0, 0.0))
+    heavy = dict(eq, mass=1e12, inertia=(1e12, 1e12, 1e12, 0.0, 0.0, 0.0), v_target=bl["linvel"],
+                 w_target=bl["angvel"], f_max=1e20, t_max=1e20, gamma_drive=1e-6)
+    oh = O.macro_step(flat, x, v, np.zeros((n, 3)), equipment=[heavy], mu_ab=0.3, mu_ac=0.6, c_b=500.0)[0]
+    ok = O.macro_step(flat, x, v, np.zeros((n, 3)), mu_ab=0.3, mu_ac=0.6, c_b=500.0)[0]
+    np.testing.assert_allclose(oh["v_b"], bl["linvel"], atol=1e-9)
+    np.testing.assert_allclose(oh["w_b"], bl["angvel"], atol=1e-9)
+    np.testing.assert_allclose(oh["v"], ok["v"], rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(oh["lam"], ok["lam"], rtol=0, atol=1e-8 * np.abs(ok["lam"]).max())
