@@ -99,8 +99,8 @@ typedef struct tr_scene_desc {
                                 (particles outside are clamped to the border cells) */
     double r_ref;            /* nominal radius (learned-start feature scale); <= 0 means 1 m */
     void* stream;            /* hipStream_t, or NULL */
-    tr_alloc_fn alloc_fn;    /* NULL: hipMalloc */
-    tr_free_fn free_fn;      /* NULL: hipFree */
+    tr_alloc_fn alloc_fn;    /* NULL: hipMalloc (alloc_fn and free_fn are given together or not at all) */
+    tr_free_fn free_fn;      /* NULL: hipFree; called once for every block alloc_fn returned, at latest by destroy_scene */
     void* alloc_ctx;
 } tr_scene_desc;
 
@@ -380,6 +380,83 @@ int get_contact_forces(tr_scene* s, int32_t env, int32_t body_id, double force[3
  * with a zone, in body order.  Writes min(cap, count) records and the count
  * to *n_out.  Synchronises. */
 int get_aggregates(tr_scene* s, int32_t env, int32_t cap, tr_aggregate* out, int32_t* n_out);
+
+/* Bulk properties of the aggregate body of the macroscale model (section
+ * "Macroscale model", Eqs. aggregateNormal and aggregateTangent). */
+typedef struct tr_macro_params {
+    double E_b;      /* bulk modulus [Pa], > 0 */
+    double c_b;      /* bulk cohesion [Pa], >= 0 */
+    double mu_ab;    /* friction at the equipment interface AB, >= 0 */
+    double mu_ac;    /* friction in the failure surface AC (tan phi_b), >= 0 */
+    double cas_ab;   /* aggregate stiffness multiplier c_as at AB, > 0 */
+    double cas_ac;   /* aggregate stiffness multiplier c_as at AC, > 0 */
+} tr_macro_params;
+
+/* An equipment body that moves under the macroscale step (Eq. mdb:eqEq)
+ * instead of being kinematic: its mass and body-frame inertia, and the drive
+ * that holds and actuates it, one row per world axis (linear, then angular)
+ * pulling its velocity toward the target with compliance gamma_drive and an
+ * impulse limit of f_max dt (t_max dt).  Gravity acts on it; the penetration
+ * resistance and its contacts with the terrain are not included. */
+typedef struct tr_macro_equipment {
+    int32_t body_id;         /* id of the body (tr_body_desc.id) */
+    int32_t pad;
+    double mass;             /* > 0 */
+    double inertia[6];       /* body frame: xx, yy, zz, xy, xz, yz (positive definite) */
+    double v_target[3];      /* drive target, world frame [m/s] */
+    double w_target[3];      /* [rad/s] */
+    double f_max;            /* drive force limit per axis [N], >= 0 */
+    double t_max;            /* drive torque limit per axis [N m], >= 0 */
+    double gamma_drive;      /* drive compliance (velocity per impulse), > 0 */
+} tr_macro_equipment;
+
+/* One zone's macroscale step.  Points and impulses of interface AB sit in
+ * entries 0..3, those of AC in 4..7; n_points[q] of each are used. */
+typedef struct tr_macro_result {
+    int32_t zone;            /* id of the body that owns the zone */
+    int32_t n_points[2];     /* reduced points of AB, AC (at most 4 each) */
+    int32_t sweeps;          /* iterations of the solve: Newton steps plus Gauss-Seidel sweeps */
+    int64_t n_cand[2];       /* candidate contacts of AB, AC */
+    double area[2];          /* A_AB, A_AC: sum of the candidates' pi r^2 */
+    double gamma[2];         /* regularisation of AB, AC (velocity per impulse) */
+    double p[8][3];          /* points */
+    double n[8][3];          /* normals, from B (or the terrain C) into A */
+    int64_t src[8];          /* env-local index (id - env's first id) of each point's particle */
+    double lam[8][4];        /* impulses on A: normal, tangential xyz */
+    double M, x[3], v0[3], w0[3];  /* the aggregate before the step */
+    double v[3], w[3];       /* its velocity after the step */
+    double force[3];         /* mean force of A on B (impulse / dt) */
+    double torque[3];        /* its torque about B's position */
+    double v_b[3], w_b[3];   /* B's velocity after the step (its own when kinematic) */
+    double lam_drive[6];     /* drive impulses on B: linear xyz, angular xyz (0 when kinematic) */
+} tr_macro_result;
+
+/* The macroscale step (section "Macroscale model") of every zone of env whose
+ * body has at least two half-spaces (half-space 0 the separation plate,
+ * half-space 1 the failure plane) and holds particles, for the current
+ * particle state and body poses: the zone's aggregate body (Eqs.
+ * aggregate_mass .. aggregate_rot_vel) advanced one step under Eq. mdb:eqAgg
+ * with the constraints of Eqs. aggregateNormal and aggregateTangent at its
+ * interface to the equipment (particles touching the body's shapes) and to
+ * the failure surface (particles within their radius of the failure plane),
+ * each interface reduced to the four candidates extreme along its in-plane
+ * axes.  The impulses are the fixed point of the interface rows' projected
+ * Gauss-Seidel (normal row, then the tangential disk, per point), found by a
+ * damped Newton iteration on the aggregate's six velocities with each point's
+ * impulse in closed form and finished by Gauss-Seidel sweeps until no impulse
+ * changes by more than 1e-15 of the largest.  The bodies named in eq[0 ..
+ * n_eq - 1] (eq may be NULL when n_eq = 0) move with the aggregate under Eq.
+ * mdb:eqEq (their AB rows act on both bodies, their drive rows follow the
+ * points); the other bodies are kinematic.  A particle belongs to the first body, in body order, whose
+ * half-spaces all contain it.  The particle state is not changed.  Writes
+ * min(cap, count) results in body order and the count to *n_out.  The scene
+ * allocates a small device table on the first call.  Synchronises.
+ * TR_E_INVAL for bad arguments or parameters (an equipment entry naming no
+ * body of env, twice the same body, a mass, inertia or compliance that is not
+ * positive, negative limits), TR_E_CAPACITY for more than 8 bodies with
+ * half-spaces in env, TR_E_NOMEM. */
+int macro_step(tr_scene* s, int32_t env, const tr_macro_params* mp, int32_t n_eq, const tr_macro_equipment* eq,
+               int32_t cap, tr_macro_result* out, int32_t* n_out);
 
 /* Message of the last error on this scene ("" when none); valid until the
  * next call on the scene. */

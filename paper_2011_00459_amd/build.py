@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libterrain.so")
-SOURCES = ["csrc/terrain_kernels.hip", "csrc/terrain_voxels.hip", "csrc/terrain_mlp.hip", "csrc/terrain_capi.hip"]
+SOURCES = ["csrc/terrain_kernels.hip", "csrc/terrain_voxels.hip", "csrc/terrain_mlp.hip", "csrc/terrain_macro.hip",
+           "csrc/terrain_capi.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

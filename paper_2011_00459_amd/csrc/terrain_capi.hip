@@ -54,6 +54,8 @@ struct tr_scene {
     std::vector<BodyDev> body_host;   // last uploaded body table (poses refreshed on download)
     std::vector<ShapeDev> shape_host; // last uploaded shape table
     WedgeDev* conv_wedges = nullptr;  // caller wedges of the conversion entry points (device)
+    MacroZone* macro_zone = nullptr;       // macroscale step: per-zone reductions (device)
+    tr_macro_result* macro_out = nullptr;  // and its results (device)
     double* conv_total = nullptr;     // one device double: the converted mass
     double* adv_bmax = nullptr;       // per-block Courant maxima of the advection
     int64_t adv_cap = 0;
@@ -571,6 +573,7 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
         !std::isfinite(d->material.v_imp))
         return TR_E_INVAL;
     if (d->warm_start < TR_WARM_COLD || d->warm_start > TR_WARM_LEARNED) return TR_E_INVAL;
+    if ((d->alloc_fn == nullptr) != (d->free_fn == nullptr)) return TR_E_INVAL;  // both or neither
     if ((int64_t)d->n_envs * d->cap_particles >= ((int64_t)1 << 31) ||
         (int64_t)d->n_envs * d->cap_contacts >= ((int64_t)1 << 31))
         return TR_E_CAPACITY;
@@ -1414,6 +1417,82 @@ int get_aggregates(tr_scene* s, int32_t env, int32_t cap, tr_aggregate* out, int
     HIP_CHECK(s, hipStreamSynchronize(s->stream));
     for (int k = 0; k < (int)zs.size() && k < cap; ++k)
         HIP_CHECK(s, hipMemcpy(&out[k], s->b.aggs + zs[k], sizeof(tr_aggregate), hipMemcpyDeviceToHost));
+    return TR_OK;
+}
+
+int macro_step(tr_scene* s, int32_t env, const tr_macro_params* mp, int32_t n_eq, const tr_macro_equipment* eq,
+               int32_t cap, tr_macro_result* out, int32_t* n_out)
+{
+    if (!s || !mp || !n_out || cap < 0 || (cap > 0 && !out) || n_eq < 0 || (n_eq > 0 && !eq)) return TR_E_INVAL;
+    s->err.clear();
+    *n_out = 0;
+    if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "macro_step: env");
+    const double pv[6] = {mp->E_b, mp->c_b, mp->mu_ab, mp->mu_ac, mp->cas_ab, mp->cas_ac};
+    if (!finite3(pv, 6) || !(mp->E_b > 0.0) || !(mp->cas_ab > 0.0) || !(mp->cas_ac > 0.0) || mp->c_b < 0.0 ||
+        mp->mu_ab < 0.0 || mp->mu_ac < 0.0)
+        return fail(s, TR_E_INVAL, "macro_step: parameters");
+    if (s->tables_dirty) {
+        int rc = rebuild_tables(s);
+        if (rc) return rc;
+    }
+    const EnvDev& E = s->env_host[env];
+    for (int32_t k = 0; k < n_eq; ++k) {
+        const tr_macro_equipment& q = eq[k];
+        bool found = false;
+        for (int g = E.body_begin; g < E.body_end; ++g) found |= s->body_host[g].user_id == q.body_id;
+        for (int32_t j = 0; j < k; ++j)
+            if (eq[j].body_id == q.body_id) return fail(s, TR_E_INVAL, "macro_step: equipment named twice");
+        const double* I = q.inertia;
+        const double vals[13] = {q.mass, I[0], I[1], I[2], I[3], I[4], I[5], q.f_max, q.t_max, q.gamma_drive,
+                                 q.v_target[0] + q.v_target[1] + q.v_target[2],
+                                 q.w_target[0] + q.w_target[1] + q.w_target[2], 0.0};
+        // positive definite inertia: leading principal minors > 0
+        const double m2 = I[0] * I[1] - I[3] * I[3];
+        const double m3 = I[0] * (I[1] * I[2] - I[5] * I[5]) - I[3] * (I[3] * I[2] - I[5] * I[4]) +
+                          I[4] * (I[3] * I[5] - I[1] * I[4]);
+        if (!found || !finite3(vals, 13) || !(q.mass > 0.0) || !(I[0] > 0.0) || !(m2 > 0.0) || !(m3 > 0.0) ||
+            !(q.gamma_drive > 0.0) || q.f_max < 0.0 || q.t_max < 0.0)
+            return fail(s, TR_E_INVAL, "macro_step: equipment entry");
+    }
+    MacroArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = (int)s->envs[env].n;
+    a.id_base = E.id_base;
+    a.shape_begin = E.shape_begin;
+    a.shape_end = E.shape_end;
+    a.mp = *mp;
+    for (int k = 0; k < 3; ++k) a.g[k] = s->desc.gravity[k];
+    for (int g = E.body_begin; g < E.body_end; ++g) {
+        const BodyDev& B = s->body_host[g];
+        if (B.nplanes <= 0) continue;
+        if (a.n_zones >= kMacroMaxZones) return fail(s, TR_E_CAPACITY, "macro_step: more than 8 bodies with half-spaces");
+        a.body[a.n_zones] = g;
+        a.eligible[a.n_zones] = B.nplanes >= 2;
+        for (int32_t k = 0; k < n_eq; ++k)
+            if (eq[k].body_id == B.user_id) {
+                a.has_eq[a.n_zones] = 1;
+                a.eq[a.n_zones] = eq[k];
+            }
+        ++a.n_zones;
+    }
+    if (a.n_zones == 0) return TR_OK;
+    if (!s->macro_zone) {
+        if (!alloc_n(s, s->macro_zone, kMacroMaxZones) || !alloc_n(s, s->macro_out, kMacroMaxZones))
+            return fail(s, TR_E_NOMEM, "macro_step: device table");
+    }
+    launch_macro(s->b, s->p, a, s->macro_zone, s->macro_out, s->stream);
+    HIP_CHECK(s, hipGetLastError());
+    std::vector<tr_macro_result> h(a.n_zones);
+    HIP_CHECK(s, hipMemcpyAsync(h.data(), s->macro_out, sizeof(tr_macro_result) * a.n_zones, hipMemcpyDeviceToHost,
+                                s->stream));
+    HIP_CHECK(s, hipStreamSynchronize(s->stream));
+    int32_t m = 0;
+    for (int z = 0; z < a.n_zones; ++z) {
+        if (!a.eligible[z] || !(h[z].M > 0.0)) continue;
+        if (m < cap) out[m] = h[z];
+        ++m;
+    }
+    *n_out = m;
     return TR_OK;
 }
 

@@ -345,6 +345,31 @@ void launch_adam(float* W, const float* g, float* m, float* v, int n, float lr, 
 int64_t mlp_grad_scratch(int64_t B);
 int mlp_trainable();
 void launch_finish(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+// macroscale step (one env): its zones in body order, candidate reductions
+constexpr int kMacroMaxZones = 8;
+struct MacroZone {
+    double mom[kZoneMoments];            // moments as in the zone sums of a step
+    double vol;                          // solid volume of the zone's particles
+    double area[2];                      // AB, AC: sum of the candidates' pi r^2
+    unsigned long long cnt[2];           // candidates of AB, AC
+    unsigned long long vmax[2][4];       // order-preserving image of the largest projection along +-e1, +-e2
+    unsigned long long kmin[2][4];       // smallest candidate key reaching it
+};
+struct MacroArgs {
+    int n;                               // particles of the env (ids id_base .. id_base + n - 1)
+    int id_base;
+    int shape_begin, shape_end;          // the env's shapes
+    int n_zones;                         // bodies with half-spaces, in body order
+    int body[kMacroMaxZones];            // global body index of each
+    int eligible[kMacroMaxZones];        // 1: at least two half-spaces (separation plate, failure plane)
+    tr_macro_params mp;
+    int has_eq[kMacroMaxZones];          // 1: the zone's body is a dynamic equipment (eq below)
+    tr_macro_equipment eq[kMacroMaxZones];
+    double g[3];                         // gravity (FP64, as the scene was given it)
+};
+void launch_macro(const DevBuffers& b, const StepParams& p, const MacroArgs& a, MacroZone* mz, tr_macro_result* out,
+                  hipStream_t s);
+
 void launch_gather_by_id(const DevBuffers& b, int id_base, int n, float4* xo, float4* vo, float4* wo,
                          hipStream_t s);
 void launch_scatter_by_id(const DevBuffers& b, int id_base, int n, const float4* xi, const float4* vi,

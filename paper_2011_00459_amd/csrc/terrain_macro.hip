@@ -1,0 +1,864 @@
+// terrain_macro.hip -- the macroscale step of each active zone (section
+// "Macroscale model"): the zone's aggregate body (Eqs. aggregate_mass ..
+// aggregate_rot_vel) under Eq. mdb:eqAgg with the frictional-cohesive velocity
+// constraints of Eqs. aggregateNormal and aggregateTangent at its interfaces
+// to the equipment B (AB) and to the terrain's failure surface C (AC), each
+// interface reduced to four contact points.
+//
+//   k_macro_pass1  per particle of the env: zone membership (planes posed from
+//                  the bodies' current poses), the aggregate's moments, and for
+//                  the AB / AC candidates their count, cross-section area and
+//                  the largest projection along +-e1, +-e2 of the interface
+//                  (order-preserving 64-bit atomic maxima of the FP64 values)
+//   k_macro_pass2  the smallest candidate key reaching each maximum (ties to
+//                  the smaller particle id, then shape index)
+//   k_macro_solve  one thread per zone: the aggregate, the (at most) four
+//                  points of each interface, and the small complementarity
+//                  problem solved to machine precision in FP64: a damped
+//                  semismooth Newton iteration on the aggregate's six
+//                  velocities reaches the fixed point of the rows' projected
+//                  Gauss-Seidel, whose sweeps then confirm it (the regularised
+//                  rows of a rigid body with redundant points contract by only
+//                  about 1 - gamma / W per sweep, so Gauss-Seidel alone needs
+//                  ~1e5 sweeps for a stiff bulk)
+//
+// Readings: the zone's half-spaces follow the wedge convention (plane 0 the
+// separation plate, plane 1 the failure plane); AB candidates are the zone's
+// particles touching the zone body's shapes, AC candidates the zone's particles
+// within their radius of the failure plane, projected onto it; the interface
+// area is the sum of the candidates' cross sections; gamma = L / (c_as E_b A
+// dt^2), the compliance of the bulk as a spring c_as E_b A / L regularising a
+// velocity row over one step (velocity per impulse), L the cube root of the
+// aggregate's solid volume; the equipment is kinematic, the terrain static.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "terrain_geom.h"
+#include "terrain_internal.h"
+
+// every FP64 expression below is evaluated as written (no fused multiply-add),
+// like the reference arithmetic it is compared with
+#pragma clang fp contract(off)
+
+namespace trk {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ inline double dot3d(const double* a, const double* b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+__device__ inline void cross3d(const double* a, const double* b, double* c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// order-preserving image of a double in the unsigned integers (-0 and +0
+// map to the same image, as they compare equal)
+__device__ inline unsigned long long ord64(double v)
+{
+    unsigned long long u = (unsigned long long)__double_as_longlong(v + 0.0);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+
+// world-frame half-space p of a body at its current pose: normal nw, offset dw
+__device__ inline void plane_world(const BodyDev& B, int p, double nw[3], double& dw)
+{
+#pragma clang fp contract(off)
+    double R[9];
+    quat_to_R(B.quat, R);
+    const double* pl = B.planes[p];
+    for (int k = 0; k < 3; ++k) nw[k] = (R[k * 3 + 0] * pl[0] + R[k * 3 + 1] * pl[1]) + R[k * 3 + 2] * pl[2];
+    dw = pl[3] + dot3d(nw, B.pos);
+}
+
+// in-plane axes: e1 the normalised projection of the world axis least aligned
+// with n (the lower axis on ties), e2 = n x e1
+__device__ inline void plane_axes(const double* n, double* e1, double* e2)
+{
+#pragma clang fp contract(off)
+    int k0 = 0;
+    for (int k = 1; k < 3; ++k)
+        if (fabs(n[k]) < fabs(n[k0])) k0 = k;
+    double a[3] = {0.0, 0.0, 0.0};
+    a[k0] = 1.0;
+    double an = dot3d(a, n);
+    for (int k = 0; k < 3; ++k) e1[k] = a[k] - an * n[k];
+    double m = sqrt(dot3d(e1, e1));
+    for (int k = 0; k < 3; ++k) e1[k] /= m;
+    cross3d(n, e1, e2);
+}
+
+// a shape posed at its body's current pose (the step's kernels pose shapes at
+// the start of a step)
+__device__ inline ShapeDev posed_shape(const DevBuffers& b, int g)
+{
+#pragma clang fp contract(off)
+    ShapeDev S = b.shapes[g];
+    const BodyDev& B = b.bodies[S.body];
+    double R[9];
+    quat_to_R(B.quat, R);
+    for (int k = 0; k < 9; ++k) S.R[k] = R[k];
+    for (int k = 0; k < 3; ++k) S.wn[k] = (R[k * 3 + 0] * S.n[0] + R[k * 3 + 1] * S.n[1]) + R[k * 3 + 2] * S.n[2];
+    S.wd = S.d + ((S.wn[0] * B.pos[0] + S.wn[1] * B.pos[1]) + S.wn[2] * B.pos[2]);
+    for (int k = 0; k < 3; ++k) S.wc[k] = B.pos[k] + ((R[k * 3 + 0] * S.off[0] + R[k * 3 + 1] * S.off[1]) + R[k * 3 + 2] * S.off[2]);
+    return S;
+}
+
+// the env's zone (index into MacroArgs) containing x: the first body (in the
+// env's zone order) whose half-spaces all contain it; -1 when none
+__device__ inline int zone_at(const DevBuffers& b, const MacroArgs& a, const double* x)
+{
+#pragma clang fp contract(off)
+    for (int z = 0; z < a.n_zones; ++z) {
+        const BodyDev& B = b.bodies[a.body[z]];
+        bool in = B.nplanes > 0;
+        for (int p = 0; p < B.nplanes && in; ++p) {
+            double nw[3], dw;
+            plane_world(B, p, nw, dw);
+            if (dot3d(nw, x) - dw > 0.0) in = false;
+        }
+        if (in) return z;
+    }
+    return -1;
+}
+
+// interface q (0: AB, 1: AC) normal of zone z, from B or C into A
+__device__ inline void iface_normal(const DevBuffers& b, const MacroArgs& a, int z, int q, double* n, double& dfail)
+{
+    double nw[3], dw;
+    plane_world(b.bodies[a.body[z]], q, nw, dw);
+    for (int k = 0; k < 3; ++k) n[k] = -nw[k];
+    dfail = dw;
+}
+
+// AB candidate of a sphere against shape g: the contact point at the middle
+// of the overlap
+__device__ inline bool ab_point(const DevBuffers& b, const StepParams& p, int g, const double* x, double r,
+                                double* pt)
+{
+    ShapeDev S = posed_shape(b, g);
+    ShapeHit hit;
+    if (!shape_touch(S, b.hf_pool, x[0], x[1], x[2], r, p.kappa_c, &hit)) return false;
+    const double l2 = r - 0.5 * hit.delta;
+    for (int k = 0; k < 3; ++k) pt[k] = x[k] - l2 * hit.n[k];
+    return true;
+}
+
+// AC candidate of a sphere of zone z: within its radius of the failure plane,
+// projected onto it
+__device__ inline bool ac_point(const DevBuffers& b, const MacroArgs& a, int z, const double* x, double r, double* pt)
+{
+    double nw[3], dw;
+    plane_world(b.bodies[a.body[z]], 1, nw, dw);
+    const double d = dot3d(nw, x) - dw;
+    if (!(d >= -r)) return false;
+    for (int k = 0; k < 3; ++k) pt[k] = x[k] - d * nw[k];
+    return true;
+}
+
+// Candidates of sphere id (env-local) in zone z, interface q: calls f(key,
+// point) for each (AB: one per touching shape of the zone's body, key = id
+// << 16 | shape index in the env; AC: key = id << 16).
+template <class F>
+__device__ inline void candidates(const DevBuffers& b, const StepParams& p, const MacroArgs& a, int z, int q, int id,
+                                  const double* x, double r, F f)
+{
+    double pt[3];
+    if (q == 0) {
+        for (int g = a.shape_begin; g < a.shape_end; ++g)
+            if (b.shapes[g].body == a.body[z] && ab_point(b, p, g, x, r, pt))
+                f(((unsigned long long)id << 16) | (unsigned long long)(g - a.shape_begin), pt);
+    } else if (ac_point(b, a, z, x, r, pt)) {
+        f((unsigned long long)id << 16, pt);
+    }
+}
+
+// wave (64 lanes) sum and maximum; every lane of the wave takes part
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ inline unsigned long long wave_max(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// this lane's candidate (if `has`) of interface q added to its zone's count,
+// area and extreme projections: one atomic per zone and wave
+__device__ inline void wave_add_candidate(MacroZone* mz, int n_zones, int z, bool has, int q, double r,
+                                          const double* pt, const double* e1, const double* e2)
+{
+    const int lane = threadIdx.x & 63;
+    unsigned long long o4[4] = {0ull, 0ull, 0ull, 0ull};
+    if (has) {
+        const double s1 = dot3d(pt, e1), s2 = dot3d(pt, e2);
+        o4[0] = ord64(s1); o4[1] = ord64(-s1); o4[2] = ord64(s2); o4[3] = ord64(-s2);
+    }
+    for (int zz = 0; zz < n_zones; ++zz) {
+        const bool mine = has && z == zz;
+        const unsigned long long m = __ballot(mine);
+        if (m == 0) continue;
+        const double area = wave_sum(mine ? kPi * r * r : 0.0);
+        unsigned long long mx[4];
+        for (int d = 0; d < 4; ++d) mx[d] = wave_max(mine ? o4[d] : 0ull);
+        if (lane == __ffsll((unsigned long long)m) - 1) {
+            atomicAdd(&mz[zz].cnt[q], (unsigned long long)__popcll(m));
+            atomicAdd(&mz[zz].area[q], area);
+            for (int d = 0; d < 4; ++d) atomicMax(&mz[zz].vmax[q][d], mx[d]);
+        }
+    }
+}
+
+// Pass 1: zone membership, the zones' moments and the candidates' count, area
+// and extreme projections, each reduced over the wave before its atomic (all
+// the spheres of a zone add to the same few addresses)
+__global__ void __launch_bounds__(256) k_macro_pass1(DevBuffers b, StepParams p, MacroArgs a, MacroZone* mz)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int z = -1;
+    double x[3] = {0.0, 0.0, 0.0}, r = 0.0, vol = 0.0;
+    double mom[kZoneMoments];
+    for (int k = 0; k < kZoneMoments; ++k) mom[k] = 0.0;
+    if (t < a.n) {
+        const int s = b.id2slot[a.id_base + t];
+        const float4 xf = b.xr[s], vf = b.vm[s], wf = b.wi[s];
+        x[0] = xf.x; x[1] = xf.y; x[2] = xf.z;
+        r = xf.w;
+        z = zone_at(b, a, x);
+        if (z >= 0) {
+            const double m = (double)b.rho[s] * (4.0 / 3.0) * kPi * r * r * r;
+            const double v[3] = {vf.x, vf.y, vf.z};
+            const double Is = 0.4 * m * r * r;
+            mom[0] = m;
+            for (int k = 0; k < 3; ++k) { mom[1 + k] = m * x[k]; mom[4 + k] = m * v[k]; }
+            mom[7] = m * x[0] * x[0]; mom[8] = m * x[1] * x[1]; mom[9] = m * x[2] * x[2];
+            mom[10] = m * x[0] * x[1]; mom[11] = m * x[0] * x[2]; mom[12] = m * x[1] * x[2];
+            mom[13] = m * (x[1] * v[2] - x[2] * v[1]);
+            mom[14] = m * (x[2] * v[0] - x[0] * v[2]);
+            mom[15] = m * (x[0] * v[1] - x[1] * v[0]);
+            mom[16] = Is;
+            mom[17] = Is * wf.x; mom[18] = Is * wf.y; mom[19] = Is * wf.z;
+            vol = (4.0 / 3.0) * kPi * r * r * r;
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    for (int zz = 0; zz < a.n_zones; ++zz) {
+        const unsigned long long m = __ballot(z == zz);
+        if (m == 0) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        for (int k = 0; k <= kZoneMoments; ++k) {
+            const double v = wave_sum(z == zz ? (k < kZoneMoments ? mom[k] : vol) : 0.0);
+            if (lane == leader) atomicAdd(k < kZoneMoments ? &mz[zz].mom[k] : &mz[zz].vol, v);
+        }
+    }
+    const bool elig = z >= 0 && a.eligible[z];
+    double e1[2][3], e2[2][3];
+    for (int q = 0; q < 2; ++q) {
+        double n[3], dfail;
+        if (elig) {
+            iface_normal(b, a, z, q, n, dfail);
+            plane_axes(n, e1[q], e2[q]);
+        }
+    }
+    // AB: the env's shapes in turn, the same loop on every lane
+    for (int g = a.shape_begin; g < a.shape_end; ++g) {
+        double pt[3];
+        const bool has = elig && b.shapes[g].body == a.body[z] && ab_point(b, p, g, x, r, pt);
+        wave_add_candidate(mz, a.n_zones, z, has, 0, r, pt, e1[0], e2[0]);
+    }
+    double pt[3];
+    const bool has = elig && ac_point(b, a, z, x, r, pt);
+    wave_add_candidate(mz, a.n_zones, z, has, 1, r, pt, e1[1], e2[1]);
+}
+
+__global__ void __launch_bounds__(256) k_macro_pass2(DevBuffers b, StepParams p, MacroArgs a, MacroZone* mz)
+{
+#pragma clang fp contract(off)
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n) return;
+    const int s = b.id2slot[a.id_base + t];
+    float4 xf = b.xr[s];
+    double x[3] = {xf.x, xf.y, xf.z};
+    const int z = zone_at(b, a, x);
+    if (z < 0 || !a.eligible[z]) return;
+    MacroZone& Z = mz[z];
+    for (int q = 0; q < 2; ++q) {
+        double n[3], e1[3], e2[3], dfail;
+        iface_normal(b, a, z, q, n, dfail);
+        plane_axes(n, e1, e2);
+        candidates(b, p, a, z, q, t, x, (double)xf.w, [&](unsigned long long key, const double* pt) {
+            const double s1 = dot3d(pt, e1), s2 = dot3d(pt, e2);
+            const double val[4] = {s1, -s1, s2, -s2};
+            for (int d = 0; d < 4; ++d)
+                if (ord64(val[d]) == Z.vmax[q][d]) atomicMin(&Z.kmin[q][d], key);
+        });
+    }
+}
+
+// the point of a chosen candidate key (recomputed from its particle)
+__device__ inline void key_point(const DevBuffers& b, const StepParams& p, const MacroArgs& a, int z, int q,
+                                 unsigned long long key, double* pt)
+{
+    const int id = (int)(key >> 16);
+    const int s = b.id2slot[a.id_base + id];
+    float4 xf = b.xr[s];
+    double x[3] = {xf.x, xf.y, xf.z};
+    candidates(b, p, a, z, q, id, x, (double)xf.w, [&](unsigned long long k2, const double* c) {
+        if (k2 == key)
+            for (int k = 0; k < 3; ++k) pt[k] = c[k];
+    });
+}
+
+// inverse of a symmetric positive definite 3 x 3 matrix by cofactors
+__device__ inline void inv3(const double (*A)[3], double (*B)[3])
+{
+    const double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+    const double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+    const double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+    const double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+    B[0][0] = c00 / det;
+    B[1][0] = c01 / det;
+    B[2][0] = c02 / det;
+    B[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+    B[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+    B[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+    B[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+    B[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+    B[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+}
+
+__device__ inline double point_w(double invM, const double (*Iinv)[3], const double* rr, const double* u,
+                                 const double* w)
+{
+    double ra[3], rb[3], t[3];
+    cross3d(rr, u, ra);
+    cross3d(rr, w, rb);
+    for (int k = 0; k < 3; ++k) t[k] = (Iinv[k][0] * rb[0] + Iinv[k][1] * rb[1]) + Iinv[k][2] * rb[2];
+    return invM * dot3d(u, w) + dot3d(ra, t);
+}
+
+// Impulse of one interface point at the fixed point of its rows, as a function
+// of the point's relative velocity u: lambda_n = max(lo, -u_n / gamma) (the
+// normal row's complementarity) and lambda_t the projection of -u_t / gamma
+// onto the disk of radius mu |lambda_n| (the tangential rows' variational
+// inequality).  lam4 = (lambda_n, lambda_t xyz); K = d(lambda_n n + lambda_t)
+// / du (a generalized derivative) when K is not NULL.
+__device__ inline void point_impulse(const double* u, const double* n, double gam, double lo, double mu,
+                                     double* lam4, double (*K)[3])
+{
+#pragma clang fp contract(off)
+    const double un = dot3d(n, u);
+    const double zn = -un / gam;
+    const bool nact = zn > lo;
+    const double ln = nact ? zn : lo;
+    double z[3];
+    for (int k = 0; k < 3; ++k) z[k] = -(u[k] - un * n[k]) / gam;
+    const double zz = sqrt(dot3d(z, z));
+    const double rho = mu * fabs(ln);
+    const bool stick = zz <= rho;
+    const double sc = stick ? 1.0 : (zz > 0.0 ? rho / zz : 0.0);
+    lam4[0] = ln;
+    for (int k = 0; k < 3; ++k) lam4[1 + k] = sc * z[k];
+    if (!K) return;
+    double dln[3];
+    for (int k = 0; k < 3; ++k) dln[k] = nact ? -n[k] / gam : 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) K[i][j] = n[i] * dln[j];
+    if (stick) {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) K[i][j] -= ((i == j ? 1.0 : 0.0) - n[i] * n[j]) / gam;
+    } else if (zz > 0.0) {
+        const double sg = ln > 0.0 ? 1.0 : (ln < 0.0 ? -1.0 : 0.0);
+        double zh[3] = {z[0] / zz, z[1] / zz, z[2] / zz};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                K[i][j] += zh[i] * (mu * sg) * dln[j] -
+                           (rho / zz) * (((i == j ? 1.0 : 0.0) - n[i] * n[j]) - zh[i] * zh[j]) / gam;
+    }
+}
+
+// The aggregate's small system: its interface points and, with a dynamic
+// equipment, the equipment body and its drive.  Unknowns w: the aggregate's
+// (v, omega), then the equipment's (v, omega) when ndof = 12.
+struct MacroSys {
+    int np, ndof;
+    double rr[8][3], rb[8][3], uo[8][3], n[8][3], gam[8], lo[8], mu[8];
+    int onB[8];                    // AB point of a dynamic equipment: its rows act on both bodies
+    double invM, Iinv[3][3];       // aggregate
+    double invMB, IBinv[3][3];     // dynamic equipment (world frame)
+    double target[6], lim[6], gd;  // drive: velocity targets, impulse limits, compliance
+};
+
+__device__ inline void mat3v(const double (*M)[3], const double* x, double* y)
+{
+    for (int k = 0; k < 3; ++k) y[k] = (M[k][0] * x[0] + M[k][1] * x[1]) + M[k][2] * x[2];
+}
+
+// velocity of point c relative to the other side (u = D_c w - uo_c)
+__device__ inline void point_vel(const MacroSys& S, int c, const double* w, double* u)
+{
+    double t[3];
+    cross3d(w + 3, S.rr[c], t);
+    for (int k = 0; k < 3; ++k) u[k] = w[k] + t[k] - S.uo[c][k];
+    if (S.onB[c]) {
+        cross3d(w + 9, S.rb[c], t);
+        for (int k = 0; k < 3; ++k) u[k] -= w[6 + k] + t[k];
+    }
+}
+
+// D_c (3 x 12): [I, -[r_A]x, -I, [r_B]x] (the last two blocks only on a dynamic equipment)
+__device__ inline void point_D(const MacroSys& S, int c, double (*D)[12])
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 12; ++j) D[i][j] = 0.0;
+    const double* r = S.rr[c];
+    const double X[3][3] = {{0.0, -r[2], r[1]}, {r[2], 0.0, -r[0]}, {-r[1], r[0], 0.0}};
+    for (int i = 0; i < 3; ++i) {
+        D[i][i] = 1.0;
+        for (int j = 0; j < 3; ++j) D[i][3 + j] = -X[i][j];
+    }
+    if (!S.onB[c]) return;
+    const double* q = S.rb[c];
+    const double Y[3][3] = {{0.0, -q[2], q[1]}, {q[2], 0.0, -q[0]}, {-q[1], q[0], 0.0}};
+    for (int i = 0; i < 3; ++i) {
+        D[i][6 + i] = -1.0;
+        for (int j = 0; j < 3; ++j) D[i][9 + j] = Y[i][j];
+    }
+}
+
+// G(w) = w - w0 - M^-1 F(w), F the generalized impulse of every row at its
+// closed-form fixed point given w; and, when jac is not NULL, dG/dw
+// (ndof x ndof, row-major).
+__device__ inline void macro_residual(const MacroSys& S, const double* w0, const double* w, double* G, double* jac)
+{
+    const int nd = S.ndof;
+    double F[12];
+    for (int k = 0; k < 12; ++k) F[k] = 0.0;
+    double Sm[12][12];
+    if (jac)
+        for (int i = 0; i < 12; ++i)
+            for (int j = 0; j < 12; ++j) Sm[i][j] = 0.0;
+    for (int c = 0; c < S.np; ++c) {
+        double u[3], lam4[4], K[3][3], D[3][12], J[3];
+        point_vel(S, c, w, u);
+        point_impulse(u, S.n[c], S.gam[c], S.lo[c], S.mu[c], lam4, jac ? K : nullptr);
+        for (int k = 0; k < 3; ++k) J[k] = lam4[0] * S.n[c][k] + lam4[1 + k];
+        point_D(S, c, D);
+        for (int j = 0; j < nd; ++j) F[j] += (D[0][j] * J[0] + D[1][j] * J[1]) + D[2][j] * J[2];
+        if (!jac) continue;
+        double KD[3][12];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < nd; ++j) KD[i][j] = (K[i][0] * D[0][j] + K[i][1] * D[1][j]) + K[i][2] * D[2][j];
+        for (int i = 0; i < nd; ++i)
+            for (int j = 0; j < nd; ++j) Sm[i][j] += (D[0][i] * KD[0][j] + D[1][i] * KD[1][j]) + D[2][i] * KD[2][j];
+    }
+    if (nd == 12) {
+        for (int k = 0; k < 6; ++k) {
+            const double z = -(w[6 + k] - S.target[k]) / S.gd;
+            const double l = z > S.lim[k] ? S.lim[k] : (z < -S.lim[k] ? -S.lim[k] : z);
+            F[6 + k] += l;
+            if (jac && z < S.lim[k] && z > -S.lim[k]) Sm[6 + k][6 + k] -= 1.0 / S.gd;
+        }
+    }
+    // M^-1 blocks: aggregate (1/M, I^-1), equipment (1/M_B, I_B^-1)
+    double MF[12];
+    for (int k = 0; k < 3; ++k) MF[k] = S.invM * F[k];
+    mat3v(S.Iinv, F + 3, MF + 3);
+    if (nd == 12) {
+        for (int k = 0; k < 3; ++k) MF[6 + k] = S.invMB * F[6 + k];
+        mat3v(S.IBinv, F + 9, MF + 9);
+    }
+    for (int k = 0; k < nd; ++k) G[k] = w[k] - w0[k] - MF[k];
+    if (!jac) return;
+    for (int j = 0; j < nd; ++j) {
+        double col[12], mc[12];
+        for (int i = 0; i < nd; ++i) col[i] = Sm[i][j];
+        for (int k = 0; k < 3; ++k) mc[k] = S.invM * col[k];
+        mat3v(S.Iinv, col + 3, mc + 3);
+        if (nd == 12) {
+            for (int k = 0; k < 3; ++k) mc[6 + k] = S.invMB * col[6 + k];
+            mat3v(S.IBinv, col + 9, mc + 9);
+        }
+        for (int i = 0; i < nd; ++i) jac[i * nd + j] = (i == j ? 1.0 : 0.0) - mc[i];
+    }
+}
+
+// solves A x = b (n x n, row-major, overwritten) by Gaussian elimination with
+// partial pivoting; false when singular
+__device__ inline bool solve_n(double* A, double* b, int n)
+{
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+        if (!(fabs(A[piv * n + k]) > 0.0)) return false;
+        if (piv != k) {
+            for (int j = 0; j < n; ++j) {
+                double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t;
+            }
+            double t = b[k]; b[k] = b[piv]; b[piv] = t;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            const double f = A[i * n + k] / A[k * n + k];
+            for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+            b[i] -= f * b[k];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * b[j];
+        b[i] = s / A[i * n + i];
+    }
+    return true;
+}
+
+// size of G in velocity units: linear parts and the angular parts times Lc
+__device__ inline double gnorm(const double* G, int nd, double Lc)
+{
+    double s = 0.0;
+    for (int k = 0; k < nd; ++k) {
+        const double g = (k % 6) < 3 ? G[k] : Lc * G[k];
+        s += g * g;
+    }
+    return sqrt(s);
+}
+
+// Damped semismooth Newton on G(w) = 0 from w = w0; returns its iterations
+// and leaves the best w found in w.
+__device__ inline int macro_newton(const MacroSys& S, const double* w0, double Lc, double scale, double* w)
+{
+    const int nd = S.ndof;
+    for (int k = 0; k < nd; ++k) w[k] = w0[k];
+    double G[12], A[144];
+    macro_residual(S, w0, w, G, A);
+    double g = gnorm(G, nd, Lc);
+    int it = 0;
+    for (; it < 100 && g > 1e-15 * scale; ++it) {
+        double d[12];
+        for (int k = 0; k < nd; ++k) d[k] = -G[k];
+        if (!solve_n(A, d, nd)) break;
+        double step = 1.0, wt[12], Gt[12];
+        bool took = false;
+        for (int ls = 0; ls < 40; ++ls, step *= 0.5) {
+            for (int k = 0; k < nd; ++k) wt[k] = w[k] + step * d[k];
+            macro_residual(S, w0, wt, Gt, nullptr);
+            const double gt = gnorm(Gt, nd, Lc);
+            if (gt < (1.0 - 1e-4 * step) * g) {
+                took = true;
+                g = gt;
+                break;
+            }
+        }
+        if (!took) break;
+        for (int k = 0; k < nd; ++k) w[k] = wt[k];
+        macro_residual(S, w0, w, G, A);
+        g = gnorm(G, nd, Lc);
+    }
+    return it;
+}
+
+__global__ void __launch_bounds__(64) k_macro_solve(DevBuffers b, StepParams p, MacroArgs a, MacroZone* mz, tr_macro_result* out)
+{
+#pragma clang fp contract(off)
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= a.n_zones) return;
+    const MacroZone& Z = mz[z];
+    const BodyDev& B = b.bodies[a.body[z]];
+    tr_macro_result o;
+    memset(&o, 0, sizeof(o));
+    o.zone = B.user_id;
+    const double* S = Z.mom;
+    const double M = S[0];
+    o.M = M;
+    if (!(M > 0.0) || !a.eligible[z]) {
+        out[z] = o;
+        return;
+    }
+    // the aggregate (Eqs. aggregate_mass .. aggregate_rot_vel, read R14)
+    double xA[3] = {S[1] / M, S[2] / M, S[3] / M}, vA[3] = {S[4] / M, S[5] / M, S[6] / M};
+    double Cxx = S[7] - M * xA[0] * xA[0], Cyy = S[8] - M * xA[1] * xA[1], Czz = S[9] - M * xA[2] * xA[2];
+    double Cxy = S[10] - M * xA[0] * xA[1], Cxz = S[11] - M * xA[0] * xA[2], Cyz = S[12] - M * xA[1] * xA[2];
+    double tr = Cxx + Cyy + Czz;
+    double I[3][3] = {{S[16] + tr - Cxx, -Cxy, -Cxz}, {-Cxy, S[16] + tr - Cyy, -Cyz}, {-Cxz, -Cyz, S[16] + tr - Czz}};
+    double L[3] = {S[13] - (xA[1] * S[6] - xA[2] * S[5]) + S[17], S[14] - (xA[2] * S[4] - xA[0] * S[6]) + S[18],
+                   S[15] - (xA[0] * S[5] - xA[1] * S[4]) + S[19]};
+    double c00 = I[1][1] * I[2][2] - I[1][2] * I[2][1], c01 = I[1][2] * I[2][0] - I[1][0] * I[2][2];
+    double c02 = I[1][0] * I[2][1] - I[1][1] * I[2][0];
+    double det = I[0][0] * c00 + I[0][1] * c01 + I[0][2] * c02;
+    double Iinv[3][3];
+    Iinv[0][0] = c00 / det; Iinv[1][0] = c01 / det; Iinv[2][0] = c02 / det;
+    Iinv[0][1] = (I[0][2] * I[2][1] - I[0][1] * I[2][2]) / det;
+    Iinv[1][1] = (I[0][0] * I[2][2] - I[0][2] * I[2][0]) / det;
+    Iinv[2][1] = (I[0][1] * I[2][0] - I[0][0] * I[2][1]) / det;
+    Iinv[0][2] = (I[0][1] * I[1][2] - I[0][2] * I[1][1]) / det;
+    Iinv[1][2] = (I[0][2] * I[1][0] - I[0][0] * I[1][2]) / det;
+    Iinv[2][2] = (I[0][0] * I[1][1] - I[0][1] * I[1][0]) / det;
+    double wA[3];
+    for (int k = 0; k < 3; ++k) wA[k] = (Iinv[k][0] * L[0] + Iinv[k][1] * L[1]) + Iinv[k][2] * L[2];
+    for (int k = 0; k < 3; ++k) { o.x[k] = xA[k]; o.v0[k] = vA[k]; o.w0[k] = wA[k]; }
+    const double invM = 1.0 / M;
+    const double Lc = cbrt(Z.vol);
+    // the reduced points of each interface: +e1, -e1, +e2, -e2, each kept once
+    int np = 0, map[8];
+    for (int q = 0; q < 2; ++q) {
+        o.n_cand[q] = (int64_t)Z.cnt[q];
+        o.area[q] = Z.area[q];
+        o.gamma[q] = Z.area[q] > 0.0 ? Lc / ((q == 0 ? a.mp.cas_ab : a.mp.cas_ac) * a.mp.E_b * Z.area[q] * (double)p.dt_d * (double)p.dt_d) : 0.0;
+        if (Z.cnt[q] == 0) continue;
+        double n[3], dfail;
+        iface_normal(b, a, z, q, n, dfail);
+        int m = 0;
+        unsigned long long chosen[4];
+        for (int d = 0; d < 4; ++d) {
+            bool dup = false;
+            for (int j = 0; j < m; ++j) dup |= chosen[j] == Z.kmin[q][d];
+            if (dup) continue;
+            chosen[m] = Z.kmin[q][d];
+            key_point(b, p, a, z, q, chosen[m], o.p[4 * q + m]);
+            for (int k = 0; k < 3; ++k) o.n[4 * q + m][k] = n[k];
+            o.src[4 * q + m] = (int64_t)(chosen[m] >> 16);
+            map[np++] = 4 * q + m;
+            ++m;
+        }
+        o.n_points[q] = m;
+    }
+    // Eq. mdb:eqAgg in impulse form with the rows of Eqs. aggregateNormal and
+    // aggregateTangent; with a dynamic equipment (Eq. mdb:eqEq) its body and
+    // drive rows join the system
+    const double dt = p.dt_d;
+    const tr_macro_equipment* E = a.has_eq[z] ? &a.eq[z] : nullptr;
+    MacroSys Q;
+    Q.np = np;
+    Q.ndof = E ? 12 : 6;
+    Q.invM = invM;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) { Q.Iinv[i][j] = Iinv[i][j]; Q.IBinv[i][j] = 0.0; }
+    Q.invMB = 0.0;
+    Q.gd = 1.0;
+    double w0[12];
+    for (int k = 0; k < 3; ++k) { w0[k] = vA[k] + dt * a.g[k]; w0[3 + k] = wA[k]; }
+    for (int k = 0; k < 3; ++k) { w0[6 + k] = B.linvel[k]; w0[9 + k] = B.angvel[k]; }
+    if (E) {
+        Q.invMB = 1.0 / E->mass;
+        double R[9], Iw[3][3];
+        quat_to_R(B.quat, R);
+        const double* J6 = E->inertia;
+        const double Ib[3][3] = {{J6[0], J6[3], J6[4]}, {J6[3], J6[1], J6[5]}, {J6[4], J6[5], J6[2]}};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l) acc += R[i * 3 + k] * Ib[k][l] * R[j * 3 + l];
+                Iw[i][j] = acc;
+            }
+        inv3(Iw, Q.IBinv);
+        for (int k = 0; k < 3; ++k) {
+            w0[6 + k] = B.linvel[k] + dt * a.g[k];
+            Q.target[k] = E->v_target[k];
+            Q.target[3 + k] = E->w_target[k];
+            Q.lim[k] = E->f_max * dt;
+            Q.lim[3 + k] = E->t_max * dt;
+        }
+        Q.gd = E->gamma_drive;
+    }
+    double Wn[8], Wt[8], lam[8][4];
+    for (int c = 0; c < np; ++c) {
+        const int k8 = map[c], q = k8 / 4;
+        Q.onB[c] = q == 0 && E != nullptr;
+        for (int k = 0; k < 3; ++k) {
+            Q.rr[c][k] = o.p[k8][k] - xA[k];
+            Q.rb[c][k] = o.p[k8][k] - B.pos[k];
+            Q.n[c][k] = o.n[k8][k];
+            Q.uo[c][k] = 0.0;
+        }
+        if (q == 0 && !E) {
+            double t[3];
+            cross3d(B.angvel, Q.rb[c], t);
+            for (int k = 0; k < 3; ++k) Q.uo[c][k] = B.linvel[k] + t[k];
+        }
+        double t1[3], t2[3];
+        plane_axes(o.n[k8], t1, t2);
+        Wn[c] = point_w(invM, Iinv, Q.rr[c], o.n[k8], o.n[k8]);
+        Wt[c] = 0.5 * (point_w(invM, Iinv, Q.rr[c], t1, t1) + point_w(invM, Iinv, Q.rr[c], t2, t2));
+        if (Q.onB[c]) {
+            Wn[c] += point_w(Q.invMB, Q.IBinv, Q.rb[c], o.n[k8], o.n[k8]);
+            Wt[c] += 0.5 * (point_w(Q.invMB, Q.IBinv, Q.rb[c], t1, t1) + point_w(Q.invMB, Q.IBinv, Q.rb[c], t2, t2));
+        }
+        Q.lo[c] = -a.mp.c_b * o.area[q] * dt / (double)o.n_points[q];
+        Q.mu[c] = q == 0 ? a.mp.mu_ab : a.mp.mu_ac;
+        Q.gam[c] = o.gamma[q];
+    }
+    // the fixed point of the rows directly: Newton on the bodies' velocities
+    // (six, or twelve with a dynamic equipment) with each row's impulse in
+    // closed form, then the rows' projected Gauss-Seidel from there until no
+    // impulse changes (one or two sweeps when Newton converged, else it
+    // finishes the solve)
+    double scale = dt * sqrt(dot3d(a.g, a.g)) + 1e-300;
+    for (int k = 0; k < Q.ndof; ++k) scale += (k % 6) < 3 ? fabs(w0[k]) : Lc * fabs(w0[k]);
+    double wn[12];
+    const int newton_its = macro_newton(Q, w0, Lc, scale, wn);
+    double vv[3], ww[3], vB[3], wB[3], ld[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    {
+        double F[12];
+        for (int k = 0; k < 12; ++k) F[k] = 0.0;
+        for (int c = 0; c < np; ++c) {
+            double u[3], D[3][12], J[3];
+            point_vel(Q, c, wn, u);
+            point_impulse(u, Q.n[c], Q.gam[c], Q.lo[c], Q.mu[c], lam[c], nullptr);
+            for (int k = 0; k < 3; ++k) J[k] = lam[c][0] * Q.n[c][k] + lam[c][1 + k];
+            point_D(Q, c, D);
+            for (int j = 0; j < Q.ndof; ++j) F[j] += (D[0][j] * J[0] + D[1][j] * J[1]) + D[2][j] * J[2];
+        }
+        if (E)
+            for (int k = 0; k < 6; ++k) {
+                const double zz = -(wn[6 + k] - Q.target[k]) / Q.gd;
+                ld[k] = zz > Q.lim[k] ? Q.lim[k] : (zz < -Q.lim[k] ? -Q.lim[k] : zz);
+                F[6 + k] += ld[k];
+            }
+        double t[3];
+        mat3v(Q.Iinv, F + 3, t);
+        for (int k = 0; k < 3; ++k) { vv[k] = w0[k] + invM * F[k]; ww[k] = w0[3 + k] + t[k]; }
+        if (E) {
+            mat3v(Q.IBinv, F + 9, t);
+            for (int k = 0; k < 3; ++k) { vB[k] = w0[6 + k] + Q.invMB * F[6 + k]; wB[k] = w0[9 + k] + t[k]; }
+        } else {
+            for (int k = 0; k < 3; ++k) { vB[k] = B.linvel[k]; wB[k] = B.angvel[k]; }
+        }
+    }
+    int sweep = 0;
+    for (; sweep < 200000; ++sweep) {
+        double dmax = 0.0, lmax = 0.0;
+        for (int c = 0; c < np; ++c) {
+            const double* nn = Q.n[c];
+            for (int row = 0; row < 2; ++row) {
+                double u[3], t[3], J[3];
+                cross3d(ww, Q.rr[c], t);
+                for (int k = 0; k < 3; ++k) u[k] = vv[k] + t[k] - Q.uo[c][k];
+                if (Q.onB[c]) {
+                    cross3d(wB, Q.rb[c], t);
+                    for (int k = 0; k < 3; ++k) u[k] -= vB[k] + t[k];
+                }
+                const double un = dot3d(nn, u);
+                if (row == 0) {
+                    double ln = lam[c][0] - (un + Q.gam[c] * lam[c][0]) / (Wn[c] + Q.gam[c]);
+                    if (ln < Q.lo[c]) ln = Q.lo[c];
+                    const double d = ln - lam[c][0];
+                    lam[c][0] = ln;
+                    for (int k = 0; k < 3; ++k) J[k] = d * nn[k];
+                    if (fabs(d) > dmax) dmax = fabs(d);
+                } else {
+                    double lt[3];
+                    for (int k = 0; k < 3; ++k) {
+                        const double ut = u[k] - un * nn[k];
+                        lt[k] = lam[c][1 + k] - (ut + Q.gam[c] * lam[c][1 + k]) / (Wt[c] + Q.gam[c]);
+                    }
+                    const double ltn = dot3d(lt, nn);
+                    for (int k = 0; k < 3; ++k) lt[k] -= ltn * nn[k];
+                    const double lim = Q.mu[c] * fabs(lam[c][0]);
+                    const double m2 = sqrt(dot3d(lt, lt));
+                    if (m2 > lim) {
+                        const double sc = m2 > 0.0 ? lim / m2 : 0.0;
+                        for (int k = 0; k < 3; ++k) lt[k] *= sc;
+                    }
+                    for (int k = 0; k < 3; ++k) {
+                        J[k] = lt[k] - lam[c][1 + k];
+                        if (fabs(J[k]) > dmax) dmax = fabs(J[k]);
+                        lam[c][1 + k] = lt[k];
+                    }
+                }
+                double tj[3], dw[3];
+                cross3d(Q.rr[c], J, tj);
+                mat3v(Iinv, tj, dw);
+                for (int k = 0; k < 3; ++k) { vv[k] += invM * J[k]; ww[k] += dw[k]; }
+                if (Q.onB[c]) {
+                    cross3d(Q.rb[c], J, tj);
+                    mat3v(Q.IBinv, tj, dw);
+                    for (int k = 0; k < 3; ++k) { vB[k] -= Q.invMB * J[k]; wB[k] -= dw[k]; }
+                }
+            }
+            for (int k = 0; k < 4; ++k)
+                if (fabs(lam[c][k]) > lmax) lmax = fabs(lam[c][k]);
+        }
+        if (E) {
+            for (int k = 0; k < 6; ++k) {
+                const int ax = k % 3;
+                const double u = k < 3 ? vB[ax] - Q.target[k] : wB[ax] - Q.target[k];
+                const double W = k < 3 ? Q.invMB : Q.IBinv[ax][ax];
+                double l = ld[k] - (u + Q.gd * ld[k]) / (W + Q.gd);
+                if (l > Q.lim[k]) l = Q.lim[k];
+                if (l < -Q.lim[k]) l = -Q.lim[k];
+                const double d = l - ld[k];
+                ld[k] = l;
+                if (k < 3) vB[ax] += Q.invMB * d;
+                else
+                    for (int j = 0; j < 3; ++j) wB[j] += Q.IBinv[j][ax] * d;
+                if (fabs(d) > dmax) dmax = fabs(d);
+                if (fabs(l) > lmax) lmax = fabs(l);
+            }
+        }
+        if (dmax <= 1e-15 * lmax || lmax == 0.0) {
+            ++sweep;
+            break;
+        }
+    }
+    o.sweeps = newton_its + sweep;
+    for (int k = 0; k < 3; ++k) {
+        o.v[k] = vv[k]; o.w[k] = ww[k]; o.force[k] = 0.0; o.torque[k] = 0.0;
+        o.v_b[k] = vB[k]; o.w_b[k] = wB[k];
+    }
+    for (int k = 0; k < 6; ++k) o.lam_drive[k] = ld[k];
+    for (int c = 0; c < np; ++c) {
+        const int k8 = map[c];
+        for (int k = 0; k < 4; ++k) o.lam[k8][k] = lam[c][k];
+        if (k8 >= 4) continue;
+        double J[3], t[3];
+        for (int k = 0; k < 3; ++k) J[k] = lam[c][0] * Q.n[c][k] + lam[c][1 + k];
+        for (int k = 0; k < 3; ++k) o.force[k] -= J[k] / dt;
+        cross3d(Q.rb[c], J, t);
+        for (int k = 0; k < 3; ++k) o.torque[k] -= t[k] / dt;
+    }
+    out[z] = o;
+}
+
+__global__ void k_macro_clear(MacroZone* mz, int n_zones)
+{
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= n_zones) return;
+    MacroZone& Z = mz[z];
+    for (int k = 0; k < kZoneMoments; ++k) Z.mom[k] = 0.0;
+    Z.vol = 0.0;
+    for (int q = 0; q < 2; ++q) {
+        Z.cnt[q] = 0;
+        Z.area[q] = 0.0;
+        for (int d = 0; d < 4; ++d) {
+            Z.vmax[q][d] = 0ull;
+            Z.kmin[q][d] = ~0ull;
+        }
+    }
+}
+
+}  // namespace
+
+void launch_macro(const DevBuffers& b, const StepParams& p, const MacroArgs& a, MacroZone* mz, tr_macro_result* out,
+                  hipStream_t s)
+{
+    if (a.n_zones <= 0) return;
+    hipLaunchKernelGGL(k_macro_clear, dim3(1), dim3(64), 0, s, mz, a.n_zones);
+    if (a.n > 0) {
+        const unsigned g = (unsigned)((a.n + 255) / 256);
+        hipLaunchKernelGGL(k_macro_pass1, dim3(g), dim3(256), 0, s, b, p, a, mz);
+        hipLaunchKernelGGL(k_macro_pass2, dim3(g), dim3(256), 0, s, b, p, a, mz);
+    }
+    hipLaunchKernelGGL(k_macro_solve, dim3(1), dim3(64), 0, s, b, p, a, mz, out);
+}
+
+}  // namespace trk

@@ -27,7 +27,7 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state", "autotune",
            "get_rolling_impulses", "set_tool", "get_zone_wedges", "coarse_grain", "advect_fluid",
            "terrain_from_voxels", "convert_cut", "convert_deposit", "grow_particles", "form_particles",
-           "remove_particles", "settle_particles", "get_colours", "mlp_loss_grad_noalloc")
+           "remove_particles", "settle_particles", "get_colours", "mlp_loss_grad_noalloc", "macro_step")
 CG_KERNEL = {"heaviside": 0, "gauss": 1}
 PGS_MODE = {"grouped": 0, "per_env": 1, "spread": 2}
 MLP_TRAINABLE = MLP_PARAMS - 12
@@ -47,6 +47,26 @@ class tr_material(C.Structure):
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class tr_macro_params(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("E_b", "c_b", "mu_ab", "mu_ac", "cas_ab", "cas_ac")]
+
+
+class tr_macro_result(C.Structure):
+    _fields_ = [("zone", C.c_int32), ("n_points", C.c_int32 * 2), ("sweeps", C.c_int32),
+                ("n_cand", C.c_int64 * 2), ("area", C.c_double * 2), ("gamma", C.c_double * 2),
+                ("p", C.c_double * 24), ("n", C.c_double * 24), ("src", C.c_int64 * 8), ("lam", C.c_double * 32),
+                ("M", C.c_double), ("x", C.c_double * 3), ("v0", C.c_double * 3), ("w0", C.c_double * 3),
+                ("v", C.c_double * 3), ("w", C.c_double * 3), ("force", C.c_double * 3),
+                ("torque", C.c_double * 3), ("v_b", C.c_double * 3), ("w_b", C.c_double * 3),
+                ("lam_drive", C.c_double * 6)]
+
+
+class tr_macro_equipment(C.Structure):
+    _fields_ = [("body_id", C.c_int32), ("pad", C.c_int32), ("mass", C.c_double), ("inertia", C.c_double * 6),
+                ("v_target", C.c_double * 3), ("w_target", C.c_double * 3), ("f_max", C.c_double),
+                ("t_max", C.c_double), ("gamma_drive", C.c_double)]
 
 
 class tr_scene_desc(C.Structure):
@@ -113,6 +133,33 @@ class tr_aggregate(C.Structure):
 _lib = None
 
 
+def torch_first():
+    """Import PyTorch before the library is loaded, so that the library binds
+    to the HIP runtime the PyTorch wheel carries (one runtime in the process:
+    PyTorch's tensors, caching allocator and streams are then the library's
+    device memory and streams).  Loading the library first gives the process
+    a second runtime that PyTorch's devices are not visible to.  Returns the
+    torch module; raises if the library is already loaded."""
+    if _lib is not None:
+        raise RuntimeError("libterrain is already loaded: call torch_first() before anything else uses it")
+    import torch
+    return torch
+
+
+def torch_allocator(device=0):
+    """ALLOC_FN / FREE_FN over PyTorch's caching allocator (after torch_first())."""
+    import torch
+
+    def alloc(ctx, nbytes, stream):
+        with torch.cuda.device(device):
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream or 0)
+
+    def free(ctx, ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return ALLOC_FN(alloc), FREE_FN(free)
+
+
 def lib():
     """Load libterrain.so (raises if it has not been built)."""
     global _lib
@@ -156,6 +203,8 @@ def lib():
         L.autotune.argtypes = [P, C.c_int32, C.c_char_p, C.POINTER(tr_solver_config), C.POINTER(C.c_float)]
         L.get_rolling_impulses.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_int64)]
         L.get_colours.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.macro_step.argtypes = [P, C.c_int32, C.POINTER(tr_macro_params), C.c_int32, C.POINTER(tr_macro_equipment),
+                                 C.c_int32, C.POINTER(tr_macro_result), C.POINTER(C.c_int32)]
         L.coarse_grain.argtypes = [P, C.c_int32, C.POINTER(tr_voxel_grid), C.c_int32, C.c_double, P, P, P]
         L.advect_fluid.argtypes = [P, C.POINTER(tr_voxel_grid), C.c_double, P, P, P, C.POINTER(C.c_double)]
         L.remove_particles.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_int64)]
@@ -199,7 +248,10 @@ class Scene:
 
     def __init__(self, n_envs=1, dt=1.0 / 60.0, gravity=(0.0, 0.0, -9.81), max_sweeps=100, tol=0.0,
                  warm_start="cold", material=None, cap_particles=1024, cap_contacts=16384, env_bounds=None,
-                 r_ref=0.0, stream=None):
+                 r_ref=0.0, stream=None, alloc_fn=None, free_fn=None, alloc_ctx=None):
+        """stream: a hipStream_t (int) the scene runs on; alloc_fn / free_fn:
+        ALLOC_FN / FREE_FN callbacks for its device buffers (kept alive with
+        the scene)."""
         L = lib()
         d = tr_scene_desc()
         d.n_envs = n_envs
@@ -220,6 +272,13 @@ class Scene:
         d.r_ref = r_ref
         if stream is not None:
             d.stream = stream
+        if (alloc_fn is None) != (free_fn is None):
+            raise ValueError("alloc_fn and free_fn go together")
+        if alloc_fn is not None:
+            d.alloc_fn = alloc_fn
+            d.free_fn = free_fn
+            d.alloc_ctx = alloc_ctx
+        self._callbacks = (alloc_fn, free_fn)
         self.n_envs = n_envs
         self.max_sweeps = max_sweeps
         h = C.c_void_p()
@@ -435,6 +494,44 @@ class Scene:
         t = np.zeros(3)
         self._check(lib().get_contact_forces(self.h, env, body_id, _dp(f), _dp(t)), "get_contact_forces")
         return f, t
+
+    def macro_step(self, env, E_b, c_b, mu_ab, mu_ac, cas_ab, cas_ac, equipment=None, cap=8):
+        """The macroscale step of env's zones for the current state (the C-ABI
+        macro_step); one dict per zone, arrays per interface point.
+        equipment: dicts (body id, mass, inertia (xx, yy, zz, xy, xz, yz, body
+        frame), v_target, w_target, f_max, t_max, gamma_drive) of the bodies
+        that move with their aggregate; the others are kinematic."""
+        mp = tr_macro_params(E_b, c_b, mu_ab, mu_ac, cas_ab, cas_ac)
+        eqs = list(equipment or [])
+        eq = (tr_macro_equipment * max(len(eqs), 1))()
+        for k, e in enumerate(eqs):
+            eq[k].body_id = int(e["body"])
+            eq[k].mass = e["mass"]
+            for j in range(6):
+                eq[k].inertia[j] = e["inertia"][j]
+            for j in range(3):
+                eq[k].v_target[j] = e.get("v_target", (0.0, 0.0, 0.0))[j]
+                eq[k].w_target[j] = e.get("w_target", (0.0, 0.0, 0.0))[j]
+            eq[k].f_max = e.get("f_max", 0.0)
+            eq[k].t_max = e.get("t_max", 0.0)
+            eq[k].gamma_drive = e.get("gamma_drive", 1e-6)
+        out = (tr_macro_result * cap)()
+        n = C.c_int32()
+        self._check(lib().macro_step(self.h, env, C.byref(mp), len(eqs), eq, cap, out, C.byref(n)), "macro_step")
+        res = []
+        for o in out[: min(n.value, cap)]:
+            npt = (o.n_points[0], o.n_points[1])
+            sel = list(range(npt[0])) + [4 + j for j in range(npt[1])]   # AB points, then AC points
+            p = np.array(o.p[:]).reshape(8, 3)
+            nn = np.array(o.n[:]).reshape(8, 3)
+            lam = np.array(o.lam[:]).reshape(8, 4)
+            res.append(dict(zone=o.zone, n_points=npt, sweeps=o.sweeps, n_cand=(o.n_cand[0], o.n_cand[1]),
+                            area=(o.area[0], o.area[1]), gamma=(o.gamma[0], o.gamma[1]), p=p[sel], n=nn[sel],
+                            src=[o.src[k] for k in sel], lam=lam[sel], M=o.M, x=np.array(o.x[:]),
+                            v0=np.array(o.v0[:]), w0=np.array(o.w0[:]), v=np.array(o.v[:]), w=np.array(o.w[:]),
+                            force=np.array(o.force[:]), torque=np.array(o.torque[:]), v_b=np.array(o.v_b[:]),
+                            w_b=np.array(o.w_b[:]), lam_drive=np.array(o.lam_drive[:])))
+        return res
 
     def get_aggregates(self, env, cap=8):
         out = (tr_aggregate * cap)()
