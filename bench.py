@@ -47,7 +47,7 @@ PAIR_BYTES, BOUND_BYTES = 176, 128
 # runs scaled by a copy kernel of known size (profiles named below); valid
 # only for the kernel source it was measured on, else reported as null.
 PGS_TRAFFIC = {
-    "batched": {"kernels_sha256_prefix": "", "bytes_per_launch": None,
+    "batched": {"kernels_sha256_prefix": "1c97d3337b9f040b", "bytes_per_launch": 76.37e9,
                 "profile": "profiles/k_pgs_env_batched256_hbm_traffic.md"},
     "bed": {"kernels_sha256_prefix": "", "bytes_per_launch": None,
             "profile": "profiles/k_pgs_bed50k_hbm_traffic.md"},
@@ -111,6 +111,46 @@ def roofline(tot, kernel, traffic_key):
             "algorithmic_bytes_per_launch": bpl, "launch_ms": ms, "kernel": kernel}
 
 
+def pgs_kernel_name(sc):
+    mode = sc.get_solver_config()["mode"]
+    return {"grouped": "k_pgs (grouped persistent colour-synchronous PGS)",
+            "spread": "k_pgs (spread: one env on all XCDs, colour-synchronous PGS)",
+            "per_env": "k_pgs_env (per-env persistent colour-synchronous PGS)"}[mode]
+
+
+# bulk properties of the aggregate in the timed macroscale step: the bed's
+# friction (tan phi_b = 0.7) and cohesion (2 kPa), a stiff bulk
+MACRO_PARAMS = dict(E_b=1e7, c_b=2000.0, mu_ab=0.4, mu_ac=0.7, cas_ab=1.0, cas_ac=0.001)
+
+
+def time_macro(sc, env=0, calls=10, equipment=None):
+    """Wall time of the macroscale step of env's zones on the state after the
+    timed steps (each call synchronises), and what it found."""
+    res = sc.macro_step(env, equipment=equipment, **MACRO_PARAMS)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        res = sc.macro_step(env, equipment=equipment, **MACRO_PARAMS)
+    ms = 1e3 * (time.perf_counter() - t0) / calls
+    if not res:
+        return dict(ms_per_call=ms, zones=0)
+    o = res[0]
+    out = dict(ms_per_call=ms, zones=len(res), n_cand=[int(k) for k in o["n_cand"]], n_points=list(o["n_points"]),
+               iterations=int(o["sweeps"]), aggregate_mass_kg=float(o["M"]), v_after=[float(k) for k in o["v"]],
+               force_on_tool_N=[float(k) for k in o["force"]])
+    if equipment:
+        out.update(tool_v_after=[float(k) for k in o["v_b"]], drive_impulse=[float(k) for k in o["lam_drive"]])
+    return out
+
+
+def bucket_equipment(body_id, speed):
+    """The excavation's 1.2 x 1.0 x 0.8 m bucket as a dynamic body: 1.5 t, a
+    box's inertia, driven at its dig speed with 60 kN and 20 kN m limits."""
+    m, a, b, c = 1500.0, 1.0, 1.2, 0.8
+    inertia = (m * (b * b + c * c) / 12.0, m * (a * a + c * c) / 12.0, m * (a * a + b * b) / 12.0, 0.0, 0.0, 0.0)
+    return [dict(body=body_id, mass=m, inertia=inertia, v_target=(speed, 0.0, 0.0), w_target=(0.0, 0.0, 0.0),
+                 f_max=6e4, t_max=2e4, gamma_drive=1e-6)]
+
+
 # ---------------------------------------------------------------------------
 # config 3: 256 batched beds (the headline)
 # ---------------------------------------------------------------------------
@@ -153,7 +193,7 @@ def leg_batched(args):
                sweeps=st[0]["sweeps"], schedule=sc.get_solver_config(),
                autotune_ms_per_step=tuned[1] if tuned else None,
                phase_ms_last_step={k: float(v) for k, v in ph.items()},
-               roofline=roofline(tot, "k_pgs_env (per-env persistent colour-synchronous PGS)", "batched"))
+               roofline=roofline(tot, pgs_kernel_name(sc), "batched"))
     sc.close()
     return out, specs
 
@@ -196,7 +236,8 @@ def leg_bed(args, n=50000, sweeps=150):
                phase_ms_last_step={k: float(v) for k, v in ph.items()}, blade_force_N=[float(x) for x in f],
                zone_particles=int(agg[0]["n_particles"]) if agg else 0,
                zone_mass_kg=float(agg[0]["M"]) if agg else 0.0,
-               roofline=roofline(tot, "k_pgs (grouped persistent colour-synchronous PGS)", "bed"))
+               macro_step=time_macro(sc),
+               roofline=roofline(tot, pgs_kernel_name(sc), "bed"))
     sc.close()
     return out
 
@@ -212,6 +253,8 @@ def leg_excavation(args, weights=None, n=500000, sweeps=200):
     parked = dict(bucket, pos=(-3.0, 0.0, lattice_top + 0.5), linvel=(0.0, 0.0, 0.0))
     spec = dict(spec, bodies=[floor, parked], warm_start="prev")
     sc = T.scene_from_specs(spec, cap_contacts=8 * n)
+    if args.schedule:
+        sc.set_solver_config(**json.loads(args.schedule))
     t0 = time.perf_counter()
     sc.step(args.settle_excavation, stats=False)
     settle_s = time.perf_counter() - t0
@@ -261,7 +304,9 @@ def leg_excavation(args, weights=None, n=500000, sweeps=200):
                phase_ms_last_step={k: float(v) for k, v in ph.items()}, bucket_force_N=[float(x) for x in f],
                zone_particles=int(agg[0]["n_particles"]) if agg else 0,
                zone_mass_kg=float(agg[0]["M"]) if agg else 0.0,
-               roofline=roofline(tot, "k_pgs (grouped persistent colour-synchronous PGS)", "bed"))
+               macro_step=time_macro(sc),
+               macro_step_driven_bucket=time_macro(sc, equipment=bucket_equipment(1, speed)),
+               roofline=roofline(tot, pgs_kernel_name(sc), "bed"))
     sc.close()
     return out
 
@@ -335,7 +380,7 @@ def learned_eval(args):
     t0 = time.perf_counter()
     feat, label = LN.gen_mixed_dataset(seed=100, cap=args.train_samples)
     tr = LN.Trainer(LN.init_weights(0, LN.input_scale(feat)), feat, LN.residual_targets(feat, label), batch=4096)
-    hist = tr.fit(epochs=args.epochs, lr=3e-3, lr_end=2e-4)
+    hist = tr.fit(epochs=args.epochs, lr=1e-3, lr_end=1e-4)
     w = tr.weights()
     res = {"training": dict(samples=len(feat), epochs=args.epochs, loss_first=hist[0], loss_last=hist[-1],
                             seconds=time.perf_counter() - t0)}
