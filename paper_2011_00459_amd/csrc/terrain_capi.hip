@@ -44,6 +44,7 @@ struct tr_scene {
     bool tables_dirty = true;
     bool have_prev = false;
     bool stepped = false;
+    bool slots_env_major = true;     // every env's spheres hold the slots [slot_begin, slot_begin + n)
     bool graph_events = false;        // the step graphs record the phase events themselves
     std::vector<std::pair<void*, size_t>> allocs;
     int64_t cells_alloc = 0;
@@ -683,6 +684,8 @@ int add_particles(tr_scene* s, int32_t env, int64_t n, const double* pos, const 
     int64_t id0 = (int64_t)env * s->desc.cap_particles + H.n;
     if (first_id) *first_id = id0;
     if (n == 0) return TR_OK;
+    for (int e2 = env + 1; e2 < s->desc.n_envs; ++e2)
+        if (s->envs[e2].n > 0) s->slots_env_major = false;  // appended behind a later env's spheres
     std::vector<float4> xr(n), vm(n), wi(n);
     std::vector<int> pid(n), id2s(n);
     std::vector<float> rho(n);
@@ -925,6 +928,7 @@ static int step_scene(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
         s->parity ^= 1;
         s->have_prev = true;
         s->stepped = true;
+        s->slots_env_major = true;  // the step's sort orders the slots by (env, cell, id)
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(s, e, "step launch");
@@ -1458,6 +1462,7 @@ int macro_step(tr_scene* s, int32_t env, const tr_macro_params* mp, int32_t n_eq
     memset(&a, 0, sizeof(a));
     a.n = (int)s->envs[env].n;
     a.id_base = E.id_base;
+    a.slot_begin = s->slots_env_major ? E.slot_begin : -1;
     a.shape_begin = E.shape_begin;
     a.shape_end = E.shape_end;
     a.mp = *mp;
@@ -1853,6 +1858,7 @@ int load_state(tr_scene* s, const void* buf, int64_t size)
     HIP_CHECK(s, hipMemcpy(s->body_host.data(), s->b.bodies, sizeof(BodyDev) * s->body_host.size(), hipMemcpyDeviceToHost));
     s->have_prev = h.have_prev != 0;
     s->stepped = h.stepped != 0;
+    s->slots_env_major = false;  // the snapshot's slot order is not recorded; the next step restores it
     return TR_OK;
 }
 

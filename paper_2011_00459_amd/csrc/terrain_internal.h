@@ -354,10 +354,13 @@ struct MacroZone {
     unsigned long long cnt[2];           // candidates of AB, AC
     unsigned long long vmax[2][4];       // order-preserving image of the largest projection along +-e1, +-e2
     unsigned long long kmin[2][4];       // smallest candidate key reaching it
+    double wpl[8][4];                    // the body's half-spaces in the world frame at its current pose
+    int nplanes;
 };
 struct MacroArgs {
     int n;                               // particles of the env (ids id_base .. id_base + n - 1)
     int id_base;
+    int slot_begin;                      // the env's spheres hold slots slot_begin .. + n - 1 (-1: unknown, go by id)
     int shape_begin, shape_end;          // the env's shapes
     int n_zones;                         // bodies with half-spaces, in body order
     int body[kMacroMaxZones];            // global body index of each

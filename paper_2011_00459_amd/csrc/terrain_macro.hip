@@ -110,17 +110,13 @@ __device__ inline ShapeDev posed_shape(const DevBuffers& b, int g)
 
 // the env's zone (index into MacroArgs) containing x: the first body (in the
 // env's zone order) whose half-spaces all contain it; -1 when none
-__device__ inline int zone_at(const DevBuffers& b, const MacroArgs& a, const double* x)
+__device__ inline int zone_at(const MacroArgs& a, const MacroZone* mz, const double* x)
 {
-#pragma clang fp contract(off)
     for (int z = 0; z < a.n_zones; ++z) {
-        const BodyDev& B = b.bodies[a.body[z]];
-        bool in = B.nplanes > 0;
-        for (int p = 0; p < B.nplanes && in; ++p) {
-            double nw[3], dw;
-            plane_world(B, p, nw, dw);
-            if (dot3d(nw, x) - dw > 0.0) in = false;
-        }
+        const MacroZone& Z = mz[z];
+        bool in = Z.nplanes > 0;
+        for (int p = 0; p < Z.nplanes && in; ++p)
+            if (dot3d(Z.wpl[p], x) - Z.wpl[p][3] > 0.0) in = false;
         if (in) return z;
     }
     return -1;
@@ -229,11 +225,11 @@ __global__ void __launch_bounds__(256) k_macro_pass1(DevBuffers b, StepParams p,
     double mom[kZoneMoments];
     for (int k = 0; k < kZoneMoments; ++k) mom[k] = 0.0;
     if (t < a.n) {
-        const int s = b.id2slot[a.id_base + t];
+        const int s = a.slot_begin >= 0 ? a.slot_begin + t : b.id2slot[a.id_base + t];
         const float4 xf = b.xr[s], vf = b.vm[s], wf = b.wi[s];
         x[0] = xf.x; x[1] = xf.y; x[2] = xf.z;
         r = xf.w;
-        z = zone_at(b, a, x);
+        z = zone_at(a, mz, x);
         if (z >= 0) {
             const double m = (double)b.rho[s] * (4.0 / 3.0) * kPi * r * r * r;
             const double v[3] = {vf.x, vf.y, vf.z};
@@ -285,17 +281,18 @@ __global__ void __launch_bounds__(256) k_macro_pass2(DevBuffers b, StepParams p,
 #pragma clang fp contract(off)
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.n) return;
-    const int s = b.id2slot[a.id_base + t];
+    const int s = a.slot_begin >= 0 ? a.slot_begin + t : b.id2slot[a.id_base + t];
     float4 xf = b.xr[s];
     double x[3] = {xf.x, xf.y, xf.z};
-    const int z = zone_at(b, a, x);
+    const int z = zone_at(a, mz, x);
     if (z < 0 || !a.eligible[z]) return;
+    const int id = a.slot_begin >= 0 ? b.pid[s] - a.id_base : t;
     MacroZone& Z = mz[z];
     for (int q = 0; q < 2; ++q) {
         double n[3], e1[3], e2[3], dfail;
         iface_normal(b, a, z, q, n, dfail);
         plane_axes(n, e1, e2);
-        candidates(b, p, a, z, q, t, x, (double)xf.w, [&](unsigned long long key, const double* pt) {
+        candidates(b, p, a, z, q, id, x, (double)xf.w, [&](unsigned long long key, const double* pt) {
             const double s1 = dot3d(pt, e1), s2 = dot3d(pt, e2);
             const double val[4] = {s1, -s1, s2, -s2};
             for (int d = 0; d < 4; ++d)
@@ -435,92 +432,6 @@ __device__ inline void point_D(const MacroSys& S, int c, double (*D)[12])
     }
 }
 
-// G(w) = w - w0 - M^-1 F(w), F the generalized impulse of every row at its
-// closed-form fixed point given w; and, when jac is not NULL, dG/dw
-// (ndof x ndof, row-major).
-__device__ inline void macro_residual(const MacroSys& S, const double* w0, const double* w, double* G, double* jac)
-{
-    const int nd = S.ndof;
-    double F[12];
-    for (int k = 0; k < 12; ++k) F[k] = 0.0;
-    double Sm[12][12];
-    if (jac)
-        for (int i = 0; i < 12; ++i)
-            for (int j = 0; j < 12; ++j) Sm[i][j] = 0.0;
-    for (int c = 0; c < S.np; ++c) {
-        double u[3], lam4[4], K[3][3], D[3][12], J[3];
-        point_vel(S, c, w, u);
-        point_impulse(u, S.n[c], S.gam[c], S.lo[c], S.mu[c], lam4, jac ? K : nullptr);
-        for (int k = 0; k < 3; ++k) J[k] = lam4[0] * S.n[c][k] + lam4[1 + k];
-        point_D(S, c, D);
-        for (int j = 0; j < nd; ++j) F[j] += (D[0][j] * J[0] + D[1][j] * J[1]) + D[2][j] * J[2];
-        if (!jac) continue;
-        double KD[3][12];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < nd; ++j) KD[i][j] = (K[i][0] * D[0][j] + K[i][1] * D[1][j]) + K[i][2] * D[2][j];
-        for (int i = 0; i < nd; ++i)
-            for (int j = 0; j < nd; ++j) Sm[i][j] += (D[0][i] * KD[0][j] + D[1][i] * KD[1][j]) + D[2][i] * KD[2][j];
-    }
-    if (nd == 12) {
-        for (int k = 0; k < 6; ++k) {
-            const double z = -(w[6 + k] - S.target[k]) / S.gd;
-            const double l = z > S.lim[k] ? S.lim[k] : (z < -S.lim[k] ? -S.lim[k] : z);
-            F[6 + k] += l;
-            if (jac && z < S.lim[k] && z > -S.lim[k]) Sm[6 + k][6 + k] -= 1.0 / S.gd;
-        }
-    }
-    // M^-1 blocks: aggregate (1/M, I^-1), equipment (1/M_B, I_B^-1)
-    double MF[12];
-    for (int k = 0; k < 3; ++k) MF[k] = S.invM * F[k];
-    mat3v(S.Iinv, F + 3, MF + 3);
-    if (nd == 12) {
-        for (int k = 0; k < 3; ++k) MF[6 + k] = S.invMB * F[6 + k];
-        mat3v(S.IBinv, F + 9, MF + 9);
-    }
-    for (int k = 0; k < nd; ++k) G[k] = w[k] - w0[k] - MF[k];
-    if (!jac) return;
-    for (int j = 0; j < nd; ++j) {
-        double col[12], mc[12];
-        for (int i = 0; i < nd; ++i) col[i] = Sm[i][j];
-        for (int k = 0; k < 3; ++k) mc[k] = S.invM * col[k];
-        mat3v(S.Iinv, col + 3, mc + 3);
-        if (nd == 12) {
-            for (int k = 0; k < 3; ++k) mc[6 + k] = S.invMB * col[6 + k];
-            mat3v(S.IBinv, col + 9, mc + 9);
-        }
-        for (int i = 0; i < nd; ++i) jac[i * nd + j] = (i == j ? 1.0 : 0.0) - mc[i];
-    }
-}
-
-// solves A x = b (n x n, row-major, overwritten) by Gaussian elimination with
-// partial pivoting; false when singular
-__device__ inline bool solve_n(double* A, double* b, int n)
-{
-    for (int k = 0; k < n; ++k) {
-        int piv = k;
-        for (int i = k + 1; i < n; ++i)
-            if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
-        if (!(fabs(A[piv * n + k]) > 0.0)) return false;
-        if (piv != k) {
-            for (int j = 0; j < n; ++j) {
-                double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t;
-            }
-            double t = b[k]; b[k] = b[piv]; b[piv] = t;
-        }
-        for (int i = k + 1; i < n; ++i) {
-            const double f = A[i * n + k] / A[k * n + k];
-            for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
-            b[i] -= f * b[k];
-        }
-    }
-    for (int i = n - 1; i >= 0; --i) {
-        double s = b[i];
-        for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * b[j];
-        b[i] = s / A[i * n + i];
-    }
-    return true;
-}
-
 // size of G in velocity units: linear parts and the angular parts times Lc
 __device__ inline double gnorm(const double* G, int nd, double Lc)
 {
@@ -532,308 +443,462 @@ __device__ inline double gnorm(const double* G, int nd, double Lc)
     return sqrt(s);
 }
 
-// Damped semismooth Newton on G(w) = 0 from w = w0; returns its iterations
-// and leaves the best w found in w.
-__device__ inline int macro_newton(const MacroSys& S, const double* w0, double Lc, double scale, double* w)
+// One zone's solve in LDS; one wave (64 lanes) per zone.
+struct SolveShared {
+    MacroSys S;
+    tr_macro_result o;
+    double w0[12], w[12], wt[12], G[12], Gt[12], d[12], F[12];
+    double Fp[8][12];              // generalized impulse of each point's rows
+    double Sp[8][144];             // D_c^T K_c D_c of each point (nd x nd, row-major)
+    double lamp[8][4];             // each point's impulses at the evaluated w
+    double Fd[6], Kd[6];           // drive impulses and their derivatives
+    double A[144];                 // Jacobian, then its LU factors
+    double Wn[8], Wt[8], lam[8][4];
+    double g, scale, Lc;
+    int piv, ok, run, map[8];
+};
+
+// G(w) = w - w0 - M^-1 F(w), F the generalized impulse of every row at its
+// closed-form fixed point given w, and with jac dG/dw into sh.A.  Lanes
+// 0 .. np-1 evaluate one point each, lanes 8 .. 13 the drive rows, then the
+// sums and the block inverse mass are spread over the lanes.  Every lane of
+// the wave calls it.
+__device__ void eval_G(SolveShared& sh, const double* w, double* G, bool jac)
 {
-    const int nd = S.ndof;
-    for (int k = 0; k < nd; ++k) w[k] = w0[k];
-    double G[12], A[144];
-    macro_residual(S, w0, w, G, A);
-    double g = gnorm(G, nd, Lc);
-    int it = 0;
-    for (; it < 100 && g > 1e-15 * scale; ++it) {
-        double d[12];
-        for (int k = 0; k < nd; ++k) d[k] = -G[k];
-        if (!solve_n(A, d, nd)) break;
-        double step = 1.0, wt[12], Gt[12];
-        bool took = false;
-        for (int ls = 0; ls < 40; ++ls, step *= 0.5) {
-            for (int k = 0; k < nd; ++k) wt[k] = w[k] + step * d[k];
-            macro_residual(S, w0, wt, Gt, nullptr);
-            const double gt = gnorm(Gt, nd, Lc);
-            if (gt < (1.0 - 1e-4 * step) * g) {
-                took = true;
-                g = gt;
-                break;
-            }
+    const int lane = threadIdx.x;
+    const MacroSys& S = sh.S;
+    const int nd = S.ndof, np = S.np;
+    if (lane < np) {
+        const int c = lane;
+        double u[3], lam4[4], K[3][3], D[3][12], J[3];
+        point_vel(S, c, w, u);
+        point_impulse(u, S.n[c], S.gam[c], S.lo[c], S.mu[c], lam4, jac ? K : nullptr);
+        for (int k = 0; k < 4; ++k) sh.lamp[c][k] = lam4[k];
+        for (int k = 0; k < 3; ++k) J[k] = lam4[0] * S.n[c][k] + lam4[1 + k];
+        point_D(S, c, D);
+        for (int j = 0; j < 12; ++j) sh.Fp[c][j] = (D[0][j] * J[0] + D[1][j] * J[1]) + D[2][j] * J[2];
+        if (jac) {
+            double KD[3][12];
+            for (int r = 0; r < 3; ++r)
+                for (int j = 0; j < 12; ++j) KD[r][j] = (K[r][0] * D[0][j] + K[r][1] * D[1][j]) + K[r][2] * D[2][j];
+            for (int i = 0; i < 12; ++i)
+                for (int j = 0; j < 12; ++j)
+                    if (i < nd && j < nd)
+                        sh.Sp[c][i * nd + j] = (D[0][i] * KD[0][j] + D[1][i] * KD[1][j]) + D[2][i] * KD[2][j];
         }
-        if (!took) break;
-        for (int k = 0; k < nd; ++k) w[k] = wt[k];
-        macro_residual(S, w0, w, G, A);
-        g = gnorm(G, nd, Lc);
+    } else if (nd == 12 && lane >= 8 && lane < 14) {
+        const int k = lane - 8;
+        const double zz = -(w[6 + k] - S.target[k]) / S.gd;
+        sh.Fd[k] = zz > S.lim[k] ? S.lim[k] : (zz < -S.lim[k] ? -S.lim[k] : zz);
+        sh.Kd[k] = (zz < S.lim[k] && zz > -S.lim[k]) ? -1.0 / S.gd : 0.0;
     }
-    return it;
+    __syncthreads();
+    if (lane < nd) {
+        double f = (nd == 12 && lane >= 6) ? sh.Fd[lane - 6] : 0.0;
+        for (int c = 0; c < np; ++c) f += sh.Fp[c][lane];
+        sh.F[lane] = f;
+    }
+    if (jac)
+        for (int t = 0; t < 3; ++t) {
+            const int e = lane + 64 * t;
+            if (e >= nd * nd) continue;
+            double v = 0.0;
+            for (int c = 0; c < np; ++c) v += sh.Sp[c][e];
+            const int i = e / nd, j = e % nd;
+            if (nd == 12 && i == j && i >= 6) v += sh.Kd[i - 6];
+            sh.A[e] = v;
+        }
+    __syncthreads();
+    if (lane < nd) {
+        const int blk = lane / 3, k = lane % 3;
+        double mf;
+        if (blk == 0) mf = S.invM * sh.F[lane];
+        else if (blk == 1) mf = (S.Iinv[k][0] * sh.F[3] + S.Iinv[k][1] * sh.F[4]) + S.Iinv[k][2] * sh.F[5];
+        else if (blk == 2) mf = S.invMB * sh.F[lane];
+        else mf = (S.IBinv[k][0] * sh.F[9] + S.IBinv[k][1] * sh.F[10]) + S.IBinv[k][2] * sh.F[11];
+        G[lane] = w[lane] - sh.w0[lane] - mf;
+    }
+    if (jac) {
+        double jv[3];
+        for (int t = 0; t < 3; ++t) {
+            const int e = lane + 64 * t;
+            jv[t] = 0.0;
+            if (e >= nd * nd) continue;
+            const int i = e / nd, j = e % nd, blk = i / 3, k = i % 3;
+            double ms;
+            if (blk == 0) ms = S.invM * sh.A[e];
+            else if (blk == 1)
+                ms = (S.Iinv[k][0] * sh.A[3 * nd + j] + S.Iinv[k][1] * sh.A[4 * nd + j]) + S.Iinv[k][2] * sh.A[5 * nd + j];
+            else if (blk == 2) ms = S.invMB * sh.A[e];
+            else
+                ms = (S.IBinv[k][0] * sh.A[9 * nd + j] + S.IBinv[k][1] * sh.A[10 * nd + j]) +
+                     S.IBinv[k][2] * sh.A[11 * nd + j];
+            jv[t] = (i == j ? 1.0 : 0.0) - ms;
+        }
+        __syncthreads();  // every lane has read the summed S before it becomes the Jacobian
+        for (int t = 0; t < 3; ++t) {
+            const int e = lane + 64 * t;
+            if (e < nd * nd) sh.A[e] = jv[t];
+        }
+    }
+    __syncthreads();
 }
 
-__global__ void __launch_bounds__(64) k_macro_solve(DevBuffers b, StepParams p, MacroArgs a, MacroZone* mz, tr_macro_result* out)
+// solves sh.A x = sh.d (nd x nd) in place by Gaussian elimination with partial
+// pivoting, a row per lane; false (on every lane) when singular
+__device__ bool lu_solve(SolveShared& sh, int nd)
 {
-#pragma clang fp contract(off)
-    const int z = blockIdx.x * blockDim.x + threadIdx.x;
-    if (z >= a.n_zones) return;
+    const int lane = threadIdx.x;
+    for (int k = 0; k < nd; ++k) {
+        if (lane == 0) {
+            int piv = k;
+            double best = fabs(sh.A[k * nd + k]);
+            for (int i = k + 1; i < nd; ++i) {
+                const double v = fabs(sh.A[i * nd + k]);
+                if (v > best) { best = v; piv = i; }
+            }
+            sh.piv = best > 0.0 ? piv : -1;
+        }
+        __syncthreads();
+        const int piv = sh.piv;
+        if (piv < 0) return false;
+        if (piv != k) {
+            if (lane < nd) {
+                const double t = sh.A[k * nd + lane];
+                sh.A[k * nd + lane] = sh.A[piv * nd + lane];
+                sh.A[piv * nd + lane] = t;
+            }
+            if (lane == 0) {
+                const double t = sh.d[k];
+                sh.d[k] = sh.d[piv];
+                sh.d[piv] = t;
+            }
+        }
+        __syncthreads();
+        if (lane > k && lane < nd) {
+            const double f = sh.A[lane * nd + k] / sh.A[k * nd + k];
+            for (int j = k; j < nd; ++j) sh.A[lane * nd + j] -= f * sh.A[k * nd + j];
+            sh.d[lane] -= f * sh.d[k];
+        }
+        __syncthreads();
+    }
+    if (lane == 0)
+        for (int i = nd - 1; i >= 0; --i) {
+            double s = sh.d[i];
+            for (int j = i + 1; j < nd; ++j) s -= sh.A[i * nd + j] * sh.d[j];
+            sh.d[i] = s / sh.A[i * nd + i];
+        }
+    __syncthreads();
+    return true;
+}
+
+// one wave per zone (grid = zones, 64 threads)
+__global__ void __launch_bounds__(64) k_macro_solve(DevBuffers b, StepParams p, MacroArgs a, MacroZone* mz,
+                                                    tr_macro_result* out)
+{
+    __shared__ SolveShared sh;
+    const int z = blockIdx.x, lane = threadIdx.x;
     const MacroZone& Z = mz[z];
     const BodyDev& B = b.bodies[a.body[z]];
-    tr_macro_result o;
-    memset(&o, 0, sizeof(o));
-    o.zone = B.user_id;
-    const double* S = Z.mom;
-    const double M = S[0];
-    o.M = M;
-    if (!(M > 0.0) || !a.eligible[z]) {
-        out[z] = o;
-        return;
-    }
-    // the aggregate (Eqs. aggregate_mass .. aggregate_rot_vel, read R14)
-    double xA[3] = {S[1] / M, S[2] / M, S[3] / M}, vA[3] = {S[4] / M, S[5] / M, S[6] / M};
-    double Cxx = S[7] - M * xA[0] * xA[0], Cyy = S[8] - M * xA[1] * xA[1], Czz = S[9] - M * xA[2] * xA[2];
-    double Cxy = S[10] - M * xA[0] * xA[1], Cxz = S[11] - M * xA[0] * xA[2], Cyz = S[12] - M * xA[1] * xA[2];
-    double tr = Cxx + Cyy + Czz;
-    double I[3][3] = {{S[16] + tr - Cxx, -Cxy, -Cxz}, {-Cxy, S[16] + tr - Cyy, -Cyz}, {-Cxz, -Cyz, S[16] + tr - Czz}};
-    double L[3] = {S[13] - (xA[1] * S[6] - xA[2] * S[5]) + S[17], S[14] - (xA[2] * S[4] - xA[0] * S[6]) + S[18],
-                   S[15] - (xA[0] * S[5] - xA[1] * S[4]) + S[19]};
-    double c00 = I[1][1] * I[2][2] - I[1][2] * I[2][1], c01 = I[1][2] * I[2][0] - I[1][0] * I[2][2];
-    double c02 = I[1][0] * I[2][1] - I[1][1] * I[2][0];
-    double det = I[0][0] * c00 + I[0][1] * c01 + I[0][2] * c02;
-    double Iinv[3][3];
-    Iinv[0][0] = c00 / det; Iinv[1][0] = c01 / det; Iinv[2][0] = c02 / det;
-    Iinv[0][1] = (I[0][2] * I[2][1] - I[0][1] * I[2][2]) / det;
-    Iinv[1][1] = (I[0][0] * I[2][2] - I[0][2] * I[2][0]) / det;
-    Iinv[2][1] = (I[0][1] * I[2][0] - I[0][0] * I[2][1]) / det;
-    Iinv[0][2] = (I[0][1] * I[1][2] - I[0][2] * I[1][1]) / det;
-    Iinv[1][2] = (I[0][2] * I[1][0] - I[0][0] * I[1][2]) / det;
-    Iinv[2][2] = (I[0][0] * I[1][1] - I[0][1] * I[1][0]) / det;
-    double wA[3];
-    for (int k = 0; k < 3; ++k) wA[k] = (Iinv[k][0] * L[0] + Iinv[k][1] * L[1]) + Iinv[k][2] * L[2];
-    for (int k = 0; k < 3; ++k) { o.x[k] = xA[k]; o.v0[k] = vA[k]; o.w0[k] = wA[k]; }
-    const double invM = 1.0 / M;
-    const double Lc = cbrt(Z.vol);
-    // the reduced points of each interface: +e1, -e1, +e2, -e2, each kept once
-    int np = 0, map[8];
-    for (int q = 0; q < 2; ++q) {
-        o.n_cand[q] = (int64_t)Z.cnt[q];
-        o.area[q] = Z.area[q];
-        o.gamma[q] = Z.area[q] > 0.0 ? Lc / ((q == 0 ? a.mp.cas_ab : a.mp.cas_ac) * a.mp.E_b * Z.area[q] * (double)p.dt_d * (double)p.dt_d) : 0.0;
-        if (Z.cnt[q] == 0) continue;
-        double n[3], dfail;
-        iface_normal(b, a, z, q, n, dfail);
-        int m = 0;
-        unsigned long long chosen[4];
-        for (int d = 0; d < 4; ++d) {
-            bool dup = false;
-            for (int j = 0; j < m; ++j) dup |= chosen[j] == Z.kmin[q][d];
-            if (dup) continue;
-            chosen[m] = Z.kmin[q][d];
-            key_point(b, p, a, z, q, chosen[m], o.p[4 * q + m]);
-            for (int k = 0; k < 3; ++k) o.n[4 * q + m][k] = n[k];
-            o.src[4 * q + m] = (int64_t)(chosen[m] >> 16);
-            map[np++] = 4 * q + m;
-            ++m;
-        }
-        o.n_points[q] = m;
-    }
-    // Eq. mdb:eqAgg in impulse form with the rows of Eqs. aggregateNormal and
-    // aggregateTangent; with a dynamic equipment (Eq. mdb:eqEq) its body and
-    // drive rows join the system
     const double dt = p.dt_d;
     const tr_macro_equipment* E = a.has_eq[z] ? &a.eq[z] : nullptr;
-    MacroSys Q;
-    Q.np = np;
-    Q.ndof = E ? 12 : 6;
-    Q.invM = invM;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) { Q.Iinv[i][j] = Iinv[i][j]; Q.IBinv[i][j] = 0.0; }
-    Q.invMB = 0.0;
-    Q.gd = 1.0;
-    double w0[12];
-    for (int k = 0; k < 3; ++k) { w0[k] = vA[k] + dt * a.g[k]; w0[3 + k] = wA[k]; }
-    for (int k = 0; k < 3; ++k) { w0[6 + k] = B.linvel[k]; w0[9 + k] = B.angvel[k]; }
-    if (E) {
-        Q.invMB = 1.0 / E->mass;
-        double R[9], Iw[3][3];
-        quat_to_R(B.quat, R);
-        const double* J6 = E->inertia;
-        const double Ib[3][3] = {{J6[0], J6[3], J6[4]}, {J6[3], J6[1], J6[5]}, {J6[4], J6[5], J6[2]}};
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                double acc = 0.0;
-                for (int k = 0; k < 3; ++k)
-                    for (int l = 0; l < 3; ++l) acc += R[i * 3 + k] * Ib[k][l] * R[j * 3 + l];
-                Iw[i][j] = acc;
-            }
-        inv3(Iw, Q.IBinv);
-        for (int k = 0; k < 3; ++k) {
-            w0[6 + k] = B.linvel[k] + dt * a.g[k];
-            Q.target[k] = E->v_target[k];
-            Q.target[3 + k] = E->w_target[k];
-            Q.lim[k] = E->f_max * dt;
-            Q.lim[3 + k] = E->t_max * dt;
-        }
-        Q.gd = E->gamma_drive;
-    }
-    double Wn[8], Wt[8], lam[8][4];
-    for (int c = 0; c < np; ++c) {
-        const int k8 = map[c], q = k8 / 4;
-        Q.onB[c] = q == 0 && E != nullptr;
-        for (int k = 0; k < 3; ++k) {
-            Q.rr[c][k] = o.p[k8][k] - xA[k];
-            Q.rb[c][k] = o.p[k8][k] - B.pos[k];
-            Q.n[c][k] = o.n[k8][k];
-            Q.uo[c][k] = 0.0;
-        }
-        if (q == 0 && !E) {
-            double t[3];
-            cross3d(B.angvel, Q.rb[c], t);
-            for (int k = 0; k < 3; ++k) Q.uo[c][k] = B.linvel[k] + t[k];
-        }
-        double t1[3], t2[3];
-        plane_axes(o.n[k8], t1, t2);
-        Wn[c] = point_w(invM, Iinv, Q.rr[c], o.n[k8], o.n[k8]);
-        Wt[c] = 0.5 * (point_w(invM, Iinv, Q.rr[c], t1, t1) + point_w(invM, Iinv, Q.rr[c], t2, t2));
-        if (Q.onB[c]) {
-            Wn[c] += point_w(Q.invMB, Q.IBinv, Q.rb[c], o.n[k8], o.n[k8]);
-            Wt[c] += 0.5 * (point_w(Q.invMB, Q.IBinv, Q.rb[c], t1, t1) + point_w(Q.invMB, Q.IBinv, Q.rb[c], t2, t2));
-        }
-        Q.lo[c] = -a.mp.c_b * o.area[q] * dt / (double)o.n_points[q];
-        Q.mu[c] = q == 0 ? a.mp.mu_ab : a.mp.mu_ac;
-        Q.gam[c] = o.gamma[q];
-    }
-    // the fixed point of the rows directly: Newton on the bodies' velocities
-    // (six, or twelve with a dynamic equipment) with each row's impulse in
-    // closed form, then the rows' projected Gauss-Seidel from there until no
-    // impulse changes (one or two sweeps when Newton converged, else it
-    // finishes the solve)
-    double scale = dt * sqrt(dot3d(a.g, a.g)) + 1e-300;
-    for (int k = 0; k < Q.ndof; ++k) scale += (k % 6) < 3 ? fabs(w0[k]) : Lc * fabs(w0[k]);
-    double wn[12];
-    const int newton_its = macro_newton(Q, w0, Lc, scale, wn);
-    double vv[3], ww[3], vB[3], wB[3], ld[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     {
-        double F[12];
-        for (int k = 0; k < 12; ++k) F[k] = 0.0;
-        for (int c = 0; c < np; ++c) {
-            double u[3], D[3][12], J[3];
-            point_vel(Q, c, wn, u);
-            point_impulse(u, Q.n[c], Q.gam[c], Q.lo[c], Q.mu[c], lam[c], nullptr);
-            for (int k = 0; k < 3; ++k) J[k] = lam[c][0] * Q.n[c][k] + lam[c][1 + k];
-            point_D(Q, c, D);
-            for (int j = 0; j < Q.ndof; ++j) F[j] += (D[0][j] * J[0] + D[1][j] * J[1]) + D[2][j] * J[2];
-        }
-        if (E)
-            for (int k = 0; k < 6; ++k) {
-                const double zz = -(wn[6 + k] - Q.target[k]) / Q.gd;
-                ld[k] = zz > Q.lim[k] ? Q.lim[k] : (zz < -Q.lim[k] ? -Q.lim[k] : zz);
-                F[6 + k] += ld[k];
-            }
-        double t[3];
-        mat3v(Q.Iinv, F + 3, t);
-        for (int k = 0; k < 3; ++k) { vv[k] = w0[k] + invM * F[k]; ww[k] = w0[3 + k] + t[k]; }
-        if (E) {
-            mat3v(Q.IBinv, F + 9, t);
-            for (int k = 0; k < 3; ++k) { vB[k] = w0[6 + k] + Q.invMB * F[6 + k]; wB[k] = w0[9 + k] + t[k]; }
-        } else {
-            for (int k = 0; k < 3; ++k) { vB[k] = B.linvel[k]; wB[k] = B.angvel[k]; }
-        }
+        unsigned long long* ow = reinterpret_cast<unsigned long long*>(&sh.o);
+        for (int k = lane; k < (int)(sizeof(tr_macro_result) / 8); k += 64) ow[k] = 0ull;
     }
-    int sweep = 0;
-    for (; sweep < 200000; ++sweep) {
-        double dmax = 0.0, lmax = 0.0;
-        for (int c = 0; c < np; ++c) {
-            const double* nn = Q.n[c];
-            for (int row = 0; row < 2; ++row) {
-                double u[3], t[3], J[3];
-                cross3d(ww, Q.rr[c], t);
-                for (int k = 0; k < 3; ++k) u[k] = vv[k] + t[k] - Q.uo[c][k];
+    __syncthreads();
+    if (lane == 0) {
+        tr_macro_result& o = sh.o;
+        o.zone = B.user_id;
+        const double* S = Z.mom;
+        const double M = S[0];
+        o.M = M;
+        sh.run = (M > 0.0) && a.eligible[z];
+        if (sh.run) {
+            // the aggregate (Eqs. aggregate_mass .. aggregate_rot_vel, read R14)
+            double xA[3] = {S[1] / M, S[2] / M, S[3] / M}, vA[3] = {S[4] / M, S[5] / M, S[6] / M};
+            double Cxx = S[7] - M * xA[0] * xA[0], Cyy = S[8] - M * xA[1] * xA[1], Czz = S[9] - M * xA[2] * xA[2];
+            double Cxy = S[10] - M * xA[0] * xA[1], Cxz = S[11] - M * xA[0] * xA[2], Cyz = S[12] - M * xA[1] * xA[2];
+            double tr = Cxx + Cyy + Czz;
+            double I[3][3] = {{S[16] + tr - Cxx, -Cxy, -Cxz}, {-Cxy, S[16] + tr - Cyy, -Cyz},
+                              {-Cxz, -Cyz, S[16] + tr - Czz}};
+            double L[3] = {S[13] - (xA[1] * S[6] - xA[2] * S[5]) + S[17], S[14] - (xA[2] * S[4] - xA[0] * S[6]) + S[18],
+                           S[15] - (xA[0] * S[5] - xA[1] * S[4]) + S[19]};
+            MacroSys& Q = sh.S;
+            inv3(I, Q.Iinv);
+            double wA[3];
+            mat3v(Q.Iinv, L, wA);
+            for (int k = 0; k < 3; ++k) { o.x[k] = xA[k]; o.v0[k] = vA[k]; o.w0[k] = wA[k]; }
+            Q.invM = 1.0 / M;
+            sh.Lc = cbrt(Z.vol);
+            // the reduced points of each interface: +e1, -e1, +e2, -e2, each kept once
+            int np = 0;
+            for (int q = 0; q < 2; ++q) {
+                o.n_cand[q] = (int64_t)Z.cnt[q];
+                o.area[q] = Z.area[q];
+                o.gamma[q] = Z.area[q] > 0.0 ? sh.Lc / ((q == 0 ? a.mp.cas_ab : a.mp.cas_ac) * a.mp.E_b * Z.area[q] *
+                                                       dt * dt)
+                                             : 0.0;
+                if (Z.cnt[q] == 0) continue;
+                double n[3], dfail;
+                iface_normal(b, a, z, q, n, dfail);
+                int m = 0;
+                unsigned long long chosen[4];
+                for (int d = 0; d < 4; ++d) {
+                    bool dup = false;
+                    for (int j = 0; j < m; ++j) dup |= chosen[j] == Z.kmin[q][d];
+                    if (dup) continue;
+                    chosen[m] = Z.kmin[q][d];
+                    key_point(b, p, a, z, q, chosen[m], o.p[4 * q + m]);
+                    for (int k = 0; k < 3; ++k) o.n[4 * q + m][k] = n[k];
+                    o.src[4 * q + m] = (int64_t)(chosen[m] >> 16);
+                    sh.map[np++] = 4 * q + m;
+                    ++m;
+                }
+                o.n_points[q] = m;
+            }
+            // Eq. mdb:eqAgg in impulse form with the rows of Eqs. aggregateNormal
+            // and aggregateTangent; with a dynamic equipment (Eq. mdb:eqEq) its
+            // body and drive rows join the system
+            Q.np = np;
+            Q.ndof = E ? 12 : 6;
+            Q.invMB = 0.0;
+            Q.gd = 1.0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) Q.IBinv[i][j] = 0.0;
+            for (int k = 0; k < 6; ++k) { Q.target[k] = 0.0; Q.lim[k] = 0.0; }
+            for (int k = 0; k < 3; ++k) {
+                sh.w0[k] = vA[k] + dt * a.g[k];
+                sh.w0[3 + k] = wA[k];
+                sh.w0[6 + k] = B.linvel[k];
+                sh.w0[9 + k] = B.angvel[k];
+            }
+            if (E) {
+                Q.invMB = 1.0 / E->mass;
+                double R[9], Iw[3][3];
+                quat_to_R(B.quat, R);
+                const double* J6 = E->inertia;
+                const double Ib[3][3] = {{J6[0], J6[3], J6[4]}, {J6[3], J6[1], J6[5]}, {J6[4], J6[5], J6[2]}};
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        double acc = 0.0;
+                        for (int k = 0; k < 3; ++k)
+                            for (int l = 0; l < 3; ++l) acc += R[i * 3 + k] * Ib[k][l] * R[j * 3 + l];
+                        Iw[i][j] = acc;
+                    }
+                inv3(Iw, Q.IBinv);
+                for (int k = 0; k < 3; ++k) {
+                    sh.w0[6 + k] = B.linvel[k] + dt * a.g[k];
+                    Q.target[k] = E->v_target[k];
+                    Q.target[3 + k] = E->w_target[k];
+                    Q.lim[k] = E->f_max * dt;
+                    Q.lim[3 + k] = E->t_max * dt;
+                }
+                Q.gd = E->gamma_drive;
+            }
+            for (int c = 0; c < np; ++c) {
+                const int k8 = sh.map[c], q = k8 / 4;
+                Q.onB[c] = q == 0 && E != nullptr;
+                for (int k = 0; k < 3; ++k) {
+                    Q.rr[c][k] = o.p[k8][k] - xA[k];
+                    Q.rb[c][k] = o.p[k8][k] - B.pos[k];
+                    Q.n[c][k] = o.n[k8][k];
+                    Q.uo[c][k] = 0.0;
+                }
+                if (q == 0 && !E) {
+                    double t[3];
+                    cross3d(B.angvel, Q.rb[c], t);
+                    for (int k = 0; k < 3; ++k) Q.uo[c][k] = B.linvel[k] + t[k];
+                }
+                double t1[3], t2[3];
+                plane_axes(o.n[k8], t1, t2);
+                sh.Wn[c] = point_w(Q.invM, Q.Iinv, Q.rr[c], o.n[k8], o.n[k8]);
+                sh.Wt[c] = 0.5 * (point_w(Q.invM, Q.Iinv, Q.rr[c], t1, t1) + point_w(Q.invM, Q.Iinv, Q.rr[c], t2, t2));
                 if (Q.onB[c]) {
-                    cross3d(wB, Q.rb[c], t);
-                    for (int k = 0; k < 3; ++k) u[k] -= vB[k] + t[k];
+                    sh.Wn[c] += point_w(Q.invMB, Q.IBinv, Q.rb[c], o.n[k8], o.n[k8]);
+                    sh.Wt[c] += 0.5 * (point_w(Q.invMB, Q.IBinv, Q.rb[c], t1, t1) +
+                                       point_w(Q.invMB, Q.IBinv, Q.rb[c], t2, t2));
                 }
-                const double un = dot3d(nn, u);
-                if (row == 0) {
-                    double ln = lam[c][0] - (un + Q.gam[c] * lam[c][0]) / (Wn[c] + Q.gam[c]);
-                    if (ln < Q.lo[c]) ln = Q.lo[c];
-                    const double d = ln - lam[c][0];
-                    lam[c][0] = ln;
-                    for (int k = 0; k < 3; ++k) J[k] = d * nn[k];
-                    if (fabs(d) > dmax) dmax = fabs(d);
-                } else {
-                    double lt[3];
-                    for (int k = 0; k < 3; ++k) {
-                        const double ut = u[k] - un * nn[k];
-                        lt[k] = lam[c][1 + k] - (ut + Q.gam[c] * lam[c][1 + k]) / (Wt[c] + Q.gam[c]);
-                    }
-                    const double ltn = dot3d(lt, nn);
-                    for (int k = 0; k < 3; ++k) lt[k] -= ltn * nn[k];
-                    const double lim = Q.mu[c] * fabs(lam[c][0]);
-                    const double m2 = sqrt(dot3d(lt, lt));
-                    if (m2 > lim) {
-                        const double sc = m2 > 0.0 ? lim / m2 : 0.0;
-                        for (int k = 0; k < 3; ++k) lt[k] *= sc;
-                    }
-                    for (int k = 0; k < 3; ++k) {
-                        J[k] = lt[k] - lam[c][1 + k];
-                        if (fabs(J[k]) > dmax) dmax = fabs(J[k]);
-                        lam[c][1 + k] = lt[k];
-                    }
+                Q.lo[c] = -a.mp.c_b * o.area[q] * dt / (double)o.n_points[q];
+                Q.mu[c] = q == 0 ? a.mp.mu_ab : a.mp.mu_ac;
+                Q.gam[c] = o.gamma[q];
+            }
+            double scale = dt * sqrt(dot3d(a.g, a.g)) + 1e-300;
+            for (int k = 0; k < Q.ndof; ++k) scale += (k % 6) < 3 ? fabs(sh.w0[k]) : sh.Lc * fabs(sh.w0[k]);
+            sh.scale = scale;
+        }
+    }
+    __syncthreads();
+    if (sh.run) {
+        // the fixed point of the rows directly: damped semismooth Newton on the
+        // bodies' velocities (six, or twelve with a dynamic equipment) with each
+        // row's impulse in closed form, then the rows' projected Gauss-Seidel
+        // from there until no impulse changes (one or two sweeps when Newton
+        // converged, else it finishes the solve)
+        const int nd = sh.S.ndof, np = sh.S.np;
+        if (lane < nd) sh.w[lane] = sh.w0[lane];
+        __syncthreads();
+        eval_G(sh, sh.w, sh.G, true);
+        if (lane == 0) sh.g = gnorm(sh.G, nd, sh.Lc);
+        __syncthreads();
+        int its = 0;
+        for (; its < 100; ++its) {
+            if (!(sh.g > 1e-15 * sh.scale)) break;
+            if (lane < nd) sh.d[lane] = -sh.G[lane];
+            __syncthreads();
+            if (!lu_solve(sh, nd)) break;
+            double step = 1.0;
+            bool took = false;
+            for (int ls = 0; ls < 40; ++ls, step *= 0.5) {
+                if (lane < nd) sh.wt[lane] = sh.w[lane] + step * sh.d[lane];
+                __syncthreads();
+                eval_G(sh, sh.wt, sh.Gt, false);
+                if (lane == 0) {
+                    const double gt = gnorm(sh.Gt, nd, sh.Lc);
+                    sh.ok = gt < (1.0 - 1e-4 * step) * sh.g;
+                    if (sh.ok) sh.g = gt;
                 }
-                double tj[3], dw[3];
-                cross3d(Q.rr[c], J, tj);
-                mat3v(Iinv, tj, dw);
-                for (int k = 0; k < 3; ++k) { vv[k] += invM * J[k]; ww[k] += dw[k]; }
-                if (Q.onB[c]) {
-                    cross3d(Q.rb[c], J, tj);
-                    mat3v(Q.IBinv, tj, dw);
-                    for (int k = 0; k < 3; ++k) { vB[k] -= Q.invMB * J[k]; wB[k] -= dw[k]; }
+                __syncthreads();
+                if (sh.ok) {
+                    took = true;
+                    break;
                 }
             }
-            for (int k = 0; k < 4; ++k)
-                if (fabs(lam[c][k]) > lmax) lmax = fabs(lam[c][k]);
+            if (!took) break;
+            if (lane < nd) sh.w[lane] = sh.wt[lane];
+            __syncthreads();
+            eval_G(sh, sh.w, sh.G, true);
+            if (lane == 0) sh.g = gnorm(sh.G, nd, sh.Lc);
+            __syncthreads();
         }
-        if (E) {
-            for (int k = 0; k < 6; ++k) {
-                const int ax = k % 3;
-                const double u = k < 3 ? vB[ax] - Q.target[k] : wB[ax] - Q.target[k];
-                const double W = k < 3 ? Q.invMB : Q.IBinv[ax][ax];
-                double l = ld[k] - (u + Q.gd * ld[k]) / (W + Q.gd);
-                if (l > Q.lim[k]) l = Q.lim[k];
-                if (l < -Q.lim[k]) l = -Q.lim[k];
-                const double d = l - ld[k];
-                ld[k] = l;
-                if (k < 3) vB[ax] += Q.invMB * d;
-                else
-                    for (int j = 0; j < 3; ++j) wB[j] += Q.IBinv[j][ax] * d;
-                if (fabs(d) > dmax) dmax = fabs(d);
-                if (fabs(l) > lmax) lmax = fabs(l);
+        // the impulses and velocities at the Newton point (the last evaluation
+        // may have been a rejected trial)
+        eval_G(sh, sh.w, sh.G, false);
+        if (lane == 0) {
+            const MacroSys& Q = sh.S;
+            tr_macro_result& o = sh.o;
+            for (int c = 0; c < np; ++c)
+                for (int k = 0; k < 4; ++k) sh.lam[c][k] = sh.lamp[c][k];
+            double vv[3], ww[3], vB[3], wB[3], ld[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, t[3];
+            if (E)
+                for (int k = 0; k < 6; ++k) ld[k] = sh.Fd[k];
+            mat3v(Q.Iinv, sh.F + 3, t);
+            for (int k = 0; k < 3; ++k) { vv[k] = sh.w0[k] + Q.invM * sh.F[k]; ww[k] = sh.w0[3 + k] + t[k]; }
+            if (E) {
+                mat3v(Q.IBinv, sh.F + 9, t);
+                for (int k = 0; k < 3; ++k) { vB[k] = sh.w0[6 + k] + Q.invMB * sh.F[6 + k]; wB[k] = sh.w0[9 + k] + t[k]; }
+            } else {
+                for (int k = 0; k < 3; ++k) { vB[k] = B.linvel[k]; wB[k] = B.angvel[k]; }
+            }
+            int sweep = 0;
+            for (; sweep < 200000; ++sweep) {
+                double dmax = 0.0, lmax = 0.0;
+                for (int c = 0; c < np; ++c) {
+                    const double* nn = Q.n[c];
+                    for (int row = 0; row < 2; ++row) {
+                        double u[3], J[3];
+                        cross3d(ww, Q.rr[c], t);
+                        for (int k = 0; k < 3; ++k) u[k] = vv[k] + t[k] - Q.uo[c][k];
+                        if (Q.onB[c]) {
+                            cross3d(wB, Q.rb[c], t);
+                            for (int k = 0; k < 3; ++k) u[k] -= vB[k] + t[k];
+                        }
+                        const double un = dot3d(nn, u);
+                        if (row == 0) {
+                            double ln = sh.lam[c][0] - (un + Q.gam[c] * sh.lam[c][0]) / (sh.Wn[c] + Q.gam[c]);
+                            if (ln < Q.lo[c]) ln = Q.lo[c];
+                            const double d = ln - sh.lam[c][0];
+                            sh.lam[c][0] = ln;
+                            for (int k = 0; k < 3; ++k) J[k] = d * nn[k];
+                            if (fabs(d) > dmax) dmax = fabs(d);
+                        } else {
+                            double lt[3];
+                            for (int k = 0; k < 3; ++k) {
+                                const double ut = u[k] - un * nn[k];
+                                lt[k] = sh.lam[c][1 + k] - (ut + Q.gam[c] * sh.lam[c][1 + k]) / (sh.Wt[c] + Q.gam[c]);
+                            }
+                            const double ltn = dot3d(lt, nn);
+                            for (int k = 0; k < 3; ++k) lt[k] -= ltn * nn[k];
+                            const double lim = Q.mu[c] * fabs(sh.lam[c][0]);
+                            const double m2 = sqrt(dot3d(lt, lt));
+                            if (m2 > lim) {
+                                const double sc = m2 > 0.0 ? lim / m2 : 0.0;
+                                for (int k = 0; k < 3; ++k) lt[k] *= sc;
+                            }
+                            for (int k = 0; k < 3; ++k) {
+                                J[k] = lt[k] - sh.lam[c][1 + k];
+                                if (fabs(J[k]) > dmax) dmax = fabs(J[k]);
+                                sh.lam[c][1 + k] = lt[k];
+                            }
+                        }
+                        double tj[3], dw[3];
+                        cross3d(Q.rr[c], J, tj);
+                        mat3v(Q.Iinv, tj, dw);
+                        for (int k = 0; k < 3; ++k) { vv[k] += Q.invM * J[k]; ww[k] += dw[k]; }
+                        if (Q.onB[c]) {
+                            cross3d(Q.rb[c], J, tj);
+                            mat3v(Q.IBinv, tj, dw);
+                            for (int k = 0; k < 3; ++k) { vB[k] -= Q.invMB * J[k]; wB[k] -= dw[k]; }
+                        }
+                    }
+                    for (int k = 0; k < 4; ++k)
+                        if (fabs(sh.lam[c][k]) > lmax) lmax = fabs(sh.lam[c][k]);
+                }
+                if (E) {
+                    for (int k = 0; k < 6; ++k) {
+                        const int ax = k % 3;
+                        const double u = k < 3 ? vB[ax] - Q.target[k] : wB[ax] - Q.target[k];
+                        const double W = k < 3 ? Q.invMB : Q.IBinv[ax][ax];
+                        double l = ld[k] - (u + Q.gd * ld[k]) / (W + Q.gd);
+                        if (l > Q.lim[k]) l = Q.lim[k];
+                        if (l < -Q.lim[k]) l = -Q.lim[k];
+                        const double d = l - ld[k];
+                        ld[k] = l;
+                        if (k < 3) vB[ax] += Q.invMB * d;
+                        else
+                            for (int j = 0; j < 3; ++j) wB[j] += Q.IBinv[j][ax] * d;
+                        if (fabs(d) > dmax) dmax = fabs(d);
+                        if (fabs(l) > lmax) lmax = fabs(l);
+                    }
+                }
+                if (dmax <= 1e-15 * lmax || lmax == 0.0) {
+                    ++sweep;
+                    break;
+                }
+            }
+            o.sweeps = its + sweep;
+            for (int k = 0; k < 3; ++k) {
+                o.v[k] = vv[k]; o.w[k] = ww[k]; o.force[k] = 0.0; o.torque[k] = 0.0;
+                o.v_b[k] = vB[k]; o.w_b[k] = wB[k];
+            }
+            for (int k = 0; k < 6; ++k) o.lam_drive[k] = ld[k];
+            for (int c = 0; c < np; ++c) {
+                const int k8 = sh.map[c];
+                for (int k = 0; k < 4; ++k) o.lam[k8][k] = sh.lam[c][k];
+                if (k8 >= 4) continue;
+                double J[3];
+                for (int k = 0; k < 3; ++k) J[k] = sh.lam[c][0] * Q.n[c][k] + sh.lam[c][1 + k];
+                for (int k = 0; k < 3; ++k) o.force[k] -= J[k] / dt;
+                cross3d(Q.rb[c], J, t);
+                for (int k = 0; k < 3; ++k) o.torque[k] -= t[k] / dt;
             }
         }
-        if (dmax <= 1e-15 * lmax || lmax == 0.0) {
-            ++sweep;
-            break;
-        }
+        __syncthreads();
     }
-    o.sweeps = newton_its + sweep;
-    for (int k = 0; k < 3; ++k) {
-        o.v[k] = vv[k]; o.w[k] = ww[k]; o.force[k] = 0.0; o.torque[k] = 0.0;
-        o.v_b[k] = vB[k]; o.w_b[k] = wB[k];
-    }
-    for (int k = 0; k < 6; ++k) o.lam_drive[k] = ld[k];
-    for (int c = 0; c < np; ++c) {
-        const int k8 = map[c];
-        for (int k = 0; k < 4; ++k) o.lam[k8][k] = lam[c][k];
-        if (k8 >= 4) continue;
-        double J[3], t[3];
-        for (int k = 0; k < 3; ++k) J[k] = lam[c][0] * Q.n[c][k] + lam[c][1 + k];
-        for (int k = 0; k < 3; ++k) o.force[k] -= J[k] / dt;
-        cross3d(Q.rb[c], J, t);
-        for (int k = 0; k < 3; ++k) o.torque[k] -= t[k] / dt;
-    }
-    out[z] = o;
+    const unsigned long long* ow = reinterpret_cast<const unsigned long long*>(&sh.o);
+    unsigned long long* gw = reinterpret_cast<unsigned long long*>(&out[z]);
+    for (int k = lane; k < (int)(sizeof(tr_macro_result) / 8); k += 64) gw[k] = ow[k];
 }
 
-__global__ void k_macro_clear(MacroZone* mz, int n_zones)
+// clears the zone sums and poses each zone's half-spaces once
+__global__ void k_macro_clear(DevBuffers b, MacroArgs a, MacroZone* mz)
 {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
-    if (z >= n_zones) return;
+    if (z >= a.n_zones) return;
     MacroZone& Z = mz[z];
+    const BodyDev& B = b.bodies[a.body[z]];
+    Z.nplanes = B.nplanes;
+    for (int q = 0; q < B.nplanes; ++q) plane_world(B, q, Z.wpl[q], Z.wpl[q][3]);
     for (int k = 0; k < kZoneMoments; ++k) Z.mom[k] = 0.0;
     Z.vol = 0.0;
     for (int q = 0; q < 2; ++q) {
@@ -852,13 +917,13 @@ void launch_macro(const DevBuffers& b, const StepParams& p, const MacroArgs& a, 
                   hipStream_t s)
 {
     if (a.n_zones <= 0) return;
-    hipLaunchKernelGGL(k_macro_clear, dim3(1), dim3(64), 0, s, mz, a.n_zones);
+    hipLaunchKernelGGL(k_macro_clear, dim3(1), dim3(64), 0, s, b, a, mz);
     if (a.n > 0) {
         const unsigned g = (unsigned)((a.n + 255) / 256);
         hipLaunchKernelGGL(k_macro_pass1, dim3(g), dim3(256), 0, s, b, p, a, mz);
         hipLaunchKernelGGL(k_macro_pass2, dim3(g), dim3(256), 0, s, b, p, a, mz);
     }
-    hipLaunchKernelGGL(k_macro_solve, dim3(1), dim3(64), 0, s, b, p, a, mz, out);
+    hipLaunchKernelGGL(k_macro_solve, dim3((unsigned)a.n_zones), dim3(64), 0, s, b, p, a, mz, out);
 }
 
 }  // namespace trk

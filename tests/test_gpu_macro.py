@@ -271,6 +271,26 @@ def test_second_env_of_a_two_env_scene():
         compare(gpu[0], orc[0], float(np.max(np.abs(spec["x"]))) + 1.0)
 
 
+def test_envs_loaded_out_of_order_go_through_the_id_map():
+    # env 1's spheres added before env 0's: the slots are not in env order
+    # until a step sorts them, so the macroscale step reads each env by id
+    a = bed_with_zone(43, 3000, 0.1)
+    b = bed_with_zone(44, 4000, -0.2, tool="bucket")
+    ref = T.scene_from_specs([a, b], cap_particles=4000)
+    sc = T.Scene(n_envs=2, dt=a["dt"], gravity=a["gravity"], max_sweeps=a["max_sweeps"], material=a["material"],
+                 cap_particles=4000, cap_contacts=64000, r_ref=a["r_ref"],
+                 env_bounds=[list(s["grid_lo"]) + list(s["grid_hi"]) for s in (a, b)])
+    for env, spec in ((1, b), (0, a)):
+        sc.add_particles(env, spec["x"], spec["r"], vel=spec["v"])
+        sc.set_particles(env, w=spec["w"])
+        sc.set_kinematic_bodies(env, [dict(bd, id=i) for i, bd in enumerate(spec["bodies"])])
+    for env, spec in ((0, a), (1, b)):
+        orc = O.macro_step(spec, spec["x"], spec["v"], spec["w"], **MACRO)
+        for g in (sc.macro_step(env, **MACRO), ref.macro_step(env, **MACRO)):
+            assert [q["zone"] for q in g] == [o["zone"] for o in orc] == [1]
+            compare(g[0], orc[0], float(np.max(np.abs(spec["x"]))) + 1.0)
+
+
 def test_after_steps_the_state_is_read_from_the_stepped_buffers():
     # macro_step reads the particles through the id map after the step's sort:
     # stepping then restoring the original state gives the original result
