@@ -6,8 +6,8 @@
 //                 contacts, weights and activations in BF16, FP32 accumulate
 //   k_mlp_f32     the same network in FP32 on the vector ALU (reference)
 //   k_learned_lam lambda^0 = frame x output x scale, projected onto the bounds
-//   k_mlp_train   FP32 forward + backward of 0.5 mean ||y - label||^2, with
-//                 per-block gradient partials reduced in fixed order
+//   k_mlp_train   FP32 forward + backward of 0.5 mean ||y - label||^2 on
+//                 MFMA (FP32), per-block gradient partials reduced in fixed order
 //   k_adam        Adam update
 #include <hip/hip_runtime.h>
 
@@ -265,104 +265,224 @@ void launch_learned_lam(const DevBuffers& b, const StepParams& p, const Sizes& z
 }
 
 // ---------------------------------------------------------------------------
-// training: per block of 64 samples, forward + backward in FP32, gradient
-// partials of the block written to part[block][kNP], loss to part[.][kNP]
+// training: forward + backward of 0.5 mean ||y - label||^2 in FP32 on MFMA
+// (v_mfma_f32_32x32x2f32, FP32 products and sums).  Each wave takes tiles of
+// 32 samples; a block's 4 waves take R tiles each (128 R samples, R from 1
+// to 4 so that a call fills the 256 CUs where the batch allows).  Per tile:
+//   layer 1   Z1[32 x 64] = X[32 x 12] . W1^T          2 N-tiles x 6 K-steps
+//   layer 2   Z2 = H1 . W2^T                           2 N-tiles x 32 K-steps
+//   layer 3   y = H2 . W3^T (3 outputs: vector ALU)
+//   backward  gZ2 = (gy . W3) o silu'(Z2) (vector ALU)
+//             gZ1 = (gZ2 . W2) o silu'(Z1)             2 N-tiles x 32 K-steps
+//   gradients dW2 += gZ2^T . H1  (64 x 64, K = 32 samples: 2 x 2 tiles x 16)
+//             dW1 += gZ1^T . X   (64 x 12 of one 32-wide N-tile: 2 tiles x 16)
+//             dW3, the biases and the loss on the vector ALU
+// The gradient accumulators stay in registers across a wave's tiles; the
+// block's waves add theirs in LDS in a fixed order and write the block's
+// partial to part[block][kNP] (loss at part[.][kNP]).
+// Operand layouts (A 32x2, B 2x32, D 32x32): A[i][k] -> lane i + 32 k,
+// B[k][j] -> lane j + 32 k, D[i][j] -> lane j + 32 ((i / 4) % 2), element
+// (i % 4) + 4 (i / 8).
 // ---------------------------------------------------------------------------
-constexpr int kTrainB = 64;
+constexpr int kTrainWaves = 4, kTrainMaxTiles = 4;
+constexpr int kTP = kH + 1;  // LDS pitch of the 64-wide rows
 
-__global__ __launch_bounds__(kTrainB) void k_mlp_train(const float* __restrict__ W, const float* __restrict__ feat,
-                                                       const float* __restrict__ label, int64_t B, float* __restrict__ part)
+// tiles per wave and blocks of a batch of B samples
+__host__ __device__ constexpr int train_tiles(int64_t B)
 {
-    __shared__ float w[kMlpParams];
-    __shared__ float x0s[kTrainB][kIn];
-    __shared__ float h1s[kTrainB][kH + 1];
-    __shared__ float h2s[kTrainB][kH + 1];
-    __shared__ float g1s[kTrainB][kH + 1];
-    __shared__ float g2s[kTrainB][kH + 1];
-    __shared__ float gys[kTrainB][kOut];
-    __shared__ float lred[kTrainB];
-    const int t = threadIdx.x;
-    for (int k = t; k < kMlpParams; k += blockDim.x) w[k] = W[k];
-    __syncthreads();
-    int64_t s = (int64_t)blockIdx.x * kTrainB + t;
-    bool act = s < B;
-    float inv_b = 1.0f / (float)B;
-    float loss = 0.0f;
-    // forward
-    for (int k = 0; k < kIn; ++k) x0s[t][k] = act ? feat[s * kIn + k] * w[oScale + k] : 0.0f;
-    for (int o = 0; o < kH; ++o) {
-        float z = w[ob1 + o];
-        for (int k = 0; k < kIn; ++k) z += w[oW1 + o * kIn + k] * x0s[t][k];
-        g1s[t][o] = z;          // z1 kept for the backward pass
-        h1s[t][o] = silu(z);
-    }
-    float y[kOut] = {w[ob3], w[ob3 + 1], w[ob3 + 2]};
-    for (int o = 0; o < kH; ++o) {
-        float z = w[ob2 + o];
-        for (int k = 0; k < kH; ++k) z += w[oW2 + o * kH + k] * h1s[t][k];
-        g2s[t][o] = z;          // z2
-        float h = silu(z);
-        h2s[t][o] = h;
-        for (int q = 0; q < kOut; ++q) y[q] += w[oW3 + q * kH + o] * h;
-    }
-    for (int q = 0; q < kOut; ++q) {
-        float e = act ? y[q] - label[s * kOut + q] : 0.0f;
-        loss += 0.5f * e * e;
-        gys[t][q] = e * inv_b;
-    }
-    // backward to gz2 (in place of z2), then gz1 (in place of z1)
-    for (int o = 0; o < kH; ++o) {
-        float gh = 0.0f;
-        for (int q = 0; q < kOut; ++q) gh += w[oW3 + q * kH + o] * gys[t][q];
-        g2s[t][o] = gh * dsilu(g2s[t][o]);
-    }
-    for (int i = 0; i < kH; ++i) {
-        float gh = 0.0f;
-        for (int o = 0; o < kH; ++o) gh += w[oW2 + o * kH + i] * g2s[t][o];
-        g1s[t][i] = gh * dsilu(g1s[t][i]);
-    }
-    lred[t] = act ? loss * inv_b : 0.0f;
-    __syncthreads();
-    // gradient partials of this block: thread t handles parameters t, t + 64, ...
-    float* out = part + (size_t)blockIdx.x * (kNP + 1);
-    for (int pidx = t; pidx < kNP; pidx += blockDim.x) {
-        float g = 0.0f;
-        if (pidx < ob1) {
-            int o = pidx / kIn, k = pidx % kIn;
-            for (int q = 0; q < kTrainB; ++q) g += g1s[q][o] * x0s[q][k];
-        } else if (pidx < oW2) {
-            int o = pidx - ob1;
-            for (int q = 0; q < kTrainB; ++q) g += g1s[q][o];
-        } else if (pidx < ob2) {
-            int o = (pidx - oW2) / kH, k = (pidx - oW2) % kH;
-            for (int q = 0; q < kTrainB; ++q) g += g2s[q][o] * h1s[q][k];
-        } else if (pidx < oW3) {
-            int o = pidx - ob2;
-            for (int q = 0; q < kTrainB; ++q) g += g2s[q][o];
-        } else if (pidx < ob3) {
-            int o = (pidx - oW3) / kH, k = (pidx - oW3) % kH;
-            for (int q = 0; q < kTrainB; ++q) g += gys[q][o] * h2s[q][k];
-        } else {
-            int o = pidx - ob3;
-            for (int q = 0; q < kTrainB; ++q) g += gys[q][o];
-        }
-        out[pidx] = g;
-    }
-    if (t == 0) {
-        float l = 0.0f;
-        for (int q = 0; q < kTrainB; ++q) l += lred[q];
-        out[kNP] = l;
-    }
+    return B > (int64_t)3 * kTrainWaves * 32 * 256 ? 4 : (B > (int64_t)kTrainWaves * 32 * 256 ? 2 : 1);
+}
+__host__ __device__ constexpr int64_t train_blocks(int64_t B)
+{
+    return (B + (int64_t)kTrainWaves * 32 * train_tiles(B) - 1) / ((int64_t)kTrainWaves * 32 * train_tiles(B));
 }
 
-__global__ void k_grad_reduce(const float* __restrict__ part, int nblocks, float* __restrict__ grad, float* loss)
+__device__ inline floatx16 mfma32(float a, float b, floatx16 c)
 {
-    int pidx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pidx > kNP) return;
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train(const float* __restrict__ W,
+                                                                const float* __restrict__ feat,
+                                                                const float* __restrict__ label, int64_t B,
+                                                                int tiles, float* __restrict__ part)
+{
+    __shared__ float w[kMlpParams];
+    __shared__ float xs[kTrainWaves][32][kIn + 1];
+    __shared__ float h1s[kTrainWaves][32][kTP];
+    __shared__ float h2s[kTrainWaves][32][kTP];  // H2, then gZ2
+    __shared__ float g1s[kTrainWaves][32][kTP];  // gZ1
+    __shared__ float gys[kTrainWaves][32][kOut];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63, col = lane & 31, half = lane >> 5;
+    for (int k = t; k < kMlpParams; k += blockDim.x) w[k] = W[k];
+    __syncthreads();
+    const float inv_b = 1.0f / (float)B;
+    floatx16 dW2[2][2], dW1[2];
+    for (int m = 0; m < 2; ++m) {
+        dW1[m] = floatx16{};
+        for (int n = 0; n < 2; ++n) dW2[m][n] = floatx16{};
+    }
+    float dW3[kOut] = {0.0f, 0.0f, 0.0f}, db1[2] = {0.0f, 0.0f}, db2[2] = {0.0f, 0.0f}, db3 = 0.0f, loss = 0.0f;
+    for (int r = 0; r < tiles; ++r) {
+        const int64_t s0 = (((int64_t)blockIdx.x * tiles + r) * kTrainWaves + wave) * 32;
+        for (int e = lane; e < 32 * kIn; e += 64) {
+            const int i = e / kIn, k = e % kIn;
+            const int64_t sm = s0 + i;
+            xs[wave][i][k] = sm < B ? feat[sm * kIn + k] * w[oScale + k] : 0.0f;
+        }
+        __syncthreads();
+        // layer 1: Z1 in registers (D layout), H1 into LDS
+        floatx16 z1[2], z2[2];
+        for (int n = 0; n < 2; ++n) {
+            floatx16 acc = {};
+            for (int kk = 0; kk < kIn / 2; ++kk) {
+                const int k = 2 * kk + half;
+                acc = mfma32(xs[wave][col][k], w[oW1 + (n * 32 + col) * kIn + k], acc);
+            }
+            const float bias = w[ob1 + n * 32 + col];
+            for (int e = 0; e < 16; ++e) {
+                const int i = (e & 3) + 8 * (e >> 2) + 4 * half;
+                const float zz = acc[e] + bias;
+                z1[n][e] = zz;
+                h1s[wave][i][n * 32 + col] = silu(zz);
+            }
+        }
+        __syncthreads();
+        // layer 2: Z2 in registers, H2 into LDS
+        for (int n = 0; n < 2; ++n) {
+            floatx16 acc = {};
+            for (int kk = 0; kk < kH / 2; ++kk) {
+                const int k = 2 * kk + half;
+                acc = mfma32(h1s[wave][col][k], w[oW2 + (n * 32 + col) * kH + k], acc);
+            }
+            const float bias = w[ob2 + n * 32 + col];
+            for (int e = 0; e < 16; ++e) {
+                const int i = (e & 3) + 8 * (e >> 2) + 4 * half;
+                const float zz = acc[e] + bias;
+                z2[n][e] = zz;
+                h2s[wave][i][n * 32 + col] = silu(zz);
+            }
+        }
+        __syncthreads();
+        // layer 3 and the error: sample col, the two lane halves summing half
+        // of H2's columns each
+        {
+            float y[kOut] = {0.0f, 0.0f, 0.0f};
+            for (int k = half * 32; k < half * 32 + 32; ++k) {
+                const float h = h2s[wave][col][k];
+                for (int q = 0; q < kOut; ++q) y[q] += w[oW3 + q * kH + k] * h;
+            }
+            const int64_t sm = s0 + col;
+            for (int q = 0; q < kOut; ++q) {
+                y[q] += __shfl_xor(y[q], 32);
+                const float e = sm < B ? (y[q] + w[ob3 + q]) - label[sm * kOut + q] : 0.0f;
+                if (half == 0) {
+                    gys[wave][col][q] = e * inv_b;
+                    loss += 0.5f * e * e;
+                }
+            }
+        }
+        __syncthreads();
+        // dW3 (row q, column lane), db3
+        for (int i = 0; i < 32; ++i) {
+            const float h = h2s[wave][i][lane];
+            for (int q = 0; q < kOut; ++q) dW3[q] += gys[wave][i][q] * h;
+        }
+        if (lane < kOut)
+            for (int i = 0; i < 32; ++i) db3 += gys[wave][i][lane];
+        __syncthreads();
+        // gZ2 = (gy . W3) o silu'(Z2), into h2s
+        for (int n = 0; n < 2; ++n)
+            for (int e = 0; e < 16; ++e) {
+                const int i = (e & 3) + 8 * (e >> 2) + 4 * half, j = n * 32 + col;
+                float gh = 0.0f;
+                for (int q = 0; q < kOut; ++q) gh += gys[wave][i][q] * w[oW3 + q * kH + j];
+                const float g = gh * dsilu(z2[n][e]);
+                h2s[wave][i][j] = g;
+                db2[n] += g;
+            }
+        __syncthreads();
+        // dW2 += gZ2^T . H1
+        for (int m = 0; m < 2; ++m)
+            for (int n = 0; n < 2; ++n)
+                for (int kk = 0; kk < 16; ++kk) {
+                    const int i = 2 * kk + half;
+                    dW2[m][n] = mfma32(h2s[wave][i][m * 32 + col], h1s[wave][i][n * 32 + col], dW2[m][n]);
+                }
+        // gZ1 = (gZ2 . W2) o silu'(Z1), into g1s
+        for (int n = 0; n < 2; ++n) {
+            floatx16 acc = {};
+            for (int kk = 0; kk < kH / 2; ++kk) {
+                const int o = 2 * kk + half;
+                acc = mfma32(h2s[wave][col][o], w[oW2 + o * kH + n * 32 + col], acc);
+            }
+            for (int e = 0; e < 16; ++e) {
+                const int i = (e & 3) + 8 * (e >> 2) + 4 * half;
+                const float g = acc[e] * dsilu(z1[n][e]);
+                g1s[wave][i][n * 32 + col] = g;
+                db1[n] += g;
+            }
+        }
+        __syncthreads();
+        // dW1 += gZ1^T . X (columns col < 12 of one N-tile)
+        for (int m = 0; m < 2; ++m)
+            for (int kk = 0; kk < 16; ++kk) {
+                const int i = 2 * kk + half;
+                dW1[m] = mfma32(g1s[wave][i][m * 32 + col], col < kIn ? xs[wave][i][col] : 0.0f, dW1[m]);
+            }
+        __syncthreads();  // the wave's buffers are rewritten by its next tile
+    }
+    // the block's partial: the waves add theirs in order
+    float* red = &h1s[0][0][0];
+    for (int wv = 0; wv < kTrainWaves; ++wv) {
+        if (wave == wv) {
+            auto put = [&](int idx, float v) { red[idx] = wv == 0 ? v : red[idx] + v; };
+            for (int m = 0; m < 2; ++m)
+                for (int e = 0; e < 16; ++e) {
+                    const int o = m * 32 + (e & 3) + 8 * (e >> 2) + 4 * half;
+                    for (int n = 0; n < 2; ++n) put(oW2 + o * kH + n * 32 + col, dW2[m][n][e]);
+                    if (col < kIn) put(oW1 + o * kIn + col, dW1[m][e]);
+                }
+            for (int q = 0; q < kOut; ++q) put(oW3 + q * kH + lane, dW3[q]);
+            for (int n = 0; n < 2; ++n) {
+                const float v1 = db1[n] + __shfl_xor(db1[n], 32), v2 = db2[n] + __shfl_xor(db2[n], 32);
+                if (half == 0) {
+                    put(ob1 + n * 32 + col, v1);
+                    put(ob2 + n * 32 + col, v2);
+                }
+            }
+            if (lane < kOut) put(ob3 + lane, db3);
+            float l = loss;
+            for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o);
+            if (lane == 0) put(kNP, l * inv_b);
+        }
+        __syncthreads();
+    }
+    float* out = part + (size_t)blockIdx.x * (kNP + 1);
+    for (int k = t; k <= kNP; k += blockDim.x) out[k] = red[k];
+}
+
+// the blocks' partials summed in a fixed order: 64 parameters per block of
+// 1024 threads, 16 groups each summing every 16th partial (64 consecutive
+// parameters per load: coalesced), then the 16 group sums in group order
+constexpr int kRedGroups = 16;
+__global__ __launch_bounds__(64 * kRedGroups) void k_grad_reduce(const float* __restrict__ part, int nblocks,
+                                                                   float* __restrict__ grad, float* loss)
+{
+    __shared__ float gs[kRedGroups][64];
+    const int j = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int pidx = blockIdx.x * 64 + j;
     float g = 0.0f;
-    for (int b = 0; b < nblocks; ++b) g += part[(size_t)b * (kNP + 1) + pidx];
-    if (pidx < kNP) grad[pidx] = g;
-    else if (loss) *loss = g;
+    if (pidx <= kNP)
+        for (int b = grp; b < nblocks; b += kRedGroups) g += part[(size_t)b * (kNP + 1) + pidx];
+    gs[grp][j] = g;
+    __syncthreads();
+    if (grp == 0 && pidx <= kNP) {
+        float t = 0.0f;
+        for (int k = 0; k < kRedGroups; ++k) t += gs[k][j];
+        if (pidx < kNP) grad[pidx] = t;
+        else if (loss) *loss = t;
+    }
 }
 
 __global__ void k_adam(float* W, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
@@ -378,15 +498,16 @@ __global__ void k_adam(float* W, const float* g, float* m, float* v, int n, floa
     W[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
 }
 
-int64_t mlp_grad_scratch(int64_t B) { return ((B + kTrainB - 1) / kTrainB) * (int64_t)(kNP + 1); }
+int64_t mlp_grad_scratch(int64_t B) { return train_blocks(B) * (int64_t)(kNP + 1); }
 int mlp_trainable() { return kNP; }
 
 void launch_mlp_grad(const float* W, const float* feat, const float* label, int64_t B, float* grad, float* loss,
                      float* scratch, hipStream_t s)
 {
-    int nb = (int)((B + kTrainB - 1) / kTrainB);
-    hipLaunchKernelGGL(k_mlp_train, dim3(nb), dim3(kTrainB), 0, s, W, feat, label, B, scratch);
-    hipLaunchKernelGGL(k_grad_reduce, dim3((kNP + 1 + 255) / 256), dim3(256), 0, s, scratch, nb, grad, loss);
+    const int nb = (int)train_blocks(B);
+    hipLaunchKernelGGL(k_mlp_train, dim3(nb), dim3(64 * kTrainWaves), 0, s, W, feat, label, B, train_tiles(B),
+                       scratch);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((kNP + 1 + 63) / 64), dim3(64 * kRedGroups), 0, s, scratch, nb, grad, loss);
 }
 
 void launch_adam(float* W, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps, int t,
@@ -404,7 +525,7 @@ void launch_adam(float* W, const float* g, float* m, float* v, int n, float lr, 
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int64_t kNoAllocMaxBatch = TR_MLP_NOALLOC_MAX_BATCH;
-constexpr int64_t kNoAllocFloats = ((kNoAllocMaxBatch + trk::kTrainB - 1) / trk::kTrainB) * (int64_t)(trk::kNP + 1);
+constexpr int64_t kNoAllocFloats = trk::train_blocks(kNoAllocMaxBatch) * (int64_t)(trk::kNP + 1);
 constexpr int kMaxDevices = 64;
 
 // One copy per GPU, held until the process ends.  Host code never passes the
