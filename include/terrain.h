@@ -567,7 +567,10 @@ int mlp_adam_step(float* weights, const float* grad, float* m, float* v, float l
  *     LDS when it has at most lds_particles particles) or, when it has more
  *     than T particles, by a cluster of ceil(n / T) blocks; small envs share
  *     blocks and run on them one after another.  T = cluster_particles, or
- *     with 0 the mean particles per resident block (at least 4096).
+ *     with 0 the mean particles per resident block (at least 4096).  With
+ *     TR_CLUSTER_NONE no env takes more than one block: an env that does not
+ *     fit LDS gets a block of its own (bodies in global memory), the others
+ *     are packed into blocks of at most lds_particles particles.
  *   TR_PGS_SPREAD: one env (n_envs must be 1) spread over all 8 XCDs: its
  *     sorted spheres in eighths (compact regions of the Morton order), each
  *     contact solved by the XCD group of its second sphere with
@@ -576,11 +579,12 @@ int mlp_adam_step(float* weights, const float* grad, float* m, float* v, float l
 #define TR_PGS_GROUPED 0
 #define TR_PGS_PER_ENV 1
 #define TR_PGS_SPREAD 2
+#define TR_CLUSTER_NONE (-1)
 typedef struct tr_solver_config {
     int32_t mode;              /* TR_PGS_GROUPED, TR_PGS_PER_ENV or TR_PGS_SPREAD */
     int32_t blocks_per_xcd;    /* grouped: >= 1, clamped to the resident limit */
     int32_t lds_particles;     /* per-env: >= 0, clamped to what LDS holds */
-    int32_t cluster_particles; /* per-env: T, or 0 for the automatic choice */
+    int32_t cluster_particles; /* per-env: T, 0 for the automatic choice, or TR_CLUSTER_NONE */
     int32_t dataflow;          /* 1: inside a multi-block solve the colour order of each sphere's
                                   updates is kept by per-sphere update counters instead of a
                                   barrier after every colour (same results); 0: barriers */

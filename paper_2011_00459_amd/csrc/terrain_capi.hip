@@ -197,6 +197,12 @@ int rebuild_plan(tr_scene* s)
         // about half as fast per sphere as one solving a set from LDS).
         const double T = s->cfg.cluster_particles > 0 ? (double)s->cfg.cluster_particles
                                                        : std::max(total / B, 4096.0);
+        // single-block solves only: an env too large for LDS takes a block of
+        // its own (measured on MI355X, a multi-block share pays about 12 us of
+        // cross-block barrier per colour, where one block of 1,024 threads
+        // solving the env alone meets at workgroup barriers)
+        const bool solo = s->cfg.cluster_particles == TR_CLUSTER_NONE;
+        const double set_cap = solo ? (double)std::max(lds_cap, 1) : T;
         std::vector<std::vector<int4>> tasks(B);
         std::vector<double> load(B, 0.0);
         std::vector<int> lane_next(kGroups, 0);
@@ -204,7 +210,7 @@ int rebuild_plan(tr_scene* s)
         std::vector<double> fill;
         for (int e : order) {
             const double n = (double)s->envs[e].n;
-            int K = (int)std::min<double>(std::ceil(n / T), (double)per_lane);
+            int K = solo ? 1 : (int)std::min<double>(std::ceil(n / T), (double)per_lane);
             int lane = 0;
             for (int x = 1; x < kGroups; ++x)
                 if (lane_next[x] < lane_next[lane]) lane = x;
@@ -219,7 +225,7 @@ int rebuild_plan(tr_scene* s)
                 continue;
             }
             size_t k = 0;
-            while (k < sets.size() && (fill[k] + n > T || (int)sets[k].size() >= waves)) ++k;
+            while (k < sets.size() && (fill[k] + n > set_cap || (int)sets[k].size() >= waves)) ++k;
             if (k == sets.size()) {
                 sets.emplace_back();
                 fill.push_back(0.0);
@@ -1506,7 +1512,7 @@ int set_solver_config(tr_scene* s, const tr_solver_config* cfg)
     if (!s || !cfg) return TR_E_INVAL;
     s->err.clear();
     if ((cfg->mode != TR_PGS_GROUPED && cfg->mode != TR_PGS_PER_ENV && cfg->mode != TR_PGS_SPREAD) ||
-        cfg->blocks_per_xcd < 1 || cfg->lds_particles < 0 || cfg->cluster_particles < 0 ||
+        cfg->blocks_per_xcd < 1 || cfg->lds_particles < 0 || cfg->cluster_particles < TR_CLUSTER_NONE ||
         (cfg->dataflow != 0 && cfg->dataflow != 1))
         return fail(s, TR_E_INVAL, "set_solver_config: bad field");
     if (cfg->mode == TR_PGS_SPREAD && (s->desc.n_envs != 1 || cfg->dataflow))
@@ -1962,7 +1968,7 @@ int autotune(tr_scene* s, int32_t steps, const char* cache_path, tr_solver_confi
     if (!(s->desc.tol > 0.0 && s->desc.n_envs > kGroups))
         for (int bpx : {64, 32, 16, 8}) cands.push_back({TR_PGS_GROUPED, bpx, s->max_lds_particles, 0, 0});
     if (s->desc.n_envs == 1) cands.push_back({TR_PGS_SPREAD, 32, s->max_lds_particles, 0, 0});
-    for (int cp : {0, 8192, 16384}) cands.push_back({TR_PGS_PER_ENV, 32, s->max_lds_particles, cp, 0});
+    for (int cp : {0, 8192, 16384, (int)TR_CLUSTER_NONE}) cands.push_back({TR_PGS_PER_ENV, 32, s->max_lds_particles, cp, 0});
     cands.push_back({TR_PGS_PER_ENV, 32, 0, 0, 0});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_CHECK(s, hipEventCreate(&e0));

@@ -72,8 +72,9 @@ def gen_dataset(n_envs=16, steps=120, skip=8, seed=100, tol=1e-5, max_sweeps=400
     """Features and converged impulses (`get_learn_samples`) from column
     trajectories stepped on the GPU with the previous-step warm start and a
     tight residual tolerance.  The first `skip` steps (free fall, few contacts)
-    are not recorded; when the trajectories hold more than `cap` samples, a
-    seeded uniform subset is kept."""
+    and env-steps stopped by the sweep cap are not recorded; when the
+    trajectories hold more than `cap` samples, a seeded uniform subset is
+    kept."""
     specs = column_batch(n_envs, seed, sweeps=max_sweeps, tol=tol)
     sc = T.scene_from_specs(specs)
     feats, labels, total = [], [], 0
@@ -82,6 +83,8 @@ def gen_dataset(n_envs=16, steps=120, skip=8, seed=100, tol=1e-5, max_sweeps=400
         if k < skip:
             continue
         for e in range(n_envs):
+            if st[e]["sweeps"] >= max_sweeps:
+                continue  # stopped by the cap, not by the tolerance
             f, lab = sc.get_learn_samples(e)
             feats.append(f)
             labels.append(lab)
@@ -104,7 +107,8 @@ def gen_bed_dataset(n_envs=32, steps=60, skip=20, seed=7000, tol=1e-5, max_sweep
     distribution (`scenegen.batch_specs` with seeds seed .. seed + n_envs - 1,
     disjoint from the evaluation beds), their tools moving, stepped on the GPU
     with the previous-step start and a tight residual tolerance; the first
-    `skip` steps (the pour) are not recorded."""
+    `skip` steps (the pour) are not recorded, nor the env-steps that reached
+    the sweep cap before the tolerance."""
     specs = SG.batch_specs(seed=seed, n_envs=n_envs, sweeps=max_sweeps)
     mat = specs[0]["material"]
     specs = [dict(s, material=mat, tol=tol, warm_start="prev") for s in specs]
@@ -116,6 +120,8 @@ def gen_bed_dataset(n_envs=32, steps=60, skip=20, seed=7000, tol=1e-5, max_sweep
         if k < skip:
             continue
         for e in range(n_envs):
+            if st[e]["sweeps"] >= max_sweeps:
+                continue  # stopped by the cap, not by the tolerance: its impulses are not converged
             f, lab = sc.get_learn_samples(e)
             feats.append(f)
             labels.append(lab)
@@ -184,10 +190,9 @@ class Trainer:
         losses = []
         for i in range(0, len(perm) - self.batch + 1, self.batch):
             self.loss_grad(self.feat.at(i), self.label.at(i), self.batch)
+            losses.append(float(self.L.get()[0]))  # every minibatch: the targets are heavy-tailed
             self.t += 1
             T.mlp_adam_step(self.W.ptr, self.G.ptr, self.M.ptr, self.V.ptr, lr, self.t)
-            if (self.t & 15) == 0:
-                losses.append(float(self.L.get()[0]))
         return float(np.mean(losses)) if losses else float(self.L.get()[0])
 
     def fit(self, epochs=20, lr=2e-3, lr_end=2e-4, check=None, log=None):

@@ -30,6 +30,7 @@ EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodi
            "remove_particles", "settle_particles", "get_colours", "mlp_loss_grad_noalloc", "macro_step")
 CG_KERNEL = {"heaviside": 0, "gauss": 1}
 PGS_MODE = {"grouped": 0, "per_env": 1, "spread": 2}
+CLUSTER_NONE = -1  # TR_CLUSTER_NONE: per-env solves of one block each
 MLP_TRAINABLE = MLP_PARAMS - 12
 
 

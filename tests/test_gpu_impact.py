@@ -146,6 +146,7 @@ SCHEDULES = {
     "grouped": dict(mode="grouped", blocks_per_xcd=4, dataflow=0),
     "per_env_lds": dict(mode="per_env", lds_particles=100000, cluster_particles=0),
     "per_env_global": dict(mode="per_env", lds_particles=0, cluster_particles=0),
+    "per_env_solo": dict(mode="per_env", lds_particles=350, cluster_particles=-1),
     "per_env_clusters": dict(mode="per_env", lds_particles=350, cluster_particles=150, dataflow=0),
     "per_env_clusters_flow": dict(mode="per_env", lds_particles=350, cluster_particles=150, dataflow=1),
 }
