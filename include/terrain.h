@@ -207,7 +207,10 @@ typedef struct tr_scene tr_scene;
 
 /* Creates a scene from *d (copied, env_bounds included).  Allocates all
  * device buffers at their capacities.  TR_E_INVAL for bad sizes or options
- * (mu_r negative, restitution outside [0, 1], v_imp not finite), TR_E_NOMEM, TR_E_DEVICE. */
+ * (mu_r negative, restitution outside [0, 1], v_imp not finite), TR_E_NOMEM, TR_E_DEVICE.
+ * TR_E_CAPACITY when n_envs x cap_particles exceeds 2^26 (the solver addresses
+ * the particles' 32 B velocity records with 31-bit byte offsets) or
+ * n_envs x cap_contacts reaches 2^31. */
 int create_scene(const tr_scene_desc* d, tr_scene** out);
 
 /* Releases every buffer of the scene.  NULL is accepted. */

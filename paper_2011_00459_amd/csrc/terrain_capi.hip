@@ -581,7 +581,8 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
         return TR_E_INVAL;
     if (d->warm_start < TR_WARM_COLD || d->warm_start > TR_WARM_LEARNED) return TR_E_INVAL;
     if ((d->alloc_fn == nullptr) != (d->free_fn == nullptr)) return TR_E_INVAL;  // both or neither
-    if ((int64_t)d->n_envs * d->cap_particles >= ((int64_t)1 << 31) ||
+    // the solver's body loads take 31-bit byte offsets into the 32 B velocity records
+    if ((int64_t)d->n_envs * d->cap_particles > ((int64_t)1 << 26) ||
         (int64_t)d->n_envs * d->cap_contacts >= ((int64_t)1 << 31))
         return TR_E_CAPACITY;
     if (!finite3(d->env_bounds, 6 * (int64_t)d->n_envs)) return TR_E_NONFINITE;
@@ -613,8 +614,8 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
     z.pgs_grid = kGroups * std::max(1, std::min(s->cfg.blocks_per_xcd, pgs_resident_blocks(512) / kGroups));
     z.col_grid = std::min(colour_resident_blocks(), 2048);
     DevBuffers& b = s->b;
-    bool ok = alloc_n(s, b.xr, z.P) && alloc_n(s, b.vm, z.P) && alloc_n(s, b.wi, z.P) && alloc_n(s, b.xr2, z.P) &&
-              alloc_n(s, b.vm2, z.P) && alloc_n(s, b.wi2, z.P) && alloc_n(s, b.pid, z.P) && alloc_n(s, b.pid2, z.P) &&
+    bool ok = alloc_n(s, b.xr, z.P) && alloc_n(s, b.vw, 2 * z.P) && alloc_n(s, b.xr2, z.P) &&
+              alloc_n(s, b.vw2, 2 * z.P) && alloc_n(s, b.pid, z.P) && alloc_n(s, b.pid2, z.P) &&
               alloc_n(s, b.rho, z.P) && alloc_n(s, b.rho2, z.P) && alloc_n(s, b.pkey, z.P) &&
               alloc_n(s, b.perm, z.P) && alloc_n(s, b.id2slot, z.NID) && alloc_n(s, b.rkey, z.C) &&
               alloc_n(s, b.ckey, z.C) && alloc_n(s, b.pkeyc, z.C) && alloc_n(s, b.rpair, z.C) &&
@@ -692,7 +693,7 @@ int add_particles(tr_scene* s, int32_t env, int64_t n, const double* pos, const 
     if (n == 0) return TR_OK;
     for (int e2 = env + 1; e2 < s->desc.n_envs; ++e2)
         if (s->envs[e2].n > 0) s->slots_env_major = false;  // appended behind a later env's spheres
-    std::vector<float4> xr(n), vm(n), wi(n);
+    std::vector<float4> xr(n), vw(2 * n);
     std::vector<int> pid(n), id2s(n);
     std::vector<float> rho(n);
     const double pi = 3.14159265358979323846;
@@ -703,9 +704,9 @@ int add_particles(tr_scene* s, int32_t env, int64_t n, const double* pos, const 
         double rr = r;
         double m = (double)rhof * (4.0 / 3.0) * pi * rr * rr * rr;
         xr[i] = make_float4((float)pos[3 * i], (float)pos[3 * i + 1], (float)pos[3 * i + 2], r);
-        vm[i] = make_float4(vel ? (float)vel[3 * i] : 0.f, vel ? (float)vel[3 * i + 1] : 0.f,
-                            vel ? (float)vel[3 * i + 2] : 0.f, (float)(1.0 / m));
-        wi[i] = make_float4(0.f, 0.f, 0.f, (float)(1.0 / (0.4 * m * rr * rr)));
+        vel_at(vw.data(), i) = make_float4(vel ? (float)vel[3 * i] : 0.f, vel ? (float)vel[3 * i + 1] : 0.f,
+                                           vel ? (float)vel[3 * i + 2] : 0.f, (float)(1.0 / m));
+        angv_at(vw.data(), i) = make_float4(0.f, 0.f, 0.f, (float)(1.0 / (0.4 * m * rr * rr)));
         pid[i] = (int)(id0 + i);
         id2s[i] = (int)(s->n_total + i);
         rho[i] = rhof;
@@ -714,8 +715,7 @@ int add_particles(tr_scene* s, int32_t env, int64_t n, const double* pos, const 
     hipStream_t st = s->stream;
     int64_t at = s->n_total;
     HIP_CHECK(s, hipMemcpyAsync(s->b.xr + at, xr.data(), sizeof(float4) * n, hipMemcpyHostToDevice, st));
-    HIP_CHECK(s, hipMemcpyAsync(s->b.vm + at, vm.data(), sizeof(float4) * n, hipMemcpyHostToDevice, st));
-    HIP_CHECK(s, hipMemcpyAsync(s->b.wi + at, wi.data(), sizeof(float4) * n, hipMemcpyHostToDevice, st));
+    HIP_CHECK(s, hipMemcpyAsync(s->b.vw + 2 * at, vw.data(), sizeof(float4) * 2 * n, hipMemcpyHostToDevice, st));
     HIP_CHECK(s, hipMemcpyAsync(s->b.pid + at, pid.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
     HIP_CHECK(s, hipMemcpyAsync(s->b.rho + at, rho.data(), sizeof(float) * n, hipMemcpyHostToDevice, st));
     HIP_CHECK(s, hipMemcpyAsync(s->b.id2slot + id0, id2s.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
@@ -798,8 +798,7 @@ namespace {
 void swap_particle_buffers(tr_scene* s)
 {
     std::swap(s->b.xr, s->b.xr2);
-    std::swap(s->b.vm, s->b.vm2);
-    std::swap(s->b.wi, s->b.wi2);
+    std::swap(s->b.vw, s->b.vw2);
     std::swap(s->b.pid, s->b.pid2);
     std::swap(s->b.rho, s->b.rho2);
 }
@@ -1323,13 +1322,12 @@ int remove_particles(tr_scene* s, int32_t env, int64_t n, const int64_t* ids)
     for (int64_t q = 0; q < H.n; ++q)
         if (!gone[q]) renum[q] = (int)(id0 + kept++);
     const int64_t N = s->n_total;
-    std::vector<float4> xr(N), vm(N), wi(N);
+    std::vector<float4> xr(N), vw(2 * N);
     std::vector<int> pid(N);
     std::vector<float> rho(N);
     HIP_CHECK(s, hipStreamSynchronize(s->stream));
     HIP_CHECK(s, hipMemcpy(xr.data(), s->b.xr, sizeof(float4) * N, hipMemcpyDeviceToHost));
-    HIP_CHECK(s, hipMemcpy(vm.data(), s->b.vm, sizeof(float4) * N, hipMemcpyDeviceToHost));
-    HIP_CHECK(s, hipMemcpy(wi.data(), s->b.wi, sizeof(float4) * N, hipMemcpyDeviceToHost));
+    HIP_CHECK(s, hipMemcpy(vw.data(), s->b.vw, sizeof(float4) * 2 * N, hipMemcpyDeviceToHost));
     HIP_CHECK(s, hipMemcpy(pid.data(), s->b.pid, sizeof(int) * N, hipMemcpyDeviceToHost));
     HIP_CHECK(s, hipMemcpy(rho.data(), s->b.rho, sizeof(float) * N, hipMemcpyDeviceToHost));
     // compact the slots in their order, renumbering env's ids
@@ -1340,14 +1338,13 @@ int remove_particles(tr_scene* s, int32_t env, int64_t n, const int64_t* ids)
             if (gone[q]) continue;
             pid[sl] = renum[q];
         }
-        xr[w] = xr[sl]; vm[w] = vm[sl]; wi[w] = wi[sl]; pid[w] = pid[sl]; rho[w] = rho[sl];
+        xr[w] = xr[sl]; vw[2 * w] = vw[2 * sl]; vw[2 * w + 1] = vw[2 * sl + 1]; pid[w] = pid[sl]; rho[w] = rho[sl];
         ++w;
     }
     std::vector<int> id2s(s->z.NID, 0);
     for (int64_t sl = 0; sl < w; ++sl) id2s[pid[sl]] = (int)sl;
     HIP_CHECK(s, hipMemcpy(s->b.xr, xr.data(), sizeof(float4) * w, hipMemcpyHostToDevice));
-    HIP_CHECK(s, hipMemcpy(s->b.vm, vm.data(), sizeof(float4) * w, hipMemcpyHostToDevice));
-    HIP_CHECK(s, hipMemcpy(s->b.wi, wi.data(), sizeof(float4) * w, hipMemcpyHostToDevice));
+    HIP_CHECK(s, hipMemcpy(s->b.vw, vw.data(), sizeof(float4) * 2 * w, hipMemcpyHostToDevice));
     HIP_CHECK(s, hipMemcpy(s->b.pid, pid.data(), sizeof(int) * w, hipMemcpyHostToDevice));
     HIP_CHECK(s, hipMemcpy(s->b.rho, rho.data(), sizeof(float) * w, hipMemcpyHostToDevice));
     HIP_CHECK(s, hipMemcpy(s->b.id2slot, id2s.data(), sizeof(int) * s->z.NID, hipMemcpyHostToDevice));
@@ -1752,7 +1749,7 @@ namespace {
 // Snapshot layout: header, then the arrays that persist across steps, each
 // as raw bytes in this order.
 struct StateHeader {
-    char magic[8];         // "TRSTATE1"
+    char magic[8];         // "TRSTATE2"
     int32_t n_envs;
     int32_t n_bodies;
     int64_t cap_particles;
@@ -1773,8 +1770,7 @@ std::vector<Span> state_spans(tr_scene* s, int64_t n_cache)
 {
     const int64_t n = s->n_total;
     return {{s->b.xr, sizeof(float4) * n},
-            {s->b.vm, sizeof(float4) * n},
-            {s->b.wi, sizeof(float4) * n},
+            {s->b.vw, sizeof(float4) * 2 * n},
             {s->b.pid, sizeof(int) * n},
             {s->b.rho, sizeof(float) * n},
             {s->b.id2slot, sizeof(int) * s->z.NID},
@@ -1813,7 +1809,7 @@ int save_state(tr_scene* s, void* buf, int64_t cap, int64_t* size)
     char* o = (char*)buf;
     StateHeader h;
     memset(&h, 0, sizeof(h));
-    memcpy(h.magic, "TRSTATE1", 8);
+    memcpy(h.magic, "TRSTATE2", 8);
     h.n_envs = s->desc.n_envs;
     h.n_bodies = (int32_t)s->body_host.size();
     h.cap_particles = s->desc.cap_particles;
@@ -1838,7 +1834,7 @@ int load_state(tr_scene* s, const void* buf, int64_t size)
     s->err.clear();
     StateHeader h;
     memcpy(&h, buf, sizeof(h));
-    if (memcmp(h.magic, "TRSTATE1", 8) != 0) return fail(s, TR_E_INVAL, "load_state: not a state snapshot");
+    if (memcmp(h.magic, "TRSTATE2", 8) != 0) return fail(s, TR_E_INVAL, "load_state: not a state snapshot");
     if (s->tables_dirty) {
         int rc = rebuild_tables(s);
         if (rc) return rc;

@@ -2,8 +2,8 @@
 //
 // Layout in HBM (all arrays allocated once at their capacities):
 //   particles, sorted every step by (environment, Morton cell, id):
-//     xr[P]  float4 (x, y, z, r)         vm[P] float4 (v, 1/m)
-//     wi[P]  float4 (omega, 1/I)         pid[P] int32 global id   rho[P] float
+//     xr[P]  float4 (x, y, z, r)         vw[2P] float4 pairs (v, 1/m), (omega, 1/I)
+//     pid[P] int32 global id             rho[P] float
 //   cells: per environment a dense grid, keys = cell_base + Morton code
 //   contacts (capacity C):
 //     raw detection output  rkey[C] u64, rpair[C] int2
@@ -180,10 +180,16 @@ struct EnvStats {
     unsigned long long impacts;  // contacts of the env treated as impacts this step
 };
 
+// A particle's velocity (v, 1/m) and angular velocity (omega, 1/I) are the
+// two halves of its 32 B record in vw: the solver gathers both for every
+// contact, and one record is one memory line where two arrays were two.
+__host__ __device__ inline float4& vel_at(float4* vw, int64_t s) { return vw[2 * s]; }
+__host__ __device__ inline float4& angv_at(float4* vw, int64_t s) { return vw[2 * s + 1]; }
+
 // Everything the kernels touch, as raw device pointers.
 struct DevBuffers {
     // particles (capacity P, double buffered for the sort)
-    float4 *xr, *vm, *wi, *xr2, *vm2, *wi2;
+    float4 *xr, *vw, *xr2, *vw2;  // vw: two float4 per slot, see vel_at
     int *pid, *pid2;
     float *rho, *rho2;
     uint32_t *pkey, *perm;

@@ -293,8 +293,8 @@ __global__ void k_gather(DevBuffers b, StepParams p)
     if (s >= p.n_particles) return;
     uint32_t i = b.perm[s];
     b.xr2[s] = b.xr[i];
-    b.vm2[s] = b.vm[i];
-    b.wi2[s] = b.wi[i];
+    vel_at(b.vw2, s) = vel_at(b.vw, i);
+    angv_at(b.vw2, s) = angv_at(b.vw, i);
     b.rho2[s] = b.rho[i];
     int id = b.pid[i];
     b.pid2[s] = id;
@@ -844,7 +844,7 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     int2 pr = b.cpair[c];
     int ia = pr.x, ib = pr.y;
     float4 x2 = b.xr[ib];
-    float4 v2 = b.vm[ib];
+    float4 v2 = vel_at(b.vw, ib);
     double X2[3] = {x2.x, x2.y, x2.z};
     double r2 = x2.w;
     double n[3], delta, l1, l2, dstar, dref, rmin, im1 = 0.0, iI1 = 0.0, un;
@@ -852,8 +852,8 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     double u1[3] = {0.0, 0.0, 0.0};  // velocity of body 1 at the contact point
     if (ia >= 0) {
         float4 x1 = b.xr[ia];
-        float4 v1 = b.vm[ia];
-        float4 w1 = b.wi[ia];
+        float4 v1 = vel_at(b.vw, ia);
+        float4 w1 = angv_at(b.vw, ia);
         double r1 = x1.w;
         double e[3] = {X2[0] - x1.x, X2[1] - x1.y, X2[2] - x1.z};
         double d = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
@@ -899,7 +899,7 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     double eps = 4.0 / (5.0 * kn * sqrt(de));
     double Sig = p.sig_coef * eps;
     double q = p.a_coef * (0.8 * delta) + p.b_coef * un;
-    double im2 = v2.w, iI2 = b.wi[ib].w;
+    double im2 = v2.w, iI2 = angv_at(b.vw, ib).w;
     double Wn = im1 + im2;
     double Wt = im1 + im2 + l1 * l1 * iI1 + l2 * l2 * iI2;
     double Dn = Wn + Sig;
@@ -924,7 +924,7 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     uint32_t pos = b.cpos[c];
     // learned-start features (12), contact frame and impulse scale, in FP64
     {
-        float4 w2 = b.wi[ib];
+        float4 w2 = angv_at(b.vw, ib);
         double u[3];
         u[0] = ((double)v2.x - l2 * ((double)w2.y * n[2] - (double)w2.z * n[1])) - u1[0];
         u[1] = ((double)v2.y - l2 * ((double)w2.z * n[0] - (double)w2.x * n[2])) - u1[1];
@@ -1075,10 +1075,10 @@ __global__ void k_impact_q(DevBuffers b, StepParams p, int64_t cap)
     const int ia = __float_as_int(q.z), ib = __float_as_int(q.w);
     const int e = (int)((uint32_t)b.pid[ib] / p.id_cap);
     if (b.env_stats[e].impacts == 0) return;
-    const float4 a = b.r0[pos], v2 = b.vm[ib];
+    const float4 a = b.r0[pos], v2 = vel_at(b.vw, ib);
     double v1[3];
     if (ia >= 0) {
-        const float4 t = b.vm[ia];
+        const float4 t = vel_at(b.vw, ia);
         v1[0] = t.x; v1[1] = t.y; v1[2] = t.z;
     } else {
         const float4 k = b.rk[pos];
@@ -1115,7 +1115,7 @@ __global__ void k_warm_apply(DevBuffers b, StepParams p)
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= p.n_particles) return;
     if (b.cnt->overflow) return;
-    float4 v = b.vm[s], w = b.wi[s];
+    float4 v = vel_at(b.vw, s), w = angv_at(b.vw, s);
     v.x += p.dt * p.g[0];
     v.y += p.dt * p.g[1];
     v.z += p.dt * p.g[2];
@@ -1139,8 +1139,8 @@ __global__ void k_warm_apply(DevBuffers b, StepParams p)
             w.x += sgn * w.w * Lr.x; w.y += sgn * w.w * Lr.y; w.z += sgn * w.w * Lr.z;
         }
     }
-    b.vm[s] = v;
-    b.wi[s] = w;
+    vel_at(b.vw, s) = v;
+    angv_at(b.vw, s) = w;
 }
 
 void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
@@ -1312,29 +1312,29 @@ __device__ inline RowRegs load_rows(const DevBuffers& b, uint32_t c, bool roll)
 // for a solve confined to one block (its waves share one CU and its L1) or
 // ordered by agent-scope fences.  Lds: the env's bodies staged in LDS.
 struct XcdBodies {
-    __amdgpu_buffer_rsrc_t rv, rw;
-    __device__ float4 v(int i) const { return ld_body<kCoherent>(rv, i); }
-    __device__ float4 w(int i) const { return ld_body<kCoherent>(rw, i); }
-    __device__ void set(int i, float4 v, float4 w) const { st_body<0>(rv, i, v); st_body<0>(rw, i, w); }
+    __amdgpu_buffer_rsrc_t r;  // vw: record i is float4 2i (v) and 2i + 1 (omega)
+    __device__ float4 v(int i) const { return ld_body<kCoherent>(r, 2 * i); }
+    __device__ float4 w(int i) const { return ld_body<kCoherent>(r, 2 * i + 1); }
+    __device__ void set(int i, float4 v, float4 w) const { st_body<0>(r, 2 * i, v); st_body<0>(r, 2 * i + 1, w); }
 };
 // Spread mode: one env's contacts on all XCDs, so every body store is written
 // through (sc1) and every load is device-scope: measured on MI355X, such a
 // store is seen by another XCD's device-scope load once it has completed.
 struct SpreadBodies {
-    __amdgpu_buffer_rsrc_t rv, rw;
-    __device__ float4 v(int i) const { return ld_body<kCoherent>(rv, i); }
-    __device__ float4 w(int i) const { return ld_body<kCoherent>(rw, i); }
+    __amdgpu_buffer_rsrc_t r;
+    __device__ float4 v(int i) const { return ld_body<kCoherent>(r, 2 * i); }
+    __device__ float4 w(int i) const { return ld_body<kCoherent>(r, 2 * i + 1); }
     __device__ void set(int i, float4 v, float4 w) const
     {
-        st_body<kCoherent>(rv, i, v);
-        st_body<kCoherent>(rw, i, w);
+        st_body<kCoherent>(r, 2 * i, v);
+        st_body<kCoherent>(r, 2 * i + 1, w);
     }
 };
 struct PlainBodies {
-    float4 *pv, *pw;
-    __device__ float4 v(int i) const { return pv[i]; }
-    __device__ float4 w(int i) const { return pw[i]; }
-    __device__ void set(int i, float4 v, float4 w) const { pv[i] = v; pw[i] = w; }
+    float4* vw;
+    __device__ float4 v(int i) const { return vel_at(vw, i); }
+    __device__ float4 w(int i) const { return angv_at(vw, i); }
+    __device__ void set(int i, float4 v, float4 w) const { vel_at(vw, i) = v; angv_at(vw, i) = w; }
 };
 struct LdsBodies {
     float4 *sv, *sw;  // env slots [base, base + n)
@@ -1753,11 +1753,11 @@ __global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int
         int mode = cluster_placement(b.cnt, counter, gx, flag);
         if (mode == 1)
             pgs_solve<SpreadBodies, true, false, false, ROLL, kPgsBlk / 64, GroupStarts, true>(
-                b, p, SpreadBodies{raw_rsrc(b.vm), raw_rsrc(b.wi)}, cs, ncol, counter, 1, rank, gx, (unsigned)g,
+                b, p, SpreadBodies{raw_rsrc(b.vw)}, cs, ncol, counter, 1, rank, gx, (unsigned)g,
                 sweeps_cap, slot, 0, red, cb, flag);
         else if (mode == 2)
             pgs_solve<PlainBodies, true, true, false, ROLL, kPgsBlk / 64, GroupStarts, true>(
-                b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, gx, (unsigned)g, sweeps_cap, slot, 0, red,
+                b, p, PlainBodies{b.vw}, cs, ncol, counter, 1, rank, gx, (unsigned)g, sweeps_cap, slot, 0, red,
                 cb, flag);
         return;
     }
@@ -1768,7 +1768,7 @@ __global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int
     if (slot == kSlotImpact && !b.ustats[g].imp_any) ncol = 0;  // no impact in the group
     int mode = cluster_placement(b.cnt, counter, gx, flag);
     if (mode == 1) {
-        XcdBodies ba{raw_rsrc(b.vm), raw_rsrc(b.wi)};
+        XcdBodies ba{raw_rsrc(b.vw)};
         if (flow)
             pgs_solve<XcdBodies, true, false, true, ROLL>(b, p, ba, cs, ncol, counter, 1, rank, gx, (unsigned)g, sweeps_cap,
                                                     slot, g, red, cb, flag);
@@ -1777,7 +1777,7 @@ __global__ __launch_bounds__(kPgsBlk) void k_pgs(DevBuffers b, StepParams p, int
                                                      sweeps_cap, slot, g, red, cb, flag);
     }
     else if (mode == 2)
-        pgs_solve<PlainBodies, true, true, false, ROLL>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, gx,
+        pgs_solve<PlainBodies, true, true, false, ROLL>(b, p, PlainBodies{b.vw}, cs, ncol, counter, 1, rank, gx,
                                                   (unsigned)g, sweeps_cap, slot, g, red, cb, flag);
 }
 
@@ -1807,11 +1807,11 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
     const uint32_t nthr = 64u * (uint32_t)(we - wb), lt = threadIdx.x - 64u * (uint32_t)wb;
     const int sb = e >= 0 ? b.envs[e].slot_begin : 0, n = e >= 0 ? b.envs[e].n : 0;
     LdsBodies lb{dyn + (off >= 0 ? off : 0), dyn + lds_cap + (off >= 0 ? off : 0), sb};
-    PlainBodies gb{b.vm, b.wi};
+    PlainBodies gb{b.vw};
     if (off >= 0)
         for (int i = (int)lt; i < n; i += (int)nthr) {
-            lb.sv[i] = b.vm[sb + i];
-            lb.sw[i] = b.wi[sb + i];
+            lb.sv[i] = vel_at(b.vw, sb + i);
+            lb.sw[i] = angv_at(b.vw, sb + i);
         }
     __syncthreads();
     const uint32_t* ec = b.env_col + (size_t)(e >= 0 ? e : 0) * (kMaxColours + 1);
@@ -1866,8 +1866,8 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
     }
     if (off >= 0)
         for (int i = (int)lt; i < n; i += (int)nthr) {
-            b.vm[sb + i] = lb.sv[i];
-            b.wi[sb + i] = lb.sw[i];
+            vel_at(b.vw, sb + i) = lb.sv[i];
+            angv_at(b.vw, sb + i) = lb.sw[i];
         }
     if (e >= 0 && lt == 0) {
         UnitStats& G = b.ustats[e];
@@ -1914,7 +1914,7 @@ __global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p,
         const uint32_t ncol = slot == kSlotImpact && !b.ustats[e].imp_any ? 0u : b.env_ncol[e];
         uint32_t* counter = b.env_bar + (size_t)e * 16;
         int mode = cluster_placement(b.cnt, counter, K, flag);
-        XcdBodies xb{raw_rsrc(b.vm), raw_rsrc(b.wi)};
+        XcdBodies xb{raw_rsrc(b.vw)};
         if (mode == 1 && flow)
             pgs_solve<XcdBodies, true, false, true, ROLL>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap, slot,
                                                     e, red, cb, flag);
@@ -1922,7 +1922,7 @@ __global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p,
             pgs_solve<XcdBodies, true, false, false, ROLL>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap, slot,
                                                      e, red, cb, flag);
         else if (mode == 2)
-            pgs_solve<PlainBodies, true, true, false, ROLL>(b, p, PlainBodies{b.vm, b.wi}, cs, ncol, counter, 1, rank, K,
+            pgs_solve<PlainBodies, true, true, false, ROLL>(b, p, PlainBodies{b.vw}, cs, ncol, counter, 1, rank, K,
                                                       first, sweeps_cap, slot, e, red, cb, flag);
         if (!flag) return;  // failed barrier: the step is abandoned
         __syncthreads();
@@ -2065,8 +2065,8 @@ __global__ void k_vel_copy(DevBuffers b, int n, int backup)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    if (backup) { b.vm2[s] = b.vm[s]; b.wi2[s] = b.wi[s]; }
-    else { b.vm[s] = b.vm2[s]; b.wi[s] = b.wi2[s]; }
+    if (backup) { vel_at(b.vw2, s) = vel_at(b.vw, s); angv_at(b.vw2, s) = angv_at(b.vw, s); }
+    else { vel_at(b.vw, s) = vel_at(b.vw2, s); angv_at(b.vw, s) = angv_at(b.vw2, s); }
 }
 
 void launch_vel_copy(const DevBuffers& b, const StepParams& p, bool backup, hipStream_t s)
@@ -2232,7 +2232,7 @@ __global__ void k_integrate(DevBuffers b, StepParams p)
     if (s >= p.n_particles) return;
     if (b.cnt->overflow) return;
     float4 x = b.xr[s];
-    float4 v = b.vm[s];
+    float4 v = vel_at(b.vw, s);
     x.x += p.dt * v.x;
     x.y += p.dt * v.y;
     x.z += p.dt * v.z;
@@ -2450,7 +2450,7 @@ __global__ __launch_bounds__(kRedBlk) void k_zone_part(DevBuffers b, StepParams 
             if (zone != z) continue;
             double r = xf.w;
             double m = (double)b.rho[s] * (4.0 / 3.0) * 3.14159265358979323846 * r * r * r;
-            float4 vf = b.vm[s], wf = b.wi[s];
+            float4 vf = vel_at(b.vw, s), wf = angv_at(b.vw, s);
             double v[3] = {vf.x, vf.y, vf.z};
             double Is = 0.4 * m * r * r;
             acc[0] += m;
@@ -2588,8 +2588,8 @@ __global__ void k_gather_by_id(DevBuffers b, int id_base, int n, float4* xo, flo
     if (k >= n) return;
     int s = b.id2slot[id_base + k];
     xo[k] = b.xr[s];
-    vo[k] = b.vm[s];
-    wo[k] = b.wi[s];
+    vo[k] = vel_at(b.vw, s);
+    wo[k] = angv_at(b.vw, s);
 }
 
 void launch_gather_by_id(const DevBuffers& b, int id_base, int n, float4* xo, float4* vo, float4* wo, hipStream_t s)
@@ -2605,8 +2605,8 @@ __global__ void k_scatter_by_id(DevBuffers b, int id_base, int n, const float4* 
     if (k >= n) return;
     int s = b.id2slot[id_base + k];
     if (mask & 1) { float4 o = b.xr[s]; float4 v = xi[k]; b.xr[s] = make_float4(v.x, v.y, v.z, o.w); }
-    if (mask & 2) { float4 o = b.vm[s]; float4 v = vi[k]; b.vm[s] = make_float4(v.x, v.y, v.z, o.w); }
-    if (mask & 4) { float4 o = b.wi[s]; float4 v = wi[k]; b.wi[s] = make_float4(v.x, v.y, v.z, o.w); }
+    if (mask & 2) { float4 o = vel_at(b.vw, s); float4 v = vi[k]; vel_at(b.vw, s) = make_float4(v.x, v.y, v.z, o.w); }
+    if (mask & 4) { float4 o = angv_at(b.vw, s); float4 v = wi[k]; angv_at(b.vw, s) = make_float4(v.x, v.y, v.z, o.w); }
 }
 
 void launch_scatter_by_id(const DevBuffers& b, int id_base, int n, const float4* xi, const float4* vi,

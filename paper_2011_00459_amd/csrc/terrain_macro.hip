@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) k_macro_pass1(DevBuffers b, StepParams p,
     for (int k = 0; k < kZoneMoments; ++k) mom[k] = 0.0;
     if (t < a.n) {
         const int s = a.slot_begin >= 0 ? a.slot_begin + t : b.id2slot[a.id_base + t];
-        const float4 xf = b.xr[s], vf = b.vm[s], wf = b.wi[s];
+        const float4 xf = b.xr[s], vf = vel_at(b.vw, s), wf = angv_at(b.vw, s);
         x[0] = xf.x; x[1] = xf.y; x[2] = xf.z;
         r = xf.w;
         z = zone_at(a, mz, x);

@@ -38,9 +38,6 @@ __device__ inline float dsilu(float z)
     return s * (1.0f + z * (1.0f - s));
 }
 
-// FP32 -> BF16 bits, round to nearest even (the hardware conversion)
-__device__ inline short to_bf16(float f) { return __builtin_bit_cast(short, (__bf16)f); }
-
 // SiLU of the BF16 inference: the hardware reciprocal (about 1 ulp) in place
 // of a full division
 __device__ inline float silu_fast(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
@@ -284,7 +281,7 @@ void launch_learned_lam(const DevBuffers& b, const StepParams& p, const Sizes& z
 // B[k][j] -> lane j + 32 k, D[i][j] -> lane j + 32 ((i / 4) % 2), element
 // (i % 4) + 4 (i / 8).
 // ---------------------------------------------------------------------------
-constexpr int kTrainWaves = 4, kTrainMaxTiles = 4;
+constexpr int kTrainWaves = 4;
 constexpr int kTP = kH + 1;  // LDS pitch of the 64-wide rows
 
 // tiles per wave and blocks of a batch of B samples

@@ -44,7 +44,7 @@ __global__ void k_coarse_grain(DevBuffers b, EnvDev E, tr_voxel_grid g, int kern
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= E.n) return;
     const int sl = E.slot_begin + a;
-    const float4 xf = b.xr[sl], vf = b.vm[sl];
+    const float4 xf = b.xr[sl], vf = vel_at(b.vw, sl);
     const double x[3] = {xf.x, xf.y, xf.z}, v[3] = {vf.x, vf.y, vf.z};
     const double r = xf.w;
     const double m = (double)b.rho[sl] * (4.0 / 3.0) * 3.14159265358979323846 * r * r * r;
@@ -707,8 +707,8 @@ __global__ void k_grow_apply(DevBuffers b, EnvDev E, tr_voxel_grid g, double dt,
     atomicAdd(&used[v], m_new - m);
     xr.w = r_new;
     b.xr[sl] = xr;
-    b.vm[sl].w = (float)(1.0 / m_new);
-    b.wi[sl].w = (float)(1.0 / (0.4 * m_new * rn * rn));
+    vel_at(b.vw, sl).w = (float)(1.0 / m_new);
+    angv_at(b.vw, sl).w = (float)(1.0 / (0.4 * m_new * rn * rn));
 }
 
 __global__ void k_grow_fluid(int64_t nv, double* mf, const double* used, double* total)
@@ -810,7 +810,7 @@ __global__ void k_settle(DevBuffers b, EnvDev E, tr_voxel_grid g, double v_rest,
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= E.n) return;
     const int sl = E.slot_begin + a;
-    const float4 xr = b.xr[sl], vm = b.vm[sl];
+    const float4 xr = b.xr[sl], vm = vel_at(b.vw, sl);
     const double v[3] = {vm.x, vm.y, vm.z};
     if (!(sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]) < v_rest)) return;
     const int64_t vox = voxel_index(g, xr);

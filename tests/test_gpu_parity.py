@@ -257,3 +257,11 @@ def test_empty_env_and_no_contacts():
     assert st["contacts"] == 0 and st["overflow"] == 0
     p = g.get_particles(0)
     assert p["v"][0, 2] == pytest.approx(-2 * 9.81 / 60.0, rel=1e-6)
+
+
+def test_particle_capacity_limit():
+    # the solver addresses each particle's 32 B velocity record with a 31-bit
+    # byte offset: at most 2^26 particle slots over all envs
+    with pytest.raises(T.TerrainError) as ei:
+        T.Scene(n_envs=2, cap_particles=(1 << 25) + 1, cap_contacts=16, env_bounds=[(0, 0, 0, 1, 1, 1)] * 2)
+    assert ei.value.code == T.TR_E_CAPACITY
