@@ -1316,6 +1316,8 @@ struct XcdBodies {
     __device__ float4 v(int i) const { return ld_body<kCoherent>(r, 2 * i); }
     __device__ float4 w(int i) const { return ld_body<kCoherent>(r, 2 * i + 1); }
     __device__ void set(int i, float4 v, float4 w) const { st_body<0>(r, 2 * i, v); st_body<0>(r, 2 * i + 1, w); }
+    __device__ float4 half(int i, int h) const { return ld_body<kCoherent>(r, 2 * i + h); }
+    __device__ void set_half(int i, int h, float4 v) const { st_body<0>(r, 2 * i + h, v); }
 };
 // Spread mode: one env's contacts on all XCDs, so every body store is written
 // through (sc1) and every load is device-scope: measured on MI355X, such a
@@ -1329,12 +1331,16 @@ struct SpreadBodies {
         st_body<kCoherent>(r, 2 * i, v);
         st_body<kCoherent>(r, 2 * i + 1, w);
     }
+    __device__ float4 half(int i, int h) const { return ld_body<kCoherent>(r, 2 * i + h); }
+    __device__ void set_half(int i, int h, float4 v) const { st_body<kCoherent>(r, 2 * i + h, v); }
 };
 struct PlainBodies {
     float4* vw;
     __device__ float4 v(int i) const { return vel_at(vw, i); }
     __device__ float4 w(int i) const { return angv_at(vw, i); }
     __device__ void set(int i, float4 v, float4 w) const { vel_at(vw, i) = v; angv_at(vw, i) = w; }
+    __device__ float4 half(int i, int h) const { return vw[2 * i + h]; }
+    __device__ void set_half(int i, int h, float4 v) const { vw[2 * i + h] = v; }
 };
 struct LdsBodies {
     float4 *sv, *sw;  // env slots [base, base + n)
@@ -1365,13 +1371,94 @@ __device__ inline BodyRegs load_bodies(const BA& ba, const RowRegs& R)
     return B;
 }
 
+// Lane pairs.  A wave's body loads and stores scatter: each lane's 16 B
+// lands in its own memory line, and the vector memory unit's throughput in
+// lines, not bytes, bounds the colour phase.  Lanes 2k and 2k+1 therefore
+// access the two 32 B records of their two contacts' sphere together: the
+// even lane the velocity half and the odd lane the angular half of the even
+// lane's record, then the same for the odd lane's record, and exchange what
+// the other needs.  Two lanes share each line an instruction touches; the
+// values are those of the lane's own loads and stores.  Both lanes of a pair
+// must be active (the swap reads the partner); a lane without a contact
+// loads its partner's records and stores nothing.
+__device__ inline int pair_swap(int x) { return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false); }
+__device__ inline float pair_swap(float x) { return __int_as_float(pair_swap(__float_as_int(x))); }
+__device__ inline float4 pair_swap(float4 x)
+{
+    return make_float4(pair_swap(x.x), pair_swap(x.y), pair_swap(x.z), pair_swap(x.w));
+}
+
+// the record of sphere self (own: the lane has a contact) as (v, w)
 template <class BA>
-__device__ inline void pgs_contact(const DevBuffers& b, const BA& ba, uint32_t c, const RowRegs& R, BodyRegs B,
-                                   float mu, float gdt, float& num, float& den, bool roll)
+__device__ inline void pair_load(const BA& ba, int self, bool own, int odd, float4& v, float4& w)
+{
+    int part = pair_swap(own ? self : -1);
+    if (!own) self = part;      // no contact: the partner's record, never stored
+    if (part < 0) part = self;  // the partner has no contact: this lane's record twice
+    const int r1 = odd ? part : self, r2 = odd ? self : part;  // the even lane's sphere, the odd lane's
+    const float4 x1 = ba.half(r1, odd), x2 = ba.half(r2, odd);
+    const float4 recv = pair_swap(odd ? x1 : x2);
+    v = odd ? recv : x1;
+    w = odd ? x2 : recv;
+}
+
+// stores (v, w) as the record of sphere self when want
+template <class BA>
+__device__ inline void pair_store(const BA& ba, int self, bool want, int odd, float4 v, float4 w)
+{
+    const int part = pair_swap(self);
+    const bool pwant = pair_swap(want ? 1 : 0) != 0;
+    const float4 recv = pair_swap(odd ? v : w);
+    const int r1 = odd ? part : self, r2 = odd ? self : part;
+    if (odd ? pwant : want) ba.set_half(r1, odd, odd ? recv : v);
+    if (odd ? want : pwant) ba.set_half(r2, odd, odd ? w : recv);
+}
+
+template <class BA>
+__device__ inline BodyRegs pair_bodies(const BA& ba, const RowRegs& R, bool own, int odd)
+{
+    BodyRegs B;
+    const int ia = __float_as_int(R.q.z), ib = __float_as_int(R.q.w);
+    pair_load(ba, ib, own, odd, B.vb, B.wb);
+    pair_load(ba, ia >= 0 ? ia : ib, own, odd, B.va, B.wa);
+    return B;
+}
+
+template <class BA>
+__device__ inline void pair_store_bodies(const BA& ba, const RowRegs& R, const BodyRegs& B, bool own, int odd)
+{
+    const int ia = __float_as_int(R.q.z), ib = __float_as_int(R.q.w);
+    pair_store(ba, ib, own, odd, B.vb, B.wb);
+    pair_store(ba, ia, own && ia >= 0, odd, B.va, B.wa);
+}
+
+// a contact's bodies with lane pairs (LANES) or by each lane alone (then own
+// is true wherever these are called)
+template <bool LANES, class BA>
+__device__ inline BodyRegs get_bodies(const BA& ba, const RowRegs& R, bool own, int odd)
+{
+    if (LANES) return pair_bodies(ba, R, own, odd);
+    return load_bodies(ba, R);
+}
+template <bool LANES, class BA>
+__device__ inline void put_bodies(const BA& ba, const RowRegs& R, const BodyRegs& B, bool own, int odd)
+{
+    if (LANES) {
+        pair_store_bodies(ba, R, B, own, odd);
+        return;
+    }
+    const int ia = __float_as_int(R.q.z), ib = __float_as_int(R.q.w);
+    ba.set(ib, B.vb, B.wb);
+    if (ia >= 0) ba.set(ia, B.va, B.wa);
+}
+
+// One contact's update on the loaded bodies B (left in B), its impulses
+// written; the caller stores the bodies.
+__device__ inline void pgs_update(const DevBuffers& b, uint32_t c, const RowRegs& R, BodyRegs& B, float mu, float gdt,
+                                  float& num, float& den, bool roll)
 {
     float4 a = R.a, r1 = R.r1, q = R.q, L = R.L;
-    int ia = __float_as_int(q.z), ib = __float_as_int(q.w);
-    bool pair = ia >= 0;
+    bool pair = __float_as_int(q.z) >= 0;
     float4 vb = B.vb, wb = B.wb, va = B.va, wa = B.wa;
     if (!pair) {
         va = make_float4(R.k.x, R.k.y, R.k.z, 0.f);
@@ -1441,9 +1528,18 @@ __device__ inline void pgs_contact(const DevBuffers& b, const BA& ba, uint32_t c
         num += Wr * (ex * ex + ey * ey + ez * ez);
         den += Wr * (rx * rx + ry * ry + rz * rz);
     }
-    ba.set(ib, vb, wb);
-    if (pair) ba.set(ia, va, wa);
     b.lam[c] = make_float4(ln, tx, ty, tz);
+    B.vb = vb; B.wb = wb; B.va = va; B.wa = wa;
+}
+
+template <class BA>
+__device__ inline void pgs_contact(const DevBuffers& b, const BA& ba, uint32_t c, const RowRegs& R, BodyRegs B,
+                                   float mu, float gdt, float& num, float& den, bool roll)
+{
+    pgs_update(b, c, R, B, mu, gdt, num, den, roll);
+    const int ia = __float_as_int(R.q.z), ib = __float_as_int(R.q.w);
+    ba.set(ib, B.vb, B.wb);
+    if (ia >= 0) ba.set(ia, B.va, B.wa);
 }
 
 // block sums of the sweep's (num, den) in a fixed order, returned to every thread
@@ -1552,10 +1648,15 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
     };
     auto resid = [](double sn, double sd) { return sd > 0.0 ? sqrt(sn) / sqrt(sd) : (sn > 0.0 ? 1.0 : 0.0); };
     uint32_t lo = 0, hi = 0, c = 0;
-    // a thread's first contact of a colour and, when the colour needs a second
-    // pass, its second: both fetched ahead (while the block waits at a barrier)
-    // (512-thread blocks only: the 1024-thread instances have no registers to spare)
+    // 512-thread instances: a thread's first contact of a colour and, when the
+    // colour needs a second pass, its second, both fetched ahead (while the
+    // block waits at a barrier), and the following two fetched during their
+    // updates.  The 1024-thread instances take one contact at a time (two
+    // would spill registers: measured slower).  Lane pairs (pair_load) in
+    // every instance but the rolling 1024-thread one, which has no registers
+    // for them.
     constexpr bool kPair = !FLOW && NW <= 8;
+    constexpr bool kLanes = !FLOW && (NW <= 8 || !ROLL);
     RowRegs cur, cur2;
     auto fetch = [&]() {
         if (c < hi) cur = load_rows(b, c, ROLL);
@@ -1573,30 +1674,11 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
             // the rows prefetched for this colour: settled here, outside the
             // loop, so that the loop waits only for its own loads
             if (!FLOW) __builtin_amdgcn_s_waitcnt(0);
-            while (c < hi) {
-                uint32_t cn = c + kThreads;
-                if (kPair && cn < hi) {
-                    // two contacts of one colour share no sphere: both gathers
-                    // in flight before either update (same order of updates
-                    // and of the residual sums as one contact at a time)
-                    BodyRegs B1 = load_bodies(ba, cur);
-                    BodyRegs B2 = load_bodies(ba, cur2);
-                    const uint32_t c3 = cn + kThreads;
-                    RowRegs n1, n2;
-                    if (c3 < hi) n1 = load_rows(b, c3, ROLL);
-                    if (c3 + kThreads < hi) n2 = load_rows(b, c3 + kThreads, ROLL);
-                    pgs_contact(b, ba, c, cur, B1, p.mu, p.gamma_dt, num, den, ROLL);
-                    pgs_contact(b, ba, cn, cur2, B2, p.mu, p.gamma_dt, num, den, ROLL);
-                    cur = n1;
-                    cur2 = n2;
-                    c = c3;
-                    continue;
-                }
-                BodyRegs B;
-                if (!FLOW) B = load_bodies(ba, cur);
-                RowRegs nxt;
-                if (cn < hi) nxt = load_rows(b, cn, ROLL);
-                if (FLOW) {
+            if (FLOW) {
+                while (c < hi) {
+                    const uint32_t cn = c + kThreads;
+                    RowRegs nxt;
+                    if (cn < hi) nxt = load_rows(b, cn, ROLL);
                     const uint32_t seq = __float_as_uint(cur.k.w);
                     const int ia = __float_as_int(cur.q.z), ib = __float_as_int(cur.q.w);
                     const uint32_t wa = (uint32_t)sw * ((seq >> 16) & 255u) + (seq & 255u);
@@ -1610,11 +1692,45 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                         __hip_atomic_store(&b.ver[ib], wb + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if (ia >= 0) __hip_atomic_store(&b.ver[ia], wa + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
-                } else {
-                    pgs_contact(b, ba, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
+                    cur = nxt;
+                    c = cn;
                 }
-                cur = nxt;
-                c = cn;
+            } else {
+                // lane pairs (pair_load): a pair runs while its even lane has a
+                // contact (kThreads is even, so the even lane's contacts are
+                // c - odd + k kThreads); the odd lane may have one fewer
+                const int odd = kLanes ? (int)(threadIdx.x & 1u) : 0;
+                while (c - odd < hi) {
+                    const uint32_t cn = c + kThreads;
+                    const bool own = c < hi;
+                    if (kPair && cn - odd < hi) {
+                        // two contacts of one colour share no sphere: both gathers
+                        // in flight before either update (same order of updates
+                        // and of the residual sums as one contact at a time)
+                        const bool own2 = cn < hi;
+                        BodyRegs B1 = get_bodies<kLanes>(ba, cur, true, odd);
+                        BodyRegs B2 = get_bodies<kLanes>(ba, cur2, own2, odd);
+                        const uint32_t c3 = cn + kThreads;
+                        RowRegs n1, n2;
+                        if (c3 < hi) n1 = load_rows(b, c3, ROLL);
+                        if (c3 + kThreads < hi) n2 = load_rows(b, c3 + kThreads, ROLL);
+                        pgs_update(b, c, cur, B1, p.mu, p.gamma_dt, num, den, ROLL);
+                        if (own2) pgs_update(b, cn, cur2, B2, p.mu, p.gamma_dt, num, den, ROLL);
+                        put_bodies<kLanes>(ba, cur, B1, true, odd);
+                        put_bodies<kLanes>(ba, cur2, B2, own2, odd);
+                        cur = n1;
+                        cur2 = n2;
+                        c = c3;
+                        continue;
+                    }
+                    BodyRegs B = get_bodies<kLanes>(ba, cur, own, odd);
+                    RowRegs nxt;
+                    if (cn < hi) nxt = load_rows(b, cn, ROLL);
+                    if (own) pgs_update(b, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
+                    put_bodies<kLanes>(ba, cur, B, own, odd);
+                    cur = nxt;
+                    c = cn;
+                }
             }
             if (CLUSTER && !FLOW && col >= tail && col + 1 < ncol) {
                 // inside the tail: the block's stores drained, then a workgroup
