@@ -20,7 +20,8 @@
 //                  Gauss-Seidel, whose sweeps then confirm it (the regularised
 //                  rows of a rigid body with redundant points contract by only
 //                  about 1 - gamma / W per sweep, so Gauss-Seidel alone needs
-//                  ~1e5 sweeps for a stiff bulk)
+//                  ~1e5 sweeps for a stiff bulk); where Newton stalls at a
+//                  kink of the projections, eight sweeps and a restart
 //
 // Readings: the zone's half-spaces follow the wedge convention (plane 0 the
 // separation plate, plane 1 the failure plane); AB candidates are the zone's
@@ -454,8 +455,9 @@ struct SolveShared {
     double Fd[6], Kd[6];           // drive impulses and their derivatives
     double A[144];                 // Jacobian, then its LU factors
     double Wn[8], Wt[8], lam[8][4];
+    double V[12], ld[6];           // velocities and drive impulses of the Gauss-Seidel sweeps
     double g, scale, Lc;
-    int piv, ok, run, map[8];
+    int piv, ok, run, again, map[8];
 };
 
 // G(w) = w - w0 - M^-1 F(w), F the generalized impulse of every row at its
@@ -590,6 +592,95 @@ __device__ bool lu_solve(SolveShared& sh, int nd)
         }
     __syncthreads();
     return true;
+}
+
+// Up to nsw sweeps of the rows' projected Gauss-Seidel (one lane): the
+// impulses sh.lam and drive impulses sh.ld, with the velocities sh.V (v, w of
+// the aggregate, then of a dynamic equipment) that they give.  Returns the
+// sweeps done, negated when the stopping rule (no impulse changed by more
+// than 1e-15 of the largest) was not met within nsw.
+__device__ int pgs_sweeps(SolveShared& sh, bool E, int nsw)
+{
+    const MacroSys& Q = sh.S;
+    const int np = Q.np;
+    double* vv = sh.V;
+    double* ww = sh.V + 3;
+    double* vB = sh.V + 6;
+    double* wB = sh.V + 9;
+    double* ld = sh.ld;
+    for (int sweep = 0; sweep < nsw; ++sweep) {
+        double dmax = 0.0, lmax = 0.0, t[3];
+        for (int c = 0; c < np; ++c) {
+            const double* nn = Q.n[c];
+            for (int row = 0; row < 2; ++row) {
+                double u[3], J[3];
+                cross3d(ww, Q.rr[c], t);
+                for (int k = 0; k < 3; ++k) u[k] = vv[k] + t[k] - Q.uo[c][k];
+                if (Q.onB[c]) {
+                    cross3d(wB, Q.rb[c], t);
+                    for (int k = 0; k < 3; ++k) u[k] -= vB[k] + t[k];
+                }
+                const double un = dot3d(nn, u);
+                if (row == 0) {
+                    double ln = sh.lam[c][0] - (un + Q.gam[c] * sh.lam[c][0]) / (sh.Wn[c] + Q.gam[c]);
+                    if (ln < Q.lo[c]) ln = Q.lo[c];
+                    const double d = ln - sh.lam[c][0];
+                    sh.lam[c][0] = ln;
+                    for (int k = 0; k < 3; ++k) J[k] = d * nn[k];
+                    if (fabs(d) > dmax) dmax = fabs(d);
+                } else {
+                    double lt[3];
+                    for (int k = 0; k < 3; ++k) {
+                        const double ut = u[k] - un * nn[k];
+                        lt[k] = sh.lam[c][1 + k] - (ut + Q.gam[c] * sh.lam[c][1 + k]) / (sh.Wt[c] + Q.gam[c]);
+                    }
+                    const double ltn = dot3d(lt, nn);
+                    for (int k = 0; k < 3; ++k) lt[k] -= ltn * nn[k];
+                    const double lim = Q.mu[c] * fabs(sh.lam[c][0]);
+                    const double m2 = sqrt(dot3d(lt, lt));
+                    if (m2 > lim) {
+                        const double sc = m2 > 0.0 ? lim / m2 : 0.0;
+                        for (int k = 0; k < 3; ++k) lt[k] *= sc;
+                    }
+                    for (int k = 0; k < 3; ++k) {
+                        J[k] = lt[k] - sh.lam[c][1 + k];
+                        if (fabs(J[k]) > dmax) dmax = fabs(J[k]);
+                        sh.lam[c][1 + k] = lt[k];
+                    }
+                }
+                double tj[3], dw[3];
+                cross3d(Q.rr[c], J, tj);
+                mat3v(Q.Iinv, tj, dw);
+                for (int k = 0; k < 3; ++k) { vv[k] += Q.invM * J[k]; ww[k] += dw[k]; }
+                if (Q.onB[c]) {
+                    cross3d(Q.rb[c], J, tj);
+                    mat3v(Q.IBinv, tj, dw);
+                    for (int k = 0; k < 3; ++k) { vB[k] -= Q.invMB * J[k]; wB[k] -= dw[k]; }
+                }
+            }
+            for (int k = 0; k < 4; ++k)
+                if (fabs(sh.lam[c][k]) > lmax) lmax = fabs(sh.lam[c][k]);
+        }
+        if (E) {
+            for (int k = 0; k < 6; ++k) {
+                const int ax = k % 3;
+                const double u = k < 3 ? vB[ax] - Q.target[k] : wB[ax] - Q.target[k];
+                const double W = k < 3 ? Q.invMB : Q.IBinv[ax][ax];
+                double l = ld[k] - (u + Q.gd * ld[k]) / (W + Q.gd);
+                if (l > Q.lim[k]) l = Q.lim[k];
+                if (l < -Q.lim[k]) l = -Q.lim[k];
+                const double d = l - ld[k];
+                ld[k] = l;
+                if (k < 3) vB[ax] += Q.invMB * d;
+                else
+                    for (int j = 0; j < 3; ++j) wB[j] += Q.IBinv[j][ax] * d;
+                if (fabs(d) > dmax) dmax = fabs(d);
+                if (fabs(l) > lmax) lmax = fabs(l);
+            }
+        }
+        if (dmax <= 1e-15 * lmax || lmax == 0.0) return sweep + 1;
+    }
+    return -nsw;
 }
 
 // one wave per zone (grid = zones, 64 threads)
@@ -734,139 +825,96 @@ __global__ void __launch_bounds__(64) k_macro_solve(DevBuffers b, StepParams p, 
         // bodies' velocities (six, or twelve with a dynamic equipment) with each
         // row's impulse in closed form, then the rows' projected Gauss-Seidel
         // from there until no impulse changes (one or two sweeps when Newton
-        // converged, else it finishes the solve)
+        // converged).  Where Newton stalls (at a kink of the projections the
+        // residual's norm is a poor merit: no step of eight halvings lowers
+        // it), a few Gauss-Seidel sweeps from its point move the active set
+        // and Newton restarts from where they end.
+        constexpr int kRounds = 8, kRoundSweeps = 8, kHalvings = 8;
         const int nd = sh.S.ndof, np = sh.S.np;
         if (lane < nd) sh.w[lane] = sh.w0[lane];
-        __syncthreads();
-        eval_G(sh, sh.w, sh.G, true);
-        if (lane == 0) sh.g = gnorm(sh.G, nd, sh.Lc);
-        __syncthreads();
-        int its = 0;
-        for (; its < 100; ++its) {
-            if (!(sh.g > 1e-15 * sh.scale)) break;
-            if (lane < nd) sh.d[lane] = -sh.G[lane];
-            __syncthreads();
-            if (!lu_solve(sh, nd)) break;
-            double step = 1.0;
-            bool took = false;
-            for (int ls = 0; ls < 40; ++ls, step *= 0.5) {
-                if (lane < nd) sh.wt[lane] = sh.w[lane] + step * sh.d[lane];
-                __syncthreads();
-                eval_G(sh, sh.wt, sh.Gt, false);
-                if (lane == 0) {
-                    const double gt = gnorm(sh.Gt, nd, sh.Lc);
-                    sh.ok = gt < (1.0 - 1e-4 * step) * sh.g;
-                    if (sh.ok) sh.g = gt;
-                }
-                __syncthreads();
-                if (sh.ok) {
-                    took = true;
-                    break;
-                }
-            }
-            if (!took) break;
-            if (lane < nd) sh.w[lane] = sh.wt[lane];
+        int its = 0, sweeps = 0;
+        for (int round = 0; round < kRounds; ++round) {
             __syncthreads();
             eval_G(sh, sh.w, sh.G, true);
             if (lane == 0) sh.g = gnorm(sh.G, nd, sh.Lc);
             __syncthreads();
+            for (int it = 0; it < 100; ++it) {
+                if (!(sh.g > 1e-15 * sh.scale)) break;
+                if (lane < nd) sh.d[lane] = -sh.G[lane];
+                __syncthreads();
+                if (!lu_solve(sh, nd)) break;
+                double step = 1.0;
+                bool took = false;
+                for (int ls = 0; ls < kHalvings; ++ls, step *= 0.5) {
+                    if (lane < nd) sh.wt[lane] = sh.w[lane] + step * sh.d[lane];
+                    __syncthreads();
+                    eval_G(sh, sh.wt, sh.Gt, false);
+                    if (lane == 0) {
+                        const double gt = gnorm(sh.Gt, nd, sh.Lc);
+                        sh.ok = gt < (1.0 - 1e-4 * step) * sh.g;
+                        if (sh.ok) sh.g = gt;
+                    }
+                    __syncthreads();
+                    if (sh.ok) {
+                        took = true;
+                        break;
+                    }
+                }
+                if (!took) break;
+                ++its;
+                if (lane < nd) sh.w[lane] = sh.wt[lane];
+                __syncthreads();
+                eval_G(sh, sh.w, sh.G, true);
+                if (lane == 0) sh.g = gnorm(sh.G, nd, sh.Lc);
+                __syncthreads();
+            }
+            // the impulses and velocities at the Newton point (the last
+            // evaluation may have been a rejected trial)
+            eval_G(sh, sh.w, sh.G, false);
+            if (lane == 0) {
+                const MacroSys& Q = sh.S;
+                for (int c = 0; c < np; ++c)
+                    for (int k = 0; k < 4; ++k) sh.lam[c][k] = sh.lamp[c][k];
+                double t[3];
+                for (int k = 0; k < 6; ++k) sh.ld[k] = E ? sh.Fd[k] : 0.0;
+                mat3v(Q.Iinv, sh.F + 3, t);
+                for (int k = 0; k < 3; ++k) { sh.V[k] = sh.w0[k] + Q.invM * sh.F[k]; sh.V[3 + k] = sh.w0[3 + k] + t[k]; }
+                if (E) {
+                    mat3v(Q.IBinv, sh.F + 9, t);
+                    for (int k = 0; k < 3; ++k) {
+                        sh.V[6 + k] = sh.w0[6 + k] + Q.invMB * sh.F[6 + k];
+                        sh.V[9 + k] = sh.w0[9 + k] + t[k];
+                    }
+                } else {
+                    for (int k = 0; k < 3; ++k) { sh.V[6 + k] = B.linvel[k]; sh.V[9 + k] = B.angvel[k]; }
+                }
+                sh.again = 0;
+                if (sh.g > 1e-15 * sh.scale && round + 1 < kRounds) {
+                    const int r = pgs_sweeps(sh, E != nullptr, kRoundSweeps);
+                    sweeps += r > 0 ? r : -r;
+                    if (r < 0) sh.again = 1;
+                    else sh.again = 2;  // the sweeps met the stopping rule
+                    if (r < 0)
+                        for (int k = 0; k < nd; ++k) sh.w[k] = sh.V[k];
+                }
+            }
+            __syncthreads();
+            if (sh.again != 1) break;
         }
-        // the impulses and velocities at the Newton point (the last evaluation
-        // may have been a rejected trial)
-        eval_G(sh, sh.w, sh.G, false);
         if (lane == 0) {
             const MacroSys& Q = sh.S;
             tr_macro_result& o = sh.o;
-            for (int c = 0; c < np; ++c)
-                for (int k = 0; k < 4; ++k) sh.lam[c][k] = sh.lamp[c][k];
-            double vv[3], ww[3], vB[3], wB[3], ld[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, t[3];
-            if (E)
-                for (int k = 0; k < 6; ++k) ld[k] = sh.Fd[k];
-            mat3v(Q.Iinv, sh.F + 3, t);
-            for (int k = 0; k < 3; ++k) { vv[k] = sh.w0[k] + Q.invM * sh.F[k]; ww[k] = sh.w0[3 + k] + t[k]; }
-            if (E) {
-                mat3v(Q.IBinv, sh.F + 9, t);
-                for (int k = 0; k < 3; ++k) { vB[k] = sh.w0[6 + k] + Q.invMB * sh.F[6 + k]; wB[k] = sh.w0[9 + k] + t[k]; }
-            } else {
-                for (int k = 0; k < 3; ++k) { vB[k] = B.linvel[k]; wB[k] = B.angvel[k]; }
+            if (sh.again != 2) {
+                const int r = pgs_sweeps(sh, E != nullptr, 200000);
+                sweeps += r > 0 ? r : -r;
             }
-            int sweep = 0;
-            for (; sweep < 200000; ++sweep) {
-                double dmax = 0.0, lmax = 0.0;
-                for (int c = 0; c < np; ++c) {
-                    const double* nn = Q.n[c];
-                    for (int row = 0; row < 2; ++row) {
-                        double u[3], J[3];
-                        cross3d(ww, Q.rr[c], t);
-                        for (int k = 0; k < 3; ++k) u[k] = vv[k] + t[k] - Q.uo[c][k];
-                        if (Q.onB[c]) {
-                            cross3d(wB, Q.rb[c], t);
-                            for (int k = 0; k < 3; ++k) u[k] -= vB[k] + t[k];
-                        }
-                        const double un = dot3d(nn, u);
-                        if (row == 0) {
-                            double ln = sh.lam[c][0] - (un + Q.gam[c] * sh.lam[c][0]) / (sh.Wn[c] + Q.gam[c]);
-                            if (ln < Q.lo[c]) ln = Q.lo[c];
-                            const double d = ln - sh.lam[c][0];
-                            sh.lam[c][0] = ln;
-                            for (int k = 0; k < 3; ++k) J[k] = d * nn[k];
-                            if (fabs(d) > dmax) dmax = fabs(d);
-                        } else {
-                            double lt[3];
-                            for (int k = 0; k < 3; ++k) {
-                                const double ut = u[k] - un * nn[k];
-                                lt[k] = sh.lam[c][1 + k] - (ut + Q.gam[c] * sh.lam[c][1 + k]) / (sh.Wt[c] + Q.gam[c]);
-                            }
-                            const double ltn = dot3d(lt, nn);
-                            for (int k = 0; k < 3; ++k) lt[k] -= ltn * nn[k];
-                            const double lim = Q.mu[c] * fabs(sh.lam[c][0]);
-                            const double m2 = sqrt(dot3d(lt, lt));
-                            if (m2 > lim) {
-                                const double sc = m2 > 0.0 ? lim / m2 : 0.0;
-                                for (int k = 0; k < 3; ++k) lt[k] *= sc;
-                            }
-                            for (int k = 0; k < 3; ++k) {
-                                J[k] = lt[k] - sh.lam[c][1 + k];
-                                if (fabs(J[k]) > dmax) dmax = fabs(J[k]);
-                                sh.lam[c][1 + k] = lt[k];
-                            }
-                        }
-                        double tj[3], dw[3];
-                        cross3d(Q.rr[c], J, tj);
-                        mat3v(Q.Iinv, tj, dw);
-                        for (int k = 0; k < 3; ++k) { vv[k] += Q.invM * J[k]; ww[k] += dw[k]; }
-                        if (Q.onB[c]) {
-                            cross3d(Q.rb[c], J, tj);
-                            mat3v(Q.IBinv, tj, dw);
-                            for (int k = 0; k < 3; ++k) { vB[k] -= Q.invMB * J[k]; wB[k] -= dw[k]; }
-                        }
-                    }
-                    for (int k = 0; k < 4; ++k)
-                        if (fabs(sh.lam[c][k]) > lmax) lmax = fabs(sh.lam[c][k]);
-                }
-                if (E) {
-                    for (int k = 0; k < 6; ++k) {
-                        const int ax = k % 3;
-                        const double u = k < 3 ? vB[ax] - Q.target[k] : wB[ax] - Q.target[k];
-                        const double W = k < 3 ? Q.invMB : Q.IBinv[ax][ax];
-                        double l = ld[k] - (u + Q.gd * ld[k]) / (W + Q.gd);
-                        if (l > Q.lim[k]) l = Q.lim[k];
-                        if (l < -Q.lim[k]) l = -Q.lim[k];
-                        const double d = l - ld[k];
-                        ld[k] = l;
-                        if (k < 3) vB[ax] += Q.invMB * d;
-                        else
-                            for (int j = 0; j < 3; ++j) wB[j] += Q.IBinv[j][ax] * d;
-                        if (fabs(d) > dmax) dmax = fabs(d);
-                        if (fabs(l) > lmax) lmax = fabs(l);
-                    }
-                }
-                if (dmax <= 1e-15 * lmax || lmax == 0.0) {
-                    ++sweep;
-                    break;
-                }
-            }
-            o.sweeps = its + sweep;
+            const double* vv = sh.V;
+            const double* ww = sh.V + 3;
+            const double* vB = sh.V + 6;
+            const double* wB = sh.V + 9;
+            const double* ld = sh.ld;
+            double t[3];
+            o.sweeps = its + sweeps;
             for (int k = 0; k < 3; ++k) {
                 o.v[k] = vv[k]; o.w[k] = ww[k]; o.force[k] = 0.0; o.torque[k] = 0.0;
                 o.v_b[k] = vB[k]; o.w_b[k] = wB[k];

@@ -261,6 +261,18 @@ def test_bed_with_a_moving_tool_and_its_wedge(heading, tool):
     assert o["n_cand"][0] > 0 and o["n_cand"][1] > 4
 
 
+@pytest.mark.parametrize("seed,heading", [(24, 0.0), (72, 0.3)])
+def test_bed_where_newton_stalls_at_a_kink(seed, heading):
+    # seeded beds whose damped Newton iteration stalls (no step of eight
+    # halvings lowers the residual): a few Gauss-Seidel sweeps from its point
+    # and a restart reach the oracle's fixed point, where Gauss-Seidel alone
+    # needs thousands of sweeps
+    spec = bed_with_zone(seed, 3000, heading, "blade")
+    gpu, orc = check(spec, expect_zones=[1])
+    assert orc[0]["sweeps"] > 1000
+    assert gpu[0]["sweeps"] < 200
+
+
 def test_second_env_of_a_two_env_scene():
     a = bed_with_zone(41, 3000, 0.1)
     b = bed_with_zone(42, 5000, -0.3, tool="bucket")
