@@ -47,10 +47,12 @@ PAIR_BYTES, BOUND_BYTES = 176, 128
 # runs scaled by a copy kernel of known size (profiles named below); valid
 # only for the kernel source it was measured on, else reported as null.
 PGS_TRAFFIC = {
-    "batched": {"kernels_sha256_prefix": "1c97d3337b9f040b", "bytes_per_launch": 76.37e9,
+    "batched": {"kernels_sha256_prefix": "592d7951a5425c51", "bytes_per_launch": 64.42e9,
                 "profile": "profiles/k_pgs_env_batched256_hbm_traffic.md"},
-    "bed": {"kernels_sha256_prefix": "", "bytes_per_launch": None,
+    "bed": {"kernels_sha256_prefix": "592d7951a5425c51", "bytes_per_launch": 3.495e9,
             "profile": "profiles/k_pgs_bed50k_hbm_traffic.md"},
+    "excavation": {"kernels_sha256_prefix": "592d7951a5425c51", "bytes_per_launch": 78.22e9,
+                   "profile": "profiles/k_pgs_excavation500k_hbm_traffic.md"},
 }
 # The same for k_advect on the 256 x 256 x 128 voxel grid
 # (profiles/k_advect_voxels256_kernel_trace.md), keyed to terrain_voxels.hip.
@@ -306,7 +308,7 @@ def leg_excavation(args, weights=None, n=500000, sweeps=200):
                zone_mass_kg=float(agg[0]["M"]) if agg else 0.0,
                macro_step=time_macro(sc),
                macro_step_driven_bucket=time_macro(sc, equipment=bucket_equipment(1, speed)),
-               roofline=roofline(tot, pgs_kernel_name(sc), "bed"))
+               roofline=roofline(tot, pgs_kernel_name(sc), "excavation"))
     sc.close()
     return out
 
