@@ -518,8 +518,15 @@ int set_learned_precision(tr_scene* s, int32_t use_bf16);
  * contact frame / (m_eff g dt), the two depths below the column top / mean
  * radius, the two radii / r_ref, is_boundary, is_persistent) and the step's
  * final impulses in the same frame / (m_eff g dt) (label, 3 per contact).
- * Writes min(cap, count) entries and the count to *n.  Synchronises. */
+ * Writes min(cap, count) entries and the count to *n.  Synchronises.
+ * TR_E_STATE when the last step wrote no features: a step writes them when
+ * it runs the learned start (LEARNED with weights) or capture is on. */
 int get_learn_samples(tr_scene* s, int32_t env, int64_t cap, float* feat, float* label, int64_t* n);
+
+/* Nonzero: every following step writes the learned start's inputs of its
+ * contacts for get_learn_samples (80 B per contact; off by default, when a
+ * step writes them only for the learned start it runs). */
+int set_learn_capture(tr_scene* s, int32_t on);
 
 /* ---- learned-start network on device buffers (training support) ----
  * weights: the set_mlp_weights layout (W1, b1, W2, b2, W3, b3, in_scale), in

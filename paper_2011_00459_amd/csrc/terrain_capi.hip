@@ -71,6 +71,8 @@ struct tr_scene {
     int64_t cols_alloc = 0;
     bool mlp_loaded = false;
     bool mlp_bf16 = true;
+    bool capture = false;             // set_learn_capture: every step writes the learned-start features
+    bool features_last = false;       // the last step wrote them
     tr_solver_config cfg{};           // PGS schedule
     int64_t plan_alloc = 0;           // plan tasks allocated
     int64_t plan_idx_alloc = 0;       // plan block offsets allocated
@@ -811,6 +813,10 @@ void swap_step_buffers(tr_scene* s)
     std::swap(s->b.id_start, s->b.pid_start);
 }
 
+// the learned start's features are written when the step runs the network or
+// the caller captures training samples
+bool rows_features(const tr_scene* s) { return s->capture || (s->p.warm == TR_WARM_LEARNED && s->mlp_loaded); }
+
 // Every launch of one step, in stream order (A1-A12).  The sorted particle
 // arrays are written into the *2 buffers and swapped in; the canonical keys,
 // impulses and id ranges become the next step's previous-step cache.
@@ -825,7 +831,7 @@ void enqueue_step(tr_scene* s, hipStream_t st, bool events)
     if (events) (void)hipEventRecord(s->ev[1], st);
     launch_depth(s->b, s->p, s->z, st);
     launch_colour(s->b, s->p, s->z, st);
-    launch_rows(s->b, s->p, s->z, s->have_prev, st);
+    launch_rows(s->b, s->p, s->z, s->have_prev, rows_features(s), st);
     launch_impact_stage(s->b, s->p, s->z, st);
     if (s->p.warm == TR_WARM_LEARNED && s->mlp_loaded) {
         // learned start, then the first-sweep trial against the previous-step start
@@ -933,6 +939,7 @@ static int step_scene(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
         s->parity ^= 1;
         s->have_prev = true;
         s->stepped = true;
+        s->features_last = rows_features(s);
         s->slots_env_major = true;  // the step's sort orders the slots by (env, cell, id)
     }
     hipError_t e = hipGetLastError();
@@ -1652,6 +1659,15 @@ int set_particles(tr_scene* s, int32_t env, const double* pos, const double* vel
     return TR_OK;
 }
 
+int set_learn_capture(tr_scene* s, int32_t on)
+{
+    if (!s) return TR_E_INVAL;
+    s->err.clear();
+    if (s->capture != (on != 0)) invalidate_graphs(s);
+    s->capture = on != 0;
+    return TR_OK;
+}
+
 int set_learned_precision(tr_scene* s, int32_t use_bf16)
 {
     if (!s) return TR_E_INVAL;
@@ -1668,6 +1684,8 @@ int get_learn_samples(tr_scene* s, int32_t env, int64_t cap, float* feat, float*
     if (env < 0 || env >= s->desc.n_envs) return fail(s, TR_E_INVAL, "get_learn_samples: env");
     *n = 0;
     if (!s->stepped) return TR_OK;
+    if (!s->features_last)
+        return fail(s, TR_E_STATE, "get_learn_samples: the last step wrote no features (set_learn_capture)");
     HIP_CHECK(s, hipStreamSynchronize(s->stream));
     int64_t base = (int64_t)env * s->desc.cap_particles;
     uint32_t r[2];
@@ -1860,6 +1878,7 @@ int load_state(tr_scene* s, const void* buf, int64_t size)
     HIP_CHECK(s, hipMemcpy(s->body_host.data(), s->b.bodies, sizeof(BodyDev) * s->body_host.size(), hipMemcpyDeviceToHost));
     s->have_prev = h.have_prev != 0;
     s->stepped = h.stepped != 0;
+    s->features_last = false;  // the snapshot holds no features
     s->slots_env_major = false;  // the snapshot's slot order is not recorded; the next step restores it
     return TR_OK;
 }

@@ -284,7 +284,8 @@ void launch_sort_particles(const DevBuffers& b, const StepParams& p, const Sizes
 void launch_narrow(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_canonical(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
 void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
-void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, hipStream_t s);
+void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, bool features,
+                 hipStream_t s);
 // wedges of a conversion call: ranges of a wedge table
 constexpr int kMaxConvRanges = 8;
 struct WedgeSet {

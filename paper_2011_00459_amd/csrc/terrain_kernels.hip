@@ -834,7 +834,11 @@ __device__ inline float4 project_roll(float4 Lr, float lim)
     return Lr;
 }
 
-__global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
+// what k_rows writes beside the rows: the previous-step match, the learned
+// start's features and frame, the counter-ordered PGS's update sequence
+constexpr int kRowsPrev = 1, kRowsFeatures = 2, kRowsSeq = 4;
+
+__global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int flags)
 {
     uint32_t nc = n_contacts(b, cap);
     uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -910,7 +914,7 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     float4 L = make_float4(0.f, 0.f, 0.f, 0.f);
     float4 Lr = make_float4(0.f, 0.f, 0.f, 0.f);
     bool persistent = false;
-    if (use_prev) {
+    if (flags & kRowsPrev) {
         uint32_t a = (uint32_t)(key >> 32);
         uint32_t beg = b.pid_start[a], end = b.pid_start[a + 1];
         for (uint32_t t = beg; t < end; ++t)
@@ -923,7 +927,7 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     }
     uint32_t pos = b.cpos[c];
     // learned-start features (12), contact frame and impulse scale, in FP64
-    {
+    if (flags & kRowsFeatures) {
         float4 w2 = angv_at(b.vw, ib);
         double u[3];
         u[0] = ((double)v2.x - l2 * ((double)w2.y * n[2] - (double)w2.z * n[1])) - u1[0];
@@ -993,7 +997,7 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     // spheres (position among the sphere's contacts, and their count), for
     // the counter-ordered PGS
     uint32_t seq = 0;
-    {
+    if (flags & kRowsSeq) {
         const int col = b.colour[c];
         uint32_t pa = 0, da = 0, pb = 0, db = 0;
         auto place = [&](int sl, uint32_t& pr, uint32_t& dg) {
@@ -1039,9 +1043,11 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int use_prev)
     }
 }
 
-void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, hipStream_t s)
+void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, bool features,
+                 hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rows, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, p, z.C, have_prev ? 1 : 0);
+    const int flags = (have_prev ? kRowsPrev : 0) | (features ? kRowsFeatures : 0) | (z.flow ? kRowsSeq : 0);
+    hipLaunchKernelGGL(k_rows, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, p, z.C, flags);
 }
 
 // Impact stage set-up: the stage's impulses start at zero, and the rows of an
@@ -1318,6 +1324,12 @@ struct XcdBodies {
     __device__ void set(int i, float4 v, float4 w) const { st_body<0>(r, 2 * i, v); st_body<0>(r, 2 * i + 1, w); }
     __device__ float4 half(int i, int h) const { return ld_body<kCoherent>(r, 2 * i + h); }
     __device__ void set_half(int i, int h, float4 v) const { st_body<0>(r, 2 * i + h, v); }
+    // half h of record i into LDS at wave_lds + 16 B x lane (a load straight to LDS)
+    __device__ void stage_half(float4* wave_lds, int i, int h) const
+    {
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)wave_lds, 16,
+                                                 (2 * i + h) * 16, 0, 0, kCoherent);
+    }
 };
 // Spread mode: one env's contacts on all XCDs, so every body store is written
 // through (sc1) and every load is device-scope: measured on MI355X, such a
@@ -1333,6 +1345,11 @@ struct SpreadBodies {
     }
     __device__ float4 half(int i, int h) const { return ld_body<kCoherent>(r, 2 * i + h); }
     __device__ void set_half(int i, int h, float4 v) const { st_body<kCoherent>(r, 2 * i + h, v); }
+    __device__ void stage_half(float4* wave_lds, int i, int h) const
+    {
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)wave_lds, 16,
+                                                 (2 * i + h) * 16, 0, 0, kCoherent);
+    }
 };
 struct PlainBodies {
     float4* vw;
@@ -1341,6 +1358,11 @@ struct PlainBodies {
     __device__ void set(int i, float4 v, float4 w) const { vel_at(vw, i) = v; angv_at(vw, i) = w; }
     __device__ float4 half(int i, int h) const { return vw[2 * i + h]; }
     __device__ void set_half(int i, int h, float4 v) const { vw[2 * i + h] = v; }
+    __device__ void stage_half(float4* wave_lds, int i, int h) const
+    {
+        __builtin_amdgcn_global_load_lds((const void*)&vw[2 * i + h], (__attribute__((address_space(3))) void*)wave_lds,
+                                         16, 0, 0);
+    }
 };
 struct LdsBodies {
     float4 *sv, *sw;  // env slots [base, base + n)
@@ -1450,6 +1472,66 @@ __device__ inline void put_bodies(const BA& ba, const RowRegs& R, const BodyRegs
     const int ia = __float_as_int(R.q.z), ib = __float_as_int(R.q.w);
     ba.set(ib, B.vb, B.wb);
     if (ia >= 0) ba.set(ia, B.va, B.wa);
+}
+
+// Staging of a thread's second contact of a colour in LDS (1024-thread
+// blocks, which have no registers for two contacts in flight).  The layout,
+// in float4 per block thread t: rows a, r1, q, L, k at [j nthr + t], j < 5;
+// then the lane pairs' body halves x1, x2 of sphere b and of sphere a at
+// [(5 + j) nthr + t], j < 4, as pair_load leaves them in registers.  Loads go
+// straight to LDS (16 B per lane, lane order), so the second contact's rows
+// are fetched during the barrier and its bodies during the first contact's
+// update, without registers.
+constexpr int kStageFloat4 = 9;  // float4 per block thread
+
+__device__ inline void stage_rows(const DevBuffers& b, float4* st, uint32_t nthr, uint32_t c)
+{
+    const uint32_t w = threadIdx.x & ~63u;
+    const float4* src[5] = {b.r0, b.r1, b.r2, b.lam, b.rk};
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+        __builtin_amdgcn_global_load_lds((const void*)&src[j][c],
+                                         (__attribute__((address_space(3))) void*)(st + j * nthr + w), 16, 0, 0);
+}
+
+// the body halves of the contact whose indices are in q (own: the lane has
+// it), into the staging area, as pair_load splits them
+template <class BA>
+__device__ inline void stage_bodies(const BA& ba, float4* st, uint32_t nthr, float4 q, bool own, int odd)
+{
+    const uint32_t w = threadIdx.x & ~63u;
+    const int ia = __float_as_int(q.z), ib = __float_as_int(q.w);
+    int sb = own ? ib : -1, sa = own ? (ia >= 0 ? ia : ib) : -1;
+    int pb = pair_swap(sb), pa = pair_swap(sa);
+    if (!own) { sb = pb; sa = pa; }
+    if (pb < 0) { pb = sb; pa = sa; }
+    ba.stage_half(st + 5 * nthr + w, odd ? pb : sb, odd);
+    ba.stage_half(st + 6 * nthr + w, odd ? sb : pb, odd);
+    ba.stage_half(st + 7 * nthr + w, odd ? pa : sa, odd);
+    ba.stage_half(st + 8 * nthr + w, odd ? sa : pa, odd);
+}
+
+__device__ inline RowRegs staged_rows(const float4* st, uint32_t nthr)
+{
+    const uint32_t t = threadIdx.x;
+    RowRegs R;
+    R.a = st[t];
+    R.r1 = st[nthr + t];
+    R.q = st[2 * nthr + t];
+    R.L = st[3 * nthr + t];
+    R.k = st[4 * nthr + t];
+    return R;
+}
+
+__device__ inline BodyRegs staged_bodies(const float4* st, uint32_t nthr, int odd)
+{
+    const uint32_t t = threadIdx.x, p = t ^ 1u;
+    BodyRegs B;
+    B.vb = odd ? st[6 * nthr + p] : st[5 * nthr + t];
+    B.wb = odd ? st[6 * nthr + t] : st[5 * nthr + p];
+    B.va = odd ? st[8 * nthr + p] : st[7 * nthr + t];
+    B.wa = odd ? st[8 * nthr + t] : st[7 * nthr + p];
+    return B;
 }
 
 // One contact's update on the loaded bodies B (left in B), its impulses
@@ -1589,7 +1671,8 @@ __device__ inline bool flow_wait(Counters* cnt, const uint32_t* ver, int j, uint
 template <class BA, bool CLUSTER, bool FENCED, bool FLOW, bool ROLL, int NW, class Starts, bool SPREAD = false>
 __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba, Starts cstart, uint32_t ncol,
                           uint32_t* counter, unsigned nbar, unsigned rank, unsigned K, unsigned first, int sweeps_cap,
-                          int slot, int unit, double (*red)[NW], uint32_t (*cb)[kMaxColours], int& flag)
+                          int slot, int unit, double (*red)[NW], uint32_t (*cb)[kMaxColours], int& flag,
+                          float4* stage = nullptr)
 {
     int sweeps = 0;
     double Rk = 0.0, R1 = 0.0;
@@ -1657,10 +1740,15 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
     // for them.
     constexpr bool kPair = !FLOW && NW <= 8;
     constexpr bool kLanes = !FLOW && (NW <= 8 || !ROLL);
+    // the 1024-thread plain instance: a thread's second contact of a colour
+    // staged in LDS (stage_rows) when the block has the room
+    constexpr bool kStage = kLanes && !kPair && !ROLL;
+    const bool staged = kStage && stage != nullptr;
     RowRegs cur, cur2;
     auto fetch = [&]() {
         if (c < hi) cur = load_rows(b, c, ROLL);
         if (kPair && c + kThreads < hi) cur2 = load_rows(b, c + kThreads, ROLL);
+        if (staged && c + kThreads < hi) stage_rows(b, stage, kThreads, c + kThreads);
     };
     if (ncol > 0) {
         range(0, lo, hi);
@@ -1700,9 +1788,29 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                 // contact (kThreads is even, so the even lane's contacts are
                 // c - odd + k kThreads); the odd lane may have one fewer
                 const int odd = kLanes ? (int)(threadIdx.x & 1u) : 0;
+                bool first = true;  // the second contact of the colour is the staged one
                 while (c - odd < hi) {
                     const uint32_t cn = c + kThreads;
                     const bool own = c < hi;
+                    if (staged && first && cn - odd < hi) {
+                        // the second contact's rows arrived in LDS with the first's
+                        // registers; its bodies go there while the first updates
+                        const bool own2 = cn < hi;
+                        BodyRegs B = get_bodies<kLanes>(ba, cur, own, odd);
+                        stage_bodies(ba, stage, kThreads, stage[2 * kThreads + threadIdx.x], own2, odd);
+                        pgs_update(b, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
+                        put_bodies<kLanes>(ba, cur, B, own, odd);
+                        __builtin_amdgcn_s_waitcnt(0);
+                        const RowRegs R2 = staged_rows(stage, kThreads);
+                        BodyRegs B2 = staged_bodies(stage, kThreads, odd);
+                        if (own2) pgs_update(b, cn, R2, B2, p.mu, p.gamma_dt, num, den, ROLL);
+                        put_bodies<kLanes>(ba, R2, B2, own2, odd);
+                        first = false;
+                        c = cn + kThreads;
+                        if (c < hi) cur = load_rows(b, c, ROLL);  // a third (rare): one chain
+                        continue;
+                    }
+                    first = false;
                     if (kPair && cn - odd < hi) {
                         // two contacts of one colour share no sphere: both gathers
                         // in flight before either update (same order of updates
@@ -1759,7 +1867,8 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                 if (SPREAD) {
                     if (!spread_wait<FENCED>(b.cnt, counter, nbar, K, rank, flag)) return;  // every block leaves
                 } else if (!cluster_wait<FENCED>(b.cnt, counter, nbar * K, flag)) {
-                    return;  // every block leaves
+                    __builtin_amdgcn_s_waitcnt(0);  // no load into LDS outlives the solve
+                    return;                         // every block leaves
                 }
             } else {
                 range(col + 1 < ncol ? col + 1 : 0, lo, hi);
@@ -1812,6 +1921,7 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
         combine(sweeps - 1, sn, sd);
         Rk = resid(sn, sd);
     }
+    if (staged) __builtin_amdgcn_s_waitcnt(0);  // the last prefetch into LDS has landed
     if (rank == 0 && threadIdx.x == 0 && (!SPREAD || first == 0)) {
         UnitStats& G = b.ustats[unit];
         if (slot == 0) {
@@ -2031,15 +2141,17 @@ __global__ __launch_bounds__(kEnvBlk) void k_pgs_env(DevBuffers b, StepParams p,
         uint32_t* counter = b.env_bar + (size_t)e * 16;
         int mode = cluster_placement(b.cnt, counter, K, flag);
         XcdBodies xb{raw_rsrc(b.vw)};
+        // the dynamic LDS (idle during a cluster share) stages second contacts
+        float4* stage = 2 * lds_cap >= kStageFloat4 * kEnvBlk ? dyn_bodies : nullptr;
         if (mode == 1 && flow)
             pgs_solve<XcdBodies, true, false, true, ROLL>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap, slot,
                                                     e, red, cb, flag);
         else if (mode == 1)
             pgs_solve<XcdBodies, true, false, false, ROLL>(b, p, xb, cs, ncol, counter, 1, rank, K, first, sweeps_cap, slot,
-                                                     e, red, cb, flag);
+                                                     e, red, cb, flag, stage);
         else if (mode == 2)
             pgs_solve<PlainBodies, true, true, false, ROLL>(b, p, PlainBodies{b.vw}, cs, ncol, counter, 1, rank, K,
-                                                      first, sweeps_cap, slot, e, red, cb, flag);
+                                                      first, sweeps_cap, slot, e, red, cb, flag, stage);
         if (!flag) return;  // failed barrier: the step is abandoned
         __syncthreads();
         ++t;

@@ -77,6 +77,7 @@ def gen_dataset(n_envs=16, steps=120, skip=8, seed=100, tol=1e-5, max_sweeps=400
     kept."""
     specs = column_batch(n_envs, seed, sweeps=max_sweeps, tol=tol)
     sc = T.scene_from_specs(specs)
+    sc.set_learn_capture(True)
     feats, labels, total = [], [], 0
     for k in range(steps):
         st = sc.step(1)
@@ -114,6 +115,7 @@ def gen_bed_dataset(n_envs=32, steps=60, skip=20, seed=7000, tol=1e-5, max_sweep
     specs = [dict(s, material=mat, tol=tol, warm_start="prev") for s in specs]
     nmax = max(len(s["x"]) for s in specs)
     sc = T.scene_from_specs(specs, cap_particles=nmax, cap_contacts=8 * nmax)
+    sc.set_learn_capture(True)
     feats, labels, total = [], [], 0
     for k in range(steps):
         st = sc.step(1)

@@ -22,7 +22,7 @@ SHAPE = {"plane": 0, "box": 1, "hfield": 2}
 MLP_PARAMS = 64 * 12 + 64 + 64 * 64 + 64 + 3 * 64 + 3 + 12
 EXPORTS = ("create_scene", "destroy_scene", "add_particles", "set_kinematic_bodies", "step",
            "get_contact_forces", "get_aggregates", "get_last_error", "get_contacts", "get_particles",
-           "set_particles", "set_mlp_weights", "get_phase_times", "set_learned_precision", "get_learn_samples",
+           "set_particles", "set_mlp_weights", "get_phase_times", "set_learned_precision", "get_learn_samples", "set_learn_capture",
            "mlp_forward", "mlp_grad_scratch_floats", "mlp_loss_grad", "mlp_adam_step", "set_solver_config",
            "get_solver_config", "set_step_graphs", "set_warm_start", "save_state", "load_state", "autotune",
            "get_rolling_impulses", "set_tool", "get_zone_wedges", "coarse_grain", "advect_fluid",
@@ -189,6 +189,7 @@ def lib():
         L.set_mlp_weights.argtypes = [P, C.POINTER(C.c_float), C.c_int64]
         L.get_phase_times.argtypes = [P, C.POINTER(C.c_float), C.c_int32]
         L.set_learned_precision.argtypes = [P, C.c_int32]
+        L.set_learn_capture.argtypes = [P, C.c_int32]
         fp = C.POINTER(C.c_float)
         L.get_learn_samples.argtypes = [P, C.c_int32, C.c_int64, fp, fp, C.POINTER(C.c_int64)]
         L.mlp_forward.argtypes = [P, P, C.c_int64, P, C.c_int32, P]
@@ -588,6 +589,10 @@ class Scene:
 
     def set_learned_precision(self, bf16=True):
         self._check(lib().set_learned_precision(self.h, 1 if bf16 else 0), "set_learned_precision")
+
+    def set_learn_capture(self, on=True):
+        """Write the learned start's inputs in every following step (for get_learn_samples)."""
+        self._check(lib().set_learn_capture(self.h, 1 if on else 0), "set_learn_capture")
 
     def get_learn_samples(self, env):
         n = C.c_int64()

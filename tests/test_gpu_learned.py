@@ -64,6 +64,7 @@ def flat(w):
 def test_features_match_oracle_first_and_second_step():
     spec = with_(settled_column(seed=11, n=500, footprint=0.7), warm_start="prev", max_sweeps=80)
     g = T.scene_from_specs(spec)
+    g.set_learn_capture(True)
     o = O.OracleScene(spec)
     for step in range(2):
         fo, fro, so = o.features()
@@ -228,3 +229,22 @@ def test_nonfinite_network_falls_back():
     st = g.step(1)[0]
     assert st["fallback_used"] == 1
     assert np.all(np.isfinite(g.get_particles(0)["v"]))
+
+
+def test_samples_need_a_step_that_wrote_features():
+    # a step writes the learned start's inputs only when it runs the network
+    # or capture is on; without them get_learn_samples is refused
+    spec = with_(settled_column(seed=12, n=300, footprint=0.6), warm_start="prev", max_sweeps=20)
+    g = T.scene_from_specs(spec)
+    g.step(1)
+    with pytest.raises(T.TerrainError) as ei:
+        g.get_learn_samples(0)
+    assert ei.value.code == T.TR_E_STATE
+    g.set_learn_capture(True)
+    g.step(1)
+    f, lab = g.get_learn_samples(0)
+    assert len(f) > 0 and f.shape[1] == 12 and lab.shape[1] == 3
+    g.set_learn_capture(False)
+    g.step(1)
+    with pytest.raises(T.TerrainError):
+        g.get_learn_samples(0)
