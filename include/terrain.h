@@ -573,14 +573,18 @@ int mlp_adam_step(float* weights, const float* grad, float* m, float* v, float l
  * has at most 8 envs), that of TR_PGS_PER_ENV per env.
  *   TR_PGS_GROUPED: envs in 8 groups, one per XCD; each group is solved by
  *     blocks_per_xcd blocks that meet at a barrier after every colour.
- *   TR_PGS_PER_ENV: each env is solved by its own block (bodies staged in
- *     LDS when it has at most lds_particles particles) or, when it has more
- *     than T particles, by a cluster of ceil(n / T) blocks; small envs share
- *     blocks and run on them one after another.  T = cluster_particles, or
- *     with 0 the mean particles per resident block (at least 4096).  With
- *     TR_CLUSTER_NONE no env takes more than one block: an env that does not
- *     fit LDS gets a block of its own (bodies in global memory), the others
- *     are packed into blocks of at most lds_particles particles.
+ *   TR_PGS_PER_ENV: each env is solved by one block or by a cluster of
+ *     blocks of one XCD.  A block solves a set of envs at once with their
+ *     bodies in its LDS (lds_particles slots; an env that does not fit keeps
+ *     its first slots there and the rest in global memory); blocks run their
+ *     tasks one after another.  cluster_particles 0: the plan of a cost model
+ *     measured on MI355X (envs that fit LDS packed into sets, somewhat larger
+ *     ones solved alone by one block, the largest by clusters sized to finish
+ *     together; the size limit and the cluster sizes searched for the
+ *     smallest predicted time).  cluster_particles T > 0: envs of more than T
+ *     particles get clusters of ceil(n / T) blocks, the others sets of at
+ *     most T particles.  TR_CLUSTER_NONE: no env takes more than one block
+ *     (sets of at most lds_particles particles, larger envs alone).
  *   TR_PGS_SPREAD: one env (n_envs must be 1) spread over all 8 XCDs: its
  *     sorted spheres in eighths (compact regions of the Morton order), each
  *     contact solved by the XCD group of its second sphere with

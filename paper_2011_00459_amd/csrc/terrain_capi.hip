@@ -164,11 +164,108 @@ void invalidate_graphs(tr_scene* s)
     s->graphs = false;
 }
 
+// The automatic per-env plan, from a cost model measured on MI355X (the
+// 256-bed batch with a timing build that clocks every block's tasks): per
+// sweep and colour, a sphere of a multi-block share costs about 2.44 units,
+// a sphere of a block solving from LDS 0.85 plus 300 per set, and a sphere
+// that a single block keeps in global memory about 2.8 (3.2 here: those
+// solves vary most, and the largest of them set the makespan).  Envs that fit LDS
+// are packed into sets (first fit, largest first); envs up to Ns spheres are
+// solved alone by one block with their first slots in LDS; larger ones by
+// clusters of ceil(2.44 n / M) blocks of one XCD lane.  Ns and the target M
+// are searched for the smallest predicted makespan (jobs placed largest first
+// on the least loaded block).  tasks gets each block's cluster share
+// (env, rank, K, first block) and then its sets as (env, set number, 1, 0);
+// false when no candidate fits the blocks.
+bool plan_auto(const tr_scene* s, const std::vector<int>& order, int B, int lds_cap,
+               std::vector<std::vector<int4>>& best_tasks)
+{
+    constexpr double kWc = 2.44, kWs = 0.85, kWset = 300.0, kWg = 3.2;
+    const int G = kGroups, PL = B / G, waves = kEnvBlk / 64;
+    std::vector<std::vector<int>> sets;
+    std::vector<double> fill;
+    double work0 = 0.0;
+    for (int e : order) {
+        const double n = (double)s->envs[e].n;
+        if (n > lds_cap) {
+            work0 += kWc * n;
+            continue;
+        }
+        work0 += kWs * n;
+        size_t k = 0;
+        while (k < sets.size() && (fill[k] + n > lds_cap || (int)sets[k].size() >= waves)) ++k;
+        if (k == sets.size()) {
+            sets.emplace_back();
+            fill.push_back(0.0);
+        }
+        sets[k].push_back(e);
+        fill[k] += n;
+    }
+    work0 += kWset * (double)sets.size();
+    double best = 1e300;
+    for (double fs : {1.0, 1.1, 1.2, 1.3, 1.4, 1.5, 1.6}) {
+        const double Ns = fs * lds_cap;
+        for (int m = 0; m <= 36; ++m) {
+            const double M = work0 / B * (0.7 + 0.025 * m);
+            std::vector<double> load(B, 0.0);
+            std::vector<int> lane_next(G, 0);
+            std::vector<std::vector<int4>> tasks(B);
+            std::vector<std::pair<double, int>> jobs;  // (cost, env) or (cost, -1 - set)
+            bool ok = true;
+            for (int e : order) {
+                const double n = (double)s->envs[e].n;
+                if (n <= lds_cap) continue;
+                if (n <= Ns) {
+                    jobs.push_back({kWs * lds_cap + kWg * (n - lds_cap) + kWset, e});
+                    continue;
+                }
+                const int K = std::max(2, (int)std::ceil(kWc * n / M));
+                int lane = 0;
+                for (int x = 1; x < G; ++x)
+                    if (lane_next[x] < lane_next[lane]) lane = x;
+                if (K > PL - lane_next[lane]) {
+                    ok = false;
+                    break;
+                }
+                const int first = lane + G * lane_next[lane];
+                for (int r = 0; r < K; ++r) {
+                    tasks[first + G * r].push_back(make_int4(e, r, K, first));
+                    load[first + G * r] += kWc * n / K;
+                }
+                lane_next[lane] += K;
+            }
+            if (!ok) continue;
+            for (size_t k = 0; k < sets.size(); ++k) jobs.push_back({kWs * fill[k] + kWset, -1 - (int)k});
+            std::stable_sort(jobs.begin(), jobs.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& c) {
+                return a.first > c.first;
+            });
+            int setno = 0;
+            for (const auto& j : jobs) {
+                int blk = 0;
+                for (int i = 1; i < B; ++i)
+                    if (load[i] < load[blk]) blk = i;
+                load[blk] += j.first;
+                if (j.second >= 0) tasks[blk].push_back(make_int4(j.second, setno, 1, 0));
+                else
+                    for (int e : sets[-1 - j.second]) tasks[blk].push_back(make_int4(e, setno, 1, 0));
+                ++setno;
+            }
+            const double mk = *std::max_element(load.begin(), load.end());
+            if (mk < best) {
+                best = mk;
+                best_tasks = tasks;
+            }
+        }
+    }
+    return best < 1e300;
+}
+
 // PGS schedule: the solve unit of every env and, in per-env mode, the plan of
-// the resident blocks.  Envs larger than T spheres per block get a cluster of
-// ceil(n / T) blocks in one XCD lane (indices congruent mod 8, so they share
-// an XCD); the others are packed into sets that one block solves at once,
-// each env on its own waves.
+// the resident blocks.  Automatic (cluster_particles 0): plan_auto.  With a
+// given T: envs larger than T spheres per block get a cluster of ceil(n / T)
+// blocks in one XCD lane (indices congruent mod 8, so they share an XCD); the
+// others are packed into sets that one block solves at once, each env on its
+// own waves.
 int rebuild_plan(tr_scene* s)
 {
     invalidate_graphs(s);
@@ -191,60 +288,11 @@ int rebuild_plan(tr_scene* s)
         for (int e = 0; e < E; ++e)
             if (s->envs[e].n > 0) order.push_back(e);
         std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return s->envs[a].n > s->envs[c].n; });
-        // T: spheres per block (the mean load).  Envs above T get ceil(n / T)
-        // blocks of one XCD lane; the rest are packed (first fit, largest first)
-        // into sets of at most T spheres and 16 envs, each solved by one block at
-        // once, placed largest first on the least loaded block (a cluster share
-        // counts twice its spheres: measured, a block of a multi-block solve is
-        // about half as fast per sphere as one solving a set from LDS).
-        const double T = s->cfg.cluster_particles > 0 ? (double)s->cfg.cluster_particles
-                                                       : std::max(total / B, 4096.0);
-        // single-block solves only: an env too large for LDS takes a block of
-        // its own (measured on MI355X, a multi-block share pays about 12 us of
-        // cross-block barrier per colour, where one block of 1,024 threads
-        // solving the env alone meets at workgroup barriers)
-        const bool solo = s->cfg.cluster_particles == TR_CLUSTER_NONE;
-        const double set_cap = solo ? (double)std::max(lds_cap, 1) : T;
         std::vector<std::vector<int4>> tasks(B);
-        std::vector<double> load(B, 0.0);
-        std::vector<int> lane_next(kGroups, 0);
-        std::vector<std::vector<int>> sets;
-        std::vector<double> fill;
-        for (int e : order) {
-            const double n = (double)s->envs[e].n;
-            int K = solo ? 1 : (int)std::min<double>(std::ceil(n / T), (double)per_lane);
-            int lane = 0;
-            for (int x = 1; x < kGroups; ++x)
-                if (lane_next[x] < lane_next[lane]) lane = x;
-            K = std::min(K, per_lane - lane_next[lane]);
-            if (K >= 2) {
-                const int first = lane + kGroups * lane_next[lane];
-                for (int r = 0; r < K; ++r) {
-                    tasks[first + kGroups * r].push_back(make_int4(e, r, K, first));
-                    load[first + kGroups * r] += 2.0 * n / K;
-                }
-                lane_next[lane] += K;
-                continue;
-            }
-            size_t k = 0;
-            while (k < sets.size() && (fill[k] + n > set_cap || (int)sets[k].size() >= waves)) ++k;
-            if (k == sets.size()) {
-                sets.emplace_back();
-                fill.push_back(0.0);
-            }
-            sets[k].push_back(e);
-            fill[k] += n;
-        }
-        std::vector<size_t> sorder(sets.size());
-        for (size_t k = 0; k < sets.size(); ++k) sorder[k] = k;
-        std::stable_sort(sorder.begin(), sorder.end(), [&](size_t a, size_t c) { return fill[a] > fill[c]; });
-        for (size_t k : sorder) {
-            const std::vector<int>& st = sets[k];
-            int blk = 0;
-            for (int i = 1; i < B; ++i)
-                if (load[i] < load[blk]) blk = i;
-            load[blk] += fill[k];
-            // waves in proportion to the envs' spheres, at least one each
+        // a set of envs solved at once by block blk: waves in proportion to
+        // the envs' spheres (at least one each), LDS slots in order while they
+        // last (an env that does not fit keeps its first slots there)
+        auto place_set = [&](int blk, const std::vector<int>& st) {
             std::vector<int> w(st.size(), 1);
             int left = waves - (int)st.size();
             while (left > 0) {
@@ -259,11 +307,79 @@ int rebuild_plan(tr_scene* s)
             }
             int wb = 0, off = 0;
             for (size_t i = 0; i < st.size(); ++i) {
-                int n = (int)s->envs[st[i]].n;
-                int lo = off + n <= lds_cap ? off : -1;  // LDS while the set's bodies fit
-                if (lo >= 0) off += n;
+                const int n = (int)s->envs[st[i]].n;
+                const int lo = off < lds_cap ? off : -1;
+                if (lo >= 0) off += std::min(n, lds_cap - off);
                 tasks[blk].push_back(make_int4(st[i], wb | ((wb + w[i]) << 8), 1, lo));
                 wb += w[i];
+            }
+        };
+        if (s->cfg.cluster_particles == 0 && lds_cap > 0 && plan_auto(s, order, B, lds_cap, tasks)) {
+            for (int blk = 0; blk < B; ++blk) {
+                // plan_auto lists each block's sets as (env, set number) pairs after its cluster share
+                std::vector<int4> mine;
+                std::vector<std::vector<int>> sets_b;
+                int cur_set = -1;
+                for (const int4& t : tasks[blk]) {
+                    if (t.z >= 2) { mine.push_back(t); continue; }
+                    if (t.y != cur_set) { sets_b.emplace_back(); cur_set = t.y; }
+                    sets_b.back().push_back(t.x);
+                }
+                tasks[blk] = mine;
+                for (const auto& st : sets_b) place_set(blk, st);
+            }
+        } else {
+            // T: spheres per block (given, or the mean load).  Envs above T get
+            // ceil(n / T) blocks of one XCD lane; the rest are packed (first fit,
+            // largest first) into sets of at most T spheres and 16 envs, each solved
+            // by one block at once, placed largest first on the least loaded block (a
+            // cluster share counts twice its spheres).
+            const double T = s->cfg.cluster_particles > 0 ? (double)s->cfg.cluster_particles
+                                                           : std::max(total / B, 4096.0);
+            // single-block solves only: an env too large for LDS takes a block of
+            // its own (measured on MI355X, a multi-block share pays about 12 us of
+            // cross-block barrier per colour, where one block of 1,024 threads
+            // solving the env alone meets at workgroup barriers)
+            const bool solo = s->cfg.cluster_particles == TR_CLUSTER_NONE;
+            const double set_cap = solo ? (double)std::max(lds_cap, 1) : T;
+            std::vector<double> load(B, 0.0);
+            std::vector<int> lane_next(kGroups, 0);
+            std::vector<std::vector<int>> sets;
+            std::vector<double> fill;
+            for (int e : order) {
+                const double n = (double)s->envs[e].n;
+                int K = solo ? 1 : (int)std::min<double>(std::ceil(n / T), (double)per_lane);
+                int lane = 0;
+                for (int x = 1; x < kGroups; ++x)
+                    if (lane_next[x] < lane_next[lane]) lane = x;
+                K = std::min(K, per_lane - lane_next[lane]);
+                if (K >= 2) {
+                    const int first = lane + kGroups * lane_next[lane];
+                    for (int r = 0; r < K; ++r) {
+                        tasks[first + kGroups * r].push_back(make_int4(e, r, K, first));
+                        load[first + kGroups * r] += 2.0 * n / K;
+                    }
+                    lane_next[lane] += K;
+                    continue;
+                }
+                size_t k = 0;
+                while (k < sets.size() && (fill[k] + n > set_cap || (int)sets[k].size() >= waves)) ++k;
+                if (k == sets.size()) {
+                    sets.emplace_back();
+                    fill.push_back(0.0);
+                }
+                sets[k].push_back(e);
+                fill[k] += n;
+            }
+            std::vector<size_t> sorder(sets.size());
+            for (size_t k = 0; k < sets.size(); ++k) sorder[k] = k;
+            std::stable_sort(sorder.begin(), sorder.end(), [&](size_t a, size_t c) { return fill[a] > fill[c]; });
+            for (size_t k : sorder) {
+                int blk = 0;
+                for (int i = 1; i < B; ++i)
+                    if (load[i] < load[blk]) blk = i;
+                load[blk] += fill[k];
+                place_set(blk, sets[k]);
             }
         }
         plan_idx.assign(B + 1, 0);

@@ -1372,6 +1372,28 @@ struct LdsBodies {
     __device__ void set(int i, float4 v, float4 w) const { sv[i - base] = v; sw[i - base] = w; }
 };
 
+// An env solved by one block whose spheres do not all fit its LDS: the
+// first cap slots in LDS, the others in global memory (one block, one CU:
+// plain accesses are ordered by its workgroup barriers)
+struct MixedBodies {
+    float4 *sv, *sw;
+    int base, cap;
+    float4* vw;
+    __device__ bool lds(int i) const { return (unsigned)(i - base) < (unsigned)cap; }
+    __device__ float4 v(int i) const { return lds(i) ? sv[i - base] : vel_at(vw, i); }
+    __device__ float4 w(int i) const { return lds(i) ? sw[i - base] : angv_at(vw, i); }
+    __device__ void set(int i, float4 v, float4 w) const
+    {
+        if (lds(i)) {
+            sv[i - base] = v;
+            sw[i - base] = w;
+        } else {
+            vel_at(vw, i) = v;
+            angv_at(vw, i) = w;
+        }
+    }
+};
+
 // the two bodies of a contact, loaded ahead of the update (the update
 // replaces body 1 of a boundary contact by the boundary's velocity)
 struct BodyRegs {
@@ -2034,11 +2056,15 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
     const int sb = e >= 0 ? b.envs[e].slot_begin : 0, n = e >= 0 ? b.envs[e].n : 0;
     LdsBodies lb{dyn + (off >= 0 ? off : 0), dyn + lds_cap + (off >= 0 ? off : 0), sb};
     PlainBodies gb{b.vw};
-    if (off >= 0)
-        for (int i = (int)lt; i < n; i += (int)nthr) {
-            lb.sv[i] = vel_at(b.vw, sb + i);
-            lb.sw[i] = angv_at(b.vw, sb + i);
-        }
+    // the env's first lcap slots in LDS: all of them when they fit (how 0),
+    // none without an LDS offset (how 1), else the rest in global memory (how 2)
+    const int lcap = off >= 0 ? min(n, lds_cap - off) : 0;
+    const int how = off < 0 ? 1 : (lcap < n ? 2 : 0);
+    MixedBodies mb{lb.sv, lb.sw, sb, lcap, b.vw};
+    for (int i = (int)lt; i < lcap; i += (int)nthr) {
+        lb.sv[i] = vel_at(b.vw, sb + i);
+        lb.sw[i] = angv_at(b.vw, sb + i);
+    }
     __syncthreads();
     const uint32_t* ec = b.env_col + (size_t)(e >= 0 ? e : 0) * (kMaxColours + 1);
     const uint32_t ncol = e >= 0 && !(slot == kSlotImpact && !b.ustats[e].imp_any) ? b.env_ncol[e] : 0;
@@ -2060,11 +2086,12 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
             if (active && col < ncol) {
                 while (c < hi) {
                     uint32_t cn = c + nthr;
-                    BodyRegs B = off >= 0 ? load_bodies(lb, cur) : load_bodies(gb, cur);
+                    BodyRegs B = how == 0 ? load_bodies(lb, cur) : how == 1 ? load_bodies(gb, cur) : load_bodies(mb, cur);
                     RowRegs nxt;
                     if (cn < hi) nxt = load_rows(b, cn, ROLL);
-                    if (off >= 0) pgs_contact(b, lb, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
-                    else pgs_contact(b, gb, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
+                    if (how == 0) pgs_contact(b, lb, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
+                    else if (how == 1) pgs_contact(b, gb, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
+                    else pgs_contact(b, mb, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
                     cur = nxt;
                     c = cn;
                 }
@@ -2090,11 +2117,10 @@ __device__ void pgs_local_set(const DevBuffers& b, const StepParams& p, const in
         }
         __syncthreads();  // red is reused
     }
-    if (off >= 0)
-        for (int i = (int)lt; i < n; i += (int)nthr) {
-            vel_at(b.vw, sb + i) = lb.sv[i];
-            angv_at(b.vw, sb + i) = lb.sw[i];
-        }
+    for (int i = (int)lt; i < lcap; i += (int)nthr) {
+        vel_at(b.vw, sb + i) = lb.sv[i];
+        angv_at(b.vw, sb + i) = lb.sw[i];
+    }
     if (e >= 0 && lt == 0) {
         UnitStats& G = b.ustats[e];
         if (slot == 0) {

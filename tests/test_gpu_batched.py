@@ -26,6 +26,11 @@ SCHEDULES = {
     "per_env_solo": dict(mode="per_env", lds_particles=350, cluster_particles=-1),
     "per_env_clusters": dict(mode="per_env", lds_particles=350, cluster_particles=150, dataflow=0),
     "per_env_clusters_flow": dict(mode="per_env", lds_particles=350, cluster_particles=150, dataflow=1),
+    # every env solved by one block, those that do not fit the 350 LDS slots
+    # with their first slots in LDS and the rest in global memory
+    "per_env_partial_lds": dict(mode="per_env", lds_particles=350, cluster_particles=600, dataflow=0),
+    # the cost-model plan with a small LDS: sets and clusters
+    "per_env_auto_small_lds": dict(mode="per_env", lds_particles=350, cluster_particles=0, dataflow=0),
 }
 
 
