@@ -72,15 +72,18 @@ def test_bed500k_contacts_bit_exact_and_momentum_balance():
 
 def test_batched256_three_beds_at_full_size_match_oracle():
     # the 256-bed batch in the per-env schedule the bench times: its smallest,
-    # median and largest beds (settled by the oracle, 30 steps of 10 sweeps)
-    # among the 253 others as generated, one 100-sweep step, each against the
-    # single-env oracle with the same global ids
+    # median and largest beds and the smallest one above the LDS capacity
+    # (5,080 spheres: the plan solves it alone on one block, partly from LDS),
+    # settled by the oracle (30 steps of 10 sweeps), among the 252 others as
+    # generated, one 100-sweep step, each against the single-env oracle with
+    # the same global ids
     from paper_2011_00459_amd import scenegen as SG
     specs = SG.batch_specs(seed=3000, n_envs=256, sweeps=100)
     mat = specs[0]["material"]
     ns = np.array([len(s["x"]) for s in specs])
     order = np.argsort(ns, kind="stable")
-    picks = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    above = [int(e) for e in order if ns[e] > 5080]
+    picks = [int(order[0]), int(order[len(order) // 2]), int(order[-1]), above[0]]
     cap = int(ns.max())
     settled = {}
     for e in picks:
