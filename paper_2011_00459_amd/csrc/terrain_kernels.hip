@@ -1293,19 +1293,27 @@ __device__ inline int cluster_placement(Counters* cnt, uint32_t* counter, unsign
     return flag;
 }
 
+// A contact's rows as the update reads them.  rk (the kinematic velocity of
+// a boundary contact, the update sequence of the counter-ordered schedule)
+// is fetched with them only by the grouped solve (kin), whose colour phases
+// are latency-bound on one XCD; elsewhere the update of a boundary contact
+// loads it itself, so a pair's row stream is 48 B of rows and the impulses
+// (measured: 256-bed batch PGS 11.1-11.2 -> 9.9-10.0 ms, 500k excavation
+// 29.4 -> 26.9 ms; 50k bed 7.1 -> 7.4 ms, hence kin there; same states).
 struct RowRegs {
-    float4 a, r1, q, L, k;
+    float4 a, r1, q, L;
+    float4 k;       // rk, when fetched with the rows
     float4 r3, Lr;  // rolling rows (loaded when mu_r > 0)
 };
 
-__device__ inline RowRegs load_rows(const DevBuffers& b, uint32_t c, bool roll)
+__device__ inline RowRegs load_rows(const DevBuffers& b, uint32_t c, bool roll, bool kin = false)
 {
     RowRegs R;
     R.a = b.r0[c];
     R.r1 = b.r1[c];
     R.q = b.r2[c];
     R.L = b.lam[c];
-    R.k = b.rk[c];
+    if (kin) R.k = b.rk[c];
     if (roll) {
         R.r3 = b.r3[c];
         R.Lr = b.lamr[c];
@@ -1498,20 +1506,20 @@ __device__ inline void put_bodies(const BA& ba, const RowRegs& R, const BodyRegs
 
 // Staging of a thread's second contact of a colour in LDS (1024-thread
 // blocks, which have no registers for two contacts in flight).  The layout,
-// in float4 per block thread t: rows a, r1, q, L, k at [j nthr + t], j < 5;
+// in float4 per block thread t: rows a, r1, q, L at [j nthr + t], j < 4;
 // then the lane pairs' body halves x1, x2 of sphere b and of sphere a at
-// [(5 + j) nthr + t], j < 4, as pair_load leaves them in registers.  Loads go
+// [(4 + j) nthr + t], j < 4, as pair_load leaves them in registers.  Loads go
 // straight to LDS (16 B per lane, lane order), so the second contact's rows
 // are fetched during the barrier and its bodies during the first contact's
 // update, without registers.
-constexpr int kStageFloat4 = 9;  // float4 per block thread
+constexpr int kStageFloat4 = 8;  // float4 per block thread
 
 __device__ inline void stage_rows(const DevBuffers& b, float4* st, uint32_t nthr, uint32_t c)
 {
     const uint32_t w = threadIdx.x & ~63u;
-    const float4* src[5] = {b.r0, b.r1, b.r2, b.lam, b.rk};
+    const float4* src[4] = {b.r0, b.r1, b.r2, b.lam};
 #pragma unroll
-    for (int j = 0; j < 5; ++j)
+    for (int j = 0; j < 4; ++j)
         __builtin_amdgcn_global_load_lds((const void*)&src[j][c],
                                          (__attribute__((address_space(3))) void*)(st + j * nthr + w), 16, 0, 0);
 }
@@ -1527,10 +1535,10 @@ __device__ inline void stage_bodies(const BA& ba, float4* st, uint32_t nthr, flo
     int pb = pair_swap(sb), pa = pair_swap(sa);
     if (!own) { sb = pb; sa = pa; }
     if (pb < 0) { pb = sb; pa = sa; }
-    ba.stage_half(st + 5 * nthr + w, odd ? pb : sb, odd);
-    ba.stage_half(st + 6 * nthr + w, odd ? sb : pb, odd);
-    ba.stage_half(st + 7 * nthr + w, odd ? pa : sa, odd);
-    ba.stage_half(st + 8 * nthr + w, odd ? sa : pa, odd);
+    ba.stage_half(st + 4 * nthr + w, odd ? pb : sb, odd);
+    ba.stage_half(st + 5 * nthr + w, odd ? sb : pb, odd);
+    ba.stage_half(st + 6 * nthr + w, odd ? pa : sa, odd);
+    ba.stage_half(st + 7 * nthr + w, odd ? sa : pa, odd);
 }
 
 __device__ inline RowRegs staged_rows(const float4* st, uint32_t nthr)
@@ -1541,7 +1549,6 @@ __device__ inline RowRegs staged_rows(const float4* st, uint32_t nthr)
     R.r1 = st[nthr + t];
     R.q = st[2 * nthr + t];
     R.L = st[3 * nthr + t];
-    R.k = st[4 * nthr + t];
     return R;
 }
 
@@ -1549,23 +1556,24 @@ __device__ inline BodyRegs staged_bodies(const float4* st, uint32_t nthr, int od
 {
     const uint32_t t = threadIdx.x, p = t ^ 1u;
     BodyRegs B;
-    B.vb = odd ? st[6 * nthr + p] : st[5 * nthr + t];
-    B.wb = odd ? st[6 * nthr + t] : st[5 * nthr + p];
-    B.va = odd ? st[8 * nthr + p] : st[7 * nthr + t];
-    B.wa = odd ? st[8 * nthr + t] : st[7 * nthr + p];
+    B.vb = odd ? st[5 * nthr + p] : st[4 * nthr + t];
+    B.wb = odd ? st[5 * nthr + t] : st[4 * nthr + p];
+    B.va = odd ? st[7 * nthr + p] : st[6 * nthr + t];
+    B.wa = odd ? st[7 * nthr + t] : st[6 * nthr + p];
     return B;
 }
 
 // One contact's update on the loaded bodies B (left in B), its impulses
 // written; the caller stores the bodies.
 __device__ inline void pgs_update(const DevBuffers& b, uint32_t c, const RowRegs& R, BodyRegs& B, float mu, float gdt,
-                                  float& num, float& den, bool roll)
+                                  float& num, float& den, bool roll, bool kin = false)
 {
     float4 a = R.a, r1 = R.r1, q = R.q, L = R.L;
     bool pair = __float_as_int(q.z) >= 0;
     float4 vb = B.vb, wb = B.wb, va = B.va, wa = B.wa;
     if (!pair) {
-        va = make_float4(R.k.x, R.k.y, R.k.z, 0.f);
+        const float4 kv = kin ? R.k : b.rk[c];  // the boundary's velocity at the contact point
+        va = make_float4(kv.x, kv.y, kv.z, 0.f);
         wa = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     float nx = a.x, ny = a.y, nz = a.z, l1 = a.w;
@@ -1765,11 +1773,12 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
     // the 1024-thread plain instance: a thread's second contact of a colour
     // staged in LDS (stage_rows) when the block has the room
     constexpr bool kStage = kLanes && !kPair && !ROLL;
+    constexpr bool kKin = NW <= 8 && !SPREAD && !FLOW;  // the grouped solve fetches rk with the rows
     const bool staged = kStage && stage != nullptr;
     RowRegs cur, cur2;
     auto fetch = [&]() {
-        if (c < hi) cur = load_rows(b, c, ROLL);
-        if (kPair && c + kThreads < hi) cur2 = load_rows(b, c + kThreads, ROLL);
+        if (c < hi) cur = load_rows(b, c, ROLL, kKin);
+        if (kPair && c + kThreads < hi) cur2 = load_rows(b, c + kThreads, ROLL, kKin);
         if (staged && c + kThreads < hi) stage_rows(b, stage, kThreads, c + kThreads);
     };
     if (ncol > 0) {
@@ -1788,8 +1797,8 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                 while (c < hi) {
                     const uint32_t cn = c + kThreads;
                     RowRegs nxt;
-                    if (cn < hi) nxt = load_rows(b, cn, ROLL);
-                    const uint32_t seq = __float_as_uint(cur.k.w);
+                    if (cn < hi) nxt = load_rows(b, cn, ROLL, kKin);
+                    const uint32_t seq = __float_as_uint(b.rk[c].w);
                     const int ia = __float_as_int(cur.q.z), ib = __float_as_int(cur.q.w);
                     const uint32_t wa = (uint32_t)sw * ((seq >> 16) & 255u) + (seq & 255u);
                     const uint32_t wb = (uint32_t)sw * (seq >> 24) + ((seq >> 8) & 255u);
@@ -1820,16 +1829,16 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                         const bool own2 = cn < hi;
                         BodyRegs B = get_bodies<kLanes>(ba, cur, own, odd);
                         stage_bodies(ba, stage, kThreads, stage[2 * kThreads + threadIdx.x], own2, odd);
-                        pgs_update(b, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
+                        pgs_update(b, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL, kKin);
                         put_bodies<kLanes>(ba, cur, B, own, odd);
                         __builtin_amdgcn_s_waitcnt(0);
                         const RowRegs R2 = staged_rows(stage, kThreads);
                         BodyRegs B2 = staged_bodies(stage, kThreads, odd);
-                        if (own2) pgs_update(b, cn, R2, B2, p.mu, p.gamma_dt, num, den, ROLL);
+                        if (own2) pgs_update(b, cn, R2, B2, p.mu, p.gamma_dt, num, den, ROLL, kKin);
                         put_bodies<kLanes>(ba, R2, B2, own2, odd);
                         first = false;
                         c = cn + kThreads;
-                        if (c < hi) cur = load_rows(b, c, ROLL);  // a third (rare): one chain
+                        if (c < hi) cur = load_rows(b, c, ROLL, kKin);  // a third (rare): one chain
                         continue;
                     }
                     first = false;
@@ -1842,10 +1851,10 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                         BodyRegs B2 = get_bodies<kLanes>(ba, cur2, own2, odd);
                         const uint32_t c3 = cn + kThreads;
                         RowRegs n1, n2;
-                        if (c3 < hi) n1 = load_rows(b, c3, ROLL);
-                        if (c3 + kThreads < hi) n2 = load_rows(b, c3 + kThreads, ROLL);
-                        pgs_update(b, c, cur, B1, p.mu, p.gamma_dt, num, den, ROLL);
-                        if (own2) pgs_update(b, cn, cur2, B2, p.mu, p.gamma_dt, num, den, ROLL);
+                        if (c3 < hi) n1 = load_rows(b, c3, ROLL, kKin);
+                        if (c3 + kThreads < hi) n2 = load_rows(b, c3 + kThreads, ROLL, kKin);
+                        pgs_update(b, c, cur, B1, p.mu, p.gamma_dt, num, den, ROLL, kKin);
+                        if (own2) pgs_update(b, cn, cur2, B2, p.mu, p.gamma_dt, num, den, ROLL, kKin);
                         put_bodies<kLanes>(ba, cur, B1, true, odd);
                         put_bodies<kLanes>(ba, cur2, B2, own2, odd);
                         cur = n1;
@@ -1855,8 +1864,8 @@ __device__ void pgs_solve(const DevBuffers& b, const StepParams& p, const BA& ba
                     }
                     BodyRegs B = get_bodies<kLanes>(ba, cur, own, odd);
                     RowRegs nxt;
-                    if (cn < hi) nxt = load_rows(b, cn, ROLL);
-                    if (own) pgs_update(b, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL);
+                    if (cn < hi) nxt = load_rows(b, cn, ROLL, kKin);
+                    if (own) pgs_update(b, c, cur, B, p.mu, p.gamma_dt, num, den, ROLL, kKin);
                     put_bodies<kLanes>(ba, cur, B, own, odd);
                     cur = nxt;
                     c = cn;
