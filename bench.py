@@ -47,7 +47,7 @@ PAIR_BYTES, BOUND_BYTES = 176, 128
 # runs scaled by a copy kernel of known size (profiles named below); valid
 # only for the kernel source it was measured on, else reported as null.
 PGS_TRAFFIC = {
-    "batched": {"kernels_sha256_prefix": "491ce3b4498ba602", "bytes_per_launch": 54.89e9,
+    "batched": {"kernels_sha256_prefix": "491ce3b4498ba602", "bytes_per_launch": 52.70e9,
                 "profile": "profiles/k_pgs_env_batched256_hbm_traffic.md"},
     "bed": {"kernels_sha256_prefix": "491ce3b4498ba602", "bytes_per_launch": 3.504e9,
             "profile": "profiles/k_pgs_bed50k_hbm_traffic.md"},
@@ -104,9 +104,20 @@ def timed_steps(sc, k):
     return tot
 
 
+def phase_ms(ph):
+    # phases a step-graph replay does not time are reported as null
+    return {k: None if math.isnan(v) else float(v) for k, v in ph.items()}
+
+
 def roofline(tot, kernel, traffic_key):
     ms = tot["pgs_ms"] / tot["steps"]
     bpl = tot["bytes"] / tot["steps"]
+    if math.isnan(ms):
+        # a step-graph replay is timed only as a whole
+        return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                "traffic": source_traffic(PGS_TRAFFIC[traffic_key]), "algorithmic_bytes_per_launch": bpl,
+                "launch_ms": None, "kernel": kernel, "note": "step graphs: the PGS launch is not timed alone; "
+                "use --launch eager"}
     achieved = bpl / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": source_traffic(PGS_TRAFFIC[traffic_key]),
@@ -194,7 +205,7 @@ def leg_batched(args):
                contacts_per_step=sum(x["contacts"] for x in st), colours_max=max(x["colours"] for x in st),
                sweeps=st[0]["sweeps"], schedule=sc.get_solver_config(),
                autotune_ms_per_step=tuned[1] if tuned else None,
-               phase_ms_last_step={k: float(v) for k, v in ph.items()},
+               phase_ms_last_step=phase_ms(ph),
                roofline=roofline(tot, pgs_kernel_name(sc), "batched"))
     sc.close()
     return out, specs
@@ -235,7 +246,7 @@ def leg_bed(args, n=50000, sweeps=150):
                contacts_per_step=st[0]["contacts"], pair_contacts=st[0]["pair_contacts"],
                colours=st[0]["colours"], sweeps=st[0]["sweeps"], settled_top_m=top,
                schedule=sc.get_solver_config(), autotune_ms_per_step=tuned[1] if tuned else None,
-               phase_ms_last_step={k: float(v) for k, v in ph.items()}, blade_force_N=[float(x) for x in f],
+               phase_ms_last_step=phase_ms(ph), blade_force_N=[float(x) for x in f],
                zone_particles=int(agg[0]["n_particles"]) if agg else 0,
                zone_mass_kg=float(agg[0]["M"]) if agg else 0.0,
                macro_step=time_macro(sc),
@@ -303,7 +314,7 @@ def leg_excavation(args, weights=None, n=500000, sweeps=200):
                warm_start="learned" if weights is not None else "prev",
                learned_fallback_last_step=int(st[0]["fallback_used"]),
                schedule=sc.get_solver_config(), autotune_ms_per_step=tuned[1] if tuned else None,
-               phase_ms_last_step={k: float(v) for k, v in ph.items()}, bucket_force_N=[float(x) for x in f],
+               phase_ms_last_step=phase_ms(ph), bucket_force_N=[float(x) for x in f],
                zone_particles=int(agg[0]["n_particles"]) if agg else 0,
                zone_mass_kg=float(agg[0]["M"]) if agg else 0.0,
                macro_step=time_macro(sc),

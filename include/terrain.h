@@ -613,8 +613,8 @@ int get_solver_config(tr_scene* s, tr_solver_config* cfg);
 /* Step graphs (on by default): from the second step after the scene or its
  * tables last changed, each step replays a captured HIP graph of its launches
  * instead of launching them one by one.  Results are identical either way;
- * enable = 0 launches every step eagerly.  With graphs, the phase times of
- * get_phase_times are all recorded around the whole step. */
+ * enable = 0 launches every step eagerly.  A replayed step is timed only as a
+ * whole (get_phase_times). */
 int set_step_graphs(tr_scene* s, int32_t enable);
 
 /* Autotuner of the PGS schedule.  Times candidate schedules (grouped with 64,
@@ -644,8 +644,9 @@ int load_state(tr_scene* s, const void* buf, int64_t size);
 
 /* Device time (ms, from HIP events on the scene's stream) of the last step's
  * phases: [0] detection+ordering, [1] rows+colouring+warm start, [2] PGS,
- * [3] integration+forces+aggregates, [4] whole step.  Writes min(cap, 5)
- * values.  Synchronises. */
+ * [3] integration+forces+aggregates, [4] whole step.  When the last step was
+ * a step-graph replay, [0]-[3] are NaN (the replay is one launch, timed as a
+ * whole).  Writes min(cap, 5) values.  Synchronises. */
 int get_phase_times(tr_scene* s, float* ms, int32_t cap);
 
 #ifdef __cplusplus

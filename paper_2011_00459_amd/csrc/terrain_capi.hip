@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -45,7 +46,7 @@ struct tr_scene {
     bool have_prev = false;
     bool stepped = false;
     bool slots_env_major = true;     // every env's spheres hold the slots [slot_begin, slot_begin + n)
-    bool graph_events = false;        // the step graphs record the phase events themselves
+    bool last_replay = false;         // the last step was a graph replay: only its total is timed
     std::vector<std::pair<void*, size_t>> allocs;
     int64_t cells_alloc = 0;
     int64_t zone_chunk_alloc = 0;
@@ -165,22 +166,23 @@ void invalidate_graphs(tr_scene* s)
 }
 
 // The automatic per-env plan, from a cost model measured on MI355X (the
-// 256-bed batch with a timing build that clocks every block's tasks): per
-// sweep and colour, a sphere of a multi-block share costs about 2.44 units,
-// a sphere of a block solving from LDS 0.85 plus 300 per set, and a sphere
-// that a single block keeps in global memory about 2.8 (3.2 here: those
-// solves vary most, and the largest of them set the makespan).  Envs that fit LDS
-// are packed into sets (first fit, largest first); envs up to Ns spheres are
-// solved alone by one block with their first slots in LDS; larger ones by
-// clusters of ceil(2.44 n / M) blocks of one XCD lane.  Ns and the target M
-// are searched for the smallest predicted makespan (jobs placed largest first
-// on the least loaded block).  tasks gets each block's cluster share
+// 256-bed batch, 100 sweeps, with a timing build that clocks every block's
+// tasks; units of microseconds): a block's share of a multi-block cluster
+// costs about 1800 (the colour phases' barriers) plus 1.77 per sphere of the
+// share, a set of envs solved from LDS by one block 1300 plus 0.6 per sphere,
+// and a sphere that a single block keeps in global memory about 2.0 (2.5
+// here: those solves vary most).  Envs that fit LDS are packed into sets
+// (first fit, largest first); envs up to Ns spheres are solved alone by one
+// block with their first slots in LDS; larger ones by clusters of
+// ceil(1.77 n / (M - 1800)) blocks of one XCD lane.  Ns and the target M are
+// searched for the smallest predicted makespan (jobs placed largest first on
+// the least loaded block).  tasks gets each block's cluster share
 // (env, rank, K, first block) and then its sets as (env, set number, 1, 0);
 // false when no candidate fits the blocks.
 bool plan_auto(const tr_scene* s, const std::vector<int>& order, int B, int lds_cap,
                std::vector<std::vector<int4>>& best_tasks)
 {
-    constexpr double kWc = 2.44, kWs = 0.85, kWset = 300.0, kWg = 3.2;
+    constexpr double kAc = 1800.0, kWc = 1.77, kWs = 0.6, kWset = 1300.0, kWg = 2.5;
     const int G = kGroups, PL = B / G, waves = kEnvBlk / 64;
     std::vector<std::vector<int>> sets;
     std::vector<double> fill;
@@ -219,7 +221,11 @@ bool plan_auto(const tr_scene* s, const std::vector<int>& order, int B, int lds_
                     jobs.push_back({kWs * lds_cap + kWg * (n - lds_cap) + kWset, e});
                     continue;
                 }
-                const int K = std::max(2, (int)std::ceil(kWc * n / M));
+                if (M <= kAc) {
+                    ok = false;
+                    break;
+                }
+                const int K = std::max(2, (int)std::ceil(kWc * n / (M - kAc)));
                 int lane = 0;
                 for (int x = 1; x < G; ++x)
                     if (lane_next[x] < lane_next[lane]) lane = x;
@@ -230,7 +236,7 @@ bool plan_auto(const tr_scene* s, const std::vector<int>& order, int B, int lds_
                 const int first = lane + G * lane_next[lane];
                 for (int r = 0; r < K; ++r) {
                     tasks[first + G * r].push_back(make_int4(e, r, K, first));
-                    load[first + G * r] += kWc * n / K;
+                    load[first + G * r] += kAc + kWc * n / K;
                 }
                 lane_next[lane] += K;
             }
@@ -982,26 +988,22 @@ int capture_graphs(tr_scene* s)
 {
     invalidate_graphs(s);
     if (!s->cap_stream) HIP_CHECK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
-    // the phase events are captured as event nodes, so that a replay times
-    // its own phases; a runtime that cannot capture them gets graphs without
-    // them (the events then bracket the whole replay)
-    for (int with_events = 1; with_events >= 0; --with_events) {
-        hipError_t e = hipSuccess;
-        for (int q = 0; q < 2 && e == hipSuccess; ++q) {
-            hipGraph_t g = nullptr;
-            HIP_CHECK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-            enqueue_step(s, s->cap_stream, with_events != 0);
-            e = hipStreamEndCapture(s->cap_stream, &g);
-            if (e == hipSuccess) e = hipGraphInstantiate(&s->gexec[q], g, nullptr, nullptr, 0);
-            if (g) (void)hipGraphDestroy(g);
-        }
-        if (e == hipSuccess) {
-            s->graph_events = with_events != 0;
-            break;
-        }
+    // no phase events inside the graphs: measured on ROCm, a replayed event
+    // node keeps the timestamps of its first recording, so a replay is timed
+    // as a whole by events recorded around its launch
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+        hipGraph_t g = nullptr;
+        HIP_CHECK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue_step(s, s->cap_stream, false);
+        e = hipStreamEndCapture(s->cap_stream, &g);
+        if (e == hipSuccess) e = hipGraphInstantiate(&s->gexec[q], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+    }
+    if (e != hipSuccess) {
         invalidate_graphs(s);
         (void)hipGetLastError();
-        if (!with_events) return hip_fail(s, e, "step graph capture");
+        return hip_fail(s, e, "step graph capture");
     }
     s->graphs = true;
     s->parity = 0;
@@ -1043,14 +1045,15 @@ static int step_scene(tr_scene* s, int32_t n_steps, tr_step_stats* stats)
             if (rc) return rc;
         }
         if (s->graphs && s->have_prev) {
-            if (!s->graph_events) (void)hipEventRecord(s->ev[0], st);
+            (void)hipEventRecord(s->ev[0], st);
             HIP_CHECK(s, hipGraphLaunch(s->gexec[s->parity], st));
-            if (!s->graph_events)
-                for (int q = 1; q < 5; ++q) (void)hipEventRecord(s->ev[q], st);
+            (void)hipEventRecord(s->ev[4], st);
+            s->last_replay = true;
             swap_particle_buffers(s);
             swap_step_buffers(s);
         } else {
             enqueue_step(s, st, true);
+            s->last_replay = false;
         }
         s->parity ^= 1;
         s->have_prev = true;
@@ -2141,7 +2144,10 @@ int get_phase_times(tr_scene* s, float* ms, int32_t cap)
     if (!s->stepped) return fail(s, TR_E_STATE, "get_phase_times: no step yet");
     HIP_CHECK(s, hipStreamSynchronize(s->stream));
     float t[5];
-    for (int k = 0; k < 4; ++k) HIP_CHECK(s, hipEventElapsedTime(&t[k], s->ev[k], s->ev[k + 1]));
+    for (int k = 0; k < 4; ++k) {
+        t[k] = std::numeric_limits<float>::quiet_NaN();
+        if (!s->last_replay) HIP_CHECK(s, hipEventElapsedTime(&t[k], s->ev[k], s->ev[k + 1]));
+    }
     HIP_CHECK(s, hipEventElapsedTime(&t[4], s->ev[0], s->ev[4]));
     for (int k = 0; k < cap && k < 5; ++k) ms[k] = t[k];
     return TR_OK;

@@ -650,6 +650,7 @@ class Scene:
         self._check(lib().set_step_graphs(self.h, 1 if enable else 0), "set_step_graphs")
 
     def get_phase_times(self):
+        """Device ms of the last step's phases; NaN per phase after a step-graph replay (only "step" is timed)."""
         t = (C.c_float * 5)()
         self._check(lib().get_phase_times(self.h, t, 5), "get_phase_times")
         return dict(detect=t[0], rows=t[1], pgs=t[2], finish=t[3], step=t[4])

@@ -164,6 +164,26 @@ def test_graph_replay_matches_eager_steps(sched, warm):
         assert np.array_equal(ga.get_particles(e)["v"], gb.get_particles(e)["v"])
 
 
+def test_phase_times_eager_and_replayed_steps():
+    # an eager step times each phase; a step-graph replay only as a whole
+    specs = batch(seed0=75, max_sweeps=10)
+    g, _ = scene(specs, "grouped")
+    g.set_step_graphs(False)
+    g.step(2)
+    ph = g.get_phase_times()
+    assert all(np.isfinite(v) and v >= 0.0 for v in ph.values()), ph
+    assert ph["pgs"] > 0.0 and ph["step"] >= ph["pgs"]
+    g.set_step_graphs(True)
+    for _ in range(2):
+        g.step(1)
+        ph = g.get_phase_times()
+        assert all(np.isnan(ph[k]) for k in ("detect", "rows", "pgs", "finish")), ph
+        assert np.isfinite(ph["step"]) and ph["step"] > 0.0
+    g.set_step_graphs(False)
+    g.step(1)
+    assert np.isfinite(g.get_phase_times()["pgs"])
+
+
 def test_save_load_state_resumes_exactly():
     specs = batch(seed0=80, max_sweeps=20, warm_start="prev")
     g, _ = scene(specs, "per_env_lds")
