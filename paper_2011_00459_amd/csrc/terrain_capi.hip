@@ -754,7 +754,7 @@ int create_scene(const tr_scene_desc* d, tr_scene** out)
               alloc_n(s, b.lamrc, z.roll_C) && alloc_n(s, b.plamr, z.roll_C) &&
               alloc_n(s, b.ri1, z.imp_C) && alloc_n(s, b.ri2, z.imp_C) && alloc_n(s, b.lami, z.imp_C) &&
               alloc_n(s, b.lamri, std::min(z.imp_C, z.roll_C)) && alloc_n(s, b.qg, z.imp_C) &&
-              alloc_n(s, b.lam, z.C) && alloc_n(s, b.lam0, z.C) &&
+              alloc_n(s, b.lam, z.C) && alloc_n(s, b.lam0, z.C) && alloc_n(s, b.wrec, 3 * z.C) &&
               alloc_n(s, b.envs, d->n_envs) && alloc_n(s, b.ustats, s->p.n_units) &&
               alloc_n(s, b.env_col, (int64_t)d->n_envs * (kMaxColours + 1)) && alloc_n(s, b.env_ncol, d->n_envs) &&
               alloc_n(s, b.env_bar, (int64_t)d->n_envs * 16) && alloc_n(s, b.ver, z.P) &&
@@ -961,17 +961,18 @@ void enqueue_step(tr_scene* s, hipStream_t st, bool events)
         launch_learned_lam(s->b, s->p, s->z, st);
         launch_vel_copy(s->b, s->p, true, st);
         launch_select_start(s->b, s->p, s->z, 1, st);
-        launch_warm_apply(s->b, s->p, s->z, st);
+        launch_warm_apply(s->b, s->p, s->z, true, st);
         launch_pgs(s->b, s->p, s->z, st, 1, 1);
         launch_vel_copy(s->b, s->p, false, st);
         launch_select_start(s->b, s->p, s->z, 0, st);
-        launch_warm_apply(s->b, s->p, s->z, st);
+        launch_warm_apply(s->b, s->p, s->z, true, st);
         launch_pgs(s->b, s->p, s->z, st, 1, 2);
         launch_choose_start(s->b, s->p, st);
         launch_vel_copy(s->b, s->p, false, st);
         launch_select_start(s->b, s->p, s->z, 2, st);
     }
-    launch_warm_apply(s->b, s->p, s->z, st);
+    // the learned path has replaced the start impulses that k_rows recorded
+    launch_warm_apply(s->b, s->p, s->z, s->p.warm == TR_WARM_LEARNED && s->mlp_loaded, st);
     if (events) (void)hipEventRecord(s->ev[2], st);
     launch_pgs(s->b, s->p, s->z, st);
     if (events) (void)hipEventRecord(s->ev[3], st);

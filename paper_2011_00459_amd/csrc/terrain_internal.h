@@ -207,6 +207,10 @@ struct DevBuffers {
     uint32_t *col_hist, *col_start;                 // [kBuckets*NB], [kBuckets*NB+1]
     uint32_t* cpos;                                 // canonical -> colour position
     float4 *r0, *r1, *r2, *rk, *lam, *lam0;         // colour order
+    // [3C] canonical order: each contact's start impulse as the velocity
+    // changes of its spheres, (J, slot of sphere 2), (dw of sphere 2, dw.x of
+    // sphere 1), (dw.yz of sphere 1, 0, 0), per unit inverse mass / inertia
+    float4* wrec;
     // rolling rows (allocated when mu_r > 0): r3 = (1/W_r, r mu_r, kinematic body, 0),
     // lamr = (lambda_r, 0) and its start value, canonical current / previous caches
     float4 *r3, *lamr, *lamr0, *lamrc, *plamr;
@@ -331,7 +335,7 @@ void launch_advect(const tr_voxel_grid& g, double dt, const double* u, const dou
 // impact stage: rows of envs without impacts neutralised, the stage's sweeps
 // (stats slot kSlotImpact), the main rows' q from the post-impact velocities
 void launch_impact_stage(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
-void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s);
+void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z, bool rebuild, hipStream_t s);
 // sweeps_cap < 0: the scene's max_sweeps; slot 0 writes the step stats,
 // slot 1/2 the first-sweep residual of the learned / previous-step trial
 void launch_pgs(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s, int sweeps_cap = -1,

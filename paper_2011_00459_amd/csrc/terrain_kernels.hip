@@ -838,6 +838,25 @@ __device__ inline float4 project_roll(float4 Lr, float lim)
 // start's features and frame, the counter-ordered PGS's update sequence
 constexpr int kRowsPrev = 1, kRowsFeatures = 2, kRowsSeq = 4;
 
+// A contact's start impulse as the velocity changes of its two spheres
+// (layout of wrec): J = lambda_n n + lambda_t acts on sphere 2 with +J and
+// on sphere 1 with -J; the angular change of a sphere is its lever times
+// (n x J), -l2 for sphere 2 and l1 for sphere 1, plus the rolling impulse.
+__device__ inline void warm_record(float4 L, float4 a, float l2, int ib, float4 Lr, bool roll, float4* rec)
+{
+    float J0 = L.x * a.x + L.y, J1 = L.x * a.y + L.z, J2 = L.x * a.z + L.w;
+    float lb = -l2, la = a.w;
+    float b0 = lb * (a.y * J2 - a.z * J1), b1 = lb * (a.z * J0 - a.x * J2), b2 = lb * (a.x * J1 - a.y * J0);
+    float a0 = la * (a.y * J2 - a.z * J1), a1 = la * (a.z * J0 - a.x * J2), a2 = la * (a.x * J1 - a.y * J0);
+    if (roll) {
+        b0 += Lr.x; b1 += Lr.y; b2 += Lr.z;
+        a0 += Lr.x; a1 += Lr.y; a2 += Lr.z;
+    }
+    rec[0] = make_float4(J0, J1, J2, __int_as_float(ib));
+    rec[1] = make_float4(b0, b1, b2, a0);
+    rec[2] = make_float4(a1, a2, 0.f, 0.f);
+}
+
 __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int flags)
 {
     uint32_t nc = n_contacts(b, cap);
@@ -1039,8 +1058,10 @@ __global__ void k_rows(DevBuffers b, StepParams p, int64_t cap, int flags)
         if (p.warm == TR_WARM_COLD) Lr = make_float4(0.f, 0.f, 0.f, 0.f);
         Lr.w = 0.f;
         b.lamr0[pos] = Lr;  // unprojected: the start's lambda_n decides the bound
-        b.lamr[pos] = project_roll(Lr, rlim * fabsf(L.x));
+        Lr = project_roll(Lr, rlim * fabsf(L.x));
+        b.lamr[pos] = Lr;
     }
+    warm_record(L, make_float4(nf[0], nf[1], nf[2], (float)l1), (float)l2, ib, Lr, p.mu_r > 0.f, b.wrec + 3 * (size_t)c);
 }
 
 void launch_rows(const DevBuffers& b, const StepParams& p, const Sizes& z, bool have_prev, bool features,
@@ -1114,46 +1135,56 @@ void launch_impact_stage(const DevBuffers& b, const StepParams& p, const Sizes& 
 
 // ---------------------------------------------------------------------------
 // v* = v + dt g + M^-1 G^T lambda^0, gathered per particle over its sorted
-// incidence list (fixed order)
+// incidence list (fixed order) from the contacts' records in canonical order
+// (one 32 or 48 B record per incident contact)
 // ---------------------------------------------------------------------------
 __global__ void k_warm_apply(DevBuffers b, StepParams p)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= p.n_particles) return;
     if (b.cnt->overflow) return;
+    const bool roll = p.mu_r > 0.f;
     float4 v = vel_at(b.vw, s), w = angv_at(b.vw, s);
     v.x += p.dt * p.g[0];
     v.y += p.dt * p.g[1];
     v.z += p.dt * p.g[2];
     uint32_t beg = b.inc_start[s], end = b.inc_start[s + 1];
     for (uint32_t t = beg; t < end; ++t) {
-        uint32_t pos = b.cpos[b.inc[t]];
-        float4 L = b.lam[pos];
-        if (L.x == 0.f && L.y == 0.f && L.z == 0.f && L.w == 0.f && !(p.mu_r > 0.f)) continue;
-        float4 a = b.r0[pos];
-        float4 q = b.r2[pos];
-        float J0 = L.x * a.x + L.y, J1 = L.x * a.y + L.z, J2 = L.x * a.z + L.w;
-        float sgn, lev;
-        if (__float_as_int(q.w) == s) { sgn = 1.f; lev = -b.r1[pos].x; }
-        else { sgn = -1.f; lev = a.w; }
-        // arm = lev n; dw = sgn * iI (arm x J)
-        float c0 = lev * (a.y * J2 - a.z * J1), c1 = lev * (a.z * J0 - a.x * J2), c2 = lev * (a.x * J1 - a.y * J0);
-        v.x += sgn * v.w * J0; v.y += sgn * v.w * J1; v.z += sgn * v.w * J2;
-        w.x += sgn * w.w * c0; w.y += sgn * w.w * c1; w.z += sgn * w.w * c2;
-        if (p.mu_r > 0.f) {
-            float4 Lr = b.lamr[pos];
-            w.x += sgn * w.w * Lr.x; w.y += sgn * w.w * Lr.y; w.z += sgn * w.w * Lr.z;
+        const float4* r = b.wrec + 3 * (size_t)b.inc[t];
+        float4 R0 = r[0], R1 = r[1];
+        if (!roll && R0.x == 0.f && R0.y == 0.f && R0.z == 0.f) continue;
+        float sgn, W0, W1, W2;
+        if (__float_as_int(R0.w) == s) { sgn = 1.f; W0 = R1.x; W1 = R1.y; W2 = R1.z; }
+        else {
+            float4 R2 = r[2];
+            sgn = -1.f; W0 = R1.w; W1 = R2.x; W2 = R2.y;
         }
+        v.x += sgn * v.w * R0.x; v.y += sgn * v.w * R0.y; v.z += sgn * v.w * R0.z;
+        w.x += sgn * w.w * W0; w.y += sgn * w.w * W1; w.z += sgn * w.w * W2;
     }
     vel_at(b.vw, s) = v;
     angv_at(b.vw, s) = w;
 }
 
-void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z, hipStream_t s)
+// the records again from the colour-ordered impulses and rows, after a
+// kernel other than k_rows has set the start impulses
+__global__ void k_warm_rec(DevBuffers b, StepParams p, int64_t cap)
 {
+    uint32_t nc = n_contacts(b, cap);
+    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    if (b.cnt->overflow) return;
+    const uint32_t pos = b.cpos[c];
+    const bool roll = p.mu_r > 0.f;
+    warm_record(b.lam[pos], b.r0[pos], b.r1[pos].x, __float_as_int(b.r2[pos].w),
+                roll ? b.lamr[pos] : make_float4(0.f, 0.f, 0.f, 0.f), roll, b.wrec + 3 * (size_t)c);
+}
+
+void launch_warm_apply(const DevBuffers& b, const StepParams& p, const Sizes& z, bool rebuild, hipStream_t s)
+{
+    if (rebuild) hipLaunchKernelGGL(k_warm_rec, dim3((unsigned)cdiv(z.C, kBlk)), dim3(kBlk), 0, s, b, p, z.C);
     if (p.n_particles <= 0) return;
     hipLaunchKernelGGL(k_warm_apply, dim3((unsigned)cdiv(p.n_particles, kBlk)), dim3(kBlk), 0, s, b, p);
-    (void)z;
 }
 
 // ---------------------------------------------------------------------------
