@@ -608,13 +608,26 @@ __device__ inline bool colour_try(const DevBuffers& b, uint32_t c, uint32_t& wai
 __global__ __launch_bounds__(kBlk) void k_colour(DevBuffers b, int64_t cap, int max_pass)
 {
     uint32_t nc = n_contacts(b, cap);
-    uint32_t stride = gridDim.x * blockDim.x;
-    uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
+    // consecutive blocks run on the 8 XCDs in turn: the contact list in eight
+    // contiguous parts, part x coloured by the blocks of XCD x, so that the
+    // colours an env's contacts read and write stay in one XCD's L2 (except
+    // where a part boundary cuts an env); measured, about 5 % less colouring
+    // time than a grid-stride over the whole list.  Placement only changes
+    // the speed: colours are written once, so a late read only delays a contact.
+    uint32_t lo = 0, hi = nc, stride = gridDim.x * blockDim.x, first = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nx = gridDim.x / kGroups;
+    if (nx > 0) {
+        const uint32_t x = blockIdx.x % kGroups, jb = blockIdx.x / kGroups;
+        lo = (uint32_t)((uint64_t)nc * x / kGroups);
+        hi = (uint32_t)((uint64_t)nc * (x + 1) / kGroups);
+        stride = nx * blockDim.x;
+        first = jb < nx ? lo + jb * blockDim.x + threadIdx.x : hi;
+    }
     int local_max = 0;
     bool ovf = false, left = true;
     for (int pass = 0; pass < max_pass; ++pass) {
         left = false;
-        for (uint32_t c = first; c < nc; c += stride) {
+        for (uint32_t c = first; c < hi; c += stride) {
             if (ld_colour(&b.colour[c]) >= 0) continue;
             // the conflict that blocked this contact last pass: while it is
             // uncoloured the contact stays blocked (a full scan decides readiness)
@@ -734,9 +747,11 @@ __global__ void k_env_ncol(DevBuffers b, int64_t cap, uint32_t id_cap)
 // cpos[c] the position of canonical contact c.  The rank among equal colours
 // keeps canonical order: inside a wave from the lanes with the same colour
 // (a 7-bit ballot match), across waves and chunks from running counts.
-constexpr int kSortWaves = kBlk / 64;
+// 1024 threads, so that the largest env takes few chunks.
+constexpr int kSortBlk = 1024;
+constexpr int kSortWaves = kSortBlk / 64;
 
-__global__ __launch_bounds__(kBlk) void k_env_colsort(DevBuffers b, uint32_t id_cap)
+__global__ __launch_bounds__(kSortBlk) void k_env_colsort(DevBuffers b, uint32_t id_cap)
 {
     __shared__ uint32_t base[kMaxColours + 1];
     __shared__ uint32_t wcount[kSortWaves][kMaxColours + 1];
@@ -748,11 +763,27 @@ __global__ __launch_bounds__(kBlk) void k_env_colsort(DevBuffers b, uint32_t id_
     for (int k = threadIdx.x; k <= kMaxColours; k += blockDim.x) base[k] = 0;
     if (threadIdx.x == 0) failed = 0;
     __syncthreads();
-    // histogram (colour kMaxColours collects failed colourings)
-    for (uint32_t c = beg + threadIdx.x; c < end; c += blockDim.x) {
-        int col = b.colour[c];
-        if (col < 0 || col >= kMaxColours) { col = kMaxColours; failed = 1; }
-        atomicAdd(&base[col], 1u);
+    // the lanes of a wave holding the same colour as this lane
+    auto same_colour = [&](int col) {
+        unsigned long long same = ~0ull;
+        for (int bit = 0; bit < 7; ++bit) {
+            unsigned long long m = __ballot((col >> bit) & 1);
+            same &= ((col >> bit) & 1) ? m : ~m;
+        }
+        return same;
+    };
+    const unsigned long long lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // histogram (colour kMaxColours collects failed colourings), one LDS
+    // atomic per colour and wave
+    for (uint32_t c0 = beg; c0 < end; c0 += blockDim.x) {
+        const uint32_t c = c0 + threadIdx.x;
+        int col = kMaxColours + 1;  // past the end: counted nowhere
+        if (c < end) {
+            col = b.colour[c];
+            if (col < 0 || col >= kMaxColours) { col = kMaxColours; failed = 1; }
+        }
+        const unsigned long long same = same_colour(col);
+        if ((same & lower) == 0 && col <= kMaxColours) atomicAdd(&base[col], (uint32_t)__popcll(same));
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -775,12 +806,7 @@ __global__ __launch_bounds__(kBlk) void k_env_colsort(DevBuffers b, uint32_t id_
             col = b.colour[c];
             if (col < 0 || col >= kMaxColours) col = kMaxColours;
         }
-        unsigned long long same = ~0ull;
-        for (int bit = 0; bit < 7; ++bit) {
-            unsigned long long m = __ballot((col >> bit) & 1);
-            same &= ((col >> bit) & 1) ? m : ~m;
-        }
-        unsigned long long lower = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        const unsigned long long same = same_colour(col);
         uint32_t rank = (uint32_t)__popcll(same & lower);
         bool leader = (same & lower) == 0;
         for (int k = lane; k <= kMaxColours; k += 64) wcount[wave][k] = 0;
@@ -807,7 +833,7 @@ void launch_colour(const DevBuffers& b, const StepParams& p, const Sizes& z, hip
     launch_fill_u32((uint32_t*)b.colour, 0xFFFFFFFFu, z.C, s);
     hipLaunchKernelGGL(k_colour, dim3(z.col_grid), dim3(kBlk), 0, s, b, z.C, 100000);
     if (z.pgs_mode == kModePerEnv) {
-        hipLaunchKernelGGL(k_env_colsort, dim3((unsigned)z.n_envs), dim3(kBlk), 0, s, b, p.id_cap);
+        hipLaunchKernelGGL(k_env_colsort, dim3((unsigned)z.n_envs), dim3(kSortBlk), 0, s, b, p.id_cap);
         return;
     }
     const int spread = z.pgs_mode == kModeSpread ? 1 : 0;
