@@ -335,20 +335,22 @@ __global__ __launch_bounds__(kBlk) void k_narrow(DevBuffers b, StepParams p, int
         int c[3];
         cell_of(E, xi.x, xi.y, xi.z, c);
         double X = xi.x, Y = xi.y, Z = xi.z, Ri = xi.w;
-        for (int dz = -1; dz <= 1; ++dz) {
+        // half shell: the own cell's later slots and the 13 cells after it
+        // in (z, y, x) order, so that each pair is met once, from the sphere
+        // whose cell comes first (the predicate is exactly symmetric)
+        for (int dz = 0; dz <= 1; ++dz) {
             int cz = c[2] + dz;
-            if (cz < 0 || cz >= E.dims[2]) continue;
-            for (int dy = -1; dy <= 1; ++dy) {
+            if (cz >= E.dims[2]) continue;
+            for (int dy = dz ? -1 : 0; dy <= 1; ++dy) {
                 int cy = c[1] + dy;
                 if (cy < 0 || cy >= E.dims[1]) continue;
-                for (int dx = -1; dx <= 1; ++dx) {
+                for (int dx = (dz || dy) ? -1 : 0; dx <= 1; ++dx) {
                     int cx = c[0] + dx;
                     if (cx < 0 || cx >= E.dims[0]) continue;
                     uint32_t key = E.cell_base + morton(cx, cy, cz, E.bits);
                     uint32_t beg = b.cell_start[key], end = b.cell_start[key + 1];
+                    if ((dx | dy | dz) == 0) beg = max(beg, (uint32_t)i + 1);
                     for (uint32_t j = beg; j < end; ++j) {
-                        int idj = b.pid[j];
-                        if (idj <= idi) continue;
                         float4 xj = b.xr[j];
                         if (pair_touch(X, Y, Z, Ri, (double)xj.x, (double)xj.y, (double)xj.z, (double)xj.w, p.kappa_c)) {
                             if (nh < kMaxHits) hits[threadIdx.x][nh++] = (int)j;
@@ -379,9 +381,12 @@ __global__ __launch_bounds__(kBlk) void k_narrow(DevBuffers b, StepParams p, int
         uint64_t idx = (uint64_t)off + (uint64_t)k;
         if (idx >= (uint64_t)cap) { ovf = true; continue; }
         if (h >= 0) {
+            // key and pair in id order: (lower id, higher id)
             int idj = b.pid[h];
-            b.rkey[idx] = ((unsigned long long)(uint32_t)idi << 32) | (uint32_t)idj;
-            b.rpair[idx] = make_int2(i, h);
+            const bool first = idi < idj;
+            const uint32_t lo = (uint32_t)(first ? idi : idj), hi = (uint32_t)(first ? idj : idi);
+            b.rkey[idx] = ((unsigned long long)lo << 32) | hi;
+            b.rpair[idx] = first ? make_int2(i, h) : make_int2(h, i);
             ++npairs;
         } else {
             int sg = -1 - h;
