@@ -47,11 +47,11 @@ PAIR_BYTES, BOUND_BYTES = 176, 128
 # runs scaled by a copy kernel of known size (profiles named below); valid
 # only for the kernel source it was measured on, else reported as null.
 PGS_TRAFFIC = {
-    "batched": {"kernels_sha256_prefix": "491ce3b4498ba602", "bytes_per_launch": 52.70e9,
+    "batched": {"kernels_sha256_prefix": "02315f89cb19c419", "bytes_per_launch": 52.76e9,
                 "profile": "profiles/k_pgs_env_batched256_hbm_traffic.md"},
-    "bed": {"kernels_sha256_prefix": "491ce3b4498ba602", "bytes_per_launch": 3.504e9,
+    "bed": {"kernels_sha256_prefix": "02315f89cb19c419", "bytes_per_launch": 3.494e9,
             "profile": "profiles/k_pgs_bed50k_hbm_traffic.md"},
-    "excavation": {"kernels_sha256_prefix": "491ce3b4498ba602", "bytes_per_launch": 71.00e9,
+    "excavation": {"kernels_sha256_prefix": "02315f89cb19c419", "bytes_per_launch": 71.00e9,
                    "profile": "profiles/k_pgs_excavation500k_hbm_traffic.md"},
 }
 # The same for k_advect on the 256 x 256 x 128 voxel grid
